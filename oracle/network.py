@@ -1,0 +1,397 @@
+"""Reference networks and LoLa schedules (the oracle side).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Three things live here, all written from the paper's text:
+
+1. Plaintext integer networks (exact Python integers, then mod t):
+   - dense64: y = (W x)^2 for a 64-vector and a 64x64 matrix;
+   - mnist:   5x5 stride-2 convolution with 5 maps -> square -> dense 845->100
+              -> square -> dense 100->10 (Sec. 4, the network of Table 1), with
+              integer biases;
+   - head:    dense 4096->256 -> square -> dense 256->10 (the private head on
+              deep features of Sec. 5, with a hidden layer).
+2. Schedules: the paper's vector representations and matrix-vector recipes
+   (Sec. 3.2) written out as op lists on ciphertext registers:
+     ("mul_scalar", dst, src, w)      message times scalar (Sec. 3.2.2, conv)
+     ("add", dst, a, b)
+     ("add_plain", dst, src, slots)   slots: {slot index: value}
+     ("mul_plain", dst, src, slots)
+     ("rotate", dst, src, step)       step > 0 left, < 0 right, "row_swap"
+     ("square", dst, src)             ct x ct product then relinearisation
+   Registers 0..n_inputs-1 hold the inputs; the schedule's "outputs" names the
+   result registers.
+3. Two interpreters for a schedule: on plain slot vectors mod t (every slot,
+   including the ones that hold partial sums) and on ciphertexts through the
+   oracle's BFV operations.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+from . import bfv
+
+ROW_SWAP = bfv.ROW_SWAP
+
+
+# ---------------------------------------------------------------- plain nets
+def _mod(a, t):
+    return np.array([int(v) % t for v in np.asarray(a, dtype=object).ravel()],
+                    dtype=np.int64).reshape(np.shape(a))
+
+
+def dense64_plain(x, W):
+    """Exact integers: ((W x)_j)^2."""
+    y = np.asarray(W, dtype=object).dot(np.asarray(x, dtype=object))
+    return y * y
+
+
+# Padding of the 28x28 image to 29x29: one zero row at the bottom and one zero
+# column at the right, so that 13 windows of 5 at stride 2 cover it
+# (rows 2y..2y+4, y < 13).
+MNIST_PAD = 29
+MNIST_OUT = 13
+
+
+def mnist_padded(img):
+    p = np.zeros((MNIST_PAD, MNIST_PAD), dtype=np.int64)
+    p[:28, :28] = img
+    return p
+
+
+def mnist_plain(img, wts):
+    """Exact integer logits of the MNIST-shaped network."""
+    p = mnist_padded(img).astype(object)
+    conv = np.zeros((5, MNIST_OUT, MNIST_OUT), dtype=object)
+    for m in range(5):
+        for y in range(MNIST_OUT):
+            for x in range(MNIST_OUT):
+                win = p[2 * y:2 * y + 5, 2 * x:2 * x + 5]
+                conv[m, y, x] = int((win * wts.conv_w[m].astype(object)).sum()) + int(wts.conv_b[m])
+    a1 = (conv * conv).reshape(845)                       # index 169 m + 13 y + x
+    h = wts.w1.astype(object).dot(a1) + wts.b1.astype(object)
+    a2 = h * h
+    return wts.w2.astype(object).dot(a2) + wts.b2.astype(object)
+
+
+def head_plain(f, wts):
+    """Exact integer logits of the 4096 -> 256 -> square -> 10 head."""
+    h = wts.w1.astype(object).dot(np.asarray(f, dtype=object)) + wts.b1.astype(object)
+    a = h * h
+    return wts.w2.astype(object).dot(a) + wts.b2.astype(object)
+
+
+# ----------------------------------------------------------------- schedule
+@dataclasses.dataclass
+class Schedule:
+    N: int
+    n_inputs: int
+    ops: List[tuple]
+    outputs: List[int]
+    # where each result value ends up: list over outputs of {slot: label}
+    out_slots: List[Dict[int, str]] = dataclasses.field(default_factory=list)
+
+    def count(self, kind: str) -> int:
+        return sum(1 for op in self.ops if op[0] == kind)
+
+
+class _Builder:
+    def __init__(self, N, n_inputs):
+        self.N = N
+        self.n_inputs = n_inputs
+        self.ops = []
+        self.next = n_inputs
+
+    def reg(self):
+        r = self.next
+        self.next += 1
+        return r
+
+    def emit(self, *op):
+        self.ops.append(tuple(op))
+        return op[1]
+
+
+def _rotate_and_sum(b: _Builder, src: int, steps: Sequence) -> int:
+    """x += rot(x, k) for k in steps (left rotations / row swap)."""
+    cur = src
+    for k in steps:
+        r = b.emit("rotate", b.reg(), cur, k)
+        cur = b.emit("add", b.reg(), cur, r)
+    return cur
+
+
+def _combine_tree(b: _Builder, regs: Sequence[int], unit: int) -> int:
+    """sum_j rot(regs[j], -unit*j), built as a binary tree: at level l the odd
+    member of each pair is rotated right by unit*2^l and added to the even one.
+    Rotating right by unit*j is the composition of the rotations for the set
+    bits of j, so the result is the same slot vector as the direct sum, with the
+    same number of rotations (len-1) but only log2(len) distinct steps."""
+    cur = list(regs)
+    stride = unit
+    while len(cur) > 1:
+        nxt = []
+        for i in range(0, len(cur), 2):
+            if i + 1 < len(cur):
+                r = b.emit("rotate", b.reg(), cur[i + 1], -stride)
+                nxt.append(b.emit("add", b.reg(), cur[i], r))
+            else:
+                nxt.append(cur[i])
+        cur = nxt
+        stride *= 2
+    return cur[0]
+
+
+def dense64_inputs(x, N):
+    """Client side: the 64-vector stacked N/64 times (stacked representation,
+    Sec. 3.2.1, with d = 6): slot i holds x[i mod 64]."""
+    x = np.asarray(x, dtype=np.int64)
+    return [{s: int(x[s % 64]) for s in range(N)}]
+
+
+def dense64_schedule(W, N: int = 4096) -> Schedule:
+    """Stacked vector - row major (Sec. 3.2.2): one point-wise product with the
+    64 rows of W laid out row j at slots 64j..64j+63, then rotations of size
+    1, 2, ..., 32 and additions; value j ends at slot 64j (interleaved), then
+    squared."""
+    assert N == 4096
+    b = _Builder(N, 1)
+    W = np.asarray(W, dtype=np.int64)
+    rows = {64 * j + i: int(W[j, i]) for j in range(64) for i in range(64)}
+    z = b.emit("mul_plain", b.reg(), 0, rows)
+    z = _rotate_and_sum(b, z, [1, 2, 4, 8, 16, 32])
+    y = b.emit("square", b.reg(), z)
+    return Schedule(N, 1, b.ops, [y], [{64 * j: f"y{j}" for j in range(64)}])
+
+
+# MNIST (N = 16384): slots are a 2 x 8192 matrix; slot index r*8192 + i.
+def conv_representation(img, k: int, stride: int):
+    """Convolution representation (Sec. 3.2.1) of a 2-D input for a k x k
+    window at the given stride: k*k messages; message a*k+b holds, at entry
+    y*n_out + x, the input value [stride*y + a][stride*x + b], so that
+    sum_{a,b} w[a,b] * message(a,b) is the convolution output at (y, x).
+    Returns a list of 1-D integer arrays."""
+    img = np.asarray(img)
+    n_out = (img.shape[0] - k) // stride + 1
+    msgs = []
+    for a in range(k):
+        for b in range(k):
+            msgs.append(np.array([img[stride * y + a, stride * x + b]
+                                  for y in range(n_out) for x in range(n_out)]))
+    return msgs
+
+
+def mnist_inputs(img, N=16384):
+    """Client side convolution representation of the zero-padded image for the
+    5x5, stride-2 window: message 5a+b holds at slot 13y+x the padded pixel
+    [2y+a][2x+b]."""
+    return [{i: int(v) for i, v in enumerate(m)}
+            for m in conv_representation(mnist_padded(img), 5, 2)]
+
+
+def mnist_schedule(wts, N: int = 16384) -> Schedule:
+    """The LoLa MNIST pipeline of Table 1, laid out for N = 16384 as the paper
+    does for LoLa-Dense in App. C (16 stacked copies, 7 rounds):
+      conv:    per map, sum_{a,b} w[m,a,b] * M_{a,b} (message x scalar) + bias
+      combine: map m rotated right by 169 m and added (4 rotations, as a
+               binary tree over steps 169, 338, 676)
+      square
+      stack:   copies at stride 1024 by rotating right 1024, 2048, 4096 and a
+               row swap (16 copies)
+      dense1:  7 rounds of stacked vector - row major: product with rows
+               16 rho + c in block c, rotate-and-sum 1..512, keep slot 1024 c
+               (mask), add bias
+      combine: round rho rotated right by rho and added -> interleaved, value
+               16 rho + c at slot 1024 c + rho (6 rotations, tree over 1, 2, 4)
+      square
+      dense2:  interleaved vector - row major: per output o, product with the
+               matching interleaved row, rotate-and-sum over 1, 2, 4, 1024,
+               2048, 4096 and the row swap -> logit o at slot 0, add bias."""
+    assert N == 16384
+    b = _Builder(N, 25)
+    maps = []
+    for m in range(5):
+        acc = None
+        for a in range(5):
+            for c in range(5):
+                t = b.emit("mul_scalar", b.reg(), 5 * a + c, int(wts.conv_w[m, a, c]))
+                acc = t if acc is None else b.emit("add", b.reg(), acc, t)
+        acc = b.emit("add_plain", b.reg(), acc, {s: int(wts.conv_b[m]) for s in range(169)})
+        maps.append(acc)
+    y = _combine_tree(b, maps, 169)
+    y = b.emit("square", b.reg(), y)
+    s = _rotate_and_sum(b, y, [-1024, -2048, -4096, ROW_SWAP])
+    rounds = []
+    for rho in range(7):
+        rows = {}
+        mask = {}
+        bias = {}
+        for c in range(16):
+            j = 16 * rho + c
+            if j >= 100:
+                continue
+            for i in range(845):
+                rows[1024 * c + i] = int(wts.w1[j, i])
+            mask[1024 * c] = 1
+            bias[1024 * c] = int(wts.b1[j])
+        z = b.emit("mul_plain", b.reg(), s, rows)
+        z = _rotate_and_sum(b, z, [1 << k for k in range(10)])
+        z = b.emit("mul_plain", b.reg(), z, mask)
+        z = b.emit("add_plain", b.reg(), z, bias)
+        rounds.append(z)
+    h = _combine_tree(b, rounds, 1)
+    h = b.emit("square", b.reg(), h)
+    outs = []
+    for o in range(10):
+        rows = {}
+        for rho in range(7):
+            for c in range(16):
+                j = 16 * rho + c
+                if j < 100:
+                    rows[1024 * c + rho] = int(wts.w2[o, j])
+        z = b.emit("mul_plain", b.reg(), h, rows)
+        z = _rotate_and_sum(b, z, [1, 2, 4, 1024, 2048, 4096, ROW_SWAP])
+        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b2[o])})
+        outs.append(z)
+    return Schedule(N, 25, b.ops, outs, [{0: f"logit{o}"} for o in range(10)])
+
+
+# Transfer-learning head (N = 16384, 4 queries per ciphertext, query q in the
+# 4096-slot block starting at slot 4096 q).
+HEAD_BLOCK = 4096
+
+
+def head_inputs(features, N=16384):
+    """Dense representation, one block per query (up to 4 per message)."""
+    f = np.asarray(features, dtype=np.int64)
+    assert f.shape[0] <= N // HEAD_BLOCK
+    return [{HEAD_BLOCK * q + i: int(f[q, i]) for q in range(f.shape[0]) for i in range(HEAD_BLOCK)}]
+
+
+def head_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int = 10) -> Schedule:
+    """Dense vector - row major (Sec. 3.2.2) for 4096 -> 256: per hidden unit
+    j, product with row j repeated in every block, rotate-and-sum over
+    1..2048 (each block's sum lands at its first slot), mask, then rotate
+    right by j and add, as a binary tree (interleaved result, h_j of query q at slot 4096 q + j),
+    bias, square; then interleaved vector - row major for 256 -> 10 with
+    rotate-and-sum over 1..128 (logit o of query q at slot 4096 q).
+    n_hidden < 256 builds a truncated head (for quick checks)."""
+    assert N == 16384
+    nb = N // HEAD_BLOCK
+    nh = wts.w1.shape[0] if n_hidden is None else n_hidden
+    b = _Builder(N, 1)
+    hidden = []
+    for j in range(nh):
+        rows = {HEAD_BLOCK * q + i: int(wts.w1[j, i]) for q in range(nb) for i in range(HEAD_BLOCK)}
+        z = b.emit("mul_plain", b.reg(), 0, rows)
+        z = _rotate_and_sum(b, z, [1 << k for k in range(12)])
+        z = b.emit("mul_plain", b.reg(), z, {HEAD_BLOCK * q: 1 for q in range(nb)})
+        hidden.append(z)
+    acc = _combine_tree(b, hidden, 1)
+    acc = b.emit("add_plain", b.reg(), acc,
+                 {HEAD_BLOCK * q + j: int(wts.b1[j]) for q in range(nb) for j in range(nh)})
+    h = b.emit("square", b.reg(), acc)
+    steps = [1 << k for k in range(int(np.ceil(np.log2(max(nh, 2)))))]
+    outs = []
+    for o in range(n_out):
+        rows = {HEAD_BLOCK * q + j: int(wts.w2[o, j]) for q in range(nb) for j in range(nh)}
+        z = b.emit("mul_plain", b.reg(), h, rows)
+        z = _rotate_and_sum(b, z, steps)
+        z = b.emit("add_plain", b.reg(), z, {HEAD_BLOCK * q: int(wts.b2[o]) for q in range(nb)})
+        outs.append(z)
+    return Schedule(N, 1, b.ops, outs,
+                    [{HEAD_BLOCK * q: f"q{q}_logit{o}" for q in range(nb)} for o in range(n_out)])
+
+
+# ------------------------------------------------------------- interpreters
+def dense_slots(sparse: Dict[int, int], N: int, t: int) -> np.ndarray:
+    v = np.zeros(N, dtype=np.int64)
+    for k, x in sparse.items():
+        v[k] = int(x) % t
+    return v
+
+
+def rotate_slots(v: np.ndarray, step) -> np.ndarray:
+    """Slot-level rotation: left by step within each row; row swap."""
+    n2 = len(v) // 2
+    if step == ROW_SWAP:
+        return np.concatenate([v[n2:], v[:n2]])
+    k = int(step) % n2
+    return np.concatenate([np.roll(v[:n2], -k), np.roll(v[n2:], -k)])
+
+
+def run_slots(sched: Schedule, inputs: Sequence[Dict[int, int]], t: int):
+    """Every register's full slot vector mod t; returns (outputs, registers)."""
+    N = sched.N
+    reg = {i: dense_slots(inputs[i], N, t) for i in range(sched.n_inputs)}
+    for op in sched.ops:
+        k = op[0]
+        if k == "mul_scalar":
+            reg[op[1]] = (reg[op[2]] * (int(op[3]) % t)) % t
+        elif k == "add":
+            reg[op[1]] = (reg[op[2]] + reg[op[3]]) % t
+        elif k == "add_plain":
+            reg[op[1]] = (reg[op[2]] + dense_slots(op[3], N, t)) % t
+        elif k == "mul_plain":
+            reg[op[1]] = (reg[op[2]] * dense_slots(op[3], N, t)) % t
+        elif k == "rotate":
+            reg[op[1]] = rotate_slots(reg[op[2]], op[3])
+        elif k == "square":
+            reg[op[1]] = (reg[op[2]] * reg[op[2]]) % t
+        else:
+            raise ValueError(k)
+    return [reg[o] for o in sched.outputs], reg
+
+
+def galois_elements(sched: Schedule) -> List[int]:
+    gs = sorted({bfv.galois_element(sched.N, op[3]) for op in sched.ops if op[0] == "rotate"})
+    return [g for g in gs if g != 1]
+
+
+def _sources(op):
+    return [op[2], op[3]] if op[0] == "add" else [op[2]]
+
+
+def run_ciphertexts(ctx: bfv.Context, keys: bfv.Keys, sched: Schedule, cts, keep=False):
+    """Evaluates the schedule on ciphertexts with the oracle's operations.
+    Intermediate registers are dropped after their last use unless keep."""
+    last_use = {}
+    for idx, op in enumerate(sched.ops):
+        for r in _sources(op):
+            last_use[r] = idx
+    for r in sched.outputs:
+        last_use[r] = len(sched.ops)
+    reg = {i: cts[i] for i in range(sched.n_inputs)}
+    N, t = sched.N, ctx.t
+    pt_cache = {}
+
+    def plain(slots):
+        key = id(slots)
+        if key not in pt_cache:
+            pt_cache[key] = bfv.encode(ctx, dense_slots(slots, N, t))
+        return pt_cache[key]
+
+    for idx, op in enumerate(sched.ops):
+        k = op[0]
+        if k == "mul_scalar":
+            reg[op[1]] = bfv.mul_scalar(ctx, reg[op[2]], op[3])
+        elif k == "add":
+            reg[op[1]] = bfv.add(ctx, reg[op[2]], reg[op[3]])
+        elif k == "add_plain":
+            reg[op[1]] = bfv.add_plain(ctx, reg[op[2]], plain(op[3]))
+        elif k == "mul_plain":
+            reg[op[1]] = bfv.mul_plain(ctx, reg[op[2]], plain(op[3]))
+        elif k == "rotate":
+            reg[op[1]] = bfv.rotate(ctx, reg[op[2]], op[3], keys)
+        elif k == "square":
+            reg[op[1]] = bfv.square(ctx, reg[op[2]], keys)
+        else:
+            raise ValueError(k)
+        if not keep:
+            for r in _sources(op):
+                if last_use.get(r) == idx and r not in sched.outputs:
+                    reg.pop(r, None)
+    return [reg[o] for o in sched.outputs], reg

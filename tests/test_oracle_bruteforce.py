@@ -1,0 +1,109 @@
+"""Pins the oracle word for word against an independent pure-Python BFV
+(tests/bruteforce_bfv.py) at tiny N, for every operation of the scheme."""
+import numpy as np
+import pytest
+
+from oracle import bfv
+from tests import bruteforce_bfv as bf
+
+
+class _P:
+    def __init__(self, N, t, q, P):
+        self.N, self.t, self.q, self.P = N, t, tuple(q), P
+
+
+TINY = [_P(16, 97, (193, 257, 353), 449), _P(32, 193, (257, 449, 577), 641)]
+
+
+def _np(limbs):
+    return np.array(limbs, dtype=np.uint64)
+
+
+def _eq(ct_oracle, ct_bf):
+    assert len(ct_oracle) == len(ct_bf)
+    for a, b in zip(ct_oracle, ct_bf):
+        assert np.array_equal(np.asarray(a, np.uint64), _np(b))
+
+
+@pytest.fixture(params=TINY, ids=lambda p: f"N{p.N}")
+def setup(request):
+    p = request.param
+    ctx = bfv.Context(p)
+    tiny = bf.Tiny(p.N, p.t, p.q, p.P)
+    gs = [bfv.galois_element(p.N, 1), bfv.galois_element(p.N, -3), bfv.galois_element(p.N, bfv.ROW_SWAP)]
+    seed = 0x1234_5678_9ABC
+    keys = bfv.keygen(ctx, seed, gs)
+    bkeys = tiny.keygen(seed, gs)
+    rs = np.random.default_rng(p.N)
+    m1 = rs.integers(0, p.t, p.N)
+    m2 = rs.integers(0, p.t, p.N)
+    ct1 = bfv.encrypt(ctx, keys, m1, 77, 3)
+    ct2 = bfv.encrypt(ctx, keys, m2, 77, 4)
+    bct1 = tiny.encrypt(bkeys, [int(v) for v in m1], 77, 3)
+    bct2 = tiny.encrypt(bkeys, [int(v) for v in m2], 77, 4)
+    return p, ctx, tiny, gs, keys, bkeys, (m1, m2), (ct1, ct2), (bct1, bct2)
+
+
+def test_chacha_words_match(setup):
+    assert list(bfv.stream_words(99, 5, 7, 2, 20)) == bf.words(99, 5, 7, 2, 20)
+
+
+def test_keys_match(setup):
+    p, ctx, tiny, gs, keys, bkeys, *_ = setup
+    assert list(keys.sk.s) == bkeys["s"]
+    assert np.array_equal(keys.pk0, _np(bkeys["pk0"]))
+    assert np.array_equal(keys.pk1, _np(bkeys["pk1"]))
+    b, a = bkeys["rlk"]
+    for i in range(ctx.L):
+        for j in range(ctx.L + 1):
+            assert list(keys.rlk.b[i, j]) == b[i][j]
+            assert list(keys.rlk.a[i, j]) == a[i][j]
+    for g in gs:
+        b, a = bkeys["gal"][g]
+        assert all(list(keys.galois[g].b[i, j]) == b[i][j]
+                   for i in range(ctx.L) for j in range(ctx.L + 1))
+
+
+def test_encode_decode_match(setup):
+    p, ctx, tiny, *_ , (m1, m2), _c, _b = setup
+    assert list(bfv.decode(ctx, m1)) == tiny.decode([int(v) for v in m1])
+    v = [int(x) for x in np.random.default_rng(5).integers(0, p.t, p.N)]
+    assert list(bfv.encode(ctx, v)) == tiny.encode(v)
+
+
+def test_encrypt_decrypt_match(setup):
+    p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
+    _eq(c1, b1)
+    _eq(c2, b2)
+    assert list(bfv.decrypt(ctx, keys, c1)) == tiny.decrypt(bkeys, b1)
+
+
+def test_linear_ops_match(setup):
+    p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
+    _eq(bfv.add(ctx, c1, c2), tiny.add(b1, b2))
+    _eq(bfv.add_plain(ctx, c1, m2), tiny.add_plain(b1, [int(v) for v in m2]))
+    _eq(bfv.mul_plain(ctx, c1, m2), tiny.mul_plain(b1, [int(v) for v in m2]))
+    for w in (0, 1, -1, 5, p.t - 2, p.t // 2 + 1):
+        _eq(bfv.mul_scalar(ctx, c1, w), tiny.mul_scalar(b1, w))
+
+
+def test_mul_relin_match(setup):
+    p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
+    d = bfv.mul(ctx, c1, c2)
+    bd = tiny.mul(b1, b2)
+    _eq(d, bd)
+    _eq(bfv.relin(ctx, d, keys.rlk), tiny.relin(bd, bkeys))
+    _eq(bfv.mul(ctx, c1, c1), tiny.mul(b1, b1))
+
+
+def test_rotate_match(setup):
+    p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
+    for step in (1, -3, bfv.ROW_SWAP):
+        g = bfv.galois_element(p.N, step)
+        _eq(bfv.rotate(ctx, c1, step, keys), tiny.rotate(b1, g, bkeys))
+
+
+def test_decrypt_of_size3_match(setup):
+    p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
+    d = bfv.mul(ctx, c1, c2)
+    assert list(bfv.decrypt(ctx, keys, d)) == tiny.decrypt(bkeys, tiny.mul(b1, b2))
