@@ -1,0 +1,208 @@
+/*
+ * liblola: BFV ciphertext arithmetic over R_q = Z_q[X]/(X^N + 1) in RNS form on
+ * one MI355X (gfx950), and the LoLa layer schedules built on it.
+ *
+ * The operations are the ones the paper (Brutzkus, Elisha, Gilad-Bachrach,
+ * "Low Latency Privacy Preserving Inference") relies on:
+ *   - Sec. 2.1 (Homomorphic Encryption): encryption E, decryption D, the
+ *     homomorphic sum and product, the plaintext ring Z_p[x]/(x^n+1) viewed as
+ *     n slots when p has a 2n-th root of unity, and the two rotations of the
+ *     2 x n/2 slot matrix (row swap, column rotation);
+ *   - Sec. 3.2.2 (Convolution vector - row major): message times scalar;
+ *   - Sec. 3.2 (vector representations and matrix-vector recipes) and Sec. 4 /
+ *     App. C (the MNIST pipeline): the layer compiler and network evaluation.
+ * Key switching (relinearisation, rotation keys) and the RNS/NTT form are how
+ * BFV realises those operations; the paper uses them through its library.
+ *
+ * Conventions for every call:
+ *   - Ownership: the caller owns every buffer.  Pointers named *_dev are device
+ *     memory on the context's GPU, *_host host memory.  The library never frees
+ *     caller memory; it owns only lola_ctx / lola_plan and their scratch.
+ *   - Asynchrony: calls enqueue work on `stream` (a hipStream_t; NULL = the
+ *     default stream) and return; device faults surface at the caller's next
+ *     synchronisation.  Calls that return host results (noted) synchronise.
+ *   - One context must not be used from two streams at once (shared scratch).
+ *   - Layouts (uint32 words, little endian):
+ *       polynomial   [L][N]       one limb (residues mod q_i) per prime
+ *       ciphertext   [size][L][N] size 2 (or 3 after lola_mul); device form is
+ *                                 the NTT (evaluation) form described below
+ *       plaintext    [N]          coefficients mod t (lola_encode output)
+ *       mul-form pt  [L][N]       from lola_plain_mul_form
+ *       add-form pt  [L][N]       from lola_plain_add_form
+ *       secret key   [L+1][N]     NTT form mod q_0..q_{L-1}, P
+ *       public key   [2][L][N]
+ *       switch key   [L][2][L+1][N]  (relinearisation or one Galois element)
+ *     Device forms are internal: NTT evaluation order with Montgomery scaling
+ *     on key and mul-form data.  lola_to_coeff / lola_*_export give the
+ *     canonical coefficient form (residues in [0, q_i)) used for comparisons.
+ *   - Errors: 0 on success, a negative LOLA_E_* code otherwise; the message of
+ *     the last error on the calling thread is lola_last_error().  Shapes are
+ *     checked against the context; pointers are not dereferenced on the host.
+ *   - Aliasing: element-wise calls (add, add_plain, mul_plain, mul_scalar) may
+ *     run in place; lola_mul, lola_relin and lola_rotate may not alias their
+ *     output with an input.
+ */
+#ifndef LOLA_H
+#define LOLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *lola_stream; /* hipStream_t */
+
+enum {
+    LOLA_OK = 0,
+    LOLA_E_INVAL = -1,       /* bad argument (null pointer, out-of-range value) */
+    LOLA_E_PARAMS = -2,      /* a modulus is not prime / not 1 mod 2N / too large; gcd(t, Q) != 1 */
+    LOLA_E_INSECURE = -3,    /* log2(Q P) above the 128-bit cap for N (ternary secret) */
+    LOLA_E_SHAPE = -4,       /* size / count does not match the context */
+    LOLA_E_NOKEY = -5,       /* a rotation needs a Galois key that was not given */
+    LOLA_E_NOMEM = -6,       /* device allocation of scratch failed */
+    LOLA_E_DEVICE = -7,      /* a HIP runtime call failed */
+    LOLA_E_UNSUPPORTED = -8  /* layer pattern or size the compiler does not handle */
+};
+
+#define LOLA_ROW_SWAP 0x7fffffff /* step value of the row swap in rotation calls */
+
+/* Parameter set.  N in {1024, 2048, 4096, 8192, 16384}; t prime, t = 1 mod 2N,
+ * t < 2^26; q[0..L-1] and P distinct primes below 2^30, each = 1 mod 2N;
+ * 1 <= L <= 12.  Unless allow_insecure, log2(Q*P) must not exceed the
+ * homomorphic-encryption standard's 128-bit classical cap for N (27, 54, 109,
+ * 218, 438 for N = 1024 ... 16384). */
+typedef struct {
+    uint32_t N;
+    uint32_t t;
+    uint32_t L;
+    const uint32_t *q; /* host array of L primes */
+    uint32_t P;
+    int allow_insecure;
+} lola_params;
+
+typedef struct lola_ctx lola_ctx;
+
+typedef struct {
+    uint32_t N, L, t, n_aux;       /* n_aux: primes of the exact product's extra basis */
+    uint64_t ct_words;             /* 2*L*N */
+    uint64_t poly_words;           /* L*N */
+    uint64_t sk_words;             /* (L+1)*N */
+    uint64_t ksk_words;            /* L*2*(L+1)*N */
+    uint64_t scratch_bytes;        /* current scratch arena */
+} lola_info;
+
+/* ---------------------------------------------------------------- context */
+/* Validates params (errors above), builds NTT tables for every prime, the
+ * exact mixed-radix constants, and selects the auxiliary basis.  Device =
+ * HIP device ordinal; the context's calls must run with that device current. */
+int lola_ctx_create(const lola_params *params, int device, lola_ctx **out);
+void lola_ctx_destroy(lola_ctx *ctx);
+int lola_ctx_info(const lola_ctx *ctx, lola_info *info);
+/* Pre-sizes the scratch arena for batches of up to n ciphertexts so later
+ * calls do not allocate (e.g. before stream capture). */
+int lola_reserve(lola_ctx *ctx, uint32_t n_ct);
+
+/* Galois element of a rotation: step > 0 rotates every slot row left by step
+ * (output slot (r,i) takes input slot (r, i+step)), step < 0 right, and
+ * LOLA_ROW_SWAP swaps the two rows (Sec. 2.1).  Returns 3^step mod 2N or
+ * 2N-1; 0 on a bad N. */
+uint32_t lola_galois_element(uint32_t N, int32_t step);
+
+/* ------------------------------------------------------------------- keys */
+/* Random values come from ChaCha20 (RFC 8439) with key = (seed lo, seed hi,
+ * 0...), nonce = (domain, object, limb), one 64-bit word per coefficient;
+ * uniform = word mod m, ternary = word mod 3 - 1, error = centred binomial
+ * popcount(w & 0x1fffff) - popcount((w >> 21) & 0x1fffff). */
+int lola_keygen_secret(lola_ctx *ctx, uint64_t seed, uint32_t *sk_dev, lola_stream stream);
+int lola_keygen_public(lola_ctx *ctx, uint64_t seed, const uint32_t *sk_dev, uint32_t *pk_dev,
+                       lola_stream stream);
+/* Switching key from s^2 (galois = 0) or from sigma_galois(s) to s. */
+int lola_keygen_switch(lola_ctx *ctx, uint64_t seed, const uint32_t *sk_dev, uint32_t galois,
+                       uint32_t *ksk_dev, lola_stream stream);
+
+/* ------------------------------------------------------------- plaintexts */
+/* Slot encoding (Sec. 2.1 batching): slot (r, i) = r*N/2 + i of the
+ * plaintext m is m(zeta^e), e = (2N-1)^r 3^i mod 2N, zeta the smallest
+ * primitive 2N-th root of unity mod t.  slots_dev: N int64 (any integers,
+ * reduced mod t); pt_dev: N words in [0, t). */
+int lola_encode(lola_ctx *ctx, const int64_t *slots_dev, uint32_t *pt_dev, lola_stream stream);
+int lola_decode(lola_ctx *ctx, const uint32_t *pt_dev, int64_t *slots_dev, lola_stream stream);
+/* Plaintext forms: mul form = centred lift [m]_t per prime (for
+ * lola_mul_plain); add form = floor(Q/t) * m per prime (for lola_add_plain). */
+int lola_plain_mul_form(lola_ctx *ctx, const uint32_t *pt_dev, uint32_t *out_dev, lola_stream stream);
+int lola_plain_add_form(lola_ctx *ctx, const uint32_t *pt_dev, uint32_t *out_dev, lola_stream stream);
+
+/* ------------------------------------------------------ encrypt / decrypt */
+/* c = (pk0 u + e1 + floor(Q/t) m, pk1 u + e2), u ternary, e1, e2 errors drawn
+ * with the seed and the object id `nonce`. */
+int lola_encrypt(lola_ctx *ctx, const uint32_t *pk_dev, const uint32_t *pt_dev, uint64_t seed,
+                 uint32_t nonce, uint32_t *ct_dev, lola_stream stream);
+/* m_k = round(t x_k / Q) mod t, x = c0 + c1 s (+ c2 s^2) mod Q, computed
+ * exactly (mixed-radix, no floating point).  size = 2 or 3. */
+int lola_decrypt(lola_ctx *ctx, const uint32_t *sk_dev, const uint32_t *ct_dev, uint32_t size,
+                 uint32_t *pt_dev, lola_stream stream);
+
+/* ------------------------------------------------------------- operations */
+/* out = a + b.  `size` components (2 or 3). */
+int lola_add(lola_ctx *ctx, const uint32_t *a_dev, const uint32_t *b_dev, uint32_t size,
+             uint32_t *out_dev, lola_stream stream);
+/* out = (c0 + floor(Q/t) m, c1). */
+int lola_add_plain(lola_ctx *ctx, const uint32_t *ct_dev, const uint32_t *pt_add_dev,
+                   uint32_t *out_dev, lola_stream stream);
+/* out = (c0 [m]_t, c1 [m]_t). */
+int lola_mul_plain(lola_ctx *ctx, const uint32_t *ct_dev, const uint32_t *pt_mul_dev,
+                   uint32_t *out_dev, lola_stream stream);
+/* out = [w]_t * ct (message times scalar, Sec. 3.2.2). */
+int lola_mul_scalar(lola_ctx *ctx, const uint32_t *ct_dev, int64_t w, uint32_t *out_dev,
+                    lola_stream stream);
+/* Size-3 product: d_j = round(t (a (x) b)_j / Q) mod Q for the tensor of the
+ * centred lifts, computed exactly. */
+int lola_mul(lola_ctx *ctx, const uint32_t *a_dev, const uint32_t *b_dev, uint32_t *out3_dev,
+             lola_stream stream);
+/* (d0, d1) + KeySwitch_{s^2 -> s}(d2). */
+int lola_relin(lola_ctx *ctx, const uint32_t *rlk_dev, const uint32_t *in3_dev, uint32_t *out_dev,
+               lola_stream stream);
+/* (sigma_g(c0), 0) + KeySwitch_{sigma_g(s) -> s}(sigma_g(c1)). */
+int lola_rotate(lola_ctx *ctx, const uint32_t *gk_dev, uint32_t galois, const uint32_t *ct_dev,
+                uint32_t *out_dev, lola_stream stream);
+
+/* Batched key switching: n independent rotations / relinearisations in one
+ * set of launches (uneven per-ciphertext work is just more descriptors). */
+typedef struct {
+    const uint32_t *in_dev;  /* rotation: ciphertext [2][L][N]; relin: [3][L][N] */
+    const uint32_t *key_dev; /* switching key */
+    uint32_t *out_dev;       /* [2][L][N] */
+    uint32_t galois;         /* Galois element; 0 = relinearisation */
+    uint32_t pad;
+} lola_ks_desc;
+int lola_keyswitch_batch(lola_ctx *ctx, const lola_ks_desc *descs_host, uint32_t n,
+                         lola_stream stream);
+
+/* ------------------------------------------------------ canonical forms */
+/* Device form <-> coefficient form for n_polys polynomials [n][L][N]. */
+int lola_to_coeff(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n_polys, uint32_t *out_dev,
+                  lola_stream stream);
+int lola_from_coeff(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n_polys, uint32_t *out_dev,
+                    lola_stream stream);
+/* Keys in coefficient form: secret [L+1][N] (residues of the ternary s),
+ * public [2][L][N], switching [L][2][L+1][N]. */
+int lola_export_sk(lola_ctx *ctx, const uint32_t *sk_dev, uint32_t *out_dev, lola_stream stream);
+int lola_export_pk(lola_ctx *ctx, const uint32_t *pk_dev, uint32_t *out_dev, lola_stream stream);
+int lola_export_ksk(lola_ctx *ctx, const uint32_t *ksk_dev, uint32_t *out_dev, lola_stream stream);
+
+/* Diagnostic: forward or inverse NTT of n limbs, limb k modulo prime index
+ * prime_idx_host[k] (0..L-1 ciphertext primes, L = P, L+1+n_aux = t), natural
+ * coefficient order <-> bit-reversed evaluation order:
+ * out[k] = a(psi^(2 brv(k) + 1)) with psi the smallest primitive 2N-th root. */
+int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uint32_t n_limbs,
+                   const uint32_t *prime_idx_host, int inverse, lola_stream stream);
+
+const char *lola_strerror(int code);
+const char *lola_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOLA_H */

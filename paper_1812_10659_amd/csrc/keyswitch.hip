@@ -1,0 +1,262 @@
+// Key switching (relinearisation and Galois rotations), batched over jobs.
+//
+// For a polynomial x (NTT form, [L][N]) and a key for s' -> s, with digits
+// D_i = x mod q_i in [0, q_i):
+//   u_m = sum_i D_i * key_i   modulo every q_j and P      (key inner product)
+//   out_j = (u_j - [u_P]_P) * P^-1 mod q_j                 (mod-down by P)
+// A rotation by the Galois element g applies the automorphism first, which in
+// the NTT domain is a fixed permutation of evaluation points, so it is folded
+// into the loads of x and of the c0 term.
+//
+// Three launches per batch, one workgroup per limb-sized unit of work:
+//   ks_digits   (L per job):    gather sigma_g(x_i) (kept), INTT -> D_i (coefficients)
+//   ks_inner    (L+1 per job):  for target modulus m_j: for each digit i,
+//                               reduce D_i mod m_j, NTT (i == j reuses x_i),
+//                               multiply-accumulate with the key; for P the
+//                               two sums are also brought back to coefficients
+//   ks_moddown  (2L per job):   lift [u_P]_P into q_j, NTT, subtract, times
+//                               P^-1, add the c0 (or d0 / d1) term.
+#include "lola_internal.hpp"
+#include "ntt_core.hpp"
+
+namespace lola {
+
+struct KsJob {
+    const uint32_t *x;     // [L][N] polynomial to switch (NTT form, before sigma_g)
+    const uint32_t *key;   // [L][2][L+1][N] Montgomery NTT form
+    const uint32_t *add0;  // [L][N] added to component 0 (sigma_g applied), or null
+    const uint32_t *add1;  // [L][N] added to component 1, or null
+    uint32_t *out;         // [2][L][N]
+    uint32_t *scratch;     // (4L + 2) N words: D [L][N], Xp [L][N], U [2][L][N], UP [2][N]
+    uint32_t galois;       // 0/1: no automorphism
+    uint32_t pad;
+};
+
+__device__ __forceinline__ uint32_t perm_src(uint32_t idx, uint32_t g, uint32_t logN) {
+    return g > 1 ? galois_src_index(idx, g, logN) : idx;
+}
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(
+    const KsJob *__restrict__ jobs, uint32_t L, const ModConst *__restrict__ mcs,
+    const uint32_t *__restrict__ itw, const uint32_t *__restrict__ itwp) {
+    __shared__ uint32_t sh[1 << LOGN];
+    const KsJob job = jobs[blockIdx.y];
+    const uint32_t i = blockIdx.x;
+    const int tid = threadIdx.x;
+    const ModConst mc = mcs[i];
+    const uint32_t *xi = job.x + ((size_t)i << LOGN);
+    uint32_t *Xp = job.scratch + ((size_t)(L + i) << LOGN);
+    uint32_t x[NTT_E];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) {
+        const int idx = spectral_index<LOGN>(tid, r);
+        x[r] = xi[perm_src(idx, job.galois, LOGN)];
+        Xp[idx] = x[r];  // sigma_g(x_i) in NTT form: the digit's own-modulus transform
+    }
+    ntt_inv_regs<LOGN>(x, tid, sh, itw + ((size_t)i << LOGN), itwp + ((size_t)i << LOGN), mc);
+    uint32_t *D = job.scratch + ((size_t)i << LOGN);
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) D[natural_index<LOGN>(tid, r)] = x[r];
+}
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(
+    const KsJob *__restrict__ jobs, uint32_t L, const ModConst *__restrict__ mcs,
+    const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twp, const uint32_t *__restrict__ itw,
+    const uint32_t *__restrict__ itwp) {
+    constexpr int N = 1 << LOGN;
+    __shared__ uint32_t sh[N];
+    const KsJob job = jobs[blockIdx.y];
+    const uint32_t j = blockIdx.x;  // target modulus: q_j (j < L) or P (j == L)
+    const ModConst mc = mcs[j];
+    const size_t M = L + 1;
+    uint32_t a0[NTT_E], a1[NTT_E];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
+    for (uint32_t i = 0; i < L; ++i) {
+        // Every index below depends only on the thread id; an opaque copy per
+        // iteration keeps the compiler from hoisting all of them (and the
+        // transform's LDS addresses) out of the loop, which would not fit in
+        // the 128 registers a 1024-thread workgroup allows.
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        uint32_t x[NTT_E];
+        if (i == j) {
+            const uint32_t *Xp = job.scratch + ((size_t)(L + i) << LOGN);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) x[r] = Xp[spectral_index<LOGN>(tid, r)];
+        } else {
+            const uint32_t *D = job.scratch + ((size_t)i << LOGN);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(D[natural_index<LOGN>(tid, r)], mc.q, mc.one_shoup);
+            // The twiddle table does not change with i; an opaque copy of j
+            // keeps the compiler from hoisting every twiddle load of the
+            // transform out of the loop (that would pin ~120 registers).
+            uint32_t jj = j;
+            asm volatile("" : "+s"(jj));
+            ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), twp + ((size_t)jj << LOGN), mc.q);
+        }
+        // Key offsets pass through an opaque copy placed after the transform,
+        // so the 32 key loads are not scheduled ahead of it.
+        uint32_t koff = i * 2 * (uint32_t)M + j;
+        asm volatile("" : "+s"(koff));
+        const uint32_t *kb = job.key + ((size_t)koff << LOGN);
+        const uint32_t *ka = job.key + ((size_t)(koff + M) << LOGN);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) {
+            const int idx = spectral_index<LOGN>(tid, r);
+            a0[r] = add_mod(a0[r], mont_mul(x[r], kb[idx], mc.q, mc.qneg_inv), mc.q);
+            a1[r] = add_mod(a1[r], mont_mul(x[r], ka[idx], mc.q, mc.qneg_inv), mc.q);
+        }
+    }
+    const int tid = threadIdx.x;
+    if (j < L) {
+        uint32_t *U0 = job.scratch + ((size_t)(2 * L + j) << LOGN);
+        uint32_t *U1 = job.scratch + ((size_t)(3 * L + j) << LOGN);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) {
+            const int idx = spectral_index<LOGN>(tid, r);
+            U0[idx] = a0[r];
+            U1[idx] = a1[r];
+        }
+    } else {
+        uint32_t *UP = job.scratch + ((size_t)(4 * L) << LOGN);
+        const uint32_t *it = itw + ((size_t)j << LOGN), *itp = itwp + ((size_t)j << LOGN);
+        ntt_inv_regs<LOGN>(a0, tid, sh, it, itp, mc);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) UP[natural_index<LOGN>(tid, r)] = a0[r];
+        int tid2 = tid;
+        asm volatile("" : "+v"(tid2));
+        uint32_t jj = j;
+        asm volatile("" : "+s"(jj));
+        ntt_inv_regs<LOGN>(a1, tid2, sh, itw + ((size_t)jj << LOGN), itwp + ((size_t)jj << LOGN), mc);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) UP[N + natural_index<LOGN>(tid2, r)] = a1[r];
+    }
+}
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(
+    const KsJob *__restrict__ jobs, uint32_t L, const ModConst *__restrict__ mcs,
+    const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twp, const MrcConst *__restrict__ mrc) {
+    __shared__ uint32_t sh[1 << LOGN];
+    const KsJob job = jobs[blockIdx.z];
+    const uint32_t j = blockIdx.x, c = blockIdx.y;
+    const int tid = threadIdx.x;
+    const ModConst mc = mcs[j];
+    const uint32_t P = mcs[L].q, halfP = P >> 1;
+    const uint32_t Pq = mrc->Pq[j];
+    const uint32_t *UP = job.scratch + ((size_t)(4 * L + c) << LOGN);
+    uint32_t x[NTT_E];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) {
+        const uint32_t v = UP[natural_index<LOGN>(tid, r)];
+        const uint32_t vr = reduce32(v, mc.q, mc.one_shoup);
+        x[r] = v > halfP ? sub_mod(vr, Pq, mc.q) : vr;  // [u_P]_P mod q_j
+    }
+    ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)j << LOGN), twp + ((size_t)j << LOGN), mc.q);
+    const uint32_t *U = job.scratch + ((size_t)((2 + c) * L + j) << LOGN);
+    const uint32_t *add = c == 0 ? job.add0 : job.add1;
+    const uint32_t g = c == 0 ? job.galois : 0u;
+    const uint32_t pinv = mrc->Pinvq[j], pinvp = mrc->Pinvqp[j];
+    uint32_t *out = job.out + ((size_t)(c * L + j) << LOGN);
+    const uint32_t *addj = add ? add + ((size_t)j << LOGN) : nullptr;
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) {
+        const int idx = spectral_index<LOGN>(tid, r);
+        uint32_t w = shoup(sub_mod(U[idx], x[r], mc.q), pinv, pinvp, mc.q);
+        if (addj) w = add_mod(w, addj[perm_src(idx, g, LOGN)], mc.q);
+        out[idx] = w;
+    }
+}
+
+static size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }
+
+int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
+    const uint32_t L = ctx->L;
+    const dim3 block(ctx->N / NTT_E);
+#define LOLA_KS_CASE(LG)                                                                                    \
+    case LG:                                                                                                \
+        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(L, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_itw,  \
+                           ctx->d_itwp);                                                                     \
+        hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(L + 1, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_tw, \
+                           ctx->d_twp, ctx->d_itw, ctx->d_itwp);                                             \
+        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(L, 2, n), block, 0, s, d_jobs, L, ctx->d_mc,         \
+                           ctx->d_tw, ctx->d_twp, ctx->d_mrc);                                               \
+        break;
+    switch (ctx->logN) {
+        LOLA_KS_CASE(10)
+        LOLA_KS_CASE(11)
+        LOLA_KS_CASE(12)
+        LOLA_KS_CASE(13)
+        LOLA_KS_CASE(14)
+        default: return set_error(LOLA_E_PARAMS, "unsupported N");
+    }
+#undef LOLA_KS_CASE
+    LOLA_HIP(hipGetLastError());
+    return LOLA_OK;
+}
+
+// Jobs per launch: bounds the scratch arena ((4L+2) N words per job).
+static constexpr uint32_t KS_CHUNK = 128;
+
+int keyswitch_host_jobs(lola_ctx *ctx, std::vector<KsJob> &jobs, hipStream_t s) {
+    const size_t per = ks_scratch_words(ctx);
+    for (size_t off = 0; off < jobs.size(); off += KS_CHUNK) {
+        const uint32_t n = (uint32_t)std::min<size_t>(KS_CHUNK, jobs.size() - off);
+        void *buf = nullptr;
+        int rc = scratch_get(ctx, per * n * 4, &buf);
+        if (rc) return rc;
+        for (uint32_t k = 0; k < n; ++k) jobs[off + k].scratch = (uint32_t *)buf + per * k;
+        void *d = nullptr;
+        if ((rc = desc_upload(ctx, jobs.data() + off, n * sizeof(KsJob), s, &d))) return rc;
+        if ((rc = launch_keyswitch(ctx, (const KsJob *)d, n, s))) return rc;
+    }
+    return LOLA_OK;
+}
+
+}  // namespace lola
+
+using namespace lola;
+
+extern "C" {
+
+int lola_reserve(lola_ctx *ctx, uint32_t n_ct) {
+    if (!ctx) return set_error(LOLA_E_INVAL, "null argument");
+    void *buf = nullptr;
+    const size_t per = std::max<size_t>(ks_scratch_words(ctx), (size_t)(4 * 2 + 3) * (ctx->L + ctx->nB + 1) * ctx->N);
+    return scratch_get(ctx, per * std::min<uint32_t>(std::max<uint32_t>(n_ct, 1), KS_CHUNK) * 4, &buf);
+}
+
+int lola_keyswitch_batch(lola_ctx *ctx, const lola_ks_desc *d, uint32_t n, lola_stream stream) {
+    if (!ctx || (!d && n)) return set_error(LOLA_E_INVAL, "null argument");
+    const size_t P = (size_t)ctx->L * ctx->N;
+    std::vector<KsJob> jobs(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        if (!d[k].in_dev || !d[k].key_dev || !d[k].out_dev) return set_error(LOLA_E_NOKEY, "null key or buffer in batch");
+        if (d[k].galois != 0 && (!(d[k].galois & 1) || d[k].galois >= 2 * ctx->N))
+            return set_error(LOLA_E_INVAL, "bad Galois element");
+        if (d[k].galois == 0)
+            jobs[k] = KsJob{d[k].in_dev + 2 * P, d[k].key_dev, d[k].in_dev, d[k].in_dev + P, d[k].out_dev, nullptr, 0, 0};
+        else
+            jobs[k] = KsJob{d[k].in_dev + P, d[k].key_dev, d[k].in_dev, nullptr, d[k].out_dev, nullptr, d[k].galois, 0};
+    }
+    return keyswitch_host_jobs(ctx, jobs, (hipStream_t)stream);
+}
+
+int lola_relin(lola_ctx *ctx, const uint32_t *rlk, const uint32_t *in3, uint32_t *out, lola_stream stream) {
+    if (!rlk) return set_error(LOLA_E_NOKEY, "missing relinearisation key");
+    lola_ks_desc d{in3, rlk, out, 0, 0};
+    return lola_keyswitch_batch(ctx, &d, 1, stream);
+}
+
+int lola_rotate(lola_ctx *ctx, const uint32_t *gk, uint32_t galois, const uint32_t *ct, uint32_t *out,
+                lola_stream stream) {
+    if (!gk) return set_error(LOLA_E_NOKEY, "missing Galois key");
+    if (galois == 0) return set_error(LOLA_E_INVAL, "Galois element 0");
+    lola_ks_desc d{ct, gk, out, galois, 0};
+    return lola_keyswitch_batch(ctx, &d, 1, stream);
+}
+
+}  // extern "C"

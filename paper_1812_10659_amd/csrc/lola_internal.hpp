@@ -1,0 +1,144 @@
+// Internal definitions of the LoLa BFV library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lola.h"
+#include "modarith.hpp"
+
+namespace lola {
+
+constexpr int MAXL = 12;   // ciphertext primes
+constexpr int MAXB = 14;   // auxiliary primes of the exact ct x ct product
+
+// Constants of the exact mixed-radix conversions, on the device.
+//   Q basis: primes q_0..q_{L-1};  B basis: primes b_0..b_{nB-1}.
+struct MrcConst {
+    uint32_t L, nB, t, pad;
+    // Garner: q_k^-1 mod q_i (k < i), Shoup pairs.   [i][k]
+    uint32_t invQ[MAXL][MAXL], invQp[MAXL][MAXL];
+    // W_k = q_0...q_{k-1} reduced mod b_j, Shoup pairs. [j][k]
+    uint32_t wQb[MAXB][MAXL], wQbp[MAXB][MAXL];
+    // W_k mod t (decrypt) [k]
+    uint32_t wQt[MAXL], wQtp[MAXL];
+    // MRC digits of (Q-1)/2
+    uint32_t hQ[MAXL];
+    // Q mod b_j and Q^-1 mod b_j (Shoup pairs)
+    uint32_t Qb[MAXB], Qbp[MAXB], Qinvb[MAXB], Qinvbp[MAXB];
+    // t mod q_i, t mod b_j (Shoup pairs)
+    uint32_t tq[MAXL], tqp[MAXL], tb[MAXB], tbp[MAXB];
+    // Q^-1 mod t (Shoup pair), Delta = floor(Q/t) mod q_i (Shoup pairs)
+    uint32_t Qinvt, Qinvtp;
+    uint32_t deltaq[MAXL], deltaqp[MAXL];
+    // B-side Garner: b_k^-1 mod b_j (k < j)   [j][k]
+    uint32_t invB[MAXB][MAXB], invBp[MAXB][MAXB];
+    // V_k = b_0...b_{k-1} mod q_i   [i][k]
+    uint32_t wBq[MAXL][MAXB], wBqp[MAXL][MAXB];
+    uint32_t hB[MAXB];            // MRC digits of (B-1)/2
+    uint32_t Bq[MAXL];            // B mod q_i
+    // key switching: P mod q_i (Shoup), P^-1 mod q_i (Shoup)
+    uint32_t Pq[MAXL], Pqp[MAXL], Pinvq[MAXL], Pinvqp[MAXL];
+};
+
+}  // namespace lola
+
+// Prime index layout inside a context: [0, L) ciphertext primes, L = special
+// prime P, [L+1, L+1+nB) auxiliary primes, L+1+nB = plaintext modulus t.
+struct lola_ctx {
+    int device = 0;
+    uint32_t N = 0, logN = 0;
+    uint32_t L = 0, nB = 0;
+    uint32_t t = 0;
+    std::vector<uint32_t> primes;        // all moduli, layout above
+    std::vector<lola::ModConst> mc_host;
+    lola::MrcConst mrc_host{};
+    // device tables
+    lola::ModConst *d_mc = nullptr;
+    lola::MrcConst *d_mrc = nullptr;
+    uint32_t *d_tw = nullptr, *d_twp = nullptr, *d_itw = nullptr, *d_itwp = nullptr;  // [nprimes][N]
+    uint32_t *d_slotpos = nullptr;       // slot s -> spectral index mod t
+    // scratch arena
+    void *d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    // descriptor staging for batched launches: a pinned host ring copied to a
+    // device ring; slabs are reused once the event recorded when leaving them
+    // has completed.
+    static constexpr int RING_SLABS = 16;
+    static constexpr size_t RING_SLAB = 256 * 1024;
+    uint8_t *h_ring = nullptr, *d_ring = nullptr;
+    size_t ring_off = 0;
+    hipEvent_t ring_ev[RING_SLABS] = {};
+    bool ring_ev_valid[RING_SLABS] = {};
+    uint32_t idxP() const { return L; }
+    uint32_t idxB(uint32_t j) const { return L + 1 + j; }
+    uint32_t idxT() const { return L + 1 + nB; }
+    uint32_t nprimes() const { return L + 2 + nB; }
+};
+
+namespace lola {
+
+// error reporting (thread-local message)
+int set_error(int code, const std::string &msg);
+int check_hip(hipError_t e, const char *what);
+#define LOLA_HIP(call)                                         \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return ::lola::check_hip(_e, #call); \
+    } while (0)
+
+// scratch arena (device); grows with a device synchronisation
+int scratch_get(lola_ctx *ctx, size_t bytes, void **out);
+// descriptor upload area (device), copied asynchronously on the stream
+int desc_upload(lola_ctx *ctx, const void *host, size_t bytes, hipStream_t s, void **dev);
+
+// host arithmetic helpers
+uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t m);
+uint64_t powmod_host(uint64_t a, uint64_t e, uint64_t m);
+uint64_t invmod_host(uint64_t a, uint64_t m);
+inline uint32_t shoup_companion(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+
+// automorphism index map in the NTT domain: output index j reads input brv-index
+LOLA_HD uint32_t galois_src_index(uint32_t j, uint32_t g, uint32_t logN) {
+    uint32_t N = 1u << logN;
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t bj = __brev(j) >> (32 - logN);
+#else
+    uint32_t bj = 0;
+    for (uint32_t b = 0; b < logN; ++b)
+        if (j & (1u << b)) bj |= 1u << (logN - 1 - b);
+#endif
+    uint32_t e = (uint32_t)(((uint64_t)g * (2 * bj + 1)) & (2 * N - 1));
+    uint32_t k = (e - 1) >> 1;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __brev(k) >> (32 - logN);
+#else
+    uint32_t r = 0;
+    for (uint32_t b = 0; b < logN; ++b)
+        if (k & (1u << b)) r |= 1u << (logN - 1 - b);
+    return r;
+#endif
+}
+
+// ---- launch helpers implemented in the .hip files ----
+struct NttJob {
+    const uint32_t *src;
+    uint32_t *dst;
+    uint32_t prime;     // prime index in the context
+    uint32_t flags;     // NTT_* below
+};
+enum : uint32_t {
+    NTT_INVERSE = 1u,
+    NTT_SRC_SIGNED_T = 2u,   // source holds residues mod t; lift centred before reducing
+    NTT_SRC_REDUCE = 4u,     // source values may exceed the prime: reduce first
+    NTT_TO_MONT = 8u,        // multiply the output by 2^32 (Montgomery form)
+    NTT_FROM_MONT = 16u,     // multiply the input by 2^-32 before an inverse transform
+    NTT_MUL_DELTA = 32u,     // multiply the forward output by floor(Q/t) mod q (prime < L)
+    NTT_SRC_SIGNED32 = 64u,  // source holds small signed int32 values (|v| < q)
+};
+int launch_ntt_jobs(lola_ctx *ctx, const NttJob *host_jobs, int n, hipStream_t s);
+
+}  // namespace lola

@@ -1,0 +1,297 @@
+"""Python binding of liblola (include/lola.h): argument marshalling only.
+
+Every operation runs in the HIP library; this module converts torch device
+tensors to pointers, passes the current HIP stream, and raises LolaError on a
+non-zero return code.  torch provides device memory and streams.  Buffers are
+int32 tensors holding the library's uint32 words.
+
+The library must be built (paper_1812_10659_amd/build_lib.py, or
+__graft_entry__.build()); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblola.so")
+
+ROW_SWAP = 0x7FFFFFFF
+
+E_CODES = {0: "OK", -1: "E_INVAL", -2: "E_PARAMS", -3: "E_INSECURE", -4: "E_SHAPE", -5: "E_NOKEY",
+           -6: "E_NOMEM", -7: "E_DEVICE", -8: "E_UNSUPPORTED"}
+
+
+class LolaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{E_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint32), ("L", ctypes.c_uint32),
+                ("q", ctypes.POINTER(ctypes.c_uint32)), ("P", ctypes.c_uint32),
+                ("allow_insecure", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("L", ctypes.c_uint32), ("t", ctypes.c_uint32),
+                ("n_aux", ctypes.c_uint32), ("ct_words", ctypes.c_uint64),
+                ("poly_words", ctypes.c_uint64), ("sk_words", ctypes.c_uint64),
+                ("ksk_words", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64)]
+
+
+class KsDesc(ctypes.Structure):
+    _fields_ = [("in_dev", ctypes.c_void_p), ("key_dev", ctypes.c_void_p), ("out_dev", ctypes.c_void_p),
+                ("galois", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1812_10659_amd/build_lib.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32, i64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
+        sig = {
+            "lola_ctx_create": [ctypes.POINTER(_Params), i32, ctypes.POINTER(vp)],
+            "lola_ctx_destroy": [vp],
+            "lola_ctx_info": [vp, ctypes.POINTER(_Info)],
+            "lola_reserve": [vp, u32],
+            "lola_galois_element": [u32, ctypes.c_int32],
+            "lola_keygen_secret": [vp, u64, vp, vp],
+            "lola_keygen_public": [vp, u64, vp, vp, vp],
+            "lola_keygen_switch": [vp, u64, vp, u32, vp, vp],
+            "lola_encode": [vp, vp, vp, vp],
+            "lola_decode": [vp, vp, vp, vp],
+            "lola_plain_mul_form": [vp, vp, vp, vp],
+            "lola_plain_add_form": [vp, vp, vp, vp],
+            "lola_encrypt": [vp, vp, vp, u64, u32, vp, vp],
+            "lola_decrypt": [vp, vp, vp, u32, vp, vp],
+            "lola_add": [vp, vp, vp, u32, vp, vp],
+            "lola_add_plain": [vp, vp, vp, vp, vp],
+            "lola_mul_plain": [vp, vp, vp, vp, vp],
+            "lola_mul_scalar": [vp, vp, i64, vp, vp],
+            "lola_mul": [vp, vp, vp, vp, vp],
+            "lola_relin": [vp, vp, vp, vp, vp],
+            "lola_rotate": [vp, vp, u32, vp, vp, vp],
+            "lola_keyswitch_batch": [vp, ctypes.POINTER(KsDesc), u32, vp],
+            "lola_to_coeff": [vp, vp, u32, vp, vp],
+            "lola_from_coeff": [vp, vp, u32, vp, vp],
+            "lola_export_sk": [vp, vp, vp, vp],
+            "lola_export_pk": [vp, vp, vp, vp],
+            "lola_export_ksk": [vp, vp, vp, vp],
+            "lola_ntt_limbs": [vp, vp, vp, u32, ctypes.POINTER(u32), i32, vp],
+            "lola_strerror": [i32],
+            "lola_last_error": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.lola_ctx_destroy.restype = None
+        L.lola_galois_element.restype = u32
+        L.lola_strerror.restype = ctypes.c_char_p
+        L.lola_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise LolaError(rc, lib().lola_last_error().decode())
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def galois_element(N: int, step) -> int:
+    return int(lib().lola_galois_element(N, ROW_SWAP if step == "row_swap" else int(step)))
+
+
+class Context:
+    """lola_ctx for one parameter set (N, t, q, P) on one device."""
+
+    def __init__(self, params, device: int = 0):
+        self.params = params
+        self.device = torch.device("cuda", device)
+        q = (ctypes.c_uint32 * len(params.q))(*params.q)
+        p = _Params(params.N, params.t, len(params.q), q, params.P, int(getattr(params, "insecure_ok", False)))
+        h = ctypes.c_void_p()
+        _check(lib().lola_ctx_create(ctypes.byref(p), device, ctypes.byref(h)))
+        self.h = h
+        info = _Info()
+        _check(lib().lola_ctx_info(self.h, ctypes.byref(info)))
+        self.N, self.L, self.t, self.n_aux = info.N, info.L, info.t, info.n_aux
+        self.ksk_words = info.ksk_words
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lola_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 (interpreter shutdown)
+            pass
+
+    # ---- buffers
+    def empty(self, *shape) -> torch.Tensor:
+        return torch.empty(*shape, dtype=torch.int32, device=self.device)
+
+    def empty_ct(self, size: int = 2) -> torch.Tensor:
+        return self.empty(size, self.L, self.N)
+
+    def reserve(self, n_ct: int) -> None:
+        _check(lib().lola_reserve(self.h, n_ct))
+
+    # ---- keys
+    def keygen_secret(self, seed: int) -> torch.Tensor:
+        sk = self.empty(self.L + 1, self.N)
+        _check(lib().lola_keygen_secret(self.h, seed, _p(sk), _stream()))
+        return sk
+
+    def keygen_public(self, seed: int, sk: torch.Tensor) -> torch.Tensor:
+        pk = self.empty(2, self.L, self.N)
+        _check(lib().lola_keygen_public(self.h, seed, _p(sk), _p(pk), _stream()))
+        return pk
+
+    def keygen_switch(self, seed: int, sk: torch.Tensor, galois: int) -> torch.Tensor:
+        k = self.empty(self.L, 2, self.L + 1, self.N)
+        _check(lib().lola_keygen_switch(self.h, seed, _p(sk), galois, _p(k), _stream()))
+        return k
+
+    # ---- plaintexts
+    def encode(self, slots) -> torch.Tensor:
+        s = torch.as_tensor(np.asarray(slots, dtype=np.int64)).to(self.device)
+        pt = self.empty(self.N)
+        _check(lib().lola_encode(self.h, _p(s), _p(pt), _stream()))
+        return pt
+
+    def decode(self, pt: torch.Tensor) -> np.ndarray:
+        s = torch.empty(self.N, dtype=torch.int64, device=self.device)
+        _check(lib().lola_decode(self.h, _p(pt), _p(s), _stream()))
+        return s.cpu().numpy()
+
+    def plain_mul_form(self, pt: torch.Tensor) -> torch.Tensor:
+        out = self.empty(self.L, self.N)
+        _check(lib().lola_plain_mul_form(self.h, _p(pt), _p(out), _stream()))
+        return out
+
+    def plain_add_form(self, pt: torch.Tensor) -> torch.Tensor:
+        out = self.empty(self.L, self.N)
+        _check(lib().lola_plain_add_form(self.h, _p(pt), _p(out), _stream()))
+        return out
+
+    # ---- encrypt / decrypt
+    def encrypt(self, pk, pt, seed: int, nonce: int) -> torch.Tensor:
+        ct = self.empty_ct()
+        _check(lib().lola_encrypt(self.h, _p(pk), _p(pt), seed, nonce, _p(ct), _stream()))
+        return ct
+
+    def decrypt(self, sk, ct) -> torch.Tensor:
+        pt = self.empty(self.N)
+        _check(lib().lola_decrypt(self.h, _p(sk), _p(ct), ct.shape[0], _p(pt), _stream()))
+        return pt
+
+    # ---- operations
+    def add(self, a, b, out=None):
+        out = self.empty_ct(a.shape[0]) if out is None else out
+        _check(lib().lola_add(self.h, _p(a), _p(b), a.shape[0], _p(out), _stream()))
+        return out
+
+    def add_plain(self, ct, pta, out=None):
+        out = self.empty_ct() if out is None else out
+        _check(lib().lola_add_plain(self.h, _p(ct), _p(pta), _p(out), _stream()))
+        return out
+
+    def mul_plain(self, ct, ptm, out=None):
+        out = self.empty_ct() if out is None else out
+        _check(lib().lola_mul_plain(self.h, _p(ct), _p(ptm), _p(out), _stream()))
+        return out
+
+    def mul_scalar(self, ct, w: int, out=None):
+        out = self.empty_ct() if out is None else out
+        _check(lib().lola_mul_scalar(self.h, _p(ct), int(w), _p(out), _stream()))
+        return out
+
+    def mul(self, a, b):
+        out = self.empty_ct(3)
+        _check(lib().lola_mul(self.h, _p(a), _p(b), _p(out), _stream()))
+        return out
+
+    def relin(self, rlk, ct3):
+        out = self.empty_ct()
+        _check(lib().lola_relin(self.h, _p(rlk), _p(ct3), _p(out), _stream()))
+        return out
+
+    def rotate(self, gk, galois: int, ct):
+        out = self.empty_ct()
+        _check(lib().lola_rotate(self.h, _p(gk), galois, _p(ct), _p(out), _stream()))
+        return out
+
+    def keyswitch_batch(self, items: Sequence) -> list:
+        """items: (input ct, key, galois) with galois 0 for relinearisation."""
+        outs = [self.empty_ct() for _ in items]
+        arr = (KsDesc * len(items))()
+        for k, (ct, key, g) in enumerate(items):
+            arr[k] = KsDesc(ct.data_ptr(), key.data_ptr(), outs[k].data_ptr(), g, 0)
+        _check(lib().lola_keyswitch_batch(self.h, arr, len(items), _stream()))
+        return outs
+
+    # ---- canonical forms
+    def to_coeff(self, x: torch.Tensor) -> torch.Tensor:
+        n = x.numel() // (self.L * self.N)
+        out = torch.empty_like(x)
+        _check(lib().lola_to_coeff(self.h, _p(x), n, _p(out), _stream()))
+        return out
+
+    def from_coeff(self, x: torch.Tensor) -> torch.Tensor:
+        n = x.numel() // (self.L * self.N)
+        out = torch.empty_like(x)
+        _check(lib().lola_from_coeff(self.h, _p(x), n, _p(out), _stream()))
+        return out
+
+    def export_sk(self, sk):
+        out = torch.empty_like(sk)
+        _check(lib().lola_export_sk(self.h, _p(sk), _p(out), _stream()))
+        return out
+
+    def export_pk(self, pk):
+        out = torch.empty_like(pk)
+        _check(lib().lola_export_pk(self.h, _p(pk), _p(out), _stream()))
+        return out
+
+    def export_ksk(self, k):
+        out = torch.empty_like(k)
+        _check(lib().lola_export_ksk(self.h, _p(k), _p(out), _stream()))
+        return out
+
+    def ntt_limbs(self, x: torch.Tensor, prime_idx: Iterable[int], inverse: bool = False) -> torch.Tensor:
+        idx = list(prime_idx)
+        arr = (ctypes.c_uint32 * len(idx))(*idx)
+        out = torch.empty_like(x)
+        _check(lib().lola_ntt_limbs(self.h, _p(x), _p(out), len(idx), arr, int(inverse), _stream()))
+        return out
+
+
+def to_numpy_u32(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def from_numpy_u32(a: np.ndarray, device) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(device)

@@ -1,0 +1,186 @@
+"""GPU parity: every library operation against the oracle, word for word, in
+coefficient form, on the same seeded inputs (N = 1024, 4096 and 16384)."""
+import numpy as np
+import pytest
+
+from oracle import bfv
+from paper_1812_10659_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PSETS = ["toy1024", "cfg0", "cfg1"]
+STEPS = [1, -1, 7, bfv.ROW_SWAP]
+SEED = 0x5EED_0001
+
+
+def _u32(t):
+    from paper_1812_10659_amd import lola
+    return lola.to_numpy_u32(t)
+
+
+def _up(ctx, limbs):
+    """oracle coefficient-form ciphertext -> device NTT form"""
+    from paper_1812_10659_amd import lola
+    arr = np.stack([np.asarray(c, dtype=np.uint64) for c in limbs]).astype(np.uint32)
+    return ctx.from_coeff(lola.from_numpy_u32(arr, ctx.device))
+
+
+def _down(ctx, ct):
+    return _u32(ctx.to_coeff(ct)).astype(np.uint64)
+
+
+def _bitrev(k, bits):
+    return int(format(k, f"0{bits}b")[::-1], 2)
+
+
+@pytest.fixture(scope="module", params=PSETS)
+def env(request):
+    import torch
+    from paper_1812_10659_amd import lola
+    p = wl.PARAMS[request.param]
+    print(f"[gpu-ops] params {p.name} N={p.N} L={p.L}", flush=True)
+    ctx = lola.Context(p)
+    octx = bfv.Context(p)
+    gal = [bfv.galois_element(p.N, s) for s in STEPS]
+    okeys = bfv.keygen(octx, SEED, gal)
+    sk = ctx.keygen_secret(SEED)
+    pk = ctx.keygen_public(SEED, sk)
+    rlk = ctx.keygen_switch(SEED, sk, 0)
+    gks = {g: ctx.keygen_switch(SEED, sk, g) for g in gal}
+    torch.cuda.synchronize()
+    rs = np.random.default_rng(p.N)
+    m1 = rs.integers(0, p.t, p.N).astype(np.uint64)
+    m2 = rs.integers(0, p.t, p.N).astype(np.uint64)
+    c1 = bfv.encrypt(octx, okeys, m1, 11, 1)
+    c2 = bfv.encrypt(octx, okeys, m2, 11, 2)
+    return dict(p=p, ctx=ctx, octx=octx, okeys=okeys, sk=sk, pk=pk, rlk=rlk, gks=gks, gal=gal,
+                m=(m1, m2), c=(c1, c2))
+
+
+def test_galois_elements_agree(env):
+    from paper_1812_10659_amd import lola
+    N = env["p"].N
+    for s in STEPS + [0, 3, -5, N // 2 - 1]:
+        assert lola.galois_element(N, s) == bfv.galois_element(N, s)
+
+
+def test_ntt_is_evaluation_at_odd_powers(env):
+    from paper_1812_10659_amd import lola
+    ctx, p = env["ctx"], env["p"]
+    primes = list(p.q) + [p.P] + [None] * ctx.n_aux + [p.t]
+    idx = [i for i in range(len(primes)) if primes[i] is not None]
+    rs = np.random.default_rng(1)
+    x = np.stack([rs.integers(0, primes[i], p.N) for i in idx]).astype(np.uint32)
+    xd = lola.from_numpy_u32(x, ctx.device)
+    y = _u32(ctx.ntt_limbs(xd, idx))
+    bits = p.N.bit_length() - 1
+    br = np.array([_bitrev(k, bits) for k in range(p.N)])
+    for row, i in enumerate(idx):
+        m = primes[i]
+        ev = np.empty(p.N, np.uint64)
+        bfv.lib().or_eval_odd(x[row].astype(np.uint64), ev, p.N, m, bfv.min_root_2n(m, p.N))
+        assert np.array_equal(y[row].astype(np.uint64), ev[br]), f"prime index {i}"
+    back = _u32(ctx.ntt_limbs(lola.from_numpy_u32(y, ctx.device), idx, inverse=True))
+    assert np.array_equal(back, x)
+
+
+def test_keys_match_oracle(env):
+    ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
+    s_res = octx.small_to_limbs(ok.sk.s, octx.moduli)
+    assert np.array_equal(_u32(ctx.export_sk(env["sk"])).astype(np.uint64), s_res)
+    pk = _u32(ctx.export_pk(env["pk"])).astype(np.uint64)
+    assert np.array_equal(pk[0], ok.pk0) and np.array_equal(pk[1], ok.pk1)
+    for key, ref in [(env["rlk"], ok.rlk)] + [(env["gks"][g], ok.galois[g]) for g in env["gal"][:2]]:
+        k = _u32(ctx.export_ksk(key)).astype(np.uint64)   # [L][2][L+1][N]
+        assert np.array_equal(k[:, 0], ref.b) and np.array_equal(k[:, 1], ref.a)
+
+
+def test_encode_decode_match_oracle(env):
+    ctx, octx, p = env["ctx"], env["octx"], env["p"]
+    v = np.random.default_rng(2).integers(-3 * p.t, 3 * p.t, p.N)
+    pt = ctx.encode(v)
+    assert np.array_equal(_u32(pt).astype(np.uint64), bfv.encode(octx, v))
+    assert np.array_equal(ctx.decode(pt), np.mod(v, p.t))
+
+
+def test_encrypt_matches_oracle(env):
+    ctx, octx, p = env["ctx"], env["octx"], env["p"]
+    m = env["m"][0]
+    from paper_1812_10659_amd import lola
+    pt = lola.from_numpy_u32(m.astype(np.uint32), ctx.device)
+    ct = ctx.encrypt(env["pk"], pt, 11, 1)
+    got = _down(ctx, ct)
+    assert np.array_equal(got[0], env["c"][0][0]) and np.array_equal(got[1], env["c"][0][1])
+
+
+def test_decrypt_matches_oracle(env):
+    ctx, octx = env["ctx"], env["octx"]
+    c1, c2 = env["c"]
+    d = _u32(ctx.decrypt(env["sk"], _up(ctx, c1))).astype(np.uint64)
+    assert np.array_equal(d, bfv.decrypt(octx, env["okeys"], c1))
+    assert np.array_equal(d, env["m"][0])
+    c3 = bfv.mul(octx, c1, c2)
+    d3 = _u32(ctx.decrypt(env["sk"], _up(ctx, c3))).astype(np.uint64)
+    assert np.array_equal(d3, bfv.decrypt(octx, env["okeys"], c3))
+
+
+def test_linear_ops_match_oracle(env):
+    from paper_1812_10659_amd import lola
+    ctx, octx, p = env["ctx"], env["octx"], env["p"]
+    c1, c2 = env["c"]
+    m2 = env["m"][1]
+    a, b = _up(ctx, c1), _up(ctx, c2)
+    pt = lola.from_numpy_u32(m2.astype(np.uint32), ctx.device)
+    assert np.array_equal(_down(ctx, ctx.add(a, b)), np.stack(bfv.add(octx, c1, c2)))
+    assert np.array_equal(_down(ctx, ctx.add_plain(a, ctx.plain_add_form(pt))), np.stack(bfv.add_plain(octx, c1, m2)))
+    assert np.array_equal(_down(ctx, ctx.mul_plain(a, ctx.plain_mul_form(pt))), np.stack(bfv.mul_plain(octx, c1, m2)))
+    for w in (0, 1, -1, 127, -128, p.t - 1, p.t // 2, p.t // 2 + 1, 10**12 + 7):
+        assert np.array_equal(_down(ctx, ctx.mul_scalar(a, w)), np.stack(bfv.mul_scalar(octx, c1, w))), w
+    # in place
+    x = _up(ctx, c1)
+    ctx.add(x, b, out=x)
+    assert np.array_equal(_down(ctx, x), np.stack(bfv.add(octx, c1, c2)))
+
+
+def test_mul_matches_oracle(env):
+    ctx, octx = env["ctx"], env["octx"]
+    c1, c2 = env["c"]
+    got = _down(ctx, ctx.mul(_up(ctx, c1), _up(ctx, c2)))
+    assert np.array_equal(got, np.stack(bfv.mul(octx, c1, c2)))
+    got = _down(ctx, ctx.mul(_up(ctx, c1), _up(ctx, c1)))
+    assert np.array_equal(got, np.stack(bfv.mul(octx, c1, c1)))
+
+
+def test_relin_matches_oracle(env):
+    ctx, octx = env["ctx"], env["octx"]
+    c1, c2 = env["c"]
+    c3 = bfv.mul(octx, c1, c2)
+    got = _down(ctx, ctx.relin(env["rlk"], _up(ctx, c3)))
+    assert np.array_equal(got, np.stack(bfv.relin(octx, c3, env["okeys"].rlk)))
+
+
+@pytest.mark.parametrize("step", STEPS, ids=str)
+def test_rotate_matches_oracle(env, step):
+    ctx, octx = env["ctx"], env["octx"]
+    c1 = env["c"][0]
+    g = bfv.galois_element(env["p"].N, step)
+    got = _down(ctx, ctx.rotate(env["gks"][g], g, _up(ctx, c1)))
+    assert np.array_equal(got, np.stack(bfv.rotate(octx, c1, step, env["okeys"])))
+
+
+def test_keyswitch_batch_ragged(env):
+    """Mixed rotations and a relinearisation in one batch (uneven keys)."""
+    ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
+    c1, c2 = env["c"]
+    c3 = bfv.mul(octx, c1, c2)
+    items, refs = [], []
+    for k, step in enumerate([1, bfv.ROW_SWAP, -1, 7, 1]):
+        src = c1 if k % 2 == 0 else c2
+        g = bfv.galois_element(env["p"].N, step)
+        items.append((_up(ctx, src), env["gks"][g], g))
+        refs.append(bfv.rotate(octx, src, step, ok))
+    items.append((_up(ctx, c3), env["rlk"], 0))
+    refs.append(bfv.relin(octx, c3, ok.rlk))
+    outs = ctx.keyswitch_batch(items)
+    for o, r in zip(outs, refs):
+        assert np.array_equal(_down(ctx, o), np.stack(r))
