@@ -1,0 +1,228 @@
+"""Benchmark: encrypted inferences/s of the MNIST-shaped LoLa network at N=16384.
+
+One step = one batched evaluation of B encrypted requests (conv 5x5 s2, 5 maps
+-> square -> dense 845->100 -> square -> dense 100->10), inputs already
+encrypted and resident in HBM, every request's 154 rotations, 24 plaintext
+products, 125 scalar products and 2 squares run by the library.  Requests
+belong to `--clients` key sets (round robin), as a server holding several
+clients' keys would see them.
+
+Also reported: single-request latency p50/p99 (the unbatched path), the
+dominant kernel's roofline (key-switch inner kernel, timed live with HIP
+events on its launch stream), NTT and key-switch HBM throughput on
+algorithmic bytes, and the CPU oracle on the host cores.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 39.3e12 /s
+PEAK_HBM = 8.0e12                           # bytes/s
+BFLY_OPS = 9                                # VALU ops of one lazy Harvey butterfly
+MAC_OPS = 7                                 # Montgomery product + modular add
+
+
+def ks_inner_ops(N, L):
+    """Algorithmic VALU lane-ops of one key switch in the inner kernel:
+    L^2 + 2 transforms of N/2 log2 N butterflies (L-1 per ciphertext prime, L
+    for the special prime plus two inverse transforms) and 2 L (L+1) N
+    multiply-accumulates."""
+    bfly = (L * L + 2) * (N // 2) * int(math.log2(N))
+    macs = 2 * L * (L + 1) * N
+    return BFLY_OPS * bfly + MAC_OPS * macs
+
+
+def ks_bytes(N, L):
+    """Algorithmic HBM bytes of one key switch: ciphertext in (2 L N words),
+    key read once (2 L (L+1) N words), result out (2 L N words)."""
+    return 4 * N * (4 * L + 2 * L * (L + 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64, help="requests per step")
+    ap.add_argument("--clients", type=int, default=8, help="distinct key sets")
+    ap.add_argument("--latency-runs", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requests shard across GPUs by request; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    p = wl.PARAMS["cfg1"]
+    N, L = p.N, p.L
+    w = wl.cfg1_weights()
+    ctx = lola.Context(p)
+    plan = lola.Plan(p, networks.mnist_layers(w))
+    plan.load(ctx)
+    gal = plan.galois()
+    B, C = args.batch, max(1, min(args.clients, args.batch))
+    keys = []
+    for c in range(C):
+        ks = wl.key_seed(1) + 7919 * c
+        sk = ctx.keygen_secret(ks)
+        pk = ctx.keygen_public(ks, sk)
+        keys.append(dict(sk=sk, pk=pk, rlk=ctx.keygen_switch(ks, sk, 0),
+                         gks=[ctx.keygen_switch(ks, sk, g) for g in gal]))
+    imap = plan.input_map()
+    reqs, images = [], []
+    for r in range(B):
+        img = wl.cfg1_image(index=r)
+        images.append(img)
+        k = keys[r % C]
+        msgs = networks.pack_inputs(imap, networks.mnist_input_values(img))
+        ins = [ctx.encrypt(k["pk"], ctx.encode(m), wl.enc_seed(1) + r, i) for i, m in enumerate(msgs)]
+        reqs.append(dict(rlk=k["rlk"], gks=k["gks"], inputs=ins,
+                         outputs=[ctx.empty_ct() for _ in range(plan.info["n_outputs"])]))
+    torch.cuda.synchronize()
+
+    # warmup (also binds the batch: descriptors uploaded once)
+    for _ in range(args.warmup):
+        plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    lola.kernel_timing(ctx)                      # drain
+    lola.timing_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lola.timing_enable(ctx, False)
+    ks_ms, ks_launches, ks_jobs = lola.kernel_timing(ctx)
+
+    # correctness spot check of the timed batch (first and last request)
+    for r in (0, B - 1):
+        k = keys[r % C]
+        slots = np.stack([ctx.decode(ctx.decrypt(k["sk"], o)) for o in reqs[r]["outputs"]])
+        got = networks.unpack_outputs(plan.output_map(), slots)
+        from oracle import network as nw   # plaintext network for the check only
+        exp = nw._mod(nw.mnist_plain(images[r], w), p.t)
+        assert list(got) == list(exp), f"request {r}: decrypted logits differ from the network"
+
+    # single-request latency (unbatched path, eager)
+    lat = []
+    one = [reqs[0]]
+    plan.evaluate(ctx, one)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    for _ in range(args.latency_runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        plan.evaluate(ctx, one)
+        e1.record(s)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
+
+    # NTT throughput: batched forward transforms of 7*512 limbs
+    nl = 7 * 512
+    x = torch.randint(0, 1 << 29, (nl, N), dtype=torch.int32, device="cuda")
+    idx = [i % L for i in range(nl)]
+    ctx.ntt_limbs(x, idx)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 5
+    for _ in range(reps):
+        ctx.ntt_limbs(x, idx)
+    e1.record()
+    e1.synchronize()
+    ntt_s = e0.elapsed_time(e1) / 1e3 / reps
+    ntt_gbps = nl * 8 * N / ntt_s / 1e9
+
+    ms_per_step = elapsed / args.steps * 1e3
+    value = B * args.steps / elapsed
+    ops_per_job = ks_inner_ops(N, L)
+    ks_avg_ms = ks_ms / max(ks_launches, 1)
+    jobs_per_launch = ks_jobs / max(ks_launches, 1)
+    achieved = ops_per_job * ks_jobs / (ks_ms / 1e3) if ks_ms > 0 else 0.0
+    ks_gbps = ks_bytes(N, L) * ks_jobs / (ks_ms / 1e3) / 1e9 if ks_ms > 0 else 0.0
+
+    out = {
+        "metric": "encrypted inferences/s (N=16384 MNIST-shaped LoLa network)",
+        "value": round(value, 2),
+        "unit": "inferences/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 (RNS residues mod 30-bit primes)",
+        "data": "synthetic (seeded uniform 28x28 images, seeded int8 weights)",
+        "config": {"workload": "cfg1 MNIST-shaped: conv5x5s2x5 -> sq -> fc845x100 -> sq -> fc100x10, "
+                               "BFV N=16384 L=7 t=1146881",
+                   "batch_requests": B, "client_key_sets": C, "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "single_request_inferences_per_s": round(1e3 / float(np.median(lat)), 2)},
+        "roofline": {"bound": "alu", "kernel": "ks_inner_kernel<14>",
+                     "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 1),
+                     "unit": "T VALU lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4),
+                     "traffic": None, "avg_launch_ms": round(ks_avg_ms, 4),
+                     "jobs_per_launch": round(jobs_per_launch, 1), "ops_per_job": ops_per_job},
+        "hbm": {"ntt_gbps": round(ntt_gbps, 1), "ntt_frac": round(ntt_gbps * 1e9 / PEAK_HBM, 4),
+                "keyswitch_gbps": round(ks_gbps, 1), "keyswitch_frac": round(ks_gbps * 1e9 / PEAK_HBM, 4),
+                "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job"},
+        "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, w)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(p, w):
+    """The oracle on the host cores: one full MNIST-shaped inference on
+    ciphertexts (keys and encrypted inputs prepared outside the timing)."""
+    from oracle import bfv
+    from oracle import network as nw
+    from paper_1812_10659_amd import workloads as wl
+    octx = bfv.Context(p)
+    sched = nw.mnist_schedule(w)
+    keys = bfv.keygen(octx, wl.key_seed(1), nw.galois_elements(sched))
+    img = wl.cfg1_image(index=0)
+    ins = nw.mnist_inputs(img)
+    cts = [bfv.encrypt(octx, keys, bfv.encode(octx, nw.dense_slots(m, p.N, p.t)), 1, i) for i, m in enumerate(ins)]
+    t0 = time.perf_counter()
+    nw.run_ciphertexts(octx, keys, sched, cts)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 5), "unit": "inferences/s", "cores": bfv.max_threads(), "kind": "oracle",
+            "sample": f"1 full inference (154 rotations, 2 squares), {dt:.1f} s",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

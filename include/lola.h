@@ -199,6 +199,94 @@ int lola_export_ksk(lola_ctx *ctx, const uint32_t *ksk_dev, uint32_t *out_dev, l
 int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uint32_t n_limbs,
                    const uint32_t *prime_idx_host, int inverse, lola_stream stream);
 
+/* ------------------------------------------------------- layer compiler */
+/* Lowers a layer list onto the operations above with the paper's vector
+ * representations and matrix-vector recipes (Sec. 3.2: dense, sparse,
+ * stacked, interleaved and convolution representations; dense-row-major,
+ * stacked-row-major, interleaved-row-major and convolution-row-major
+ * products; Sec. 4 / Table 1 and App. C / Table 3 for the MNIST pipeline).
+ * Supported layer patterns (anything else returns LOLA_E_UNSUPPORTED):
+ *   CONV2D, SQUARE, DENSE, SQUARE, DENSE   convolution representation input
+ *       (k*k messages), maps combined by rotations, stacked-row-major dense
+ *       producing an interleaved vector, interleaved-row-major output layer
+ *       (one message per output, value at slot 0);
+ *   DENSE [, SQUARE]   with in_dim <= N/4: stacked input (period = next power
+ *       of two >= in_dim), one row per block, output j at slot period*j;
+ *   DENSE, SQUARE, DENSE   with N/4 < in_dim <= N/2: dense-row-major with
+ *       N/period queries per message (query q in the block at period*q),
+ *       hidden units masked and combined into an interleaved vector, then
+ *       one message per output with query q's value at slot period*q.
+ * Weights and biases are integers, used modulo t. */
+enum { LOLA_LAYER_CONV2D = 1, LOLA_LAYER_DENSE = 2, LOLA_LAYER_SQUARE = 3 };
+typedef struct {
+    int32_t kind;
+    int32_t in_h, in_w;        /* CONV2D: input size as the client pads it (square) */
+    int32_t k, stride, maps;   /* CONV2D: window, stride, output maps */
+    int32_t in_dim, out_dim;   /* DENSE */
+    const int64_t *weight;     /* host; CONV2D [maps][k][k], DENSE [out_dim][in_dim] */
+    const int64_t *bias;       /* host; [maps] or [out_dim]; NULL = none */
+} lola_layer;
+
+typedef struct lola_plan lola_plan;
+typedef struct {
+    uint32_t n_inputs, n_outputs, n_ops, n_consts, n_galois, n_waves, queries;
+    uint32_t n_rotations, n_mul_plain, n_mul_scalar, n_square, n_add_plain, n_add;
+    uint32_t n_phys_regs;      /* device ciphertext buffers per request */
+} lola_plan_info;
+
+int lola_compile(const lola_params *params, const lola_layer *layers, uint32_t n_layers, lola_plan **out);
+void lola_plan_destroy(lola_plan *plan);
+int lola_plan_get_info(const lola_plan *plan, lola_plan_info *info);
+/* Galois elements of the rotation keys the plan needs, in the order
+ * lola_request.gk_dev must follow. */
+int lola_plan_galois(const lola_plan *plan, uint32_t *galois_host);
+/* map[m*N + s] = index of the input value the client places at slot s of
+ * input message m (queries concatenated), or -1 for a zero slot. */
+int lola_plan_input_map(const lola_plan *plan, int32_t *map_host);
+/* map[o*N + s] = index of the result value at slot s of output message o
+ * (query-major: q*out_dim + j), or -1. */
+int lola_plan_output_map(const lola_plan *plan, int32_t *map_host);
+/* The op list as text, one op per line (for inspection and tests):
+ *   lincomb DST SRC:W ... [+add CONST]   sum of scalar multiples (+ add-form constant)
+ *   mulplain DST SRC CONST [+add CONST]  product with a plaintext (+ add-form constant)
+ *   addplain DST SRC CONST
+ *   rotadd DST SRC STEP ADDEND           ADDEND + rotate(SRC, STEP) (STEP "swap" = row swap)
+ *   rot DST SRC STEP
+ *   square DST SRC
+ * followed by "outputs R ...".  Registers 0..n_inputs-1 are the inputs.
+ * Returns the needed size (with the terminating zero) if cap is too small. */
+int lola_plan_dump(const lola_plan *plan, char *buf, size_t cap);
+/* The N slot values of plaintext constant `id` (as in the dump). */
+int lola_plan_const(const lola_plan *plan, uint32_t id, int64_t *slots_host);
+/* Encodes the plan's constants on the context's device (plaintext mul /
+ * add forms).  Needed once before evaluation. */
+int lola_plan_load(lola_ctx *ctx, lola_plan *plan, lola_stream stream);
+
+typedef struct {
+    const uint32_t *rlk_dev;          /* relinearisation key */
+    const uint32_t *const *gk_dev;    /* host array [n_galois] of switching keys */
+    const uint32_t *const *in_dev;    /* host array [n_inputs] of ciphertexts */
+    uint32_t *const *out_dev;         /* host array [n_outputs] of ciphertexts */
+} lola_request;
+/* Evaluates the plan for n_req independent requests (each with its own keys
+ * and inputs).  Ops are grouped into waves of independent operations; every
+ * op kind of a wave runs as one batched launch over all requests.  Output
+ * buffers must not alias inputs.  The plan owns its device workspace
+ * (ciphertext registers and scratch), sized for the largest n_req seen. */
+int lola_evaluate(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint32_t n_req,
+                  lola_stream stream);
+/* Same, replayed through a HIP graph captured on the first call for this
+ * exact set of buffers (re-captured when any pointer or n_req changes). */
+int lola_evaluate_graph(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint32_t n_req,
+                        lola_stream stream);
+
+/* Kernel timing (for measurement): when enabled, the library records HIP
+ * events around every launch of the key-switching inner kernel (the
+ * per-modulus NTT + key inner product) on the launch stream; the totals are
+ * read with lola_kernel_timing (synchronises). */
+int lola_timing_enable(lola_ctx *ctx, int on);
+int lola_kernel_timing(lola_ctx *ctx, double *total_ms, uint64_t *launches, uint64_t *jobs);
+
 const char *lola_strerror(int code);
 const char *lola_last_error(void);
 

@@ -1,0 +1,517 @@
+// Layer compiler: lowers a layer list to an op list with the paper's vector
+// representations and matrix-vector recipes (Sec. 3.2), then levels the ops
+// into waves of independent work and assigns physical registers.
+//
+// Recipes (W: weights, values modulo t):
+//   convolution vector - row major (Sec. 3.2.2): the input is k*k messages,
+//     message a*k+b holding input[stride*y + a][stride*x + b] at slot y*n+x;
+//     map m is sum_{a,b} w[m][a][b] * message(a,b) (+ bias), one message per
+//     map, values at slots 0..n*n-1 (dense);
+//   combining messages (Table 1, "combine ... using rotations"): message j is
+//     rotated right by j*unit and added; built as a binary tree so only
+//     log2(count) distinct rotation keys are needed;
+//   stacked vector - row major (Sec. 3.2.2): copies of a dense vector at
+//     stride P (next power of two >= its length) are made by rotate-and-add
+//     over -P, -2P, ..., -N/4 and the row swap; each round multiplies by rows
+//     laid out one per block, sums each block by rotations 1..P/2, keeps the
+//     block's first slot (mask) and adds the bias; rounds are then combined
+//     into an interleaved vector (value C*rho + c at slot P*c + rho);
+//   interleaved vector - row major (Sec. 3.2.2): per output, a product with
+//     the row permuted to the interleaved layout and a rotate-and-sum that
+//     collects every occupied slot into slot 0 (sparse output);
+//   dense vector - row major (Sec. 3.2.2): per output row, product with the
+//     row in every query block, rotate-and-sum over the block, mask, then
+//     combination into an interleaved vector (value j of query q at P*q + j).
+#include <algorithm>
+#include <cstring>
+#include <set>
+
+#include "plan.hpp"
+
+namespace lola {
+namespace {
+
+uint32_t next_pow2(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Builder {
+    lola_plan *p;
+    int reg() { return (int)p->n_regs++; }
+    int cst(std::vector<int64_t> v, bool mul) {
+        for (auto &x : v) {
+            x %= (int64_t)p->t;
+            if (x < 0) x += p->t;
+        }
+        auto it = p->const_index.find(v);
+        int id;
+        if (it == p->const_index.end()) {
+            id = (int)p->consts.size();
+            p->const_index.emplace(v, id);
+            p->consts.push_back(std::move(v));
+            p->const_mul.push_back(0);
+            p->const_add.push_back(0);
+        } else {
+            id = it->second;
+        }
+        (mul ? p->const_mul : p->const_add)[id] = 1;
+        return id;
+    }
+    std::vector<int64_t> zeros() const { return std::vector<int64_t>(p->N, 0); }
+    int lincomb(const std::vector<int> &srcs, const std::vector<int64_t> &w, int cadd) {
+        Op o;
+        o.kind = OP_LINCOMB;
+        o.dst = reg();
+        o.srcs = srcs;
+        o.w = w;
+        o.cadd = cadd;
+        p->ops.push_back(o);
+        return o.dst;
+    }
+    int mulplain(int src, int cmul, int cadd = -1) {
+        Op o;
+        o.kind = OP_MULPLAIN;
+        o.dst = reg();
+        o.src = src;
+        o.cmul = cmul;
+        o.cadd = cadd;
+        p->ops.push_back(o);
+        return o.dst;
+    }
+    int addplain(int src, int cadd) {
+        Op o;
+        o.kind = OP_ADDPLAIN;
+        o.dst = reg();
+        o.src = src;
+        o.cadd = cadd;
+        p->ops.push_back(o);
+        return o.dst;
+    }
+    // addend + rotate(src, step)
+    int rotadd(int src, int32_t step, int addend) {
+        Op o;
+        o.kind = OP_ROTADD;
+        o.dst = reg();
+        o.src = src;
+        o.addend = addend;
+        o.step = step;
+        o.galois = lola_galois_element(p->N, step);
+        p->ops.push_back(o);
+        return o.dst;
+    }
+    int square(int src) {
+        Op o;
+        o.kind = OP_SQUARE;
+        o.dst = reg();
+        o.src = src;
+        p->ops.push_back(o);
+        return o.dst;
+    }
+    int rotate_and_sum(int src, const std::vector<int32_t> &steps) {
+        int cur = src;
+        for (int32_t k : steps) cur = rotadd(cur, k, cur);
+        return cur;
+    }
+    int combine_tree(std::vector<int> regs, int32_t unit) {
+        int32_t stride = unit;
+        while (regs.size() > 1) {
+            std::vector<int> nxt;
+            for (size_t i = 0; i < regs.size(); i += 2) {
+                if (i + 1 < regs.size())
+                    nxt.push_back(rotadd(regs[i + 1], -stride, regs[i]));
+                else
+                    nxt.push_back(regs[i]);
+            }
+            regs.swap(nxt);
+            stride *= 2;
+        }
+        return regs[0];
+    }
+};
+
+int unsupported(const std::string &m) { return set_error(LOLA_E_UNSUPPORTED, m); }
+
+int64_t bias_at(const lola_layer &l, int j) { return l.bias ? l.bias[j] : 0; }
+
+// ---- network families -------------------------------------------------
+int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
+    // CONV2D, SQUARE, DENSE, SQUARE, DENSE
+    if (n != 5 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE ||
+        ls[3].kind != LOLA_LAYER_SQUARE || ls[4].kind != LOLA_LAYER_DENSE)
+        return unsupported("convolution networks must be CONV2D, SQUARE, DENSE, SQUARE, DENSE");
+    const lola_layer &cv = ls[0], &d1 = ls[2], &d2 = ls[4];
+    const uint32_t N = p->N;
+    if (cv.in_h != cv.in_w || cv.k <= 0 || cv.stride <= 0 || cv.maps <= 0 || cv.in_h < cv.k || !cv.weight)
+        return unsupported("bad convolution shape");
+    const int n_out = (cv.in_h - cv.k) / cv.stride + 1, V = n_out * n_out, K2 = cv.k * cv.k;
+    if ((uint32_t)(cv.maps * V) > N / 2) return unsupported("convolution output exceeds one slot row");
+    const int D = cv.maps * V;
+    if (d1.in_dim != D || !d1.weight || d1.out_dim <= 0) return unsupported("first dense layer must take maps*n*n inputs");
+    const uint32_t P = next_pow2((uint32_t)D);
+    if (P > N / 2) return unsupported("dense input too long to stack");
+    const uint32_t C = N / P;
+    const uint32_t R = ((uint32_t)d1.out_dim + C - 1) / C;
+    if (R > P) return unsupported("too many stacked rounds for the interleaved layout");
+    if (d2.in_dim != d1.out_dim || !d2.weight || d2.out_dim <= 0) return unsupported("second dense layer shape");
+    // inputs: convolution representation
+    p->n_inputs = (uint32_t)K2;
+    p->queries = 1;
+    p->n_regs = p->n_inputs;
+    p->input_map.assign((size_t)K2 * N, -1);
+    for (int a = 0; a < cv.k; ++a)
+        for (int c = 0; c < cv.k; ++c)
+            for (int y = 0; y < n_out; ++y)
+                for (int x = 0; x < n_out; ++x)
+                    p->input_map[(size_t)(a * cv.k + c) * N + y * n_out + x] =
+                        (cv.stride * y + a) * cv.in_w + (cv.stride * x + c);
+    // convolution: one linear combination per map (+ bias at slots 0..V-1)
+    std::vector<int> maps;
+    std::vector<int> ins(K2);
+    for (int i = 0; i < K2; ++i) ins[i] = i;
+    for (int m = 0; m < cv.maps; ++m) {
+        std::vector<int64_t> w(cv.weight + (size_t)m * K2, cv.weight + (size_t)(m + 1) * K2);
+        int cadd = -1;
+        if (cv.bias) {
+            auto v = b.zeros();
+            for (int s = 0; s < V; ++s) v[s] = cv.bias[m];
+            cadd = b.cst(v, false);
+        }
+        maps.push_back(b.lincomb(ins, w, cadd));
+    }
+    int y = b.combine_tree(maps, V);
+    y = b.square(y);
+    // stack C copies at stride P
+    std::vector<int32_t> st;
+    for (uint32_t s = P; s < N / 2; s *= 2) st.push_back(-(int32_t)s);
+    st.push_back(LOLA_ROW_SWAP);
+    const int S = b.rotate_and_sum(y, st);
+    std::vector<int32_t> blk;
+    for (uint32_t s = 1; s < P; s *= 2) blk.push_back((int32_t)s);
+    std::vector<int> rounds;
+    for (uint32_t rho = 0; rho < R; ++rho) {
+        auto rows = b.zeros(), mask = b.zeros(), bias = b.zeros();
+        for (uint32_t c = 0; c < C; ++c) {
+            const uint32_t j = C * rho + c;
+            if (j >= (uint32_t)d1.out_dim) continue;
+            for (int i = 0; i < D; ++i) rows[P * c + i] = d1.weight[(size_t)j * D + i];
+            mask[P * c] = 1;
+            bias[P * c] = bias_at(d1, (int)j);
+        }
+        int z = b.mulplain(S, b.cst(rows, true));
+        z = b.rotate_and_sum(z, blk);
+        z = b.mulplain(z, b.cst(mask, true), d1.bias ? b.cst(bias, false) : -1);
+        rounds.push_back(z);
+    }
+    int h = b.combine_tree(rounds, 1);
+    h = b.square(h);
+    // interleaved row major: value j = C*rho + c at slot P*c + rho
+    std::vector<int32_t> coll;
+    for (uint32_t s = 1; s < next_pow2(R); s *= 2) coll.push_back((int32_t)s);
+    for (uint32_t s = P; s < N / 2 && s < P * C; s *= 2) coll.push_back((int32_t)s);
+    if (P * C > N / 2) coll.push_back(LOLA_ROW_SWAP);
+    p->output_map.assign((size_t)d2.out_dim * N, -1);
+    for (int o = 0; o < d2.out_dim; ++o) {
+        auto rows = b.zeros();
+        for (uint32_t rho = 0; rho < R; ++rho)
+            for (uint32_t c = 0; c < C; ++c) {
+                const uint32_t j = C * rho + c;
+                if (j < (uint32_t)d1.out_dim) rows[P * c + rho] = d2.weight[(size_t)o * d2.in_dim + j];
+            }
+        int z = b.mulplain(h, b.cst(rows, true));
+        z = b.rotate_and_sum(z, coll);
+        if (d2.bias) {
+            auto bv = b.zeros();
+            bv[0] = d2.bias[o];
+            z = b.addplain(z, b.cst(bv, false));
+        }
+        p->outputs.push_back(z);
+        p->output_map[(size_t)o * N] = o;
+    }
+    return LOLA_OK;
+}
+
+int compile_stacked_dense(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
+    // DENSE [, SQUARE] with in_dim <= N/4
+    const lola_layer &d = ls[0];
+    const uint32_t N = p->N;
+    if (n > 2 || (n == 2 && ls[1].kind != LOLA_LAYER_SQUARE)) return unsupported("stacked dense: DENSE [, SQUARE]");
+    const uint32_t P = next_pow2((uint32_t)d.in_dim), C = N / P;
+    if ((uint32_t)d.out_dim > C) return unsupported("stacked dense: more rows than blocks");
+    p->n_inputs = 1;
+    p->queries = 1;
+    p->n_regs = 1;
+    p->input_map.assign(N, -1);
+    for (uint32_t s = 0; s < N; ++s)
+        if ((int)(s % P) < d.in_dim) p->input_map[s] = (int32_t)(s % P);
+    auto rows = b.zeros();
+    for (int j = 0; j < d.out_dim; ++j)
+        for (int i = 0; i < d.in_dim; ++i) rows[P * j + i] = d.weight[(size_t)j * d.in_dim + i];
+    int z = b.mulplain(0, b.cst(rows, true));
+    std::vector<int32_t> blk;
+    for (uint32_t s = 1; s < P; s *= 2) blk.push_back((int32_t)s);
+    z = b.rotate_and_sum(z, blk);
+    if (d.bias) {
+        auto bv = b.zeros();
+        for (int j = 0; j < d.out_dim; ++j) bv[P * j] = d.bias[j];
+        z = b.addplain(z, b.cst(bv, false));
+    }
+    if (n == 2) z = b.square(z);
+    p->outputs.push_back(z);
+    p->output_map.assign(N, -1);
+    for (int j = 0; j < d.out_dim; ++j) p->output_map[P * j] = j;
+    return LOLA_OK;
+}
+
+int compile_dense_head(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
+    // DENSE, SQUARE, DENSE with N/4 < in_dim <= N/2
+    if (n != 3 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE)
+        return unsupported("dense head must be DENSE, SQUARE, DENSE");
+    const lola_layer &d1 = ls[0], &d2 = ls[2];
+    const uint32_t N = p->N;
+    const uint32_t P = next_pow2((uint32_t)d1.in_dim), Qn = N / P;
+    const uint32_t H = (uint32_t)d1.out_dim;
+    if (H > P || d2.in_dim != d1.out_dim || !d2.weight) return unsupported("dense head shape");
+    p->n_inputs = 1;
+    p->queries = Qn;
+    p->n_regs = 1;
+    p->input_map.assign(N, -1);
+    for (uint32_t q = 0; q < Qn; ++q)
+        for (int i = 0; i < d1.in_dim; ++i) p->input_map[P * q + i] = (int32_t)(q * d1.in_dim + i);
+    std::vector<int32_t> blk;
+    for (uint32_t s = 1; s < P; s *= 2) blk.push_back((int32_t)s);
+    auto mask = b.zeros();
+    for (uint32_t q = 0; q < Qn; ++q) mask[P * q] = 1;
+    const int cmask = b.cst(mask, true);
+    std::vector<int> hidden;
+    for (uint32_t j = 0; j < H; ++j) {
+        auto rows = b.zeros();
+        for (uint32_t q = 0; q < Qn; ++q)
+            for (int i = 0; i < d1.in_dim; ++i) rows[P * q + i] = d1.weight[(size_t)j * d1.in_dim + i];
+        int z = b.mulplain(0, b.cst(rows, true));
+        z = b.rotate_and_sum(z, blk);
+        z = b.mulplain(z, cmask);
+        hidden.push_back(z);
+    }
+    int acc = b.combine_tree(hidden, 1);
+    if (d1.bias) {
+        auto bv = b.zeros();
+        for (uint32_t q = 0; q < Qn; ++q)
+            for (uint32_t j = 0; j < H; ++j) bv[P * q + j] = d1.bias[j];
+        acc = b.addplain(acc, b.cst(bv, false));
+    }
+    const int h = b.square(acc);
+    std::vector<int32_t> coll;
+    for (uint32_t s = 1; s < next_pow2(std::max<uint32_t>(H, 2)); s *= 2) coll.push_back((int32_t)s);
+    p->output_map.assign((size_t)d2.out_dim * N, -1);
+    for (int o = 0; o < d2.out_dim; ++o) {
+        auto rows = b.zeros();
+        for (uint32_t q = 0; q < Qn; ++q)
+            for (uint32_t j = 0; j < H; ++j) rows[P * q + j] = d2.weight[(size_t)o * d2.in_dim + j];
+        int z = b.mulplain(h, b.cst(rows, true));
+        z = b.rotate_and_sum(z, coll);
+        if (d2.bias) {
+            auto bv = b.zeros();
+            for (uint32_t q = 0; q < Qn; ++q) bv[P * q] = d2.bias[o];
+            z = b.addplain(z, b.cst(bv, false));
+        }
+        p->outputs.push_back(z);
+        for (uint32_t q = 0; q < Qn; ++q) p->output_map[(size_t)o * N + P * q] = (int32_t)(q * d2.out_dim + o);
+    }
+    return LOLA_OK;
+}
+
+// ---- levels and registers ---------------------------------------------
+void schedule(lola_plan *p) {
+    std::vector<int> level(p->n_regs, 0);
+    auto srcs_of = [](const Op &o) {
+        std::vector<int> s;
+        if (o.kind == OP_LINCOMB) s = o.srcs;
+        else s.push_back(o.src);
+        if (o.kind == OP_ROTADD) s.push_back(o.addend);
+        return s;
+    };
+    uint32_t maxl = 0;
+    for (Op &o : p->ops) {
+        int l = 0;
+        for (int r : srcs_of(o)) l = std::max(l, level[r]);
+        o.level = l + 1;
+        level[o.dst] = o.level;
+        maxl = std::max<uint32_t>(maxl, (uint32_t)o.level);
+    }
+    p->n_waves = maxl;
+    // last level at which each register is read
+    std::vector<int> last(p->n_regs, -1);
+    for (const Op &o : p->ops)
+        for (int r : srcs_of(o)) last[r] = std::max(last[r], o.level);
+    std::set<int> outs(p->outputs.begin(), p->outputs.end());
+    p->phys.assign(p->n_regs, -1);
+    std::vector<int> order(p->ops.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return p->ops[a].level < p->ops[c].level; });
+    std::vector<int> free_list;
+    std::vector<std::vector<int>> release(maxl + 2);
+    for (uint32_t r = 0; r < p->n_regs; ++r)
+        if (last[r] >= 0 && r >= p->n_inputs && !outs.count((int)r)) release[last[r]].push_back((int)r);
+    uint32_t nphys = 0, cur_level = 0;
+    std::vector<uint32_t> squares(maxl + 1, 0);
+    for (int idx : order) {
+        const Op &o = p->ops[idx];
+        while (cur_level < (uint32_t)o.level) {   // entering a new level: buffers last read earlier are free
+            for (int r : release[cur_level]) free_list.push_back(p->phys[r]);
+            ++cur_level;
+        }
+        if (o.kind == OP_SQUARE) squares[o.level]++;
+        if (outs.count(o.dst)) continue;
+        if (free_list.empty()) free_list.push_back((int)nphys++);
+        p->phys[o.dst] = free_list.back();
+        free_list.pop_back();
+    }
+    p->n_phys = nphys;
+    p->max_squares_per_wave = *std::max_element(squares.begin(), squares.end());
+    std::set<uint32_t> g;
+    for (const Op &o : p->ops)
+        if (o.kind == OP_ROTADD || o.kind == OP_ROT) g.insert(o.galois);
+    p->galois.assign(g.begin(), g.end());
+}
+
+}  // namespace
+}  // namespace lola
+
+using namespace lola;
+
+extern "C" {
+
+int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_layers, lola_plan **out) {
+    if (!prm || !layers || !out || n_layers == 0) return set_error(LOLA_E_INVAL, "null argument");
+    *out = nullptr;
+    if (prm->N < 1024 || prm->N > 16384 || (prm->N & (prm->N - 1)) || prm->t < 3 || prm->L < 1)
+        return set_error(LOLA_E_PARAMS, "bad N, t or L");
+    const struct { uint32_t N; } sz{prm->N};
+    const auto *ctx = &sz;
+    lola_plan *p = new lola_plan();
+    p->N = prm->N;
+    p->L = prm->L;
+    p->t = prm->t;
+    Builder b{p};
+    int rc;
+    const lola_layer &l0 = layers[0];
+    if (l0.kind == LOLA_LAYER_CONV2D) {
+        rc = compile_conv_net(p, b, layers, n_layers);
+    } else if (l0.kind == LOLA_LAYER_DENSE && l0.weight && l0.in_dim > 0 && l0.out_dim > 0) {
+        if ((uint32_t)l0.in_dim > ctx->N / 2)
+            rc = unsupported("dense input longer than a slot row");
+        else if (n_layers == 3)
+            rc = compile_dense_head(p, b, layers, n_layers);
+        else if ((uint32_t)l0.in_dim <= ctx->N / 4)
+            rc = compile_stacked_dense(p, b, layers, n_layers);
+        else
+            rc = unsupported("a single dense layer needs in_dim <= N/4 (stacked input)");
+    } else {
+        rc = unsupported("first layer must be CONV2D or DENSE");
+    }
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    schedule(p);
+    *out = p;
+    return LOLA_OK;
+}
+
+int lola_plan_get_info(const lola_plan *p, lola_plan_info *info) {
+    if (!p || !info) return set_error(LOLA_E_INVAL, "null argument");
+    memset(info, 0, sizeof *info);
+    info->n_inputs = p->n_inputs;
+    info->n_outputs = (uint32_t)p->outputs.size();
+    info->n_ops = (uint32_t)p->ops.size();
+    info->n_consts = (uint32_t)p->consts.size();
+    info->n_galois = (uint32_t)p->galois.size();
+    info->n_waves = p->n_waves;
+    info->queries = p->queries;
+    info->n_phys_regs = p->n_phys;
+    for (const Op &o : p->ops) {
+        switch (o.kind) {
+            case OP_LINCOMB:
+                info->n_mul_scalar += (uint32_t)o.srcs.size();
+                info->n_add += (uint32_t)o.srcs.size() - 1;
+                if (o.cadd >= 0) info->n_add_plain++;
+                break;
+            case OP_MULPLAIN:
+                info->n_mul_plain++;
+                if (o.cadd >= 0) info->n_add_plain++;
+                break;
+            case OP_ADDPLAIN: info->n_add_plain++; break;
+            case OP_ROTADD: info->n_rotations++; info->n_add++; break;
+            case OP_ROT: info->n_rotations++; break;
+            case OP_SQUARE: info->n_square++; break;
+        }
+    }
+    return LOLA_OK;
+}
+
+int lola_plan_galois(const lola_plan *p, uint32_t *g) {
+    if (!p || !g) return set_error(LOLA_E_INVAL, "null argument");
+    std::copy(p->galois.begin(), p->galois.end(), g);
+    return LOLA_OK;
+}
+
+int lola_plan_input_map(const lola_plan *p, int32_t *m) {
+    if (!p || !m) return set_error(LOLA_E_INVAL, "null argument");
+    std::copy(p->input_map.begin(), p->input_map.end(), m);
+    return LOLA_OK;
+}
+
+int lola_plan_output_map(const lola_plan *p, int32_t *m) {
+    if (!p || !m) return set_error(LOLA_E_INVAL, "null argument");
+    std::copy(p->output_map.begin(), p->output_map.end(), m);
+    return LOLA_OK;
+}
+
+int lola_plan_dump(const lola_plan *p, char *buf, size_t cap) {
+    if (!p) return set_error(LOLA_E_INVAL, "null argument");
+    std::string s;
+    auto step = [](int32_t k) { return k == LOLA_ROW_SWAP ? std::string("swap") : std::to_string(k); };
+    for (const Op &o : p->ops) {
+        switch (o.kind) {
+            case OP_LINCOMB:
+                s += "lincomb " + std::to_string(o.dst);
+                for (size_t k = 0; k < o.srcs.size(); ++k)
+                    s += " " + std::to_string(o.srcs[k]) + ":" + std::to_string(o.w[k]);
+                if (o.cadd >= 0) s += " +add " + std::to_string(o.cadd);
+                break;
+            case OP_MULPLAIN:
+                s += "mulplain " + std::to_string(o.dst) + " " + std::to_string(o.src) + " " + std::to_string(o.cmul);
+                if (o.cadd >= 0) s += " +add " + std::to_string(o.cadd);
+                break;
+            case OP_ADDPLAIN:
+                s += "addplain " + std::to_string(o.dst) + " " + std::to_string(o.src) + " " + std::to_string(o.cadd);
+                break;
+            case OP_ROTADD:
+                s += "rotadd " + std::to_string(o.dst) + " " + std::to_string(o.src) + " " + step(o.step) + " " +
+                     std::to_string(o.addend);
+                break;
+            case OP_ROT:
+                s += "rot " + std::to_string(o.dst) + " " + std::to_string(o.src) + " " + step(o.step);
+                break;
+            case OP_SQUARE: s += "square " + std::to_string(o.dst) + " " + std::to_string(o.src); break;
+        }
+        s += "\n";
+    }
+    s += "outputs";
+    for (int r : p->outputs) s += " " + std::to_string(r);
+    s += "\n";
+    if (!buf || cap < s.size() + 1) return (int)(s.size() + 1);
+    memcpy(buf, s.c_str(), s.size() + 1);
+    return LOLA_OK;
+}
+
+int lola_plan_const(const lola_plan *p, uint32_t id, int64_t *slots) {
+    if (!p || !slots) return set_error(LOLA_E_INVAL, "null argument");
+    if (id >= p->consts.size()) return set_error(LOLA_E_INVAL, "constant id out of range");
+    std::copy(p->consts[id].begin(), p->consts[id].end(), slots);
+    return LOLA_OK;
+}
+
+}  // extern "C"

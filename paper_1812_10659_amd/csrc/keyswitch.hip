@@ -16,21 +16,11 @@
 //                               two sums are also brought back to coefficients
 //   ks_moddown  (2L per job):   lift [u_P]_P into q_j, NTT, subtract, times
 //                               P^-1, add the c0 (or d0 / d1) term.
-#include "lola_internal.hpp"
 #include "ntt_core.hpp"
+#include "program.hpp"
 
 namespace lola {
 
-struct KsJob {
-    const uint32_t *x;     // [L][N] polynomial to switch (NTT form, before sigma_g)
-    const uint32_t *key;   // [L][2][L+1][N] Montgomery NTT form
-    const uint32_t *add0;  // [L][N] added to component 0 (sigma_g applied), or null
-    const uint32_t *add1;  // [L][N] added to component 1, or null
-    uint32_t *out;         // [2][L][N]
-    uint32_t *scratch;     // (4L + 2) N words: D [L][N], Xp [L][N], U [2][L][N], UP [2][N]
-    uint32_t galois;       // 0/1: no automorphism
-    uint32_t pad;
-};
 
 __device__ __forceinline__ uint32_t perm_src(uint32_t idx, uint32_t g, uint32_t logN) {
     return g > 1 ? galois_src_index(idx, g, logN) : idx;
@@ -162,26 +152,36 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(
     const uint32_t pinv = mrc->Pinvq[j], pinvp = mrc->Pinvqp[j];
     uint32_t *out = job.out + ((size_t)(c * L + j) << LOGN);
     const uint32_t *addj = add ? add + ((size_t)j << LOGN) : nullptr;
+    const uint32_t *addc = job.addct ? job.addct + ((size_t)(c * L + j) << LOGN) : nullptr;
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) {
         const int idx = spectral_index<LOGN>(tid, r);
         uint32_t w = shoup(sub_mod(U[idx], x[r], mc.q), pinv, pinvp, mc.q);
         if (addj) w = add_mod(w, addj[perm_src(idx, g, LOGN)], mc.q);
+        if (addc) w = add_mod(w, addc[idx], mc.q);
         out[idx] = w;
     }
 }
 
-static size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }
+size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }
 
 int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
     const uint32_t L = ctx->L;
     const dim3 block(ctx->N / NTT_E);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (ctx->timing) {
+        int rc = timing_pair(ctx, &t0, &t1);
+        if (rc) return rc;
+        ctx->timed_jobs += n;
+    }
 #define LOLA_KS_CASE(LG)                                                                                    \
     case LG:                                                                                                \
         hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(L, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_itw,  \
                            ctx->d_itwp);                                                                     \
+        if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                            \
         hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(L + 1, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_tw, \
                            ctx->d_twp, ctx->d_itw, ctx->d_itwp);                                             \
+        if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                            \
         hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(L, 2, n), block, 0, s, d_jobs, L, ctx->d_mc,         \
                            ctx->d_tw, ctx->d_twp, ctx->d_mrc);                                               \
         break;
@@ -201,6 +201,18 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t
 // Jobs per launch: bounds the scratch arena ((4L+2) N words per job).
 static constexpr uint32_t KS_CHUNK = 128;
 
+void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs, uint32_t *scratch,
+                       uint32_t chunk) {
+    const size_t per = ks_scratch_words(ctx);
+    for (size_t off = 0; off < jobs.size(); off += chunk) {
+        const size_t n = std::min<size_t>(chunk, jobs.size() - off);
+        std::vector<KsJob> part(jobs.begin() + off, jobs.begin() + off + n);
+        for (size_t k = 0; k < n; ++k) part[k].scratch = scratch + per * k;
+        p.launch(LK_KS, part);
+        p.ks_jobs += n;
+    }
+}
+
 int keyswitch_host_jobs(lola_ctx *ctx, std::vector<KsJob> &jobs, hipStream_t s) {
     const size_t per = ks_scratch_words(ctx);
     for (size_t off = 0; off < jobs.size(); off += KS_CHUNK) {
@@ -208,10 +220,10 @@ int keyswitch_host_jobs(lola_ctx *ctx, std::vector<KsJob> &jobs, hipStream_t s) 
         void *buf = nullptr;
         int rc = scratch_get(ctx, per * n * 4, &buf);
         if (rc) return rc;
-        for (uint32_t k = 0; k < n; ++k) jobs[off + k].scratch = (uint32_t *)buf + per * k;
-        void *d = nullptr;
-        if ((rc = desc_upload(ctx, jobs.data() + off, n * sizeof(KsJob), s, &d))) return rc;
-        if ((rc = launch_keyswitch(ctx, (const KsJob *)d, n, s))) return rc;
+        Program p;
+        program_keyswitch(ctx, p, std::vector<KsJob>(jobs.begin() + off, jobs.begin() + off + n),
+                          (uint32_t *)buf, n);
+        if ((rc = program_run_now(ctx, p, s))) return rc;
     }
     return LOLA_OK;
 }
@@ -225,7 +237,7 @@ extern "C" {
 int lola_reserve(lola_ctx *ctx, uint32_t n_ct) {
     if (!ctx) return set_error(LOLA_E_INVAL, "null argument");
     void *buf = nullptr;
-    const size_t per = std::max<size_t>(ks_scratch_words(ctx), (size_t)(4 * 2 + 3) * (ctx->L + ctx->nB + 1) * ctx->N);
+    const size_t per = std::max<size_t>(ks_scratch_words(ctx), mul_scratch_words(ctx));
     return scratch_get(ctx, per * std::min<uint32_t>(std::max<uint32_t>(n_ct, 1), KS_CHUNK) * 4, &buf);
 }
 
@@ -238,9 +250,9 @@ int lola_keyswitch_batch(lola_ctx *ctx, const lola_ks_desc *d, uint32_t n, lola_
         if (d[k].galois != 0 && (!(d[k].galois & 1) || d[k].galois >= 2 * ctx->N))
             return set_error(LOLA_E_INVAL, "bad Galois element");
         if (d[k].galois == 0)
-            jobs[k] = KsJob{d[k].in_dev + 2 * P, d[k].key_dev, d[k].in_dev, d[k].in_dev + P, d[k].out_dev, nullptr, 0, 0};
+            jobs[k] = KsJob{d[k].in_dev + 2 * P, d[k].key_dev, d[k].in_dev, d[k].in_dev + P, nullptr, d[k].out_dev, nullptr, 0, 0};
         else
-            jobs[k] = KsJob{d[k].in_dev + P, d[k].key_dev, d[k].in_dev, nullptr, d[k].out_dev, nullptr, d[k].galois, 0};
+            jobs[k] = KsJob{d[k].in_dev + P, d[k].key_dev, d[k].in_dev, nullptr, nullptr, d[k].out_dev, nullptr, d[k].galois, 0};
     }
     return keyswitch_host_jobs(ctx, jobs, (hipStream_t)stream);
 }

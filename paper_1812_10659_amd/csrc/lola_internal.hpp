@@ -73,6 +73,11 @@ struct lola_ctx {
     size_t ring_off = 0;
     hipEvent_t ring_ev[RING_SLABS] = {};
     bool ring_ev_valid[RING_SLABS] = {};
+    // kernel timing (event pairs around the key-switch inner kernel)
+    bool timing = false;
+    std::vector<hipEvent_t> timing_events;   // pairs, in use
+    std::vector<hipEvent_t> timing_pool;     // free events
+    uint64_t timed_jobs = 0;
     uint32_t idxP() const { return L; }
     uint32_t idxB(uint32_t j) const { return L + 1 + j; }
     uint32_t idxT() const { return L + 1 + nB; }
@@ -92,6 +97,8 @@ int check_hip(hipError_t e, const char *what);
 
 // scratch arena (device); grows with a device synchronisation
 int scratch_get(lola_ctx *ctx, size_t bytes, void **out);
+// a start/stop event pair for kernel timing (kept until lola_kernel_timing)
+int timing_pair(lola_ctx *ctx, hipEvent_t *a, hipEvent_t *b);
 // descriptor upload area (device), copied asynchronously on the stream
 int desc_upload(lola_ctx *ctx, const void *host, size_t bytes, hipStream_t s, void **dev);
 
@@ -140,5 +147,27 @@ enum : uint32_t {
     NTT_SRC_SIGNED32 = 64u,  // source holds small signed int32 values (|v| < q)
 };
 int launch_ntt_jobs(lola_ctx *ctx, const NttJob *host_jobs, int n, hipStream_t s);
+int launch_ntt_jobs_dev(lola_ctx *ctx, const NttJob *d_jobs, int n, hipStream_t s);
+
+// One key switch: out = (add0' + KS(x)_0, add1 + KS(x)_1) (+ addct), where
+// add0' is add0 under the automorphism when galois > 1.
+struct KsJob {
+    const uint32_t *x;      // [L][N] polynomial to switch (NTT form, before sigma_g)
+    const uint32_t *key;    // [L][2][L+1][N] Montgomery NTT form
+    const uint32_t *add0;   // [L][N] added to component 0 (sigma_g applied), or null
+    const uint32_t *add1;   // [L][N] added to component 1, or null
+    const uint32_t *addct;  // [2][L][N] added to both components as is, or null
+    uint32_t *out;          // [2][L][N]
+    uint32_t *scratch;      // (4L + 2) N words: D [L][N], Xp [L][N], U [2][L][N], UP [2][N]
+    uint32_t galois;        // 0/1: no automorphism
+    uint32_t pad;
+};
+// Runs the jobs in chunks (assigns scratch, uploads descriptors).
+int keyswitch_host_jobs(lola_ctx *ctx, std::vector<KsJob> &jobs, hipStream_t s);
+// Exact products out3[k] = a[k] x b[k] for n pairs.
+int mul_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *a, const uint32_t *const *b,
+              uint32_t *const *out3, hipStream_t s);
+size_t mul_scratch_words(const lola_ctx *ctx);   // per pair
+size_t ks_scratch_words(const lola_ctx *ctx);    // per key switch job
 
 }  // namespace lola

@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #ifndef LOLA_HD
+#include <hip/hip_runtime.h>
 #define LOLA_HD __host__ __device__ __forceinline__
 #endif
 

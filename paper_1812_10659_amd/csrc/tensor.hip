@@ -10,17 +10,36 @@
 //   is computed modulo every b in B; round adds [R > (Q-1)/2] (no ties: Q odd).
 // The result Z (|Z| < B/2) is then converted from B back to Q, again through
 // its mixed-radix digits, and centred.
-#include "lola_internal.hpp"
+//
+// Batched: any number of independent pairs, each with its own scratch.
 #include "mrc.hpp"
+#include "program.hpp"
 
 namespace lola {
 
-// Q -> B centred extension of one coefficient of one polynomial.
-// src: [L][N] coefficient residues of 4 polynomials; dst: [nB][N] per poly.
-__global__ void tensor_extend_kernel(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, uint32_t N,
+struct MulLayout {           // word offsets inside one job's scratch
+    size_t Ac, Bx, Dq, Db, Oc, total;
+};
+static MulLayout mul_layout(size_t L, size_t nB, size_t N) {
+    MulLayout m;
+    m.Ac = 0;                       // [4][L][N]  inputs, coefficient form
+    m.Bx = m.Ac + 4 * L * N;        // [4][nB][N] inputs extended to B
+    m.Dq = m.Bx + 4 * nB * N;       // [3][L][N]  tensor in Q
+    m.Db = m.Dq + 3 * L * N;        // [3][nB][N] tensor in B
+    m.Oc = m.Db + 3 * nB * N;       // [3][L][N]  rounded result, coefficient form
+    m.total = m.Oc + 3 * L * N;
+    return m;
+}
+
+// Q -> B centred extension of one coefficient of one of the four inputs.
+// grid (N/256, 4, jobs)
+__global__ void tensor_extend_kernel(const MulJob *__restrict__ jobs, uint32_t N, size_t offAc, size_t offBx,
                                      const ModConst *__restrict__ mcs, const MrcConst *__restrict__ mrc) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x, p = blockIdx.y;
     if (k >= N) return;
+    const MulJob job = jobs[blockIdx.z];
+    const uint32_t *src = job.scr + offAc;
+    uint32_t *dst = job.scr + offBx;
     const int L = (int)mrc->L, nB = (int)mrc->nB;
     uint32_t r[MAXL], v[MAXL];
 #pragma unroll
@@ -40,22 +59,23 @@ __global__ void tensor_extend_kernel(const uint32_t *__restrict__ src, uint32_t 
 }
 
 // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 on limb l of Q u B (NTT domain).
-// grid (N/256, L + nB)
-__global__ void tensor_product_kernel(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
-                                      const uint32_t *__restrict__ ext, uint32_t *__restrict__ dq,
-                                      uint32_t *__restrict__ db, uint32_t N, uint32_t L, uint32_t nB,
+// grid (N/256, L + nB, jobs)
+__global__ void tensor_product_kernel(const MulJob *__restrict__ jobs, uint32_t N, uint32_t L, uint32_t nB,
+                                      size_t offBx, size_t offDq, size_t offDb,
                                       const ModConst *__restrict__ mcs) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x, l = blockIdx.y;
     if (k >= N) return;
+    const MulJob job = jobs[blockIdx.z];
     uint32_t a0, a1, b0, b1;
     ModConst c;
     if (l < L) {
         c = mcs[l];
         const size_t o = (size_t)l * N + k, P1 = (size_t)L * N;
-        a0 = a[o]; a1 = a[P1 + o]; b0 = b[o]; b1 = b[P1 + o];
+        a0 = job.a[o]; a1 = job.a[P1 + o]; b0 = job.b[o]; b1 = job.b[P1 + o];
     } else {
         const uint32_t j = l - L;
         c = mcs[L + 1 + j];
+        const uint32_t *ext = job.scr + offBx;
         const size_t o = (size_t)j * N + k, PB = (size_t)nB * N;
         a0 = ext[o]; a1 = ext[PB + o]; b0 = ext[2 * PB + o]; b1 = ext[3 * PB + o];
     }
@@ -64,21 +84,26 @@ __global__ void tensor_product_kernel(const uint32_t *__restrict__ a, const uint
     const uint32_t d1 = add_mod(mont_mul(a0m, b1, c.q, c.qneg_inv), mont_mul(a1m, b0, c.q, c.qneg_inv), c.q);
     const uint32_t d2 = mont_mul(a1m, b1, c.q, c.qneg_inv);
     if (l < L) {
+        uint32_t *dq = job.scr + offDq;
         const size_t o = (size_t)l * N + k, P1 = (size_t)L * N;
         dq[o] = d0; dq[P1 + o] = d1; dq[2 * P1 + o] = d2;
     } else {
+        uint32_t *db = job.scr + offDb;
         const size_t o = (size_t)(l - L) * N + k, PB = (size_t)nB * N;
         db[o] = d0; db[PB + o] = d1; db[2 * PB + o] = d2;
     }
 }
 
-// round(t d / Q) for one coefficient of output polynomial p; dq [3][L][N],
-// db [3][nB][N] coefficient residues; out [3][L][N] coefficient residues.
-__global__ void tensor_round_kernel(const uint32_t *__restrict__ dq, const uint32_t *__restrict__ db,
-                                    uint32_t *__restrict__ out, uint32_t N, const ModConst *__restrict__ mcs,
+// round(t d / Q) for one coefficient of output polynomial p.
+// grid (N/256, 3, jobs)
+__global__ void tensor_round_kernel(const MulJob *__restrict__ jobs, uint32_t N, size_t offDq, size_t offDb,
+                                    size_t offOc, const ModConst *__restrict__ mcs,
                                     const MrcConst *__restrict__ mrc) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x, p = blockIdx.y;
     if (k >= N) return;
+    const MulJob job = jobs[blockIdx.z];
+    const uint32_t *dq = job.scr + offDq, *db = job.scr + offDb;
+    uint32_t *out = job.scr + offOc;
     const int L = (int)mrc->L, nB = (int)mrc->nB;
     uint32_t r[MAXL], v[MAXL];
 #pragma unroll
@@ -113,6 +138,90 @@ __global__ void tensor_round_kernel(const uint32_t *__restrict__ dq, const uint3
     }
 }
 
+size_t mul_scratch_words(const lola_ctx *ctx) { return mul_layout(ctx->L, ctx->nB, ctx->N).total; }
+
+int launch_mul_stage(lola_ctx *ctx, uint32_t stage, const MulJob *d, uint32_t n, hipStream_t s) {
+    const uint32_t N = ctx->N, L = ctx->L, nB = ctx->nB;
+    const MulLayout ml = mul_layout(L, nB, N);
+    if (stage == LK_MUL_EXTEND)
+        hipLaunchKernelGGL(tensor_extend_kernel, dim3(N / 256, 4, n), dim3(256), 0, s, d, N, ml.Ac, ml.Bx,
+                           ctx->d_mc, ctx->d_mrc);
+    else if (stage == LK_MUL_PRODUCT)
+        hipLaunchKernelGGL(tensor_product_kernel, dim3(N / 256, L + nB, n), dim3(256), 0, s, d, N, L, nB, ml.Bx,
+                           ml.Dq, ml.Db, ctx->d_mc);
+    else
+        hipLaunchKernelGGL(tensor_round_kernel, dim3(N / 256, 3, n), dim3(256), 0, s, d, N, ml.Dq, ml.Db, ml.Oc,
+                           ctx->d_mc, ctx->d_mrc);
+    LOLA_HIP(hipGetLastError());
+    return LOLA_OK;
+}
+
+void program_mul(const lola_ctx *ctx, Program &p, const std::vector<MulJob> &pairs, uint32_t *scratch,
+                 uint32_t chunk) {
+    const size_t N = ctx->N, L = ctx->L, nB = ctx->nB, P1 = L * N;
+    const MulLayout ml = mul_layout(L, nB, N);
+    for (size_t off = 0; off < pairs.size(); off += chunk) {
+        const size_t m = std::min<size_t>(chunk, pairs.size() - off);
+        std::vector<MulJob> jobs(m);
+        std::vector<NttJob> n1, n2, n3, n4;
+        for (size_t k = 0; k < m; ++k) {
+            MulJob j = pairs[off + k];
+            j.scr = scratch + ml.total * k;
+            jobs[k] = j;
+            const uint32_t *srcs[4] = {j.a, j.a + P1, j.b, j.b + P1};
+            for (int q = 0; q < 4; ++q)
+                for (uint32_t i = 0; i < L; ++i)
+                    n1.push_back(NttJob{srcs[q] + i * N, j.scr + ml.Ac + (q * L + i) * N, i, NTT_INVERSE});
+            for (int q = 0; q < 4; ++q)
+                for (uint32_t b = 0; b < nB; ++b) {
+                    uint32_t *x = j.scr + ml.Bx + (q * nB + b) * N;
+                    n2.push_back(NttJob{x, x, ctx->idxB(b), 0});
+                }
+            for (int q = 0; q < 3; ++q) {
+                for (uint32_t i = 0; i < L; ++i) {
+                    uint32_t *x = j.scr + ml.Dq + (q * L + i) * N;
+                    n3.push_back(NttJob{x, x, i, NTT_INVERSE});
+                }
+                for (uint32_t b = 0; b < nB; ++b) {
+                    uint32_t *x = j.scr + ml.Db + (q * nB + b) * N;
+                    n3.push_back(NttJob{x, x, ctx->idxB(b), NTT_INVERSE});
+                }
+                for (uint32_t i = 0; i < L; ++i)
+                    n4.push_back(NttJob{j.scr + ml.Oc + (q * L + i) * N, j.out3 + (q * L + i) * N, i, 0});
+            }
+        }
+        const size_t dj = p.put(jobs);
+        p.launch(LK_NTT, n1);
+        p.launches.push_back(Launch{LK_MUL_EXTEND, (uint32_t)m, dj});
+        p.launch(LK_NTT, n2);
+        p.launches.push_back(Launch{LK_MUL_PRODUCT, (uint32_t)m, dj});
+        p.launch(LK_NTT, n3);
+        p.launches.push_back(Launch{LK_MUL_ROUND, (uint32_t)m, dj});
+        p.launch(LK_NTT, n4);
+    }
+}
+
+int mul_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *a, const uint32_t *const *b,
+              uint32_t *const *out3, hipStream_t s) {
+    constexpr uint32_t CHUNK = 8;   // bounds one blob to a descriptor-ring slab
+    for (uint32_t off = 0; off < n; off += CHUNK) {
+        const uint32_t m = std::min(CHUNK, n - off);
+        std::vector<MulJob> pairs(m);
+        for (uint32_t k = 0; k < m; ++k) {
+            if (out3[off + k] == a[off + k] || out3[off + k] == b[off + k])
+                return set_error(LOLA_E_INVAL, "product output may not alias an input");
+            pairs[k] = MulJob{a[off + k], b[off + k], out3[off + k], nullptr};
+        }
+        void *buf = nullptr;
+        int rc = scratch_get(ctx, mul_scratch_words(ctx) * m * 4, &buf);
+        if (rc) return rc;
+        Program p;
+        program_mul(ctx, p, pairs, (uint32_t *)buf, m);
+        if ((rc = program_run_now(ctx, p, s))) return rc;
+    }
+    return LOLA_OK;
+}
+
 }  // namespace lola
 
 using namespace lola;
@@ -121,49 +230,7 @@ extern "C" {
 
 int lola_mul(lola_ctx *ctx, const uint32_t *a, const uint32_t *b, uint32_t *out3, lola_stream stream) {
     if (!ctx || !a || !b || !out3) return set_error(LOLA_E_INVAL, "null argument");
-    if (out3 == a || out3 == b) return set_error(LOLA_E_INVAL, "lola_mul output may not alias an input");
-    hipStream_t s = (hipStream_t)stream;
-    const size_t N = ctx->N, L = ctx->L, nB = ctx->nB;
-    // Ac [4][L][N] | Bx [4][nB][N] | Dq [3][L][N] | Db [3][nB][N] | Oc [3][L][N]
-    const size_t words = (4 * L + 4 * nB + 3 * L + 3 * nB + 3 * L) * N;
-    void *buf = nullptr;
-    int rc = scratch_get(ctx, words * 4, &buf);
-    if (rc) return rc;
-    uint32_t *Ac = (uint32_t *)buf, *Bx = Ac + 4 * L * N, *Dq = Bx + 4 * nB * N, *Db = Dq + 3 * L * N,
-             *Oc = Db + 3 * nB * N;
-    const size_t P1 = L * N;
-    std::vector<NttJob> jobs;
-    const uint32_t *srcs[4] = {a, a + P1, b, b + P1};
-    for (int p = 0; p < 4; ++p)
-        for (uint32_t i = 0; i < L; ++i)
-            jobs.push_back(NttJob{srcs[p] + i * N, Ac + (p * L + i) * N, i, NTT_INVERSE});
-    if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
-    hipLaunchKernelGGL(tensor_extend_kernel, dim3((unsigned)(N / 256), 4), dim3(256), 0, s, Ac, Bx, (uint32_t)N,
-                       ctx->d_mc, ctx->d_mrc);
-    LOLA_HIP(hipGetLastError());
-    jobs.clear();
-    for (int p = 0; p < 4; ++p)
-        for (uint32_t j = 0; j < nB; ++j)
-            jobs.push_back(NttJob{Bx + (p * nB + j) * N, Bx + (p * nB + j) * N, ctx->idxB(j), 0});
-    if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
-    hipLaunchKernelGGL(tensor_product_kernel, dim3((unsigned)(N / 256), (unsigned)(L + nB)), dim3(256), 0, s, a, b,
-                       Bx, Dq, Db, (uint32_t)N, (uint32_t)L, (uint32_t)nB, ctx->d_mc);
-    LOLA_HIP(hipGetLastError());
-    jobs.clear();
-    for (int p = 0; p < 3; ++p) {
-        for (uint32_t i = 0; i < L; ++i)
-            jobs.push_back(NttJob{Dq + (p * L + i) * N, Dq + (p * L + i) * N, i, NTT_INVERSE});
-        for (uint32_t j = 0; j < nB; ++j)
-            jobs.push_back(NttJob{Db + (p * nB + j) * N, Db + (p * nB + j) * N, ctx->idxB(j), NTT_INVERSE});
-    }
-    if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
-    hipLaunchKernelGGL(tensor_round_kernel, dim3((unsigned)(N / 256), 3), dim3(256), 0, s, Dq, Db, Oc, (uint32_t)N,
-                       ctx->d_mc, ctx->d_mrc);
-    LOLA_HIP(hipGetLastError());
-    jobs.clear();
-    for (int p = 0; p < 3; ++p)
-        for (uint32_t i = 0; i < L; ++i) jobs.push_back(NttJob{Oc + (p * L + i) * N, out3 + (p * L + i) * N, i, 0});
-    return launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s);
+    return mul_batch(ctx, 1, &a, &b, &out3, (hipStream_t)stream);
 }
 
 }  // extern "C"

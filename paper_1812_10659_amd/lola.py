@@ -295,3 +295,174 @@ def to_numpy_u32(t: torch.Tensor) -> np.ndarray:
 
 def from_numpy_u32(a: np.ndarray, device) -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(device)
+
+
+# ------------------------------------------------------------- plans -----
+LAYER_CONV2D, LAYER_DENSE, LAYER_SQUARE = 1, 2, 3
+
+
+class Layer(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("in_h", ctypes.c_int32), ("in_w", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("stride", ctypes.c_int32), ("maps", ctypes.c_int32),
+                ("in_dim", ctypes.c_int32), ("out_dim", ctypes.c_int32),
+                ("weight", ctypes.POINTER(ctypes.c_int64)), ("bias", ctypes.POINTER(ctypes.c_int64))]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "n_inputs", "n_outputs", "n_ops", "n_consts", "n_galois", "n_waves", "queries",
+        "n_rotations", "n_mul_plain", "n_mul_scalar", "n_square", "n_add_plain", "n_add", "n_phys_regs")]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("rlk_dev", ctypes.c_void_p), ("gk_dev", ctypes.POINTER(ctypes.c_void_p)),
+                ("in_dev", ctypes.POINTER(ctypes.c_void_p)), ("out_dev", ctypes.POINTER(ctypes.c_void_p))]
+
+
+def conv2d(weight, bias, in_hw: int, stride: int) -> dict:
+    w = np.ascontiguousarray(weight, dtype=np.int64)
+    return dict(kind=LAYER_CONV2D, in_h=in_hw, in_w=in_hw, k=w.shape[1], stride=stride, maps=w.shape[0],
+                weight=w, bias=None if bias is None else np.ascontiguousarray(bias, dtype=np.int64))
+
+
+def dense(weight, bias=None) -> dict:
+    w = np.ascontiguousarray(weight, dtype=np.int64)
+    return dict(kind=LAYER_DENSE, in_dim=w.shape[1], out_dim=w.shape[0], weight=w,
+                bias=None if bias is None else np.ascontiguousarray(bias, dtype=np.int64))
+
+
+def square() -> dict:
+    return dict(kind=LAYER_SQUARE)
+
+
+def _params_struct(params):
+    q = (ctypes.c_uint32 * len(params.q))(*params.q)
+    return _Params(params.N, params.t, len(params.q), q, params.P, int(getattr(params, "insecure_ok", False))), q
+
+
+def _plan_sig():
+    L = lib()
+    if getattr(L, "_plan_sig_done", False):
+        return L
+    vp, u32 = ctypes.c_void_p, ctypes.c_uint32
+    sig = {
+        "lola_compile": [ctypes.POINTER(_Params), ctypes.POINTER(Layer), u32, ctypes.POINTER(vp)],
+        "lola_plan_get_info": [vp, ctypes.POINTER(_PlanInfo)],
+        "lola_plan_galois": [vp, ctypes.POINTER(u32)],
+        "lola_plan_input_map": [vp, ctypes.POINTER(ctypes.c_int32)],
+        "lola_plan_output_map": [vp, ctypes.POINTER(ctypes.c_int32)],
+        "lola_plan_dump": [vp, ctypes.c_char_p, ctypes.c_size_t],
+        "lola_plan_const": [vp, u32, ctypes.POINTER(ctypes.c_int64)],
+        "lola_plan_load": [vp, vp, vp],
+        "lola_evaluate": [vp, vp, ctypes.POINTER(Request), u32, vp],
+        "lola_evaluate_graph": [vp, vp, ctypes.POINTER(Request), u32, vp],
+        "lola_timing_enable": [vp, ctypes.c_int],
+        "lola_kernel_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
+                               ctypes.POINTER(ctypes.c_uint64)],
+        "lola_plan_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.lola_plan_destroy.restype = None
+    L._plan_sig_done = True
+    return L
+
+
+class Plan:
+    """lola_plan: a layer list compiled for a parameter set (host logic)."""
+
+    def __init__(self, params, layers):
+        L = _plan_sig()
+        arr = (Layer * len(layers))()
+        self._keep = []
+        for k, d in enumerate(layers):
+            ly = Layer()
+            for f in ("kind", "in_h", "in_w", "k", "stride", "maps", "in_dim", "out_dim"):
+                setattr(ly, f, int(d.get(f, 0)))
+            for f in ("weight", "bias"):
+                a = d.get(f)
+                if a is not None:
+                    self._keep.append(a)
+                    setattr(ly, f, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+            arr[k] = ly
+        ps, self._q = _params_struct(params)
+        h = ctypes.c_void_p()
+        _check(L.lola_compile(ctypes.byref(ps), arr, len(layers), ctypes.byref(h)))
+        self.h = h
+        self._keep = []
+        self.N = params.N
+        inf = _PlanInfo()
+        _check(L.lola_plan_get_info(self.h, ctypes.byref(inf)))
+        self.info = {f: getattr(inf, f) for f, _ in _PlanInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lola_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def galois(self) -> list:
+        n = self.info["n_galois"]
+        a = (ctypes.c_uint32 * max(n, 1))()
+        _check(lib().lola_plan_galois(self.h, a))
+        return [int(a[i]) for i in range(n)]
+
+    def input_map(self) -> np.ndarray:
+        a = np.empty(self.info["n_inputs"] * self.N, np.int32)
+        _check(lib().lola_plan_input_map(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return a.reshape(self.info["n_inputs"], self.N)
+
+    def output_map(self) -> np.ndarray:
+        a = np.empty(self.info["n_outputs"] * self.N, np.int32)
+        _check(lib().lola_plan_output_map(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return a.reshape(self.info["n_outputs"], self.N)
+
+    def dump(self) -> str:
+        need = lib().lola_plan_dump(self.h, None, 0)
+        buf = ctypes.create_string_buffer(need)
+        _check(lib().lola_plan_dump(self.h, buf, need))
+        return buf.value.decode()
+
+    def const(self, cid: int) -> np.ndarray:
+        a = np.empty(self.N, np.int64)
+        _check(lib().lola_plan_const(self.h, cid, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return a
+
+    def load(self, ctx: "Context") -> None:
+        _check(lib().lola_plan_load(ctx.h, self.h, _stream()))
+
+    def evaluate(self, ctx: "Context", requests, graph: bool = False, stream=None) -> None:
+        """requests: list of dict(rlk=tensor, gks=[tensor per galois()], inputs=[...], outputs=[...])."""
+        n = len(requests)
+        arr = (Request * n)()
+        keep = []
+        for k, r in enumerate(requests):
+            gk = (ctypes.c_void_p * max(len(r["gks"]), 1))(*[t.data_ptr() for t in r["gks"]])
+            ins = (ctypes.c_void_p * len(r["inputs"]))(*[t.data_ptr() for t in r["inputs"]])
+            outs = (ctypes.c_void_p * len(r["outputs"]))(*[t.data_ptr() for t in r["outputs"]])
+            keep += [gk, ins, outs]
+            arr[k] = Request(r["rlk"].data_ptr() if r.get("rlk") is not None else None,
+                             ctypes.cast(gk, ctypes.POINTER(ctypes.c_void_p)),
+                             ctypes.cast(ins, ctypes.POINTER(ctypes.c_void_p)),
+                             ctypes.cast(outs, ctypes.POINTER(ctypes.c_void_p)))
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+        f = lib().lola_evaluate_graph if graph else lib().lola_evaluate
+        _check(f(ctx.h, self.h, arr, n, s))
+
+
+def timing_enable(ctx: "Context", on: bool) -> None:
+    _check(_plan_sig().lola_timing_enable(ctx.h, int(on)))
+
+
+def kernel_timing(ctx: "Context"):
+    """(total ms, launches, jobs) of the key-switch inner kernel since the last read."""
+    ms, n, j = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_plan_sig().lola_kernel_timing(ctx.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(j)))
+    return ms.value, n.value, j.value

@@ -1,0 +1,148 @@
+"""The layer compiler (host logic in liblola) against the oracle: the compiled
+op list, run on plain slot vectors by the oracle's interpreter, must give the
+plaintext integer network mod t at every output slot; op counts and rotation
+keys must match the oracle's own schedules of the same recipes (Table 1 /
+App. C shapes)."""
+import numpy as np
+import pytest
+
+from oracle import bfv
+from oracle import network as nw
+from paper_1812_10659_amd import workloads as wl
+
+
+def _lola():
+    from paper_1812_10659_amd import lola
+    try:
+        lola.lib()
+    except ImportError:
+        from paper_1812_10659_amd import build_lib
+        build_lib.build()
+    return lola
+
+
+def dump_to_oracle_ops(plan):
+    """Translate the plan's text dump into the oracle's op tuples (a lincomb
+    becomes scalar products and additions, a rotadd a rotation and an add)."""
+    ops, nxt = [], 10**7
+    outputs = []
+    consts = {}
+
+    def c(i):
+        i = int(i)
+        if i not in consts:
+            consts[i] = {k: int(v) for k, v in enumerate(plan.const(i)) if v}
+        return consts[i]
+
+    for line in plan.dump().strip().split("\n"):
+        f = line.split()
+        if f[0] == "outputs":
+            outputs = [int(x) for x in f[1:]]
+        elif f[0] == "lincomb":
+            dst = int(f[1])
+            terms = [t for t in f[2:] if ":" in t]
+            acc = None
+            for t in terms:
+                s, w = t.split(":")
+                r = nxt; nxt += 1
+                ops.append(("mul_scalar", r, int(s), int(w)))
+                if acc is None:
+                    acc = r
+                else:
+                    r2 = nxt; nxt += 1
+                    ops.append(("add", r2, acc, r))
+                    acc = r2
+            if "+add" in f:
+                ops.append(("add_plain", dst, acc, c(f[f.index("+add") + 1])))
+            else:
+                ops.append(("add", dst, acc, acc)) if False else ops.append(("mul_scalar", dst, acc, 1))
+        elif f[0] == "mulplain":
+            dst, src, cm = int(f[1]), int(f[2]), f[3]
+            if "+add" in f:
+                r = nxt; nxt += 1
+                ops.append(("mul_plain", r, src, c(cm)))
+                ops.append(("add_plain", dst, r, c(f[f.index("+add") + 1])))
+            else:
+                ops.append(("mul_plain", dst, src, c(cm)))
+        elif f[0] == "addplain":
+            ops.append(("add_plain", int(f[1]), int(f[2]), c(f[3])))
+        elif f[0] == "rotadd":
+            dst, src, step, addend = int(f[1]), int(f[2]), f[3], int(f[4])
+            step = bfv.ROW_SWAP if step == "swap" else int(step)
+            r = nxt; nxt += 1
+            ops.append(("rotate", r, src, step))
+            ops.append(("add", dst, addend, r))
+        elif f[0] == "square":
+            ops.append(("square", int(f[1]), int(f[2])))
+        else:
+            raise ValueError(line)
+    return nw.Schedule(plan.N, plan.info["n_inputs"], ops, outputs)
+
+
+def _check_plan(lola, params, layers, inputs_values, expected, oracle_sched):
+    plan = lola.Plan(params, layers)
+    sched = dump_to_oracle_ops(plan)
+    msgs = lola_pack(plan, inputs_values)
+    outs, _ = nw.run_slots(sched, [{k: int(v) for k, v in enumerate(m) if v} for m in msgs], params.t)
+    from paper_1812_10659_amd import networks
+    got = networks.unpack_outputs(plan.output_map(), np.stack(outs))
+    assert list(got) == list(nw._mod(expected, params.t))
+    info = plan.info
+    assert info["n_rotations"] == oracle_sched.count("rotate")
+    assert info["n_mul_plain"] == oracle_sched.count("mul_plain")
+    assert info["n_square"] == oracle_sched.count("square")
+    assert sorted(plan.galois()) == nw.galois_elements(oracle_sched)
+    return plan
+
+
+def lola_pack(plan, values):
+    from paper_1812_10659_amd import networks
+    return networks.pack_inputs(plan.input_map(), values)
+
+
+def test_compiler_dense64_stacked():
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    x, W = wl.cfg0_inputs()
+    p = wl.PARAMS["cfg0"]
+    plan = _check_plan(lola, p, networks.dense64_layers(W), x, nw.dense64_plain(x, W), nw.dense64_schedule(W))
+    assert plan.info["n_rotations"] == 6 and plan.info["n_square"] == 1
+
+
+def test_compiler_mnist_matches_tables_and_network():
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w, img = wl.cfg1_weights(), wl.cfg1_image()
+    p = wl.PARAMS["cfg1"]
+    plan = _check_plan(lola, p, networks.mnist_layers(w), networks.mnist_input_values(img),
+                       nw.mnist_plain(img, w), nw.mnist_schedule(w))
+    info = plan.info
+    assert info["n_inputs"] == 25 and info["n_outputs"] == 10
+    assert info["n_rotations"] == 154 and info["n_mul_plain"] == 24 and info["n_mul_scalar"] == 125
+    # input map: message 5a+b, slot 13y+x holds padded pixel (2y+a, 2x+b)
+    m = plan.input_map()
+    assert m[5 * 1 + 2, 13 * 3 + 4] == (2 * 3 + 1) * 29 + (2 * 4 + 2)
+    assert (m[:, 169:] == -1).all()
+
+
+@pytest.mark.parametrize("n_hidden", [8, 256])
+def test_compiler_head(n_hidden):
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w, f = wl.cfg3_weights(), wl.cfg3_features(4)
+    p = wl.PARAMS["cfg3"]
+    layers = networks.head_layers(w, n_hidden)
+    wt = wl.HeadWeights(w.w1[:n_hidden], w.b1[:n_hidden], w.w2[:, :n_hidden], w.b2)
+    expected = np.concatenate([nw.head_plain(f[q], wt) for q in range(4)])
+    plan = _check_plan(lola, p, layers, f, expected, nw.head_schedule(w, n_hidden=n_hidden))
+    assert plan.info["queries"] == 4
+
+
+def test_compiler_rejects_unsupported():
+    lola = _lola()
+    p = wl.PARAMS["cfg1"]
+    with pytest.raises(lola.LolaError) as e:
+        lola.Plan(p, [lola.square()])
+    assert e.value.code == -8
+    with pytest.raises(lola.LolaError):
+        lola.Plan(p, [lola.dense(np.ones((3, 9000), dtype=np.int64))])

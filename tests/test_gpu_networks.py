@@ -1,0 +1,148 @@
+"""GPU parity of whole networks: the compiled plan evaluated by the library
+against the oracle's own schedule of the same recipes, ciphertext word for
+word, and the decrypted results against the plaintext integer network mod t.
+Also: batched requests equal single requests, and graph replays equal the
+eager run."""
+import numpy as np
+import pytest
+
+from oracle import bfv
+from oracle import network as nw
+from paper_1812_10659_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(pname, layers, oracle_sched, values, key_seed, enc_seed, with_oracle=True):
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    p = wl.PARAMS[pname]
+    ctx = lola.Context(p)
+    plan = lola.Plan(p, layers)
+    plan.load(ctx)
+    gal = plan.galois()
+    sk = ctx.keygen_secret(key_seed)
+    pk = ctx.keygen_public(key_seed, sk)
+    rlk = ctx.keygen_switch(key_seed, sk, 0)
+    gks = [ctx.keygen_switch(key_seed, sk, g) for g in gal]
+    msgs = networks.pack_inputs(plan.input_map(), values)
+    ins = [ctx.encrypt(pk, ctx.encode(m), enc_seed, i) for i, m in enumerate(msgs)]
+    outs = [ctx.empty_ct() for _ in range(plan.info["n_outputs"])]
+    req = dict(rlk=rlk, gks=gks, inputs=ins, outputs=outs)
+    torch.cuda.synchronize()
+    env = dict(p=p, ctx=ctx, plan=plan, sk=sk, req=req, msgs=msgs)
+    if with_oracle:
+        octx = bfv.Context(p)
+        okeys = bfv.keygen(octx, key_seed, nw.galois_elements(oracle_sched))
+        octs = [bfv.encrypt(octx, okeys, bfv.encode(octx, m), enc_seed, i) for i, m in enumerate(msgs)]
+        env.update(octx=octx, okeys=okeys, octs=octs)
+    return env
+
+
+def _coeff(ctx, t):
+    from paper_1812_10659_amd import lola
+    return lola.to_numpy_u32(ctx.to_coeff(t)).astype(np.uint64)
+
+
+def _decrypt_values(env):
+    from paper_1812_10659_amd import networks
+    ctx, plan = env["ctx"], env["plan"]
+    slots = np.stack([ctx.decode(ctx.decrypt(env["sk"], o)) for o in env["req"]["outputs"]])
+    return networks.unpack_outputs(plan.output_map(), slots)
+
+
+def _run_and_compare(env, oracle_sched, expected):
+    import torch
+    ctx, plan = env["ctx"], env["plan"]
+    plan.evaluate(ctx, [env["req"]])
+    torch.cuda.synchronize()
+    oouts, _ = nw.run_ciphertexts(env["octx"], env["okeys"], oracle_sched, env["octs"])
+    for k, (g, o) in enumerate(zip(env["req"]["outputs"], oouts)):
+        assert np.array_equal(_coeff(ctx, g), np.stack(o)), f"output {k} differs from the oracle"
+    assert list(_decrypt_values(env)) == list(nw._mod(expected, env["p"].t))
+
+
+def test_dense64_network_matches_oracle():
+    from paper_1812_10659_amd import networks
+    x, W = wl.cfg0_inputs()
+    print("[gpu-net] cfg0 dense64", flush=True)
+    sched = nw.dense64_schedule(W)
+    env = _setup("cfg0", networks.dense64_layers(W), sched, x, wl.key_seed(0), wl.enc_seed(0))
+    _run_and_compare(env, sched, nw.dense64_plain(x, W))
+
+
+def test_mnist_network_matches_oracle():
+    from paper_1812_10659_amd import networks
+    w, img = wl.cfg1_weights(), wl.cfg1_image()
+    print("[gpu-net] cfg1 mnist", flush=True)
+    sched = nw.mnist_schedule(w)
+    env = _setup("cfg1", networks.mnist_layers(w), sched, networks.mnist_input_values(img),
+                 wl.key_seed(1), wl.enc_seed(1))
+    _run_and_compare(env, sched, nw.mnist_plain(img, w))
+
+
+def test_head_network_truncated_matches_oracle():
+    from paper_1812_10659_amd import networks
+    w, f = wl.cfg3_weights(), wl.cfg3_features(4)
+    print("[gpu-net] cfg3 head, 8 hidden", flush=True)
+    sched = nw.head_schedule(w, n_hidden=8)
+    env = _setup("cfg3", networks.head_layers(w, 8), sched, f, wl.key_seed(3), wl.enc_seed(3))
+    wt = wl.HeadWeights(w.w1[:8], w.b1[:8], w.w2[:, :8], w.b2)
+    _run_and_compare(env, sched, np.concatenate([nw.head_plain(f[q], wt) for q in range(4)]))
+
+
+def test_head_network_full_size_decrypts_to_network():
+    """Full 4096 -> 256 -> 10 head with 4 queries per ciphertext: the oracle's
+    ciphertext run is too slow here, so the check is the exact decrypted
+    result against the plaintext network (mod t)."""
+    import torch
+    from paper_1812_10659_amd import networks
+    w, f = wl.cfg3_weights(), wl.cfg3_features(4)
+    print("[gpu-net] cfg3 head, full", flush=True)
+    env = _setup("cfg3", networks.head_layers(w), None, f, wl.key_seed(3), wl.enc_seed(3), with_oracle=False)
+    env["plan"].evaluate(env["ctx"], [env["req"]])
+    torch.cuda.synchronize()
+    expected = np.concatenate([nw.head_plain(f[q], w) for q in range(4)])
+    assert list(_decrypt_values(env)) == list(nw._mod(expected, env["p"].t))
+
+
+def test_batched_requests_equal_single_and_graph_replay():
+    """Three requests with different keys and inputs in one evaluation equal
+    three single evaluations; graph replays (with eager work in between)
+    equal the eager result every time."""
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    _, W = wl.cfg0_inputs()
+    envs = []
+    for k in range(3):
+        x = wl.rng(1000 + k).integers(-128, 128, size=64)
+        envs.append(_setup("cfg0", networks.dense64_layers(W), None, x, 77 + k, 99 + k, with_oracle=False))
+    ctx, plan = envs[0]["ctx"], envs[0]["plan"]
+    # re-home every request onto the first context (same parameters)
+    reqs = []
+    for e in envs:
+        r = e["req"]
+        reqs.append(dict(rlk=r["rlk"], gks=r["gks"], inputs=r["inputs"], outputs=[ctx.empty_ct() for _ in r["outputs"]]))
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    for e, r in zip(envs, reqs):
+        e["plan"].evaluate(e["ctx"], [e["req"]])
+        torch.cuda.synchronize()
+        for a, b in zip(r["outputs"], e["req"]["outputs"]):
+            assert torch.equal(a, b)
+    eager = [[o.clone() for o in r["outputs"]] for r in reqs]
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        for r in reqs:
+            for o in r["outputs"]:
+                o.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            plan.evaluate(ctx, reqs, graph=True, stream=s)
+        s.synchronize()
+        junk = ctx.mul_scalar(reqs[0]["inputs"][0], 3)   # eager work between replays
+        torch.cuda.synchronize()
+        for r, ref in zip(reqs, eager):
+            for a, b in zip(r["outputs"], ref):
+                assert torch.equal(a, b), f"replay {rep}"
+        del junk
