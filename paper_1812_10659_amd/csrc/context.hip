@@ -149,7 +149,7 @@ static std::vector<uint64_t> mrc_host(const std::vector<uint64_t> &r, const std:
 
 static int build_tables(lola_ctx *ctx) {
     const uint32_t N = ctx->N, np = ctx->nprimes();
-    std::vector<uint32_t> tw((size_t)np * N), twp(tw.size()), itw(tw.size()), itwp(tw.size());
+    std::vector<TwPair> tw((size_t)np * N), itw(tw.size());
     ctx->mc_host.assign(np, ModConst{});
     for (uint32_t p = 0; p < np; ++p) {
         const uint64_t q = ctx->primes[p];
@@ -163,10 +163,8 @@ static int build_tables(lola_ctx *ctx) {
         }
         for (uint32_t k = 0; k < N; ++k) {
             uint32_t b = bitrev(k, ctx->logN);
-            tw[(size_t)p * N + k] = (uint32_t)pw[b];
-            itw[(size_t)p * N + k] = (uint32_t)ipw[b];
-            twp[(size_t)p * N + k] = shoup_companion((uint32_t)pw[b], (uint32_t)q);
-            itwp[(size_t)p * N + k] = shoup_companion((uint32_t)ipw[b], (uint32_t)q);
+            tw[(size_t)p * N + k] = TwPair{(uint32_t)pw[b], shoup_companion((uint32_t)pw[b], (uint32_t)q)};
+            itw[(size_t)p * N + k] = TwPair{(uint32_t)ipw[b], shoup_companion((uint32_t)ipw[b], (uint32_t)q)};
         }
         ModConst &c = ctx->mc_host[p];
         c.q = (uint32_t)q;
@@ -182,18 +180,14 @@ static int build_tables(lola_ctx *ctx) {
         uint64_t ninv = invmod_host(N, q);
         c.ninv = (uint32_t)ninv;
         c.ninv_shoup = shoup_companion(c.ninv, (uint32_t)q);
-        c.last_w = (uint32_t)mulmod_host(ninv, itw[(size_t)p * N + 1], q);
+        c.last_w = (uint32_t)mulmod_host(ninv, itw[(size_t)p * N + 1].w, q);
         c.last_w_shoup = shoup_companion(c.last_w, (uint32_t)q);
     }
-    size_t tb = tw.size() * sizeof(uint32_t);
+    size_t tb = tw.size() * sizeof(TwPair);
     LOLA_HIP(hipMalloc(&ctx->d_tw, tb));
-    LOLA_HIP(hipMalloc(&ctx->d_twp, tb));
     LOLA_HIP(hipMalloc(&ctx->d_itw, tb));
-    LOLA_HIP(hipMalloc(&ctx->d_itwp, tb));
     LOLA_HIP(hipMemcpy(ctx->d_tw, tw.data(), tb, hipMemcpyHostToDevice));
-    LOLA_HIP(hipMemcpy(ctx->d_twp, twp.data(), tb, hipMemcpyHostToDevice));
     LOLA_HIP(hipMemcpy(ctx->d_itw, itw.data(), tb, hipMemcpyHostToDevice));
-    LOLA_HIP(hipMemcpy(ctx->d_itwp, itwp.data(), tb, hipMemcpyHostToDevice));
     LOLA_HIP(hipMalloc(&ctx->d_mc, np * sizeof(ModConst)));
     LOLA_HIP(hipMemcpy(ctx->d_mc, ctx->mc_host.data(), np * sizeof(ModConst), hipMemcpyHostToDevice));
 
@@ -397,8 +391,8 @@ void lola_ctx_destroy(lola_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (void *p : {(void *)ctx->d_mc, (void *)ctx->d_mrc, (void *)ctx->d_tw, (void *)ctx->d_twp,
-                    (void *)ctx->d_itw, (void *)ctx->d_itwp, (void *)ctx->d_slotpos, ctx->d_scratch,
+    for (void *p : {(void *)ctx->d_mc, (void *)ctx->d_mrc, (void *)ctx->d_tw,
+                    (void *)ctx->d_itw, (void *)ctx->d_slotpos, ctx->d_scratch,
                     (void *)ctx->d_ring})
         if (p) (void)hipFree(p);
     if (ctx->h_ring) (void)hipHostFree(ctx->h_ring);

@@ -15,52 +15,53 @@
 //                               multiply-accumulate with the key; for P the
 //                               two sums are also brought back to coefficients
 //   ks_moddown  (2L per job):   lift [u_P]_P into q_j, NTT, subtract, times
-//                               P^-1, add the c0 (or d0 / d1) term.
+//                               P^-1, add the c0 (or d0 / d1) term and an
+//                               optional whole-ciphertext addend (fused
+//                               rotate-and-add).
 #include "ntt_core.hpp"
 #include "program.hpp"
 
 namespace lola {
-
 
 __device__ __forceinline__ uint32_t perm_src(uint32_t idx, uint32_t g, uint32_t logN) {
     return g > 1 ? galois_src_index(idx, g, logN) : idx;
 }
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(
-    const KsJob *__restrict__ jobs, uint32_t L, const ModConst *__restrict__ mcs,
-    const uint32_t *__restrict__ itw, const uint32_t *__restrict__ itwp) {
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const KsJob *__restrict__ jobs, uint32_t L,
+                                                                      const ModConst *__restrict__ mcs,
+                                                                      const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[1 << LOGN];
     const KsJob job = jobs[blockIdx.y];
     const uint32_t i = blockIdx.x;
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const ModConst mc = mcs[i];
     const uint32_t *xi = job.x + ((size_t)i << LOGN);
     uint32_t *Xp = job.scratch + ((size_t)(L + i) << LOGN);
     uint32_t x[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) {
-        const int idx = spectral_index<LOGN>(tid, r);
+        const uint32_t idx = spectral_index<LOGN>(tid, r);
         x[r] = xi[perm_src(idx, job.galois, LOGN)];
         Xp[idx] = x[r];  // sigma_g(x_i) in NTT form: the digit's own-modulus transform
     }
-    ntt_inv_regs<LOGN>(x, tid, sh, itw + ((size_t)i << LOGN), itwp + ((size_t)i << LOGN), mc);
+    ntt_inv_regs<LOGN>(x, tid, sh, itw + ((size_t)i << LOGN), mc);
     uint32_t *D = job.scratch + ((size_t)i << LOGN);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) D[natural_index<LOGN>(tid, r)] = x[r];
 }
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(
-    const KsJob *__restrict__ jobs, uint32_t L, const ModConst *__restrict__ mcs,
-    const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twp, const uint32_t *__restrict__ itw,
-    const uint32_t *__restrict__ itwp) {
-    constexpr int N = 1 << LOGN;
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJob *__restrict__ jobs, uint32_t L,
+                                                                     const ModConst *__restrict__ mcs,
+                                                                     const TwPair *__restrict__ tw,
+                                                                     const TwPair *__restrict__ itw) {
+    constexpr uint32_t N = 1u << LOGN;
     __shared__ uint32_t sh[N];
     const KsJob job = jobs[blockIdx.y];
     const uint32_t j = blockIdx.x;  // target modulus: q_j (j < L) or P (j == L)
     const ModConst mc = mcs[j];
-    const size_t M = L + 1;
+    const uint32_t M = L + 1;
     uint32_t a0[NTT_E], a1[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
@@ -69,7 +70,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(
         // iteration keeps the compiler from hoisting all of them (and the
         // transform's LDS addresses) out of the loop, which would not fit in
         // the 128 registers a 1024-thread workgroup allows.
-        int tid = threadIdx.x;
+        uint32_t tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         uint32_t x[NTT_E];
         if (i == j) {
@@ -82,58 +83,58 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(
             for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(D[natural_index<LOGN>(tid, r)], mc.q, mc.one_shoup);
             // The twiddle table does not change with i; an opaque copy of j
             // keeps the compiler from hoisting every twiddle load of the
-            // transform out of the loop (that would pin ~120 registers).
+            // transform out of the loop.
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
-            ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), twp + ((size_t)jj << LOGN), mc.q);
+            ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
         }
         // Key offsets pass through an opaque copy placed after the transform,
         // so the 32 key loads are not scheduled ahead of it.
-        uint32_t koff = i * 2 * (uint32_t)M + j;
+        uint32_t koff = i * 2 * M + j;
         asm volatile("" : "+s"(koff));
         const uint32_t *kb = job.key + ((size_t)koff << LOGN);
         const uint32_t *ka = job.key + ((size_t)(koff + M) << LOGN);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) {
-            const int idx = spectral_index<LOGN>(tid, r);
+            const uint32_t idx = spectral_index<LOGN>(tid, r);
             a0[r] = add_mod(a0[r], mont_mul(x[r], kb[idx], mc.q, mc.qneg_inv), mc.q);
             a1[r] = add_mod(a1[r], mont_mul(x[r], ka[idx], mc.q, mc.qneg_inv), mc.q);
         }
     }
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     if (j < L) {
         uint32_t *U0 = job.scratch + ((size_t)(2 * L + j) << LOGN);
         uint32_t *U1 = job.scratch + ((size_t)(3 * L + j) << LOGN);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) {
-            const int idx = spectral_index<LOGN>(tid, r);
+            const uint32_t idx = spectral_index<LOGN>(tid, r);
             U0[idx] = a0[r];
             U1[idx] = a1[r];
         }
     } else {
         uint32_t *UP = job.scratch + ((size_t)(4 * L) << LOGN);
-        const uint32_t *it = itw + ((size_t)j << LOGN), *itp = itwp + ((size_t)j << LOGN);
-        ntt_inv_regs<LOGN>(a0, tid, sh, it, itp, mc);
+        ntt_inv_regs<LOGN>(a0, tid, sh, itw + ((size_t)j << LOGN), mc);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) UP[natural_index<LOGN>(tid, r)] = a0[r];
-        int tid2 = tid;
+        uint32_t tid2 = tid;
         asm volatile("" : "+v"(tid2));
         uint32_t jj = j;
         asm volatile("" : "+s"(jj));
-        ntt_inv_regs<LOGN>(a1, tid2, sh, itw + ((size_t)jj << LOGN), itwp + ((size_t)jj << LOGN), mc);
+        ntt_inv_regs<LOGN>(a1, tid2, sh, itw + ((size_t)jj << LOGN), mc);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) UP[N + natural_index<LOGN>(tid2, r)] = a1[r];
     }
 }
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(
-    const KsJob *__restrict__ jobs, uint32_t L, const ModConst *__restrict__ mcs,
-    const uint32_t *__restrict__ tw, const uint32_t *__restrict__ twp, const MrcConst *__restrict__ mrc) {
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const KsJob *__restrict__ jobs, uint32_t L,
+                                                                       const ModConst *__restrict__ mcs,
+                                                                       const TwPair *__restrict__ tw,
+                                                                       const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[1 << LOGN];
     const KsJob job = jobs[blockIdx.z];
     const uint32_t j = blockIdx.x, c = blockIdx.y;
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const ModConst mc = mcs[j];
     const uint32_t P = mcs[L].q, halfP = P >> 1;
     const uint32_t Pq = mrc->Pq[j];
@@ -145,7 +146,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(
         const uint32_t vr = reduce32(v, mc.q, mc.one_shoup);
         x[r] = v > halfP ? sub_mod(vr, Pq, mc.q) : vr;  // [u_P]_P mod q_j
     }
-    ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)j << LOGN), twp + ((size_t)j << LOGN), mc.q);
+    ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
     const uint32_t *U = job.scratch + ((size_t)((2 + c) * L + j) << LOGN);
     const uint32_t *add = c == 0 ? job.add0 : job.add1;
     const uint32_t g = c == 0 ? job.galois : 0u;
@@ -155,7 +156,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(
     const uint32_t *addc = job.addct ? job.addct + ((size_t)(c * L + j) << LOGN) : nullptr;
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) {
-        const int idx = spectral_index<LOGN>(tid, r);
+        const uint32_t idx = spectral_index<LOGN>(tid, r);
         uint32_t w = shoup(sub_mod(U[idx], x[r], mc.q), pinv, pinvp, mc.q);
         if (addj) w = add_mod(w, addj[perm_src(idx, g, LOGN)], mc.q);
         if (addc) w = add_mod(w, addc[idx], mc.q);
@@ -174,16 +175,15 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t
         if (rc) return rc;
         ctx->timed_jobs += n;
     }
-#define LOLA_KS_CASE(LG)                                                                                    \
-    case LG:                                                                                                \
-        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(L, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_itw,  \
-                           ctx->d_itwp);                                                                     \
-        if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                            \
-        hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(L + 1, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_tw, \
-                           ctx->d_twp, ctx->d_itw, ctx->d_itwp);                                             \
-        if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                            \
-        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(L, 2, n), block, 0, s, d_jobs, L, ctx->d_mc,         \
-                           ctx->d_tw, ctx->d_twp, ctx->d_mrc);                                               \
+#define LOLA_KS_CASE(LG)                                                                                     \
+    case LG:                                                                                                 \
+        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(L, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_itw);  \
+        if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                             \
+        hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(L + 1, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_tw,  \
+                           ctx->d_itw);                                                                       \
+        if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                             \
+        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(L, 2, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_tw, \
+                           ctx->d_mrc);                                                                       \
         break;
     switch (ctx->logN) {
         LOLA_KS_CASE(10)

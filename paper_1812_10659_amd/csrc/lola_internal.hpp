@@ -59,7 +59,7 @@ struct lola_ctx {
     // device tables
     lola::ModConst *d_mc = nullptr;
     lola::MrcConst *d_mrc = nullptr;
-    uint32_t *d_tw = nullptr, *d_twp = nullptr, *d_itw = nullptr, *d_itwp = nullptr;  // [nprimes][N]
+    lola::TwPair *d_tw = nullptr, *d_itw = nullptr;   // [nprimes][N] (twiddle, Shoup companion)
     uint32_t *d_slotpos = nullptr;       // slot s -> spectral index mod t
     // scratch arena
     void *d_scratch = nullptr;

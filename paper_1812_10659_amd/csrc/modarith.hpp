@@ -36,6 +36,11 @@ struct ModConst {
     uint32_t r_shoup;  // Shoup companion of r_mod
 };
 
+// A constant multiplier with its Shoup companion, loaded as one 64-bit word.
+struct TwPair {
+    uint32_t w, wp;
+};
+
 LOLA_HD uint32_t mulhi32(uint32_t a, uint32_t b) {
 #if defined(__HIP_DEVICE_COMPILE__)
     return __umulhi(a, b);

@@ -19,6 +19,12 @@
 // way, so both read and write global memory in coalesced order without an
 // extra staging pass.
 //
+// Twiddles are stored as (w, floor(w 2^32 / q)) pairs and read with one 64-bit
+// load.  When a pass's sub-transform stride is at least the wavefront width,
+// all 64 lanes of a wave sit in the same butterfly group, so the twiddle index
+// is wave-uniform; it is then moved to a scalar register and the load becomes
+// a scalar load (passes 0 and, for N = 16384, 1).
+//
 // The code is __host__ __device__ so the same pass logic can be driven thread
 // by thread on the CPU to check its indexing.
 #pragma once
@@ -28,20 +34,27 @@ namespace lola {
 
 constexpr int NTT_E = 16;      // residues per thread
 constexpr int NTT_LOGE = 4;
+constexpr int WAVE = 64;
 
 template <int LOGN, int S0, int NS>
 struct NttPass {
-    static constexpr int N = 1 << LOGN;
-    static constexpr int T = N / NTT_E;
-    static constexpr int SUB = 1 << NS;          // sub-transform length
-    static constexpr int PER = NTT_E / SUB;      // sub-transforms per thread
-    static constexpr int STR = N >> (S0 + NS);   // stride between its residues
-    // Global index held by register r = v*SUB + k of thread tid.
-    LOLA_HD static int base(int tid, int v) {
-        int u = tid + v * T;
+    static constexpr uint32_t N = 1u << LOGN;
+    static constexpr uint32_t T = N / NTT_E;
+    static constexpr uint32_t SUB = 1u << NS;          // sub-transform length
+    static constexpr uint32_t PER = NTT_E / SUB;       // sub-transforms per thread
+    static constexpr uint32_t STR = N >> (S0 + NS);    // stride between its residues
+    // Global index held by register r = v*SUB + k of thread tid.  The wave
+    // owning lanes [64w, 64w+64) takes sub-transforms [64w PER, 64(w+1) PER),
+    // lane l taking l, l + 64, ... (u = 64 w PER + l + 64 v): when
+    // 64*PER >= STR a wave's lanes hold one contiguous block of 64*16
+    // residues, and for a fixed register neighbouring lanes touch
+    // neighbouring addresses (coalesced global access).
+    LOLA_HD static uint32_t base(uint32_t tid, uint32_t v) {
+        const uint32_t u = (tid & ~(uint32_t)(WAVE - 1)) * PER + (tid & (uint32_t)(WAVE - 1)) + (uint32_t)WAVE * v;
         return (u / STR) * (N >> S0) + (u % STR);
     }
-    LOLA_HD static int index(int tid, int r) { return base(tid, r / SUB) + (r % SUB) * STR; }
+    static constexpr bool WAVE_BLOCK = (uint32_t)WAVE * PER >= STR;
+    LOLA_HD static uint32_t index(uint32_t tid, uint32_t r) { return base(tid, r / SUB) + (r % SUB) * STR; }
 };
 
 template <int LOGN>
@@ -55,26 +68,36 @@ struct NttShape {
     using Last = NttPass<LOGN, LAST_S0, LAST_NS>;
 };
 
+// Twiddle-pair index of stage s for the butterfly group containing global
+// index g: 2^s + (g >> (log2N - s)); made scalar when wave-uniform.
+template <int LOGN, int S0, int NS>
+LOLA_HD uint32_t tw_index(uint32_t b, uint32_t k, int s) {
+    using PS = NttPass<LOGN, S0, NS>;
+    uint32_t gi = (1u << s) + ((b + k * PS::STR) >> (LOGN - s));
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (PS::STR >= (uint32_t)WAVE) gi = __builtin_amdgcn_readfirstlane(gi);
+#endif
+    return gi;
+}
+
 // ---- one forward pass on registers (layout of NttPass<LOGN,S0,NS>) ----
 template <int LOGN, int S0, int NS>
-LOLA_HD void fwd_pass_regs(uint32_t (&x)[NTT_E], int tid, const uint32_t *__restrict__ tw,
-                           const uint32_t *__restrict__ twp, uint32_t q) {
+LOLA_HD void fwd_pass_regs(uint32_t (&x)[NTT_E], uint32_t tid, const TwPair *__restrict__ tw, uint32_t q) {
     using PS = NttPass<LOGN, S0, NS>;
     const uint32_t twoq = 2 * q;
 #pragma unroll
     for (int sg = 0; sg < NS; ++sg) {
         const int s = S0 + sg;
-        const int h = PS::SUB >> (sg + 1);
+        const uint32_t h = PS::SUB >> (sg + 1);
 #pragma unroll
-        for (int v = 0; v < PS::PER; ++v) {
-            const int b = PS::base(tid, v);
+        for (uint32_t v = 0; v < PS::PER; ++v) {
+            const uint32_t b = PS::base(tid, v);
 #pragma unroll
-            for (int k = 0; k < PS::SUB; ++k) {
+            for (uint32_t k = 0; k < PS::SUB; ++k) {
                 if (k & h) continue;
-                const int gi = (1 << s) + ((b + k * PS::STR) >> (LOGN - s));
-                const uint32_t w = tw[gi], wp = twp[gi];
+                const TwPair t = tw[tw_index<LOGN, S0, NS>(b, k, s)];
                 uint32_t X = csub(x[v * PS::SUB + k], twoq);
-                uint32_t Tm = shoup_lazy(x[v * PS::SUB + k + h], w, wp, q);
+                uint32_t Tm = shoup_lazy(x[v * PS::SUB + k + h], t.w, t.wp, q);
                 x[v * PS::SUB + k] = X + Tm;
                 x[v * PS::SUB + k + h] = X - Tm + twoq;
             }
@@ -84,19 +107,19 @@ LOLA_HD void fwd_pass_regs(uint32_t (&x)[NTT_E], int tid, const uint32_t *__rest
 
 // ---- one inverse pass on registers (stages S0+NS-1 down to S0) ----
 template <int LOGN, int S0, int NS, bool LASTSTAGE_SCALE>
-LOLA_HD void inv_pass_regs(uint32_t (&x)[NTT_E], int tid, const uint32_t *__restrict__ itw,
-                           const uint32_t *__restrict__ itwp, const ModConst &mc) {
+LOLA_HD void inv_pass_regs(uint32_t (&x)[NTT_E], uint32_t tid, const TwPair *__restrict__ itw,
+                           const ModConst &mc) {
     using PS = NttPass<LOGN, S0, NS>;
     const uint32_t q = mc.q, twoq = mc.twoq;
 #pragma unroll
     for (int sg = NS - 1; sg >= 0; --sg) {
         const int s = S0 + sg;
-        const int h = PS::SUB >> (sg + 1);
+        const uint32_t h = PS::SUB >> (sg + 1);
 #pragma unroll
-        for (int v = 0; v < PS::PER; ++v) {
-            const int b = PS::base(tid, v);
+        for (uint32_t v = 0; v < PS::PER; ++v) {
+            const uint32_t b = PS::base(tid, v);
 #pragma unroll
-            for (int k = 0; k < PS::SUB; ++k) {
+            for (uint32_t k = 0; k < PS::SUB; ++k) {
                 if (k & h) continue;
                 uint32_t U = x[v * PS::SUB + k], V = x[v * PS::SUB + k + h];
                 if (LASTSTAGE_SCALE && s == 0) {
@@ -104,9 +127,9 @@ LOLA_HD void inv_pass_regs(uint32_t (&x)[NTT_E], int tid, const uint32_t *__rest
                     x[v * PS::SUB + k] = shoup_lazy(U + V, mc.ninv, mc.ninv_shoup, q);
                     x[v * PS::SUB + k + h] = shoup_lazy(U - V + twoq, mc.last_w, mc.last_w_shoup, q);
                 } else {
-                    const int gi = (1 << s) + ((b + k * PS::STR) >> (LOGN - s));
+                    const TwPair t = itw[tw_index<LOGN, S0, NS>(b, k, s)];
                     x[v * PS::SUB + k] = csub(U + V, twoq);
-                    x[v * PS::SUB + k + h] = shoup_lazy(U - V + twoq, itw[gi], itwp[gi], q);
+                    x[v * PS::SUB + k + h] = shoup_lazy(U - V + twoq, t.w, t.wp, q);
                 }
             }
         }
@@ -114,17 +137,17 @@ LOLA_HD void inv_pass_regs(uint32_t (&x)[NTT_E], int tid, const uint32_t *__rest
 }
 
 template <int LOGN, int S0, int NS>
-LOLA_HD void regs_to_lds(const uint32_t (&x)[NTT_E], int tid, uint32_t *sh) {
+LOLA_HD void regs_to_lds(const uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh) {
     using PS = NttPass<LOGN, S0, NS>;
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) sh[PS::index(tid, r)] = x[r];
+    for (uint32_t r = 0; r < NTT_E; ++r) sh[PS::index(tid, r)] = x[r];
 }
 
 template <int LOGN, int S0, int NS>
-LOLA_HD void lds_to_regs(uint32_t (&x)[NTT_E], int tid, const uint32_t *sh) {
+LOLA_HD void lds_to_regs(uint32_t (&x)[NTT_E], uint32_t tid, const uint32_t *sh) {
     using PS = NttPass<LOGN, S0, NS>;
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) x[r] = sh[PS::index(tid, r)];
+    for (uint32_t r = 0; r < NTT_E; ++r) x[r] = sh[PS::index(tid, r)];
 }
 
 // Pass p of the forward transform covers stages [4p, min(4p+4, LOGN)).
@@ -136,36 +159,58 @@ struct FwdPassAt {
 
 #if defined(__HIP_DEVICE_COMPILE__)
 #define LOLA_BARRIER() __syncthreads()
+// Ordering of LDS traffic among the lanes of one wave: the LDS unit serves a
+// wave's instructions in order; this keeps the compiler from moving LDS
+// accesses across the point (no s_barrier is issued).
+#define LOLA_WAVE_SYNC()                                       \
+    do {                                                       \
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+        __builtin_amdgcn_wave_barrier();                       \
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+    } while (0)
 #else
 #define LOLA_BARRIER() ((void)0)
+#define LOLA_WAVE_SYNC() ((void)0)
 #endif
 
+// Exchange between two passes: a workgroup barrier unless every wave reads
+// back exactly the block of residues it wrote.
+template <int LOGN, class PA, class PB>
+LOLA_HD void pass_exchange_sync() {
+    if constexpr (NttPass<LOGN, PA::S0, PA::NS>::WAVE_BLOCK && NttPass<LOGN, PB::S0, PB::NS>::WAVE_BLOCK)
+        LOLA_WAVE_SYNC();
+    else
+        LOLA_BARRIER();
+}
+
 // Device-side driver.  x enters in the first pass's layout and leaves in the
-// last pass's layout (reduced to [0, q)).  sh: N words of LDS.  The caller
-// must not touch sh between the call's start and end; a barrier is taken at
-// entry so a previous use of sh by the same workgroup is complete.
+// last pass's layout (reduced to [0, q)).  sh: N words of LDS.  A barrier is
+// taken before the first LDS write, so a previous use of sh by the same
+// workgroup is complete.
 template <int LOGN, int P = 0>
 struct FwdDriver {
-    LOLA_HD static void run(uint32_t (&x)[NTT_E], int tid, uint32_t *sh, const uint32_t *tw,
-                            const uint32_t *twp, uint32_t q) {
+    LOLA_HD static void run(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
         constexpr int NPASS = NttShape<LOGN>::NPASS;
         using PA = FwdPassAt<LOGN, P>;
-        fwd_pass_regs<LOGN, PA::S0, PA::NS>(x, tid, tw, twp, q);
+        fwd_pass_regs<LOGN, PA::S0, PA::NS>(x, tid, tw, q);
         if constexpr (P + 1 < NPASS) {
             using PB = FwdPassAt<LOGN, P + 1>;
-            LOLA_BARRIER();
+            // The first exchange of a transform waits for every earlier LDS
+            // reader of the workgroup; later ones only for this wave when
+            // both layouts keep each wave on its own block.
+            if constexpr (P == 0) LOLA_BARRIER();
+            else pass_exchange_sync<LOGN, PA, PB>();
             regs_to_lds<LOGN, PA::S0, PA::NS>(x, tid, sh);
-            LOLA_BARRIER();
+            pass_exchange_sync<LOGN, PA, PB>();
             lds_to_regs<LOGN, PB::S0, PB::NS>(x, tid, sh);
-            FwdDriver<LOGN, P + 1>::run(x, tid, sh, tw, twp, q);
+            FwdDriver<LOGN, P + 1>::run(x, tid, sh, tw, q);
         }
     }
 };
 
 template <int LOGN>
-LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], int tid, uint32_t *sh, const uint32_t *tw,
-                          const uint32_t *twp, uint32_t q) {
-    FwdDriver<LOGN, 0>::run(x, tid, sh, tw, twp, q);
+LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
+    FwdDriver<LOGN, 0>::run(x, tid, sh, tw, q);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(csub(x[r], 2 * q), q);
 }
@@ -174,34 +219,35 @@ LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], int tid, uint32_t *sh, const uin
 // and leaves in the first pass's layout, reduced to [0, q).
 template <int LOGN, int P>
 struct InvDriver {
-    LOLA_HD static void run(uint32_t (&x)[NTT_E], int tid, uint32_t *sh, const uint32_t *itw,
-                            const uint32_t *itwp, const ModConst &mc) {
+    LOLA_HD static void run(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *itw,
+                            const ModConst &mc) {
         using PA = FwdPassAt<LOGN, P>;
-        inv_pass_regs<LOGN, PA::S0, PA::NS, (P == 0)>(x, tid, itw, itwp, mc);
+        inv_pass_regs<LOGN, PA::S0, PA::NS, (P == 0)>(x, tid, itw, mc);
         if constexpr (P > 0) {
             using PB = FwdPassAt<LOGN, P - 1>;
-            LOLA_BARRIER();
+            if constexpr (P == NttShape<LOGN>::NPASS - 1) LOLA_BARRIER();
+            else pass_exchange_sync<LOGN, PA, PB>();
             regs_to_lds<LOGN, PA::S0, PA::NS>(x, tid, sh);
-            LOLA_BARRIER();
+            pass_exchange_sync<LOGN, PA, PB>();
             lds_to_regs<LOGN, PB::S0, PB::NS>(x, tid, sh);
-            InvDriver<LOGN, P - 1>::run(x, tid, sh, itw, itwp, mc);
+            InvDriver<LOGN, P - 1>::run(x, tid, sh, itw, mc);
         }
     }
 };
 
 template <int LOGN>
-LOLA_HD void ntt_inv_regs(uint32_t (&x)[NTT_E], int tid, uint32_t *sh, const uint32_t *itw,
-                          const uint32_t *itwp, const ModConst &mc) {
-    InvDriver<LOGN, NttShape<LOGN>::NPASS - 1>::run(x, tid, sh, itw, itwp, mc);
+LOLA_HD void ntt_inv_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *itw,
+                          const ModConst &mc) {
+    InvDriver<LOGN, NttShape<LOGN>::NPASS - 1>::run(x, tid, sh, itw, mc);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(x[r], mc.q);
 }
 
 // Global index of register r in the forward input / inverse output layout.
 template <int LOGN>
-LOLA_HD int natural_index(int tid, int r) { return NttShape<LOGN>::First::index(tid, r); }
+LOLA_HD uint32_t natural_index(uint32_t tid, uint32_t r) { return NttShape<LOGN>::First::index(tid, r); }
 // Global index of register r in the forward output / inverse input layout.
 template <int LOGN>
-LOLA_HD int spectral_index(int tid, int r) { return NttShape<LOGN>::Last::index(tid, r); }
+LOLA_HD uint32_t spectral_index(uint32_t tid, uint32_t r) { return NttShape<LOGN>::Last::index(tid, r); }
 
 }  // namespace lola

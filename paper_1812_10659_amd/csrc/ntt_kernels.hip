@@ -6,13 +6,12 @@ namespace lola {
 
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ntt_jobs_kernel(
-    const NttJob *__restrict__ jobs, const ModConst *__restrict__ mcs, const uint32_t *__restrict__ tw,
-    const uint32_t *__restrict__ twp, const uint32_t *__restrict__ itw, const uint32_t *__restrict__ itwp,
-    uint32_t t, const MrcConst *__restrict__ mrc) {
+    const NttJob *__restrict__ jobs, const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw,
+    const TwPair *__restrict__ itw, uint32_t t, const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[1 << LOGN];
     const NttJob job = jobs[blockIdx.x];
     const ModConst mc = mcs[job.prime];
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const size_t toff = (size_t)job.prime << LOGN;
     uint32_t x[NTT_E];
     if (!(job.flags & NTT_INVERSE)) {
@@ -30,7 +29,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ntt_jobs_kernel(
             if (job.flags & NTT_SRC_REDUCE) v = reduce32(v, mc.q, mc.one_shoup);
             x[r] = v;
         }
-        ntt_fwd_regs<LOGN>(x, tid, sh, tw + toff, twp + toff, mc.q);
+        ntt_fwd_regs<LOGN>(x, tid, sh, tw + toff, mc.q);
         if (job.flags & NTT_MUL_DELTA) {
             const uint32_t d = mrc->deltaq[job.prime], dp = mrc->deltaqp[job.prime];
 #pragma unroll
@@ -49,7 +48,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ntt_jobs_kernel(
             if (job.flags & NTT_FROM_MONT) v = mont_mul(v, 1u, mc.q, mc.qneg_inv);
             x[r] = v;
         }
-        ntt_inv_regs<LOGN>(x, tid, sh, itw + toff, itwp + toff, mc);
+        ntt_inv_regs<LOGN>(x, tid, sh, itw + toff, mc);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) job.dst[natural_index<LOGN>(tid, r)] = x[r];
     }
@@ -61,7 +60,7 @@ int launch_ntt_jobs_dev(lola_ctx *ctx, const NttJob *d_jobs, int n, hipStream_t 
 #define LOLA_NTT_CASE(LG)                                                                              \
     case LG:                                                                                           \
         hipLaunchKernelGGL(ntt_jobs_kernel<LG>, grid, block, 0, s, d_jobs, ctx->d_mc, ctx->d_tw,      \
-                           ctx->d_twp, ctx->d_itw, ctx->d_itwp, ctx->t, ctx->d_mrc);                               \
+                           ctx->d_itw, ctx->t, ctx->d_mrc);                                             \
         break;
     switch (ctx->logN) {
         LOLA_NTT_CASE(10)
