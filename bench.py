@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--clients", type=int, default=8, help="distinct key sets")
     ap.add_argument("--latency-runs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="mixed Poisson serving run after the timed steps (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -188,6 +190,13 @@ def main():
                 "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job"},
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
+    if args.serve_requests > 0:
+        # Poisson arrivals at 200/s: 70% N=16384 MNIST-shaped, 30% N=4096 dense-64,
+        # 8 resident key sets per ring size, continuous batching vs one at a time
+        from paper_1812_10659_amd import serving
+        del reqs, keys
+        torch.cuda.empty_cache()
+        out["serving"] = serving.run_serving(n_req=args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, w)
     print(json.dumps(out), flush=True)

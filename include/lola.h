@@ -280,6 +280,34 @@ int lola_evaluate(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint
 int lola_evaluate_graph(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint32_t n_req,
                         lola_stream stream);
 
+/* ---------------------------------------------------------------- serving */
+/* A request loop with continuous batching (a server holding encrypted
+ * queries, keys and intermediate ciphertexts on the device).  Models are
+ * loaded plans, one per ring size; each runs on its own stream with a pool of
+ * request slots.  Admission is by HBM footprint: a model gets as many slots
+ * (register file + temporaries of one request) as fit in the remaining
+ * budget, up to max_inflight; a queued request enters when a slot is free.
+ * Every lola_server_step admits queued requests and issues, per model, the
+ * next wave of all its in-flight requests as one batched launch set, so
+ * requests that arrive while others are on the GPU join them at once.  The
+ * caller keeps a request's buffers alive until its tag is returned by
+ * lola_server_poll.  Results equal those of lola_evaluate on the request
+ * alone, word for word. */
+typedef struct lola_server lola_server;
+int lola_server_create(size_t hbm_budget_bytes, lola_server **out);
+void lola_server_destroy(lola_server *srv);
+int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint32_t max_inflight,
+                          uint32_t *model_id);
+/* Slots granted, HBM bytes per slot, the model's scratch bytes, jobs launched. */
+int lola_server_model_info(const lola_server *srv, uint32_t model_id, uint32_t *slots, uint64_t *footprint_bytes,
+                           uint64_t *scratch_bytes, uint64_t *launched_jobs);
+int lola_server_submit(lola_server *srv, uint32_t model_id, const lola_request *req, uint64_t tag);
+/* One scheduling round (non-blocking except to keep two rounds in flight per
+ * model); *pending = queued + in-flight requests. */
+int lola_server_step(lola_server *srv, uint32_t *pending);
+/* Tags of requests completed since the last poll (at most cap). */
+int lola_server_poll(lola_server *srv, uint64_t *tags, uint32_t cap, uint32_t *n);
+
 /* Kernel timing (for measurement): when enabled, the library records HIP
  * events around every launch of the key-switching inner kernel (the
  * per-modulus NTT + key inner product) on the launch stream; the totals are

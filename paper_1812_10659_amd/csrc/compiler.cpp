@@ -146,6 +146,7 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
     if (cv.in_h != cv.in_w || cv.k <= 0 || cv.stride <= 0 || cv.maps <= 0 || cv.in_h < cv.k || !cv.weight)
         return unsupported("bad convolution shape");
     const int n_out = (cv.in_h - cv.k) / cv.stride + 1, V = n_out * n_out, K2 = cv.k * cv.k;
+    if (K2 > (int)LIN_MAX) return unsupported("convolution window larger than 32 positions");
     if ((uint32_t)(cv.maps * V) > N / 2) return unsupported("convolution output exceeds one slot row");
     const int D = cv.maps * V;
     if (d1.in_dim != D || !d1.weight || d1.out_dim <= 0) return unsupported("first dense layer must take maps*n*n inputs");
@@ -341,6 +342,8 @@ void schedule(lola_plan *p) {
         maxl = std::max<uint32_t>(maxl, (uint32_t)o.level);
     }
     p->n_waves = maxl;
+    p->level_ops.assign(maxl + 1, {});
+    for (size_t i = 0; i < p->ops.size(); ++i) p->level_ops[p->ops[i].level].push_back((int)i);
     // last level at which each register is read
     std::vector<int> last(p->n_regs, -1);
     for (const Op &o : p->ops)

@@ -68,7 +68,7 @@ struct lola_ctx {
     // device ring; slabs are reused once the event recorded when leaving them
     // has completed.
     static constexpr int RING_SLABS = 16;
-    static constexpr size_t RING_SLAB = 256 * 1024;
+    static constexpr size_t RING_SLAB = 1024 * 1024;
     uint8_t *h_ring = nullptr, *d_ring = nullptr;
     size_t ring_off = 0;
     hipEvent_t ring_ev[RING_SLABS] = {};

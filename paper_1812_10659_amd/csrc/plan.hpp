@@ -42,9 +42,11 @@ struct lola_plan {
     std::vector<int> phys;                      // virtual -> physical register (-1: input/output)
     uint32_t n_phys = 0;
     uint32_t max_squares_per_wave = 0;
+    std::vector<std::vector<int>> level_ops;    // op indices of each wave (index = level)
     // loaded constants (device)
     const lola_ctx *loaded_for = nullptr;
     std::vector<uint32_t *> d_cmul, d_cadd;
+    std::vector<uint32_t *> d_wtab;             // per op: lincomb scalar table [n_src][2][L]
     // bound evaluation state
     uint32_t *d_ws = nullptr;                   // registers + square temporaries + scratch
     size_t ws_words = 0;
@@ -56,6 +58,36 @@ struct lola_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_valid = false;
-    // device arrays referenced by LinJob (pointer lists and scalar tables)
-    std::vector<uint64_t> lin_aux;              // packed into the blob at bind time
 };
+
+namespace lola {
+
+// One request's buffers inside an executor: caller-owned inputs / outputs and
+// keys (the request) plus its register file and square temporaries.
+struct ReqView {
+    const lola_request *req;
+    uint32_t *regs;      // n_phys ciphertexts
+    uint32_t *sq;        // max_squares_per_wave size-3 ciphertexts
+};
+
+// The jobs of one wave, gathered over any number of requests.
+struct LevelJobs {
+    std::vector<LinJob> lin;
+    std::vector<PlainJob> plain;
+    std::vector<KsJob> ks, relin;
+    std::vector<MulJob> muls;
+    size_t count() const { return lin.size() + plain.size() + ks.size() + muls.size(); }
+};
+
+// Appends the jobs of plan level `level` for one request.
+int emit_level(const lola_ctx *ctx, const lola_plan *p, const ReqView &rv, uint32_t level, LevelJobs &out);
+// Appends the launches of gathered jobs to a program (key switches and
+// products chunked over the given scratch).
+void program_level(const lola_ctx *ctx, Program &prog, LevelJobs &jobs, uint32_t *scratch, uint32_t ks_chunk,
+                   uint32_t mul_chunk);
+// Scratch words that program_level needs for chunk sizes ks_chunk / mul_chunk.
+size_t level_scratch_words(const lola_ctx *ctx, uint32_t ks_chunk, uint32_t mul_chunk);
+// Checks a request's arrays against the plan (keys, inputs, outputs, aliasing).
+int validate_request(const lola_plan *p, const lola_request &r);
+
+}  // namespace lola

@@ -6,7 +6,7 @@ namespace lola {
 // dst = sum_k w_k src_k (+ add on component 0).  grid (2LN/4/256, jobs)
 __global__ void lin_kernel(const LinJob *__restrict__ jobs, uint32_t logN, uint32_t L,
                            const ModConst *__restrict__ mcs) {
-    const LinJob job = jobs[blockIdx.y];
+    const LinJob &job = jobs[blockIdx.y];
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n4 = ((size_t)2 * L << logN) / 4;
     if (i >= n4) return;
@@ -15,7 +15,7 @@ __global__ void lin_kernel(const LinJob *__restrict__ jobs, uint32_t logN, uint3
     const uint32_t q = mcs[limb].q;
     uint4 acc = make_uint4(0, 0, 0, 0);
     for (uint32_t k = 0; k < job.n_src; ++k) {
-        const uint4 x = ((const uint4 *)job.srcs[k])[i];
+        const uint4 x = ((const uint4 *)jobs[blockIdx.y].srcs[k])[i];
         const uint32_t w = job.w[(2 * k) * L + limb], wp = job.w[(2 * k + 1) * L + limb];
         acc.x = add_mod(acc.x, shoup(x.x, w, wp, q), q);
         acc.y = add_mod(acc.y, shoup(x.y, w, wp, q), q);

@@ -11,8 +11,9 @@
 namespace lola {
 
 // Element-wise jobs (one ciphertext each, 2 L N words).
+constexpr uint32_t LIN_MAX = 32;   // sources of one linear combination
 struct LinJob {              // dst = sum_k w_k src_k (+ add-form constant on c0)
-    const uint32_t *const *srcs;   // device array of n_src pointers
+    const uint32_t *srcs[LIN_MAX];
     const uint32_t *w;             // device [n_src][2][L]: residue, Shoup companion per limb
     const uint32_t *add;           // [L][N] add-form constant or null
     uint32_t *dst;

@@ -1,0 +1,250 @@
+// Serving loop with continuous batching.
+//
+// A model is a loaded plan on its context (one ring size each).  Each model
+// owns a stream, a pool of request slots (register file + square temporaries
+// per slot) sized by the HBM budget, and its own scratch.  A scheduling round
+// admits queued requests into free slots, then, per model, gathers the next
+// wave of every in-flight request -- requests at different depths of the plan
+// share the round -- and issues it as one batched launch set on the model's
+// stream.  Models of different ring sizes run on separate streams, so their
+// work overlaps on the device.  A request's slot is released when the event
+// recorded after its last wave has completed.
+#include <chrono>
+#include <deque>
+
+#include "plan.hpp"
+
+namespace lola {
+namespace {
+
+constexpr uint32_t SRV_KS_CHUNK = 256;
+constexpr uint32_t SRV_MUL_CHUNK = 16;
+constexpr uint32_t SRV_LOOKAHEAD = 2;   // rounds in flight per model
+
+struct Pending {
+    uint64_t tag;
+    const uint32_t *rlk;
+    std::vector<const uint32_t *> gk, in;
+    std::vector<uint32_t *> out;
+    lola_request view() const {
+        return lola_request{rlk, gk.data(), in.data(), out.data()};
+    }
+};
+
+struct Slot {
+    bool busy = false;
+    bool finished = false;      // last wave issued; waiting for its round event
+    uint64_t finish_round = 0;
+    uint32_t level = 0;
+    Pending req;
+    lola_request rq{};
+    uint32_t *regs = nullptr, *sq = nullptr;
+};
+
+struct Model {
+    lola_ctx *ctx = nullptr;
+    lola_plan *plan = nullptr;
+    hipStream_t stream = nullptr;
+    uint32_t *ws = nullptr;         // slots' registers and temporaries, then scratch
+    uint32_t *scratch = nullptr;
+    size_t footprint_bytes = 0;     // per slot
+    std::vector<Slot> slots;
+    std::deque<Pending> queue;
+    uint64_t round = 0;             // rounds issued
+    std::deque<std::pair<uint64_t, hipEvent_t>> inflight;   // (round, event)
+    uint64_t done_round = 0;        // every round <= done_round has completed
+    std::vector<hipEvent_t> free_events;
+    uint64_t launched_jobs = 0;
+};
+
+}  // namespace
+}  // namespace lola
+
+struct lola_server {
+    size_t budget = 0, used = 0;
+    std::vector<lola::Model> models;
+    std::vector<uint64_t> completed;   // tags since the last poll
+    uint64_t rounds = 0;
+};
+
+namespace lola {
+namespace {
+
+int retire(Model &m, std::vector<uint64_t> &completed, bool wait_one) {
+    while (!m.inflight.empty()) {
+        auto &f = m.inflight.front();
+        hipError_t e = wait_one ? hipEventSynchronize(f.second) : hipEventQuery(f.second);
+        if (e == hipErrorNotReady) break;
+        if (e != hipSuccess) return check_hip(e, "server round event");
+        m.done_round = f.first;
+        m.free_events.push_back(f.second);
+        m.inflight.pop_front();
+        wait_one = false;
+    }
+    for (Slot &s : m.slots)
+        if (s.busy && s.finished && s.finish_round <= m.done_round) {
+            completed.push_back(s.req.tag);
+            s.busy = false;
+            s.finished = false;
+        }
+    return LOLA_OK;
+}
+
+int round_model(lola_server *srv, Model &m) {
+    lola_plan *p = m.plan;
+    // admission into free slots (each slot's footprint was reserved at registration)
+    for (Slot &s : m.slots) {
+        if (m.queue.empty()) break;
+        if (s.busy) continue;
+        s.busy = true;
+        s.finished = false;
+        s.level = 1;
+        s.req = std::move(m.queue.front());
+        m.queue.pop_front();
+        s.rq = s.req.view();
+    }
+    LevelJobs jobs;
+    std::vector<Slot *> finishing;
+    for (Slot &s : m.slots) {
+        if (!s.busy || s.finished) continue;
+        ReqView rv{&s.rq, s.regs, s.sq};
+        int rc = emit_level(m.ctx, p, rv, s.level, jobs);
+        if (rc) return rc;
+        if (++s.level > p->n_waves) finishing.push_back(&s);
+    }
+    if (jobs.count() == 0) return LOLA_OK;
+    while (m.inflight.size() >= SRV_LOOKAHEAD) {
+        int rc = retire(m, srv->completed, true);
+        if (rc) return rc;
+    }
+    Program prog;
+    program_level(m.ctx, prog, jobs, m.scratch, SRV_KS_CHUNK, SRV_MUL_CHUNK);
+    int rc = program_run_now(m.ctx, prog, m.stream);
+    if (rc) return rc;
+    m.launched_jobs += jobs.count();
+    hipEvent_t ev;
+    if (m.free_events.empty()) LOLA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    else { ev = m.free_events.back(); m.free_events.pop_back(); }
+    LOLA_HIP(hipEventRecord(ev, m.stream));
+    ++m.round;
+    m.inflight.emplace_back(m.round, ev);
+    for (Slot *s : finishing) {
+        s->finished = true;
+        s->finish_round = m.round;
+    }
+    return LOLA_OK;
+}
+
+}  // namespace
+}  // namespace lola
+
+using namespace lola;
+
+extern "C" {
+
+int lola_server_create(size_t hbm_budget_bytes, lola_server **out) {
+    if (!out) return set_error(LOLA_E_INVAL, "null argument");
+    *out = new lola_server();
+    (*out)->budget = hbm_budget_bytes;
+    return LOLA_OK;
+}
+
+void lola_server_destroy(lola_server *srv) {
+    if (!srv) return;
+    for (Model &m : srv->models) {
+        if (m.stream) (void)hipStreamSynchronize(m.stream);
+        for (auto &f : m.inflight) (void)hipEventDestroy(f.second);
+        for (hipEvent_t e : m.free_events) (void)hipEventDestroy(e);
+        if (m.ws) (void)hipFree(m.ws);
+        if (m.stream) (void)hipStreamDestroy(m.stream);
+    }
+    delete srv;
+}
+
+int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint32_t max_inflight, uint32_t *model_id) {
+    if (!srv || !ctx || !plan || !model_id || max_inflight == 0) return set_error(LOLA_E_INVAL, "null argument");
+    if (plan->loaded_for != ctx) return set_error(LOLA_E_INVAL, "plan not loaded on this context");
+    const size_t N = ctx->N, L = ctx->L, CT = 2 * L * N, CT3 = 3 * L * N;
+    const uint32_t nsq = std::max<uint32_t>(plan->max_squares_per_wave, 1);
+    const size_t slot_words = plan->n_phys * CT + nsq * CT3;
+    const size_t scratch_words = level_scratch_words(ctx, SRV_KS_CHUNK, SRV_MUL_CHUNK);
+    const size_t avail = srv->budget > srv->used ? srv->budget - srv->used : 0;
+    if (avail < (scratch_words + slot_words) * 4)
+        return set_error(LOLA_E_NOMEM, "HBM budget too small for one request of this model");
+    const uint32_t fit = (uint32_t)std::min<size_t>(max_inflight, (avail / 4 - scratch_words) / slot_words);
+    Model m;
+    m.ctx = ctx;
+    m.plan = plan;
+    m.footprint_bytes = slot_words * 4;
+    const size_t words = fit * slot_words + scratch_words;
+    if (hipMalloc(&m.ws, words * 4) != hipSuccess) return set_error(LOLA_E_NOMEM, "server workspace allocation failed");
+    LOLA_HIP(hipStreamCreateWithFlags(&m.stream, hipStreamNonBlocking));
+    m.slots.resize(fit);
+    for (uint32_t k = 0; k < fit; ++k) {
+        m.slots[k].regs = m.ws + k * slot_words;
+        m.slots[k].sq = m.slots[k].regs + plan->n_phys * CT;
+    }
+    m.scratch = m.ws + fit * slot_words;
+    srv->used += words * 4;
+    srv->models.push_back(std::move(m));
+    *model_id = (uint32_t)srv->models.size() - 1;
+    return LOLA_OK;
+}
+
+int lola_server_model_info(const lola_server *srv, uint32_t model_id, uint32_t *slots, uint64_t *footprint_bytes,
+                           uint64_t *scratch_bytes, uint64_t *launched_jobs) {
+    if (!srv || model_id >= srv->models.size()) return set_error(LOLA_E_INVAL, "bad model id");
+    const Model &m = srv->models[model_id];
+    if (slots) *slots = (uint32_t)m.slots.size();
+    if (footprint_bytes) *footprint_bytes = m.footprint_bytes;
+    if (scratch_bytes) *scratch_bytes = level_scratch_words(m.ctx, SRV_KS_CHUNK, SRV_MUL_CHUNK) * 4;
+    if (launched_jobs) *launched_jobs = m.launched_jobs;
+    return LOLA_OK;
+}
+
+int lola_server_submit(lola_server *srv, uint32_t model_id, const lola_request *req, uint64_t tag) {
+    if (!srv || !req || model_id >= srv->models.size()) return set_error(LOLA_E_INVAL, "bad argument");
+    Model &m = srv->models[model_id];
+    int rc = validate_request(m.plan, *req);
+    if (rc) return rc;
+    Pending pd;
+    pd.tag = tag;
+    pd.rlk = req->rlk_dev;
+    pd.gk.assign(req->gk_dev, req->gk_dev + m.plan->galois.size());
+    pd.in.assign(req->in_dev, req->in_dev + m.plan->n_inputs);
+    pd.out.assign(req->out_dev, req->out_dev + m.plan->outputs.size());
+    m.queue.push_back(std::move(pd));
+    return LOLA_OK;
+}
+
+int lola_server_step(lola_server *srv, uint32_t *pending) {
+    if (!srv) return set_error(LOLA_E_INVAL, "null argument");
+    for (Model &m : srv->models) {
+        int rc = retire(m, srv->completed, false);
+        if (rc) return rc;
+        if ((rc = round_model(srv, m))) return rc;
+    }
+    ++srv->rounds;
+    uint32_t n = 0;
+    for (Model &m : srv->models) {
+        n += (uint32_t)m.queue.size();
+        for (const Slot &s : m.slots) n += s.busy ? 1u : 0u;
+    }
+    if (pending) *pending = n;
+    return LOLA_OK;
+}
+
+int lola_server_poll(lola_server *srv, uint64_t *tags, uint32_t cap, uint32_t *n) {
+    if (!srv || !n || (!tags && cap)) return set_error(LOLA_E_INVAL, "null argument");
+    for (Model &m : srv->models) {
+        int rc = retire(m, srv->completed, false);
+        if (rc) return rc;
+    }
+    const uint32_t k = (uint32_t)std::min<size_t>(cap, srv->completed.size());
+    std::copy(srv->completed.begin(), srv->completed.begin() + k, tags);
+    srv->completed.erase(srv->completed.begin(), srv->completed.begin() + k);
+    *n = k;
+    return LOLA_OK;
+}
+
+}  // extern "C"
