@@ -55,6 +55,7 @@ def main():
     ap.add_argument("--clients", type=int, default=8, help="distinct key sets")
     ap.add_argument("--latency-runs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cfg2", action="store_true", help="skip the batched-primitive run")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="mixed Poisson serving run after the timed steps (0 = skip)")
     args = ap.parse_args()
@@ -190,6 +191,13 @@ def main():
                 "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job"},
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
+    if not args.no_cfg2:
+        # batched primitives: 512 ciphertexts, N=16384, L=8, uneven rotation chains
+        from paper_1812_10659_amd import batched
+        b2 = batched.run_cfg2()
+        b2.pop("_tensors")
+        out["batched_cfg2"] = b2
+        torch.cuda.empty_cache()
     if args.serve_requests > 0:
         # Poisson arrivals at 200/s: 70% N=16384 MNIST-shaped, 30% N=4096 dense-64,
         # 8 resident key sets per ring size, continuous batching vs one at a time

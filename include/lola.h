@@ -180,6 +180,31 @@ typedef struct {
 int lola_keyswitch_batch(lola_ctx *ctx, const lola_ks_desc *descs_host, uint32_t n,
                          lola_stream stream);
 
+/* Batched forms (host arrays of n device pointers; one launch set):
+ * out[k] = ct[k] * pt_mul[k] (mul form), and exact products out3[k] =
+ * a[k] x b[k] (outputs may not alias inputs). */
+int lola_mul_plain_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *ct, const uint32_t *const *pt_mul,
+                         uint32_t *const *out, lola_stream stream);
+int lola_mul_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *a, const uint32_t *const *b,
+                   uint32_t *const *out3, lola_stream stream);
+
+/* Chains of rotations with uneven lengths in one persistent launch: chain k
+ * applies its n_steps rotations in order, x <- rotate(x, galois[r]) with
+ * keys[r], starting from in_dev and leaving the result in out_dev (tmp_dev is
+ * a ping-pong buffer; all three distinct, [2][L][N] each).  n_wg workgroups
+ * (0 = 256) each take the next chain from a work counter, longest chains
+ * first, and run its rotations as complete key switches; they exit when the
+ * counter passes n.  galois and keys are host arrays of n_steps entries. */
+typedef struct {
+    const uint32_t *in_dev;
+    uint32_t *out_dev;
+    uint32_t *tmp_dev;
+    uint32_t n_steps;
+    const uint32_t *galois;          /* host [n_steps] */
+    const uint32_t *const *keys;     /* host [n_steps] device pointers */
+} lola_chain;
+int lola_rotate_chains(lola_ctx *ctx, const lola_chain *chains, uint32_t n, uint32_t n_wg, lola_stream stream);
+
 /* ------------------------------------------------------ canonical forms */
 /* Device form <-> coefficient form for n_polys polynomials [n][L][N]. */
 int lola_to_coeff(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n_polys, uint32_t *out_dev,

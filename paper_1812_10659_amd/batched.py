@@ -1,0 +1,213 @@
+"""Batched primitive microbenchmark (512 ciphertexts, N=16384, L=8).
+
+Per ciphertext: forward + inverse NTT of both components, a plaintext
+product, then pairs (2i, 2i+1) multiply and relinearise, and every ciphertext
+runs its own chain of 1..64 rotations (seeded, uneven) over the power-of-two
+steps and the row swap -- the chains in one persistent work-queue launch.
+The chains are also run wave by wave (batched key switches) for comparison,
+and the persistent launch's workgroup count is picked by a small autotuner
+whose choice is cached per (N, L) in a JSON file.
+
+Reported per primitive: time, ops/s and HBM GB/s on algorithmic bytes.
+Argument marshalling and timing only; every step runs in the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import lola
+from . import workloads as wl
+
+AUTOTUNE_DIR = os.environ.get("LOLA_AUTOTUNE_DIR", os.path.join(os.path.expanduser("~"), ".cache", "lola"))
+
+
+class Chain(ctypes.Structure):
+    _fields_ = [("in_dev", ctypes.c_void_p), ("out_dev", ctypes.c_void_p), ("tmp_dev", ctypes.c_void_p),
+                ("n_steps", ctypes.c_uint32), ("galois", ctypes.POINTER(ctypes.c_uint32)),
+                ("keys", ctypes.POINTER(ctypes.c_void_p))]
+
+
+def _sig():
+    L = lola._plan_sig()
+    if getattr(L, "_batch_sig", False):
+        return L
+    vp, u32 = ctypes.c_void_p, ctypes.c_uint32
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    for n, a in {"lola_rotate_chains": [vp, ctypes.POINTER(Chain), u32, u32, vp],
+                 "lola_mul_plain_batch": [vp, u32, pp, pp, pp, vp],
+                 "lola_mul_batch": [vp, u32, pp, pp, pp, vp]}.items():
+        f = getattr(L, n)
+        f.argtypes = a
+        f.restype = ctypes.c_int32
+    L._batch_sig = True
+    return L
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def rotate_chains(ctx, ins, outs, tmps, steps, keys_by_galois, n_wg=0):
+    """steps[k]: Galois elements of chain k."""
+    n = len(ins)
+    arr = (Chain * n)()
+    keep = []
+    for k in range(n):
+        g = (ctypes.c_uint32 * max(len(steps[k]), 1))(*steps[k])
+        kp = (ctypes.c_void_p * max(len(steps[k]), 1))(*[keys_by_galois[x].data_ptr() for x in steps[k]])
+        keep += [g, kp]
+        arr[k] = Chain(ins[k].data_ptr(), outs[k].data_ptr(), tmps[k].data_ptr(), len(steps[k]), g,
+                       ctypes.cast(kp, ctypes.POINTER(ctypes.c_void_p)))
+    lola._check(_sig().lola_rotate_chains(ctx.h, arr, n, n_wg, lola._stream()))
+
+
+def mul_plain_batch(ctx, cts, pts, outs):
+    lola._check(_sig().lola_mul_plain_batch(ctx.h, len(cts), _ptrs(cts), _ptrs(pts), _ptrs(outs), lola._stream()))
+
+
+def mul_batch(ctx, a, b, outs3):
+    lola._check(_sig().lola_mul_batch(ctx.h, len(a), _ptrs(a), _ptrs(b), _ptrs(outs3), lola._stream()))
+
+
+def chains_wavewise(ctx, ins, outs, tmps, steps, keys_by_galois):
+    """The same chains as rounds of batched key switches (round r rotates every
+    chain that still has a step r)."""
+    n = len(ins)
+    cur = list(ins)
+    longest = max(len(s) for s in steps)
+    for r in range(longest):
+        items, dsts = [], []
+        for k in range(n):
+            if r < len(steps[k]):
+                dst = outs[k] if (len(steps[k]) - 1 - r) % 2 == 0 else tmps[k]
+                items.append((cur[k], keys_by_galois[steps[k][r]], steps[k][r]))
+                dsts.append((k, dst))
+        res = batch_keyswitch_into(ctx, items, [d for _, d in dsts])
+        for (k, d) in dsts:
+            cur[k] = d
+    return res
+
+
+def batch_keyswitch_into(ctx, items, outs):
+    arr = (lola.KsDesc * len(items))()
+    for k, ((ct, key, g), o) in enumerate(zip(items, outs)):
+        arr[k] = lola.KsDesc(ct.data_ptr(), key.data_ptr(), o.data_ptr(), g, 0)
+    lola._check(lola.lib().lola_keyswitch_batch(ctx.h, arr, len(items), lola._stream()))
+    return outs
+
+
+def _timed(fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def autotune_chain_wg(ctx, ins, outs, tmps, steps, keys, N, L, candidates=(128, 256, 384, 512)):
+    """Workgroup count of the persistent launch: measured, cached per (N, L)."""
+    path = os.path.join(AUTOTUNE_DIR, f"autotune_N{N}_L{L}.json")
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+        if "chain_wg" in cache:
+            return cache["chain_wg"], cache
+    except (OSError, ValueError):
+        cache = {}
+    sub = list(range(0, len(ins), 2))      # half of the chains: more than any candidate count
+    trial = {}
+    for wg in candidates:
+        trial[wg] = _timed(lambda: rotate_chains(ctx, [ins[k] for k in sub], [outs[k] for k in sub],
+                                                 [tmps[k] for k in sub], [steps[k] for k in sub], keys, wg), reps=1)
+    best = min(trial, key=trial.get)
+    cache.update({"chain_wg": best, "chain_wg_trials_s": {str(k): round(v, 5) for k, v in trial.items()}})
+    try:
+        os.makedirs(AUTOTUNE_DIR, exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f)
+    except OSError:
+        pass
+    return best, cache
+
+
+def run_cfg2(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tune: bool = True) -> dict:
+    p = wl.PARAMS["cfg2"]
+    N, L = p.N, p.L
+    ctx = lola.Context(p)
+    seed = wl.cfg_seed(2)
+    sk = ctx.keygen_secret(seed)
+    rlk = ctx.keygen_switch(seed, sk, 0)
+    choices = [1 << j for j in range(int(np.log2(N // 2)))] + ["row_swap"]
+    gals = sorted({lola.galois_element(N, c) for c in choices})
+    keys = {g: ctx.keygen_switch(seed, sk, g) for g in gals}
+    res = wl.cfg2_residues(n_ct, p.q, N, seed, 11)
+    cts = [lola.from_numpy_u32(np.stack([res[k], res[(k + 1) % n_ct]]), ctx.device) for k in range(n_ct)]
+    slots = wl.rng(seed, 12).integers(0, p.t, size=(n_ct, N))
+    pts = [ctx.plain_mul_form(ctx.encode(s)) for s in slots]
+    counts = wl.cfg2_rotation_counts(n_ct)
+    if max_steps is not None:
+        counts = np.minimum(counts, max_steps)
+    raw_steps = wl.cfg2_rotation_steps(counts, N)
+    steps = [[lola.galois_element(N, "row_swap" if s == 0 else int(s)) for s in row] for row in raw_steps]
+    torch.cuda.synchronize()
+    out = {"n_ct": n_ct, "N": N, "L": L, "rotations": int(counts.sum())}
+    # 1. forward + inverse NTT of every limb of both components
+    limbs = torch.stack(cts).reshape(-1, N)
+    idx = [i % L for i in range(limbs.shape[0])]
+    fwd = [None]
+
+    def ntt_pair():
+        fwd[0] = ctx.ntt_limbs(limbs, idx)
+        return ctx.ntt_limbs(fwd[0], idx, inverse=True)
+    s = _timed(ntt_pair)
+    back = ntt_pair()
+    torch.cuda.synchronize()
+    nl = 2 * limbs.shape[0]
+    out["ntt"] = {"limb_transforms": nl, "ms": round(s * 1e3, 3), "gbps": round(nl * 8 * N / s / 1e9, 1),
+                  "roundtrip_exact": bool(torch.equal(back, limbs))}
+    # 2. plaintext products
+    prod = [ctx.empty_ct() for _ in range(n_ct)]
+    s = _timed(lambda: mul_plain_batch(ctx, cts, pts, prod))
+    out["mul_plain"] = {"ms": round(s * 1e3, 3), "gbps": round(n_ct * 20 * L * N / s / 1e9, 1)}
+    # 3. products of pairs + relinearisation
+    a, b = cts[0::2], cts[1::2]
+    t3 = [ctx.empty_ct(3) for _ in a]
+    rl = [ctx.empty_ct() for _ in a]
+    s_mul = _timed(lambda: mul_batch(ctx, a, b, t3))
+    s_rel = _timed(lambda: batch_keyswitch_into(ctx, [(x, rlk, 0) for x in t3], rl))
+    out["mul_relin"] = {"pairs": len(a), "mul_ms": round(s_mul * 1e3, 3), "relin_ms": round(s_rel * 1e3, 3),
+                        "pairs_per_s": round(len(a) / (s_mul + s_rel), 1)}
+    # 4. rotation chains: persistent work queue vs wave-by-wave batches
+    outs = [ctx.empty_ct() for _ in range(n_ct)]
+    tmps = [ctx.empty_ct() for _ in range(n_ct)]
+    wg, cache = (autotune_chain_wg(ctx, cts, outs, tmps, steps, keys, N, L) if tune else (256, {}))
+    s_p = _timed(lambda: rotate_chains(ctx, cts, outs, tmps, steps, keys, wg), reps=1)
+    pers = [o.clone() for o in outs]
+    s_w = _timed(lambda: chains_wavewise(ctx, cts, outs, tmps, steps, keys), reps=1)
+    same = all(torch.equal(x, y) for x, y in zip(pers, outs))
+    rot = int(counts.sum())
+    ks_bytes = 4 * N * (4 * L + 2 * L * (L + 1))
+    out["rotations_persistent"] = {"ms": round(s_p * 1e3, 2), "rot_per_s": round(rot / s_p, 1),
+                                   "gbps": round(rot * ks_bytes / s_p / 1e9, 1), "workgroups": wg,
+                                   "autotune": cache.get("chain_wg_trials_s")}
+    out["rotations_wavewise"] = {"ms": round(s_w * 1e3, 2), "rot_per_s": round(rot / s_w, 1),
+                                 "rounds": int(counts.max()), "equal_to_persistent": same}
+    out["_tensors"] = dict(ctx=ctx, cts=cts, pts=pts, prod=prod, t3=t3, rl=rl, outs=pers, steps=raw_steps,
+                           rlk=rlk, keys=keys, sk=sk, slots=slots, seed=seed)
+    return out
+
+
+if __name__ == "__main__":
+    r = run_cfg2()
+    r.pop("_tensors")
+    print(json.dumps(r), flush=True)

@@ -144,3 +144,32 @@ int lola_kernel_timing(lola_ctx *ctx, double *total_ms, uint64_t *launches, uint
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int lola_mul_plain_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *ct, const uint32_t *const *pt,
+                         uint32_t *const *out, lola_stream stream) {
+    if (!ctx || (n && (!ct || !pt || !out))) return set_error(LOLA_E_INVAL, "null argument");
+    const uint32_t chunk = (uint32_t)(lola_ctx::RING_SLAB / sizeof(PlainJob) / 2);
+    for (uint32_t off = 0; off < n; off += chunk) {
+        const uint32_t m = std::min(chunk, n - off);
+        Program p;
+        std::vector<PlainJob> jobs(m);
+        for (uint32_t k = 0; k < m; ++k) {
+            if (!ct[off + k] || !pt[off + k] || !out[off + k]) return set_error(LOLA_E_INVAL, "null pointer in batch");
+            jobs[k] = PlainJob{ct[off + k], pt[off + k], nullptr, out[off + k]};
+        }
+        p.launch(LK_PLAIN, jobs);
+        int rc = program_run_now(ctx, p, (hipStream_t)stream);
+        if (rc) return rc;
+    }
+    return LOLA_OK;
+}
+
+int lola_mul_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *a, const uint32_t *const *b,
+                   uint32_t *const *out3, lola_stream stream) {
+    if (!ctx || (n && (!a || !b || !out3))) return set_error(LOLA_E_INVAL, "null argument");
+    return mul_batch(ctx, n, a, b, out3, (hipStream_t)stream);
+}
+
+}  // extern "C"
