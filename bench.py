@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--clients", type=int, default=8, help="distinct key sets")
     ap.add_argument("--latency-runs", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-cfg2", action="store_true", help="skip the batched-primitive run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-primitive run")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="mixed Poisson serving run after the timed steps (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -101,9 +101,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    p = wl.PARAMS["cfg1"]
+    p = wl.PARAMS["mnist_n16384"]
     N, L = p.N, p.L
-    w = wl.cfg1_weights()
+    w = wl.mnist_weights()
     ctx = lola.Context(p)
     plan = lola.Plan(p, networks.mnist_layers(w))
     plan.load(ctx)
@@ -119,7 +119,7 @@ def main():
     imap = plan.input_map()
     reqs, images = [], []
     for r in range(B):
-        img = wl.cfg1_image(index=r)
+        img = wl.mnist_image(index=r)
         images.append(img)
         k = keys[r % C]
         msgs = networks.pack_inputs(imap, networks.mnist_input_values(img))
@@ -208,7 +208,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32 (RNS residues mod 30-bit primes)",
         "data": "synthetic (seeded uniform 28x28 images, seeded int8 weights)",
-        "config": {"workload": "cfg1 MNIST-shaped: conv5x5s2x5 -> sq -> fc845x100 -> sq -> fc100x10, "
+        "config": {"workload": "MNIST-shaped: conv5x5s2x5 -> sq -> fc845x100 -> sq -> fc100x10, "
                                "BFV N=16384 L=7 t=1146881",
                    "batch_requests": B, "client_key_sets": C, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
@@ -225,12 +225,12 @@ def main():
                 "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job"},
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
-    if not args.no_cfg2:
+    if not args.no_batched:
         # batched primitives: 512 ciphertexts, N=16384, L=8, uneven rotation chains
         from paper_1812_10659_amd import batched
-        b2 = batched.run_cfg2()
+        b2 = batched.run_batched()
         b2.pop("_tensors")
-        out["batched_cfg2"] = b2
+        out["batched_primitives"] = b2
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         # Poisson arrivals at 200/s: 70% N=16384 MNIST-shaped, 30% N=4096 dense-64,
@@ -267,7 +267,7 @@ def cpu_baseline(p, w):
     octx = bfv.Context(p)
     sched = nw.mnist_schedule(w)
     keys = bfv.keygen(octx, wl.key_seed(1), nw.galois_elements(sched))
-    img = wl.cfg1_image(index=0)
+    img = wl.mnist_image(index=0)
     ins = nw.mnist_inputs(img)
     cts = [bfv.encrypt(octx, keys, bfv.encode(octx, nw.dense_slots(m, p.N, p.t)), 1, i) for i, m in enumerate(ins)]
     t0 = time.perf_counter()

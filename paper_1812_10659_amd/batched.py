@@ -140,24 +140,24 @@ def autotune_chain_wg(ctx, ins, outs, tmps, steps, keys, N, L, candidates=(128, 
     return best, cache
 
 
-def run_cfg2(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tune: bool = True) -> dict:
-    p = wl.PARAMS["cfg2"]
+def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tune: bool = True) -> dict:
+    p = wl.PARAMS["batch_n16384"]
     N, L = p.N, p.L
     ctx = lola.Context(p)
-    seed = wl.cfg_seed(2)
+    seed = wl.workload_seed(2)
     sk = ctx.keygen_secret(seed)
     rlk = ctx.keygen_switch(seed, sk, 0)
     choices = [1 << j for j in range(int(np.log2(N // 2)))] + ["row_swap"]
     gals = sorted({lola.galois_element(N, c) for c in choices})
     keys = {g: ctx.keygen_switch(seed, sk, g) for g in gals}
-    res = wl.cfg2_residues(n_ct, p.q, N, seed, 11)
+    res = wl.uniform_residues(n_ct, p.q, N, seed, 11)
     cts = [lola.from_numpy_u32(np.stack([res[k], res[(k + 1) % n_ct]]), ctx.device) for k in range(n_ct)]
     slots = wl.rng(seed, 12).integers(0, p.t, size=(n_ct, N))
     pts = [ctx.plain_mul_form(ctx.encode(s)) for s in slots]
-    counts = wl.cfg2_rotation_counts(n_ct)
+    counts = wl.batch_rotation_counts(n_ct)
     if max_steps is not None:
         counts = np.minimum(counts, max_steps)
-    raw_steps = wl.cfg2_rotation_steps(counts, N)
+    raw_steps = wl.batch_rotation_steps(counts, N)
     steps = [[lola.galois_element(N, "row_swap" if s == 0 else int(s)) for s in row] for row in raw_steps]
     torch.cuda.synchronize()
     out = {"n_ct": n_ct, "N": N, "L": L, "rotations": int(counts.sum())}
@@ -208,6 +208,6 @@ def run_cfg2(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tun
 
 
 if __name__ == "__main__":
-    r = run_cfg2()
+    r = run_batched()
     r.pop("_tensors")
     print(json.dumps(r), flush=True)

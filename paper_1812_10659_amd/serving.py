@@ -110,12 +110,12 @@ class ModelSetup:
     def __init__(self, kind: str, clients: int, inputs_per_client: int, out_pool: int):
         self.kind = kind
         if kind == "mnist":
-            self.p = wl.PARAMS["cfg1"]
-            self.w = wl.cfg1_weights()
+            self.p = wl.PARAMS["mnist_n16384"]
+            self.w = wl.mnist_weights()
             layers = networks.mnist_layers(self.w)
         else:
-            self.p = wl.PARAMS["cfg0"]
-            _, self.W = wl.cfg0_inputs()
+            self.p = wl.PARAMS["n4096_3q"]
+            _, self.W = wl.dense64_inputs()
             layers = networks.dense64_layers(self.W)
         self.ctx = lola.Context(self.p)
         self.plan = lola.Plan(self.p, layers)
@@ -123,7 +123,7 @@ class ModelSetup:
         gal = self.plan.galois()
         imap = self.plan.input_map()
         self.keys, self.inputs, self.values = [], [], []
-        base = wl.cfg_seed(4) * 31 + (1 if kind == "mnist" else 2)
+        base = wl.workload_seed(4) * 31 + (1 if kind == "mnist" else 2)
         for c in range(clients):
             ks = base + 1009 * c
             sk = self.ctx.keygen_secret(ks)
@@ -154,8 +154,8 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
                 max_inflight: int = 64, hbm_budget_gb: float = 96.0, check_every: int = 50,
                 baseline: bool = True, seed: int | None = None) -> dict:
     assert torch.cuda.is_available()
-    arrivals, kinds = wl.cfg4_arrivals(n_req, rate, p_large, seed)
-    g = wl.rng(wl.cfg_seed(4) if seed is None else seed, 9)
+    arrivals, kinds = wl.serving_arrivals(n_req, rate, p_large, seed)
+    g = wl.rng(wl.workload_seed(4) if seed is None else seed, 9)
     client_of = g.integers(0, clients, size=n_req)
     input_of = g.integers(0, 2, size=n_req)
     models = {"mnist": ModelSetup("mnist", clients, 2, max_inflight + 16),

@@ -45,17 +45,16 @@ class ParamSet:
 PARAMS: Dict[str, ParamSet] = {
     # N=4096, t=65537 with two 30-bit primes (q ~ 2^60) as first specified.
     # The oracle's noise check shows the square activation does not fit in it.
-    "cfg0_literal": ParamSet("cfg0_literal", 4096, 65537, tuple(PRIMES_4096[:2]),
-                             PRIMES_4096[2]),
+    "n4096_2q": ParamSet("n4096_2q", 4096, 65537, tuple(PRIMES_4096[:2]), PRIMES_4096[2]),
     # N=4096 working set: three 30-bit primes and a 19-bit special prime,
     # log2(QP) = 108.7 <= 109.
-    "cfg0": ParamSet("cfg0", 4096, 65537, tuple(PRIMES_4096[:3]), 417793),
+    "n4096_3q": ParamSet("n4096_3q", 4096, 65537, tuple(PRIMES_4096[:3]), 417793),
     # MNIST-shaped network, N=16384, t ~ 2^20.13, seven data primes.
-    "cfg1": ParamSet("cfg1", 16384, 1146881, tuple(PRIMES_16384[:7]), PRIMES_16384[7]),
+    "mnist_n16384": ParamSet("mnist_n16384", 16384, 1146881, tuple(PRIMES_16384[:7]), PRIMES_16384[7]),
     # Batched primitive microbenchmark: eight data primes.
-    "cfg2": ParamSet("cfg2", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
+    "batch_n16384": ParamSet("batch_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
     # Transfer-learning head: six data primes.
-    "cfg3": ParamSet("cfg3", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
+    "head_n16384": ParamSet("head_n16384", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
     # Small sets for tests (not secure; flagged).
     # (primes = 1 mod 2^15 are also = 1 mod 2N for these smaller N)
     "toy1024": ParamSet("toy1024", 1024, 12289, tuple(PRIMES_16384[:3]), PRIMES_16384[3],
@@ -67,8 +66,14 @@ PARAMS: Dict[str, ParamSet] = {
 MASTER_SEED = 1812106590
 
 
-def cfg_seed(k: int) -> int:
-    """Master seed of configuration k."""
+# Workload ids: 0 dense-64 query (N=4096), 1 MNIST-shaped network (N=16384),
+# 2 batched primitives (N=16384, eight primes), 3 transfer-learning head
+# (N=16384), 4 mixed serving stream.
+DENSE64, MNIST, BATCH, HEAD, SERVE = 0, 1, 2, 3, 4
+
+
+def workload_seed(k: int) -> int:
+    """Master seed of workload k."""
     return MASTER_SEED + k
 
 
@@ -77,28 +82,28 @@ def rng(seed: int, stream: int = 0) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64([seed, stream]))
 
 
-# Stream ids inside a configuration's seed.
+# Stream ids inside a workload's seed.
 STREAM_KEYS, STREAM_ENC, STREAM_DATA, STREAM_WEIGHTS, STREAM_ARRIVALS = 1, 2, 3, 4, 5
 
 
 def key_seed(k: int) -> int:
-    return int(rng(cfg_seed(k), STREAM_KEYS).integers(0, 2**63))
+    return int(rng(workload_seed(k), STREAM_KEYS).integers(0, 2**63))
 
 
 def enc_seed(k: int) -> int:
-    return int(rng(cfg_seed(k), STREAM_ENC).integers(0, 2**63))
+    return int(rng(workload_seed(k), STREAM_ENC).integers(0, 2**63))
 
 
-# ---------------------------------------------------------------- cfg0 ----
-def cfg0_inputs(seed: int | None = None):
+# -------------------------------------------------------------- dense-64 query, N=4096
+def dense64_inputs(seed: int | None = None):
     """64-vector x and 64x64 matrix W, both uniform int8."""
-    s = cfg_seed(0) if seed is None else seed
+    s = workload_seed(0) if seed is None else seed
     x = rng(s, STREAM_DATA).integers(-128, 128, size=64).astype(np.int64)
     W = rng(s, STREAM_WEIGHTS).integers(-128, 128, size=(64, 64)).astype(np.int64)
     return x, W
 
 
-# ---------------------------------------------------------------- cfg1 ----
+# -------------------------------------------------------------- MNIST-shaped network, N=16384
 @dataclasses.dataclass
 class MnistWeights:
     conv_w: np.ndarray   # [5 maps][5][5] int8 values
@@ -109,14 +114,14 @@ class MnistWeights:
     b2: np.ndarray       # [10]
 
 
-def cfg1_image(seed: int | None = None, index: int = 0) -> np.ndarray:
+def mnist_image(seed: int | None = None, index: int = 0) -> np.ndarray:
     """A 28x28 image with uniform values 0..255."""
-    s = cfg_seed(1) if seed is None else seed
+    s = workload_seed(1) if seed is None else seed
     return rng(s, STREAM_DATA * 1000 + index).integers(0, 256, size=(28, 28)).astype(np.int64)
 
 
-def cfg1_weights(seed: int | None = None) -> MnistWeights:
-    s = cfg_seed(1) if seed is None else seed
+def mnist_weights(seed: int | None = None) -> MnistWeights:
+    s = workload_seed(1) if seed is None else seed
     g = rng(s, STREAM_WEIGHTS)
     conv_w = g.integers(-128, 128, size=(5, 5, 5)).astype(np.int64)
     conv_b = g.integers(-2**15, 2**15, size=5).astype(np.int64)
@@ -127,24 +132,24 @@ def cfg1_weights(seed: int | None = None) -> MnistWeights:
     return MnistWeights(conv_w, conv_b, w1, b1, w2, b2)
 
 
-# ---------------------------------------------------------------- cfg2 ----
-def cfg2_rotation_counts(n_ct: int = 512, seed: int | None = None) -> np.ndarray:
+# -------------------------------------------------------------- batched primitives, N=16384
+def batch_rotation_counts(n_ct: int = 512, seed: int | None = None) -> np.ndarray:
     """Per-ciphertext rotation counts, uniform in 1..64 (uneven on purpose)."""
-    s = cfg_seed(2) if seed is None else seed
+    s = workload_seed(2) if seed is None else seed
     return rng(s, STREAM_DATA * 10 + 1).integers(1, 65, size=n_ct).astype(np.int64)
 
 
-def cfg2_rotation_steps(counts: np.ndarray, N: int = 16384, seed: int | None = None) -> List[np.ndarray]:
+def batch_rotation_steps(counts: np.ndarray, N: int = 16384, seed: int | None = None) -> List[np.ndarray]:
     """Rotation steps per ciphertext, uniform over {+2^j : 2^j < N/2} plus the
     row swap (encoded as 0)."""
-    s = cfg_seed(2) if seed is None else seed
+    s = workload_seed(2) if seed is None else seed
     g = rng(s, STREAM_DATA * 10 + 2)
     choices = [1 << j for j in range(int(np.log2(N // 2)))] + [0]
     return [np.array([choices[i] for i in g.integers(0, len(choices), size=int(c))], dtype=np.int64)
             for c in counts]
 
 
-def cfg2_residues(n_polys: int, moduli, N: int, seed: int, stream: int) -> np.ndarray:
+def uniform_residues(n_polys: int, moduli, N: int, seed: int, stream: int) -> np.ndarray:
     """Uniform residues, shape [n_polys][len(moduli)][N], each limb mod its prime."""
     g = rng(seed, stream)
     out = np.empty((n_polys, len(moduli), N), dtype=np.uint32)
@@ -153,7 +158,7 @@ def cfg2_residues(n_polys: int, moduli, N: int, seed: int, stream: int) -> np.nd
     return out
 
 
-# ---------------------------------------------------------------- cfg3 ----
+# -------------------------------------------------------------- transfer-learning head, N=16384
 @dataclasses.dataclass
 class HeadWeights:
     w1: np.ndarray   # [256][4096] int8
@@ -162,15 +167,15 @@ class HeadWeights:
     b2: np.ndarray   # [10]
 
 
-def cfg3_features(n_queries: int = 16, seed: int | None = None) -> np.ndarray:
+def head_features(n_queries: int = 16, seed: int | None = None) -> np.ndarray:
     """Feature vectors: clip(round(N(0, 20^2)), -128, 127), dimension 4096."""
-    s = cfg_seed(3) if seed is None else seed
+    s = workload_seed(3) if seed is None else seed
     f = rng(s, STREAM_DATA).normal(0.0, 20.0, size=(n_queries, 4096))
     return np.clip(np.rint(f), -128, 127).astype(np.int64)
 
 
-def cfg3_weights(seed: int | None = None) -> HeadWeights:
-    s = cfg_seed(3) if seed is None else seed
+def head_weights(seed: int | None = None) -> HeadWeights:
+    s = workload_seed(3) if seed is None else seed
     g = rng(s, STREAM_WEIGHTS)
     w1 = g.integers(-128, 128, size=(256, 4096)).astype(np.int64)
     b1 = g.integers(-2**15, 2**15, size=256).astype(np.int64)
@@ -179,12 +184,12 @@ def cfg3_weights(seed: int | None = None) -> HeadWeights:
     return HeadWeights(w1, b1, w2, b2)
 
 
-# ---------------------------------------------------------------- cfg4 ----
-def cfg4_arrivals(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7,
+# -------------------------------------------------------------- serving mix
+def serving_arrivals(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7,
                   seed: int | None = None):
     """Poisson arrival times (s) and request kinds (1 = N=16384 MNIST-shaped,
     0 = N=4096 dense-64 query)."""
-    s = cfg_seed(4) if seed is None else seed
+    s = workload_seed(4) if seed is None else seed
     g = rng(s, STREAM_ARRIVALS)
     gaps = g.exponential(1.0 / rate, size=n_req)
     kinds = (g.random(n_req) < p_large).astype(np.int64)

@@ -103,8 +103,8 @@ def lola_pack(plan, values):
 def test_compiler_dense64_stacked():
     lola = _lola()
     from paper_1812_10659_amd import networks
-    x, W = wl.cfg0_inputs()
-    p = wl.PARAMS["cfg0"]
+    x, W = wl.dense64_inputs()
+    p = wl.PARAMS["n4096_3q"]
     plan = _check_plan(lola, p, networks.dense64_layers(W), x, nw.dense64_plain(x, W), nw.dense64_schedule(W))
     assert plan.info["n_rotations"] == 6 and plan.info["n_square"] == 1
 
@@ -112,8 +112,8 @@ def test_compiler_dense64_stacked():
 def test_compiler_mnist_matches_tables_and_network():
     lola = _lola()
     from paper_1812_10659_amd import networks
-    w, img = wl.cfg1_weights(), wl.cfg1_image()
-    p = wl.PARAMS["cfg1"]
+    w, img = wl.mnist_weights(), wl.mnist_image()
+    p = wl.PARAMS["mnist_n16384"]
     plan = _check_plan(lola, p, networks.mnist_layers(w), networks.mnist_input_values(img),
                        nw.mnist_plain(img, w), nw.mnist_schedule(w))
     info = plan.info
@@ -129,8 +129,8 @@ def test_compiler_mnist_matches_tables_and_network():
 def test_compiler_head(n_hidden):
     lola = _lola()
     from paper_1812_10659_amd import networks
-    w, f = wl.cfg3_weights(), wl.cfg3_features(4)
-    p = wl.PARAMS["cfg3"]
+    w, f = wl.head_weights(), wl.head_features(4)
+    p = wl.PARAMS["head_n16384"]
     layers = networks.head_layers(w, n_hidden)
     wt = wl.HeadWeights(w.w1[:n_hidden], w.b1[:n_hidden], w.w2[:, :n_hidden], w.b2)
     expected = np.concatenate([nw.head_plain(f[q], wt) for q in range(4)])
@@ -140,7 +140,7 @@ def test_compiler_head(n_hidden):
 
 def test_compiler_rejects_unsupported():
     lola = _lola()
-    p = wl.PARAMS["cfg1"]
+    p = wl.PARAMS["mnist_n16384"]
     with pytest.raises(lola.LolaError) as e:
         lola.Plan(p, [lola.square()])
     assert e.value.code == -8

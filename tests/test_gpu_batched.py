@@ -16,12 +16,12 @@ def test_batched_primitives_match_oracle():
     import torch
     from paper_1812_10659_amd import batched, lola
     print("[gpu-batched] 24 ciphertexts, chains of <= 4 rotations, L=8", flush=True)
-    r = batched.run_cfg2(n_ct=24, max_steps=4, tune=False)
+    r = batched.run_batched(n_ct=24, max_steps=4, tune=False)
     T = r.pop("_tensors")
     ctx = T["ctx"]
     assert r["ntt"]["roundtrip_exact"]
     assert r["rotations_wavewise"]["equal_to_persistent"]
-    p = wl.PARAMS["cfg2"]
+    p = wl.PARAMS["batch_n16384"]
     octx = bfv.Context(p)
     steps = T["steps"]
     need = sorted({bfv.galois_element(p.N, bfv.ROW_SWAP if s == 0 else int(s)) for row in steps[:4] for s in row})

@@ -64,29 +64,29 @@ def _run_and_compare(env, oracle_sched, expected):
 
 def test_dense64_network_matches_oracle():
     from paper_1812_10659_amd import networks
-    x, W = wl.cfg0_inputs()
-    print("[gpu-net] cfg0 dense64", flush=True)
+    x, W = wl.dense64_inputs()
+    print("[gpu-net] dense64", flush=True)
     sched = nw.dense64_schedule(W)
-    env = _setup("cfg0", networks.dense64_layers(W), sched, x, wl.key_seed(0), wl.enc_seed(0))
+    env = _setup("n4096_3q", networks.dense64_layers(W), sched, x, wl.key_seed(0), wl.enc_seed(0))
     _run_and_compare(env, sched, nw.dense64_plain(x, W))
 
 
 def test_mnist_network_matches_oracle():
     from paper_1812_10659_amd import networks
-    w, img = wl.cfg1_weights(), wl.cfg1_image()
-    print("[gpu-net] cfg1 mnist", flush=True)
+    w, img = wl.mnist_weights(), wl.mnist_image()
+    print("[gpu-net] mnist", flush=True)
     sched = nw.mnist_schedule(w)
-    env = _setup("cfg1", networks.mnist_layers(w), sched, networks.mnist_input_values(img),
+    env = _setup("mnist_n16384", networks.mnist_layers(w), sched, networks.mnist_input_values(img),
                  wl.key_seed(1), wl.enc_seed(1))
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
 
 
 def test_head_network_truncated_matches_oracle():
     from paper_1812_10659_amd import networks
-    w, f = wl.cfg3_weights(), wl.cfg3_features(4)
-    print("[gpu-net] cfg3 head, 8 hidden", flush=True)
+    w, f = wl.head_weights(), wl.head_features(4)
+    print("[gpu-net] head, 8 hidden", flush=True)
     sched = nw.head_schedule(w, n_hidden=8)
-    env = _setup("cfg3", networks.head_layers(w, 8), sched, f, wl.key_seed(3), wl.enc_seed(3))
+    env = _setup("head_n16384", networks.head_layers(w, 8), sched, f, wl.key_seed(3), wl.enc_seed(3))
     wt = wl.HeadWeights(w.w1[:8], w.b1[:8], w.w2[:, :8], w.b2)
     _run_and_compare(env, sched, np.concatenate([nw.head_plain(f[q], wt) for q in range(4)]))
 
@@ -97,9 +97,9 @@ def test_head_network_full_size_decrypts_to_network():
     result against the plaintext network (mod t)."""
     import torch
     from paper_1812_10659_amd import networks
-    w, f = wl.cfg3_weights(), wl.cfg3_features(4)
-    print("[gpu-net] cfg3 head, full", flush=True)
-    env = _setup("cfg3", networks.head_layers(w), None, f, wl.key_seed(3), wl.enc_seed(3), with_oracle=False)
+    w, f = wl.head_weights(), wl.head_features(4)
+    print("[gpu-net] head, full", flush=True)
+    env = _setup("head_n16384", networks.head_layers(w), None, f, wl.key_seed(3), wl.enc_seed(3), with_oracle=False)
     env["plan"].evaluate(env["ctx"], [env["req"]])
     torch.cuda.synchronize()
     expected = np.concatenate([nw.head_plain(f[q], w) for q in range(4)])
@@ -112,11 +112,11 @@ def test_batched_requests_equal_single_and_graph_replay():
     equal the eager result every time."""
     import torch
     from paper_1812_10659_amd import lola, networks
-    _, W = wl.cfg0_inputs()
+    _, W = wl.dense64_inputs()
     envs = []
     for k in range(3):
         x = wl.rng(1000 + k).integers(-128, 128, size=64)
-        envs.append(_setup("cfg0", networks.dense64_layers(W), None, x, 77 + k, 99 + k, with_oracle=False))
+        envs.append(_setup("n4096_3q", networks.dense64_layers(W), None, x, 77 + k, 99 + k, with_oracle=False))
     ctx, plan = envs[0]["ctx"], envs[0]["plan"]
     # re-home every request onto the first context (same parameters)
     reqs = []

@@ -8,7 +8,7 @@ from paper_1812_10659_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PSETS = ["toy1024", "cfg0", "cfg1"]
+PSETS = ["toy1024", "n4096_3q", "mnist_n16384"]
 STEPS = [1, -1, 7, bfv.ROW_SWAP]
 SEED = 0x5EED_0001
 

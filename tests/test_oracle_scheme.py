@@ -39,7 +39,7 @@ def test_slot_exponents_are_odd_residue_permutation():
         assert ctx_e == set(range(1, 2 * N, 2))
 
 
-@pytest.mark.parametrize("name", ["toy1024", "cfg0", "cfg1"])
+@pytest.mark.parametrize("name", ["toy1024", "n4096_3q", "mnist_n16384"])
 def test_encode_decode_roundtrip_and_homomorphism(name):
     ctx = bfv.Context(wl.PARAMS[name])
     rs = np.random.default_rng(1)
@@ -63,7 +63,7 @@ def test_zeta_is_smallest_primitive_root():
 
 
 # ---------------------------------------------------------- P3 rotations ----
-@pytest.mark.parametrize("name", ["toy1024", "cfg1"])
+@pytest.mark.parametrize("name", ["toy1024", "mnist_n16384"])
 def test_automorphism_rotates_slots(name):
     ctx = bfv.Context(wl.PARAMS[name])
     N = ctx.N
@@ -149,13 +149,13 @@ def bf_is_prime(n):
     return bfv._is_prime(n) and all(n % d for d in range(2, 1000) if d * d <= n and d < n)
 
 
-def test_literal_cfg0_fails_noise_check():
+def test_literal_two_prime_n4096_fails_noise_check():
     """With q ~ 2^60 the square activation exhausts the noise budget: the
     budget drops to ~0 and decryption no longer matches (the failure the
     working N=4096 set with three primes avoids)."""
-    x, W = wl.cfg0_inputs()
+    x, W = wl.dense64_inputs()
     out = {}
-    for name in ("cfg0_literal", "cfg0"):
+    for name in ("n4096_2q", "n4096_3q"):
         ctx = bfv.Context(wl.PARAMS[name])
         sc = nw.dense64_schedule(W)
         keys = bfv.keygen(ctx, wl.key_seed(0), nw.galois_elements(sc))
@@ -165,8 +165,8 @@ def test_literal_cfg0_fails_noise_check():
         dec = bfv.decode(ctx, bfv.decrypt(ctx, keys, res[0]))
         exp = nw._mod(nw.dense64_plain(x, W), ctx.t)
         out[name] = (bfv.noise_budget(ctx, keys, res[0]), all(dec[64 * j] == exp[j] for j in range(64)))
-    assert out["cfg0_literal"][0] < 1.0 and not out["cfg0_literal"][1]
-    assert out["cfg0"][0] > 1.0 and out["cfg0"][1]
+    assert out["n4096_2q"][0] < 1.0 and not out["n4096_2q"][1]
+    assert out["n4096_3q"][0] > 1.0 and out["n4096_3q"][1]
 
 
 # ------------------------------------------------- P7 paper examples ----
@@ -233,8 +233,8 @@ def test_footnote_convolution_representation():
 
 # --------------------------------------------------------- P8 tables ----
 def test_mnist_schedule_matches_table_shapes():
-    wts = wl.cfg1_weights()
-    img = wl.cfg1_image()
+    wts = wl.mnist_weights()
+    img = wl.mnist_image()
     sc = nw.mnist_schedule(wts)
     tab = {ln[0]: ln[1] for ln in _golden_lines("paper_tables_mnist.txt")}
     n_in, dim = map(int, tab["conv_input"].split("x"))
@@ -267,23 +267,23 @@ def test_mnist_schedule_matches_table_shapes():
 
 # ---------------------------------------------------- P9 end to end ----
 def test_slot_schedules_equal_plain_networks():
-    x, W = wl.cfg0_inputs()
+    x, W = wl.dense64_inputs()
     outs, _ = nw.run_slots(nw.dense64_schedule(W), nw.dense64_inputs(x, 4096), 65537)
     exp = nw._mod(nw.dense64_plain(x, W), 65537)
     assert all(outs[0][64 * j] == exp[j] for j in range(64))
-    wts, img = wl.cfg1_weights(), wl.cfg1_image()
+    wts, img = wl.mnist_weights(), wl.mnist_image()
     outs, _ = nw.run_slots(nw.mnist_schedule(wts), nw.mnist_inputs(img), 1146881)
     assert [int(o[0]) for o in outs] == list(nw._mod(nw.mnist_plain(img, wts), 1146881))
-    hw, f = wl.cfg3_weights(), wl.cfg3_features(4)
+    hw, f = wl.head_weights(), wl.head_features(4)
     outs, _ = nw.run_slots(nw.head_schedule(hw), nw.head_inputs(f), 1146881)
     for q in range(4):
         exp = nw._mod(nw.head_plain(f[q], hw), 1146881)
         assert [int(outs[o][4096 * q]) for o in range(10)] == list(exp)
 
 
-def test_cfg0_ciphertext_schedule_end_to_end():
-    ctx = bfv.Context(wl.PARAMS["cfg0"])
-    x, W = wl.cfg0_inputs()
+def test_dense64_ciphertext_schedule_end_to_end():
+    ctx = bfv.Context(wl.PARAMS["n4096_3q"])
+    x, W = wl.dense64_inputs()
     sc = nw.dense64_schedule(W)
     keys = bfv.keygen(ctx, wl.key_seed(0), nw.galois_elements(sc))
     inp = nw.dense_slots(nw.dense64_inputs(x, 4096)[0], 4096, ctx.t)
@@ -295,9 +295,9 @@ def test_cfg0_ciphertext_schedule_end_to_end():
 
 
 @pytest.mark.slow
-def test_cfg1_ciphertext_schedule_end_to_end():
-    ctx = bfv.Context(wl.PARAMS["cfg1"])
-    wts, img = wl.cfg1_weights(), wl.cfg1_image()
+def test_mnist_ciphertext_schedule_end_to_end():
+    ctx = bfv.Context(wl.PARAMS["mnist_n16384"])
+    wts, img = wl.mnist_weights(), wl.mnist_image()
     sc = nw.mnist_schedule(wts)
     keys = bfv.keygen(ctx, wl.key_seed(1), nw.galois_elements(sc))
     ins = nw.mnist_inputs(img)
