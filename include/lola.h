@@ -4,12 +4,12 @@
  *
  * The operations are the ones the paper (Brutzkus, Elisha, Gilad-Bachrach,
  * "Low Latency Privacy Preserving Inference") relies on:
- *   - Sec. 2.1 (Homomorphic Encryption): encryption E, decryption D, the
+ *   - Sec. 3.1 (Homomorphic Encryption): encryption E, decryption D, the
  *     homomorphic sum and product, the plaintext ring Z_p[x]/(x^n+1) viewed as
  *     n slots when p has a 2n-th root of unity, and the two rotations of the
  *     2 x n/2 slot matrix (row swap, column rotation);
- *   - Sec. 3.2.2 (Convolution vector - row major): message times scalar;
- *   - Sec. 3.2 (vector representations and matrix-vector recipes) and Sec. 4 /
+ *   - Sec. 4.2.2 (Convolution vector - row major): message times scalar;
+ *   - Sec. 4.2 (vector representations and matrix-vector recipes) and Sec. 4.3 /
  *     App. C (the MNIST pipeline): the layer compiler and network evaluation.
  * Key switching (relinearisation, rotation keys) and the RNS/NTT form are how
  * BFV realises those operations; the paper uses them through its library.
@@ -106,7 +106,7 @@ int lola_reserve(lola_ctx *ctx, uint32_t n_ct);
 
 /* Galois element of a rotation: step > 0 rotates every slot row left by step
  * (output slot (r,i) takes input slot (r, i+step)), step < 0 right, and
- * LOLA_ROW_SWAP swaps the two rows (Sec. 2.1).  Returns 3^step mod 2N or
+ * LOLA_ROW_SWAP swaps the two rows (Sec. 3.1).  Returns 3^step mod 2N or
  * 2N-1; 0 on a bad N. */
 uint32_t lola_galois_element(uint32_t N, int32_t step);
 
@@ -123,7 +123,7 @@ int lola_keygen_switch(lola_ctx *ctx, uint64_t seed, const uint32_t *sk_dev, uin
                        uint32_t *ksk_dev, lola_stream stream);
 
 /* ------------------------------------------------------------- plaintexts */
-/* Slot encoding (Sec. 2.1 batching): slot (r, i) = r*N/2 + i of the
+/* Slot encoding (Sec. 3.1 batching): slot (r, i) = r*N/2 + i of the
  * plaintext m is m(zeta^e), e = (2N-1)^r 3^i mod 2N, zeta the smallest
  * primitive 2N-th root of unity mod t.  slots_dev: N int64 (any integers,
  * reduced mod t); pt_dev: N words in [0, t). */
@@ -154,7 +154,7 @@ int lola_add_plain(lola_ctx *ctx, const uint32_t *ct_dev, const uint32_t *pt_add
 /* out = (c0 [m]_t, c1 [m]_t). */
 int lola_mul_plain(lola_ctx *ctx, const uint32_t *ct_dev, const uint32_t *pt_mul_dev,
                    uint32_t *out_dev, lola_stream stream);
-/* out = [w]_t * ct (message times scalar, Sec. 3.2.2). */
+/* out = [w]_t * ct (message times scalar, Sec. 4.2.2). */
 int lola_mul_scalar(lola_ctx *ctx, const uint32_t *ct_dev, int64_t w, uint32_t *out_dev,
                     lola_stream stream);
 /* Size-3 product: d_j = round(t (a (x) b)_j / Q) mod Q for the tensor of the
@@ -226,10 +226,10 @@ int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uin
 
 /* ------------------------------------------------------- layer compiler */
 /* Lowers a layer list onto the operations above with the paper's vector
- * representations and matrix-vector recipes (Sec. 3.2: dense, sparse,
+ * representations and matrix-vector recipes (Sec. 4.2: dense, sparse,
  * stacked, interleaved and convolution representations; dense-row-major,
  * stacked-row-major, interleaved-row-major and convolution-row-major
- * products; Sec. 4 / Table 1 and App. C / Table 3 for the MNIST pipeline).
+ * products; Sec. 4.3 / Table 1 and App. C / Table 3 for the MNIST pipeline).
  * Supported layer patterns (anything else returns LOLA_E_UNSUPPORTED):
  *   CONV2D, SQUARE, DENSE, SQUARE, DENSE   convolution representation input
  *       (k*k messages), maps combined by rotations, stacked-row-major dense

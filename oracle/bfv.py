@@ -6,8 +6,8 @@ CPU-baseline leg may import it.  It shares no code with the GPU library; the
 polynomial arithmetic comes from oracle/bfv_ref.c and every multi-precision
 step (CRT lifts, exact rounding) uses Python integers.
 
-What is computed (the paper fixes the scheme's interface in Sec. 2.1: E, D,
-the homomorphic + and x, message-times-scalar products from Sec. 3.2.2, and
+What is computed (the paper fixes the scheme's interface in Sec. 3.1: E, D,
+the homomorphic + and x, message-times-scalar products from Sec. 4.2.2, and
 the row-swap / column-rotation operations on the 2 x N/2 slot matrix):
 
   ring      R_m = Z_m[X]/(X^N+1); polynomials are numpy uint64 arrays of
@@ -15,7 +15,7 @@ the row-swap / column-rotation operations on the 2 x N/2 slot matrix):
   Q         q_0 * ... * q_{L-1};  Delta = floor(Q / t).
   slots     slot (r, i), r in {0,1}, i < N/2, of m in R_t is m(zeta^e(r,i)) with
             e(r,i) = (2N-1)^r * 3^i mod 2N and zeta the smallest g with
-            g^N = -1 (mod t)  (Sec. 2.1: a 2N-th root of unity mod p makes R_p
+            g^N = -1 (mod t)  (Sec. 3.1: a 2N-th root of unity mod p makes R_p
             a vector of N slots).
   rotate    rotate(+k) = automorphism X -> X^(3^k mod 2N): output slot (r,i)
             takes input slot (r, i+k mod N/2) (a left rotation of each row);

@@ -7,7 +7,7 @@
  * benchmark may load it; the product path never does.  It shares no code,
  * header, table or constant generator with the GPU library.
  *
- * The paper (Sec. 2.1, "Homomorphic Encryption", and App. A "Rings") fixes the
+ * The paper (Sec. 3.1, "Homomorphic Encryption", and App. A "Rings") fixes the
  * ring: polynomials with coefficients mod m, reduced modulo X^N + 1 with N a
  * power of two.  Everything here is a plain definition of an operation on that
  * ring:
@@ -18,8 +18,8 @@
  *       the schoolbook product by the tests);
  *   - or_eval_odd / or_interp_odd: evaluation of a polynomial at all odd powers
  *       of a primitive 2N-th root, and its inverse (used for slot encoding,
- *       Sec. 2.1: with a 2N-th root of unity mod p the ring splits into N slots);
- *   - or_automorph: a(X) -> a(X^g) for odd g (the rotations of Sec. 2.1 are
+ *       Sec. 3.1: with a 2N-th root of unity mod p the ring splits into N slots);
+ *   - or_automorph: a(X) -> a(X^g) for odd g (the rotations of Sec. 3.1 are
  *       such automorphisms on the slot vector);
  *   - ChaCha20 block function (RFC 8439, Sec. 2.3) and the three samplers
  *       built on it (uniform mod m, ternary, centred binomial).

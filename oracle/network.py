@@ -7,13 +7,13 @@ Three things live here, all written from the paper's text:
 1. Plaintext integer networks (exact Python integers, then mod t):
    - dense64: y = (W x)^2 for a 64-vector and a 64x64 matrix;
    - mnist:   5x5 stride-2 convolution with 5 maps -> square -> dense 845->100
-              -> square -> dense 100->10 (Sec. 4, the network of Table 1), with
+              -> square -> dense 100->10 (Sec. 4.3, the network of Table 1), with
               integer biases;
    - head:    dense 4096->256 -> square -> dense 256->10 (the private head on
               deep features of Sec. 5, with a hidden layer).
 2. Schedules: the paper's vector representations and matrix-vector recipes
-   (Sec. 3.2) written out as op lists on ciphertext registers:
-     ("mul_scalar", dst, src, w)      message times scalar (Sec. 3.2.2, conv)
+   (Sec. 4.2) written out as op lists on ciphertext registers:
+     ("mul_scalar", dst, src, w)      message times scalar (Sec. 4.2.2, conv)
      ("add", dst, a, b)
      ("add_plain", dst, src, slots)   slots: {slot index: value}
      ("mul_plain", dst, src, slots)
@@ -147,13 +147,13 @@ def _combine_tree(b: _Builder, regs: Sequence[int], unit: int) -> int:
 
 def dense64_inputs(x, N):
     """Client side: the 64-vector stacked N/64 times (stacked representation,
-    Sec. 3.2.1, with d = 6): slot i holds x[i mod 64]."""
+    Sec. 4.2.1, with d = 6): slot i holds x[i mod 64]."""
     x = np.asarray(x, dtype=np.int64)
     return [{s: int(x[s % 64]) for s in range(N)}]
 
 
 def dense64_schedule(W, N: int = 4096) -> Schedule:
-    """Stacked vector - row major (Sec. 3.2.2): one point-wise product with the
+    """Stacked vector - row major (Sec. 4.2.2): one point-wise product with the
     64 rows of W laid out row j at slots 64j..64j+63, then rotations of size
     1, 2, ..., 32 and additions; value j ends at slot 64j (interleaved), then
     squared."""
@@ -169,7 +169,7 @@ def dense64_schedule(W, N: int = 4096) -> Schedule:
 
 # MNIST (N = 16384): slots are a 2 x 8192 matrix; slot index r*8192 + i.
 def conv_representation(img, k: int, stride: int):
-    """Convolution representation (Sec. 3.2.1) of a 2-D input for a k x k
+    """Convolution representation (Sec. 4.2.1) of a 2-D input for a k x k
     window at the given stride: k*k messages; message a*k+b holds, at entry
     y*n_out + x, the input value [stride*y + a][stride*x + b], so that
     sum_{a,b} w[a,b] * message(a,b) is the convolution output at (y, x).
@@ -272,7 +272,7 @@ def head_inputs(features, N=16384):
 
 
 def head_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int = 10) -> Schedule:
-    """Dense vector - row major (Sec. 3.2.2) for 4096 -> 256: per hidden unit
+    """Dense vector - row major (Sec. 4.2.2) for 4096 -> 256: per hidden unit
     j, product with row j repeated in every block, rotate-and-sum over
     1..2048 (each block's sum lands at its first slot), mask, then rotate
     right by j and add, as a binary tree (interleaved result, h_j of query q at slot 4096 q + j),

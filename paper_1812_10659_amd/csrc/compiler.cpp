@@ -1,25 +1,25 @@
 // Layer compiler: lowers a layer list to an op list with the paper's vector
-// representations and matrix-vector recipes (Sec. 3.2), then levels the ops
+// representations and matrix-vector recipes (Sec. 4.2), then levels the ops
 // into waves of independent work and assigns physical registers.
 //
 // Recipes (W: weights, values modulo t):
-//   convolution vector - row major (Sec. 3.2.2): the input is k*k messages,
+//   convolution vector - row major (Sec. 4.2.2): the input is k*k messages,
 //     message a*k+b holding input[stride*y + a][stride*x + b] at slot y*n+x;
 //     map m is sum_{a,b} w[m][a][b] * message(a,b) (+ bias), one message per
 //     map, values at slots 0..n*n-1 (dense);
 //   combining messages (Table 1, "combine ... using rotations"): message j is
 //     rotated right by j*unit and added; built as a binary tree so only
 //     log2(count) distinct rotation keys are needed;
-//   stacked vector - row major (Sec. 3.2.2): copies of a dense vector at
+//   stacked vector - row major (Sec. 4.2.2): copies of a dense vector at
 //     stride P (next power of two >= its length) are made by rotate-and-add
 //     over -P, -2P, ..., -N/4 and the row swap; each round multiplies by rows
 //     laid out one per block, sums each block by rotations 1..P/2, keeps the
 //     block's first slot (mask) and adds the bias; rounds are then combined
 //     into an interleaved vector (value C*rho + c at slot P*c + rho);
-//   interleaved vector - row major (Sec. 3.2.2): per output, a product with
+//   interleaved vector - row major (Sec. 4.2.2): per output, a product with
 //     the row permuted to the interleaved layout and a rotate-and-sum that
 //     collects every occupied slot into slot 0 (sparse output);
-//   dense vector - row major (Sec. 3.2.2): per output row, product with the
+//   dense vector - row major (Sec. 4.2.2): per output row, product with the
 //     row in every query block, rotate-and-sum over the block, mask, then
 //     combination into an interleaved vector (value j of query q at P*q + j).
 #include <algorithm>

@@ -7,7 +7,7 @@ seeded numpy values of the shapes the paper's workloads have.
 
 Prime choice: the ciphertext primes are the largest primes below 2^30 that are
 congruent to 1 modulo 2N (so a negacyclic NTT of length N exists, the same
-condition the paper states for slot batching mod p in Sec. 2.1).  The plaintext
+condition the paper states for slot batching mod p in Sec. 3.1).  The plaintext
 modulus t is a prime congruent to 1 modulo 2N, so that R_t splits into N slots.
 """
 from __future__ import annotations

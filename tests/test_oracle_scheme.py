@@ -50,7 +50,7 @@ def test_encode_decode_roundtrip_and_homomorphism(name):
     assert mv.max() < ctx.t
     # encode is a ring homomorphism: encode(v) * encode(w) = encode(v . w) in R_t
     assert np.array_equal(bfv.poly_mul(mv, mw, ctx.t), bfv.encode(ctx, (v * w) % ctx.t))
-    # a constant polynomial sets every slot to the constant (Sec. 3.2.1 footnote)
+    # a constant polynomial sets every slot to the constant (Sec. 4.2.1 footnote)
     c = np.zeros(ctx.N, np.uint64); c[0] = 12345 % ctx.t
     assert np.all(bfv.decode(ctx, c) == 12345 % ctx.t)
 
