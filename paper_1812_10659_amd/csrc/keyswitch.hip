@@ -36,19 +36,16 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const Ks
     const uint32_t i = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const ModConst mc = mcs[i];
-    const uint32_t *xi = job.x + ((size_t)i << LOGN);
-    uint32_t *Xp = job.scratch + ((size_t)(L + i) << LOGN);
+    const GBuf xi = gbuf(job.x + ((size_t)i << LOGN), 1u << LOGN);
+    const GBuf Xp = gbuf(job.scratch + ((size_t)(L + i) << LOGN), 1u << LOGN);
     uint32_t x[NTT_E];
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) {
-        const uint32_t idx = spectral_index<LOGN>(tid, r);
-        x[r] = xi[perm_src(idx, job.galois, LOGN)];
-        Xp[idx] = x[r];  // sigma_g(x_i) in NTT form: the digit's own-modulus transform
-    }
+    for (int r = 0; r < NTT_E; ++r) x[r] = gld(xi, perm_src(spectral_index<LOGN>(tid, r), job.galois, LOGN));
+    store_spectral<LOGN>(Xp, tid, x);  // sigma_g(x_i) in NTT form: the digit's own-modulus transform
     ntt_inv_regs<LOGN>(x, tid, sh, itw + ((size_t)i << LOGN), mc);
-    uint32_t *D = job.scratch + ((size_t)i << LOGN);
+    const GBuf D = gbuf(job.scratch + ((size_t)i << LOGN), 1u << LOGN);
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) D[natural_index<LOGN>(tid, r)] = x[r];
+    for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN>(tid, r), x[r]);
 }
 
 template <int LOGN>
@@ -62,7 +59,11 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
     const uint32_t j = blockIdx.x;  // target modulus: q_j (j < L) or P (j == L)
     const ModConst mc = mcs[j];
     const uint32_t M = L + 1;
-    uint32_t a0[NTT_E], a1[NTT_E];
+    // 64-bit accumulators: every term is x * key with x < q (the transform's
+    // output is canonical) and key < q, so at most 12 digits sum below
+    // 12 q^2 < 2^64; one Montgomery reduction at the end (keys are stored
+    // times 2^32).
+    uint64_t a0[NTT_E], a1[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
     for (uint32_t i = 0; i < L; ++i) {
@@ -74,13 +75,11 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
         asm volatile("" : "+v"(tid));
         uint32_t x[NTT_E];
         if (i == j) {
-            const uint32_t *Xp = job.scratch + ((size_t)(L + i) << LOGN);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) x[r] = Xp[spectral_index<LOGN>(tid, r)];
+            load_spectral<LOGN>(gbuf(job.scratch + ((size_t)(L + i) << LOGN), N), tid, x);
         } else {
-            const uint32_t *D = job.scratch + ((size_t)i << LOGN);
+            const GBuf D = gbuf(job.scratch + ((size_t)i << LOGN), N);
 #pragma unroll
-            for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(D[natural_index<LOGN>(tid, r)], mc.q, mc.one_shoup);
+            for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN>(tid, r)), mc.q, mc.one_shoup);
             // The twiddle table does not change with i; an opaque copy of j
             // keeps the compiler from hoisting every twiddle load of the
             // transform out of the loop.
@@ -92,37 +91,45 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
         // so the 32 key loads are not scheduled ahead of it.
         uint32_t koff = i * 2 * M + j;
         asm volatile("" : "+s"(koff));
-        const uint32_t *kb = job.key + ((size_t)koff << LOGN);
-        const uint32_t *ka = job.key + ((size_t)(koff + M) << LOGN);
+        const GBuf kb = gbuf(job.key + ((size_t)koff << LOGN), N);
+        const GBuf ka = gbuf(job.key + ((size_t)(koff + M) << LOGN), N);
+        uint32_t kbv[NTT_E], kav[NTT_E];
+        load_spectral<LOGN>(kb, tid, kbv);
+        load_spectral<LOGN>(ka, tid, kav);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) {
-            const uint32_t idx = spectral_index<LOGN>(tid, r);
-            a0[r] = add_mod(a0[r], mont_mul(x[r], kb[idx], mc.q, mc.qneg_inv), mc.q);
-            a1[r] = add_mod(a1[r], mont_mul(x[r], ka[idx], mc.q, mc.qneg_inv), mc.q);
+            a0[r] += (uint64_t)x[r] * kbv[r];
+            a1[r] += (uint64_t)x[r] * kav[r];
         }
     }
     const uint32_t tid = threadIdx.x;
+    uint32_t u[NTT_E];
     if (j < L) {
-        uint32_t *U0 = job.scratch + ((size_t)(2 * L + j) << LOGN);
-        uint32_t *U1 = job.scratch + ((size_t)(3 * L + j) << LOGN);
+        const GBuf U0 = gbuf(job.scratch + ((size_t)(2 * L + j) << LOGN), N);
+        const GBuf U1 = gbuf(job.scratch + ((size_t)(3 * L + j) << LOGN), N);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) {
-            const uint32_t idx = spectral_index<LOGN>(tid, r);
-            U0[idx] = a0[r];
-            U1[idx] = a1[r];
-        }
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
+        store_spectral<LOGN>(U0, tid, u);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
+        store_spectral<LOGN>(U1, tid, u);
     } else {
-        uint32_t *UP = job.scratch + ((size_t)(4 * L) << LOGN);
-        ntt_inv_regs<LOGN>(a0, tid, sh, itw + ((size_t)j << LOGN), mc);
+        const GBuf UP = gbuf(job.scratch + ((size_t)(4 * L) << LOGN), N);
+        const GBuf UP1 = gbuf(job.scratch + ((size_t)(4 * L + 1) << LOGN), N);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) UP[natural_index<LOGN>(tid, r)] = a0[r];
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
+        ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
         uint32_t tid2 = tid;
         asm volatile("" : "+v"(tid2));
         uint32_t jj = j;
         asm volatile("" : "+s"(jj));
-        ntt_inv_regs<LOGN>(a1, tid2, sh, itw + ((size_t)jj << LOGN), mc);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) UP[N + natural_index<LOGN>(tid2, r)] = a1[r];
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
+        ntt_inv_regs<LOGN>(u, tid2, sh, itw + ((size_t)jj << LOGN), mc);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP1, natural_index<LOGN>(tid2, r), u[r]);
     }
 }
 
@@ -138,30 +145,39 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const K
     const ModConst mc = mcs[j];
     const uint32_t P = mcs[L].q, halfP = P >> 1;
     const uint32_t Pq = mrc->Pq[j];
-    const uint32_t *UP = job.scratch + ((size_t)(4 * L + c) << LOGN);
+    constexpr uint32_t N = 1u << LOGN;
+    const GBuf UP = gbuf(job.scratch + ((size_t)(4 * L + c) << LOGN), N);
     uint32_t x[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) {
-        const uint32_t v = UP[natural_index<LOGN>(tid, r)];
+        const uint32_t v = gld(UP, natural_index<LOGN>(tid, r));
         const uint32_t vr = reduce32(v, mc.q, mc.one_shoup);
         x[r] = v > halfP ? sub_mod(vr, Pq, mc.q) : vr;  // [u_P]_P mod q_j
     }
     ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
-    const uint32_t *U = job.scratch + ((size_t)((2 + c) * L + j) << LOGN);
+    const GBuf U = gbuf(job.scratch + ((size_t)((2 + c) * L + j) << LOGN), N);
     const uint32_t *add = c == 0 ? job.add0 : job.add1;
     const uint32_t g = c == 0 ? job.galois : 0u;
     const uint32_t pinv = mrc->Pinvq[j], pinvp = mrc->Pinvqp[j];
-    uint32_t *out = job.out + ((size_t)(c * L + j) << LOGN);
-    const uint32_t *addj = add ? add + ((size_t)j << LOGN) : nullptr;
-    const uint32_t *addc = job.addct ? job.addct + ((size_t)(c * L + j) << LOGN) : nullptr;
+    const GBuf out = gbuf(job.out + ((size_t)(c * L + j) << LOGN), N);
+    const bool has_add = add != nullptr, has_addc = job.addct != nullptr;
+    const GBuf addj = gbuf(has_add ? add + ((size_t)j << LOGN) : job.out, has_add ? N : 0u);
+    const GBuf addc = gbuf(has_addc ? job.addct + ((size_t)(c * L + j) << LOGN) : job.out, has_addc ? N : 0u);
+    uint32_t uu[NTT_E];
+    load_spectral<LOGN>(U, tid, uu);
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) {
-        const uint32_t idx = spectral_index<LOGN>(tid, r);
-        uint32_t w = shoup(sub_mod(U[idx], x[r], mc.q), pinv, pinvp, mc.q);
-        if (addj) w = add_mod(w, addj[perm_src(idx, g, LOGN)], mc.q);
-        if (addc) w = add_mod(w, addc[idx], mc.q);
-        out[idx] = w;
+    for (int r = 0; r < NTT_E; ++r) x[r] = shoup(sub_mod(uu[r], x[r], mc.q), pinv, pinvp, mc.q);
+    if (has_add) {
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r)
+            x[r] = add_mod(x[r], gld(addj, perm_src(spectral_index<LOGN>(tid, r), g, LOGN)), mc.q);
     }
+    if (has_addc) {
+        load_spectral<LOGN>(addc, tid, uu);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], uu[r], mc.q);
+    }
+    store_spectral<LOGN>(out, tid, x);
 }
 
 size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }

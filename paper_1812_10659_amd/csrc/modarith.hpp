@@ -20,6 +20,46 @@
 
 namespace lola {
 
+// Loads and stores of one limb (or any buffer below 4 GiB) through a buffer
+// resource: a scalar base and size plus a 32-bit lane offset.  Pointers read
+// from job descriptors are generic, and plain indexing through them costs a
+// flat access with 64-bit address arithmetic per element.  Accesses past the
+// given size read 0 and drop the store instead of faulting.
+#if defined(__HIP_DEVICE_COMPILE__)
+struct GBuf {
+    __amdgpu_buffer_rsrc_t r;
+};
+LOLA_HD GBuf gbuf(const uint32_t *base, uint32_t n_words) {
+    return GBuf{__builtin_amdgcn_make_buffer_rsrc((void *)base, 0, (int)(n_words * 4u), 0x00020000)};
+}
+LOLA_HD uint32_t gld(GBuf b, uint32_t i) { return __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)(i << 2), 0, 0); }
+LOLA_HD void gst(GBuf b, uint32_t i, uint32_t v) { __builtin_amdgcn_raw_buffer_store_b32(v, b.r, (int)(i << 2), 0, 0); }
+// Four consecutive words at i (i a multiple of 4).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+LOLA_HD u32x4 gld4(GBuf b, uint32_t i) { return __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)(i << 2), 0, 0); }
+LOLA_HD void gst4(GBuf b, uint32_t i, u32x4 v) { __builtin_amdgcn_raw_buffer_store_b128(v, b.r, (int)(i << 2), 0, 0); }
+#else
+struct GBuf {
+    uint32_t *p;
+    uint32_t n;
+};
+LOLA_HD GBuf gbuf(const uint32_t *base, uint32_t n_words) { return GBuf{(uint32_t *)base, n_words}; }
+LOLA_HD uint32_t gld(GBuf b, uint32_t i) { return i < b.n ? b.p[i] : 0u; }
+LOLA_HD void gst(GBuf b, uint32_t i, uint32_t v) {
+    if (i < b.n) b.p[i] = v;
+}
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+LOLA_HD u32x4 gld4(GBuf b, uint32_t i) { return u32x4{gld(b, i), gld(b, i + 1), gld(b, i + 2), gld(b, i + 3)}; }
+LOLA_HD void gst4(GBuf b, uint32_t i, u32x4 v) {
+    gst(b, i, v.x);
+    gst(b, i + 1, v.y);
+    gst(b, i + 2, v.z);
+    gst(b, i + 3, v.w);
+}
+#endif
+
 // Per-modulus constants (one entry per prime of a context).
 struct ModConst {
     uint32_t q;        // the prime

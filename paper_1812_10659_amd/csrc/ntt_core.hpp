@@ -250,4 +250,40 @@ LOLA_HD uint32_t natural_index(uint32_t tid, uint32_t r) { return NttShape<LOGN>
 template <int LOGN>
 LOLA_HD uint32_t spectral_index(uint32_t tid, uint32_t r) { return NttShape<LOGN>::Last::index(tid, r); }
 
+// Registers r..r+3 of the forward output layout hold four consecutive,
+// 4-aligned residues when the last pass's sub-transforms have at least four
+// elements (stride 1, base a multiple of the length): then they move with one
+// 16-byte access per lane and neighbouring lanes touch neighbouring 16 bytes.
+template <int LOGN>
+constexpr bool spectral_vec4() { return NttShape<LOGN>::Last::SUB >= 4 && NttShape<LOGN>::Last::STR == 1; }
+
+template <int LOGN>
+LOLA_HD void load_spectral(GBuf b, uint32_t tid, uint32_t (&y)[NTT_E]) {
+    if constexpr (spectral_vec4<LOGN>()) {
+#pragma unroll
+        for (int r = 0; r < NTT_E; r += 4) {
+            const u32x4 v = gld4(b, spectral_index<LOGN>(tid, r));
+            y[r] = v.x, y[r + 1] = v.y, y[r + 2] = v.z, y[r + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) y[r] = gld(b, spectral_index<LOGN>(tid, r));
+    }
+}
+
+template <int LOGN>
+LOLA_HD void store_spectral(GBuf b, uint32_t tid, const uint32_t (&y)[NTT_E]) {
+    if constexpr (spectral_vec4<LOGN>()) {
+#pragma unroll
+        for (int r = 0; r < NTT_E; r += 4) {
+            u32x4 v;
+            v.x = y[r], v.y = y[r + 1], v.z = y[r + 2], v.w = y[r + 3];
+            gst4(b, spectral_index<LOGN>(tid, r), v);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(b, spectral_index<LOGN>(tid, r), y[r]);
+    }
+}
+
 }  // namespace lola
