@@ -1,0 +1,173 @@
+// The three stages of one key switch as workgroup-level device functions,
+// shared by the batched launches (one stage per launch, one workgroup per
+// limb-sized unit) and by the persistent kernel (one workgroup runs all
+// stages of a rotation).
+//
+// For a polynomial x (NTT form, [L][N]) and a switching key for s' -> s with
+// digits D_i = x mod q_i in [0, q_i):
+//   u_m = sum_i D_i * key_i   modulo every q_j and P      (key inner product)
+//   out_j = (u_j - [u_P]_P) * P^-1 mod q_j                 (mod-down by P)
+// A Galois automorphism sigma_g acts on NTT-form limbs as a permutation of
+// evaluation points, so a rotation folds it into the loads of x and of c0.
+//
+// Scratch of one key switch, (4L + 2) N words:
+//   D  [L][N]   digits in coefficient form          (words 0 .. L N)
+//   X' [L][N]   sigma_g(x_i) in NTT form             (L N .. 2 L N)
+//   U  [2][L][N] inner products mod q_j, NTT form    (2 L N .. 4 L N)
+//   UP [2][N]   inner products mod P, coefficients   (4 L N .. (4L+2) N)
+//
+// Key layout: [i][0 = b, 1 = a][m][N], m over q_0..q_{L-1}, P, stored times
+// 2^32 mod m (Montgomery form), canonical.
+//
+// Every index that depends only on the thread id goes through an opaque copy
+// (asm volatile with a "+v" or "+s" constraint) inside loops: otherwise the
+// compiler hoists all of them, and the transforms' LDS and twiddle addresses,
+// out of the loops, which does not fit in the 128 registers that a
+// 1024-thread workgroup allows.
+#pragma once
+#include "lola_internal.hpp"
+#include "ntt_core.hpp"
+
+namespace lola {
+
+__device__ __forceinline__ uint32_t ks_perm(uint32_t idx, uint32_t g, uint32_t logN) {
+    return g > 1 ? galois_src_index(idx, g, logN) : idx;
+}
+
+// Stage 1 for digit i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, uint32_t *scratch, uint32_t i,
+                                               uint32_t L, uint32_t *sh, const ModConst &mc,
+                                               const TwPair *itw) {
+    constexpr uint32_t N = 1u << LOGN;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t ii = i;
+    asm volatile("" : "+s"(ii));
+    const GBuf xi = gbuf(x + ((size_t)ii << LOGN), N);
+    uint32_t v[NTT_E];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) v[r] = gld(xi, ks_perm(spectral_index<LOGN>(tid, r), g, LOGN));
+    store_spectral<LOGN>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
+    ntt_inv_regs<LOGN>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
+    const GBuf D = gbuf(scratch + ((size_t)ii << LOGN), N);
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN>(tid, r), v[r]);
+}
+
+// Stage 2 for target modulus j (q_j for j < L, P for j == L): for every
+// digit, reduce it mod the target, transform it (j == i reuses X'_i), and
+// accumulate its products with both key components.  The sums mod q_j go to
+// U in NTT form; the sums mod P are brought back to coefficients into UP.
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t L,
+                                               uint32_t *sh, const ModConst &mc, const TwPair *tw,
+                                               const TwPair *itw) {
+    constexpr uint32_t N = 1u << LOGN;
+    const uint32_t M = L + 1;
+    // 64-bit accumulators: every term is x * key with x < q (a transform's
+    // output is canonical) and key < q, so at most 12 digits sum below
+    // 12 q^2 < 2^64; one Montgomery reduction at the end.
+    uint64_t a0[NTT_E], a1[NTT_E];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
+    for (uint32_t i = 0; i < L; ++i) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        uint32_t x[NTT_E];
+        if (i == j) {
+            load_spectral<LOGN>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
+        } else {
+            const GBuf D = gbuf(scratch + ((size_t)i << LOGN), N);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN>(tid, r)), mc.q, mc.one_shoup);
+            uint32_t jj = j;
+            asm volatile("" : "+s"(jj));
+            ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
+        }
+        // The key offset passes through an opaque copy placed after the
+        // transform, so the key loads are not scheduled ahead of it.
+        uint32_t koff = i * 2 * M + j;
+        asm volatile("" : "+s"(koff));
+        uint32_t kb[NTT_E], ka[NTT_E];
+        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kb);
+        load_spectral<LOGN>(gbuf(key + ((size_t)(koff + M) << LOGN), N), tid, ka);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) {
+            a0[r] += (uint64_t)x[r] * kb[r];
+            a1[r] += (uint64_t)x[r] * ka[r];
+        }
+    }
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t u[NTT_E];
+    if (j < L) {
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
+        store_spectral<LOGN>(gbuf(scratch + ((size_t)(2 * L + j) << LOGN), N), tid, u);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
+        store_spectral<LOGN>(gbuf(scratch + ((size_t)(3 * L + j) << LOGN), N), tid, u);
+    } else {
+        const GBuf UP0 = gbuf(scratch + ((size_t)(4 * L) << LOGN), N);
+        const GBuf UP1 = gbuf(scratch + ((size_t)(4 * L + 1) << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
+        ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP0, natural_index<LOGN>(tid, r), u[r]);
+        uint32_t tid2 = tid;
+        asm volatile("" : "+v"(tid2));
+        uint32_t jj = j;
+        asm volatile("" : "+s"(jj));
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
+        ntt_inv_regs<LOGN>(u, tid2, sh, itw + ((size_t)jj << LOGN), mc);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP1, natural_index<LOGN>(tid2, r), u[r]);
+    }
+}
+
+// Stage 3 for (target q_j, component c): lift [u_P]_P into q_j, transform,
+// out = (U - lift) * P^-1, plus the optional addends: `add` ([L][N], read
+// through sigma_g when g > 1: the rotation's c0 or the relinearisation's d0 /
+// d1) and `addct` ([2][L][N], a whole ciphertext: fused rotate-and-add).
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
+                                                 const uint32_t *add, uint32_t g, const uint32_t *addct,
+                                                 uint32_t *out, uint32_t *sh, const ModConst &mc,
+                                                 const TwPair *tw, const MrcConst *mrc, uint32_t P) {
+    constexpr uint32_t N = 1u << LOGN;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t jj = j;
+    asm volatile("" : "+s"(jj));
+    const uint32_t halfP = P >> 1, Pq = mrc->Pq[jj];
+    const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+    uint32_t x[NTT_E];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) {
+        const uint32_t v = gld(UP, natural_index<LOGN>(tid, r));
+        const uint32_t vr = reduce32(v, mc.q, mc.one_shoup);
+        x[r] = v > halfP ? sub_mod(vr, Pq, mc.q) : vr;  // [u_P]_P mod q_j
+    }
+    ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
+    const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
+    uint32_t u[NTT_E];
+    load_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + jj) << LOGN), N), tid, u);
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) x[r] = shoup(sub_mod(u[r], x[r], mc.q), pinv, pinvp, mc.q);
+    if (add) {
+        const GBuf a = gbuf(add + ((size_t)jj << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], gld(a, ks_perm(spectral_index<LOGN>(tid, r), g, LOGN)), mc.q);
+    }
+    if (addct) {
+        load_spectral<LOGN>(gbuf(addct + ((size_t)(c * L + jj) << LOGN), N), tid, u);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], u[r], mc.q);
+    }
+    store_spectral<LOGN>(gbuf(out + ((size_t)(c * L + jj) << LOGN), N), tid, x);
+}
+
+}  // namespace lola

@@ -13,11 +13,13 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ntt_jobs_kernel(
     const ModConst mc = mcs[job.prime];
     const uint32_t tid = threadIdx.x;
     const size_t toff = (size_t)job.prime << LOGN;
+    constexpr uint32_t N = 1u << LOGN;
+    const GBuf src = gbuf(job.src, N), dst = gbuf(job.dst, N);
     uint32_t x[NTT_E];
     if (!(job.flags & NTT_INVERSE)) {
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) {
-            uint32_t v = job.src[natural_index<LOGN>(tid, r)];
+            uint32_t v = gld(src, natural_index<LOGN>(tid, r));
             if (job.flags & NTT_SRC_SIGNED_T) {
                 // [v]_t mod q: values above t/2 stand for v - t
                 v = (v > (t >> 1)) ? mc.q - (t - v) : v;
@@ -39,18 +41,16 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ntt_jobs_kernel(
 #pragma unroll
             for (int r = 0; r < NTT_E; ++r) x[r] = shoup(x[r], mc.r_mod, mc.r_shoup, mc.q);
         }
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) job.dst[spectral_index<LOGN>(tid, r)] = x[r];
+        store_spectral<LOGN>(dst, tid, x);
     } else {
+        load_spectral<LOGN>(src, tid, x);
+        if (job.flags & NTT_FROM_MONT) {
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) {
-            uint32_t v = job.src[spectral_index<LOGN>(tid, r)];
-            if (job.flags & NTT_FROM_MONT) v = mont_mul(v, 1u, mc.q, mc.qneg_inv);
-            x[r] = v;
+            for (int r = 0; r < NTT_E; ++r) x[r] = mont_mul(x[r], 1u, mc.q, mc.qneg_inv);
         }
         ntt_inv_regs<LOGN>(x, tid, sh, itw + toff, mc);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) job.dst[natural_index<LOGN>(tid, r)] = x[r];
+        for (int r = 0; r < NTT_E; ++r) gst(dst, natural_index<LOGN>(tid, r), x[r]);
     }
 }
 

@@ -7,7 +7,7 @@
 // key inner products, mod-down) with its own scratch -- and takes the next
 // chain.  Workgroups never wait on each other; each leaves the loop once the
 // counter has passed the number of chains, so the grid always drains.
-#include "ntt_core.hpp"
+#include "ks_core.hpp"
 #include "program.hpp"
 
 namespace lola {
@@ -29,121 +29,21 @@ __global__ void chain_counter_reset(uint32_t *counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
-__device__ __forceinline__ uint32_t chain_perm(uint32_t idx, uint32_t g, uint32_t logN) {
-    return g > 1 ? galois_src_index(idx, g, logN) : idx;
-}
-
-// One rotation by one workgroup: out = rotate(in) under key.
+// One rotation by one workgroup: out = rotate(in) under key, through the
+// three key-switch stages in turn (scratch: (4L+2) N words of its own).
 template <int LOGN>
 __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key, uint32_t g, uint32_t L,
                           uint32_t *scr, uint32_t *sh, const ModConst *mcs, const TwPair *tw,
                           const TwPair *itw, const MrcConst *mrc) {
-    constexpr uint32_t N = 1u << LOGN;
-    const uint32_t M = L + 1;
-    const uint32_t *c0 = in, *c1 = in + (size_t)L * N;
-    uint32_t *D = scr, *Xp = scr + (size_t)L * N, *U = scr + (size_t)2 * L * N, *UP = scr + (size_t)4 * L * N;
-    // digits: sigma_g(c1_i) kept in NTT form, inverse transform to coefficients
-    for (uint32_t i = 0; i < L; ++i) {
-        uint32_t tid = threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        uint32_t x[NTT_E];
-        const uint32_t *xi = c1 + ((size_t)i << LOGN);
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) {
-            const uint32_t idx = spectral_index<LOGN>(tid, r);
-            x[r] = xi[chain_perm(idx, g, LOGN)];
-            Xp[((size_t)i << LOGN) + idx] = x[r];
-        }
-        uint32_t ii = i;
-        asm volatile("" : "+s"(ii));
-        ntt_inv_regs<LOGN>(x, tid, sh, itw + ((size_t)ii << LOGN), mcs[ii]);
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) D[((size_t)i << LOGN) + natural_index<LOGN>(tid, r)] = x[r];
-    }
+    const uint32_t *c1 = in + ((size_t)L << LOGN);
+    for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN>(c1, g, scr, i, L, sh, mcs[i], itw);
     __syncthreads();
-    // per target modulus: transforms of the digits and the key inner product
-    for (uint32_t j = 0; j <= L; ++j) {
-        uint32_t jj = j;
-        asm volatile("" : "+s"(jj));
-        const ModConst mc = mcs[jj];
-        uint32_t a0[NTT_E], a1[NTT_E];
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
-        for (uint32_t i = 0; i < L; ++i) {
-            uint32_t tid = threadIdx.x;
-            asm volatile("" : "+v"(tid));
-            uint32_t x[NTT_E];
-            if (i == jj) {
-#pragma unroll
-                for (int r = 0; r < NTT_E; ++r) x[r] = Xp[((size_t)i << LOGN) + spectral_index<LOGN>(tid, r)];
-            } else {
-#pragma unroll
-                for (int r = 0; r < NTT_E; ++r)
-                    x[r] = reduce32(D[((size_t)i << LOGN) + natural_index<LOGN>(tid, r)], mc.q, mc.one_shoup);
-                uint32_t j2 = jj;
-                asm volatile("" : "+s"(j2));
-                ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)j2 << LOGN), mc.q);
-            }
-            uint32_t koff = i * 2 * M + jj;
-            asm volatile("" : "+s"(koff));
-            const uint32_t *kb = key + ((size_t)koff << LOGN), *ka = key + ((size_t)(koff + M) << LOGN);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) {
-                const uint32_t idx = spectral_index<LOGN>(tid, r);
-                a0[r] = add_mod(a0[r], mont_mul(x[r], kb[idx], mc.q, mc.qneg_inv), mc.q);
-                a1[r] = add_mod(a1[r], mont_mul(x[r], ka[idx], mc.q, mc.qneg_inv), mc.q);
-            }
-        }
-        uint32_t tid = threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        if (jj < L) {
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) {
-                const uint32_t idx = spectral_index<LOGN>(tid, r);
-                U[((size_t)jj << LOGN) + idx] = a0[r];
-                U[((size_t)(L + jj) << LOGN) + idx] = a1[r];
-            }
-        } else {
-            ntt_inv_regs<LOGN>(a0, tid, sh, itw + ((size_t)jj << LOGN), mc);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) UP[natural_index<LOGN>(tid, r)] = a0[r];
-            uint32_t tid2 = tid;
-            asm volatile("" : "+v"(tid2));
-            ntt_inv_regs<LOGN>(a1, tid2, sh, itw + ((size_t)jj << LOGN), mc);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) UP[N + natural_index<LOGN>(tid2, r)] = a1[r];
-        }
-    }
+    for (uint32_t j = 0; j <= L; ++j) ks_stage_inner<LOGN>(key, scr, j, L, sh, mcs[j], tw, itw);
     __syncthreads();
-    // mod-down by P and the automorphism of c0
-    const uint32_t P = mcs[L].q, halfP = P >> 1;
+    const uint32_t P = mcs[L].q;
     for (uint32_t c = 0; c < 2; ++c)
-        for (uint32_t j = 0; j < L; ++j) {
-            uint32_t jj = j;
-            asm volatile("" : "+s"(jj));
-            uint32_t tid = threadIdx.x;
-            asm volatile("" : "+v"(tid));
-            const ModConst mc = mcs[jj];
-            uint32_t x[NTT_E];
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) {
-                const uint32_t v = UP[(size_t)c * N + natural_index<LOGN>(tid, r)];
-                const uint32_t vr = reduce32(v, mc.q, mc.one_shoup);
-                x[r] = v > halfP ? sub_mod(vr, mrc->Pq[jj], mc.q) : vr;
-            }
-            ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
-            const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
-            const uint32_t *Uc = U + ((size_t)(c * L + jj) << LOGN);
-            const uint32_t *c0j = c0 + ((size_t)jj << LOGN);
-            uint32_t *o = out + ((size_t)(c * L + jj) << LOGN);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) {
-                const uint32_t idx = spectral_index<LOGN>(tid, r);
-                uint32_t w = shoup(sub_mod(Uc[idx], x[r], mc.q), pinv, pinvp, mc.q);
-                if (c == 0) w = add_mod(w, c0j[chain_perm(idx, g, LOGN)], mc.q);
-                o[idx] = w;
-            }
-        }
+        for (uint32_t j = 0; j < L; ++j)
+            ks_stage_moddown<LOGN>(scr, j, c, L, c == 0 ? in : nullptr, g, nullptr, out, sh, mcs[j], tw, mrc, P);
     __syncthreads();   // out is the next rotation's input
 }
 
