@@ -96,10 +96,13 @@ LOLA_HD void fwd_pass_regs(uint32_t (&x)[NTT_E], uint32_t tid, const TwPair *__r
             for (uint32_t k = 0; k < PS::SUB; ++k) {
                 if (k & h) continue;
                 const TwPair t = tw[tw_index<LOGN, S0, NS>(b, k, s)];
-                uint32_t X = csub(x[v * PS::SUB + k], twoq);
-                uint32_t Tm = shoup_lazy(x[v * PS::SUB + k + h], t.w, t.wp, q);
-                x[v * PS::SUB + k] = X + Tm;
-                x[v * PS::SUB + k + h] = X - Tm + twoq;
+                const uint32_t X = csub(x[v * PS::SUB + k], twoq);
+                // nT = -(w y mod q, lazily in [0, 2q)) modulo 2^32; written
+                // negated so the second output is one three-input add.
+                const uint32_t y = x[v * PS::SUB + k + h];
+                const uint32_t nT = mulhi32(y, t.wp) * q - y * t.w;
+                x[v * PS::SUB + k] = X - nT;
+                x[v * PS::SUB + k + h] = X + twoq + nT;
             }
         }
     }
