@@ -31,7 +31,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
                                                                      const ModConst *__restrict__ mcs,
                                                                      const TwPair *__restrict__ tw,
                                                                      const TwPair *__restrict__ itw) {
-    __shared__ uint32_t sh[1 << LOGN];
+    __shared__ uint32_t sh[2 << LOGN];
     const KsJob job = jobs[blockIdx.y];
     const uint32_t j = blockIdx.x;  // target modulus: q_j (j < L) or P (j == L)
     ks_stage_inner<LOGN>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);

@@ -59,6 +59,12 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
 // digit, reduce it mod the target, transform it (j == i reuses X'_i), and
 // accumulate its products with both key components.  The sums mod q_j go to
 // U in NTT form; the sums mod P are brought back to coefficients into UP.
+// sh: 2N words of LDS.  Consecutive transforms alternate between its halves,
+// so each needs only the workgroup barrier inside its first exchange: when a
+// transform starts writing a half, every wave has passed that barrier of the
+// transform before it, and so has finished the one before that, the last
+// user of the same half.  The caller must not have left reads of sh pending
+// (a workgroup barrier since its last use of sh).
 template <int LOGN>
 __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t L,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
@@ -71,6 +77,7 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
     uint64_t a0[NTT_E], a1[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
+    uint32_t half = 0;   // LDS half of the next transform
     for (uint32_t i = 0; i < L; ++i) {
         uint32_t tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
@@ -83,7 +90,8 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
             for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN>(tid, r)), mc.q, mc.one_shoup);
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
-            ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
+            ntt_fwd_regs<LOGN, true>(x, tid, sh + (half << LOGN), tw + ((size_t)jj << LOGN), mc.q);
+            half ^= 1u;
         }
         // The key offset passes through an opaque copy placed after the
         // transform, so the key loads are not scheduled ahead of it.

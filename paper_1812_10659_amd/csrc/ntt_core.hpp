@@ -190,7 +190,11 @@ LOLA_HD void pass_exchange_sync() {
 // last pass's layout (reduced to [0, q)).  sh: N words of LDS.  A barrier is
 // taken before the first LDS write, so a previous use of sh by the same
 // workgroup is complete.
-template <int LOGN, int P = 0>
+// FRESH: no wave of the workgroup can still be reading sh from an earlier
+// use (e.g. the caller alternates two buffers and the transform before the
+// previous one ended behind a workgroup barrier), so the first exchange
+// needs no barrier before its writes.
+template <int LOGN, int P = 0, bool FRESH = false>
 struct FwdDriver {
     LOLA_HD static void run(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
         constexpr int NPASS = NttShape<LOGN>::NPASS;
@@ -201,19 +205,22 @@ struct FwdDriver {
             // The first exchange of a transform waits for every earlier LDS
             // reader of the workgroup; later ones only for this wave when
             // both layouts keep each wave on its own block.
-            if constexpr (P == 0) LOLA_BARRIER();
-            else pass_exchange_sync<LOGN, PA, PB>();
+            if constexpr (P == 0) {
+                if constexpr (!FRESH) LOLA_BARRIER();
+            } else {
+                pass_exchange_sync<LOGN, PA, PB>();
+            }
             regs_to_lds<LOGN, PA::S0, PA::NS>(x, tid, sh);
             pass_exchange_sync<LOGN, PA, PB>();
             lds_to_regs<LOGN, PB::S0, PB::NS>(x, tid, sh);
-            FwdDriver<LOGN, P + 1>::run(x, tid, sh, tw, q);
+            FwdDriver<LOGN, P + 1, FRESH>::run(x, tid, sh, tw, q);
         }
     }
 };
 
-template <int LOGN>
+template <int LOGN, bool FRESH = false>
 LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
-    FwdDriver<LOGN, 0>::run(x, tid, sh, tw, q);
+    FwdDriver<LOGN, 0, FRESH>::run(x, tid, sh, tw, q);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(csub(x[r], 2 * q), q);
 }

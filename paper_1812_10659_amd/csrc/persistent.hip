@@ -38,8 +38,10 @@ __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key
     const uint32_t *c1 = in + ((size_t)L << LOGN);
     for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN>(c1, g, scr, i, L, sh, mcs[i], itw);
     __syncthreads();
-    for (uint32_t j = 0; j <= L; ++j) ks_stage_inner<LOGN>(key, scr, j, L, sh, mcs[j], tw, itw);
-    __syncthreads();
+    for (uint32_t j = 0; j <= L; ++j) {
+        ks_stage_inner<LOGN>(key, scr, j, L, sh, mcs[j], tw, itw);
+        __syncthreads();   // the next target's transforms reuse both LDS halves
+    }
     const uint32_t P = mcs[L].q;
     for (uint32_t c = 0; c < 2; ++c)
         for (uint32_t j = 0; j < L; ++j)
@@ -53,7 +55,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void chain_persistent_kernel(
     uint32_t *__restrict__ counter, uint32_t *__restrict__ scratch, size_t scratch_per_wg, uint32_t L,
     const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw, const TwPair *__restrict__ itw,
     const MrcConst *__restrict__ mrc) {
-    __shared__ uint32_t sh[1 << LOGN];
+    __shared__ uint32_t sh[2 << LOGN];
     __shared__ uint32_t item;
     uint32_t *scr = scratch + scratch_per_wg * blockIdx.x;
     for (;;) {
