@@ -17,34 +17,40 @@
 namespace lola {
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const KsJob *__restrict__ jobs, uint32_t L,
-                                                                      const ModConst *__restrict__ mcs,
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                      uint32_t L, const ModConst *__restrict__ mcs,
                                                                       const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[1 << LOGN];
-    const KsJob job = jobs[blockIdx.y];
-    const uint32_t i = blockIdx.x;
+    const JobUnit ju = xcd_job_unit(blockIdx.x, L);
+    if (ju.job >= n) return;
+    const KsJob job = jobs[ju.job];
+    const uint32_t i = ju.unit;
     ks_stage_digit<LOGN>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw);
 }
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJob *__restrict__ jobs, uint32_t L,
-                                                                     const ModConst *__restrict__ mcs,
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                     uint32_t L, const ModConst *__restrict__ mcs,
                                                                      const TwPair *__restrict__ tw,
                                                                      const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[2 << LOGN];
-    const KsJob job = jobs[blockIdx.y];
-    const uint32_t j = blockIdx.x;  // target modulus: q_j (j < L) or P (j == L)
+    const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1);
+    if (ju.job >= n) return;
+    const KsJob job = jobs[ju.job];
+    const uint32_t j = ju.unit;  // target modulus: q_j (j < L) or P (j == L)
     ks_stage_inner<LOGN>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
 }
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const KsJob *__restrict__ jobs, uint32_t L,
-                                                                       const ModConst *__restrict__ mcs,
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                       uint32_t L, const ModConst *__restrict__ mcs,
                                                                        const TwPair *__restrict__ tw,
                                                                        const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[1 << LOGN];
-    const KsJob job = jobs[blockIdx.z];
-    const uint32_t j = blockIdx.x, c = blockIdx.y;
+    const JobUnit ju = xcd_job_unit(blockIdx.x, 2 * L);
+    if (ju.job >= n) return;
+    const KsJob job = jobs[ju.job];
+    const uint32_t j = ju.unit % L, c = ju.unit / L;
     ks_stage_moddown<LOGN>(job.scratch, j, c, L, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
                            job.addct, job.out, sh, mcs[j], tw, mrc, mcs[L].q);
 }
@@ -52,6 +58,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const K
 size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }
 
 int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
+    if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
     const dim3 block(ctx->N / NTT_E);
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -62,13 +69,14 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t
     }
 #define LOLA_KS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
-        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(L, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_itw);  \
-        if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                             \
-        hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(L + 1, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_tw,  \
+        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L, ctx->d_mc,    \
                            ctx->d_itw);                                                                       \
+        if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                             \
+        hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L, ctx->d_mc, \
+                           ctx->d_tw, ctx->d_itw);                                                            \
         if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                             \
-        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(L, 2, n), block, 0, s, d_jobs, L, ctx->d_mc, ctx->d_tw, \
-                           ctx->d_mrc);                                                                       \
+        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, L,         \
+                           ctx->d_mc, ctx->d_tw, ctx->d_mrc);                                                 \
         break;
     switch (ctx->logN) {
         LOLA_KS_CASE(10)
