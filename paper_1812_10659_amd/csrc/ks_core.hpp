@@ -168,21 +168,23 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
     asm volatile("" : "+v"(tid));
     uint32_t jj = j;
     asm volatile("" : "+s"(jj));
-    const uint32_t halfP = P >> 1, Pq = mrc->Pq[jj];
+    // [u_P]_P mod q_j: v, or v - P for v > P/2, i.e. v + (q_j - P mod q_j);
+    // v < P < 2^30 keeps the sum below 2^31 for one reduction.
+    const uint32_t halfP = P >> 1, negPq = mc.q - mrc->Pq[jj];
     const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
     uint32_t x[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) {
         const uint32_t v = gld(UP, natural_index<LOGN>(tid, r));
-        const uint32_t vr = reduce32(v, mc.q, mc.one_shoup);
-        x[r] = v > halfP ? sub_mod(vr, Pq, mc.q) : vr;  // [u_P]_P mod q_j
+        x[r] = reduce32(v + (v > halfP ? negPq : 0u), mc.q, mc.one_shoup);
     }
     ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
     const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
     uint32_t u[NTT_E];
     load_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + jj) << LOGN), N), tid, u);
+    // (U - lift) P^-1: U + q - lift < 2q feeds the lazy product directly
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) x[r] = shoup(sub_mod(u[r], x[r], mc.q), pinv, pinvp, mc.q);
+    for (int r = 0; r < NTT_E; ++r) x[r] = csub(shoup_lazy(u[r] + mc.q - x[r], pinv, pinvp, mc.q), mc.q);
     if (add) {
         const GBuf a = gbuf(add + ((size_t)jj << LOGN), N);
 #pragma unroll

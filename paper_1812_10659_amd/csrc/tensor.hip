@@ -208,6 +208,7 @@ int mul_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *a, const uint32_
         const uint32_t m = std::min(CHUNK, n - off);
         std::vector<MulJob> pairs(m);
         for (uint32_t k = 0; k < m; ++k) {
+            if (!a[off + k] || !b[off + k] || !out3[off + k]) return set_error(LOLA_E_INVAL, "null pointer in batch");
             if (out3[off + k] == a[off + k] || out3[off + k] == b[off + k])
                 return set_error(LOLA_E_INVAL, "product output may not alias an input");
             pairs[k] = MulJob{a[off + k], b[off + k], out3[off + k], nullptr};

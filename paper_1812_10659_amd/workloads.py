@@ -55,6 +55,8 @@ PARAMS: Dict[str, ParamSet] = {
     "batch_n16384": ParamSet("batch_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
     # Transfer-learning head: six data primes.
     "head_n16384": ParamSet("head_n16384", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
+    # N=8192 for tests of that ring size: five data primes, log2(QP) = 180 <= 218.
+    "n8192": ParamSet("n8192", 8192, 65537, tuple(PRIMES_16384[:5]), PRIMES_16384[5]),
     # Small sets for tests (not secure; flagged).
     # (primes = 1 mod 2^15 are also = 1 mod 2N for these smaller N)
     "toy1024": ParamSet("toy1024", 1024, 12289, tuple(PRIMES_16384[:3]), PRIMES_16384[3],

@@ -1,5 +1,5 @@
 """GPU parity: every library operation against the oracle, word for word, in
-coefficient form, on the same seeded inputs (N = 1024, 4096 and 16384)."""
+coefficient form, on the same seeded inputs (N = 1024 to 16384)."""
 import numpy as np
 import pytest
 
@@ -8,7 +8,7 @@ from paper_1812_10659_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PSETS = ["toy1024", "n4096_3q", "mnist_n16384"]
+PSETS = ["toy1024", "toy2048", "n4096_3q", "n8192", "mnist_n16384"]
 STEPS = [1, -1, 7, bfv.ROW_SWAP]
 SEED = 0x5EED_0001
 
