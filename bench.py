@@ -30,13 +30,14 @@ BFLY_OPS = 9                                # VALU ops of one lazy Harvey butter
 MAC_OPS = 7                                 # Montgomery product + modular add
 
 
-# HBM bytes per job of the key-switch inner kernel on this workload (batch 64,
-# 8 key sets), from rocprofv3 FETCH_SIZE and WRITE_SIZE over the batched
-# launches, each scaled by that counter's reading for a 1 GiB device copy
-# (FETCH_SIZE read 0.5 GiB: x2.0; WRITE_SIZE read 1 GiB: x1.0).  Valid only
-# for kernel sources with this digest; otherwise the traffic is reported null.
-KS_INNER_TRAFFIC = {"digest": "f5b8cbc38be61913", "fetch_per_job": 4.8758e6, "write_per_job": 1.0486e6}
-KS_INNER_SOURCES = ["keyswitch.hip", "ntt_core.hpp", "modarith.hpp", "lola_internal.hpp"]
+# HBM-side bytes per job of the key-switch inner kernel on this workload
+# (batch 64, 8 key sets): rocprofv3 FETCH_SIZE and WRITE_SIZE summed over the
+# batched launches, each scaled by that counter's reading for a 1 GiB device
+# copy (FETCH_SIZE read 0.5 GiB: x2.0; WRITE_SIZE read 1 GiB: x1.0).  These
+# count L2 misses, so reads served by the last-level cache count too.  Valid
+# only for kernel sources with this digest; otherwise the traffic is null.
+KS_INNER_TRAFFIC = {"digest": "d4ecaadedeb645fe", "fetch_per_job": 9.1732e6, "write_per_job": 1.0486e6}
+KS_INNER_SOURCES = ["keyswitch.hip", "ks_core.hpp", "ntt_core.hpp", "modarith.hpp", "lola_internal.hpp"]
 
 
 def ks_inner_digest():
