@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-primitive run")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="mixed Poisson serving run after the timed steps (0 = skip)")
+    ap.add_argument("--serve-high-rate", type=float, default=800.0,
+                    help="arrival rate of a second serving run above what one-at-a-time can sustain (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device once (scale for HBM counters) and exit")
     args = ap.parse_args()
@@ -240,6 +242,8 @@ def main():
         del reqs, keys
         torch.cuda.empty_cache()
         out["serving"] = serving.run_serving(n_req=args.serve_requests)
+        if args.serve_high_rate > 0:
+            out["serving_high_load"] = serving.run_serving(n_req=args.serve_requests, rate=args.serve_high_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, w)
     print(json.dumps(out), flush=True)
