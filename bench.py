@@ -79,6 +79,8 @@ def main():
                     help="mixed Poisson serving run after the timed steps (0 = skip)")
     ap.add_argument("--serve-high-rate", type=float, default=800.0,
                     help="arrival rate of a second serving run above what one-at-a-time can sustain (0 = skip)")
+    ap.add_argument("--no-integer-logits", action="store_true",
+                    help="skip the run under seven plaintext moduli (exact integer logits by CRT)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device once (scale for HBM counters) and exit")
     args = ap.parse_args()
@@ -228,6 +230,12 @@ def main():
                 "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job"},
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
+    if not args.no_integer_logits:
+        del reqs, keys
+        torch.cuda.empty_cache()
+        out["integer_logits"] = integer_logits_run(w, B, C)
+        reqs, keys = None, None
+        torch.cuda.empty_cache()
     if not args.no_batched:
         # batched primitives: 512 ciphertexts, N=16384, L=8, uneven rotation chains
         from paper_1812_10659_amd import batched
@@ -239,7 +247,7 @@ def main():
         # Poisson arrivals at 200/s: 70% N=16384 MNIST-shaped, 30% N=4096 dense-64,
         # 8 resident key sets per ring size, continuous batching vs one at a time
         from paper_1812_10659_amd import serving
-        del reqs, keys
+        reqs, keys = None, None
         torch.cuda.empty_cache()
         out["serving"] = serving.run_serving(n_req=args.serve_requests)
         if args.serve_high_rate > 0:
@@ -247,6 +255,54 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, w)
     print(json.dumps(out), flush=True)
+
+
+def integer_logits_run(w, B, C, steps=3):
+    """The same network and batch under the seven plaintext moduli of the CRT
+    set: one encrypted evaluation per modulus, exact integer logits from the
+    device combination; two requests checked against the integer network."""
+    import torch
+    from paper_1812_10659_amd import crt, networks
+    from paper_1812_10659_amd import workloads as wl
+    net = crt.CrtNetwork(wl.crt_params(), networks.mnist_layers(w))
+    keys = [net.keygen(wl.key_seed(1) + 7919 * c + 3) for c in range(C)]
+    imgs = [wl.mnist_image(index=r) for r in range(B)]
+    reqs = [net.request(keys[r % C], networks.mnist_input_values(imgs[r]), wl.enc_seed(1) + r) for r in range(B)]
+    net.evaluate(reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.evaluate(reqs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    t1 = time.perf_counter()
+    got = [net.integers(keys[r % C], reqs[r]) for r in (0, B - 1)]
+    torch.cuda.synchronize()
+    dec_ms = (time.perf_counter() - t1) / 2 * 1e3
+    for r, g in zip((0, B - 1), got):
+        assert g == _plain_logits_exact(imgs[r], w), f"request {r}: integer logits differ from the network"
+    mx = max(abs(v) for g in got for v in g)
+    return {"moduli": list(net.moduli), "requests": B, "ms_per_batch": round(dt * 1e3, 3),
+            "inferences_per_s": round(B / dt, 2), "decrypt_and_combine_ms_per_request": round(dec_ms, 3),
+            "max_abs_logit_bits": round(math.log2(mx), 1) if mx else 0.0,
+            "product_of_moduli_bits": round(math.log2(math.prod(net.moduli)), 1), "checked": 2}
+
+
+def _plain_logits_exact(img, w):
+    """The network on plaintext Python integers (no reduction)."""
+    import numpy as np
+    pad = np.zeros((29, 29), dtype=object)
+    pad[:28, :28] = img
+    wc = w.conv_w.astype(object)
+    a1 = []
+    for m in range(5):
+        for y in range(13):
+            for x in range(13):
+                v = int((pad[2 * y:2 * y + 5, 2 * x:2 * x + 5] * wc[m]).sum()) + int(w.conv_b[m])
+                a1.append(v * v)
+    h = [sum(int(a) * int(b) for a, b in zip(row, a1)) + int(bb) for row, bb in zip(w.w1, w.b1)]
+    a2 = [v * v for v in h]
+    return [sum(int(a) * int(b) for a, b in zip(row, a2)) + int(bb) for row, bb in zip(w.w2, w.b2)]
 
 
 def _plain_logits_mod_t(img, w, t):

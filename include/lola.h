@@ -134,6 +134,19 @@ int lola_decode(lola_ctx *ctx, const uint32_t *pt_dev, int64_t *slots_dev, lola_
 int lola_plain_mul_form(lola_ctx *ctx, const uint32_t *pt_dev, uint32_t *out_dev, lola_stream stream);
 int lola_plain_add_form(lola_ctx *ctx, const uint32_t *pt_dev, uint32_t *out_dev, lola_stream stream);
 
+/* Exact integers from residues modulo several plaintext moduli (Chinese
+ * remainder theorem; Sec. 4.4 combines the CIFAR network's three plaintext
+ * moduli this way).  residues_dev: k device arrays of n int64 values, array i
+ * taken mod moduli[i] (e.g. decoded slots of the same network run under each
+ * t_i).  moduli: k (1..16) pairwise coprime host values in [2, 2^26).
+ * out_dev: n * words int64 (device): value j is the integer X with
+ * X = r_i mod t_i for every i and -M/2 <= X < M/2, M = prod t_i, as
+ * little-endian two's complement in `words` (1..8) 64-bit words.  Needs
+ * M < 2^(64 words), else LOLA_E_INVAL.  No context: the call only enqueues a
+ * kernel on `stream` of the current device. */
+int lola_crt_combine(const int64_t *const *residues_dev, const uint32_t *moduli, uint32_t k, uint32_t n,
+                     int64_t *out_dev, uint32_t words, lola_stream stream);
+
 /* ------------------------------------------------------ encrypt / decrypt */
 /* c = (pk0 u + e1 + floor(Q/t) m, pk1 u + e2), u ternary, e1, e2 errors drawn
  * with the seed and the object id `nonce`. */

@@ -183,9 +183,13 @@ class Context:
         return pt
 
     def decode(self, pt: torch.Tensor) -> np.ndarray:
-        s = torch.empty(self.N, dtype=torch.int64, device=self.device)
+        return self.decode_dev(pt).cpu().numpy()
+
+    def decode_dev(self, pt: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Slots of a plaintext as a device int64 tensor of N values in [0, t)."""
+        s = torch.empty(self.N, dtype=torch.int64, device=self.device) if out is None else out
         _check(lib().lola_decode(self.h, _p(pt), _p(s), _stream()))
-        return s.cpu().numpy()
+        return s
 
     def plain_mul_form(self, pt: torch.Tensor) -> torch.Tensor:
         out = self.empty(self.L, self.N)

@@ -65,6 +65,20 @@ PARAMS: Dict[str, ParamSet] = {
                         insecure_ok=True),
 }
 
+# Plaintext moduli for exact integer outputs of the MNIST-shaped network by
+# CRT: primes t = 1 mod 2N (N = 16384), product 2^132.7 above twice the
+# network's worst-case |logit| (2^119.6 for the seeded weights), each leaving
+# a positive noise budget after the whole network at seven data primes
+# (t = 1769473, 2424833 and larger were measured to exhaust it).
+MNIST_CRT_T = (65537, 163841, 557057, 786433, 1146881, 1179649, 1376257)
+
+
+def crt_params(base: str = "mnist_n16384", moduli=MNIST_CRT_T) -> List[ParamSet]:
+    """One parameter set per plaintext modulus, ciphertext primes of `base`."""
+    b = PARAMS[base]
+    return [dataclasses.replace(b, name=f"{base}_t{t}", t=int(t)) for t in moduli]
+
+
 MASTER_SEED = 1812106590
 
 
