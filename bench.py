@@ -230,6 +230,7 @@ def main():
                 "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job"},
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
+    out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
     if not args.no_integer_logits:
         del reqs, keys
         torch.cuda.empty_cache()
@@ -255,6 +256,73 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, w)
     print(json.dumps(out), flush=True)
+
+
+def small_network_run(ctx, B, C, latency_runs, steps=5):
+    """The small variant (convolution, square, dense 845 -> 10; 18 rotations,
+    one square) on the same context: batch throughput and one-request
+    latency; two requests checked against the plaintext network mod t."""
+    import numpy as np
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import workloads as wl
+    w = wl.mnist_small_weights()
+    p = wl.PARAMS["mnist_n16384"]
+    plan = lola.Plan(p, networks.mnist_small_layers(w))
+    plan.load(ctx)
+    keys = []
+    for c in range(C):
+        ks = wl.key_seed(1) + 7919 * c + 1
+        sk = ctx.keygen_secret(ks)
+        keys.append(dict(sk=sk, pk=ctx.keygen_public(ks, sk), rlk=ctx.keygen_switch(ks, sk, 0),
+                         gks=[ctx.keygen_switch(ks, sk, g) for g in plan.galois()]))
+    imap, imgs, reqs = plan.input_map(), [], []
+    for r in range(B):
+        img = wl.mnist_image(index=r)
+        imgs.append(img)
+        k = keys[r % C]
+        msgs = networks.pack_inputs(imap, networks.mnist_input_values(img))
+        reqs.append(dict(rlk=k["rlk"], gks=k["gks"],
+                         inputs=[ctx.encrypt(k["pk"], ctx.encode(m), wl.enc_seed(1) + 100 + r, i) for i, m in enumerate(msgs)],
+                         outputs=[ctx.empty_ct()]))
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    for r in (0, B - 1):
+        got = networks.unpack_outputs(plan.output_map(), np.stack([ctx.decode(ctx.decrypt(keys[r % C]["sk"], reqs[r]["outputs"][0]))]))
+        exp = [(int(v) % p.t) for v in _plain_small_logits(imgs[r], w)]
+        assert [int(v) for v in got] == exp, f"small network request {r} differs"
+    lat = []
+    one = [reqs[0]]
+    s = torch.cuda.current_stream()
+    for _ in range(latency_runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        plan.evaluate(ctx, one)
+        e1.record(s)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    return {"layers": "conv5x5s2x5 -> sq -> fc845x10", "rotations": plan.info["n_rotations"],
+            "batch_requests": B, "inferences_per_s": round(B / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+            "latency_p50_ms": round(float(np.percentile(lat, 50)), 3), "paper_latency_s": 0.29, "checked": 2}
+
+
+def _plain_small_logits(img, w):
+    """The small network on plaintext Python integers."""
+    import numpy as np
+    pad = np.zeros((29, 29), dtype=object)
+    pad[:28, :28] = img
+    a1 = []
+    for m in range(5):
+        for y in range(13):
+            for x in range(13):
+                v = int((pad[2 * y:2 * y + 5, 2 * x:2 * x + 5] * w.conv_w[m].astype(object)).sum()) + int(w.conv_b[m])
+                a1.append(v * v)
+    return [sum(int(a) * int(b) for a, b in zip(row, a1)) + int(bb) for row, bb in zip(w.w, w.b)]
 
 
 def integer_logits_run(w, B, C, steps=3):

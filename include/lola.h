@@ -248,9 +248,12 @@ int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uin
  *       (k*k messages), maps combined by rotations, stacked-row-major dense
  *       producing an interleaved vector, interleaved-row-major output layer
  *       (one message per output, value at slot 0);
+ *   CONV2D, SQUARE, DENSE   (the small variant of Sec. 4.3) the same front
+ *       end, then one stacked-row-major round as the output layer (out_dim <=
+ *       N / period): one message, output o at slot period*o;
  *   DENSE [, SQUARE]   with in_dim <= N/4: stacked input (period = next power
  *       of two >= in_dim), one row per block, output j at slot period*j;
- *   DENSE, SQUARE, DENSE   with N/4 < in_dim <= N/2: dense-row-major with
+ *   DENSE, SQUARE, DENSE   with in_dim <= N/2: dense-row-major with
  *       N/period queries per message (query q in the block at period*q),
  *       hidden units masked and combined into an interleaved vector, then
  *       one message per output with query q's value at slot period*q.

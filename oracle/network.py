@@ -77,6 +77,20 @@ def mnist_plain(img, wts):
     return wts.w2.astype(object).dot(a2) + wts.b2.astype(object)
 
 
+def mnist_small_plain(img, wts):
+    """Exact integer logits of the small variant: convolution -> square ->
+    dense 845 -> 10."""
+    p = mnist_padded(img).astype(object)
+    a1 = []
+    for m in range(5):
+        for y in range(MNIST_OUT):
+            for x in range(MNIST_OUT):
+                v = int((p[2 * y:2 * y + 5, 2 * x:2 * x + 5] * wts.conv_w[m].astype(object)).sum()) + int(wts.conv_b[m])
+                a1.append(v * v)
+    a1 = np.array(a1, dtype=object)
+    return wts.w.astype(object).dot(a1) + wts.b.astype(object)
+
+
 def head_plain(f, wts):
     """Exact integer logits of the 4096 -> 256 -> square -> 10 head."""
     h = wts.w1.astype(object).dot(np.asarray(f, dtype=object)) + wts.b1.astype(object)
@@ -257,6 +271,35 @@ def mnist_schedule(wts, N: int = 16384) -> Schedule:
         z = b.emit("add_plain", b.reg(), z, {0: int(wts.b2[o])})
         outs.append(z)
     return Schedule(N, 25, b.ops, outs, [{0: f"logit{o}"} for o in range(10)])
+
+
+def mnist_small_schedule(wts, N: int = 16384) -> Schedule:
+    """LoLa-Small (Sec. 4.3: a convolution layer, the square activation and one
+    dense layer), laid out like the first half of `mnist_schedule`:
+      conv, combine (tree over 169, 338, 676), square, stack 16 copies at
+      stride 1024;
+      dense:   one round of stacked vector - row major: the product with row o
+               in block o (o < 10), rotate-and-sum 1..512, bias added at slot
+               1024 o -> logit o at slot 1024 o of the one output message."""
+    assert N == 16384
+    b = _Builder(N, 25)
+    maps = []
+    for m in range(5):
+        acc = None
+        for a in range(5):
+            for c in range(5):
+                t = b.emit("mul_scalar", b.reg(), 5 * a + c, int(wts.conv_w[m, a, c]))
+                acc = t if acc is None else b.emit("add", b.reg(), acc, t)
+        acc = b.emit("add_plain", b.reg(), acc, {s: int(wts.conv_b[m]) for s in range(169)})
+        maps.append(acc)
+    y = _combine_tree(b, maps, 169)
+    y = b.emit("square", b.reg(), y)
+    s = _rotate_and_sum(b, y, [-1024, -2048, -4096, ROW_SWAP])
+    rows = {1024 * o + i: int(wts.w[o, i]) for o in range(10) for i in range(845)}
+    z = b.emit("mul_plain", b.reg(), s, rows)
+    z = _rotate_and_sum(b, z, [1 << k for k in range(10)])
+    z = b.emit("add_plain", b.reg(), z, {1024 * o: int(wts.b[o]) for o in range(10)})
+    return Schedule(N, 25, b.ops, [z], [{1024 * o: f"logit{o}" for o in range(10)}])
 
 
 # Transfer-learning head (N = 16384, 4 queries per ciphertext, query q in the

@@ -15,7 +15,9 @@
 //     over -P, -2P, ..., -N/4 and the row swap; each round multiplies by rows
 //     laid out one per block, sums each block by rotations 1..P/2, keeps the
 //     block's first slot (mask) and adds the bias; rounds are then combined
-//     into an interleaved vector (value C*rho + c at slot P*c + rho);
+//     into an interleaved vector (value C*rho + c at slot P*c + rho); as the
+//     last layer (convolution, square, dense) a single round without mask
+//     is the output, value o at slot P*o;
 //   interleaved vector - row major (Sec. 4.2.2): per output, a product with
 //     the row permuted to the interleaved layout and a rotate-and-sum that
 //     collects every occupied slot into slot 0 (sparse output);
@@ -137,11 +139,12 @@ int64_t bias_at(const lola_layer &l, int j) { return l.bias ? l.bias[j] : 0; }
 
 // ---- network families -------------------------------------------------
 int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
-    // CONV2D, SQUARE, DENSE, SQUARE, DENSE
-    if (n != 5 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE ||
-        ls[3].kind != LOLA_LAYER_SQUARE || ls[4].kind != LOLA_LAYER_DENSE)
-        return unsupported("convolution networks must be CONV2D, SQUARE, DENSE, SQUARE, DENSE");
-    const lola_layer &cv = ls[0], &d1 = ls[2], &d2 = ls[4];
+    // CONV2D, SQUARE, DENSE [, SQUARE, DENSE]
+    const bool small = n == 3;
+    if ((n != 5 && n != 3) || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE ||
+        (!small && (ls[3].kind != LOLA_LAYER_SQUARE || ls[4].kind != LOLA_LAYER_DENSE)))
+        return unsupported("convolution networks must be CONV2D, SQUARE, DENSE [, SQUARE, DENSE]");
+    const lola_layer &cv = ls[0], &d1 = ls[2], &d2 = ls[small ? 2 : 4];
     const uint32_t N = p->N;
     if (cv.in_h != cv.in_w || cv.k <= 0 || cv.stride <= 0 || cv.maps <= 0 || cv.in_h < cv.k || !cv.weight)
         return unsupported("bad convolution shape");
@@ -154,8 +157,10 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
     if (P > N / 2) return unsupported("dense input too long to stack");
     const uint32_t C = N / P;
     const uint32_t R = ((uint32_t)d1.out_dim + C - 1) / C;
+    if (small && R != 1) return unsupported("a final dense layer after the convolution needs out_dim <= N / next_pow2(in_dim)");
     if (R > P) return unsupported("too many stacked rounds for the interleaved layout");
-    if (d2.in_dim != d1.out_dim || !d2.weight || d2.out_dim <= 0) return unsupported("second dense layer shape");
+    if (!small && (d2.in_dim != d1.out_dim || !d2.weight || d2.out_dim <= 0))
+        return unsupported("second dense layer shape");
     // inputs: convolution representation
     p->n_inputs = (uint32_t)K2;
     p->queries = 1;
@@ -190,6 +195,22 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
     const int S = b.rotate_and_sum(y, st);
     std::vector<int32_t> blk;
     for (uint32_t s = 1; s < P; s *= 2) blk.push_back((int32_t)s);
+    if (small) {
+        // one stacked round is the output layer: row o in block o, result o
+        // at slot P*o of the single output message
+        auto rows = b.zeros(), bias = b.zeros();
+        for (int o = 0; o < d1.out_dim; ++o) {
+            for (int i = 0; i < D; ++i) rows[P * o + i] = d1.weight[(size_t)o * D + i];
+            bias[P * o] = bias_at(d1, o);
+        }
+        int z = b.mulplain(S, b.cst(rows, true));
+        z = b.rotate_and_sum(z, blk);
+        if (d1.bias) z = b.addplain(z, b.cst(bias, false));
+        p->outputs.push_back(z);
+        p->output_map.assign(N, -1);
+        for (int o = 0; o < d1.out_dim; ++o) p->output_map[(size_t)P * o] = o;
+        return LOLA_OK;
+    }
     std::vector<int> rounds;
     for (uint32_t rho = 0; rho < R; ++rho) {
         auto rows = b.zeros(), mask = b.zeros(), bias = b.zeros();

@@ -19,6 +19,11 @@ def mnist_layers(w: wl.MnistWeights):
             lola.dense(w.w1, w.b1), lola.square(), lola.dense(w.w2, w.b2)]
 
 
+def mnist_small_layers(w: wl.MnistSmallWeights):
+    """The small variant: convolution, square, one dense layer 845 -> 10."""
+    return [lola.conv2d(w.conv_w, w.conv_b, MNIST_PAD, 2), lola.square(), lola.dense(w.w, w.b)]
+
+
 def mnist_input_values(img) -> np.ndarray:
     p = np.zeros((MNIST_PAD, MNIST_PAD), dtype=np.int64)
     p[:28, :28] = img

@@ -148,6 +148,25 @@ def mnist_weights(seed: int | None = None) -> MnistWeights:
     return MnistWeights(conv_w, conv_b, w1, b1, w2, b2)
 
 
+@dataclasses.dataclass
+class MnistSmallWeights:
+    conv_w: np.ndarray   # [5 maps][5][5] int8 values (those of the MNIST-shaped network)
+    conv_b: np.ndarray   # [5]
+    w: np.ndarray        # [10][845] int8, input index 169*map + 13*y + x
+    b: np.ndarray        # [10]
+
+
+def mnist_small_weights(seed: int | None = None) -> MnistSmallWeights:
+    """The small variant: the MNIST-shaped network's convolution, then one
+    dense layer 845 -> 10 with its own seeded weights."""
+    s = workload_seed(1) if seed is None else seed
+    big = mnist_weights(s)
+    g = rng(s, STREAM_WEIGHTS * 10 + 1)
+    w = g.integers(-128, 128, size=(10, 845)).astype(np.int64)
+    b = g.integers(-2**15, 2**15, size=10).astype(np.int64)
+    return MnistSmallWeights(big.conv_w, big.conv_b, w, b)
+
+
 # -------------------------------------------------------------- batched primitives, N=16384
 def batch_rotation_counts(n_ct: int = 512, seed: int | None = None) -> np.ndarray:
     """Per-ciphertext rotation counts, uniform in 1..64 (uneven on purpose)."""

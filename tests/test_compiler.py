@@ -125,6 +125,20 @@ def test_compiler_mnist_matches_tables_and_network():
     assert (m[:, 169:] == -1).all()
 
 
+def test_compiler_mnist_small():
+    """The small variant (convolution, square, one dense layer): same front
+    end, one stacked round as the output layer, 18 rotations."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w, img = wl.mnist_small_weights(), wl.mnist_image(index=3)
+    p = wl.PARAMS["mnist_n16384"]
+    plan = _check_plan(lola, p, networks.mnist_small_layers(w), networks.mnist_input_values(img),
+                       nw.mnist_small_plain(img, w), nw.mnist_small_schedule(w))
+    info = plan.info
+    assert info["n_outputs"] == 1 and info["n_rotations"] == 18 and info["n_square"] == 1
+    assert [int(v) for v in np.nonzero(plan.output_map()[0] >= 0)[0]] == [1024 * o for o in range(10)]
+
+
 @pytest.mark.parametrize("n_hidden", [8, 256])
 def test_compiler_head(n_hidden):
     lola = _lola()

@@ -81,6 +81,16 @@ def test_mnist_network_matches_oracle():
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
 
 
+def test_mnist_small_network_matches_oracle():
+    from paper_1812_10659_amd import networks
+    w, img = wl.mnist_small_weights(), wl.mnist_image(index=3)
+    print("[gpu-net] mnist small", flush=True)
+    sched = nw.mnist_small_schedule(w)
+    env = _setup("mnist_n16384", networks.mnist_small_layers(w), sched, networks.mnist_input_values(img),
+                 wl.key_seed(1) + 5, wl.enc_seed(1) + 5)
+    _run_and_compare(env, sched, nw.mnist_small_plain(img, w))
+
+
 def test_head_network_truncated_matches_oracle():
     from paper_1812_10659_amd import networks
     w, f = wl.head_weights(), wl.head_features(4)
