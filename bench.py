@@ -231,6 +231,7 @@ def main():
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
     out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
+    out["mnist_dense_input"] = dense_input_run(B, C, args.latency_runs)
     if not args.no_integer_logits:
         del reqs, keys
         torch.cuda.empty_cache()
@@ -309,6 +310,61 @@ def small_network_run(ctx, B, C, latency_runs, steps=5):
     return {"layers": "conv5x5s2x5 -> sq -> fc845x10", "rotations": plan.info["n_rotations"],
             "batch_requests": B, "inferences_per_s": round(B / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
             "latency_p50_ms": round(float(np.percentile(lat, 50)), 3), "paper_latency_s": 0.29, "checked": 2}
+
+
+def dense_input_run(B, C, latency_runs, steps=3):
+    """LoLa-Dense: the same network with the image sent as one dense message
+    (25 masks and 24 more rotations build the convolution messages; 256
+    rotations, eight data primes).  Batch throughput and one-request latency;
+    two requests checked against the plaintext network mod t."""
+    import numpy as np
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import workloads as wl
+    p = wl.PARAMS["mnist_dense_n16384"]
+    w = wl.mnist_weights()
+    ctx = lola.Context(p)
+    plan = lola.Plan(p, networks.mnist_dense_layers(w))
+    plan.load(ctx)
+    keys = []
+    for c in range(C):
+        ks = wl.key_seed(1) + 7919 * c + 2
+        sk = ctx.keygen_secret(ks)
+        keys.append(dict(sk=sk, pk=ctx.keygen_public(ks, sk), rlk=ctx.keygen_switch(ks, sk, 0),
+                         gks=[ctx.keygen_switch(ks, sk, g) for g in plan.galois()]))
+    imap, imgs, reqs = plan.input_map(), [], []
+    for r in range(B):
+        img = wl.mnist_image(index=r)
+        imgs.append(img)
+        k = keys[r % C]
+        msgs = networks.pack_inputs(imap, networks.mnist_input_values(img))
+        reqs.append(dict(rlk=k["rlk"], gks=k["gks"],
+                         inputs=[ctx.encrypt(k["pk"], ctx.encode(m), wl.enc_seed(1) + 200 + r, i) for i, m in enumerate(msgs)],
+                         outputs=[ctx.empty_ct() for _ in range(plan.info["n_outputs"])]))
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    for r in (0, B - 1):
+        slots = np.stack([ctx.decode(ctx.decrypt(keys[r % C]["sk"], o)) for o in reqs[r]["outputs"]])
+        got = networks.unpack_outputs(plan.output_map(), slots)
+        assert [int(v) for v in got] == [int(v) for v in _plain_logits_mod_t(imgs[r], w, p.t)], f"dense-input request {r} differs"
+    lat = []
+    s = torch.cuda.current_stream()
+    for _ in range(latency_runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        plan.evaluate(ctx, reqs[:1])
+        e1.record(s)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    return {"input": "one dense message (padded 29x29 image)", "data_primes": p.L,
+            "rotations": plan.info["n_rotations"], "batch_requests": B,
+            "inferences_per_s": round(B / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+            "latency_p50_ms": round(float(np.percentile(lat, 50)), 3), "paper_latency_s": 7.2, "checked": 2}
 
 
 def _plain_small_logits(img, w):

@@ -248,6 +248,12 @@ int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uin
  *       (k*k messages), maps combined by rotations, stacked-row-major dense
  *       producing an interleaved vector, interleaved-row-major output layer
  *       (one message per output, value at slot 0);
+ *   CONV2D_DENSE_INPUT, SQUARE, DENSE, SQUARE, DENSE   (LoLa-Dense, App. C)
+ *       the input is one dense message (padded pixel (i, j) at slot
+ *       i*in_w + j); the k*k convolution messages are made from it by
+ *       rotations and one 0/1 mask of the window corners; stride 2 only;
+ *       maps are combined into the four parity classes of the corner lattice
+ *       (and bands below), then stacked as above;
  *   CONV2D, SQUARE, DENSE   (the small variant of Sec. 4.3) the same front
  *       end, then one stacked-row-major round as the output layer (out_dim <=
  *       N / period): one message, output o at slot period*o;
@@ -258,10 +264,10 @@ int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uin
  *       hidden units masked and combined into an interleaved vector, then
  *       one message per output with query q's value at slot period*q.
  * Weights and biases are integers, used modulo t. */
-enum { LOLA_LAYER_CONV2D = 1, LOLA_LAYER_DENSE = 2, LOLA_LAYER_SQUARE = 3 };
+enum { LOLA_LAYER_CONV2D = 1, LOLA_LAYER_DENSE = 2, LOLA_LAYER_SQUARE = 3, LOLA_LAYER_CONV2D_DENSE_INPUT = 4 };
 typedef struct {
     int32_t kind;
-    int32_t in_h, in_w;        /* CONV2D: input size as the client pads it (square) */
+    int32_t in_h, in_w;        /* CONV2D*: input size as the client pads it (square) */
     int32_t k, stride, maps;   /* CONV2D: window, stride, output maps */
     int32_t in_dim, out_dim;   /* DENSE */
     const int64_t *weight;     /* host; CONV2D [maps][k][k], DENSE [out_dim][in_dim] */

@@ -302,6 +302,98 @@ def mnist_small_schedule(wts, N: int = 16384) -> Schedule:
     return Schedule(N, 25, b.ops, [z], [{1024 * o: f"logit{o}" for o in range(10)}])
 
 
+# LoLa-Dense (App. C): the image arrives as one dense message and the
+# convolution representation is built from it with masks and rotations.
+MNIST_DENSE_OFFSETS = (0, 1, 29, 30, 754)   # placement of map m after the convolution
+MNIST_DENSE_BLOCK = 2048                    # stacking period: 754 + 720 < 2048
+
+
+def mnist_dense_inputs(img, N=16384):
+    """Dense representation: the zero-padded 29 x 29 image row by row, padded
+    pixel (i, j) at slot 29 i + j."""
+    p = mnist_padded(img)
+    return [{29 * i + j: int(p[i, j]) for i in range(29) for j in range(29) if p[i, j]}]
+
+
+def mnist_dense_schedule(wts, N: int = 16384) -> Schedule:
+    """LoLa-Dense (App. C, Table 3) for N = 16384:
+      masks:   message (a, b) = the input rotated left by 29 a + b (so padded
+               pixel (2y + a, 2x + b) sits at slot 58 y + 2 x) times the 0/1
+               mask of the window corners {58 y + 2 x : y, x < 13}; 24
+               rotations and 25 products;
+      conv:    per map, sum_{a,b} w[m,a,b] * message(a,b) + bias at the corners;
+      combine: map m rotated right by (0, 1, 29, 30, 754)[m] and added, so the
+               845 values occupy distinct slots below 2048 (4 rotations);
+      square;
+      stack:   8 copies at stride 2048 (rotations right 2048, 4096, row swap);
+      dense1:  13 rounds of stacked vector - row major: block c holds row
+               8 rho + c laid out on the combined positions, rotate-and-sum
+               1..1024, mask slot 2048 c, add bias;
+      combine: round rho rotated right by rho (tree over 1, 2, 4, 8) -> value
+               8 rho + c at slot 2048 c + rho;
+      square;
+      dense2:  interleaved vector - row major: per output, rotate-and-sum over
+               1, 2, 4, 8, 2048, 4096 and the row swap -> logit at slot 0."""
+    assert N == 16384
+    P, C = MNIST_DENSE_BLOCK, N // MNIST_DENSE_BLOCK
+    R = (100 + C - 1) // C
+    b = _Builder(N, 1)
+    corners = {58 * y + 2 * x: 1 for y in range(MNIST_OUT) for x in range(MNIST_OUT)}
+    msgs = []
+    for a in range(5):
+        for c in range(5):
+            r = 29 * a + c
+            src = 0 if r == 0 else b.emit("rotate", b.reg(), 0, r)
+            msgs.append(b.emit("mul_plain", b.reg(), src, corners))
+    maps = []
+    for m in range(5):
+        acc = None
+        for k in range(25):
+            t = b.emit("mul_scalar", b.reg(), msgs[k], int(wts.conv_w[m, k // 5, k % 5]))
+            acc = t if acc is None else b.emit("add", b.reg(), acc, t)
+        acc = b.emit("add_plain", b.reg(), acc, {s: int(wts.conv_b[m]) for s in corners})
+        maps.append(acc)
+    y = maps[0]
+    for m in range(1, 5):
+        r = b.emit("rotate", b.reg(), maps[m], -MNIST_DENSE_OFFSETS[m])
+        y = b.emit("add", b.reg(), y, r)
+    y = b.emit("square", b.reg(), y)
+    s = _rotate_and_sum(b, y, [-2048, -4096, ROW_SWAP])
+    pos = [MNIST_DENSE_OFFSETS[m] + 58 * yy + 2 * xx
+           for m in range(5) for yy in range(MNIST_OUT) for xx in range(MNIST_OUT)]
+    rounds = []
+    for rho in range(R):
+        rows, mask, bias = {}, {}, {}
+        for c in range(C):
+            j = C * rho + c
+            if j >= 100:
+                continue
+            for i in range(845):
+                rows[P * c + pos[i]] = int(wts.w1[j, i])
+            mask[P * c] = 1
+            bias[P * c] = int(wts.b1[j])
+        z = b.emit("mul_plain", b.reg(), s, rows)
+        z = _rotate_and_sum(b, z, [1 << k for k in range(11)])
+        z = b.emit("mul_plain", b.reg(), z, mask)
+        z = b.emit("add_plain", b.reg(), z, bias)
+        rounds.append(z)
+    h = _combine_tree(b, rounds, 1)
+    h = b.emit("square", b.reg(), h)
+    outs = []
+    for o in range(10):
+        rows = {}
+        for rho in range(R):
+            for c in range(C):
+                j = C * rho + c
+                if j < 100:
+                    rows[P * c + rho] = int(wts.w2[o, j])
+        z = b.emit("mul_plain", b.reg(), h, rows)
+        z = _rotate_and_sum(b, z, [1, 2, 4, 8, 2048, 4096, ROW_SWAP])
+        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b2[o])})
+        outs.append(z)
+    return Schedule(N, 1, b.ops, outs, [{0: f"logit{o}"} for o in range(10)])
+
+
 # Transfer-learning head (N = 16384, 4 queries per ciphertext, query q in the
 # 4096-slot block starting at slot 4096 q).
 HEAD_BLOCK = 4096

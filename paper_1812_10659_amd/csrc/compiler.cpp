@@ -103,6 +103,16 @@ struct Builder {
         p->ops.push_back(o);
         return o.dst;
     }
+    int rot(int src, int32_t step) {
+        Op o;
+        o.kind = OP_ROT;
+        o.dst = reg();
+        o.src = src;
+        o.step = step;
+        o.galois = lola_galois_element(p->N, step);
+        p->ops.push_back(o);
+        return o.dst;
+    }
     int square(int src) {
         Op o;
         o.kind = OP_SQUARE;
@@ -139,8 +149,9 @@ int64_t bias_at(const lola_layer &l, int j) { return l.bias ? l.bias[j] : 0; }
 
 // ---- network families -------------------------------------------------
 int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
-    // CONV2D, SQUARE, DENSE [, SQUARE, DENSE]
+    // CONV2D (or CONV2D_DENSE_INPUT), SQUARE, DENSE [, SQUARE, DENSE]
     const bool small = n == 3;
+    const bool dense_in = ls[0].kind == LOLA_LAYER_CONV2D_DENSE_INPUT;
     if ((n != 5 && n != 3) || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE ||
         (!small && (ls[3].kind != LOLA_LAYER_SQUARE || ls[4].kind != LOLA_LAYER_DENSE)))
         return unsupported("convolution networks must be CONV2D, SQUARE, DENSE [, SQUARE, DENSE]");
@@ -153,7 +164,31 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
     if ((uint32_t)(cv.maps * V) > N / 2) return unsupported("convolution output exceeds one slot row");
     const int D = cv.maps * V;
     if (d1.in_dim != D || !d1.weight || d1.out_dim <= 0) return unsupported("first dense layer must take maps*n*n inputs");
-    const uint32_t P = next_pow2((uint32_t)D);
+    // slot of the first dense layer's input i = m*V + y*n_out + x after the
+    // convolution and the combination of the maps
+    std::vector<uint32_t> pos((size_t)D);
+    uint32_t span = (uint32_t)D;
+    std::vector<uint32_t> offs;
+    if (dense_in) {
+        // window corners at stride*(y*W + x); maps go to the four parity
+        // classes of that lattice (stride 2), further ones to bands below
+        if (cv.stride != 2 || small) return unsupported("dense-input convolution: stride 2, five-layer network");
+        const uint32_t W = (uint32_t)cv.in_w, band = W * (uint32_t)(2 * n_out);
+        const uint32_t cls[4] = {0, 1, W, W + 1};
+        for (int m = 0; m < cv.maps; ++m) offs.push_back(cls[m % 4] + band * (uint32_t)(m / 4));
+        span = 0;
+        for (int m = 0; m < cv.maps; ++m)
+            for (int yy = 0; yy < n_out; ++yy)
+                for (int xx = 0; xx < n_out; ++xx) {
+                    const uint32_t sl = offs[m] + 2 * (uint32_t)yy * W + 2 * (uint32_t)xx;
+                    pos[(size_t)m * V + yy * n_out + xx] = sl;
+                    span = std::max(span, sl + 1);
+                }
+        if (span > N / 2) return unsupported("dense-input convolution output exceeds one slot row");
+    } else {
+        for (int i = 0; i < D; ++i) pos[i] = (uint32_t)i;
+    }
+    const uint32_t P = next_pow2(span);
     if (P > N / 2) return unsupported("dense input too long to stack");
     const uint32_t C = N / P;
     const uint32_t R = ((uint32_t)d1.out_dim + C - 1) / C;
@@ -161,32 +196,66 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
     if (R > P) return unsupported("too many stacked rounds for the interleaved layout");
     if (!small && (d2.in_dim != d1.out_dim || !d2.weight || d2.out_dim <= 0))
         return unsupported("second dense layer shape");
-    // inputs: convolution representation
-    p->n_inputs = (uint32_t)K2;
-    p->queries = 1;
-    p->n_regs = p->n_inputs;
-    p->input_map.assign((size_t)K2 * N, -1);
-    for (int a = 0; a < cv.k; ++a)
-        for (int c = 0; c < cv.k; ++c)
-            for (int y = 0; y < n_out; ++y)
-                for (int x = 0; x < n_out; ++x)
-                    p->input_map[(size_t)(a * cv.k + c) * N + y * n_out + x] =
-                        (cv.stride * y + a) * cv.in_w + (cv.stride * x + c);
-    // convolution: one linear combination per map (+ bias at slots 0..V-1)
-    std::vector<int> maps;
     std::vector<int> ins(K2);
-    for (int i = 0; i < K2; ++i) ins[i] = i;
+    std::vector<uint32_t> corner((size_t)V);   // slot of window (y, x) in the conv messages
+    if (dense_in) {
+        // input: one dense message, padded pixel (i, j) at slot i*W + j
+        // (App. C); message (a, b) of the convolution representation is the
+        // input rotated left by a*W + b, times the 0/1 mask of the corners
+        const uint32_t W = (uint32_t)cv.in_w;
+        if ((uint32_t)(cv.in_h * cv.in_w) > N / 2) return unsupported("dense input longer than a slot row");
+        p->n_inputs = 1;
+        p->queries = 1;
+        p->n_regs = 1;
+        p->input_map.assign(N, -1);
+        for (int i = 0; i < cv.in_h; ++i)
+            for (int j = 0; j < cv.in_w; ++j) p->input_map[(size_t)i * W + j] = i * cv.in_w + j;
+        auto mask = b.zeros();
+        for (int yy = 0; yy < n_out; ++yy)
+            for (int xx = 0; xx < n_out; ++xx) {
+                corner[yy * n_out + xx] = 2 * (uint32_t)yy * W + 2 * (uint32_t)xx;
+                mask[corner[yy * n_out + xx]] = 1;
+            }
+        const int cm = b.cst(mask, true);
+        for (int a = 0; a < cv.k; ++a)
+            for (int c = 0; c < cv.k; ++c) {
+                const int32_t r = a * (int32_t)W + c;
+                ins[a * cv.k + c] = b.mulplain(r ? b.rot(0, r) : 0, cm);
+            }
+    } else {
+        // inputs: convolution representation
+        p->n_inputs = (uint32_t)K2;
+        p->queries = 1;
+        p->n_regs = p->n_inputs;
+        p->input_map.assign((size_t)K2 * N, -1);
+        for (int a = 0; a < cv.k; ++a)
+            for (int c = 0; c < cv.k; ++c)
+                for (int y = 0; y < n_out; ++y)
+                    for (int x = 0; x < n_out; ++x)
+                        p->input_map[(size_t)(a * cv.k + c) * N + y * n_out + x] =
+                            (cv.stride * y + a) * cv.in_w + (cv.stride * x + c);
+        for (int i = 0; i < K2; ++i) ins[i] = i;
+        for (int v = 0; v < V; ++v) corner[v] = (uint32_t)v;
+    }
+    // convolution: one linear combination per map (+ bias at the window slots)
+    std::vector<int> maps;
     for (int m = 0; m < cv.maps; ++m) {
         std::vector<int64_t> w(cv.weight + (size_t)m * K2, cv.weight + (size_t)(m + 1) * K2);
         int cadd = -1;
         if (cv.bias) {
             auto v = b.zeros();
-            for (int s = 0; s < V; ++s) v[s] = cv.bias[m];
+            for (int s = 0; s < V; ++s) v[corner[s]] = cv.bias[m];
             cadd = b.cst(v, false);
         }
         maps.push_back(b.lincomb(ins, w, cadd));
     }
-    int y = b.combine_tree(maps, V);
+    int y;
+    if (dense_in) {
+        y = maps[0];
+        for (int m = 1; m < cv.maps; ++m) y = b.rotadd(maps[m], -(int32_t)offs[m], y);
+    } else {
+        y = b.combine_tree(maps, V);
+    }
     y = b.square(y);
     // stack C copies at stride P
     std::vector<int32_t> st;
@@ -200,7 +269,7 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
         // at slot P*o of the single output message
         auto rows = b.zeros(), bias = b.zeros();
         for (int o = 0; o < d1.out_dim; ++o) {
-            for (int i = 0; i < D; ++i) rows[P * o + i] = d1.weight[(size_t)o * D + i];
+            for (int i = 0; i < D; ++i) rows[P * o + pos[i]] = d1.weight[(size_t)o * D + i];
             bias[P * o] = bias_at(d1, o);
         }
         int z = b.mulplain(S, b.cst(rows, true));
@@ -217,7 +286,7 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
         for (uint32_t c = 0; c < C; ++c) {
             const uint32_t j = C * rho + c;
             if (j >= (uint32_t)d1.out_dim) continue;
-            for (int i = 0; i < D; ++i) rows[P * c + i] = d1.weight[(size_t)j * D + i];
+            for (int i = 0; i < D; ++i) rows[P * c + pos[i]] = d1.weight[(size_t)j * D + i];
             mask[P * c] = 1;
             bias[P * c] = bias_at(d1, (int)j);
         }
@@ -421,7 +490,7 @@ int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_la
     Builder b{p};
     int rc;
     const lola_layer &l0 = layers[0];
-    if (l0.kind == LOLA_LAYER_CONV2D) {
+    if (l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) {
         rc = compile_conv_net(p, b, layers, n_layers);
     } else if (l0.kind == LOLA_LAYER_DENSE && l0.weight && l0.in_dim > 0 && l0.out_dim > 0) {
         if ((uint32_t)l0.in_dim > ctx->N / 2)

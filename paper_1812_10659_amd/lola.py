@@ -302,7 +302,7 @@ def from_numpy_u32(a: np.ndarray, device) -> torch.Tensor:
 
 
 # ------------------------------------------------------------- plans -----
-LAYER_CONV2D, LAYER_DENSE, LAYER_SQUARE = 1, 2, 3
+LAYER_CONV2D, LAYER_DENSE, LAYER_SQUARE, LAYER_CONV2D_DENSE_INPUT = 1, 2, 3, 4
 
 
 class Layer(ctypes.Structure):
@@ -323,9 +323,12 @@ class Request(ctypes.Structure):
                 ("in_dev", ctypes.POINTER(ctypes.c_void_p)), ("out_dev", ctypes.POINTER(ctypes.c_void_p))]
 
 
-def conv2d(weight, bias, in_hw: int, stride: int) -> dict:
+def conv2d(weight, bias, in_hw: int, stride: int, dense_input: bool = False) -> dict:
+    """dense_input: the client sends the padded image as one dense message
+    (row by row) instead of the k*k convolution-representation messages."""
     w = np.ascontiguousarray(weight, dtype=np.int64)
-    return dict(kind=LAYER_CONV2D, in_h=in_hw, in_w=in_hw, k=w.shape[1], stride=stride, maps=w.shape[0],
+    kind = LAYER_CONV2D_DENSE_INPUT if dense_input else LAYER_CONV2D
+    return dict(kind=kind, in_h=in_hw, in_w=in_hw, k=w.shape[1], stride=stride, maps=w.shape[0],
                 weight=w, bias=None if bias is None else np.ascontiguousarray(bias, dtype=np.int64))
 
 

@@ -19,6 +19,13 @@ def mnist_layers(w: wl.MnistWeights):
             lola.dense(w.w1, w.b1), lola.square(), lola.dense(w.w2, w.b2)]
 
 
+def mnist_dense_layers(w: wl.MnistWeights):
+    """LoLa-Dense: the MNIST-shaped network with the image sent as one dense
+    message (padded 29 x 29, row by row; values from mnist_input_values)."""
+    return [lola.conv2d(w.conv_w, w.conv_b, MNIST_PAD, 2, dense_input=True), lola.square(),
+            lola.dense(w.w1, w.b1), lola.square(), lola.dense(w.w2, w.b2)]
+
+
 def mnist_small_layers(w: wl.MnistSmallWeights):
     """The small variant: convolution, square, one dense layer 845 -> 10."""
     return [lola.conv2d(w.conv_w, w.conv_b, MNIST_PAD, 2), lola.square(), lola.dense(w.w, w.b)]

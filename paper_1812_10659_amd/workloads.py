@@ -53,6 +53,9 @@ PARAMS: Dict[str, ParamSet] = {
     "mnist_n16384": ParamSet("mnist_n16384", 16384, 1146881, tuple(PRIMES_16384[:7]), PRIMES_16384[7]),
     # Batched primitive microbenchmark: eight data primes.
     "batch_n16384": ParamSet("batch_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
+    # LoLa-Dense input path: the mask products at the input cost noise that
+    # seven data primes do not leave room for; eight primes, log2(QP) = 270.
+    "mnist_dense_n16384": ParamSet("mnist_dense_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
     # Transfer-learning head: six data primes.
     "head_n16384": ParamSet("head_n16384", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
     # N=8192 for tests of that ring size: five data primes, log2(QP) = 180 <= 218.

@@ -72,6 +72,9 @@ def dump_to_oracle_ops(plan):
             r = nxt; nxt += 1
             ops.append(("rotate", r, src, step))
             ops.append(("add", dst, addend, r))
+        elif f[0] == "rot":
+            step = bfv.ROW_SWAP if f[3] == "swap" else int(f[3])
+            ops.append(("rotate", int(f[1]), int(f[2]), step))
         elif f[0] == "square":
             ops.append(("square", int(f[1]), int(f[2])))
         else:
@@ -123,6 +126,22 @@ def test_compiler_mnist_matches_tables_and_network():
     m = plan.input_map()
     assert m[5 * 1 + 2, 13 * 3 + 4] == (2 * 3 + 1) * 29 + (2 * 4 + 2)
     assert (m[:, 169:] == -1).all()
+
+
+def test_compiler_mnist_dense_input():
+    """LoLa-Dense (App. C): one dense input message, 24 rotations and 25 mask
+    products build the convolution messages; 256 rotations in all."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w, img = wl.mnist_weights(), wl.mnist_image(index=2)
+    p = wl.PARAMS["mnist_dense_n16384"]
+    plan = _check_plan(lola, p, networks.mnist_dense_layers(w), networks.mnist_input_values(img),
+                       nw.mnist_plain(img, w), nw.mnist_dense_schedule(w))
+    info = plan.info
+    assert info["n_inputs"] == 1 and info["n_outputs"] == 10
+    assert info["n_rotations"] == 256 and info["n_mul_plain"] == 25 + 2 * 13 + 10
+    m = plan.input_map()
+    assert m[0, 29 * 3 + 4] == 29 * 3 + 4 and (m[0, 29 * 29:] == -1).all()
 
 
 def test_compiler_mnist_small():
