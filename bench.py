@@ -232,6 +232,7 @@ def main():
     }
     out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
     out["mnist_dense_input"] = dense_input_run(B, C, args.latency_runs)
+    out["cifar_shaped"] = cifar_run()
     if not args.no_integer_logits:
         del reqs, keys
         torch.cuda.empty_cache()
@@ -365,6 +366,74 @@ def dense_input_run(B, C, latency_runs, steps=3):
             "rotations": plan.info["n_rotations"], "batch_requests": B,
             "inferences_per_s": round(B / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
             "latency_p50_ms": round(float(np.percentile(lat, 50)), 3), "paper_latency_s": 7.2, "checked": 2}
+
+
+def cifar_run(runs=3):
+    """The collapsed CIFAR network of Sec. 4.4 (8x8x3 convolution, 83 maps;
+    square; 6x6x83 convolution, 163 maps, as dense vector - row major; square;
+    dense 4075 -> 10): 57251 rotations for one image.  Latency of one
+    encrypted image (eight data primes); decrypted logits checked against the
+    plaintext network mod t."""
+    import numpy as np
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import workloads as wl
+    p = wl.PARAMS["cifar_n16384"]
+    w = wl.cifar_weights()
+    img = wl.cifar_image(index=0)
+    t0 = time.perf_counter()
+    plan = lola.Plan(p, networks.cifar_layers(w))
+    compile_s = time.perf_counter() - t0
+    ctx = lola.Context(p)
+    plan.load(ctx)
+    ks = wl.key_seed(5)
+    sk = ctx.keygen_secret(ks)
+    pk = ctx.keygen_public(ks, sk)
+    msgs = networks.pack_inputs(plan.input_map(), networks.cifar_input_values(img))
+    req = dict(rlk=ctx.keygen_switch(ks, sk, 0), gks=[ctx.keygen_switch(ks, sk, g) for g in plan.galois()],
+               inputs=[ctx.encrypt(pk, ctx.encode(m), wl.enc_seed(5), i) for i, m in enumerate(msgs)],
+               outputs=[ctx.empty_ct() for _ in range(plan.info["n_outputs"])])
+    plan.evaluate(ctx, [req])
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(runs):
+        t1 = time.perf_counter()
+        plan.evaluate(ctx, [req])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+    slots = np.stack([ctx.decode(ctx.decrypt(sk, o)) for o in req["outputs"]])
+    got = networks.unpack_outputs(plan.output_map(), slots)
+    exp = _cifar_plain_mod_t(img, w, p.t)
+    assert [int(v) for v in got] == exp, "CIFAR-shaped logits differ from the network"
+    info = plan.info
+    return {"layers": "conv8x8x3s2x83 -> sq -> conv6x6x83s2x163 -> sq -> fc4075x10", "data_primes": p.L,
+            "rotations": info["n_rotations"], "mul_plain": info["n_mul_plain"], "squares": info["n_square"],
+            "latency_s": round(float(np.median(lat)), 4), "rotations_per_s": round(info["n_rotations"] / float(np.median(lat)), 1),
+            "compile_s": round(compile_s, 2), "paper_latency_s": 730, "checked": 1}
+
+
+def _cifar_plain_mod_t(img, w, t):
+    """The CIFAR-shaped network on plaintext integers mod t (image padded by
+    one pixel on every side)."""
+    import numpy as np
+    x = np.zeros((3, 34, 34), dtype=np.int64)
+    x[:, 1:33, 1:33] = img
+
+    def conv(x, wt, b):
+        M, C, k, _ = wt.shape
+        n = (x.shape[1] - k) // 2 + 1
+        out = np.zeros((M, n, n), dtype=np.int64)
+        for y in range(n):
+            for xx in range(n):
+                win = x[:, 2 * y:2 * y + k, 2 * xx:2 * xx + k].reshape(-1)
+                out[:, y, xx] = (wt.reshape(M, -1) % t).dot(win % t) % t
+        return (out + b[:, None, None]) % t
+
+    a1 = conv(x, w.conv1_w, w.conv1_b)
+    a1 = a1 * a1 % t
+    a2 = conv(a1, w.conv2_w, w.conv2_b)
+    a2 = (a2 * a2 % t).reshape(-1)
+    return [int(v) for v in ((w.w3 % t).dot(a2) + w.b3) % t]
 
 
 def _plain_small_logits(img, w):

@@ -254,6 +254,15 @@ int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uin
  *       rotations and one 0/1 mask of the window corners; stride 2 only;
  *       maps are combined into the four parity classes of the corner lattice
  *       (and bands below), then stacked as above;
+ *   CONV2D, SQUARE, CONV2D, SQUARE, DENSE   (the collapsed CIFAR network of
+ *       Sec. 4.4 / App. D) convolution representation of every channel
+ *       (channels*k*k messages), maps placed in blocks of n1*n1 slots (as
+ *       many per slot row as fit, both rows per message, more messages if
+ *       needed) and squared; the second convolution as dense vector - row
+ *       major: per output the products with its weights, a sum over the
+ *       whole message (rotations 1 .. N/4 and the row swap), then the one-hot
+ *       product that keeps slot j; the outputs summed into one message,
+ *       squared, and one message per logit (value at slot 0);
  *   CONV2D, SQUARE, DENSE   (the small variant of Sec. 4.3) the same front
  *       end, then one stacked-row-major round as the output layer (out_dim <=
  *       N / period): one message, output o at slot period*o;
@@ -269,8 +278,8 @@ typedef struct {
     int32_t kind;
     int32_t in_h, in_w;        /* CONV2D*: input size as the client pads it (square) */
     int32_t k, stride, maps;   /* CONV2D: window, stride, output maps */
-    int32_t in_dim, out_dim;   /* DENSE */
-    const int64_t *weight;     /* host; CONV2D [maps][k][k], DENSE [out_dim][in_dim] */
+    int32_t in_dim, out_dim;   /* DENSE; CONV2D: in_dim = input channels (0 = 1) */
+    const int64_t *weight;     /* host; CONV2D [maps][channels][k][k], DENSE [out_dim][in_dim] */
     const int64_t *bias;       /* host; [maps] or [out_dim]; NULL = none */
 } lola_layer;
 

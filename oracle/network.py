@@ -394,6 +394,147 @@ def mnist_dense_schedule(wts, N: int = 16384) -> Schedule:
     return Schedule(N, 1, b.ops, outs, [{0: f"logit{o}"} for o in range(10)])
 
 
+# CIFAR-shaped network (Sec. 4.4, App. D, collapsed form): 8x8x3 convolution
+# at stride 2 -> square -> 6xkx convolution at stride 2 over all maps -> square
+# -> dense -> 10.  The 32x32 image is zero-padded by one pixel on every side
+# (34x34), so the first convolution has 14x14 outputs (83 maps: 16268 values)
+# and the second 5x5 (163 maps: 4075 values).
+CIFAR_PAD = 34
+
+
+def cifar_padded(img):
+    img = np.asarray(img, dtype=np.int64)
+    c, h, w = img.shape
+    p = np.zeros((c, h + 2, w + 2), dtype=np.int64)
+    p[:, 1:h + 1, 1:w + 1] = img
+    return p
+
+
+def _conv_plain(x, w, b, stride):
+    """x: [C][H][H] integers (object), w: [M][C][k][k] -> [M][n][n]."""
+    C, H, _ = x.shape
+    M, _, k, _ = w.shape
+    n = (H - k) // stride + 1
+    out = np.zeros((M, n, n), dtype=object)
+    wo = w.astype(object)
+    for m in range(M):
+        for y in range(n):
+            for xx in range(n):
+                out[m, y, xx] = int((x[:, stride * y:stride * y + k, stride * xx:stride * xx + k] * wo[m]).sum()) + int(b[m])
+    return out
+
+
+def cifar_plain(padded, wts):
+    """Exact integer logits of the CIFAR-shaped network on an already padded
+    [3][H][H] input."""
+    a1 = _conv_plain(np.asarray(padded).astype(object), wts.conv1_w, wts.conv1_b, 2)
+    a1 = a1 * a1
+    a2 = _conv_plain(a1, wts.conv2_w, wts.conv2_b, 2)
+    a2 = (a2 * a2).reshape(-1)          # index 25 m + 5 y + x at full size
+    return wts.w3.astype(object).dot(a2) + wts.b3.astype(object)
+
+
+def cifar_inputs(padded):
+    """Convolution representation of the padded input for the 8x8 window at
+    stride 2: message 64 c + 8 a + b holds padded[c][2y+a][2x+b] at slot
+    n1*y + x."""
+    p = np.asarray(padded)
+    return [{i: int(v) for i, v in enumerate(m)}
+            for c in range(p.shape[0]) for m in conv_representation(p[c], 8, 2)]
+
+
+def cifar_layout(m1, n1, N):
+    """Where the first convolution's maps go after combining: map m in message
+    m // (2 R), row (m mod 2R) // R, block (m mod R) of n1*n1 slots, with R
+    maps per slot row (rotations stay inside a row)."""
+    V1 = n1 * n1
+    R = (N // 2) // V1
+    return [(m // (2 * R), (m % (2 * R)) // R * (N // 2) + (m % R) * V1) for m in range(m1)], R
+
+
+def cifar_schedule(wts, n_in: int, N: int = 16384) -> Schedule:
+    """LoLa on the CIFAR-shaped network (Sec. 4.4), for a padded input of
+    n_in x n_in pixels per channel:
+      conv1:   per map, sum over the 3*64 convolution messages (message x
+               scalar) + bias at slots 0..n1^2-1;
+      combine: within a slot row, maps as blocks of n1^2 slots (binary tree of
+               right rotations); the second row's maps brought over by the row
+               swap; 2R maps per message (R per row);
+      square   (one product per message);
+      conv2:   dense vector - row major: per output (map, y, x), the products
+               of every message with its weights at the window's slots, summed,
+               then rotate-and-sum over 1 .. N/4 and the row swap, so every
+               slot holds the output;
+      gather:  output j multiplied by the one-hot plaintext of slot j, all
+               summed into one dense message, then the biases added at once
+               (one plaintext: adding them one output at a time would give
+               the same slots but other ciphertext words, since the scaled
+               plaintext floor(Q/t) m depends on m's representative in [0, t));
+      square;
+      dense:   per logit, the product with its row, rotate-and-sum over the
+               next power of two above the hidden size -> logit at slot 0."""
+    m1, C, k1, _ = wts.conv1_w.shape
+    m2, _, k2, _ = wts.conv2_w.shape
+    n1 = (n_in - k1) // 2 + 1
+    n2 = (n1 - k2) // 2 + 1
+    V1, V2 = n1 * n1, n2 * n2
+    H = m2 * V2
+    place, R = cifar_layout(m1, n1, N)
+    G = max(g for g, _ in place) + 1
+    b = _Builder(N, C * k1 * k1)
+    maps = []
+    for m in range(m1):
+        acc = None
+        for c in range(C):
+            for a in range(k1):
+                for cc in range(k1):
+                    t = b.emit("mul_scalar", b.reg(), c * k1 * k1 + a * k1 + cc, int(wts.conv1_w[m, c, a, cc]))
+                    acc = t if acc is None else b.emit("add", b.reg(), acc, t)
+        maps.append(b.emit("add_plain", b.reg(), acc, {s: int(wts.conv1_b[m]) for s in range(V1)}))
+    msgs = []
+    for g in range(G):
+        rows = []
+        for r in range(2):
+            ms = [maps[m] for m in range(m1) if place[m][0] == g and place[m][1] // (N // 2) == r]
+            if ms:
+                rows.append(_combine_tree(b, ms, V1))
+        y = rows[0]
+        if len(rows) == 2:
+            sw = b.emit("rotate", b.reg(), rows[1], ROW_SWAP)
+            y = b.emit("add", b.reg(), y, sw)
+        msgs.append(b.emit("square", b.reg(), y))
+    full = [1 << i for i in range(int(np.log2(N // 2)))] + [ROW_SWAP]
+    gathered = None
+    for j in range(H):
+        mo, yx = divmod(j, V2)
+        y2, x2 = divmod(yx, n2)
+        z = None
+        for g in range(G):
+            row = {}
+            for m in range(m1):
+                if place[m][0] != g:
+                    continue
+                base = place[m][1]
+                for a in range(k2):
+                    for cc in range(k2):
+                        row[base + n1 * (2 * y2 + a) + 2 * x2 + cc] = int(wts.conv2_w[mo, m, a, cc])
+            t = b.emit("mul_plain", b.reg(), msgs[g], row)
+            z = t if z is None else b.emit("add", b.reg(), z, t)
+        z = _rotate_and_sum(b, z, full)
+        z = b.emit("mul_plain", b.reg(), z, {j: 1})
+        gathered = z if gathered is None else b.emit("add", b.reg(), gathered, z)
+    gathered = b.emit("add_plain", b.reg(), gathered, {j: int(wts.conv2_b[j // V2]) for j in range(H)})
+    h = b.emit("square", b.reg(), gathered)
+    steps = [1 << i for i in range(max(1, int(np.ceil(np.log2(H)))))]
+    outs = []
+    for o in range(wts.w3.shape[0]):
+        z = b.emit("mul_plain", b.reg(), h, {j: int(wts.w3[o, j]) for j in range(H)})
+        z = _rotate_and_sum(b, z, steps)
+        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b3[o])})
+        outs.append(z)
+    return Schedule(N, C * k1 * k1, b.ops, outs, [{0: f"logit{o}"} for o in range(len(outs))])
+
+
 # Transfer-learning head (N = 16384, 4 queries per ciphertext, query q in the
 # 4096-slot block starting at slot 4096 q).
 HEAD_BLOCK = 4096

@@ -126,6 +126,24 @@ struct Builder {
         for (int32_t k : steps) cur = rotadd(cur, k, cur);
         return cur;
     }
+    // sum_k w[k] * srcs[k] (+ cadd) for any number of sources: linear
+    // combinations of at most LIN_MAX sources, each later one taking the
+    // previous partial sum as its first source (weight 1)
+    int lincomb_any(const std::vector<int> &srcs, const std::vector<int64_t> &w, int cadd) {
+        size_t k = std::min<size_t>(srcs.size(), LIN_MAX);
+        int acc = lincomb(std::vector<int>(srcs.begin(), srcs.begin() + k),
+                          std::vector<int64_t>(w.begin(), w.begin() + k), cadd);
+        while (k < srcs.size()) {
+            const size_t m = std::min<size_t>(srcs.size() - k, LIN_MAX - 1);
+            std::vector<int> s2{acc};
+            std::vector<int64_t> w2{1};
+            s2.insert(s2.end(), srcs.begin() + k, srcs.begin() + k + m);
+            w2.insert(w2.end(), w.begin() + k, w.begin() + k + m);
+            acc = lincomb(s2, w2, -1);
+            k += m;
+        }
+        return acc;
+    }
     int combine_tree(std::vector<int> regs, int32_t unit) {
         int32_t stride = unit;
         while (regs.size() > 1) {
@@ -476,6 +494,119 @@ using namespace lola;
 
 extern "C" {
 
+int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
+    // CONV2D (C channels), SQUARE, CONV2D (over all maps), SQUARE, DENSE
+    if (n != 5 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_CONV2D ||
+        ls[3].kind != LOLA_LAYER_SQUARE || ls[4].kind != LOLA_LAYER_DENSE)
+        return unsupported("two-convolution networks must be CONV2D, SQUARE, CONV2D, SQUARE, DENSE");
+    const lola_layer &c1 = ls[0], &c2 = ls[2], &d = ls[4];
+    const uint32_t N = p->N;
+    const int C = c1.in_dim > 0 ? c1.in_dim : 1;
+    if (c1.in_h != c1.in_w || c1.k <= 0 || c1.stride <= 0 || c1.maps <= 0 || c1.in_h < c1.k || !c1.weight ||
+        !c2.weight || c2.k <= 0 || c2.stride <= 0 || c2.maps <= 0)
+        return unsupported("bad convolution shape");
+    const int n1 = (c1.in_h - c1.k) / c1.stride + 1, V1 = n1 * n1, K = C * c1.k * c1.k;
+    const int C2 = c2.in_dim > 0 ? c2.in_dim : 1;
+    if (c2.in_h != n1 || c2.in_w != n1 || C2 != c1.maps || n1 < c2.k)
+        return unsupported("second convolution must cover the first one's maps and outputs");
+    const int n2 = (n1 - c2.k) / c2.stride + 1, V2 = n2 * n2, H = c2.maps * V2;
+    if ((uint32_t)V1 > N / 2 || (uint32_t)H > N / 2) return unsupported("layer larger than a slot row");
+    if (d.in_dim != H || !d.weight || d.out_dim <= 0) return unsupported("dense layer must take maps2*n2*n2 inputs");
+    // inputs: convolution representation of every channel
+    p->n_inputs = (uint32_t)K;
+    p->queries = 1;
+    p->n_regs = p->n_inputs;
+    p->input_map.assign((size_t)K * N, -1);
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < c1.k; ++a)
+            for (int e = 0; e < c1.k; ++e)
+                for (int y = 0; y < n1; ++y)
+                    for (int x = 0; x < n1; ++x)
+                        p->input_map[(size_t)((c * c1.k + a) * c1.k + e) * N + y * n1 + x] =
+                            (c * c1.in_h + c1.stride * y + a) * c1.in_w + c1.stride * x + e;
+    // convolution 1: one linear combination of all K messages per map
+    std::vector<int> ins(K);
+    for (int i = 0; i < K; ++i) ins[i] = i;
+    std::vector<int> maps;
+    for (int m = 0; m < c1.maps; ++m) {
+        std::vector<int64_t> w(c1.weight + (size_t)m * K, c1.weight + (size_t)(m + 1) * K);
+        int cadd = -1;
+        if (c1.bias) {
+            auto v = b.zeros();
+            for (int s = 0; s < V1; ++s) v[s] = c1.bias[m];
+            cadd = b.cst(v, false);
+        }
+        maps.push_back(b.lincomb_any(ins, w, cadd));
+    }
+    // placement: R maps of V1 slots per slot row, 2R per message
+    const uint32_t R = (N / 2) / (uint32_t)V1;
+    const int G = (int)((c1.maps + 2 * R - 1) / (2 * R));
+    std::vector<uint32_t> base(c1.maps);
+    std::vector<int> msg(c1.maps);
+    for (int m = 0; m < c1.maps; ++m) {
+        msg[m] = m / (int)(2 * R);
+        base[m] = ((uint32_t)m % (2 * R)) / R * (N / 2) + ((uint32_t)m % R) * (uint32_t)V1;
+    }
+    std::vector<int> sq;
+    for (int g = 0; g < G; ++g) {
+        std::vector<int> rows[2];
+        for (int m = 0; m < c1.maps; ++m)
+            if (msg[m] == g) rows[base[m] / (N / 2)].push_back(maps[m]);
+        int y = b.combine_tree(rows[0], V1);
+        if (!rows[1].empty()) y = b.rotadd(b.combine_tree(rows[1], V1), LOLA_ROW_SWAP, y);
+        sq.push_back(b.square(y));
+    }
+    // convolution 2, dense vector - row major: one full-vector sum per output
+    std::vector<int32_t> full;
+    for (uint32_t s = 1; s < N / 2; s *= 2) full.push_back((int32_t)s);
+    full.push_back(LOLA_ROW_SWAP);
+    const int K2 = c2.k * c2.k;
+    std::vector<int> gathered;
+    auto bias2 = b.zeros();
+    for (int j = 0; j < H; ++j) {
+        const int mo = j / V2, y2 = (j % V2) / n2, x2 = j % n2;
+        std::vector<int> parts;
+        for (int g = 0; g < G; ++g) {
+            auto row = b.zeros();
+            for (int m = 0; m < c1.maps; ++m) {
+                if (msg[m] != g) continue;
+                for (int a = 0; a < c2.k; ++a)
+                    for (int e = 0; e < c2.k; ++e)
+                        row[base[m] + (uint32_t)(n1 * (c2.stride * y2 + a) + c2.stride * x2 + e)] =
+                            c2.weight[((size_t)mo * c1.maps + m) * K2 + a * c2.k + e];
+            }
+            parts.push_back(b.mulplain(sq[g], b.cst(row, true)));
+        }
+        int z = parts.size() == 1 ? parts[0] : b.lincomb_any(parts, std::vector<int64_t>(parts.size(), 1), -1);
+        z = b.rotate_and_sum(z, full);
+        auto onehot = b.zeros();
+        onehot[j] = 1;
+        gathered.push_back(b.mulplain(z, b.cst(onehot, true)));
+        bias2[j] = bias_at(c2, mo);
+    }
+    // the sparse outputs into one dense message (+ all biases at once)
+    int h = b.lincomb_any(gathered, std::vector<int64_t>(gathered.size(), 1), c2.bias ? b.cst(bias2, false) : -1);
+    h = b.square(h);
+    std::vector<int32_t> steps;
+    for (uint32_t s = 1; s < next_pow2((uint32_t)H); s *= 2) steps.push_back((int32_t)s);
+    if (steps.empty()) steps.push_back(1);
+    p->output_map.assign((size_t)d.out_dim * N, -1);
+    for (int o = 0; o < d.out_dim; ++o) {
+        auto row = b.zeros();
+        for (int i = 0; i < H; ++i) row[i] = d.weight[(size_t)o * H + i];
+        int z = b.mulplain(h, b.cst(row, true));
+        z = b.rotate_and_sum(z, steps);
+        if (d.bias) {
+            auto bv = b.zeros();
+            bv[0] = d.bias[o];
+            z = b.addplain(z, b.cst(bv, false));
+        }
+        p->outputs.push_back(z);
+        p->output_map[(size_t)o * N] = o;
+    }
+    return LOLA_OK;
+}
+
 int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_layers, lola_plan **out) {
     if (!prm || !layers || !out || n_layers == 0) return set_error(LOLA_E_INVAL, "null argument");
     *out = nullptr;
@@ -490,7 +621,9 @@ int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_la
     Builder b{p};
     int rc;
     const lola_layer &l0 = layers[0];
-    if (l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) {
+    if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
+        rc = compile_cifar_net(p, b, layers, n_layers);
+    } else if (l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) {
         rc = compile_conv_net(p, b, layers, n_layers);
     } else if (l0.kind == LOLA_LAYER_DENSE && l0.weight && l0.in_dim > 0 && l0.out_dim > 0) {
         if ((uint32_t)l0.in_dim > ctx->N / 2)

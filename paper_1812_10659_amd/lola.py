@@ -324,11 +324,13 @@ class Request(ctypes.Structure):
 
 
 def conv2d(weight, bias, in_hw: int, stride: int, dense_input: bool = False) -> dict:
-    """dense_input: the client sends the padded image as one dense message
-    (row by row) instead of the k*k convolution-representation messages."""
+    """weight: [maps][k][k] or [maps][channels][k][k].  dense_input: the
+    client sends the padded image as one dense message (row by row) instead of
+    the k*k convolution-representation messages."""
     w = np.ascontiguousarray(weight, dtype=np.int64)
     kind = LAYER_CONV2D_DENSE_INPUT if dense_input else LAYER_CONV2D
-    return dict(kind=kind, in_h=in_hw, in_w=in_hw, k=w.shape[1], stride=stride, maps=w.shape[0],
+    channels = w.shape[1] if w.ndim == 4 else 0
+    return dict(kind=kind, in_h=in_hw, in_w=in_hw, k=w.shape[-1], stride=stride, maps=w.shape[0], in_dim=channels,
                 weight=w, bias=None if bias is None else np.ascontiguousarray(bias, dtype=np.int64))
 
 

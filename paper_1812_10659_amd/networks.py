@@ -26,6 +26,25 @@ def mnist_dense_layers(w: wl.MnistWeights):
             lola.dense(w.w1, w.b1), lola.square(), lola.dense(w.w2, w.b2)]
 
 
+def cifar_layers(w: wl.CifarWeights, n_in: int = 34):
+    """The collapsed CIFAR network on a padded n_in x n_in input: 8x8
+    convolution over 3 channels at stride 2, square, 6x6 convolution over
+    all maps at stride 2, square, dense -> 10."""
+    n1 = (n_in - w.conv1_w.shape[-1]) // 2 + 1
+    return [lola.conv2d(w.conv1_w, w.conv1_b, n_in, 2), lola.square(),
+            lola.conv2d(w.conv2_w, w.conv2_b, n1, 2), lola.square(), lola.dense(w.w3, w.b3)]
+
+
+def cifar_input_values(img) -> np.ndarray:
+    """The [3][H][W] image zero-padded by one pixel on every side, flattened
+    channel by channel, row by row."""
+    img = np.asarray(img, dtype=np.int64)
+    c, h, w = img.shape
+    p = np.zeros((c, h + 2, w + 2), dtype=np.int64)
+    p[:, 1:h + 1, 1:w + 1] = img
+    return p.reshape(-1)
+
+
 def mnist_small_layers(w: wl.MnistSmallWeights):
     """The small variant: convolution, square, one dense layer 845 -> 10."""
     return [lola.conv2d(w.conv_w, w.conv_b, MNIST_PAD, 2), lola.square(), lola.dense(w.w, w.b)]

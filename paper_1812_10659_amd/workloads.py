@@ -56,6 +56,9 @@ PARAMS: Dict[str, ParamSet] = {
     # LoLa-Dense input path: the mask products at the input cost noise that
     # seven data primes do not leave room for; eight primes, log2(QP) = 270.
     "mnist_dense_n16384": ParamSet("mnist_dense_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
+    # CIFAR-shaped network: the same noise demand (seven primes leave no
+    # budget after the second convolution's one-hot products); eight primes.
+    "cifar_n16384": ParamSet("cifar_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
     # Transfer-learning head: six data primes.
     "head_n16384": ParamSet("head_n16384", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
     # N=8192 for tests of that ring size: five data primes, log2(QP) = 180 <= 218.
@@ -168,6 +171,39 @@ def mnist_small_weights(seed: int | None = None) -> MnistSmallWeights:
     w = g.integers(-128, 128, size=(10, 845)).astype(np.int64)
     b = g.integers(-2**15, 2**15, size=10).astype(np.int64)
     return MnistSmallWeights(big.conv_w, big.conv_b, w, b)
+
+
+# ----------------------------------------------- CIFAR-shaped network, N=16384
+@dataclasses.dataclass
+class CifarWeights:
+    conv1_w: np.ndarray   # [m1][3][8][8] int8 values
+    conv1_b: np.ndarray   # [m1]
+    conv2_w: np.ndarray   # [m2][m1][6][6] int8 values
+    conv2_b: np.ndarray   # [m2]
+    w3: np.ndarray        # [10][m2*v2] int8, input index v2*map + n2*y + x (v2 = n2^2 = 25)
+    b3: np.ndarray        # [10]
+
+
+def cifar_image(seed: int | None = None, index: int = 0) -> np.ndarray:
+    """A 3x32x32 image with uniform values 0..255."""
+    s = workload_seed(5) if seed is None else seed
+    return rng(s, STREAM_DATA * 1000 + index).integers(0, 256, size=(3, 32, 32)).astype(np.int64)
+
+
+def cifar_weights(seed: int | None = None, m1: int = 83, m2: int = 163, v2: int = 25) -> CifarWeights:
+    """The collapsed CIFAR network's shapes (8x8x3 convolution, 83 maps;
+    6x6x83 convolution, 163 maps; dense 4075 -> 10) with seeded int8
+    weights; m1 and m2 shrink the map counts and v2 (outputs per map of the
+    second convolution) the dense layer for small test cases."""
+    s = workload_seed(5) if seed is None else seed
+    g = rng(s, STREAM_WEIGHTS)
+    c1w = g.integers(-128, 128, size=(83, 3, 8, 8)).astype(np.int64)[:m1]
+    c1b = g.integers(-2**15, 2**15, size=83).astype(np.int64)[:m1]
+    c2w = g.integers(-128, 128, size=(163, 83, 6, 6)).astype(np.int64)[:m2, :m1]
+    c2b = g.integers(-2**15, 2**15, size=163).astype(np.int64)[:m2]
+    w3 = g.integers(-128, 128, size=(10, 163 * 25)).astype(np.int64)[:, :m2 * v2]
+    b3 = g.integers(-2**15, 2**15, size=10).astype(np.int64)
+    return CifarWeights(c1w, c1b, c2w, c2b, w3, b3)
 
 
 # -------------------------------------------------------------- batched primitives, N=16384

@@ -144,6 +144,40 @@ def test_compiler_mnist_dense_input():
     assert m[0, 29 * 3 + 4] == 29 * 3 + 4 and (m[0, 29 * 29:] == -1).all()
 
 
+@pytest.mark.parametrize("m1,m2,side", [(5, 3, 16), (2, 2, 20)])
+def test_compiler_cifar_shaped_small(m1, m2, side):
+    """The two-convolution recipe on reduced sizes (the full network is
+    checked on the GPU by decryption): the plan replayed by the oracle's slot
+    interpreter equals the plaintext network; counts and keys equal
+    `cifar_schedule`."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    n1 = (side + 2 - 8) // 2 + 1
+    n2 = (n1 - 6) // 2 + 1
+    w = wl.cifar_weights(m1=m1, m2=m2, v2=n2 * n2)
+    img = wl.cifar_image(index=1)[:, :side, :side]
+    pad = nw.cifar_padded(img)
+    p = wl.PARAMS["mnist_n16384"]
+    plan = _check_plan(lola, p, networks.cifar_layers(w, side + 2), networks.cifar_input_values(img),
+                       nw.cifar_plain(pad, w), nw.cifar_schedule(w, side + 2))
+    assert plan.info["n_inputs"] == 192 and plan.info["n_outputs"] == 10
+
+
+def test_compiler_cifar_full_size_counts():
+    """The full CIFAR-shaped plan: 83 maps of 14x14 fill one message (41 per
+    slot row) plus one; the second convolution's 4075 outputs take a
+    full-message sum each."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    plan = lola.Plan(wl.PARAMS["mnist_n16384"], networks.cifar_layers(wl.cifar_weights()))
+    info = plan.info
+    assert info["n_inputs"] == 192 and info["n_outputs"] == 10
+    assert info["n_square"] == 3          # two messages after the first convolution, then one
+    assert info["n_rotations"] == 81 + 4075 * 14 + 10 * 12
+    m = plan.input_map()
+    assert m[64 * 2 + 8 * 3 + 4, 14 * 5 + 6] == (2 * 34 + 2 * 5 + 3) * 34 + 2 * 6 + 4
+
+
 def test_compiler_mnist_small():
     """The small variant (convolution, square, one dense layer): same front
     end, one stacked round as the output layer, 18 rotations."""

@@ -93,6 +93,35 @@ def test_mnist_dense_input_network_matches_oracle():
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
 
 
+def test_cifar_shaped_small_matches_oracle():
+    """The two-convolution recipe on a reduced case (3x16x16 image, 5 and 3
+    maps), ciphertext words against the oracle's schedule."""
+    from paper_1812_10659_amd import networks
+    w = wl.cifar_weights(m1=5, m2=3, v2=1)
+    img = wl.cifar_image(index=2)[:, :16, :16]
+    print("[gpu-net] cifar-shaped, reduced", flush=True)
+    sched = nw.cifar_schedule(w, 18)
+    env = _setup("cifar_n16384", networks.cifar_layers(w, 18), sched, networks.cifar_input_values(img),
+                 wl.key_seed(5), wl.enc_seed(5))
+    _run_and_compare(env, sched, nw.cifar_plain(nw.cifar_padded(img), w))
+
+
+def test_cifar_shaped_full_size_decrypts_to_network():
+    """The full CIFAR-shaped network (83 and 163 maps, 57251 rotations): the
+    oracle's ciphertext run is far too slow, so the check is the decrypted
+    logits against the plaintext network mod t."""
+    import torch
+    from paper_1812_10659_amd import networks
+    w = wl.cifar_weights()
+    img = wl.cifar_image(index=0)
+    print("[gpu-net] cifar-shaped, full size", flush=True)
+    env = _setup("cifar_n16384", networks.cifar_layers(w), None, networks.cifar_input_values(img),
+                 wl.key_seed(5) + 1, wl.enc_seed(5) + 1, with_oracle=False)
+    env["plan"].evaluate(env["ctx"], [env["req"]])
+    torch.cuda.synchronize()
+    assert list(_decrypt_values(env)) == list(nw._mod(nw.cifar_plain(nw.cifar_padded(img), w), env["p"].t))
+
+
 def test_mnist_small_network_matches_oracle():
     from paper_1812_10659_amd import networks
     w, img = wl.mnist_small_weights(), wl.mnist_image(index=3)
