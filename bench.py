@@ -233,6 +233,7 @@ def main():
     out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
     out["mnist_dense_input"] = dense_input_run(B, C, args.latency_runs)
     out["cifar_shaped"] = cifar_run()
+    out["head_recipes"] = head_recipes_run()
     if not args.no_integer_logits:
         del reqs, keys
         torch.cuda.empty_cache()
@@ -366,6 +367,68 @@ def dense_input_run(B, C, latency_runs, steps=3):
             "rotations": plan.info["n_rotations"], "batch_requests": B,
             "inferences_per_s": round(B / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
             "latency_p50_ms": round(float(np.percentile(lat, 50)), 3), "paper_latency_s": 7.2, "checked": 2}
+
+
+def head_recipes_run(n_queries=64, steps=3):
+    """The transfer-learning head (4096 -> 256 -> square -> 10) under both
+    recipes the compiler prices: dense vector - row major with 4 queries per
+    message, and stacked vector - row major with one.  Measured time per query
+    for a batch of n_queries and for one query alone, beside the cost model's
+    prediction; both checked against the plaintext head mod t."""
+    import numpy as np
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import workloads as wl
+    p = wl.PARAMS["head_n16384"]
+    w = wl.head_weights()
+    feats = wl.head_features(n_queries)
+    exp = [[int(v) % p.t for v in _head_plain(feats[q], w)] for q in range(n_queries)]
+    ctx = lola.Context(p)
+    res = {}
+    for name, rec in (("dense_row_major", lola.RECIPE_DENSE_ROW_MAJOR), ("stacked_row_major", lola.RECIPE_STACKED_ROW_MAJOR)):
+        plan = lola.Plan(p, networks.head_layers(w), recipe=rec)
+        plan.load(ctx)
+        Q = plan.info["queries"]
+        ks = wl.key_seed(3) + rec
+        sk = ctx.keygen_secret(ks)
+        pk = ctx.keygen_public(ks, sk)
+        rlk, gks = ctx.keygen_switch(ks, sk, 0), [ctx.keygen_switch(ks, sk, g) for g in plan.galois()]
+        reqs = []
+        for m in range(n_queries // Q):
+            vals = feats[m * Q:(m + 1) * Q].reshape(-1)
+            msgs = networks.pack_inputs(plan.input_map(), vals)
+            reqs.append(dict(rlk=rlk, gks=gks, inputs=[ctx.encrypt(pk, ctx.encode(x), 77 + m, i) for i, x in enumerate(msgs)],
+                             outputs=[ctx.empty_ct() for _ in range(plan.info["n_outputs"])]))
+        plan.evaluate(ctx, reqs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.evaluate(ctx, reqs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        t1 = time.perf_counter()
+        plan.evaluate(ctx, reqs[:1])
+        torch.cuda.synchronize()
+        one = time.perf_counter() - t1
+        for m in (0, len(reqs) - 1):
+            slots = np.stack([ctx.decode(ctx.decrypt(sk, o)) for o in reqs[m]["outputs"]])
+            got = networks.unpack_outputs(plan.output_map(), slots).reshape(Q, -1)
+            for q in range(Q):
+                assert [int(v) for v in got[q]] == exp[m * Q + q], f"head {name}: query {m * Q + q} differs"
+        res[name] = {"queries_per_message": Q, "rotations_per_message": plan.info["n_rotations"],
+                     "batch_ms_per_query": round(dt * 1e3 / n_queries, 4),
+                     "one_message_ms": round(one * 1e3, 3),
+                     "predicted_us_per_message": round(float(plan.info["predicted_us"]), 1)}
+    res["chosen"] = {"throughput": lola.Plan(p, networks.head_layers(w), objective=lola.OBJECTIVE_THROUGHPUT).info["recipe"],
+                     "latency": lola.Plan(p, networks.head_layers(w), objective=lola.OBJECTIVE_LATENCY).info["recipe"],
+                     "codes": {"1": "dense_row_major", "2": "stacked_row_major"}}
+    res["batch_queries"] = n_queries
+    return res
+
+
+def _head_plain(f, w):
+    h = w.w1.astype(object).dot(f.astype(object)) + w.b1.astype(object)
+    return w.w2.astype(object).dot(h * h) + w.b2.astype(object)
 
 
 def cifar_run(runs=3):

@@ -268,7 +268,10 @@ int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uin
  *       N / period): one message, output o at slot period*o;
  *   DENSE [, SQUARE]   with in_dim <= N/4: stacked input (period = next power
  *       of two >= in_dim), one row per block, output j at slot period*j;
- *   DENSE, SQUARE, DENSE   with in_dim <= N/2: dense-row-major with
+ *   DENSE, SQUARE, DENSE   with in_dim <= N/2, two recipes (see
+ *       lola_compile_ex): stacked-row-major with one query per message (the
+ *       client sends N/period copies; rounds, interleaved hidden vector,
+ *       interleaved-row-major output, value at slot 0), or dense-row-major with
  *       N/period queries per message (query q in the block at period*q),
  *       hidden units masked and combined into an interleaved vector, then
  *       one message per output with query q's value at slot period*q.
@@ -288,9 +291,30 @@ typedef struct {
     uint32_t n_inputs, n_outputs, n_ops, n_consts, n_galois, n_waves, queries;
     uint32_t n_rotations, n_mul_plain, n_mul_scalar, n_square, n_add_plain, n_add;
     uint32_t n_phys_regs;      /* device ciphertext buffers per request */
+    uint32_t recipe;           /* LOLA_RECIPE_* used for the network's dense layers */
+    float predicted_us;        /* cost model: one request (all its queries), MI355X */
 } lola_plan_info;
 
+/* Representation choice.  Where more than one of the paper's recipes applies
+ * (today: DENSE, SQUARE, DENSE with in_dim <= N/2: dense vector - row major
+ * with N/period queries per message, or stacked vector - row major with one
+ * query per message; Sec. 4.2.2), the compiler builds each candidate, prices
+ * it with a per-operation cost model (key switches, products and element-wise
+ * passes timed on MI355X at N = 16384, L = 7, scaled by N and L) and keeps the
+ * cheapest for the objective: THROUGHPUT = least time per query with full
+ * messages, LATENCY = least time for one query.  recipe forces one (an
+ * inapplicable one gives LOLA_E_UNSUPPORTED).  lola_compile = AUTO, THROUGHPUT. */
+enum { LOLA_OBJECTIVE_THROUGHPUT = 0, LOLA_OBJECTIVE_LATENCY = 1 };
+enum { LOLA_RECIPE_AUTO = 0, LOLA_RECIPE_DENSE_ROW_MAJOR = 1, LOLA_RECIPE_STACKED_ROW_MAJOR = 2,
+       LOLA_RECIPE_FIXED = 3 /* reported for patterns with a single recipe */ };
+typedef struct {
+    int32_t objective;
+    int32_t recipe;
+} lola_compile_options;
+
 int lola_compile(const lola_params *params, const lola_layer *layers, uint32_t n_layers, lola_plan **out);
+int lola_compile_ex(const lola_params *params, const lola_layer *layers, uint32_t n_layers,
+                    const lola_compile_options *options, lola_plan **out);
 void lola_plan_destroy(lola_plan *plan);
 int lola_plan_get_info(const lola_plan *plan, lola_plan_info *info);
 /* Galois elements of the rotation keys the plan needs, in the order

@@ -582,6 +582,68 @@ def head_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int =
                     [{HEAD_BLOCK * q: f"q{q}_logit{o}" for q in range(nb)} for o in range(n_out)])
 
 
+def head_stacked_inputs(features, N=16384):
+    """Stacked representation of one query (Sec. 4.2.1): the feature vector
+    repeated in every block of HEAD_BLOCK slots (the client sends the copies)."""
+    f = np.asarray(features, dtype=np.int64).reshape(-1)
+    return [{HEAD_BLOCK * c + i: int(f[i]) for c in range(N // HEAD_BLOCK) for i in range(f.size)}]
+
+
+def head_stacked_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int = 10) -> Schedule:
+    """The same head, one query per message, with the stacked vector - row
+    major method (Sec. 4.2.2) for the hidden layer:
+      rounds:  C = N / 4096 copies; round rho multiplies by rows C rho + c in
+               block c, rotate-and-sum over 1..2048, keeps slot 4096 c (mask),
+               adds the bias there;
+      combine: round rho rotated right by rho (binary tree) -> hidden unit
+               C rho + c at slot 4096 c + rho;
+      square;
+      output:  interleaved vector - row major: per logit, the product with
+               the row in that layout and rotate-and-sum over 1 .. (rounds)/2,
+               the block strides and the row swap -> logit at slot 0."""
+    assert N == 16384
+    P = HEAD_BLOCK
+    C = N // P
+    nh = wts.w1.shape[0] if n_hidden is None else n_hidden
+    R = (nh + C - 1) // C
+    b = _Builder(N, 1)
+    rounds = []
+    for rho in range(R):
+        rows, mask, bias = {}, {}, {}
+        for c in range(C):
+            j = C * rho + c
+            if j >= nh:
+                continue
+            for i in range(wts.w1.shape[1]):
+                rows[P * c + i] = int(wts.w1[j, i])
+            mask[P * c] = 1
+            bias[P * c] = int(wts.b1[j])
+        z = b.emit("mul_plain", b.reg(), 0, rows)
+        z = _rotate_and_sum(b, z, [1 << k for k in range(12)])
+        z = b.emit("mul_plain", b.reg(), z, mask)
+        z = b.emit("add_plain", b.reg(), z, bias)
+        rounds.append(z)
+    h = _combine_tree(b, rounds, 1)
+    h = b.emit("square", b.reg(), h)
+    coll = [1 << k for k in range(int(np.ceil(np.log2(max(R, 2)))))]
+    coll += [s for s in (P, 2 * P, 4 * P) if s < N // 2 and s < P * C]
+    if P * C > N // 2:
+        coll.append(ROW_SWAP)
+    outs = []
+    for o in range(n_out):
+        rows = {}
+        for rho in range(R):
+            for c in range(C):
+                j = C * rho + c
+                if j < nh:
+                    rows[P * c + rho] = int(wts.w2[o, j])
+        z = b.emit("mul_plain", b.reg(), h, rows)
+        z = _rotate_and_sum(b, z, coll)
+        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b2[o])})
+        outs.append(z)
+    return Schedule(N, 1, b.ops, outs, [{0: f"logit{o}"} for o in range(n_out)])
+
+
 # ------------------------------------------------------------- interpreters
 def dense_slots(sparse: Dict[int, int], N: int, t: int) -> np.ndarray:
     v = np.zeros(N, dtype=np.int64)

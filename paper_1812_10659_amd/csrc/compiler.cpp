@@ -431,6 +431,92 @@ int compile_dense_head(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t 
     return LOLA_OK;
 }
 
+int compile_dense_head_stacked(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
+    // DENSE, SQUARE, DENSE with in_dim <= N/2, one query per message: the
+    // client sends N/P copies of the input (stacked representation); the
+    // hidden layer is stacked vector - row major in rounds, the output layer
+    // interleaved vector - row major (value at slot 0)
+    if (n != 3 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE)
+        return unsupported("dense head must be DENSE, SQUARE, DENSE");
+    const lola_layer &d1 = ls[0], &d2 = ls[2];
+    const uint32_t N = p->N;
+    const uint32_t P = next_pow2((uint32_t)d1.in_dim), C = N / P;
+    const uint32_t H = (uint32_t)d1.out_dim, R = (H + C - 1) / C;
+    if (C < 2 || R > P || d2.in_dim != d1.out_dim || !d2.weight) return unsupported("stacked head shape");
+    p->n_inputs = 1;
+    p->queries = 1;
+    p->n_regs = 1;
+    p->input_map.assign(N, -1);
+    for (uint32_t c = 0; c < C; ++c)
+        for (int i = 0; i < d1.in_dim; ++i) p->input_map[P * c + i] = i;
+    std::vector<int32_t> blk;
+    for (uint32_t s = 1; s < P; s *= 2) blk.push_back((int32_t)s);
+    std::vector<int> rounds;
+    for (uint32_t rho = 0; rho < R; ++rho) {
+        auto rows = b.zeros(), mask = b.zeros(), bias = b.zeros();
+        for (uint32_t c = 0; c < C; ++c) {
+            const uint32_t j = C * rho + c;
+            if (j >= H) continue;
+            for (int i = 0; i < d1.in_dim; ++i) rows[P * c + i] = d1.weight[(size_t)j * d1.in_dim + i];
+            mask[P * c] = 1;
+            bias[P * c] = bias_at(d1, (int)j);
+        }
+        int z = b.mulplain(0, b.cst(rows, true));
+        z = b.rotate_and_sum(z, blk);
+        z = b.mulplain(z, b.cst(mask, true), d1.bias ? b.cst(bias, false) : -1);
+        rounds.push_back(z);
+    }
+    int h = b.combine_tree(rounds, 1);
+    h = b.square(h);
+    std::vector<int32_t> coll;
+    for (uint32_t s = 1; s < next_pow2(std::max<uint32_t>(R, 2)); s *= 2) coll.push_back((int32_t)s);
+    for (uint32_t s = P; s < N / 2 && s < P * C; s *= 2) coll.push_back((int32_t)s);
+    if (P * C > N / 2) coll.push_back(LOLA_ROW_SWAP);
+    p->output_map.assign((size_t)d2.out_dim * N, -1);
+    for (int o = 0; o < d2.out_dim; ++o) {
+        auto rows = b.zeros();
+        for (uint32_t rho = 0; rho < R; ++rho)
+            for (uint32_t c = 0; c < C; ++c) {
+                const uint32_t j = C * rho + c;
+                if (j < H) rows[P * c + rho] = d2.weight[(size_t)o * d2.in_dim + j];
+            }
+        int z = b.mulplain(h, b.cst(rows, true));
+        z = b.rotate_and_sum(z, coll);
+        if (d2.bias) {
+            auto bv = b.zeros();
+            bv[0] = d2.bias[o];
+            z = b.addplain(z, b.cst(bv, false));
+        }
+        p->outputs.push_back(z);
+        p->output_map[(size_t)o * N] = o;
+    }
+    return LOLA_OK;
+}
+
+// ---- cost model ---------------------------------------------------------
+// Microseconds per operation of one request inside a large batch, measured on
+// MI355X at N = 16384 with seven data primes (batched key switch 4.8, ct x ct
+// product and relinearisation 27, plaintext product 0.55, one source of a
+// linear combination 0.35, plaintext add 0.5); key switches and products
+// scale with N log N and the number of limb transforms (L^2 + 3L + 2),
+// element-wise passes with L N.
+float predict_us(const lola_plan *p) {
+    const double sN = (double)p->N / 16384.0, L = (double)p->L;
+    const double ks = sN * (L * L + 3 * L + 2) / 72.0, ew = sN * L / 7.0;
+    double us = 0;
+    for (const Op &o : p->ops) {
+        switch (o.kind) {
+            case OP_ROT:
+            case OP_ROTADD: us += 4.8 * ks; break;
+            case OP_SQUARE: us += 27.0 * ks; break;
+            case OP_MULPLAIN: us += (0.55 + (o.cadd >= 0 ? 0.25 : 0.0)) * ew; break;
+            case OP_LINCOMB: us += 0.35 * (double)o.srcs.size() * ew; break;
+            case OP_ADDPLAIN: us += 0.5 * ew; break;
+        }
+    }
+    return (float)us;
+}
+
 // ---- levels and registers ---------------------------------------------
 void schedule(lola_plan *p) {
     std::vector<int> level(p->n_regs, 0);
@@ -607,13 +693,10 @@ int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n
     return LOLA_OK;
 }
 
-int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_layers, lola_plan **out) {
-    if (!prm || !layers || !out || n_layers == 0) return set_error(LOLA_E_INVAL, "null argument");
+// Compiles with one recipe for the dense head pattern (LOLA_RECIPE_*).
+static int compile_with(const lola_params *prm, const lola_layer *layers, uint32_t n_layers, int recipe,
+                        lola_plan **out) {
     *out = nullptr;
-    if (prm->N < 1024 || prm->N > 16384 || (prm->N & (prm->N - 1)) || prm->t < 3 || prm->L < 1)
-        return set_error(LOLA_E_PARAMS, "bad N, t or L");
-    const struct { uint32_t N; } sz{prm->N};
-    const auto *ctx = &sz;
     lola_plan *p = new lola_plan();
     p->N = prm->N;
     p->L = prm->L;
@@ -621,19 +704,30 @@ int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_la
     Builder b{p};
     int rc;
     const lola_layer &l0 = layers[0];
-    if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
+    const uint32_t N = prm->N;
+    const bool head = l0.kind == LOLA_LAYER_DENSE && n_layers == 3;
+    if (recipe != LOLA_RECIPE_AUTO && recipe != LOLA_RECIPE_FIXED && !head) {
+        rc = unsupported("the recipe choice applies to DENSE, SQUARE, DENSE networks");
+    } else if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
         rc = compile_cifar_net(p, b, layers, n_layers);
     } else if (l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) {
         rc = compile_conv_net(p, b, layers, n_layers);
     } else if (l0.kind == LOLA_LAYER_DENSE && l0.weight && l0.in_dim > 0 && l0.out_dim > 0) {
-        if ((uint32_t)l0.in_dim > ctx->N / 2)
+        if ((uint32_t)l0.in_dim > N / 2) {
             rc = unsupported("dense input longer than a slot row");
-        else if (n_layers == 3)
-            rc = compile_dense_head(p, b, layers, n_layers);
-        else if ((uint32_t)l0.in_dim <= ctx->N / 4)
+        } else if (head) {
+            if (recipe == LOLA_RECIPE_STACKED_ROW_MAJOR) {
+                rc = compile_dense_head_stacked(p, b, layers, n_layers);
+                p->recipe = LOLA_RECIPE_STACKED_ROW_MAJOR;
+            } else {
+                rc = compile_dense_head(p, b, layers, n_layers);
+                p->recipe = LOLA_RECIPE_DENSE_ROW_MAJOR;
+            }
+        } else if ((uint32_t)l0.in_dim <= N / 4) {
             rc = compile_stacked_dense(p, b, layers, n_layers);
-        else
+        } else {
             rc = unsupported("a single dense layer needs in_dim <= N/4 (stacked input)");
+        }
     } else {
         rc = unsupported("first layer must be CONV2D or DENSE");
     }
@@ -642,8 +736,49 @@ int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_la
         return rc;
     }
     schedule(p);
+    p->predicted_us = predict_us(p);
     *out = p;
     return LOLA_OK;
+}
+
+int lola_compile_ex(const lola_params *prm, const lola_layer *layers, uint32_t n_layers,
+                    const lola_compile_options *opts, lola_plan **out) {
+    if (!prm || !layers || !out || n_layers == 0) return set_error(LOLA_E_INVAL, "null argument");
+    *out = nullptr;
+    if (prm->N < 1024 || prm->N > 16384 || (prm->N & (prm->N - 1)) || prm->t < 3 || prm->L < 1)
+        return set_error(LOLA_E_PARAMS, "bad N, t or L");
+    const int objective = opts ? opts->objective : LOLA_OBJECTIVE_THROUGHPUT;
+    const int recipe = opts ? opts->recipe : LOLA_RECIPE_AUTO;
+    if (objective != LOLA_OBJECTIVE_THROUGHPUT && objective != LOLA_OBJECTIVE_LATENCY)
+        return set_error(LOLA_E_INVAL, "unknown objective");
+    if (recipe < LOLA_RECIPE_AUTO || recipe > LOLA_RECIPE_STACKED_ROW_MAJOR)
+        return set_error(LOLA_E_INVAL, "unknown recipe");
+    const bool head = layers[0].kind == LOLA_LAYER_DENSE && n_layers == 3;
+    if (recipe != LOLA_RECIPE_AUTO || !head) return compile_with(prm, layers, n_layers, recipe, out);
+    // both candidates; keep the cheaper for the objective
+    lola_plan *a = nullptr, *c = nullptr;
+    const int ra = compile_with(prm, layers, n_layers, LOLA_RECIPE_DENSE_ROW_MAJOR, &a);
+    const int rc2 = compile_with(prm, layers, n_layers, LOLA_RECIPE_STACKED_ROW_MAJOR, &c);
+    if (ra && rc2) return ra;
+    if (ra) {
+        *out = c;
+        return LOLA_OK;
+    }
+    if (rc2) {
+        *out = a;
+        return LOLA_OK;
+    }
+    auto cost = [&](const lola_plan *q) {
+        return objective == LOLA_OBJECTIVE_LATENCY ? q->predicted_us : q->predicted_us / (float)q->queries;
+    };
+    if (cost(c) < cost(a)) std::swap(a, c);
+    delete c;
+    *out = a;
+    return LOLA_OK;
+}
+
+int lola_compile(const lola_params *prm, const lola_layer *layers, uint32_t n_layers, lola_plan **out) {
+    return lola_compile_ex(prm, layers, n_layers, nullptr, out);
 }
 
 int lola_plan_get_info(const lola_plan *p, lola_plan_info *info) {
@@ -657,6 +792,8 @@ int lola_plan_get_info(const lola_plan *p, lola_plan_info *info) {
     info->n_waves = p->n_waves;
     info->queries = p->queries;
     info->n_phys_regs = p->n_phys;
+    info->recipe = p->recipe;
+    info->predicted_us = p->predicted_us;
     for (const Op &o : p->ops) {
         switch (o.kind) {
             case OP_LINCOMB:

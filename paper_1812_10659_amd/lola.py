@@ -315,7 +315,16 @@ class Layer(ctypes.Structure):
 class _PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n_inputs", "n_outputs", "n_ops", "n_consts", "n_galois", "n_waves", "queries",
-        "n_rotations", "n_mul_plain", "n_mul_scalar", "n_square", "n_add_plain", "n_add", "n_phys_regs")]
+        "n_rotations", "n_mul_plain", "n_mul_scalar", "n_square", "n_add_plain", "n_add", "n_phys_regs",
+        "recipe")] + [("predicted_us", ctypes.c_float)]
+
+
+class _CompileOptions(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_int32), ("recipe", ctypes.c_int32)]
+
+
+OBJECTIVE_THROUGHPUT, OBJECTIVE_LATENCY = 0, 1
+RECIPE_AUTO, RECIPE_DENSE_ROW_MAJOR, RECIPE_STACKED_ROW_MAJOR, RECIPE_FIXED = 0, 1, 2, 3
 
 
 class Request(ctypes.Structure):
@@ -356,6 +365,8 @@ def _plan_sig():
     vp, u32 = ctypes.c_void_p, ctypes.c_uint32
     sig = {
         "lola_compile": [ctypes.POINTER(_Params), ctypes.POINTER(Layer), u32, ctypes.POINTER(vp)],
+        "lola_compile_ex": [ctypes.POINTER(_Params), ctypes.POINTER(Layer), u32, ctypes.POINTER(_CompileOptions),
+                            ctypes.POINTER(vp)],
         "lola_plan_get_info": [vp, ctypes.POINTER(_PlanInfo)],
         "lola_plan_galois": [vp, ctypes.POINTER(u32)],
         "lola_plan_input_map": [vp, ctypes.POINTER(ctypes.c_int32)],
@@ -382,7 +393,7 @@ def _plan_sig():
 class Plan:
     """lola_plan: a layer list compiled for a parameter set (host logic)."""
 
-    def __init__(self, params, layers):
+    def __init__(self, params, layers, objective: int = OBJECTIVE_THROUGHPUT, recipe: int = RECIPE_AUTO):
         L = _plan_sig()
         arr = (Layer * len(layers))()
         self._keep = []
@@ -398,7 +409,8 @@ class Plan:
             arr[k] = ly
         ps, self._q = _params_struct(params)
         h = ctypes.c_void_p()
-        _check(L.lola_compile(ctypes.byref(ps), arr, len(layers), ctypes.byref(h)))
+        opts = _CompileOptions(int(objective), int(recipe))
+        _check(L.lola_compile_ex(ctypes.byref(ps), arr, len(layers), ctypes.byref(opts), ctypes.byref(h)))
         self.h = h
         self._keep = []
         self.N = params.N

@@ -82,8 +82,8 @@ def dump_to_oracle_ops(plan):
     return nw.Schedule(plan.N, plan.info["n_inputs"], ops, outputs)
 
 
-def _check_plan(lola, params, layers, inputs_values, expected, oracle_sched):
-    plan = lola.Plan(params, layers)
+def _check_plan(lola, params, layers, inputs_values, expected, oracle_sched, recipe=0):
+    plan = lola.Plan(params, layers, recipe=recipe)
     sched = dump_to_oracle_ops(plan)
     msgs = lola_pack(plan, inputs_values)
     outs, _ = nw.run_slots(sched, [{k: int(v) for k, v in enumerate(m) if v} for m in msgs], params.t)
@@ -203,6 +203,52 @@ def test_compiler_head(n_hidden):
     expected = np.concatenate([nw.head_plain(f[q], wt) for q in range(4)])
     plan = _check_plan(lola, p, layers, f, expected, nw.head_schedule(w, n_hidden=n_hidden))
     assert plan.info["queries"] == 4
+
+
+@pytest.mark.parametrize("n_hidden", [8, 256])
+def test_compiler_head_stacked_recipe(n_hidden):
+    """The same head with the stacked vector - row major recipe (one query
+    per message, the client sends the copies)."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w, f = wl.head_weights(), wl.head_features(1)
+    p = wl.PARAMS["head_n16384"]
+    wt = wl.HeadWeights(w.w1[:n_hidden], w.b1[:n_hidden], w.w2[:, :n_hidden], w.b2)
+    plan = _check_plan(lola, p, networks.head_layers(w, n_hidden), f[0], nw.head_plain(f[0], wt),
+                       nw.head_stacked_schedule(w, n_hidden=n_hidden), recipe=lola.RECIPE_STACKED_ROW_MAJOR)
+    assert plan.info["queries"] == 1 and plan.info["recipe"] == lola.RECIPE_STACKED_ROW_MAJOR
+
+
+def test_recipe_choice_follows_the_cost_model():
+    """AUTO keeps the candidate with the lower predicted cost for the
+    objective: per query with full messages (throughput) or for one query
+    (latency); forced recipes are honoured; other patterns have one recipe."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w = wl.head_weights()
+    p = wl.PARAMS["head_n16384"]
+    layers = networks.head_layers(w)
+    drm = lola.Plan(p, layers, recipe=lola.RECIPE_DENSE_ROW_MAJOR).info
+    stk = lola.Plan(p, layers, recipe=lola.RECIPE_STACKED_ROW_MAJOR).info
+    assert drm["recipe"] == lola.RECIPE_DENSE_ROW_MAJOR and drm["queries"] == 4
+    assert stk["recipe"] == lola.RECIPE_STACKED_ROW_MAJOR and stk["queries"] == 1
+    per_query = {r["recipe"]: r["predicted_us"] / r["queries"] for r in (drm, stk)}
+    per_msg = {r["recipe"]: r["predicted_us"] for r in (drm, stk)}
+    thr = lola.Plan(p, layers, objective=lola.OBJECTIVE_THROUGHPUT).info["recipe"]
+    lat = lola.Plan(p, layers, objective=lola.OBJECTIVE_LATENCY).info["recipe"]
+    assert thr == min(per_query, key=per_query.get)
+    assert lat == min(per_msg, key=per_msg.get)
+    # for this head: four queries per message amortise the per-row rotations
+    # (throughput), one query alone is cheaper stacked (latency)
+    assert thr == lola.RECIPE_DENSE_ROW_MAJOR and lat == lola.RECIPE_STACKED_ROW_MAJOR
+    # the prediction grows with the work
+    assert stk["predicted_us"] < drm["predicted_us"] and drm["n_rotations"] > stk["n_rotations"]
+    mn = lola.Plan(wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights())).info
+    assert mn["recipe"] == lola.RECIPE_FIXED and mn["predicted_us"] > 0
+    with pytest.raises(lola.LolaError) as e:
+        lola.Plan(wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights()),
+                  recipe=lola.RECIPE_STACKED_ROW_MAJOR)
+    assert e.value.code == -8
 
 
 def test_compiler_rejects_unsupported():

@@ -13,12 +13,12 @@ from paper_1812_10659_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def _setup(pname, layers, oracle_sched, values, key_seed, enc_seed, with_oracle=True):
+def _setup(pname, layers, oracle_sched, values, key_seed, enc_seed, with_oracle=True, recipe=0):
     import torch
     from paper_1812_10659_amd import lola, networks
     p = wl.PARAMS[pname]
     ctx = lola.Context(p)
-    plan = lola.Plan(p, layers)
+    plan = lola.Plan(p, layers, recipe=recipe)
     plan.load(ctx)
     gal = plan.galois()
     sk = ctx.keygen_secret(key_seed)
@@ -140,6 +140,19 @@ def test_head_network_truncated_matches_oracle():
     env = _setup("head_n16384", networks.head_layers(w, 8), sched, f, wl.key_seed(3), wl.enc_seed(3))
     wt = wl.HeadWeights(w.w1[:8], w.b1[:8], w.w2[:, :8], w.b2)
     _run_and_compare(env, sched, np.concatenate([nw.head_plain(f[q], wt) for q in range(4)]))
+
+
+def test_head_stacked_recipe_truncated_matches_oracle():
+    """The head compiled with the stacked vector - row major recipe (one
+    query per message), ciphertext words against the oracle's schedule."""
+    from paper_1812_10659_amd import lola, networks
+    w, f = wl.head_weights(), wl.head_features(1)
+    print("[gpu-net] head, stacked recipe, 8 hidden", flush=True)
+    sched = nw.head_stacked_schedule(w, n_hidden=8)
+    env = _setup("head_n16384", networks.head_layers(w, 8), sched, f[0], wl.key_seed(3) + 1, wl.enc_seed(3) + 1,
+                 recipe=lola.RECIPE_STACKED_ROW_MAJOR)
+    wt = wl.HeadWeights(w.w1[:8], w.b1[:8], w.w2[:, :8], w.b2)
+    _run_and_compare(env, sched, nw.head_plain(f[0], wt))
 
 
 def test_head_network_full_size_decrypts_to_network():
