@@ -37,7 +37,10 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
     const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
-    const uint32_t j = ju.unit;  // target modulus: q_j (j < L) or P (j == L)
+    // target modulus: q_j (j < L) or P (j == L); the special prime's unit,
+    // half again as long as the others, is dispatched first of its job so the
+    // launch's tail holds short units
+    const uint32_t j = ju.unit == 0 ? L : ju.unit - 1;
     ks_stage_inner<LOGN>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
 }
 
