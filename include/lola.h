@@ -295,18 +295,32 @@ typedef struct {
     float predicted_us;        /* cost model: one request (all its queries), MI355X */
 } lola_plan_info;
 
-/* Representation choice.  Where more than one of the paper's recipes applies
- * (today: DENSE, SQUARE, DENSE with in_dim <= N/2: dense vector - row major
- * with N/period queries per message, or stacked vector - row major with one
- * query per message; Sec. 4.2.2), the compiler builds each candidate, prices
- * it with a per-operation cost model (key switches, products and element-wise
- * passes timed on MI355X at N = 16384, L = 7, scaled by N and L) and keeps the
- * cheapest for the objective: THROUGHPUT = least time per query with full
- * messages, LATENCY = least time for one query.  recipe forces one (an
- * inapplicable one gives LOLA_E_UNSUPPORTED).  lola_compile = AUTO, THROUGHPUT. */
+/* Representation choice.  Where more than one recipe applies (candidates
+ * below), the compiler builds each candidate, prices it with a per-operation
+ * cost model (key switches, products and element-wise passes timed on MI355X
+ * at N = 16384, L = 7, scaled by N and L) and keeps the cheapest for the
+ * objective: THROUGHPUT = least time per query with full messages, LATENCY =
+ * least time for one query.  recipe forces one (an inapplicable one gives
+ * LOLA_E_UNSUPPORTED).  lola_compile = AUTO, THROUGHPUT. */
 enum { LOLA_OBJECTIVE_THROUGHPUT = 0, LOLA_OBJECTIVE_LATENCY = 1 };
+/* Candidates:
+ *  - DENSE, SQUARE, DENSE with in_dim <= N/2 (Sec. 4.2.2): DENSE_ROW_MAJOR
+ *    (dense vector - row major, N/period queries per message) or
+ *    STACKED_ROW_MAJOR (stacked vector - row major, one query per message).
+ *  - CONV2D or CONV2D_DENSE_INPUT, SQUARE, DENSE, SQUARE, DENSE (Sec. 4.3,
+ *    App. C): FULL_REDUCTION, the layout the paper describes (every stacked
+ *    round summed over its whole block, masked and combined; one output
+ *    message per class: 154 rotations for the MNIST network), or
+ *    SHARED_REDUCTION (each round summed only within groups of
+ *    next_pow2(rounds) slots, masked to the group starts, combined, then one
+ *    rotate-and-sum over the rest of the block for all rounds together; the
+ *    last layer on shifted copies of its input into one packed message, class
+ *    o at slot next_pow2(rounds)*o: 58 rotations for the MNIST network).  Both
+ *    give the same values at the valid slots of every layer.
+ *  - Everything else: FIXED. */
 enum { LOLA_RECIPE_AUTO = 0, LOLA_RECIPE_DENSE_ROW_MAJOR = 1, LOLA_RECIPE_STACKED_ROW_MAJOR = 2,
-       LOLA_RECIPE_FIXED = 3 /* reported for patterns with a single recipe */ };
+       LOLA_RECIPE_FIXED = 3 /* reported for patterns with a single recipe */,
+       LOLA_RECIPE_FULL_REDUCTION = 4, LOLA_RECIPE_SHARED_REDUCTION = 5 };
 typedef struct {
     int32_t objective;
     int32_t recipe;

@@ -159,6 +159,102 @@ def _combine_tree(b: _Builder, regs: Sequence[int], unit: int) -> int:
     return cur[0]
 
 
+def _log2(x: int) -> int:
+    assert x > 0 and x & (x - 1) == 0
+    return x.bit_length() - 1
+
+
+def _next_pow2(x: int) -> int:
+    return 1 << max(0, (x - 1).bit_length())
+
+
+def _stacked_rounds(b: _Builder, s: int, P: int, C: int, R: int, pos, w1, b1, recipe: str) -> int:
+    """Dense layer on C stacked copies of its input (block c = slots P c ..
+    P c + P - 1, input i at offset pos[i]) in R rounds of stacked vector - row
+    major (Sec. 4.2.2): round rho multiplies by the rows C rho + c laid out in
+    block c.  Returns the combined message, value C rho + c at slot P c + rho.
+
+    recipe "full": each round is summed over its whole block (rotations 1 ..
+    P/2), masked to slot P c with the bias added there, and the rounds are
+    combined by shifting round rho right by rho.
+    recipe "shared": each round is summed only within groups of G =
+    next_pow2(R) slots (rotations 1 .. G/2), masked to the group starts
+    P c + G m (bias at P c), the rounds are shifted right by rho into the free
+    offsets of those groups, and one rotate-and-sum over G .. P/2 finishes
+    every round's block sum at once: slot P c + rho then holds
+    sum_m sum_{d<G} round_rho[P c + G m + d], the full block sum.  Slots other
+    than P c + rho hold partial sums (garbage)."""
+    out_dim = w1.shape[0]
+    G = _next_pow2(R) if recipe == "shared" else P
+    rounds = []
+    for rho in range(R):
+        rows, mask, bias = {}, {}, {}
+        for c in range(C):
+            j = C * rho + c
+            if j >= out_dim:
+                continue
+            for i, p_i in enumerate(pos):
+                rows[P * c + p_i] = int(w1[j, i])
+            for m in range(P // G):
+                mask[P * c + G * m] = 1
+            bias[P * c] = int(b1[j])
+        z = b.emit("mul_plain", b.reg(), s, rows)
+        z = _rotate_and_sum(b, z, [1 << k for k in range(_log2(G))])
+        z = b.emit("mul_plain", b.reg(), z, mask)
+        z = b.emit("add_plain", b.reg(), z, bias)
+        rounds.append(z)
+    h = _combine_tree(b, rounds, 1)
+    if recipe == "shared":
+        h = _rotate_and_sum(b, h, [1 << k for k in range(_log2(G), _log2(P))])
+    return h
+
+
+def _interleaved_output(b: _Builder, h: int, N: int, P: int, C: int, R: int, w2, b2, recipe: str):
+    """Last dense layer on an interleaved vector (value C rho + c at slot
+    P c + rho), Interleaved vector - Row Major (Sec. 4.2.2).  Returns
+    (outputs, out_slots).
+
+    recipe "full": per output o, the product with the row permuted to the
+    interleaved layout and a rotate-and-sum over 1 .. G/2 (G = next_pow2(R)),
+    P .. and the row swap when the blocks fill both rows -> logit o at slot 0
+    of message o.
+    recipe "shared": one packed message.  Copy o of the input is the input
+    rotated right by G o (built as a binary tree: copy o is copy o - 2^k
+    rotated right by G 2^k, 2^k the highest power of two <= o), multiplied by
+    row o laid out at slots P c + G o + rho; the products are added and one
+    rotate-and-sum over the same steps leaves logit o at slot G o."""
+    n_out, in_dim = w2.shape
+    G = _next_pow2(R)
+    coll = [1 << k for k in range(_log2(G))]
+    coll += [P << k for k in range(_log2(N // 2) - _log2(P)) if (P << k) < P * C]
+    if P * C > N // 2:
+        coll.append(ROW_SWAP)
+    if recipe == "full":
+        outs = []
+        for o in range(n_out):
+            rows = {P * c + rho: int(w2[o, C * rho + c])
+                    for rho in range(R) for c in range(C) if C * rho + c < in_dim}
+            z = b.emit("mul_plain", b.reg(), h, rows)
+            z = _rotate_and_sum(b, z, coll)
+            z = b.emit("add_plain", b.reg(), z, {0: int(b2[o])})
+            outs.append(z)
+        return outs, [{0: f"logit{o}"} for o in range(n_out)]
+    assert G * n_out <= P
+    copies = [h]
+    for o in range(1, n_out):
+        hb = 1 << (o.bit_length() - 1)
+        copies.append(b.emit("rotate", b.reg(), copies[o - hb], -G * hb))
+    acc = None
+    for o in range(n_out):
+        rows = {P * c + G * o + rho: int(w2[o, C * rho + c])
+                for rho in range(R) for c in range(C) if C * rho + c < in_dim}
+        z = b.emit("mul_plain", b.reg(), copies[o], rows)
+        acc = z if acc is None else b.emit("add", b.reg(), acc, z)
+    z = _rotate_and_sum(b, acc, coll)
+    z = b.emit("add_plain", b.reg(), z, {G * o: int(b2[o]) for o in range(n_out)})
+    return [z], [{G * o: f"logit{o}" for o in range(n_out)}]
+
+
 def dense64_inputs(x, N):
     """Client side: the 64-vector stacked N/64 times (stacked representation,
     Sec. 4.2.1, with d = 6): slot i holds x[i mod 64]."""
@@ -206,7 +302,7 @@ def mnist_inputs(img, N=16384):
             for m in conv_representation(mnist_padded(img), 5, 2)]
 
 
-def mnist_schedule(wts, N: int = 16384) -> Schedule:
+def mnist_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
     """The LoLa MNIST pipeline of Table 1, laid out for N = 16384 as the paper
     does for LoLa-Dense in App. C (16 stacked copies, 7 rounds):
       conv:    per map, sum_{a,b} w[m,a,b] * M_{a,b} (message x scalar) + bias
@@ -215,15 +311,17 @@ def mnist_schedule(wts, N: int = 16384) -> Schedule:
       square
       stack:   copies at stride 1024 by rotating right 1024, 2048, 4096 and a
                row swap (16 copies)
-      dense1:  7 rounds of stacked vector - row major: product with rows
-               16 rho + c in block c, rotate-and-sum 1..512, keep slot 1024 c
-               (mask), add bias
-      combine: round rho rotated right by rho and added -> interleaved, value
-               16 rho + c at slot 1024 c + rho (6 rotations, tree over 1, 2, 4)
+      dense1:  7 rounds of stacked vector - row major with rows 16 rho + c in
+               block c, combined into an interleaved vector, value 16 rho + c
+               at slot 1024 c + rho (`_stacked_rounds`)
       square
-      dense2:  interleaved vector - row major: per output o, product with the
-               matching interleaved row, rotate-and-sum over 1, 2, 4, 1024,
-               2048, 4096 and the row swap -> logit o at slot 0, add bias."""
+      dense2:  interleaved vector - row major (`_interleaved_output`).
+    recipe "full" is the layout the paper describes: every round summed over
+    its block (10 rotations), masked, combined (6 rotations), and one message
+    per logit (7 rotations each) -> 154 rotations.  recipe "shared" sums the
+    rounds only within groups of 8 slots before combining them and finishes
+    with one shared rotate-and-sum, and packs the ten logits into one message
+    -> 58 rotations, the same values at the valid slots."""
     assert N == 16384
     b = _Builder(N, 25)
     maps = []
@@ -238,39 +336,10 @@ def mnist_schedule(wts, N: int = 16384) -> Schedule:
     y = _combine_tree(b, maps, 169)
     y = b.emit("square", b.reg(), y)
     s = _rotate_and_sum(b, y, [-1024, -2048, -4096, ROW_SWAP])
-    rounds = []
-    for rho in range(7):
-        rows = {}
-        mask = {}
-        bias = {}
-        for c in range(16):
-            j = 16 * rho + c
-            if j >= 100:
-                continue
-            for i in range(845):
-                rows[1024 * c + i] = int(wts.w1[j, i])
-            mask[1024 * c] = 1
-            bias[1024 * c] = int(wts.b1[j])
-        z = b.emit("mul_plain", b.reg(), s, rows)
-        z = _rotate_and_sum(b, z, [1 << k for k in range(10)])
-        z = b.emit("mul_plain", b.reg(), z, mask)
-        z = b.emit("add_plain", b.reg(), z, bias)
-        rounds.append(z)
-    h = _combine_tree(b, rounds, 1)
+    h = _stacked_rounds(b, s, 1024, 16, 7, range(845), wts.w1, wts.b1, recipe)
     h = b.emit("square", b.reg(), h)
-    outs = []
-    for o in range(10):
-        rows = {}
-        for rho in range(7):
-            for c in range(16):
-                j = 16 * rho + c
-                if j < 100:
-                    rows[1024 * c + rho] = int(wts.w2[o, j])
-        z = b.emit("mul_plain", b.reg(), h, rows)
-        z = _rotate_and_sum(b, z, [1, 2, 4, 1024, 2048, 4096, ROW_SWAP])
-        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b2[o])})
-        outs.append(z)
-    return Schedule(N, 25, b.ops, outs, [{0: f"logit{o}"} for o in range(10)])
+    outs, slots = _interleaved_output(b, h, N, 1024, 16, 7, wts.w2, wts.b2, recipe)
+    return Schedule(N, 25, b.ops, outs, slots)
 
 
 def mnist_small_schedule(wts, N: int = 16384) -> Schedule:
@@ -315,7 +384,7 @@ def mnist_dense_inputs(img, N=16384):
     return [{29 * i + j: int(p[i, j]) for i in range(29) for j in range(29) if p[i, j]}]
 
 
-def mnist_dense_schedule(wts, N: int = 16384) -> Schedule:
+def mnist_dense_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
     """LoLa-Dense (App. C, Table 3) for N = 16384:
       masks:   message (a, b) = the input rotated left by 29 a + b (so padded
                pixel (2y + a, 2x + b) sits at slot 58 y + 2 x) times the 0/1
@@ -327,13 +396,12 @@ def mnist_dense_schedule(wts, N: int = 16384) -> Schedule:
       square;
       stack:   8 copies at stride 2048 (rotations right 2048, 4096, row swap);
       dense1:  13 rounds of stacked vector - row major: block c holds row
-               8 rho + c laid out on the combined positions, rotate-and-sum
-               1..1024, mask slot 2048 c, add bias;
-      combine: round rho rotated right by rho (tree over 1, 2, 4, 8) -> value
-               8 rho + c at slot 2048 c + rho;
+               8 rho + c laid out on the combined positions, combined into
+               value 8 rho + c at slot 2048 c + rho (`_stacked_rounds`);
       square;
-      dense2:  interleaved vector - row major: per output, rotate-and-sum over
-               1, 2, 4, 8, 2048, 4096 and the row swap -> logit at slot 0."""
+      dense2:  interleaved vector - row major (`_interleaved_output`).
+    recipe "full": 256 rotations (each round summed over 1 .. 1024, one
+    message per logit); recipe "shared": 118 rotations."""
     assert N == 16384
     P, C = MNIST_DENSE_BLOCK, N // MNIST_DENSE_BLOCK
     R = (100 + C - 1) // C
@@ -361,37 +429,10 @@ def mnist_dense_schedule(wts, N: int = 16384) -> Schedule:
     s = _rotate_and_sum(b, y, [-2048, -4096, ROW_SWAP])
     pos = [MNIST_DENSE_OFFSETS[m] + 58 * yy + 2 * xx
            for m in range(5) for yy in range(MNIST_OUT) for xx in range(MNIST_OUT)]
-    rounds = []
-    for rho in range(R):
-        rows, mask, bias = {}, {}, {}
-        for c in range(C):
-            j = C * rho + c
-            if j >= 100:
-                continue
-            for i in range(845):
-                rows[P * c + pos[i]] = int(wts.w1[j, i])
-            mask[P * c] = 1
-            bias[P * c] = int(wts.b1[j])
-        z = b.emit("mul_plain", b.reg(), s, rows)
-        z = _rotate_and_sum(b, z, [1 << k for k in range(11)])
-        z = b.emit("mul_plain", b.reg(), z, mask)
-        z = b.emit("add_plain", b.reg(), z, bias)
-        rounds.append(z)
-    h = _combine_tree(b, rounds, 1)
+    h = _stacked_rounds(b, s, P, C, R, pos, wts.w1, wts.b1, recipe)
     h = b.emit("square", b.reg(), h)
-    outs = []
-    for o in range(10):
-        rows = {}
-        for rho in range(R):
-            for c in range(C):
-                j = C * rho + c
-                if j < 100:
-                    rows[P * c + rho] = int(wts.w2[o, j])
-        z = b.emit("mul_plain", b.reg(), h, rows)
-        z = _rotate_and_sum(b, z, [1, 2, 4, 8, 2048, 4096, ROW_SWAP])
-        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b2[o])})
-        outs.append(z)
-    return Schedule(N, 1, b.ops, outs, [{0: f"logit{o}"} for o in range(10)])
+    outs, slots = _interleaved_output(b, h, N, P, C, R, wts.w2, wts.b2, recipe)
+    return Schedule(N, 1, b.ops, outs, slots)
 
 
 # CIFAR-shaped network (Sec. 4.4, App. D, collapsed form): 8x8x3 convolution

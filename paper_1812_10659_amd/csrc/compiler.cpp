@@ -166,7 +166,11 @@ int unsupported(const std::string &m) { return set_error(LOLA_E_UNSUPPORTED, m);
 int64_t bias_at(const lola_layer &l, int j) { return l.bias ? l.bias[j] : 0; }
 
 // ---- network families -------------------------------------------------
-int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
+// shared: the two dense layers of the five-layer network with one shared
+// reduction tail and a packed output message (LOLA_RECIPE_SHARED_REDUCTION);
+// otherwise every stacked round is summed over its whole block and each
+// output gets its own message (LOLA_RECIPE_FULL_REDUCTION).
+int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n, bool shared) {
     // CONV2D (or CONV2D_DENSE_INPUT), SQUARE, DENSE [, SQUARE, DENSE]
     const bool small = n == 3;
     const bool dense_in = ls[0].kind == LOLA_LAYER_CONV2D_DENSE_INPUT;
@@ -298,6 +302,17 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
         for (int o = 0; o < d1.out_dim; ++o) p->output_map[(size_t)P * o] = o;
         return LOLA_OK;
     }
+    // rounds of stacked vector - row major.  Full: each round summed over its
+    // block (rotations 1 .. P/2), masked to slot P c with the bias there, and
+    // round rho shifted right by rho.  Shared: each round summed only within
+    // groups of G = next_pow2(R) slots and masked to the group starts
+    // P c + G m (bias at P c); after the shift by rho the rounds fill distinct
+    // offsets of those groups, and one rotate-and-sum over G .. P/2 completes
+    // every round's block sum at slot P c + rho together.
+    const uint32_t G = shared ? next_pow2(R) : P;
+    std::vector<int32_t> grp, tail;
+    for (uint32_t s = 1; s < G; s *= 2) grp.push_back((int32_t)s);
+    for (uint32_t s = G; s < P; s *= 2) tail.push_back((int32_t)s);
     std::vector<int> rounds;
     for (uint32_t rho = 0; rho < R; ++rho) {
         auto rows = b.zeros(), mask = b.zeros(), bias = b.zeros();
@@ -305,30 +320,60 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
             const uint32_t j = C * rho + c;
             if (j >= (uint32_t)d1.out_dim) continue;
             for (int i = 0; i < D; ++i) rows[P * c + pos[i]] = d1.weight[(size_t)j * D + i];
-            mask[P * c] = 1;
+            for (uint32_t m = 0; m < P / G; ++m) mask[P * c + G * m] = 1;
             bias[P * c] = bias_at(d1, (int)j);
         }
         int z = b.mulplain(S, b.cst(rows, true));
-        z = b.rotate_and_sum(z, blk);
+        z = b.rotate_and_sum(z, grp);
         z = b.mulplain(z, b.cst(mask, true), d1.bias ? b.cst(bias, false) : -1);
         rounds.push_back(z);
     }
     int h = b.combine_tree(rounds, 1);
+    if (shared) h = b.rotate_and_sum(h, tail);
     h = b.square(h);
     // interleaved row major: value j = C*rho + c at slot P*c + rho
+    const uint32_t GR = next_pow2(R);
     std::vector<int32_t> coll;
-    for (uint32_t s = 1; s < next_pow2(R); s *= 2) coll.push_back((int32_t)s);
+    for (uint32_t s = 1; s < GR; s *= 2) coll.push_back((int32_t)s);
     for (uint32_t s = P; s < N / 2 && s < P * C; s *= 2) coll.push_back((int32_t)s);
     if (P * C > N / 2) coll.push_back(LOLA_ROW_SWAP);
-    p->output_map.assign((size_t)d2.out_dim * N, -1);
-    for (int o = 0; o < d2.out_dim; ++o) {
+    auto out_row = [&](int o, uint32_t shift) {
         auto rows = b.zeros();
         for (uint32_t rho = 0; rho < R; ++rho)
             for (uint32_t c = 0; c < C; ++c) {
                 const uint32_t j = C * rho + c;
-                if (j < (uint32_t)d1.out_dim) rows[P * c + rho] = d2.weight[(size_t)o * d2.in_dim + j];
+                if (j < (uint32_t)d1.out_dim) rows[P * c + shift + rho] = d2.weight[(size_t)o * d2.in_dim + j];
             }
-        int z = b.mulplain(h, b.cst(rows, true));
+        return b.cst(rows, true);
+    };
+    if (shared) {
+        // one packed message: copy o of the input is rotated right by GR*o
+        // (copy o - 2^k rotated by GR*2^k, 2^k the highest power of two <= o),
+        // times row o at offset GR*o of every block; the products are added
+        // and one rotate-and-sum leaves output o at slot GR*o
+        if ((uint64_t)GR * (uint64_t)d2.out_dim > P) return unsupported("packed output does not fit one stacking block");
+        std::vector<int> copies{h}, prods;
+        for (int o = 1; o < d2.out_dim; ++o) {
+            const int hb = 1 << (31 - __builtin_clz((uint32_t)o));
+            copies.push_back(b.rot(copies[o - hb], -(int32_t)(GR * (uint32_t)hb)));
+        }
+        for (int o = 0; o < d2.out_dim; ++o) prods.push_back(b.mulplain(copies[o], out_row(o, GR * (uint32_t)o)));
+        int z = b.lincomb_any(prods, std::vector<int64_t>(prods.size(), 1), -1);
+        z = b.rotate_and_sum(z, coll);
+        if (d2.bias) {
+            auto bv = b.zeros();
+            for (int o = 0; o < d2.out_dim; ++o) bv[GR * (uint32_t)o] = d2.bias[o];
+            z = b.addplain(z, b.cst(bv, false));
+        }
+        p->outputs.push_back(z);
+        p->output_map.assign(N, -1);
+        for (int o = 0; o < d2.out_dim; ++o) p->output_map[(size_t)GR * o] = o;
+        p->recipe = LOLA_RECIPE_SHARED_REDUCTION;
+        return LOLA_OK;
+    }
+    p->output_map.assign((size_t)d2.out_dim * N, -1);
+    for (int o = 0; o < d2.out_dim; ++o) {
+        int z = b.mulplain(h, out_row(o, 0));
         z = b.rotate_and_sum(z, coll);
         if (d2.bias) {
             auto bv = b.zeros();
@@ -338,6 +383,7 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n)
         p->outputs.push_back(z);
         p->output_map[(size_t)o * N] = o;
     }
+    p->recipe = LOLA_RECIPE_FULL_REDUCTION;
     return LOLA_OK;
 }
 
@@ -693,7 +739,20 @@ int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n
     return LOLA_OK;
 }
 
-// Compiles with one recipe for the dense head pattern (LOLA_RECIPE_*).
+// The recipes that apply to a layer list: DENSE, SQUARE, DENSE has two for
+// its dense layers, the five-layer convolution networks two for their
+// reductions; everything else has one (LOLA_RECIPE_FIXED).
+static std::vector<int> recipe_candidates(const lola_layer *layers, uint32_t n_layers) {
+    const lola_layer &l0 = layers[0];
+    if (l0.kind == LOLA_LAYER_DENSE && n_layers == 3)
+        return {LOLA_RECIPE_DENSE_ROW_MAJOR, LOLA_RECIPE_STACKED_ROW_MAJOR};
+    if ((l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) && n_layers == 5 &&
+        layers[2].kind != LOLA_LAYER_CONV2D)
+        return {LOLA_RECIPE_FULL_REDUCTION, LOLA_RECIPE_SHARED_REDUCTION};
+    return {LOLA_RECIPE_FIXED};
+}
+
+// Compiles with one recipe (one of recipe_candidates()).
 static int compile_with(const lola_params *prm, const lola_layer *layers, uint32_t n_layers, int recipe,
                         lola_plan **out) {
     *out = nullptr;
@@ -706,12 +765,10 @@ static int compile_with(const lola_params *prm, const lola_layer *layers, uint32
     const lola_layer &l0 = layers[0];
     const uint32_t N = prm->N;
     const bool head = l0.kind == LOLA_LAYER_DENSE && n_layers == 3;
-    if (recipe != LOLA_RECIPE_AUTO && recipe != LOLA_RECIPE_FIXED && !head) {
-        rc = unsupported("the recipe choice applies to DENSE, SQUARE, DENSE networks");
-    } else if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
+    if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
         rc = compile_cifar_net(p, b, layers, n_layers);
     } else if (l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) {
-        rc = compile_conv_net(p, b, layers, n_layers);
+        rc = compile_conv_net(p, b, layers, n_layers, recipe == LOLA_RECIPE_SHARED_REDUCTION);
     } else if (l0.kind == LOLA_LAYER_DENSE && l0.weight && l0.in_dim > 0 && l0.out_dim > 0) {
         if ((uint32_t)l0.in_dim > N / 2) {
             rc = unsupported("dense input longer than a slot row");
@@ -751,29 +808,36 @@ int lola_compile_ex(const lola_params *prm, const lola_layer *layers, uint32_t n
     const int recipe = opts ? opts->recipe : LOLA_RECIPE_AUTO;
     if (objective != LOLA_OBJECTIVE_THROUGHPUT && objective != LOLA_OBJECTIVE_LATENCY)
         return set_error(LOLA_E_INVAL, "unknown objective");
-    if (recipe < LOLA_RECIPE_AUTO || recipe > LOLA_RECIPE_STACKED_ROW_MAJOR)
+    if (recipe < LOLA_RECIPE_AUTO || recipe > LOLA_RECIPE_SHARED_REDUCTION)
         return set_error(LOLA_E_INVAL, "unknown recipe");
-    const bool head = layers[0].kind == LOLA_LAYER_DENSE && n_layers == 3;
-    if (recipe != LOLA_RECIPE_AUTO || !head) return compile_with(prm, layers, n_layers, recipe, out);
-    // both candidates; keep the cheaper for the objective
-    lola_plan *a = nullptr, *c = nullptr;
-    const int ra = compile_with(prm, layers, n_layers, LOLA_RECIPE_DENSE_ROW_MAJOR, &a);
-    const int rc2 = compile_with(prm, layers, n_layers, LOLA_RECIPE_STACKED_ROW_MAJOR, &c);
-    if (ra && rc2) return ra;
-    if (ra) {
-        *out = c;
-        return LOLA_OK;
+    const std::vector<int> cand = recipe_candidates(layers, n_layers);
+    if (recipe != LOLA_RECIPE_AUTO) {
+        if (std::find(cand.begin(), cand.end(), recipe) == cand.end())
+            return unsupported("the recipe does not apply to this layer list");
+        return compile_with(prm, layers, n_layers, recipe, out);
     }
-    if (rc2) {
-        *out = a;
-        return LOLA_OK;
-    }
+    // every candidate; keep the cheapest for the objective (the first on ties)
     auto cost = [&](const lola_plan *q) {
         return objective == LOLA_OBJECTIVE_LATENCY ? q->predicted_us : q->predicted_us / (float)q->queries;
     };
-    if (cost(c) < cost(a)) std::swap(a, c);
-    delete c;
-    *out = a;
+    lola_plan *best = nullptr;
+    int first_rc = LOLA_OK;
+    for (int r : cand) {
+        lola_plan *q = nullptr;
+        const int rc = compile_with(prm, layers, n_layers, r, &q);
+        if (rc) {
+            if (!first_rc) first_rc = rc;
+            continue;
+        }
+        if (!best || cost(q) < cost(best)) {
+            delete best;
+            best = q;
+        } else {
+            delete q;
+        }
+    }
+    if (!best) return first_rc;
+    *out = best;
     return LOLA_OK;
 }
 

@@ -11,6 +11,8 @@
 //                               P^-1, add the c0 (or d0 / d1) term and an
 //                               optional whole-ciphertext addend (fused
 //                               rotate-and-add).
+#include <algorithm>
+
 #include "ks_core.hpp"
 #include "program.hpp"
 
@@ -21,7 +23,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const Ks
                                                                       uint32_t L, const ModConst *__restrict__ mcs,
                                                                       const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[1 << LOGN];
-    const JobUnit ju = xcd_job_unit(blockIdx.x, L);
+    const JobUnit ju = xcd_job_unit(blockIdx.x, L, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t i = ju.unit;
@@ -34,7 +36,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
                                                                      const TwPair *__restrict__ tw,
                                                                      const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[2 << LOGN];
-    const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1);
+    const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     // target modulus: q_j (j < L) or P (j == L); the special prime's unit,
@@ -50,7 +52,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const K
                                                                        const TwPair *__restrict__ tw,
                                                                        const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[1 << LOGN];
-    const JobUnit ju = xcd_job_unit(blockIdx.x, 2 * L);
+    const JobUnit ju = xcd_job_unit(blockIdx.x, 2 * L, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t j = ju.unit % L, c = ju.unit / L;
@@ -100,6 +102,9 @@ static constexpr uint32_t KS_CHUNK = 128;
 void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs, uint32_t *scratch,
                        uint32_t chunk) {
     const size_t per = ks_scratch_words(ctx);
+    // jobs that share a key side by side (see xcd_job_unit); the order of the
+    // jobs of one launch does not change any result
+    std::stable_sort(jobs.begin(), jobs.end(), [](const KsJob &a, const KsJob &b) { return a.key < b.key; });
     for (size_t off = 0; off < jobs.size(); off += chunk) {
         const size_t n = std::min<size_t>(chunk, jobs.size() - off);
         std::vector<KsJob> part(jobs.begin() + off, jobs.begin() + off + n);

@@ -35,15 +35,18 @@ namespace lola {
 // land on one XCD: every XCD gets the same mix of short and long units
 // (with one unit per target modulus, the special prime's unit is half again
 // as long as the others, and a plain 2-D grid of L+1 = 8 units per job would
-// put all of those on one XCD), and the jobs of one client, 8 apart in a
-// batch, read their shared keys through the same L2.
+// put all of those on one XCD).  XCD x takes the contiguous block of jobs
+// [x J, x J + J), J = ceil(n / 8), in order, so the few jobs it runs at once
+// are neighbours in the job list; the host sorts a launch's jobs by key, and
+// neighbours that share a key (one client's requests at the same rotation)
+// then read it through the same L2.
 constexpr uint32_t N_XCD = 8;
 struct JobUnit {
     uint32_t job, unit;
 };
-__device__ __forceinline__ JobUnit xcd_job_unit(uint32_t k, uint32_t units) {
-    const uint32_t x = k % N_XCD, r = k / N_XCD;
-    return JobUnit{x + N_XCD * (r / units), r % units};
+__device__ __forceinline__ JobUnit xcd_job_unit(uint32_t k, uint32_t units, uint32_t n) {
+    const uint32_t x = k % N_XCD, r = k / N_XCD, per_xcd = (n + N_XCD - 1) / N_XCD;
+    return JobUnit{x * per_xcd + r / units, r % units};
 }
 // Grid size for n jobs of `units` workgroups each (ids past the last job exit).
 inline uint32_t xcd_grid(uint32_t n, uint32_t units) { return (n + N_XCD - 1) / N_XCD * N_XCD * units; }

@@ -325,6 +325,7 @@ class _CompileOptions(ctypes.Structure):
 
 OBJECTIVE_THROUGHPUT, OBJECTIVE_LATENCY = 0, 1
 RECIPE_AUTO, RECIPE_DENSE_ROW_MAJOR, RECIPE_STACKED_ROW_MAJOR, RECIPE_FIXED = 0, 1, 2, 3
+RECIPE_FULL_REDUCTION, RECIPE_SHARED_REDUCTION = 4, 5
 
 
 class Request(ctypes.Structure):

@@ -118,14 +118,38 @@ def test_compiler_mnist_matches_tables_and_network():
     w, img = wl.mnist_weights(), wl.mnist_image()
     p = wl.PARAMS["mnist_n16384"]
     plan = _check_plan(lola, p, networks.mnist_layers(w), networks.mnist_input_values(img),
-                       nw.mnist_plain(img, w), nw.mnist_schedule(w))
+                       nw.mnist_plain(img, w), nw.mnist_schedule(w, recipe="full"),
+                       recipe=lola.RECIPE_FULL_REDUCTION)
     info = plan.info
+    assert info["recipe"] == lola.RECIPE_FULL_REDUCTION
     assert info["n_inputs"] == 25 and info["n_outputs"] == 10
     assert info["n_rotations"] == 154 and info["n_mul_plain"] == 24 and info["n_mul_scalar"] == 125
     # input map: message 5a+b, slot 13y+x holds padded pixel (2y+a, 2x+b)
     m = plan.input_map()
     assert m[5 * 1 + 2, 13 * 3 + 4] == (2 * 3 + 1) * 29 + (2 * 4 + 2)
     assert (m[:, 169:] == -1).all()
+
+
+@pytest.mark.parametrize("index", [0, 5])
+def test_compiler_mnist_shared_reduction(index):
+    """The shared-reduction recipe (chosen by default): the seven rounds summed
+    within groups of 8 slots, combined, one shared rotate-and-sum; the ten
+    logits packed into one message at slots 8 o.  58 rotations instead of 154,
+    the same products and squares."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w, img = wl.mnist_weights(), wl.mnist_image(index=index)
+    p = wl.PARAMS["mnist_n16384"]
+    plan = _check_plan(lola, p, networks.mnist_layers(w), networks.mnist_input_values(img),
+                       nw.mnist_plain(img, w), nw.mnist_schedule(w, recipe="shared"))
+    info = plan.info
+    assert info["recipe"] == lola.RECIPE_SHARED_REDUCTION
+    assert info["n_rotations"] == 58 and info["n_mul_plain"] == 24 and info["n_square"] == 2
+    assert info["n_outputs"] == 1
+    om = plan.output_map()
+    assert [int(np.nonzero(om.reshape(-1) == o)[0][0]) for o in range(10)] == [8 * o for o in range(10)]
+    forced = lola.Plan(p, networks.mnist_layers(w), recipe=lola.RECIPE_SHARED_REDUCTION).info
+    assert forced["n_rotations"] == 58 and forced["predicted_us"] == info["predicted_us"]
 
 
 def test_compiler_mnist_dense_input():
@@ -136,12 +160,19 @@ def test_compiler_mnist_dense_input():
     w, img = wl.mnist_weights(), wl.mnist_image(index=2)
     p = wl.PARAMS["mnist_dense_n16384"]
     plan = _check_plan(lola, p, networks.mnist_dense_layers(w), networks.mnist_input_values(img),
-                       nw.mnist_plain(img, w), nw.mnist_dense_schedule(w))
+                       nw.mnist_plain(img, w), nw.mnist_dense_schedule(w, recipe="full"),
+                       recipe=lola.RECIPE_FULL_REDUCTION)
     info = plan.info
     assert info["n_inputs"] == 1 and info["n_outputs"] == 10
     assert info["n_rotations"] == 256 and info["n_mul_plain"] == 25 + 2 * 13 + 10
     m = plan.input_map()
     assert m[0, 29 * 3 + 4] == 29 * 3 + 4 and (m[0, 29 * 29:] == -1).all()
+    # shared reduction: 13 rounds summed within groups of 16 slots, packed
+    # output at slots 16 o
+    sh = _check_plan(lola, p, networks.mnist_dense_layers(w), networks.mnist_input_values(img),
+                     nw.mnist_plain(img, w), nw.mnist_dense_schedule(w, recipe="shared"))
+    assert sh.info["recipe"] == lola.RECIPE_SHARED_REDUCTION and sh.info["n_rotations"] == 118
+    assert sh.info["n_outputs"] == 1 and sh.info["n_mul_plain"] == info["n_mul_plain"]
 
 
 @pytest.mark.parametrize("m1,m2,side", [(5, 3, 16), (2, 2, 20)])
@@ -243,12 +274,22 @@ def test_recipe_choice_follows_the_cost_model():
     assert thr == lola.RECIPE_DENSE_ROW_MAJOR and lat == lola.RECIPE_STACKED_ROW_MAJOR
     # the prediction grows with the work
     assert stk["predicted_us"] < drm["predicted_us"] and drm["n_rotations"] > stk["n_rotations"]
-    mn = lola.Plan(wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights())).info
-    assert mn["recipe"] == lola.RECIPE_FIXED and mn["predicted_us"] > 0
-    with pytest.raises(lola.LolaError) as e:
-        lola.Plan(wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights()),
-                  recipe=lola.RECIPE_STACKED_ROW_MAJOR)
-    assert e.value.code == -8
+    # the convolution networks: the shared reduction needs fewer rotations for
+    # the same products and squares, so AUTO keeps it under both objectives
+    pm, lm = wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights())
+    full = lola.Plan(pm, lm, recipe=lola.RECIPE_FULL_REDUCTION).info
+    shared = lola.Plan(pm, lm, recipe=lola.RECIPE_SHARED_REDUCTION).info
+    assert shared["predicted_us"] < full["predicted_us"]
+    for obj in (lola.OBJECTIVE_THROUGHPUT, lola.OBJECTIVE_LATENCY):
+        assert lola.Plan(pm, lm, objective=obj).info["recipe"] == lola.RECIPE_SHARED_REDUCTION
+    sm = lola.Plan(pm, networks.mnist_small_layers(wl.mnist_small_weights())).info
+    assert sm["recipe"] == lola.RECIPE_FIXED and sm["predicted_us"] > 0
+    for bad_layers, bad_recipe in [(lm, lola.RECIPE_STACKED_ROW_MAJOR), (layers, lola.RECIPE_SHARED_REDUCTION),
+                                   (networks.mnist_small_layers(wl.mnist_small_weights()),
+                                    lola.RECIPE_FULL_REDUCTION)]:
+        with pytest.raises(lola.LolaError) as e:
+            lola.Plan(pm if bad_layers is not layers else p, bad_layers, recipe=bad_recipe)
+        assert e.value.code == -8
 
 
 def test_compiler_rejects_unsupported():

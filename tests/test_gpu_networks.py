@@ -71,25 +71,33 @@ def test_dense64_network_matches_oracle():
     _run_and_compare(env, sched, nw.dense64_plain(x, W))
 
 
-def test_mnist_network_matches_oracle():
+# (oracle recipe name, LOLA_RECIPE_*): the paper's layout and the shared reduction
+RECIPES = [("full", 4), ("shared", 5)]
+
+
+@pytest.mark.parametrize("name,recipe", RECIPES)
+def test_mnist_network_matches_oracle(name, recipe):
     from paper_1812_10659_amd import networks
     w, img = wl.mnist_weights(), wl.mnist_image()
-    print("[gpu-net] mnist", flush=True)
-    sched = nw.mnist_schedule(w)
+    print(f"[gpu-net] mnist {name}", flush=True)
+    sched = nw.mnist_schedule(w, recipe=name)
     env = _setup("mnist_n16384", networks.mnist_layers(w), sched, networks.mnist_input_values(img),
-                 wl.key_seed(1), wl.enc_seed(1))
+                 wl.key_seed(1), wl.enc_seed(1), recipe=recipe)
+    assert env["plan"].info["recipe"] == recipe
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
 
 
-def test_mnist_dense_input_network_matches_oracle():
+@pytest.mark.parametrize("name,recipe", RECIPES)
+def test_mnist_dense_input_network_matches_oracle(name, recipe):
     """LoLa-Dense: one dense input message, masks and rotations build the
     convolution messages; eight data primes."""
     from paper_1812_10659_amd import networks
     w, img = wl.mnist_weights(), wl.mnist_image(index=2)
-    print("[gpu-net] mnist dense input", flush=True)
-    sched = nw.mnist_dense_schedule(w)
+    print(f"[gpu-net] mnist dense input {name}", flush=True)
+    sched = nw.mnist_dense_schedule(w, recipe=name)
     env = _setup("mnist_dense_n16384", networks.mnist_dense_layers(w), sched, networks.mnist_input_values(img),
-                 wl.key_seed(1) + 9, wl.enc_seed(1) + 9)
+                 wl.key_seed(1) + 9, wl.enc_seed(1) + 9, recipe=recipe)
+    assert env["plan"].info["recipe"] == recipe
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
 
 

@@ -81,18 +81,20 @@ def test_moduli_cover_the_network():
 
 
 @pytest.mark.slow
-def test_tightest_modulus_keeps_a_noise_budget():
+@pytest.mark.parametrize("recipe", ["full", "shared"])
+def test_tightest_modulus_keeps_a_noise_budget(recipe):
     """The modulus with the least room (t = 1179649) still decrypts the whole
     network exactly, with a positive noise budget, at seven data primes."""
     p = [q for q in wl.crt_params() if q.t == 1179649][0]
     ctx = bfv.Context(p)
     w = wl.mnist_weights()
-    sched = nw.mnist_schedule(w)
+    sched = nw.mnist_schedule(w, recipe=recipe)
     keys = bfv.keygen(ctx, 5, nw.galois_elements(sched))
     img = wl.mnist_image(index=0)
     cts = [bfv.encrypt(ctx, keys, bfv.encode(ctx, nw.dense_slots(m, p.N, p.t)), 1, i)
            for i, m in enumerate(nw.mnist_inputs(img))]
     outs, _ = nw.run_ciphertexts(ctx, keys, sched, cts)
     assert min(bfv.noise_budget(ctx, keys, o) for o in outs) > 1.0
-    got = [int(bfv.decode(ctx, bfv.decrypt(ctx, keys, o))[0]) for o in outs]
+    dec = [bfv.decode(ctx, bfv.decrypt(ctx, keys, o)) for o in outs]
+    got = [int(dec[k][s]) for k, sl in enumerate(sched.out_slots) for s in sl]
     assert got == [int(v) for v in nw._mod(nw.mnist_plain(img, w), p.t)]

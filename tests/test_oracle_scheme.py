@@ -274,11 +274,36 @@ def test_slot_schedules_equal_plain_networks():
     wts, img = wl.mnist_weights(), wl.mnist_image()
     outs, _ = nw.run_slots(nw.mnist_schedule(wts), nw.mnist_inputs(img), 1146881)
     assert [int(o[0]) for o in outs] == list(nw._mod(nw.mnist_plain(img, wts), 1146881))
+    outs, _ = nw.run_slots(nw.mnist_schedule(wts, recipe="shared"), nw.mnist_inputs(img), 1146881)
+    assert [int(outs[0][8 * o]) for o in range(10)] == list(nw._mod(nw.mnist_plain(img, wts), 1146881))
     hw, f = wl.head_weights(), wl.head_features(4)
     outs, _ = nw.run_slots(nw.head_schedule(hw), nw.head_inputs(f), 1146881)
     for q in range(4):
         exp = nw._mod(nw.head_plain(f[q], hw), 1146881)
         assert [int(outs[o][4096 * q]) for o in range(10)] == list(exp)
+
+
+@pytest.mark.parametrize("index", [0, 1, 4])
+def test_shared_reduction_equals_full_at_valid_slots(index):
+    """The two reduction recipes of the MNIST networks (full: every round summed
+    over its block; shared: rounds summed within groups, combined, one shared
+    tail) give the same hidden vector at every valid slot P c + rho of the
+    second square's input, and the same logits; the shared schedule's garbage
+    slots differ.  Also for LoLa-Dense (P = 2048, 13 rounds, groups of 16)."""
+    wts, img = wl.mnist_weights(), wl.mnist_image(index=index)
+    for mk, ins, P, C, R, t in [(nw.mnist_schedule, nw.mnist_inputs(img), 1024, 16, 7, 1146881),
+                                (nw.mnist_dense_schedule, nw.mnist_dense_inputs(img), 2048, 8, 13, 1146881)]:
+        hid = {}
+        res = {}
+        for rec in ("full", "shared"):
+            sc = mk(wts, recipe=rec)
+            outs, reg = nw.run_slots(sc, ins, t)
+            hid[rec] = reg[[op for op in sc.ops if op[0] == "square"][1][2]]
+            res[rec] = [int(outs[k][s]) for k, sl in enumerate(sc.out_slots) for s in sl]
+        valid = [P * c + rho for rho in range(R) for c in range(C) if C * rho + c < 100]
+        assert np.array_equal(hid["full"][valid], hid["shared"][valid])
+        assert not np.array_equal(hid["full"], hid["shared"])
+        assert res["full"] == res["shared"] == list(nw._mod(nw.mnist_plain(img, wts), t))
 
 
 def test_dense64_ciphertext_schedule_end_to_end():
@@ -295,10 +320,11 @@ def test_dense64_ciphertext_schedule_end_to_end():
 
 
 @pytest.mark.slow
-def test_mnist_ciphertext_schedule_end_to_end():
+@pytest.mark.parametrize("recipe", ["full", "shared"])
+def test_mnist_ciphertext_schedule_end_to_end(recipe):
     ctx = bfv.Context(wl.PARAMS["mnist_n16384"])
     wts, img = wl.mnist_weights(), wl.mnist_image()
-    sc = nw.mnist_schedule(wts)
+    sc = nw.mnist_schedule(wts, recipe=recipe)
     keys = bfv.keygen(ctx, wl.key_seed(1), nw.galois_elements(sc))
     ins = nw.mnist_inputs(img)
     cts = [bfv.encrypt(ctx, keys, bfv.encode(ctx, nw.dense_slots(m, ctx.N, ctx.t)), wl.enc_seed(1), i)
@@ -308,7 +334,8 @@ def test_mnist_ciphertext_schedule_end_to_end():
     for o, s in zip(outs, slots):
         assert np.array_equal(bfv.decode(ctx, bfv.decrypt(ctx, keys, o)), s)
         assert bfv.noise_budget(ctx, keys, o) > 1.0
-    assert [int(s[0]) for s in slots] == list(nw._mod(nw.mnist_plain(img, wts), ctx.t))
+    got = [int(slots[k][s]) for k, sl in enumerate(sc.out_slots) for s in sl]
+    assert got == list(nw._mod(nw.mnist_plain(img, wts), ctx.t))
 
 
 def test_bruteforce_chacha_quarter_round_vector():
