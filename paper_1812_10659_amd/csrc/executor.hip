@@ -2,6 +2,7 @@
 // each wave for any set of requests (one batched launch per op kind per wave,
 // over all requests), runs a bound program, or replays it through a captured
 // HIP graph.  The serving loop reuses emit_level / program_level.
+#include <algorithm>
 #include <cstddef>
 #include <cstring>
 
@@ -11,6 +12,7 @@ namespace lola {
 
 constexpr uint32_t EXEC_KS_CHUNK = 256;
 constexpr uint32_t EXEC_MUL_CHUNK = 16;
+constexpr uint32_t EXEC_LANE_MIN_REQUESTS = 16;   // batches from this size run as two lanes
 
 int validate_request(const lola_plan *p, const lola_request &r) {
     if (!r.in_dev || !r.out_dev || (!p->galois.empty() && !r.gk_dev))
@@ -125,33 +127,40 @@ int release_graph(lola_plan *p) {
     return LOLA_OK;
 }
 
-int ensure_ws(lola_plan *p, size_t words) {
-    if (words <= p->ws_words) return LOLA_OK;
-    if (p->d_ws) {
+int ensure_ws(ExecLane &ln, size_t words) {
+    if (words <= ln.ws_words) return LOLA_OK;
+    if (ln.d_ws) {
         LOLA_HIP(hipDeviceSynchronize());
-        LOLA_HIP(hipFree(p->d_ws));
-        p->d_ws = nullptr;
-        p->ws_words = 0;
+        LOLA_HIP(hipFree(ln.d_ws));
+        ln.d_ws = nullptr;
+        ln.ws_words = 0;
     }
-    if (hipMalloc(&p->d_ws, words * 4) != hipSuccess)
+    if (hipMalloc(&ln.d_ws, words * 4) != hipSuccess)
         return set_error(LOLA_E_NOMEM, "plan workspace allocation of " + std::to_string(words * 4) + " bytes failed");
-    p->ws_words = words;
+    ln.ws_words = words;
     return LOLA_OK;
 }
 
-int ensure_blob(lola_plan *p, size_t bytes) {
-    if (bytes <= p->blob_cap) return LOLA_OK;
-    if (p->d_blob) {
+int ensure_blob(ExecLane &ln, size_t bytes) {
+    if (bytes <= ln.blob_cap) return LOLA_OK;
+    if (ln.d_blob) {
         LOLA_HIP(hipDeviceSynchronize());
-        LOLA_HIP(hipFree(p->d_blob));
-        LOLA_HIP(hipHostFree(p->h_blob));
-        p->d_blob = p->h_blob = nullptr;
+        LOLA_HIP(hipFree(ln.d_blob));
+        LOLA_HIP(hipHostFree(ln.h_blob));
+        ln.d_blob = ln.h_blob = nullptr;
     }
     size_t cap = bytes + bytes / 4 + 4096;
-    if (hipMalloc((void **)&p->d_blob, cap) != hipSuccess) return set_error(LOLA_E_NOMEM, "plan blob allocation failed");
-    LOLA_HIP(hipHostMalloc((void **)&p->h_blob, cap, hipHostMallocDefault));
-    p->blob_cap = cap;
+    if (hipMalloc((void **)&ln.d_blob, cap) != hipSuccess) return set_error(LOLA_E_NOMEM, "plan blob allocation failed");
+    LOLA_HIP(hipHostMalloc((void **)&ln.h_blob, cap, hipHostMallocDefault));
+    ln.blob_cap = cap;
     return LOLA_OK;
+}
+
+void free_lane(ExecLane &ln) {
+    if (ln.d_ws) (void)hipFree(ln.d_ws);
+    if (ln.d_blob) (void)hipFree(ln.d_blob);
+    if (ln.h_blob) (void)hipHostFree(ln.h_blob);
+    ln = ExecLane();
 }
 
 std::vector<std::vector<const uint32_t *>> request_ptrs(const lola_plan *p, const lola_request *reqs, uint32_t n) {
@@ -166,7 +175,7 @@ std::vector<std::vector<const uint32_t *>> request_ptrs(const lola_plan *p, cons
 }
 
 // Builds the whole launch program for n requests evaluated together.
-int bind(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n) {
+int bind(lola_ctx *ctx, lola_plan *p, ExecLane &ln, const lola_request *reqs, uint32_t n) {
     const size_t N = p->N, L = p->L, CT = 2 * L * N, CT3 = 3 * L * N;
     size_t max_ks = 1;
     for (uint32_t lev = 1; lev <= p->n_waves; ++lev) {
@@ -183,13 +192,13 @@ int bind(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n) {
     const uint32_t nsq = std::max<uint32_t>(p->max_squares_per_wave, 1);
     const size_t reg_words = (size_t)n * p->n_phys * CT;
     const size_t sq_words = (size_t)n * nsq * CT3;
-    int rc = ensure_ws(p, reg_words + sq_words + level_scratch_words(ctx, ks_chunk, mul_chunk));
+    int rc = ensure_ws(ln, reg_words + sq_words + level_scratch_words(ctx, ks_chunk, mul_chunk));
     if (rc) return rc;
-    uint32_t *regs = p->d_ws, *sqt = p->d_ws + reg_words, *scratch = p->d_ws + reg_words + sq_words;
+    uint32_t *regs = ln.d_ws, *sqt = ln.d_ws + reg_words, *scratch = ln.d_ws + reg_words + sq_words;
     std::vector<ReqView> views(n);
     for (uint32_t r = 0; r < n; ++r)
         views[r] = ReqView{&reqs[r], regs + (size_t)r * p->n_phys * CT, sqt + (size_t)r * nsq * CT3};
-    Program &prog = p->prog;
+    Program &prog = ln.prog;
     prog = Program();
     for (uint32_t lev = 1; lev <= p->n_waves; ++lev) {
         LevelJobs jobs;
@@ -200,31 +209,59 @@ int bind(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n) {
     return LOLA_OK;
 }
 
-int upload(lola_plan *p, hipStream_t s) {
-    Program &prog = p->prog;
-    int rc = ensure_blob(p, prog.blob.size());
+int upload(ExecLane &ln, hipStream_t s) {
+    Program &prog = ln.prog;
+    int rc = ensure_blob(ln, prog.blob.size());
     if (rc) return rc;
     LOLA_HIP(hipStreamSynchronize(s));   // the previous upload from h_blob is complete
-    memcpy(p->h_blob, prog.blob.data(), prog.blob.size());
-    LOLA_HIP(hipMemcpyAsync(p->d_blob, p->h_blob, prog.blob.size(), hipMemcpyHostToDevice, s));
+    memcpy(ln.h_blob, prog.blob.data(), prog.blob.size());
+    LOLA_HIP(hipMemcpyAsync(ln.d_blob, ln.h_blob, prog.blob.size(), hipMemcpyHostToDevice, s));
     return LOLA_OK;
 }
 
-int prepare(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n, hipStream_t s) {
+// Binds (when the request pointers changed) and uploads the programs of
+// n_lanes lanes: lane k takes requests [k * half, ...), half = ceil(n / n_lanes).
+int prepare(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n, hipStream_t s, uint32_t n_lanes) {
     if (p->loaded_for != ctx) return set_error(LOLA_E_INVAL, "plan constants not loaded for this context (lola_plan_load)");
     for (uint32_t r = 0; r < n; ++r) {
         int rc = validate_request(p, reqs[r]);
         if (rc) return rc;
     }
-    auto ptrs = request_ptrs(p, reqs, n);
-    if (p->prog_valid && ptrs == p->bound_ptrs) return LOLA_OK;
-    p->prog_valid = false;
-    release_graph(p);
-    int rc = bind(ctx, p, reqs, n);
-    if (rc) return rc;
-    if ((rc = upload(p, s))) return rc;
-    p->bound_ptrs = ptrs;
-    p->prog_valid = true;
+    const uint32_t half = (n + n_lanes - 1) / n_lanes;
+    for (uint32_t k = 0; k < 2; ++k) {
+        ExecLane &ln = p->lanes[k];
+        const uint32_t off = std::min(n, k * half), cnt = k < n_lanes ? std::min(half, n - off) : 0;
+        auto ptrs = request_ptrs(p, reqs + off, cnt);
+        if (ln.prog_valid && ptrs == ln.bound_ptrs) continue;
+        ln.prog_valid = false;
+        if (k == 0) release_graph(p);
+        if (cnt == 0) {   // unused lane: nothing bound
+            ln.prog = Program();
+            ln.bound_ptrs = ptrs;
+            ln.prog_valid = true;
+            continue;
+        }
+        int rc = bind(ctx, p, ln, reqs + off, cnt);
+        if (rc) return rc;
+        if ((rc = upload(ln, s))) return rc;
+        ln.bound_ptrs = ptrs;
+        ln.prog_valid = true;
+    }
+    return LOLA_OK;
+}
+
+// Launches two bound programs, interleaved launch by launch so both streams
+// have work queued from the start.
+int run_two(lola_ctx *ctx, const ExecLane &a, hipStream_t sa, const ExecLane &b, hipStream_t sb) {
+    const size_t na = a.prog.launches.size(), nb = b.prog.launches.size();
+    size_t i = 0, j = 0;
+    while (i < na || j < nb) {
+        // keep the two lanes' progress proportional
+        const bool take_a = j >= nb || (i < na && i * nb <= j * na);
+        int rc = take_a ? program_run_launch(ctx, a.prog.launches[i++], a.d_blob, sa)
+                        : program_run_launch(ctx, b.prog.launches[j++], b.d_blob, sb);
+        if (rc) return rc;
+    }
     return LOLA_OK;
 }
 
@@ -296,7 +333,7 @@ int lola_plan_load(lola_ctx *ctx, lola_plan *p, lola_stream stream) {
     (void)hipFree(d_pt);
     if (rc) return rc;
     p->loaded_for = ctx;
-    p->prog_valid = false;
+    p->lanes[0].prog_valid = p->lanes[1].prog_valid = false;
     release_graph(p);
     return LOLA_OK;
 }
@@ -306,9 +343,11 @@ void lola_plan_destroy(lola_plan *p) {
     (void)hipDeviceSynchronize();
     release_graph(p);
     free_consts(p);
-    if (p->d_ws) (void)hipFree(p->d_ws);
-    if (p->d_blob) (void)hipFree(p->d_blob);
-    if (p->h_blob) (void)hipHostFree(p->h_blob);
+    free_lane(p->lanes[0]);
+    free_lane(p->lanes[1]);
+    if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+    if (p->join_ev) (void)hipEventDestroy(p->join_ev);
     delete p;
 }
 
@@ -316,9 +355,25 @@ int lola_evaluate(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_
     if (!ctx || !p || (!reqs && n)) return set_error(LOLA_E_INVAL, "null argument");
     if (n == 0) return LOLA_OK;
     hipStream_t s = (hipStream_t)stream;
-    int rc = prepare(ctx, p, reqs, n, s);
+    // two lanes for batches large enough that each half still fills the
+    // launches: kernels of one half run in the other's launch tails.  Kernel
+    // timing measures launches alone, so it keeps one lane.
+    const uint32_t n_lanes = (!ctx->timing && n >= EXEC_LANE_MIN_REQUESTS) ? 2 : 1;
+    int rc = prepare(ctx, p, reqs, n, s, n_lanes);
     if (rc) return rc;
-    return program_run(ctx, p->prog, p->d_blob, s);
+    if (n_lanes == 1) return program_run(ctx, p->lanes[0].prog, p->lanes[0].d_blob, s);
+    if (!p->side_stream) {
+        LOLA_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
+        LOLA_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+        LOLA_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
+    }
+    LOLA_HIP(hipEventRecord(p->fork_ev, s));   // inputs and uploads on s come first
+    LOLA_HIP(hipStreamWaitEvent(p->side_stream, p->fork_ev, 0));
+    rc = run_two(ctx, p->lanes[0], s, p->lanes[1], p->side_stream);
+    // join even after an error, so s never runs ahead of queued side work
+    LOLA_HIP(hipEventRecord(p->join_ev, p->side_stream));
+    LOLA_HIP(hipStreamWaitEvent(s, p->join_ev, 0));
+    return rc;
 }
 
 int lola_evaluate_graph(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n, lola_stream stream) {
@@ -327,12 +382,12 @@ int lola_evaluate_graph(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, u
     if (ctx->timing) return set_error(LOLA_E_INVAL, "kernel timing and graph replay are exclusive");
     hipStream_t s = (hipStream_t)stream;
     if (!s) return set_error(LOLA_E_INVAL, "graph replay needs a non-default stream");
-    int rc = prepare(ctx, p, reqs, n, s);
+    int rc = prepare(ctx, p, reqs, n, s, 1);
     if (rc) return rc;
     if (!p->graph_valid) {
         LOLA_HIP(hipStreamSynchronize(s));   // blob upload done before capture
         LOLA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        rc = program_run(ctx, p->prog, p->d_blob, s);
+        rc = program_run(ctx, p->lanes[0].prog, p->lanes[0].d_blob, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (rc) {

@@ -26,6 +26,21 @@ struct Op {
 
 }  // namespace lola
 
+namespace lola {
+// Device state of one execution lane: the program bound for a set of
+// requests, its workspace (registers, square temporaries, scratch) and its
+// launch descriptors.
+struct ExecLane {
+    uint32_t *d_ws = nullptr;
+    size_t ws_words = 0;
+    uint8_t *d_blob = nullptr, *h_blob = nullptr;
+    size_t blob_cap = 0;
+    std::vector<std::vector<const uint32_t *>> bound_ptrs;   // request pointer sets of the last bind
+    Program prog;
+    bool prog_valid = false;
+};
+}  // namespace lola
+
 struct lola_plan {
     uint32_t N = 0, L = 0, t = 0;
     uint32_t n_inputs = 0, queries = 1;
@@ -49,15 +64,13 @@ struct lola_plan {
     const lola_ctx *loaded_for = nullptr;
     std::vector<uint32_t *> d_cmul, d_cadd;
     std::vector<uint32_t *> d_wtab;             // per op: lincomb scalar table [n_src][2][L]
-    // bound evaluation state
-    uint32_t *d_ws = nullptr;                   // registers + square temporaries + scratch
-    size_t ws_words = 0;
-    uint8_t *d_blob = nullptr, *h_blob = nullptr;
-    size_t blob_cap = 0;
-    std::vector<std::vector<const uint32_t *>> bound_ptrs;   // request pointer sets of the last bind
-    lola::Program prog;
-    bool prog_valid = false;
-    hipGraph_t graph = nullptr;
+    // bound evaluation state: a batch runs as one lane on the caller's stream
+    // or as two lanes (halves of the batch), the second on side_stream, forked
+    // from and joined back to the caller's stream with events
+    lola::ExecLane lanes[2];
+    hipStream_t side_stream = nullptr;          // non-blocking, default priority
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipGraph_t graph = nullptr;                 // captured from lane 0 (one lane)
     hipGraphExec_t graph_exec = nullptr;
     bool graph_valid = false;
 };

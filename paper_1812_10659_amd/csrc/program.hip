@@ -69,20 +69,23 @@ int launch_plain_dev(lola_ctx *ctx, const PlainJob *d, uint32_t n, hipStream_t s
     return LOLA_OK;
 }
 
+int program_run_launch(lola_ctx *ctx, const Launch &l, const uint8_t *d_blob, hipStream_t s) {
+    const void *d = d_blob + l.off;
+    switch (l.kind) {
+        case LK_NTT: return launch_ntt_jobs_dev(ctx, (const NttJob *)d, (int)l.n, s);
+        case LK_LIN: return launch_lin_dev(ctx, (const LinJob *)d, l.n, s);
+        case LK_PLAIN: return launch_plain_dev(ctx, (const PlainJob *)d, l.n, s);
+        case LK_KS: return launch_keyswitch(ctx, (const KsJob *)d, l.n, s);
+        case LK_MUL_EXTEND:
+        case LK_MUL_PRODUCT:
+        case LK_MUL_ROUND: return launch_mul_stage(ctx, l.kind, (const MulJob *)d, l.n, s);
+        default: return set_error(LOLA_E_INVAL, "bad launch kind");
+    }
+}
+
 int program_run(lola_ctx *ctx, const Program &p, const uint8_t *d_blob, hipStream_t s) {
     for (const Launch &l : p.launches) {
-        const void *d = d_blob + l.off;
-        int rc = LOLA_OK;
-        switch (l.kind) {
-            case LK_NTT: rc = launch_ntt_jobs_dev(ctx, (const NttJob *)d, (int)l.n, s); break;
-            case LK_LIN: rc = launch_lin_dev(ctx, (const LinJob *)d, l.n, s); break;
-            case LK_PLAIN: rc = launch_plain_dev(ctx, (const PlainJob *)d, l.n, s); break;
-            case LK_KS: rc = launch_keyswitch(ctx, (const KsJob *)d, l.n, s); break;
-            case LK_MUL_EXTEND:
-            case LK_MUL_PRODUCT:
-            case LK_MUL_ROUND: rc = launch_mul_stage(ctx, l.kind, (const MulJob *)d, l.n, s); break;
-            default: rc = set_error(LOLA_E_INVAL, "bad launch kind");
-        }
+        int rc = program_run_launch(ctx, l, d_blob, s);
         if (rc) return rc;
     }
     return LOLA_OK;

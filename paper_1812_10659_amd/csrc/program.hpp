@@ -71,6 +71,8 @@ void program_mul(const lola_ctx *ctx, Program &p, const std::vector<MulJob> &pai
 
 // Issues the launches; d_blob is the device copy of p.blob.
 int program_run(lola_ctx *ctx, const Program &p, const uint8_t *d_blob, hipStream_t s);
+// Issues one launch of a program.
+int program_run_launch(lola_ctx *ctx, const Launch &l, const uint8_t *d_blob, hipStream_t s);
 // Uploads the blob through the context's descriptor ring and runs (immediate
 // API calls; the blob must fit one ring slab).
 int program_run_now(lola_ctx *ctx, const Program &p, hipStream_t s);

@@ -218,3 +218,52 @@ def test_batched_requests_equal_single_and_graph_replay():
             for a, b in zip(r["outputs"], ref):
                 assert torch.equal(a, b), f"replay {rep}"
         del junk
+
+
+def test_two_lane_batch_equals_single_requests():
+    """A batch of 17 requests (two lanes of 9 and 8 on two streams) equals
+    each request evaluated alone; so does the same batch as one lane (kernel
+    timing on) and as a graph replay, and a second two-lane run after them."""
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    _, W = wl.dense64_inputs()
+    envs = []
+    for k in range(17):
+        x = wl.rng(2000 + k).integers(-128, 128, size=64)
+        envs.append(_setup("n4096_3q", networks.dense64_layers(W), None, x, 300 + k % 3, 400 + k, with_oracle=False))
+    print("[gpu-net] two lanes, 17 requests", flush=True)
+    ctx, plan = envs[0]["ctx"], envs[0]["plan"]
+    reqs = [dict(rlk=e["req"]["rlk"], gks=e["req"]["gks"], inputs=e["req"]["inputs"],
+                 outputs=[ctx.empty_ct() for _ in e["req"]["outputs"]]) for e in envs]
+    singles = []
+    for e in envs:
+        e["plan"].evaluate(e["ctx"], [e["req"]])
+        torch.cuda.synchronize()
+        singles.append([o.clone() for o in e["req"]["outputs"]])
+
+    def check(tag):
+        for k, (r, ref) in enumerate(zip(reqs, singles)):
+            for a, b in zip(r["outputs"], ref):
+                assert torch.equal(a, b), f"{tag}: request {k}"
+        for r in reqs:
+            for o in r["outputs"]:
+                o.zero_()
+        torch.cuda.synchronize()
+
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    check("two lanes")
+    lola.timing_enable(ctx, True)
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    lola.timing_enable(ctx, False)
+    lola.kernel_timing(ctx)
+    check("one lane")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.evaluate(ctx, reqs, graph=True, stream=s)
+    s.synchronize()
+    check("graph")
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    check("two lanes again")
