@@ -237,6 +237,37 @@ int lola_export_ksk(lola_ctx *ctx, const uint32_t *ksk_dev, uint32_t *out_dev, l
 int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uint32_t n_limbs,
                    const uint32_t *prime_idx_host, int inverse, lola_stream stream);
 
+/* Batched NTT variants and their autotuner.  The batched limb transforms
+ * (lola_ntt_limbs, lola_to_coeff / lola_from_coeff, encoding, key generation
+ * and the executor's transforms) run one compiled variant per context:
+ *   split          how the log2(N) butterfly stages group into register
+ *                  passes, as decimal digits, first pass first (4442 at
+ *                  N = 16384: passes of 4, 4, 4 and 2 stages; one LDS
+ *                  exchange between passes);
+ *   limbs_per_wg   transforms each workgroup runs in turn (1, 2 or 4).
+ * Every variant gives the same words.  Variant 0 is the default.
+ * lola_ntt_variants lists them (count = how many; at most cap written; ms
+ * = 0).  lola_ntt_set_variant / _get_variant select by index.
+ * lola_ntt_autotune times every variant on the context's device: n_limbs
+ * limbs of pseudo-random residues (limb k modulo prime k mod L), one forward
+ * and one inverse batch per repetition, reps repetitions, timed with HIP
+ * events on `stream`; each variant's output is first compared with the
+ * default's (LOLA_E_DEVICE if any word differs).  It keeps the fastest
+ * (forward + inverse) as the context's variant, writes the index to *chosen
+ * and up to cap entries {split, limbs_per_wg, ms per repetition} to out.  It
+ * allocates 4 n_limbs N words of device scratch for the duration and
+ * synchronises `stream`. */
+typedef struct {
+    uint32_t split;
+    uint32_t limbs_per_wg;
+    float ms;
+} lola_ntt_variant;
+int lola_ntt_variants(const lola_ctx *ctx, lola_ntt_variant *out, uint32_t cap, uint32_t *count);
+int lola_ntt_get_variant(const lola_ctx *ctx, uint32_t *index);
+int lola_ntt_set_variant(lola_ctx *ctx, uint32_t index);
+int lola_ntt_autotune(lola_ctx *ctx, uint32_t n_limbs, uint32_t reps, lola_ntt_variant *out, uint32_t cap,
+                      uint32_t *chosen, lola_stream stream);
+
 /* ------------------------------------------------------- layer compiler */
 /* Lowers a layer list onto the operations above with the paper's vector
  * representations and matrix-vector recipes (Sec. 4.2: dense, sparse,

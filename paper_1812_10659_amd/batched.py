@@ -4,9 +4,10 @@ Per ciphertext: forward + inverse NTT of both components, a plaintext
 product, then pairs (2i, 2i+1) multiply and relinearise, and every ciphertext
 runs its own chain of 1..64 rotations (seeded, uneven) over the power-of-two
 steps and the row swap -- the chains in one persistent work-queue launch.
-The chains are also run wave by wave (batched key switches) for comparison,
-and the persistent launch's workgroup count is picked by a small autotuner
-whose choice is cached per (N, L) in a JSON file.
+The chains are also run wave by wave (batched key switches) for comparison.
+Two choices are autotuned and cached per (N, L) in a JSON file: the batched
+NTT's radix split and tile (limbs per workgroup), timed by the library over
+every compiled variant, and the persistent launch's workgroup count.
 
 Reported per primitive: time, ops/s and HBM GB/s on algorithmic bytes.
 Argument marshalling and timing only; every step runs in the library.
@@ -140,6 +141,35 @@ def autotune_chain_wg(ctx, ins, outs, tmps, steps, keys, N, L, candidates=(128, 
     return best, cache
 
 
+def autotune_ntt(ctx, N, L, n_limbs=2048, reps=3):
+    """Radix split and tile (limbs per workgroup) of the batched NTT, picked by
+    the library's autotuner (every variant timed on the device, forward +
+    inverse of n_limbs limbs, each checked word for word against the default
+    first); the choice is cached per (N, L) beside the chain workgroup count."""
+    path = os.path.join(AUTOTUNE_DIR, f"autotune_N{N}_L{L}.json")
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        cache = {}
+    variants = ctx.ntt_variants()
+    hit = cache.get("ntt_variant")
+    if hit and [hit["split"], hit["limbs_per_wg"]] in [list(v) for v in variants]:
+        ctx.ntt_set_variant([list(v) for v in variants].index([hit["split"], hit["limbs_per_wg"]]))
+        return cache
+    chosen, table = ctx.ntt_autotune(n_limbs=n_limbs, reps=reps)
+    cache.update({"ntt_variant": {"split": table[chosen][0], "limbs_per_wg": table[chosen][1]},
+                  "ntt_trials_ms": {f"{sp}/{lp}": round(ms, 4) for sp, lp, ms in table},
+                  "ntt_trial_limbs": n_limbs})
+    try:
+        os.makedirs(AUTOTUNE_DIR, exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f)
+    except OSError:
+        pass
+    return cache
+
+
 def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tune: bool = True) -> dict:
     p = wl.PARAMS["batch_n16384"]
     N, L = p.N, p.L
@@ -161,7 +191,10 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
     steps = [[lola.galois_element(N, "row_swap" if s == 0 else int(s)) for s in row] for row in raw_steps]
     torch.cuda.synchronize()
     out = {"n_ct": n_ct, "N": N, "L": L, "rotations": int(counts.sum())}
-    # 1. forward + inverse NTT of every limb of both components
+    # 1. forward + inverse NTT of every limb of both components, with the
+    # radix split and tile the autotuner picked (the default timed beside it)
+    ntt_cache = autotune_ntt(ctx, N, L) if tune else {}
+    chosen = ctx.ntt_variant()
     limbs = torch.stack(cts).reshape(-1, N)
     idx = [i % L for i in range(limbs.shape[0])]
     fwd = [None]
@@ -172,9 +205,17 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
     s = _timed(ntt_pair)
     back = ntt_pair()
     torch.cuda.synchronize()
+    ctx.ntt_set_variant(0)
+    s_default = _timed(ntt_pair)
+    same = bool(torch.equal(fwd[0], ctx.ntt_limbs(limbs, idx)))
+    ctx.ntt_set_variant(chosen)
     nl = 2 * limbs.shape[0]
+    sp, lp = ctx.ntt_variants()[chosen]
     out["ntt"] = {"limb_transforms": nl, "ms": round(s * 1e3, 3), "gbps": round(nl * 8 * N / s / 1e9, 1),
-                  "roundtrip_exact": bool(torch.equal(back, limbs))}
+                  "roundtrip_exact": bool(torch.equal(back, limbs)),
+                  "variant": {"split": sp, "limbs_per_wg": lp},
+                  "default_variant_ms": round(s_default * 1e3, 3), "equal_to_default": same,
+                  "autotune_ms": ntt_cache.get("ntt_trials_ms"), "autotune_limbs": ntt_cache.get("ntt_trial_limbs")}
     # 2. plaintext products
     prod = [ctx.empty_ct() for _ in range(n_ct)]
     s = _timed(lambda: mul_plain_batch(ctx, cts, pts, prod))

@@ -78,6 +78,8 @@ struct lola_ctx {
     std::vector<hipEvent_t> timing_events;   // pairs, in use
     std::vector<hipEvent_t> timing_pool;     // free events
     uint64_t timed_jobs = 0;
+    // batched NTT variant (index into the variant list of this N; 0 = default)
+    uint32_t ntt_variant = 0;
     uint32_t idxP() const { return L; }
     uint32_t idxB(uint32_t j) const { return L + 1 + j; }
     uint32_t idxT() const { return L + 1 + nB; }

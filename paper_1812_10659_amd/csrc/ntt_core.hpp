@@ -10,7 +10,8 @@
 // values in [0, 4q) and inverse values in [0, 2q) between stages.
 //
 // Work split: T = N/16 threads, 16 residues per thread.  Stages are grouped
-// into passes of (up to) 4; inside a pass each thread owns whole radix-16 (or
+// into passes of (up to) 4 (the radix split, a template choice: see
+// NttShape); inside a pass each thread owns whole radix-16 (or
 // smaller) sub-transforms and runs their butterflies in registers, so LDS is
 // touched once per pass (write 16, barrier, read 16).  The forward transform
 // starts in the layout of pass 0 (register k of thread t holds a[t + k T],
@@ -57,14 +58,49 @@ struct NttPass {
     LOLA_HD static uint32_t index(uint32_t tid, uint32_t r) { return base(tid, r / SUB) + (r % SUB) * STR; }
 };
 
-template <int LOGN>
+// Radix split: how the log2(N) stages group into passes.  SPLIT = 0 takes
+// passes of 4 stages from the first, the remainder last (4442 at N = 16384);
+// otherwise SPLIT lists the stages of each pass as decimal digits, first pass
+// first (e.g. 2444 or 4433), each between 1 and 4 and summing to log2(N).
+constexpr int split_npass(int logn, int split) {
+    if (split == 0) return (logn + NTT_LOGE - 1) / NTT_LOGE;
+    int n = 0;
+    for (int v = split; v > 0; v /= 10) ++n;
+    return n;
+}
+// Stages of pass p (0 = first).
+constexpr int split_width(int logn, int split, int p) {
+    if (split == 0) return (logn - p * NTT_LOGE) < NTT_LOGE ? (logn - p * NTT_LOGE) : NTT_LOGE;
+    int v = split;
+    for (int k = split_npass(logn, split) - 1; k > p; --k) v /= 10;
+    return v % 10;
+}
+// First stage of pass p.
+constexpr int split_s0(int logn, int split, int p) {
+    int s = 0;
+    for (int k = 0; k < p; ++k) s += split_width(logn, split, k);
+    return s;
+}
+constexpr bool split_valid(int logn, int split) {
+    if (split < 0) return false;
+    int total = 0;
+    for (int p = 0; p < split_npass(logn, split); ++p) {
+        const int w = split_width(logn, split, p);
+        if (w < 1 || w > NTT_LOGE) return false;
+        total += w;
+    }
+    return total == logn;
+}
+
+template <int LOGN, int SPLIT = 0>
 struct NttShape {
+    static_assert(split_valid(LOGN, SPLIT), "radix split must list passes of 1..4 stages summing to log2(N)");
     static constexpr int N = 1 << LOGN;
     static constexpr int T = N / NTT_E;
-    static constexpr int NPASS = (LOGN + NTT_LOGE - 1) / NTT_LOGE;
-    static constexpr int LAST_S0 = (NPASS - 1) * NTT_LOGE;
+    static constexpr int NPASS = split_npass(LOGN, SPLIT);
+    static constexpr int LAST_S0 = split_s0(LOGN, SPLIT, NPASS - 1);
     static constexpr int LAST_NS = LOGN - LAST_S0;
-    using First = NttPass<LOGN, 0, (LOGN < NTT_LOGE ? LOGN : NTT_LOGE)>;
+    using First = NttPass<LOGN, 0, split_width(LOGN, SPLIT, 0)>;
     using Last = NttPass<LOGN, LAST_S0, LAST_NS>;
 };
 
@@ -153,11 +189,11 @@ LOLA_HD void lds_to_regs(uint32_t (&x)[NTT_E], uint32_t tid, const uint32_t *sh)
     for (uint32_t r = 0; r < NTT_E; ++r) x[r] = sh[PS::index(tid, r)];
 }
 
-// Pass p of the forward transform covers stages [4p, min(4p+4, LOGN)).
-template <int LOGN, int P>
+// Pass P of the forward transform under radix split SPLIT.
+template <int LOGN, int P, int SPLIT = 0>
 struct FwdPassAt {
-    static constexpr int S0 = P * NTT_LOGE;
-    static constexpr int NS = (LOGN - S0) < NTT_LOGE ? (LOGN - S0) : NTT_LOGE;
+    static constexpr int S0 = split_s0(LOGN, SPLIT, P);
+    static constexpr int NS = split_width(LOGN, SPLIT, P);
 };
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -194,14 +230,14 @@ LOLA_HD void pass_exchange_sync() {
 // use (e.g. the caller alternates two buffers and the transform before the
 // previous one ended behind a workgroup barrier), so the first exchange
 // needs no barrier before its writes.
-template <int LOGN, int P = 0, bool FRESH = false>
+template <int LOGN, int P = 0, bool FRESH = false, int SPLIT = 0>
 struct FwdDriver {
     LOLA_HD static void run(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
-        constexpr int NPASS = NttShape<LOGN>::NPASS;
-        using PA = FwdPassAt<LOGN, P>;
+        constexpr int NPASS = NttShape<LOGN, SPLIT>::NPASS;
+        using PA = FwdPassAt<LOGN, P, SPLIT>;
         fwd_pass_regs<LOGN, PA::S0, PA::NS>(x, tid, tw, q);
         if constexpr (P + 1 < NPASS) {
-            using PB = FwdPassAt<LOGN, P + 1>;
+            using PB = FwdPassAt<LOGN, P + 1, SPLIT>;
             // The first exchange of a transform waits for every earlier LDS
             // reader of the workgroup; later ones only for this wave when
             // both layouts keep each wave on its own block.
@@ -213,86 +249,88 @@ struct FwdDriver {
             regs_to_lds<LOGN, PA::S0, PA::NS>(x, tid, sh);
             pass_exchange_sync<LOGN, PA, PB>();
             lds_to_regs<LOGN, PB::S0, PB::NS>(x, tid, sh);
-            FwdDriver<LOGN, P + 1, FRESH>::run(x, tid, sh, tw, q);
+            FwdDriver<LOGN, P + 1, FRESH, SPLIT>::run(x, tid, sh, tw, q);
         }
     }
 };
 
-template <int LOGN, bool FRESH = false>
+template <int LOGN, bool FRESH = false, int SPLIT = 0>
 LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
-    FwdDriver<LOGN, 0, FRESH>::run(x, tid, sh, tw, q);
+    FwdDriver<LOGN, 0, FRESH, SPLIT>::run(x, tid, sh, tw, q);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(csub(x[r], 2 * q), q);
 }
 
 // Inverse: x enters in the last forward pass's layout (values in [0, 2q))
 // and leaves in the first pass's layout, reduced to [0, q).
-template <int LOGN, int P>
+template <int LOGN, int P, int SPLIT = 0>
 struct InvDriver {
     LOLA_HD static void run(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *itw,
                             const ModConst &mc) {
-        using PA = FwdPassAt<LOGN, P>;
+        using PA = FwdPassAt<LOGN, P, SPLIT>;
         inv_pass_regs<LOGN, PA::S0, PA::NS, (P == 0)>(x, tid, itw, mc);
         if constexpr (P > 0) {
-            using PB = FwdPassAt<LOGN, P - 1>;
-            if constexpr (P == NttShape<LOGN>::NPASS - 1) LOLA_BARRIER();
+            using PB = FwdPassAt<LOGN, P - 1, SPLIT>;
+            if constexpr (P == NttShape<LOGN, SPLIT>::NPASS - 1) LOLA_BARRIER();
             else pass_exchange_sync<LOGN, PA, PB>();
             regs_to_lds<LOGN, PA::S0, PA::NS>(x, tid, sh);
             pass_exchange_sync<LOGN, PA, PB>();
             lds_to_regs<LOGN, PB::S0, PB::NS>(x, tid, sh);
-            InvDriver<LOGN, P - 1>::run(x, tid, sh, itw, mc);
+            InvDriver<LOGN, P - 1, SPLIT>::run(x, tid, sh, itw, mc);
         }
     }
 };
 
-template <int LOGN>
+template <int LOGN, int SPLIT = 0>
 LOLA_HD void ntt_inv_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *itw,
                           const ModConst &mc) {
-    InvDriver<LOGN, NttShape<LOGN>::NPASS - 1>::run(x, tid, sh, itw, mc);
+    InvDriver<LOGN, NttShape<LOGN, SPLIT>::NPASS - 1, SPLIT>::run(x, tid, sh, itw, mc);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(x[r], mc.q);
 }
 
 // Global index of register r in the forward input / inverse output layout.
-template <int LOGN>
-LOLA_HD uint32_t natural_index(uint32_t tid, uint32_t r) { return NttShape<LOGN>::First::index(tid, r); }
+template <int LOGN, int SPLIT = 0>
+LOLA_HD uint32_t natural_index(uint32_t tid, uint32_t r) { return NttShape<LOGN, SPLIT>::First::index(tid, r); }
 // Global index of register r in the forward output / inverse input layout.
-template <int LOGN>
-LOLA_HD uint32_t spectral_index(uint32_t tid, uint32_t r) { return NttShape<LOGN>::Last::index(tid, r); }
+template <int LOGN, int SPLIT = 0>
+LOLA_HD uint32_t spectral_index(uint32_t tid, uint32_t r) { return NttShape<LOGN, SPLIT>::Last::index(tid, r); }
 
 // Registers r..r+3 of the forward output layout hold four consecutive,
 // 4-aligned residues when the last pass's sub-transforms have at least four
 // elements (stride 1, base a multiple of the length): then they move with one
 // 16-byte access per lane and neighbouring lanes touch neighbouring 16 bytes.
-template <int LOGN>
-constexpr bool spectral_vec4() { return NttShape<LOGN>::Last::SUB >= 4 && NttShape<LOGN>::Last::STR == 1; }
+template <int LOGN, int SPLIT = 0>
+constexpr bool spectral_vec4() {
+    return NttShape<LOGN, SPLIT>::Last::SUB >= 4 && NttShape<LOGN, SPLIT>::Last::STR == 1;
+}
 
-template <int LOGN>
+template <int LOGN, int SPLIT = 0>
 LOLA_HD void load_spectral(GBuf b, uint32_t tid, uint32_t (&y)[NTT_E]) {
-    if constexpr (spectral_vec4<LOGN>()) {
+    if constexpr (spectral_vec4<LOGN, SPLIT>()) {
 #pragma unroll
         for (int r = 0; r < NTT_E; r += 4) {
-            const u32x4 v = gld4(b, spectral_index<LOGN>(tid, r));
+            const u32x4 v = gld4(b, spectral_index<LOGN, SPLIT>(tid, r));
             y[r] = v.x, y[r + 1] = v.y, y[r + 2] = v.z, y[r + 3] = v.w;
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) y[r] = gld(b, spectral_index<LOGN>(tid, r));
+        for (int r = 0; r < NTT_E; ++r) y[r] = gld(b, spectral_index<LOGN, SPLIT>(tid, r));
     }
 }
 
-template <int LOGN>
+template <int LOGN, int SPLIT = 0>
 LOLA_HD void store_spectral(GBuf b, uint32_t tid, const uint32_t (&y)[NTT_E]) {
-    if constexpr (spectral_vec4<LOGN>()) {
+    if constexpr (spectral_vec4<LOGN, SPLIT>()) {
 #pragma unroll
         for (int r = 0; r < NTT_E; r += 4) {
             u32x4 v;
             v.x = y[r], v.y = y[r + 1], v.z = y[r + 2], v.w = y[r + 3];
-            gst4(b, spectral_index<LOGN>(tid, r), v);
+            gst4(b, spectral_index<LOGN, SPLIT>(tid, r), v);
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) gst(b, spectral_index<LOGN>(tid, r), y[r]);
+        for (int r = 0; r < NTT_E; ++r) gst(b, spectral_index<LOGN, SPLIT>(tid, r), y[r]);
     }
 }
 

@@ -53,6 +53,10 @@ class KsDesc(ctypes.Structure):
 _lib = None
 
 
+class NttVariant(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_uint32), ("limbs_per_wg", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+
 def lib() -> ctypes.CDLL:
     """The loaded library; raises if it has not been built."""
     global _lib
@@ -90,6 +94,10 @@ def lib() -> ctypes.CDLL:
             "lola_export_pk": [vp, vp, vp, vp],
             "lola_export_ksk": [vp, vp, vp, vp],
             "lola_ntt_limbs": [vp, vp, vp, u32, ctypes.POINTER(u32), i32, vp],
+            "lola_ntt_variants": [vp, ctypes.POINTER(NttVariant), u32, ctypes.POINTER(u32)],
+            "lola_ntt_get_variant": [vp, ctypes.POINTER(u32)],
+            "lola_ntt_set_variant": [vp, u32],
+            "lola_ntt_autotune": [vp, u32, u32, ctypes.POINTER(NttVariant), u32, ctypes.POINTER(u32), vp],
             "lola_strerror": [i32],
             "lola_last_error": [],
         }
@@ -284,6 +292,31 @@ class Context:
         out = torch.empty_like(k)
         _check(lib().lola_export_ksk(self.h, _p(k), _p(out), _stream()))
         return out
+
+    def ntt_variants(self) -> list:
+        """[(split, limbs_per_wg)] of the batched NTT variants compiled for this N."""
+        n = ctypes.c_uint32()
+        _check(lib().lola_ntt_variants(self.h, None, 0, ctypes.byref(n)))
+        arr = (NttVariant * n.value)()
+        _check(lib().lola_ntt_variants(self.h, arr, n.value, ctypes.byref(n)))
+        return [(v.split, v.limbs_per_wg) for v in arr]
+
+    def ntt_variant(self) -> int:
+        k = ctypes.c_uint32()
+        _check(lib().lola_ntt_get_variant(self.h, ctypes.byref(k)))
+        return k.value
+
+    def ntt_set_variant(self, index: int) -> None:
+        _check(lib().lola_ntt_set_variant(self.h, int(index)))
+
+    def ntt_autotune(self, n_limbs: int = 512, reps: int = 5):
+        """Times every batched NTT variant (forward + inverse of n_limbs limbs),
+        keeps the fastest; returns (chosen index, [(split, limbs_per_wg, ms)])."""
+        n = len(self.ntt_variants())
+        arr = (NttVariant * n)()
+        k = ctypes.c_uint32()
+        _check(lib().lola_ntt_autotune(self.h, int(n_limbs), int(reps), arr, n, ctypes.byref(k), _stream()))
+        return k.value, [(v.split, v.limbs_per_wg, float(v.ms)) for v in arr]
 
     def ntt_limbs(self, x: torch.Tensor, prime_idx: Iterable[int], inverse: bool = False) -> torch.Tensor:
         idx = list(prime_idx)

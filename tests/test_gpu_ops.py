@@ -84,6 +84,58 @@ def test_ntt_is_evaluation_at_odd_powers(env):
     assert np.array_equal(back, x)
 
 
+def _ntt_case(env):
+    """Five limbs (first and last data prime, P, t, first prime again: an odd
+    count, so the last workgroup of the 2- and 4-limb tiles is partial) with
+    the oracle's evaluation at odd powers of the minimal root, bit-reversed."""
+    from paper_1812_10659_amd import lola
+    ctx, p = env["ctx"], env["p"]
+    primes = list(p.q) + [p.P] + [None] * ctx.n_aux + [p.t]
+    idx = [0, p.L - 1, p.L, len(primes) - 1, 0]
+    rs = np.random.default_rng(7)
+    x = np.stack([rs.integers(0, primes[i], p.N) for i in idx]).astype(np.uint32)
+    bits = p.N.bit_length() - 1
+    br = np.array([_bitrev(k, bits) for k in range(p.N)])
+    exp = []
+    for row, i in enumerate(idx):
+        ev = np.empty(p.N, np.uint64)
+        bfv.lib().or_eval_odd(x[row].astype(np.uint64), ev, p.N, primes[i], bfv.min_root_2n(primes[i], p.N))
+        exp.append(ev[br])
+    return idx, x, lola.from_numpy_u32(x, ctx.device), np.stack(exp)
+
+
+def test_every_ntt_variant_is_evaluation_at_odd_powers(env):
+    """Every compiled batched-NTT variant (radix split x limbs per workgroup)
+    gives the oracle's evaluation and inverts exactly."""
+    from paper_1812_10659_amd import lola
+    ctx = env["ctx"]
+    idx, x, xd, exp = _ntt_case(env)
+    variants = ctx.ntt_variants()
+    assert variants[0][1] == 1 and len(variants) >= 12
+    try:
+        for v, (split, lpw) in enumerate(variants):
+            ctx.ntt_set_variant(v)
+            y = _u32(ctx.ntt_limbs(xd, idx))
+            assert np.array_equal(y.astype(np.uint64), exp), f"variant {split}/{lpw}"
+            back = _u32(ctx.ntt_limbs(lola.from_numpy_u32(y, ctx.device), idx, inverse=True))
+            assert np.array_equal(back, x), f"variant {split}/{lpw} inverse"
+    finally:
+        ctx.ntt_set_variant(0)
+
+
+def test_ntt_autotune_picks_fastest_and_keeps_results(env):
+    ctx = env["ctx"]
+    idx, x, xd, exp = _ntt_case(env)
+    try:
+        chosen, table = ctx.ntt_autotune(n_limbs=2 * env["p"].L + 3, reps=2)
+        assert ctx.ntt_variant() == chosen and len(table) == len(ctx.ntt_variants())
+        ms = [t[2] for t in table]
+        assert all(m > 0 for m in ms) and ms[chosen] == min(ms)
+        assert np.array_equal(_u32(ctx.ntt_limbs(xd, idx)).astype(np.uint64), exp)
+    finally:
+        ctx.ntt_set_variant(0)
+
+
 def test_keys_match_oracle(env):
     ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
     s_res = octx.small_to_limbs(ok.sk.s, octx.moduli)
