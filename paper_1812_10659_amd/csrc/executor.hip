@@ -102,7 +102,7 @@ int emit_level(const lola_ctx *ctx, const lola_plan *p, const ReqView &rv, uint3
 }
 
 size_t level_scratch_words(const lola_ctx *ctx, uint32_t ks_chunk, uint32_t mul_chunk) {
-    return std::max(ks_chunk * ks_scratch_words(ctx), mul_chunk * mul_scratch_words(ctx));
+    return std::max(ks_chunk_words(ctx, ks_chunk), mul_chunk * mul_scratch_words(ctx));
 }
 
 void program_level(const lola_ctx *ctx, Program &prog, LevelJobs &jobs, uint32_t *scratch, uint32_t ks_chunk,

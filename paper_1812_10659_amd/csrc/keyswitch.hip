@@ -46,6 +46,38 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
     ks_stage_inner<LOGN>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
 }
 
+// Latency form of the inner stage (launches of at most KS_TERM_MAX_JOBS
+// jobs): L (L+1) workgroups per job, one digit term each, then 2 (L+1) that
+// fold the terms.  The special prime's units come first, as above.  Grid =
+// jobs x units, workgroup k taking unit k mod units of job k / units: the
+// units of one job spread over all XCDs (few jobs, so latency, not key reuse
+// through L2, is what matters).
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_term_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                    uint32_t L, const ModConst *__restrict__ mcs,
+                                                                    const TwPair *__restrict__ tw) {
+    __shared__ uint32_t sh[1 << LOGN];
+    const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
+    if (jb >= n) return;
+    const KsJob job = jobs[jb];
+    const uint32_t jr = unit / L, i = unit % L;
+    const uint32_t j = jr == 0 ? L : jr - 1;
+    ks_stage_term<LOGN>(job.key, job.scratch, j, i, L, sh, mcs[j], tw);
+}
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_fold_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                    uint32_t L, const ModConst *__restrict__ mcs,
+                                                                    const TwPair *__restrict__ itw) {
+    __shared__ uint32_t sh[1 << LOGN];
+    const uint32_t units = 2 * (L + 1), jb = blockIdx.x / units, unit = blockIdx.x % units;
+    if (jb >= n) return;
+    const KsJob job = jobs[jb];
+    const uint32_t jr = unit / 2, c = unit % 2;
+    const uint32_t j = jr == 0 ? L : jr - 1;
+    ks_stage_fold<LOGN>(job.scratch, j, c, L, sh, mcs[j], itw);
+}
+
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                        uint32_t L, const ModConst *__restrict__ mcs,
@@ -62,6 +94,21 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const K
 
 size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }
 
+// Launches of at most this many jobs take the latency form of the inner
+// stage (ks_term + ks_fold): L (L+1) workgroups per job instead of L+1, each
+// one transform deep instead of L, at the price of 2 L (L+1) N more scratch
+// words per job.
+static constexpr uint32_t KS_TERM_MAX_JOBS = 16;
+static bool ks_term_mode(uint32_t n) { return n <= KS_TERM_MAX_JOBS; }
+static size_t ks_job_words(const lola_ctx *ctx, uint32_t n) {
+    const size_t L = ctx->L;
+    return ks_scratch_words(ctx) + (ks_term_mode(n) ? 2 * L * (L + 1) * ctx->N : 0);
+}
+size_t ks_launch_words(const lola_ctx *ctx, uint32_t n) { return (size_t)n * ks_job_words(ctx, n); }
+size_t ks_chunk_words(const lola_ctx *ctx, uint32_t chunk) {
+    return std::max(ks_launch_words(ctx, chunk), ks_launch_words(ctx, std::min(chunk, KS_TERM_MAX_JOBS)));
+}
+
 int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
     if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
@@ -72,13 +119,21 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t
         if (rc) return rc;
         ctx->timed_jobs += n;
     }
+    const bool term = ks_term_mode(n);
 #define LOLA_KS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
         hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L, ctx->d_mc,    \
                            ctx->d_itw);                                                                       \
         if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                             \
-        hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L, ctx->d_mc, \
-                           ctx->d_tw, ctx->d_itw);                                                            \
+        if (term) {                                                                                          \
+            hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, ctx->d_mc, \
+                               ctx->d_tw);                                                                    \
+            hipLaunchKernelGGL(ks_fold_kernel<LG>, dim3(n * 2 * (L + 1)), block, 0, s, d_jobs, n, L, ctx->d_mc,  \
+                               ctx->d_itw);                                                                   \
+        } else {                                                                                             \
+            hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L,      \
+                               ctx->d_mc, ctx->d_tw, ctx->d_itw);                                             \
+        }                                                                                                    \
         if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                             \
         hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, L,         \
                            ctx->d_mc, ctx->d_tw, ctx->d_mrc);                                                 \
@@ -101,12 +156,12 @@ static constexpr uint32_t KS_CHUNK = 128;
 
 void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs, uint32_t *scratch,
                        uint32_t chunk) {
-    const size_t per = ks_scratch_words(ctx);
     // jobs that share a key side by side (see xcd_job_unit); the order of the
     // jobs of one launch does not change any result
     std::stable_sort(jobs.begin(), jobs.end(), [](const KsJob &a, const KsJob &b) { return a.key < b.key; });
     for (size_t off = 0; off < jobs.size(); off += chunk) {
         const size_t n = std::min<size_t>(chunk, jobs.size() - off);
+        const size_t per = ks_job_words(ctx, (uint32_t)n);   // fits in ks_chunk_words(ctx, chunk)
         std::vector<KsJob> part(jobs.begin() + off, jobs.begin() + off + n);
         for (size_t k = 0; k < n; ++k) part[k].scratch = scratch + per * k;
         p.launch(LK_KS, part);
@@ -115,11 +170,10 @@ void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs,
 }
 
 int keyswitch_host_jobs(lola_ctx *ctx, std::vector<KsJob> &jobs, hipStream_t s) {
-    const size_t per = ks_scratch_words(ctx);
     for (size_t off = 0; off < jobs.size(); off += KS_CHUNK) {
         const uint32_t n = (uint32_t)std::min<size_t>(KS_CHUNK, jobs.size() - off);
         void *buf = nullptr;
-        int rc = scratch_get(ctx, per * n * 4, &buf);
+        int rc = scratch_get(ctx, ks_launch_words(ctx, n) * 4, &buf);
         if (rc) return rc;
         Program p;
         program_keyswitch(ctx, p, std::vector<KsJob>(jobs.begin() + off, jobs.begin() + off + n),
@@ -138,8 +192,8 @@ extern "C" {
 int lola_reserve(lola_ctx *ctx, uint32_t n_ct) {
     if (!ctx) return set_error(LOLA_E_INVAL, "null argument");
     void *buf = nullptr;
-    const size_t per = std::max<size_t>(ks_scratch_words(ctx), mul_scratch_words(ctx));
-    return scratch_get(ctx, per * std::min<uint32_t>(std::max<uint32_t>(n_ct, 1), KS_CHUNK) * 4, &buf);
+    const uint32_t n = std::min<uint32_t>(std::max<uint32_t>(n_ct, 1), KS_CHUNK);
+    return scratch_get(ctx, std::max(ks_chunk_words(ctx, n), n * mul_scratch_words(ctx)) * 4, &buf);
 }
 
 int lola_keyswitch_batch(lola_ctx *ctx, const lola_ks_desc *d, uint32_t n, lola_stream stream) {

@@ -86,11 +86,20 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
 // transform before it, and so has finished the one before that, the last
 // user of the same half.  The caller must not have left reads of sh pending
 // (a workgroup barrier since its last use of sh).
+// Radix split of the inner stage's transforms (see NttShape).  Every stage
+// reads and writes the canonical global layouts, so each may take its own:
+// at N = 16384 passes of 4, 4, 3 and 3 stages measured 2% faster than the
+// default 4, 4, 4, 2 for this stage, while the digit and mod-down stages were
+// faster with the default.
+template <int LOGN>
+constexpr int ks_inner_split() { return LOGN == 14 ? 4433 : 0; }
+
 template <int LOGN>
 __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t L,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
                                                const TwPair *itw) {
     constexpr uint32_t N = 1u << LOGN;
+    constexpr int KSI = ks_inner_split<LOGN>();
     const uint32_t M = L + 1;
     // 64-bit accumulators: every term is x * key with x < q (a transform's
     // output is canonical) and key < q, so at most 12 digits sum below
@@ -104,14 +113,14 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
         asm volatile("" : "+v"(tid));
         uint32_t x[NTT_E];
         if (i == j) {
-            load_spectral<LOGN>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
+            load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
         } else {
             const GBuf D = gbuf(scratch + ((size_t)i << LOGN), N);
 #pragma unroll
-            for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN>(tid, r)), mc.q, mc.one_shoup);
+            for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
-            ntt_fwd_regs<LOGN, true>(x, tid, sh + (half << LOGN), tw + ((size_t)jj << LOGN), mc.q);
+            ntt_fwd_regs<LOGN, true, KSI>(x, tid, sh + (half << LOGN), tw + ((size_t)jj << LOGN), mc.q);
             half ^= 1u;
         }
         // The key offset passes through an opaque copy placed after the
@@ -119,8 +128,8 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
         uint32_t koff = i * 2 * M + j;
         asm volatile("" : "+s"(koff));
         uint32_t kb[NTT_E], ka[NTT_E];
-        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kb);
-        load_spectral<LOGN>(gbuf(key + ((size_t)(koff + M) << LOGN), N), tid, ka);
+        load_spectral<LOGN, KSI>(gbuf(key + ((size_t)koff << LOGN), N), tid, kb);
+        load_spectral<LOGN, KSI>(gbuf(key + ((size_t)(koff + M) << LOGN), N), tid, ka);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) {
             a0[r] += (uint64_t)x[r] * kb[r];
@@ -133,27 +142,95 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
     if (j < L) {
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
-        store_spectral<LOGN>(gbuf(scratch + ((size_t)(2 * L + j) << LOGN), N), tid, u);
+        store_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(2 * L + j) << LOGN), N), tid, u);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
-        store_spectral<LOGN>(gbuf(scratch + ((size_t)(3 * L + j) << LOGN), N), tid, u);
+        store_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(3 * L + j) << LOGN), N), tid, u);
     } else {
         const GBuf UP0 = gbuf(scratch + ((size_t)(4 * L) << LOGN), N);
         const GBuf UP1 = gbuf(scratch + ((size_t)(4 * L + 1) << LOGN), N);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
-        ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
+        ntt_inv_regs<LOGN, KSI>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) gst(UP0, natural_index<LOGN>(tid, r), u[r]);
+        for (int r = 0; r < NTT_E; ++r) gst(UP0, natural_index<LOGN, KSI>(tid, r), u[r]);
         uint32_t tid2 = tid;
         asm volatile("" : "+v"(tid2));
         uint32_t jj = j;
         asm volatile("" : "+s"(jj));
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
-        ntt_inv_regs<LOGN>(u, tid2, sh, itw + ((size_t)jj << LOGN), mc);
+        ntt_inv_regs<LOGN, KSI>(u, tid2, sh, itw + ((size_t)jj << LOGN), mc);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) gst(UP1, natural_index<LOGN>(tid2, r), u[r]);
+        for (int r = 0; r < NTT_E; ++r) gst(UP1, natural_index<LOGN, KSI>(tid2, r), u[r]);
+    }
+}
+
+// Stage 2 split for launches of few jobs (latency): the term of digit i for
+// target modulus m_j alone, (x_i mod m_j) * key[i][c][j] for c = 0, 1, by one
+// workgroup, written canonical to the job's term area; ks_stage_fold then adds
+// the L terms of each (j, c).  A sum of Montgomery reductions is congruent to
+// the reduction of the sum, and both are canonical, so the words equal those
+// of ks_stage_inner.  Term area: limb 4L + 2 + 2 (j L + i) + c of the job's
+// scratch.
+__host__ __device__ constexpr size_t ks_term_limb(uint32_t L, uint32_t j, uint32_t i, uint32_t c) {
+    return (size_t)(4 * L + 2) + 2 * ((size_t)j * L + i) + c;
+}
+
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_term(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t i,
+                                              uint32_t L, uint32_t *sh, const ModConst &mc, const TwPair *tw) {
+    constexpr uint32_t N = 1u << LOGN;
+    constexpr int KSI = ks_inner_split<LOGN>();
+    const uint32_t M = L + 1;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t x[NTT_E];
+    if (i == j) {
+        load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
+    } else {
+        const GBuf D = gbuf(scratch + ((size_t)i << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
+        ntt_fwd_regs<LOGN, false, KSI>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
+    }
+    uint32_t koff = i * 2 * M + j;
+    asm volatile("" : "+s"(koff));
+    uint32_t kv[NTT_E], u[NTT_E];
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c) {
+        load_spectral<LOGN, KSI>(gbuf(key + ((size_t)(koff + c * M) << LOGN), N), tid, kv);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) {
+            const uint64_t a = (uint64_t)x[r] * kv[r];
+            u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mc);
+        }
+        store_spectral<LOGN, KSI>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, u);
+    }
+}
+
+// Fold for (target m_j, component c): the sum of the L terms, stored where
+// ks_stage_inner stores its result (U, or for P back in coefficients, UP).
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L, uint32_t *sh,
+                                              const ModConst &mc, const TwPair *itw) {
+    constexpr uint32_t N = 1u << LOGN;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t u[NTT_E], v[NTT_E];
+    load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, 0, c) << LOGN), N), tid, u);
+    for (uint32_t i = 1; i < L; ++i) {
+        load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, v);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = add_mod(u[r], v[r], mc.q);
+    }
+    if (j < L) {
+        store_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + j) << LOGN), N), tid, u);
+    } else {
+        ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
+        const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
     }
 }
 

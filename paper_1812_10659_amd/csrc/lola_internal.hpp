@@ -170,6 +170,8 @@ int keyswitch_host_jobs(lola_ctx *ctx, std::vector<KsJob> &jobs, hipStream_t s);
 int mul_batch(lola_ctx *ctx, uint32_t n, const uint32_t *const *a, const uint32_t *const *b,
               uint32_t *const *out3, hipStream_t s);
 size_t mul_scratch_words(const lola_ctx *ctx);   // per pair
-size_t ks_scratch_words(const lola_ctx *ctx);    // per key switch job
+size_t ks_scratch_words(const lola_ctx *ctx);    // per key switch job, launches of many jobs
+size_t ks_launch_words(const lola_ctx *ctx, uint32_t n);     // a launch of n jobs
+size_t ks_chunk_words(const lola_ctx *ctx, uint32_t chunk);  // any launch of at most chunk jobs
 
 }  // namespace lola

@@ -236,3 +236,26 @@ def test_keyswitch_batch_ragged(env):
     outs = ctx.keyswitch_batch(items)
     for o, r in zip(outs, refs):
         assert np.array_equal(_down(ctx, o), np.stack(r))
+
+
+@pytest.mark.parametrize("n_jobs", [1, 16, 17, 40])
+def test_keyswitch_both_inner_forms(env, n_jobs):
+    """Launches of at most 16 jobs split the key inner product into one
+    workgroup per (prime, digit) term plus a fold; larger ones accumulate all
+    digits per prime.  Both give the oracle's words (16 and 17 jobs sit on
+    either side of the switch)."""
+    ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
+    c1, c2 = env["c"]
+    c3 = bfv.mul(octx, c1, c2)
+    base, refs = [], []
+    for k, step in enumerate([1, bfv.ROW_SWAP, -1, 7]):
+        src = c1 if k % 2 == 0 else c2
+        g = bfv.galois_element(env["p"].N, step)
+        base.append((_up(ctx, src), env["gks"][g], g))
+        refs.append(bfv.rotate(octx, src, step, ok))
+    base.append((_up(ctx, c3), env["rlk"], 0))
+    refs.append(bfv.relin(octx, c3, ok.rlk))
+    items = [base[k % len(base)] for k in range(n_jobs)]
+    outs = ctx.keyswitch_batch(items)
+    for k, o in enumerate(outs):
+        assert np.array_equal(_down(ctx, o), np.stack(refs[k % len(base)])), f"job {k} of {n_jobs}"
