@@ -44,7 +44,7 @@ MAC_OPS = 7                                 # Montgomery product + modular add
 # copy (FETCH_SIZE read 0.5 GiB: x2.0; WRITE_SIZE read 1 GiB: x1.0).  These
 # count L2 misses, so reads served by the last-level cache count too.  Valid
 # only for kernel sources with this digest; otherwise the traffic is null.
-KS_INNER_TRAFFIC = {"digest": "6ce2826f604d3ec2", "fetch_per_job": 9.0165e6, "write_per_job": 1.0486e6}
+KS_INNER_TRAFFIC = {"digest": "ce8493b15debb868", "fetch_per_job": 5.5925e6, "write_per_job": 1.0486e6}
 KS_INNER_SOURCES = ["keyswitch.hip", "ks_core.hpp", "ntt_core.hpp", "modarith.hpp", "lola_internal.hpp"]
 
 
@@ -89,6 +89,8 @@ def main():
                     help="arrival rate of a second serving run above what one-at-a-time can sustain (0 = skip)")
     ap.add_argument("--no-integer-logits", action="store_true",
                     help="skip the run under seven plaintext moduli (exact integer logits by CRT)")
+    ap.add_argument("--lanes", type=int, default=2, choices=(1, 2),
+                    help="lanes of the batched evaluation (2: halves of the batch on two streams)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed MNIST steps and latency runs: no other network, batched, serving "
                          "or CPU section (for profiler runs whose per-kernel sums must cover that workload alone)")
@@ -123,6 +125,7 @@ def main():
     ctx = lola.Context(p)
     plan = lola.Plan(p, networks.mnist_layers(w))
     plan.load(ctx)
+    plan.set_lanes(args.lanes)
     gal = plan.galois()
     B, C = args.batch, max(1, min(args.clients, args.batch))
     keys = []
@@ -240,7 +243,7 @@ def main():
                             "rotations": plan.info["n_rotations"], "mul_plain": plan.info["n_mul_plain"],
                             "mul_scalar": plan.info["n_mul_scalar"], "squares": plan.info["n_square"],
                             "output_messages": plan.info["n_outputs"]},
-                   "batch_requests": B, "client_key_sets": C, "parallelism": "single GPU"},
+                   "batch_requests": B, "client_key_sets": C, "lanes": args.lanes, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "single_request_inferences_per_s": round(1e3 / float(np.median(lat)), 2)},

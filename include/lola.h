@@ -397,11 +397,20 @@ typedef struct {
  * and inputs).  Ops are grouped into waves of independent operations; every
  * op kind of a wave runs as one batched launch over all requests.  Output
  * buffers must not alias inputs.  The plan owns its device workspace
- * (ciphertext registers and scratch), sized for the largest n_req seen. */
+ * (ciphertext registers and scratch), sized for the largest n_req seen.
+ * Batches of 16 or more requests run as two lanes: the first half on
+ * `stream`, the second on a stream the plan owns (non-blocking, default
+ * priority) that waits for `stream`'s earlier work and is waited for by it,
+ * so the call stays ordered on `stream` like a single-stream one.  Each lane
+ * has its own workspace.  With kernel timing on (lola_timing_enable), or
+ * after lola_plan_set_lanes(plan, 1), a batch runs as one lane. */
 int lola_evaluate(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint32_t n_req,
                   lola_stream stream);
+/* Upper bound on the lanes of lola_evaluate: 1 or 2 (the default). */
+int lola_plan_set_lanes(lola_plan *plan, uint32_t max_lanes);
 /* Same, replayed through a HIP graph captured on the first call for this
- * exact set of buffers (re-captured when any pointer or n_req changes). */
+ * exact set of buffers (re-captured when any pointer or n_req changes); one
+ * lane. */
 int lola_evaluate_graph(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint32_t n_req,
                         lola_stream stream);
 

@@ -358,7 +358,7 @@ int lola_evaluate(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_
     // two lanes for batches large enough that each half still fills the
     // launches: kernels of one half run in the other's launch tails.  Kernel
     // timing measures launches alone, so it keeps one lane.
-    const uint32_t n_lanes = (!ctx->timing && n >= EXEC_LANE_MIN_REQUESTS) ? 2 : 1;
+    const uint32_t n_lanes = (!ctx->timing && n >= EXEC_LANE_MIN_REQUESTS && p->max_lanes >= 2) ? 2 : 1;
     int rc = prepare(ctx, p, reqs, n, s, n_lanes);
     if (rc) return rc;
     if (n_lanes == 1) return program_run(ctx, p->lanes[0].prog, p->lanes[0].d_blob, s);
@@ -374,6 +374,13 @@ int lola_evaluate(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_
     LOLA_HIP(hipEventRecord(p->join_ev, p->side_stream));
     LOLA_HIP(hipStreamWaitEvent(s, p->join_ev, 0));
     return rc;
+}
+
+int lola_plan_set_lanes(lola_plan *p, uint32_t max_lanes) {
+    if (!p) return set_error(LOLA_E_INVAL, "null argument");
+    if (max_lanes < 1 || max_lanes > 2) return set_error(LOLA_E_INVAL, "lanes must be 1 or 2");
+    p->max_lanes = max_lanes;
+    return LOLA_OK;
 }
 
 int lola_evaluate_graph(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n, lola_stream stream) {

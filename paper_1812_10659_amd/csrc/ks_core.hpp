@@ -94,12 +94,11 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
 template <int LOGN>
 constexpr int ks_inner_split() { return LOGN == 14 ? 4433 : 0; }
 
-template <int LOGN>
+template <int LOGN, int KSI = ks_inner_split<LOGN>()>
 __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t L,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
                                                const TwPair *itw) {
     constexpr uint32_t N = 1u << LOGN;
-    constexpr int KSI = ks_inner_split<LOGN>();
     const uint32_t M = L + 1;
     // 64-bit accumulators: every term is x * key with x < q (a transform's
     // output is canonical) and key < q, so at most 12 digits sum below

@@ -14,8 +14,10 @@
 
 namespace lola {
 
+// Launch bound: at least 8 waves per SIMD, i.e. at most 64 VGPRs, so two
+// 1024-thread workgroups (64 KiB of LDS each) fit one CU at N = 16384.
 template <int LOGN, int SPLIT, int LPW>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ntt_jobs_kernel(
+__global__ __launch_bounds__((1 << LOGN) / NTT_E, 8) void ntt_jobs_kernel(
     const NttJob *__restrict__ jobs, uint32_t n, const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw,
     const TwPair *__restrict__ itw, uint32_t t, const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[1 << LOGN];

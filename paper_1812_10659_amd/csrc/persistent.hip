@@ -39,7 +39,9 @@ __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key
     for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN>(c1, g, scr, i, L, sh, mcs[i], itw);
     __syncthreads();
     for (uint32_t j = 0; j <= L; ++j) {
-        ks_stage_inner<LOGN>(key, scr, j, L, sh, mcs[j], tw, itw);
+        // the default radix split here: the 4433 split that suits the
+        // batched inner kernel measured slower inside this larger kernel
+        ks_stage_inner<LOGN, 0>(key, scr, j, L, sh, mcs[j], tw, itw);
         __syncthreads();   // the next target's transforms reuse both LDS halves
     }
     const uint32_t P = mcs[L].q;

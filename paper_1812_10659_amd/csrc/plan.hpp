@@ -68,6 +68,7 @@ struct lola_plan {
     // or as two lanes (halves of the batch), the second on side_stream, forked
     // from and joined back to the caller's stream with events
     lola::ExecLane lanes[2];
+    uint32_t max_lanes = 2;                     // lola_plan_set_lanes
     hipStream_t side_stream = nullptr;          // non-blocking, default priority
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     hipGraph_t graph = nullptr;                 // captured from lane 0 (one lane)

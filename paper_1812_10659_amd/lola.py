@@ -410,6 +410,7 @@ def _plan_sig():
         "lola_plan_load": [vp, vp, vp],
         "lola_evaluate": [vp, vp, ctypes.POINTER(Request), u32, vp],
         "lola_evaluate_graph": [vp, vp, ctypes.POINTER(Request), u32, vp],
+        "lola_plan_set_lanes": [vp, u32],
         "lola_timing_enable": [vp, ctypes.c_int],
         "lola_kernel_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                ctypes.POINTER(ctypes.c_uint64)],
@@ -492,6 +493,11 @@ class Plan:
 
     def load(self, ctx: "Context") -> None:
         _check(lib().lola_plan_load(ctx.h, self.h, _stream()))
+
+    def set_lanes(self, max_lanes: int) -> None:
+        """1: every batch on the caller's stream; 2 (default): batches of 16 or
+        more requests as two lanes on two streams."""
+        _check(_plan_sig().lola_plan_set_lanes(self.h, int(max_lanes)))
 
     def evaluate(self, ctx: "Context", requests, graph: bool = False, stream=None) -> None:
         """requests: list of dict(rlk=tensor, gks=[tensor per galois()], inputs=[...], outputs=[...])."""

@@ -267,3 +267,8 @@ def test_two_lane_batch_equals_single_requests():
     plan.evaluate(ctx, reqs)
     torch.cuda.synchronize()
     check("two lanes again")
+    plan.set_lanes(1)
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    check("lanes limited to one")
+    plan.set_lanes(2)
