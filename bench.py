@@ -242,7 +242,8 @@ def main():
                    "plan": {"recipe": RECIPE_NAMES.get(plan.info["recipe"], str(plan.info["recipe"])),
                             "rotations": plan.info["n_rotations"], "mul_plain": plan.info["n_mul_plain"],
                             "mul_scalar": plan.info["n_mul_scalar"], "squares": plan.info["n_square"],
-                            "output_messages": plan.info["n_outputs"]},
+                            "output_messages": plan.info["n_outputs"],
+                            "predicted_latency_ms": round(plan.info["predicted_latency_us"] / 1e3, 3)},
                    "batch_requests": B, "client_key_sets": C, "lanes": args.lanes, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
@@ -351,6 +352,7 @@ def paper_layout_run(ctx, w, images, B, C, latency_runs, steps=5):
         lat.append(e0.elapsed_time(e1))
     out = {"recipe": RECIPE_NAMES[plan.info["recipe"]], "rotations": plan.info["n_rotations"],
            "output_messages": plan.info["n_outputs"], "batch_requests": B,
+           "predicted_latency_ms": round(plan.info["predicted_latency_us"] / 1e3, 3),
            "inferences_per_s": round(B / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
            "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
            "latency_p99_ms": round(float(np.percentile(lat, 99)), 3), "checked": 2}
@@ -516,7 +518,8 @@ def head_recipes_run(n_queries=64, steps=3):
         res[name] = {"queries_per_message": Q, "rotations_per_message": plan.info["n_rotations"],
                      "batch_ms_per_query": round(dt * 1e3 / n_queries, 4),
                      "one_message_ms": round(one * 1e3, 3),
-                     "predicted_us_per_message": round(float(plan.info["predicted_us"]), 1)}
+                     "predicted_us_per_message": round(float(plan.info["predicted_us"]), 1),
+                     "predicted_latency_ms": round(float(plan.info["predicted_latency_us"]) / 1e3, 3)}
     res["chosen"] = {"throughput": lola.Plan(p, networks.head_layers(w), objective=lola.OBJECTIVE_THROUGHPUT).info["recipe"],
                      "latency": lola.Plan(p, networks.head_layers(w), objective=lola.OBJECTIVE_LATENCY).info["recipe"],
                      "codes": {"1": "dense_row_major", "2": "stacked_row_major"}}

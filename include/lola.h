@@ -323,15 +323,18 @@ typedef struct {
     uint32_t n_rotations, n_mul_plain, n_mul_scalar, n_square, n_add_plain, n_add;
     uint32_t n_phys_regs;      /* device ciphertext buffers per request */
     uint32_t recipe;           /* LOLA_RECIPE_* used for the network's dense layers */
-    float predicted_us;        /* cost model: one request (all its queries), MI355X */
+    float predicted_us;        /* cost model: one request (all its queries) inside a large batch, MI355X */
+    float predicted_latency_us; /* cost model: one request alone (waves in turn), MI355X */
 } lola_plan_info;
 
 /* Representation choice.  Where more than one recipe applies (candidates
  * below), the compiler builds each candidate, prices it with a per-operation
  * cost model (key switches, products and element-wise passes timed on MI355X
  * at N = 16384, L = 7, scaled by N and L) and keeps the cheapest for the
- * objective: THROUGHPUT = least time per query with full messages, LATENCY =
- * least time for one query.  recipe forces one (an inapplicable one gives
+ * objective: THROUGHPUT = least time per query with full messages
+ * (predicted_us / queries), LATENCY = least time for one request alone
+ * (predicted_latency_us: waves in turn, each launch priced by its rounds of
+ * workgroups over the CUs).  recipe forces one (an inapplicable one gives
  * LOLA_E_UNSUPPORTED).  lola_compile = AUTO, THROUGHPUT. */
 enum { LOLA_OBJECTIVE_THROUGHPUT = 0, LOLA_OBJECTIVE_LATENCY = 1 };
 /* Candidates:

@@ -25,6 +25,7 @@
 //     row in every query block, rotate-and-sum over the block, mask, then
 //     combination into an interleaved vector (value j of query q at P*q + j).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <set>
 
@@ -563,6 +564,46 @@ float predict_us(const lola_plan *p) {
     return (float)us;
 }
 
+// Microseconds for one request alone: waves run one after another, and a
+// wave's launches (linear combinations, plaintext ops, products with their
+// relinearisation, key switches) one after another; a launch is priced by its
+// rounds of workgroups over the 256 CUs.  Per round, measured on MI355X for
+// single-request launches at N = 16384: one transform per workgroup (digits,
+// mod-down, the key switch's latency form) 17-19 us, one transform plus its key
+// products 13 us each in the batched inner stage (L of them per workgroup),
+// the exact product of a square 42 us at L = 7, a linear combination 12 us, a
+// plaintext op 5 us.  Transform times scale with log2 N.
+float predict_latency_us(const lola_plan *p) {
+    const double sl = std::log2((double)p->N) / 14.0, L = (double)p->L;
+    auto rounds = [](double wgs) { return std::ceil(wgs / 256.0); };
+    auto ks_us = [&](double n) {
+        if (n <= 0) return 0.0;
+        double t = 17.0 * sl * (rounds(n * L) + rounds(2 * n * L));   // digits, mod-down
+        if (n <= 16) t += 19.0 * sl * (rounds(n * L * (L + 1)) + rounds(2 * n * (L + 1)));   // terms, fold
+        else t += 13.0 * sl * L * rounds(n * (L + 1));
+        return t;
+    };
+    double us = 0;
+    for (uint32_t lev = 1; lev <= p->n_waves; ++lev) {
+        double lin = 0, plain = 0, sq = 0, rot = 0;
+        for (int i : p->level_ops[lev]) {
+            switch (p->ops[i].kind) {
+                case OP_LINCOMB: lin += 1; break;
+                case OP_MULPLAIN:
+                case OP_ADDPLAIN: plain += 1; break;
+                case OP_SQUARE: sq += 1; break;
+                case OP_ROT:
+                case OP_ROTADD: rot += 1; break;
+            }
+        }
+        if (lin > 0) us += 12.0;
+        if (plain > 0) us += 5.0;
+        if (sq > 0) us += 42.0 * sl * (L / 7.0) * rounds(sq) + ks_us(sq);
+        us += ks_us(rot);
+    }
+    return (float)us;
+}
+
 // ---- levels and registers ---------------------------------------------
 void schedule(lola_plan *p) {
     std::vector<int> level(p->n_regs, 0);
@@ -794,6 +835,7 @@ static int compile_with(const lola_params *prm, const lola_layer *layers, uint32
     }
     schedule(p);
     p->predicted_us = predict_us(p);
+    p->predicted_latency_us = predict_latency_us(p);
     *out = p;
     return LOLA_OK;
 }
@@ -818,7 +860,7 @@ int lola_compile_ex(const lola_params *prm, const lola_layer *layers, uint32_t n
     }
     // every candidate; keep the cheapest for the objective (the first on ties)
     auto cost = [&](const lola_plan *q) {
-        return objective == LOLA_OBJECTIVE_LATENCY ? q->predicted_us : q->predicted_us / (float)q->queries;
+        return objective == LOLA_OBJECTIVE_LATENCY ? q->predicted_latency_us : q->predicted_us / (float)q->queries;
     };
     lola_plan *best = nullptr;
     int first_rc = LOLA_OK;
@@ -858,6 +900,7 @@ int lola_plan_get_info(const lola_plan *p, lola_plan_info *info) {
     info->n_phys_regs = p->n_phys;
     info->recipe = p->recipe;
     info->predicted_us = p->predicted_us;
+    info->predicted_latency_us = p->predicted_latency_us;
     for (const Op &o : p->ops) {
         switch (o.kind) {
             case OP_LINCOMB:

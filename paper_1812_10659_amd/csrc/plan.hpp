@@ -45,7 +45,8 @@ struct lola_plan {
     uint32_t N = 0, L = 0, t = 0;
     uint32_t n_inputs = 0, queries = 1;
     uint32_t recipe = 3;                        // LOLA_RECIPE_*
-    float predicted_us = 0;                     // cost model, one request
+    float predicted_us = 0;                     // cost model, one request inside a large batch
+    float predicted_latency_us = 0;             // cost model, one request alone
     uint32_t n_regs = 0;                        // virtual registers (SSA)
     std::vector<lola::Op> ops;                  // in emission order
     std::vector<int> outputs;                   // output registers

@@ -349,7 +349,7 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n_inputs", "n_outputs", "n_ops", "n_consts", "n_galois", "n_waves", "queries",
         "n_rotations", "n_mul_plain", "n_mul_scalar", "n_square", "n_add_plain", "n_add", "n_phys_regs",
-        "recipe")] + [("predicted_us", ctypes.c_float)]
+        "recipe")] + [("predicted_us", ctypes.c_float), ("predicted_latency_us", ctypes.c_float)]
 
 
 class _CompileOptions(ctypes.Structure):

@@ -264,7 +264,7 @@ def test_recipe_choice_follows_the_cost_model():
     assert drm["recipe"] == lola.RECIPE_DENSE_ROW_MAJOR and drm["queries"] == 4
     assert stk["recipe"] == lola.RECIPE_STACKED_ROW_MAJOR and stk["queries"] == 1
     per_query = {r["recipe"]: r["predicted_us"] / r["queries"] for r in (drm, stk)}
-    per_msg = {r["recipe"]: r["predicted_us"] for r in (drm, stk)}
+    per_msg = {r["recipe"]: r["predicted_latency_us"] for r in (drm, stk)}
     thr = lola.Plan(p, layers, objective=lola.OBJECTIVE_THROUGHPUT).info["recipe"]
     lat = lola.Plan(p, layers, objective=lola.OBJECTIVE_LATENCY).info["recipe"]
     assert thr == min(per_query, key=per_query.get)
@@ -280,6 +280,7 @@ def test_recipe_choice_follows_the_cost_model():
     full = lola.Plan(pm, lm, recipe=lola.RECIPE_FULL_REDUCTION).info
     shared = lola.Plan(pm, lm, recipe=lola.RECIPE_SHARED_REDUCTION).info
     assert shared["predicted_us"] < full["predicted_us"]
+    assert shared["predicted_latency_us"] < full["predicted_latency_us"]
     for obj in (lola.OBJECTIVE_THROUGHPUT, lola.OBJECTIVE_LATENCY):
         assert lola.Plan(pm, lm, objective=obj).info["recipe"] == lola.RECIPE_SHARED_REDUCTION
     sm = lola.Plan(pm, networks.mnist_small_layers(wl.mnist_small_weights())).info
@@ -290,6 +291,53 @@ def test_recipe_choice_follows_the_cost_model():
         with pytest.raises(lola.LolaError) as e:
             lola.Plan(pm if bad_layers is not layers else p, bad_layers, recipe=bad_recipe)
         assert e.value.code == -8
+
+
+def test_latency_model_tracks_depth_and_launch_rounds():
+    """The one-request latency model sums the waves; a wave's key switches cost
+    by rounds of workgroups, so a plan with fewer rotations but more waves is not
+    automatically faster alone, and a wave of many rotations costs more than one
+    of a few.  Values in microseconds, measured counterparts in the design notes
+    (MNIST shared 2.57 ms, paper's layout 2.66 ms, LoLa-Small 1.37 ms)."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    pm, w = wl.PARAMS["mnist_n16384"], wl.mnist_weights()
+    shared = lola.Plan(pm, networks.mnist_layers(w), recipe=lola.RECIPE_SHARED_REDUCTION).info
+    full = lola.Plan(pm, networks.mnist_layers(w), recipe=lola.RECIPE_FULL_REDUCTION).info
+    small = lola.Plan(pm, networks.mnist_small_layers(wl.mnist_small_weights())).info
+    for info, ms in [(shared, 2.57), (full, 2.66), (small, 1.37)]:
+        assert abs(info["predicted_latency_us"] / 1e3 - ms) < 0.15 * ms
+    # per rotation, the shared layout's waves are costlier alone (fewer rotations per wave)
+    assert shared["predicted_latency_us"] / shared["n_rotations"] > full["predicted_latency_us"] / full["n_rotations"]
+    assert shared["n_waves"] > full["n_waves"]
+
+
+def test_compile_options_are_validated():
+    """Unknown objectives and recipe codes are argument errors; a recipe that
+    does not apply to the layer list is unsupported; the shared-reduction
+    layout needs the packed output to fit one stacking block."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    pm, lm = wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights())
+    for obj, rec in [(2, 0), (-1, 0), (0, 6), (0, -1)]:
+        with pytest.raises(lola.LolaError) as e:
+            lola.Plan(pm, lm, objective=obj, recipe=rec)
+        assert e.value.code == -1
+    with pytest.raises(lola.LolaError) as e:   # FIXED names a pattern with one recipe, not a choice
+        lola.Plan(pm, lm, recipe=lola.RECIPE_FIXED)
+    assert e.value.code == -8
+    # 130 classes at 8 slots each do not fit the 1024-slot block: only the
+    # paper's layout applies, and AUTO falls back to it
+    w = wl.mnist_weights()
+    rs = np.random.default_rng(5)
+    w2 = rs.integers(-128, 128, size=(130, 100)).astype(np.int64)
+    big = lm[:4] + [lola.dense(w2, rs.integers(-100, 100, size=130).astype(np.int64))]
+    with pytest.raises(lola.LolaError) as e:
+        lola.Plan(pm, big, recipe=lola.RECIPE_SHARED_REDUCTION)
+    assert e.value.code == -8
+    auto = lola.Plan(pm, big).info
+    assert auto["recipe"] == lola.RECIPE_FULL_REDUCTION and auto["n_outputs"] == 130
+    assert w.w2.shape == (10, 100)
 
 
 def test_compiler_rejects_unsupported():

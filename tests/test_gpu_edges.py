@@ -118,6 +118,17 @@ def test_error_codes(toy):
     with pytest.raises(lola.LolaError) as e:
         ctx.ntt_limbs(torch.zeros((1, p.N), dtype=torch.int32, device=ctx.device), [99])
     assert _code(e) == -1
+    # NTT variants: an index past the list, autotune sizes out of range
+    nv = len(ctx.ntt_variants())
+    with pytest.raises(lola.LolaError) as e:
+        ctx.ntt_set_variant(nv)
+    assert _code(e) == -1
+    assert ctx.ntt_variant() == 0
+    for n_limbs, reps in [(0, 1), (65537, 1), (4, 0), (4, 1001)]:
+        with pytest.raises(lola.LolaError) as e:
+            ctx.ntt_autotune(n_limbs=n_limbs, reps=reps)
+        assert _code(e) == -1
+    assert ctx.ntt_variant() == 0
     # a key switch without a key
     arr = (lola.KsDesc * 1)()
     out = ctx.empty_ct()
@@ -169,6 +180,11 @@ def test_plan_errors():
         plan.evaluate(ctx, [dict(rlk=rlk, gks=gks, inputs=ins, outputs=outs)], graph=True,
                       stream=torch.cuda.default_stream())
     assert e.value.code == -1
+    # lanes: only 1 or 2
+    for bad in (0, 3):
+        with pytest.raises(lola.LolaError) as e:
+            plan.set_lanes(bad)
+        assert e.value.code == -1
     # an empty batch of requests is a no-op
     plan.evaluate(ctx, [])
     torch.cuda.synchronize()
