@@ -180,6 +180,18 @@ int lola_relin(lola_ctx *ctx, const uint32_t *rlk_dev, const uint32_t *in3_dev, 
 /* (sigma_g(c0), 0) + KeySwitch_{sigma_g(s) -> s}(sigma_g(c1)). */
 int lola_rotate(lola_ctx *ctx, const uint32_t *gk_dev, uint32_t galois, const uint32_t *ct_dev,
                 uint32_t *out_dev, lola_stream stream);
+/* n rotations of one ciphertext in_dev [2][L][N], by galois[k] (host, odd,
+ * 3 <= g < 2N) under keys[k] (host array of device keys) into out_dev[k]
+ * (host array of device [2][L][N], none equal to in_dev), sharing one
+ * decomposition (hoisting): the key switch's digits are taken from c1 before
+ * the automorphism, sigma_g(|c1|_{q_i}) as integer polynomials, so their
+ * transforms to every modulus are computed once for all n.  Each output
+ * decrypts to the same slots as lola_rotate's; the words differ from it
+ * (Sec. 3.1 rotations; the digits are this library's key-switching reading).
+ * Scratch: (L^2 + 3L) N words for the source plus (4L + 2) N per rotation, in
+ * chunks of 128. */
+int lola_rotate_hoisted(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n, const uint32_t *galois,
+                        const uint32_t *const *keys, uint32_t *const *out_dev, lola_stream stream);
 
 /* Batched key switching: n independent rotations / relinearisations in one
  * set of launches (uneven per-ciphertext work is just more descriptors). */

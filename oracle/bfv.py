@@ -512,15 +512,24 @@ def mul(ctx: Context, a, b) -> List[np.ndarray]:
     return out
 
 
-def keyswitch(ctx: Context, x, ksk: KeySwitchKey):
+def keyswitch(ctx: Context, x, ksk: KeySwitchKey, digit_galois: int = 1):
     """x: [L][N] residues of a polynomial under s'.  Returns (k0, k1) with
-    k0 + k1 s ~ x s' (mod Q)."""
+    k0 + k1 s ~ x s' (mod Q).
+
+    digit_galois = g > 1: the digits are sigma_g(|x|_{q_i}), the automorphism
+    applied to each digit as an integer polynomial (coefficients in
+    (-q_i, q_i)), i.e. to its residues mod every modulus; then the call
+    switches sigma_g(x) (each digit is still congruent to sigma_g(x) mod q_i),
+    and all rotations of one x share the digits |x|_{q_i} -- the hoisted
+    rotation."""
     L, N = ctx.L, ctx.N
     D = [np.asarray(x[i], np.uint64) for i in range(L)]     # digits in [0, q_i)
     pairs = []
     for j, m in enumerate(ctx.moduli):
         for i in range(L):
             Dij = D[i] % np.uint64(m)
+            if digit_galois != 1:
+                Dij = automorph(Dij, m, digit_galois)
             pairs.append((Dij, ksk.b[i, j], m))
             pairs.append((Dij, ksk.a[i, j], m))
     prods = poly_mul_many(pairs)
@@ -565,6 +574,21 @@ def rotate(ctx: Context, ct, step, keys: Keys) -> List[np.ndarray]:
     ksk = keys.galois[g]
     c0g, c1g = apply_galois(ctx, ct, g)
     k0, k1 = keyswitch(ctx, c1g, ksk)
+    return [np.stack([(c0g[j] + k0[j]) % qj for j, qj in enumerate(ctx.q)]), k1]
+
+
+def rotate_hoisted(ctx: Context, ct, step, keys: Keys) -> List[np.ndarray]:
+    """The same rotation as `rotate` (it decrypts to the same slots), with the
+    key switch's digits taken before the automorphism: digit i is
+    sigma_g(|c1|_{q_i}) (see keyswitch).  Rotations of one ciphertext by
+    several g then share |c1|_{q_i} and its reductions to every modulus; the
+    words differ from `rotate`'s where sigma_g negates a coefficient."""
+    g = galois_element(ctx.N, step)
+    if g == 1:
+        return [c.copy() for c in ct]
+    ksk = keys.galois[g]
+    c0g = [automorph(ct[0][j], qj, g) for j, qj in enumerate(ctx.q)]
+    k0, k1 = keyswitch(ctx, ct[1], ksk, digit_galois=g)
     return [np.stack([(c0g[j] + k0[j]) % qj for j, qj in enumerate(ctx.q)]), k1]
 
 

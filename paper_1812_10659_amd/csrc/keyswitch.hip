@@ -78,6 +78,34 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_fold_kernel(const KsJo
     ks_stage_fold<LOGN>(job.scratch, j, c, L, sh, mcs[j], itw);
 }
 
+// Hoisted rotations (see ks_stage_hoisted_inner).  Mod-up: one workgroup per
+// (source, modulus j, digit i), units with i == j exit at once; grid = jobs x
+// units so one source spreads over all XCDs.
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_modup_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                     uint32_t L, const ModConst *__restrict__ mcs,
+                                                                     const TwPair *__restrict__ tw) {
+    __shared__ uint32_t sh[1 << LOGN];
+    const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
+    if (jb >= n) return;
+    const uint32_t jr = unit / L, i = unit % L;
+    const uint32_t j = jr == 0 ? L : jr - 1;
+    if (i == j) return;   // c1's own limb, used as is
+    ks_stage_modup<LOGN>(jobs[jb].scratch, j, i, sh, mcs[j], tw, L);
+}
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_hoisted_inner_kernel(
+    const KsJob *__restrict__ jobs, uint32_t n, uint32_t L, const ModConst *__restrict__ mcs,
+    const TwPair *__restrict__ itw) {
+    __shared__ uint32_t sh[1 << LOGN];
+    const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1, n);
+    if (ju.job >= n) return;
+    const KsJob job = jobs[ju.job];
+    const uint32_t j = ju.unit == 0 ? L : ju.unit - 1;
+    ks_stage_hoisted_inner<LOGN>(job.key, job.x, job.hoist, job.scratch, job.galois, j, L, sh, mcs[j], itw);
+}
+
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                        uint32_t L, const ModConst *__restrict__ mcs,
@@ -151,6 +179,56 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t
     return LOLA_OK;
 }
 
+int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
+    if (n == 0) return LOLA_OK;
+    const uint32_t L = ctx->L;
+    const dim3 block(ctx->N / NTT_E);
+#define LOLA_HS_CASE(LG)                                                                                     \
+    case LG:                                                                                                 \
+        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L, ctx->d_mc,    \
+                           ctx->d_itw);                                                                       \
+        hipLaunchKernelGGL(ks_modup_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, ctx->d_mc,  \
+                           ctx->d_tw);                                                                        \
+        break;
+    switch (ctx->logN) {
+        LOLA_HS_CASE(10)
+        LOLA_HS_CASE(11)
+        LOLA_HS_CASE(12)
+        LOLA_HS_CASE(13)
+        LOLA_HS_CASE(14)
+        default: return set_error(LOLA_E_PARAMS, "unsupported N");
+    }
+#undef LOLA_HS_CASE
+    LOLA_HIP(hipGetLastError());
+    return LOLA_OK;
+}
+
+int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
+    if (n == 0) return LOLA_OK;
+    const uint32_t L = ctx->L;
+    const dim3 block(ctx->N / NTT_E);
+#define LOLA_HR_CASE(LG)                                                                                     \
+    case LG:                                                                                                 \
+        hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L,  \
+                           ctx->d_mc, ctx->d_itw);                                                            \
+        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, L,         \
+                           ctx->d_mc, ctx->d_tw, ctx->d_mrc);                                                 \
+        break;
+    switch (ctx->logN) {
+        LOLA_HR_CASE(10)
+        LOLA_HR_CASE(11)
+        LOLA_HR_CASE(12)
+        LOLA_HR_CASE(13)
+        LOLA_HR_CASE(14)
+        default: return set_error(LOLA_E_PARAMS, "unsupported N");
+    }
+#undef LOLA_HR_CASE
+    LOLA_HIP(hipGetLastError());
+    return LOLA_OK;
+}
+
+size_t ks_hoist_words(const lola_ctx *ctx) { return ks_hoist_limbs(ctx->L) * ctx->N; }
+
 // Jobs per launch: bounds the scratch arena ((4L+2) N words per job).
 static constexpr uint32_t KS_CHUNK = 128;
 
@@ -194,6 +272,39 @@ int lola_reserve(lola_ctx *ctx, uint32_t n_ct) {
     void *buf = nullptr;
     const uint32_t n = std::min<uint32_t>(std::max<uint32_t>(n_ct, 1), KS_CHUNK);
     return scratch_get(ctx, std::max(ks_chunk_words(ctx, n), n * mul_scratch_words(ctx)) * 4, &buf);
+}
+
+int lola_rotate_hoisted(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n, const uint32_t *galois,
+                        const uint32_t *const *keys, uint32_t *const *out_dev, lola_stream stream) {
+    if (!ctx || (n && (!in_dev || !galois || !keys || !out_dev))) return set_error(LOLA_E_INVAL, "null argument");
+    if (n == 0) return LOLA_OK;
+    const size_t P = (size_t)ctx->L * ctx->N;
+    for (uint32_t k = 0; k < n; ++k) {
+        if (!keys[k]) return set_error(LOLA_E_NOKEY, "hoisted rotation without key");
+        if (!out_dev[k]) return set_error(LOLA_E_INVAL, "null output ciphertext");
+        if (out_dev[k] == in_dev) return set_error(LOLA_E_INVAL, "output aliases the input");
+        if (galois[k] < 3 || !(galois[k] & 1) || galois[k] >= 2 * ctx->N)
+            return set_error(LOLA_E_INVAL, "bad Galois element");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t per = ks_scratch_words(ctx), hw = ks_hoist_words(ctx);
+    for (uint32_t off = 0; off < n; off += KS_CHUNK) {
+        const uint32_t m = std::min<uint32_t>(KS_CHUNK, n - off);
+        void *buf = nullptr;
+        int rc = scratch_get(ctx, (hw + per * m) * 4, &buf);
+        if (rc) return rc;
+        uint32_t *hoist = (uint32_t *)buf, *scr = hoist + hw;
+        std::vector<KsJob> src{KsJob{in_dev + P, nullptr, nullptr, nullptr, nullptr, nullptr, hoist, 1, 0, nullptr}};
+        std::vector<KsJob> rot(m);
+        for (uint32_t k = 0; k < m; ++k)
+            rot[k] = KsJob{in_dev + P, keys[off + k], in_dev, nullptr, nullptr, out_dev[off + k], scr + per * k,
+                           galois[off + k], 0, hoist};
+        Program p;
+        p.launch(LK_KS_HSRC, src);
+        p.launch(LK_KS_HROT, rot);
+        if ((rc = program_run_now(ctx, p, s))) return rc;
+    }
+    return LOLA_OK;
 }
 
 int lola_keyswitch_batch(lola_ctx *ctx, const lola_ks_desc *d, uint32_t n, lola_stream stream) {

@@ -277,4 +277,103 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
     store_spectral<LOGN>(gbuf(out + ((size_t)(c * L + jj) << LOGN), N), tid, x);
 }
 
+// ---- hoisted rotations ---------------------------------------------------
+// Rotations of one ciphertext by several Galois elements share its
+// decomposition: the digits D_i = |c1|_{q_i} are taken before the
+// automorphism, transformed to every other modulus once, and each rotation
+// gathers them through sigma_g in the NTT domain (a permutation of the
+// evaluation points), so its inner product needs no transform.  The key
+// switch then acts on the digits sigma_g(D_i) (signed integer polynomials),
+// which are still congruent to sigma_g(c1) mod q_i; the words differ from a
+// plain rotation's.  Hoist area of a source, in limbs of N words: [0, L) the
+// digits in coefficients, [L, 2L) a copy of c1 written by the digit stage
+// (unused), and 2L + j L + i digit i transformed to modulus j (j <= L, i != j).
+__host__ __device__ constexpr size_t ks_hoist_limb(uint32_t L, uint32_t j, uint32_t i) {
+    return 2 * (size_t)L + (size_t)j * L + i;
+}
+__host__ __device__ constexpr size_t ks_hoist_limbs(uint32_t L) { return 2 * (size_t)L + (size_t)(L + 1) * L; }
+
+// Digit i transformed to modulus j (j != i).
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_modup(uint32_t *hoist, uint32_t j, uint32_t i, uint32_t *sh,
+                                               const ModConst &mc, const TwPair *tw, uint32_t L) {
+    constexpr uint32_t N = 1u << LOGN;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t x[NTT_E];
+    const GBuf D = gbuf(hoist + ((size_t)i << LOGN), N);
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN>(tid, r)), mc.q, mc.one_shoup);
+    ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
+    store_spectral<LOGN>(gbuf(hoist + (ks_hoist_limb(L, j, i) << LOGN), N), tid, x);
+}
+
+// Inner product of one hoisted rotation for target modulus m_j: each digit's
+// transform (c1's own limb when i == j) is staged in LDS with coalesced
+// 16-byte loads, read back through sigma_g, and multiplied by the key as in
+// ks_stage_inner, whose results (U, or the special prime's sums back in
+// coefficients) it writes to the same places.
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, const uint32_t *x,
+                                                       const uint32_t *hoist, uint32_t *scratch, uint32_t g,
+                                                       uint32_t j, uint32_t L, uint32_t *sh, const ModConst &mc,
+                                                       const TwPair *itw) {
+    constexpr uint32_t N = 1u << LOGN, T = N / NTT_E;
+    const uint32_t M = L + 1;
+    uint64_t a0[NTT_E], a1[NTT_E];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    for (uint32_t i = 0; i < L; ++i) {
+        const uint32_t *src = i == j ? x + ((size_t)i << LOGN) : hoist + (ks_hoist_limb(L, j, i) << LOGN);
+        const GBuf S = gbuf(src, N);
+        __syncthreads();   // the previous digit's gathers are done
+#pragma unroll
+        for (uint32_t r = 0; r < NTT_E / 4; ++r) {
+            const uint32_t w = 4 * (tid + r * T);
+            const u32x4 v = gld4(S, w);
+            sh[w] = v.x, sh[w + 1] = v.y, sh[w + 2] = v.z, sh[w + 3] = v.w;
+        }
+        __syncthreads();
+        uint32_t xv[NTT_E];
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) xv[r] = sh[galois_src_index(spectral_index<LOGN>(tid, r), g, LOGN)];
+        const uint32_t koff = i * 2 * M + j;
+        uint32_t kb[NTT_E], ka[NTT_E];
+        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kb);
+        load_spectral<LOGN>(gbuf(key + ((size_t)(koff + M) << LOGN), N), tid, ka);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) {
+            a0[r] += (uint64_t)xv[r] * kb[r];
+            a1[r] += (uint64_t)xv[r] * ka[r];
+        }
+    }
+    uint32_t u[NTT_E];
+    if (j < L) {
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
+        store_spectral<LOGN>(gbuf(scratch + ((size_t)(2 * L + j) << LOGN), N), tid, u);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
+        store_spectral<LOGN>(gbuf(scratch + ((size_t)(3 * L + j) << LOGN), N), tid, u);
+    } else {
+        // the transforms below reuse sh, which other waves may still be
+        // reading for the last digit's gather
+        __syncthreads();
+#pragma unroll
+        for (uint32_t c = 0; c < 2; ++c) {
+            const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) {
+                const uint64_t a = c == 0 ? a0[r] : a1[r];
+                u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mc);
+            }
+            ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
+        }
+    }
+}
+
 }  // namespace lola

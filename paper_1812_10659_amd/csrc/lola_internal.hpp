@@ -163,6 +163,7 @@ struct KsJob {
     uint32_t *scratch;      // (4L + 2) N words: D [L][N], Xp [L][N], U [2][L][N], UP [2][N]
     uint32_t galois;        // 0/1: no automorphism
     uint32_t pad;
+    const uint32_t *hoist;  // hoisted rotation: the source's hoist area (ks_hoist_limb), else null
 };
 // Runs the jobs in chunks (assigns scratch, uploads descriptors).
 int keyswitch_host_jobs(lola_ctx *ctx, std::vector<KsJob> &jobs, hipStream_t s);

@@ -76,6 +76,8 @@ int program_run_launch(lola_ctx *ctx, const Launch &l, const uint8_t *d_blob, hi
         case LK_LIN: return launch_lin_dev(ctx, (const LinJob *)d, l.n, s);
         case LK_PLAIN: return launch_plain_dev(ctx, (const PlainJob *)d, l.n, s);
         case LK_KS: return launch_keyswitch(ctx, (const KsJob *)d, l.n, s);
+        case LK_KS_HSRC: return launch_keyswitch_hoist_src(ctx, (const KsJob *)d, l.n, s);
+        case LK_KS_HROT: return launch_keyswitch_hoist_rot(ctx, (const KsJob *)d, l.n, s);
         case LK_MUL_EXTEND:
         case LK_MUL_PRODUCT:
         case LK_MUL_ROUND: return launch_mul_stage(ctx, l.kind, (const MulJob *)d, l.n, s);

@@ -32,7 +32,9 @@ struct MulJob {
 };
 
 enum LaunchKind : uint32_t {
-    LK_NTT, LK_LIN, LK_PLAIN, LK_KS, LK_MUL_EXTEND, LK_MUL_PRODUCT, LK_MUL_ROUND
+    LK_NTT, LK_LIN, LK_PLAIN, LK_KS, LK_MUL_EXTEND, LK_MUL_PRODUCT, LK_MUL_ROUND,
+    LK_KS_HSRC,   // hoisted rotations: decomposition and transforms of each source
+    LK_KS_HROT    // hoisted rotations: gathered inner products and mod-down
 };
 struct Launch {
     uint32_t kind, n;
@@ -81,6 +83,10 @@ int program_run_now(lola_ctx *ctx, const Program &p, hipStream_t s);
 int launch_lin_dev(lola_ctx *ctx, const LinJob *d, uint32_t n, hipStream_t s);
 int launch_plain_dev(lola_ctx *ctx, const PlainJob *d, uint32_t n, hipStream_t s);
 int launch_keyswitch(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s);
+// Hoisted rotations: sources (x = c1, scratch = hoist area, galois 1), then
+// rotations (hoist = the source's area, scratch = their own).
+int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s);
+int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s);
 int launch_mul_stage(lola_ctx *ctx, uint32_t stage, const MulJob *d, uint32_t n, hipStream_t s);
 
 }  // namespace lola

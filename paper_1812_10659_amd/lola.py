@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
             "lola_mul": [vp, vp, vp, vp, vp],
             "lola_relin": [vp, vp, vp, vp, vp],
             "lola_rotate": [vp, vp, u32, vp, vp, vp],
+            "lola_rotate_hoisted": [vp, vp, u32, ctypes.POINTER(u32), ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
             "lola_keyswitch_batch": [vp, ctypes.POINTER(KsDesc), u32, vp],
             "lola_to_coeff": [vp, vp, u32, vp, vp],
             "lola_from_coeff": [vp, vp, u32, vp, vp],
@@ -255,6 +256,17 @@ class Context:
         out = self.empty_ct()
         _check(lib().lola_rotate(self.h, _p(gk), galois, _p(ct), _p(out), _stream()))
         return out
+
+    def rotate_hoisted(self, ct: torch.Tensor, galois: Sequence[int], keys: Sequence[torch.Tensor]) -> list:
+        """Rotations of one ciphertext by each Galois element, sharing its
+        decomposition (lola_rotate_hoisted)."""
+        n = len(galois)
+        outs = [self.empty_ct() for _ in range(n)]
+        g = (ctypes.c_uint32 * n)(*[int(x) for x in galois])
+        k = (ctypes.c_void_p * n)(*[t.data_ptr() for t in keys])
+        o = (ctypes.c_void_p * n)(*[t.data_ptr() for t in outs])
+        _check(lib().lola_rotate_hoisted(self.h, ct.data_ptr(), n, g, k, o, _stream()))
+        return outs
 
     def keyswitch_batch(self, items: Sequence) -> list:
         """items: (input ct, key, galois) with galois 0 for relinearisation."""

@@ -232,7 +232,9 @@ class Tiny:
             out.append(self.limbs(r))
         return out
 
-    def keyswitch(self, x, key):
+    def keyswitch(self, x, key, digit_g=1):
+        """digit_g > 1: digit i is the automorphism of x's residues mod q_i
+        taken as an integer polynomial (signed), reduced mod each modulus."""
         b, a = key
         L, N, P = self.L, self.N, self.P
         u0, u1 = [], []
@@ -240,7 +242,8 @@ class Tiny:
             s0 = [0] * N
             s1 = [0] * N
             for i in range(L):
-                Di = [v % m for v in x[i]]
+                xi = automorphism(x[i], digit_g) if digit_g != 1 else x[i]
+                Di = [v % m for v in xi]
                 s0 = [(p + r) % m for p, r in zip(s0, negacyclic(Di, b[i][j], m))]
                 s1 = [(p + r) % m for p, r in zip(s1, negacyclic(Di, a[i][j], m))]
             u0.append(s0)
@@ -260,4 +263,10 @@ class Tiny:
         c0 = [[v % qj for v in automorphism(ct[0][j], g)] for j, qj in enumerate(self.q)]
         c1 = [[v % qj for v in automorphism(ct[1][j], g)] for j, qj in enumerate(self.q)]
         k0, k1 = self.keyswitch(c1, keys["gal"][g])
+        return self.add([c0, k1], [k0, [[0] * self.N for _ in self.q]])
+
+    def rotate_hoisted(self, ct, g, keys):
+        """Digits from c1 before the automorphism, permuted afterwards."""
+        c0 = [[v % qj for v in automorphism(ct[0][j], g)] for j, qj in enumerate(self.q)]
+        k0, k1 = self.keyswitch(ct[1], keys["gal"][g], digit_g=g)
         return self.add([c0, k1], [k0, [[0] * self.N for _ in self.q]])

@@ -238,6 +238,19 @@ def test_keyswitch_batch_ragged(env):
         assert np.array_equal(_down(ctx, o), np.stack(r))
 
 
+def test_rotate_hoisted_matches_oracle(env):
+    """Rotations of one ciphertext sharing its decomposition: words equal the
+    oracle's hoisted rotation; each decrypts like the plain rotation."""
+    ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
+    c1 = env["c"][0]
+    gs = [bfv.galois_element(env["p"].N, s) for s in STEPS]
+    outs = ctx.rotate_hoisted(_up(ctx, c1), gs, [env["gks"][g] for g in gs])
+    for step, o in zip(STEPS, outs):
+        ref = bfv.rotate_hoisted(octx, c1, step, ok)
+        assert np.array_equal(_down(ctx, o), np.stack(ref)), f"step {step}"
+        assert list(bfv.decrypt(octx, ok, ref)) == list(bfv.decrypt(octx, ok, bfv.rotate(octx, c1, step, ok)))
+
+
 @pytest.mark.parametrize("n_jobs", [1, 16, 17, 40])
 def test_keyswitch_both_inner_forms(env, n_jobs):
     """Launches of at most 16 jobs split the key inner product into one

@@ -103,6 +103,19 @@ def test_rotate_match(setup):
         _eq(bfv.rotate(ctx, c1, step, keys), tiny.rotate(b1, g, bkeys))
 
 
+def test_rotate_hoisted_match(setup):
+    """The hoisted rotation (digits taken before the automorphism) word for
+    word, and it decrypts like the plain rotation while its words differ."""
+    p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
+    for step in (1, -3, bfv.ROW_SWAP):
+        g = bfv.galois_element(p.N, step)
+        h = bfv.rotate_hoisted(ctx, c1, step, keys)
+        _eq(h, tiny.rotate_hoisted(b1, g, bkeys))
+        r = bfv.rotate(ctx, c1, step, keys)
+        assert list(bfv.decrypt(ctx, keys, h)) == list(bfv.decrypt(ctx, keys, r))
+        assert any(not np.array_equal(x, y) for x, y in zip(h, r))
+
+
 def test_decrypt_of_size3_match(setup):
     p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
     d = bfv.mul(ctx, c1, c2)
