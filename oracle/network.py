@@ -18,6 +18,8 @@ Three things live here, all written from the paper's text:
      ("add_plain", dst, src, slots)   slots: {slot index: value}
      ("mul_plain", dst, src, slots)
      ("rotate", dst, src, step)       step > 0 left, < 0 right, "row_swap"
+     ("rotate_hoisted", dst, src, step)  the same rotation, digits taken before
+                                      the automorphism (bfv.rotate_hoisted)
      ("square", dst, src)             ct x ct product then relinearisation
    Registers 0..n_inputs-1 hold the inputs; the schedule's "outputs" names the
    result registers.
@@ -109,6 +111,9 @@ class Schedule:
     out_slots: List[Dict[int, str]] = dataclasses.field(default_factory=list)
 
     def count(self, kind: str) -> int:
+        """Ops of one kind; "rotate" counts hoisted rotations too."""
+        if kind == "rotate":
+            return sum(1 for op in self.ops if op[0] in ("rotate", "rotate_hoisted"))
         return sum(1 for op in self.ops if op[0] == kind)
 
 
@@ -219,9 +224,9 @@ def _interleaved_output(b: _Builder, h: int, N: int, P: int, C: int, R: int, w2,
     P .. and the row swap when the blocks fill both rows -> logit o at slot 0
     of message o.
     recipe "shared": one packed message.  Copy o of the input is the input
-    rotated right by G o (built as a binary tree: copy o is copy o - 2^k
-    rotated right by G 2^k, 2^k the highest power of two <= o), multiplied by
-    row o laid out at slots P c + G o + rho; the products are added and one
+    rotated right by G o, all copies hoisted rotations of the one input
+    (bfv.rotate_hoisted: they share its decomposition), multiplied by row o
+    laid out at slots P c + G o + rho; the products are added and one
     rotate-and-sum over the same steps leaves logit o at slot G o."""
     n_out, in_dim = w2.shape
     G = _next_pow2(R)
@@ -240,10 +245,7 @@ def _interleaved_output(b: _Builder, h: int, N: int, P: int, C: int, R: int, w2,
             outs.append(z)
         return outs, [{0: f"logit{o}"} for o in range(n_out)]
     assert G * n_out <= P
-    copies = [h]
-    for o in range(1, n_out):
-        hb = 1 << (o.bit_length() - 1)
-        copies.append(b.emit("rotate", b.reg(), copies[o - hb], -G * hb))
+    copies = [h] + [b.emit("rotate_hoisted", b.reg(), h, -G * o) for o in range(1, n_out)]
     acc = None
     for o in range(n_out):
         rows = {P * c + G * o + rho: int(w2[o, C * rho + c])
@@ -389,7 +391,8 @@ def mnist_dense_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
       masks:   message (a, b) = the input rotated left by 29 a + b (so padded
                pixel (2y + a, 2x + b) sits at slot 58 y + 2 x) times the 0/1
                mask of the window corners {58 y + 2 x : y, x < 13}; 24
-               rotations and 25 products;
+               rotations of the one input, hoisted (they share its
+               decomposition), and 25 products;
       conv:    per map, sum_{a,b} w[m,a,b] * message(a,b) + bias at the corners;
       combine: map m rotated right by (0, 1, 29, 30, 754)[m] and added, so the
                845 values occupy distinct slots below 2048 (4 rotations);
@@ -411,7 +414,7 @@ def mnist_dense_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
     for a in range(5):
         for c in range(5):
             r = 29 * a + c
-            src = 0 if r == 0 else b.emit("rotate", b.reg(), 0, r)
+            src = 0 if r == 0 else b.emit("rotate_hoisted", b.reg(), 0, r)
             msgs.append(b.emit("mul_plain", b.reg(), src, corners))
     maps = []
     for m in range(5):
@@ -716,7 +719,7 @@ def run_slots(sched: Schedule, inputs: Sequence[Dict[int, int]], t: int):
             reg[op[1]] = (reg[op[2]] + dense_slots(op[3], N, t)) % t
         elif k == "mul_plain":
             reg[op[1]] = (reg[op[2]] * dense_slots(op[3], N, t)) % t
-        elif k == "rotate":
+        elif k in ("rotate", "rotate_hoisted"):
             reg[op[1]] = rotate_slots(reg[op[2]], op[3])
         elif k == "square":
             reg[op[1]] = (reg[op[2]] * reg[op[2]]) % t
@@ -726,7 +729,7 @@ def run_slots(sched: Schedule, inputs: Sequence[Dict[int, int]], t: int):
 
 
 def galois_elements(sched: Schedule) -> List[int]:
-    gs = sorted({bfv.galois_element(sched.N, op[3]) for op in sched.ops if op[0] == "rotate"})
+    gs = sorted({bfv.galois_element(sched.N, op[3]) for op in sched.ops if op[0] in ("rotate", "rotate_hoisted")})
     return [g for g in gs if g != 1]
 
 
@@ -765,6 +768,8 @@ def run_ciphertexts(ctx: bfv.Context, keys: bfv.Keys, sched: Schedule, cts, keep
             reg[op[1]] = bfv.mul_plain(ctx, reg[op[2]], plain(op[3]))
         elif k == "rotate":
             reg[op[1]] = bfv.rotate(ctx, reg[op[2]], op[3], keys)
+        elif k == "rotate_hoisted":
+            reg[op[1]] = bfv.rotate_hoisted(ctx, reg[op[2]], op[3], keys)
         elif k == "square":
             reg[op[1]] = bfv.square(ctx, reg[op[2]], keys)
         else:

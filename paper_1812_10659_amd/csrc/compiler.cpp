@@ -104,13 +104,16 @@ struct Builder {
         p->ops.push_back(o);
         return o.dst;
     }
-    int rot(int src, int32_t step) {
+    // hoist: the rotation shares its source's decomposition with the other
+    // hoisted rotations of that source in its wave
+    int rot(int src, int32_t step, bool hoist = false) {
         Op o;
         o.kind = OP_ROT;
         o.dst = reg();
         o.src = src;
         o.step = step;
         o.galois = lola_galois_element(p->N, step);
+        o.hoist = hoist;
         p->ops.push_back(o);
         return o.dst;
     }
@@ -243,7 +246,7 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n,
         for (int a = 0; a < cv.k; ++a)
             for (int c = 0; c < cv.k; ++c) {
                 const int32_t r = a * (int32_t)W + c;
-                ins[a * cv.k + c] = b.mulplain(r ? b.rot(0, r) : 0, cm);
+                ins[a * cv.k + c] = b.mulplain(r ? b.rot(0, r, true) : 0, cm);
             }
     } else {
         // inputs: convolution representation
@@ -349,15 +352,12 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n,
     };
     if (shared) {
         // one packed message: copy o of the input is rotated right by GR*o
-        // (copy o - 2^k rotated by GR*2^k, 2^k the highest power of two <= o),
-        // times row o at offset GR*o of every block; the products are added
-        // and one rotate-and-sum leaves output o at slot GR*o
+        // (all copies hoisted rotations of the input), times row o at offset
+        // GR*o of every block; the products are added and one rotate-and-sum
+        // leaves output o at slot GR*o
         if ((uint64_t)GR * (uint64_t)d2.out_dim > P) return unsupported("packed output does not fit one stacking block");
         std::vector<int> copies{h}, prods;
-        for (int o = 1; o < d2.out_dim; ++o) {
-            const int hb = 1 << (31 - __builtin_clz((uint32_t)o));
-            copies.push_back(b.rot(copies[o - hb], -(int32_t)(GR * (uint32_t)hb)));
-        }
+        for (int o = 1; o < d2.out_dim; ++o) copies.push_back(b.rot(h, -(int32_t)(GR * (uint32_t)o), true));
         for (int o = 0; o < d2.out_dim; ++o) prods.push_back(b.mulplain(copies[o], out_row(o, GR * (uint32_t)o)));
         int z = b.lincomb_any(prods, std::vector<int64_t>(prods.size(), 1), -1);
         z = b.rotate_and_sum(z, coll);
@@ -551,7 +551,15 @@ float predict_us(const lola_plan *p) {
     const double sN = (double)p->N / 16384.0, L = (double)p->L;
     const double ks = sN * (L * L + 3 * L + 2) / 72.0, ew = sN * L / 7.0;
     double us = 0;
+    std::set<std::pair<int, int>> hoist_sources;   // (wave, source)
     for (const Op &o : p->ops) {
+        if (o.kind == OP_ROT && o.hoist) {
+            // hoisted: the gathered inner product and the mod-down, plus the
+            // source's decomposition and transforms once per wave
+            us += 4.8 * ks * 0.35;
+            if (hoist_sources.insert({o.level, o.src}).second) us += 4.8 * ks * 0.85;
+            continue;
+        }
         switch (o.kind) {
             case OP_ROT:
             case OP_ROTADD: us += 4.8 * ks; break;
@@ -585,8 +593,14 @@ float predict_latency_us(const lola_plan *p) {
     };
     double us = 0;
     for (uint32_t lev = 1; lev <= p->n_waves; ++lev) {
-        double lin = 0, plain = 0, sq = 0, rot = 0;
+        double lin = 0, plain = 0, sq = 0, rot = 0, hrot = 0;
+        std::set<int> hsrc;
         for (int i : p->level_ops[lev]) {
+            if (p->ops[i].kind == OP_ROT && p->ops[i].hoist) {
+                hrot += 1;
+                hsrc.insert(p->ops[i].src);
+                continue;
+            }
             switch (p->ops[i].kind) {
                 case OP_LINCOMB: lin += 1; break;
                 case OP_MULPLAIN:
@@ -600,6 +614,11 @@ float predict_latency_us(const lola_plan *p) {
         if (plain > 0) us += 5.0;
         if (sq > 0) us += 42.0 * sl * (L / 7.0) * rounds(sq) + ks_us(sq);
         us += ks_us(rot);
+        if (hrot > 0) {   // sources' digits and transforms, then gathered products and mod-down
+            const double ns = (double)hsrc.size();
+            us += 17.0 * sl * rounds(ns * L) + 19.0 * sl * rounds(ns * L * (L + 1));
+            us += 14.0 * sl * (L / 7.0) * rounds(hrot * (L + 1)) + 17.0 * sl * rounds(2 * hrot * L);
+        }
     }
     return (float)us;
 }
@@ -640,6 +659,7 @@ void schedule(lola_plan *p) {
         if (last[r] >= 0 && r >= p->n_inputs && !outs.count((int)r)) release[last[r]].push_back((int)r);
     uint32_t nphys = 0, cur_level = 0;
     std::vector<uint32_t> squares(maxl + 1, 0);
+    std::vector<std::set<int>> hoist_src(maxl + 1);
     for (int idx : order) {
         const Op &o = p->ops[idx];
         while (cur_level < (uint32_t)o.level) {   // entering a new level: buffers last read earlier are free
@@ -647,6 +667,7 @@ void schedule(lola_plan *p) {
             ++cur_level;
         }
         if (o.kind == OP_SQUARE) squares[o.level]++;
+        if (o.kind == OP_ROT && o.hoist) hoist_src[o.level].insert(o.src);
         if (outs.count(o.dst)) continue;
         if (free_list.empty()) free_list.push_back((int)nphys++);
         p->phys[o.dst] = free_list.back();
@@ -654,6 +675,8 @@ void schedule(lola_plan *p) {
     }
     p->n_phys = nphys;
     p->max_squares_per_wave = *std::max_element(squares.begin(), squares.end());
+    p->max_hoist_per_wave = 0;
+    for (const auto &hs : hoist_src) p->max_hoist_per_wave = std::max<uint32_t>(p->max_hoist_per_wave, (uint32_t)hs.size());
     std::set<uint32_t> g;
     for (const Op &o : p->ops)
         if (o.kind == OP_ROTADD || o.kind == OP_ROT) g.insert(o.galois);
@@ -963,7 +986,8 @@ int lola_plan_dump(const lola_plan *p, char *buf, size_t cap) {
                      std::to_string(o.addend);
                 break;
             case OP_ROT:
-                s += "rot " + std::to_string(o.dst) + " " + std::to_string(o.src) + " " + step(o.step);
+                s += (o.hoist ? "hrot " : "rot ") + std::to_string(o.dst) + " " + std::to_string(o.src) + " " +
+                     step(o.step);
                 break;
             case OP_SQUARE: s += "square " + std::to_string(o.dst) + " " + std::to_string(o.src); break;
         }

@@ -48,6 +48,8 @@ int emit_level(const lola_ctx *ctx, const lola_plan *p, const ReqView &rv, uint3
         return rq.gk_dev[k];
     };
     uint32_t sq_slot = 0;
+    std::vector<const uint32_t *> hoisted;   // sources of hoisted rotations in this wave
+    const size_t HW = ks_hoist_words(ctx);
     for (int i : p->level_ops[level]) {
         const Op &o = p->ops[i];
         uint32_t *dst = ptr(o.dst);
@@ -72,6 +74,27 @@ int emit_level(const lola_ctx *ctx, const lola_plan *p, const ReqView &rv, uint3
             case OP_ROTADD:
             case OP_ROT: {
                 const uint32_t *src = ptr(o.src);
+                if (o.kind == OP_ROT && o.hoist) {
+                    size_t k = std::find(hoisted.begin(), hoisted.end(), src) - hoisted.begin();
+                    if (k == hoisted.size()) {
+                        if (k >= p->max_hoist_per_wave) return set_error(LOLA_E_INVAL, "internal: hoist areas");
+                        hoisted.push_back(src);
+                        KsJob hs{};
+                        hs.x = src + L * N;
+                        hs.scratch = rv.hoist + k * HW;
+                        hs.galois = 1;
+                        out.hsrc.push_back(hs);
+                    }
+                    KsJob j{};
+                    j.x = src + L * N;
+                    j.key = gk(o.galois);
+                    j.add0 = src;
+                    j.out = dst;
+                    j.galois = o.galois;
+                    j.hoist = rv.hoist + k * HW;
+                    out.hrot.push_back(j);
+                    break;
+                }
                 KsJob j{};
                 j.x = src + L * N;
                 j.key = gk(o.galois);
@@ -97,7 +120,6 @@ int emit_level(const lola_ctx *ctx, const lola_plan *p, const ReqView &rv, uint3
             }
         }
     }
-    (void)ctx;
     return LOLA_OK;
 }
 
@@ -114,6 +136,12 @@ void program_level(const lola_ctx *ctx, Program &prog, LevelJobs &jobs, uint32_t
         program_keyswitch(ctx, prog, jobs.relin, scratch, ks_chunk);
     }
     program_keyswitch(ctx, prog, jobs.ks, scratch, ks_chunk);
+    if (!jobs.hrot.empty()) {
+        // sources first (their hoist areas are their own), then the rotations
+        // in chunks over the level scratch
+        prog.launch(LK_KS_HSRC, jobs.hsrc);
+        program_keyswitch(ctx, prog, jobs.hrot, scratch, ks_chunk, LK_KS_HROT);
+    }
 }
 
 namespace {
@@ -192,12 +220,16 @@ int bind(lola_ctx *ctx, lola_plan *p, ExecLane &ln, const lola_request *reqs, ui
     const uint32_t nsq = std::max<uint32_t>(p->max_squares_per_wave, 1);
     const size_t reg_words = (size_t)n * p->n_phys * CT;
     const size_t sq_words = (size_t)n * nsq * CT3;
-    int rc = ensure_ws(ln, reg_words + sq_words + level_scratch_words(ctx, ks_chunk, mul_chunk));
+    const size_t hoist_per_req = (size_t)p->max_hoist_per_wave * ks_hoist_words(ctx);
+    const size_t hoist_words = (size_t)n * hoist_per_req;
+    int rc = ensure_ws(ln, reg_words + sq_words + hoist_words + level_scratch_words(ctx, ks_chunk, mul_chunk));
     if (rc) return rc;
-    uint32_t *regs = ln.d_ws, *sqt = ln.d_ws + reg_words, *scratch = ln.d_ws + reg_words + sq_words;
+    uint32_t *regs = ln.d_ws, *sqt = ln.d_ws + reg_words, *hst = ln.d_ws + reg_words + sq_words;
+    uint32_t *scratch = hst + hoist_words;
     std::vector<ReqView> views(n);
     for (uint32_t r = 0; r < n; ++r)
-        views[r] = ReqView{&reqs[r], regs + (size_t)r * p->n_phys * CT, sqt + (size_t)r * nsq * CT3};
+        views[r] = ReqView{&reqs[r], regs + (size_t)r * p->n_phys * CT, sqt + (size_t)r * nsq * CT3,
+                           hst + (size_t)r * hoist_per_req};
     Program &prog = ln.prog;
     prog = Program();
     for (uint32_t lev = 1; lev <= p->n_waves; ++lev) {

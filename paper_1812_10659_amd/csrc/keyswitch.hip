@@ -233,16 +233,18 @@ size_t ks_hoist_words(const lola_ctx *ctx) { return ks_hoist_limbs(ctx->L) * ctx
 static constexpr uint32_t KS_CHUNK = 128;
 
 void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs, uint32_t *scratch,
-                       uint32_t chunk) {
+                       uint32_t chunk, LaunchKind kind) {
     // jobs that share a key side by side (see xcd_job_unit); the order of the
     // jobs of one launch does not change any result
     std::stable_sort(jobs.begin(), jobs.end(), [](const KsJob &a, const KsJob &b) { return a.key < b.key; });
     for (size_t off = 0; off < jobs.size(); off += chunk) {
         const size_t n = std::min<size_t>(chunk, jobs.size() - off);
-        const size_t per = ks_job_words(ctx, (uint32_t)n);   // fits in ks_chunk_words(ctx, chunk)
+        // fits in ks_chunk_words(ctx, chunk); hoisted rotations take the
+        // batched form whatever their number
+        const size_t per = kind == LK_KS ? ks_job_words(ctx, (uint32_t)n) : ks_scratch_words(ctx);
         std::vector<KsJob> part(jobs.begin() + off, jobs.begin() + off + n);
         for (size_t k = 0; k < n; ++k) part[k].scratch = scratch + per * k;
-        p.launch(LK_KS, part);
+        p.launch(kind, part);
         p.ks_jobs += n;
     }
 }

@@ -174,5 +174,6 @@ size_t mul_scratch_words(const lola_ctx *ctx);   // per pair
 size_t ks_scratch_words(const lola_ctx *ctx);    // per key switch job, launches of many jobs
 size_t ks_launch_words(const lola_ctx *ctx, uint32_t n);     // a launch of n jobs
 size_t ks_chunk_words(const lola_ctx *ctx, uint32_t chunk);  // any launch of at most chunk jobs
+size_t ks_hoist_words(const lola_ctx *ctx);      // hoist area of one source of hoisted rotations
 
 }  // namespace lola

@@ -21,6 +21,8 @@ struct Op {
     int cmul = -1, cadd = -1;     // plaintext constants (mul form, add form)
     int32_t step = 0;             // rotation step (LOLA_ROW_SWAP for the row swap)
     uint32_t galois = 0;
+    bool hoist = false;           // ROT: shares its source's decomposition with the other hoisted
+                                  // rotations of that source in its wave
     int level = 0;
 };
 
@@ -60,6 +62,7 @@ struct lola_plan {
     std::vector<int> phys;                      // virtual -> physical register (-1: input/output)
     uint32_t n_phys = 0;
     uint32_t max_squares_per_wave = 0;
+    uint32_t max_hoist_per_wave = 0;            // distinct sources of hoisted rotations in one wave
     std::vector<std::vector<int>> level_ops;    // op indices of each wave (index = level)
     // loaded constants (device)
     const lola_ctx *loaded_for = nullptr;
@@ -85,6 +88,7 @@ struct ReqView {
     const lola_request *req;
     uint32_t *regs;      // n_phys ciphertexts
     uint32_t *sq;        // max_squares_per_wave size-3 ciphertexts
+    uint32_t *hoist;     // max_hoist_per_wave hoist areas (ks_hoist_words each)
 };
 
 // The jobs of one wave, gathered over any number of requests.
@@ -92,8 +96,9 @@ struct LevelJobs {
     std::vector<LinJob> lin;
     std::vector<PlainJob> plain;
     std::vector<KsJob> ks, relin;
+    std::vector<KsJob> hsrc, hrot;   // hoisted rotations: sources, then the rotations
     std::vector<MulJob> muls;
-    size_t count() const { return lin.size() + plain.size() + ks.size() + muls.size(); }
+    size_t count() const { return lin.size() + plain.size() + ks.size() + muls.size() + hrot.size(); }
 };
 
 // Appends the jobs of plan level `level` for one request.

@@ -67,7 +67,7 @@ struct Program {
 // Builders.  Key switches and products are split into chunks that reuse the
 // scratch region [scratch, scratch + chunk * per-job words) in stream order.
 void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs, uint32_t *scratch,
-                       uint32_t chunk);
+                       uint32_t chunk, LaunchKind kind = LK_KS);
 void program_mul(const lola_ctx *ctx, Program &p, const std::vector<MulJob> &pairs, uint32_t *scratch,
                  uint32_t chunk);
 

@@ -38,7 +38,7 @@ struct Slot {
     uint32_t level = 0;
     Pending req;
     lola_request rq{};
-    uint32_t *regs = nullptr, *sq = nullptr;
+    uint32_t *regs = nullptr, *sq = nullptr, *hoist = nullptr;
 };
 
 struct Model {
@@ -107,7 +107,7 @@ int round_model(lola_server *srv, Model &m) {
     std::vector<Slot *> finishing;
     for (Slot &s : m.slots) {
         if (!s.busy || s.finished) continue;
-        ReqView rv{&s.rq, s.regs, s.sq};
+        ReqView rv{&s.rq, s.regs, s.sq, s.hoist};
         int rc = emit_level(m.ctx, p, rv, s.level, jobs);
         if (rc) return rc;
         if (++s.level > p->n_waves) finishing.push_back(&s);
@@ -166,7 +166,7 @@ int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint
     if (plan->loaded_for != ctx) return set_error(LOLA_E_INVAL, "plan not loaded on this context");
     const size_t N = ctx->N, L = ctx->L, CT = 2 * L * N, CT3 = 3 * L * N;
     const uint32_t nsq = std::max<uint32_t>(plan->max_squares_per_wave, 1);
-    const size_t slot_words = plan->n_phys * CT + nsq * CT3;
+    const size_t slot_words = plan->n_phys * CT + nsq * CT3 + (size_t)plan->max_hoist_per_wave * ks_hoist_words(ctx);
     const size_t scratch_words = level_scratch_words(ctx, SRV_KS_CHUNK, SRV_MUL_CHUNK);
     const size_t avail = srv->budget > srv->used ? srv->budget - srv->used : 0;
     if (avail < (scratch_words + slot_words) * 4)
@@ -183,6 +183,7 @@ int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint
     for (uint32_t k = 0; k < fit; ++k) {
         m.slots[k].regs = m.ws + k * slot_words;
         m.slots[k].sq = m.slots[k].regs + plan->n_phys * CT;
+        m.slots[k].hoist = m.slots[k].sq + nsq * CT3;
     }
     m.scratch = m.ws + fit * slot_words;
     srv->used += words * 4;

@@ -72,9 +72,9 @@ def dump_to_oracle_ops(plan):
             r = nxt; nxt += 1
             ops.append(("rotate", r, src, step))
             ops.append(("add", dst, addend, r))
-        elif f[0] == "rot":
+        elif f[0] in ("rot", "hrot"):
             step = bfv.ROW_SWAP if f[3] == "swap" else int(f[3])
-            ops.append(("rotate", int(f[1]), int(f[2]), step))
+            ops.append(("rotate" if f[0] == "rot" else "rotate_hoisted", int(f[1]), int(f[2]), step))
         elif f[0] == "square":
             ops.append(("square", int(f[1]), int(f[2])))
         else:
@@ -92,6 +92,7 @@ def _check_plan(lola, params, layers, inputs_values, expected, oracle_sched, rec
     assert list(got) == list(nw._mod(expected, params.t))
     info = plan.info
     assert info["n_rotations"] == oracle_sched.count("rotate")
+    assert plan.dump().count("\nhrot ") + plan.dump().startswith("hrot ") == oracle_sched.count("rotate_hoisted")
     assert info["n_mul_plain"] == oracle_sched.count("mul_plain")
     assert info["n_square"] == oracle_sched.count("square")
     assert sorted(plan.galois()) == nw.galois_elements(oracle_sched)
