@@ -51,8 +51,31 @@ __device__ __forceinline__ JobUnit xcd_job_unit(uint32_t k, uint32_t units, uint
 // Grid size for n jobs of `units` workgroups each (ids past the last job exit).
 inline uint32_t xcd_grid(uint32_t n, uint32_t units) { return (n + N_XCD - 1) / N_XCD * N_XCD * units; }
 
-__device__ __forceinline__ uint32_t ks_perm(uint32_t idx, uint32_t g, uint32_t logN) {
-    return g > 1 ? galois_src_index(idx, g, logN) : idx;
+// v = the limb src (N words, NTT form) read through sigma_g at this thread's
+// positions of the transform's output layout.  Without an automorphism
+// (g <= 1) a plain 16-byte-per-lane read; otherwise the limb is staged in LDS
+// with coalesced 16-byte loads and gathered from there (a gather straight from
+// global memory touches a different cache line per lane).  g is the same for
+// the whole workgroup.  Uses sh (N words) between two workgroup barriers.
+template <int LOGN>
+__device__ __forceinline__ void ks_read_sigma(const uint32_t *src, uint32_t g, uint32_t tid, uint32_t *sh,
+                                              uint32_t (&v)[NTT_E]) {
+    constexpr uint32_t N = 1u << LOGN, T = N / NTT_E;
+    const GBuf S = gbuf(src, N);
+    if (g <= 1) {
+        load_spectral<LOGN>(S, tid, v);
+        return;
+    }
+    __syncthreads();   // earlier readers of sh are done
+#pragma unroll
+    for (uint32_t r = 0; r < NTT_E / 4; ++r) {
+        const uint32_t w = 4 * (tid + r * T);
+        const u32x4 q = gld4(S, w);
+        sh[w] = q.x, sh[w + 1] = q.y, sh[w + 2] = q.z, sh[w + 3] = q.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) v[r] = sh[galois_src_index(spectral_index<LOGN>(tid, r), g, LOGN)];
 }
 
 // Stage 1 for digit i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
@@ -65,12 +88,10 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
     asm volatile("" : "+v"(tid));
     uint32_t ii = i;
     asm volatile("" : "+s"(ii));
-    const GBuf xi = gbuf(x + ((size_t)ii << LOGN), N);
     uint32_t v[NTT_E];
-#pragma unroll
-    for (int r = 0; r < NTT_E; ++r) v[r] = gld(xi, ks_perm(spectral_index<LOGN>(tid, r), g, LOGN));
+    ks_read_sigma<LOGN>(x + ((size_t)ii << LOGN), g, tid, sh, v);
     store_spectral<LOGN>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
-    ntt_inv_regs<LOGN>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
+    ntt_inv_regs<LOGN>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);   // starts with a barrier
     const GBuf D = gbuf(scratch + ((size_t)ii << LOGN), N);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN>(tid, r), v[r]);
@@ -265,9 +286,9 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(shoup_lazy(u[r] + mc.q - x[r], pinv, pinvp, mc.q), mc.q);
     if (add) {
-        const GBuf a = gbuf(add + ((size_t)jj << LOGN), N);
+        ks_read_sigma<LOGN>(add + ((size_t)jj << LOGN), g, tid, sh, u);   // after the transform's last use of sh
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], gld(a, ks_perm(spectral_index<LOGN>(tid, r), g, LOGN)), mc.q);
+        for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], u[r], mc.q);
     }
     if (addct) {
         load_spectral<LOGN>(gbuf(addct + ((size_t)(c * L + jj) << LOGN), N), tid, u);
