@@ -542,8 +542,9 @@ int compile_dense_head_stacked(lola_plan *p, Builder &b, const lola_layer *ls, u
 
 // ---- cost model ---------------------------------------------------------
 // Microseconds per operation of one request inside a large batch, measured on
-// MI355X at N = 16384 with seven data primes (batched key switch 4.8, ct x ct
-// product and relinearisation 27, plaintext product 0.55, one source of a
+// MI355X at N = 16384 with seven data primes (batched key switch 3.9, hoisted
+// rotation 0.69 of that plus 0.48 of it once per source and wave, ct x ct
+// product and relinearisation 24, plaintext product 0.55, one source of a
 // linear combination 0.35, plaintext add 0.5); key switches and products
 // scale with N log N and the number of limb transforms (L^2 + 3L + 2),
 // element-wise passes with L N.
@@ -556,14 +557,14 @@ float predict_us(const lola_plan *p) {
         if (o.kind == OP_ROT && o.hoist) {
             // hoisted: the gathered inner product and the mod-down, plus the
             // source's decomposition and transforms once per wave
-            us += 4.8 * ks * 0.35;
-            if (hoist_sources.insert({o.level, o.src}).second) us += 4.8 * ks * 0.85;
+            us += 3.9 * ks * 0.69;
+            if (hoist_sources.insert({o.level, o.src}).second) us += 3.9 * ks * 0.48;
             continue;
         }
         switch (o.kind) {
             case OP_ROT:
-            case OP_ROTADD: us += 4.8 * ks; break;
-            case OP_SQUARE: us += 27.0 * ks; break;
+            case OP_ROTADD: us += 3.9 * ks; break;
+            case OP_SQUARE: us += 24.0 * ks; break;
             case OP_MULPLAIN: us += (0.55 + (o.cadd >= 0 ? 0.25 : 0.0)) * ew; break;
             case OP_LINCOMB: us += 0.35 * (double)o.srcs.size() * ew; break;
             case OP_ADDPLAIN: us += 0.5 * ew; break;

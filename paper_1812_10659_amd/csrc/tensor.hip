@@ -38,6 +38,7 @@ __global__ void tensor_extend_kernel(const MulJob *__restrict__ jobs, uint32_t N
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x, p = blockIdx.y;
     if (k >= N) return;
     const MulJob job = jobs[blockIdx.z];
+    if (p >= 2 && job.a == job.b) return;   // a square: the second operand is the first
     const uint32_t *src = job.scr + offAc;
     uint32_t *dst = job.scr + offBx;
     const int L = (int)mrc->L, nB = (int)mrc->nB;
@@ -76,8 +77,8 @@ __global__ void tensor_product_kernel(const MulJob *__restrict__ jobs, uint32_t 
         const uint32_t j = l - L;
         c = mcs[L + 1 + j];
         const uint32_t *ext = job.scr + offBx;
-        const size_t o = (size_t)j * N + k, PB = (size_t)nB * N;
-        a0 = ext[o]; a1 = ext[PB + o]; b0 = ext[2 * PB + o]; b1 = ext[3 * PB + o];
+        const size_t o = (size_t)j * N + k, PB = (size_t)nB * N, ob = job.a == job.b ? o : 2 * PB + o;
+        a0 = ext[o]; a1 = ext[PB + o]; b0 = ext[ob]; b1 = ext[PB + ob];
     }
     const uint32_t a0m = shoup(a0, c.r_mod, c.r_shoup, c.q), a1m = shoup(a1, c.r_mod, c.r_shoup, c.q);
     const uint32_t d0 = mont_mul(a0m, b0, c.q, c.qneg_inv);
@@ -168,11 +169,14 @@ void program_mul(const lola_ctx *ctx, Program &p, const std::vector<MulJob> &pai
             MulJob j = pairs[off + k];
             j.scr = scratch + ml.total * k;
             jobs[k] = j;
+            // a square (a == b) transforms and extends its operand once; the
+            // product kernel reads the first operand's extension for both
+            const int nops = j.a == j.b ? 2 : 4;
             const uint32_t *srcs[4] = {j.a, j.a + P1, j.b, j.b + P1};
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < nops; ++q)
                 for (uint32_t i = 0; i < L; ++i)
                     n1.push_back(NttJob{srcs[q] + i * N, j.scr + ml.Ac + (q * L + i) * N, i, NTT_INVERSE});
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < nops; ++q)
                 for (uint32_t b = 0; b < nB; ++b) {
                     uint32_t *x = j.scr + ml.Bx + (q * nB + b) * N;
                     n2.push_back(NttJob{x, x, ctx->idxB(b), 0});

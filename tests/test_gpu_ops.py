@@ -201,6 +201,23 @@ def test_mul_matches_oracle(env):
     assert np.array_equal(got, np.stack(bfv.mul(octx, c1, c2)))
     got = _down(ctx, ctx.mul(_up(ctx, c1), _up(ctx, c1)))
     assert np.array_equal(got, np.stack(bfv.mul(octx, c1, c1)))
+    # a square from one buffer transforms and extends its operand once
+    x = _up(ctx, c2)
+    assert np.array_equal(_down(ctx, ctx.mul(x, x)), np.stack(bfv.mul(octx, c2, c2)))
+
+
+def test_mul_batch_mixes_squares_and_products(env):
+    """One batched launch with products of two buffers and squares of one."""
+    from paper_1812_10659_amd import batched
+    ctx, octx = env["ctx"], env["octx"]
+    c1, c2 = env["c"]
+    x1, x2 = _up(ctx, c1), _up(ctx, c2)
+    a, b = [x1, x2, x1, x2], [x2, x2, x1, x1]
+    outs = [ctx.empty_ct(3) for _ in a]
+    batched.mul_batch(ctx, a, b, outs)
+    refs = [bfv.mul(octx, c1, c2), bfv.mul(octx, c2, c2), bfv.mul(octx, c1, c1), bfv.mul(octx, c2, c1)]
+    for k, (o, r) in enumerate(zip(outs, refs)):
+        assert np.array_equal(_down(ctx, o), np.stack(r)), f"pair {k}"
 
 
 def test_relin_matches_oracle(env):
