@@ -118,6 +118,19 @@ def test_error_codes(toy):
     with pytest.raises(lola.LolaError) as e:
         ctx.ntt_limbs(torch.zeros((1, p.N), dtype=torch.int32, device=ctx.device), [99])
     assert _code(e) == -1
+    # hoisted rotations: g = 1 or even, an output that is the input, a missing key
+    for bad_g in (1, 2, 2 * p.N + 1):
+        with pytest.raises(lola.LolaError) as e:
+            ctx.rotate_hoisted(ct, [bad_g], [toy["gks"][g1]])
+        assert _code(e) == -1
+    garr = (ctypes.c_uint32 * 1)(g1)
+    karr = (ctypes.c_void_p * 1)(toy["gks"][g1].data_ptr())
+    oarr = (ctypes.c_void_p * 1)(ct.data_ptr())
+    assert lola.lib().lola_rotate_hoisted(ctx.h, ct.data_ptr(), 1, garr, karr, oarr, lola._stream()) == -1
+    karr0 = (ctypes.c_void_p * 1)(None)
+    oarr2 = (ctypes.c_void_p * 1)(ctx.empty_ct().data_ptr())
+    assert lola.lib().lola_rotate_hoisted(ctx.h, ct.data_ptr(), 1, garr, karr0, oarr2, lola._stream()) == -5
+    assert lola.lib().lola_rotate_hoisted(ctx.h, ct.data_ptr(), 0, garr, karr, oarr2, lola._stream()) == 0
     # NTT variants: an index past the list, autotune sizes out of range
     nv = len(ctx.ntt_variants())
     with pytest.raises(lola.LolaError) as e:
