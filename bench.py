@@ -87,6 +87,8 @@ def main():
                     help="mixed Poisson serving run after the timed steps (0 = skip)")
     ap.add_argument("--serve-high-rate", type=float, default=800.0,
                     help="arrival rate of a second serving run above what one-at-a-time can sustain (0 = skip)")
+    ap.add_argument("--serve-saturation-rate", type=float, default=4000.0,
+                    help="arrival rate of a third serving run, above what the GPU can sustain (0 = skip)")
     ap.add_argument("--no-integer-logits", action="store_true",
                     help="skip the run under seven plaintext moduli (exact integer logits by CRT)")
     ap.add_argument("--lanes", type=int, default=2, choices=(1, 2),
@@ -293,6 +295,8 @@ def main():
         out["serving"] = serving.run_serving(n_req=args.serve_requests)
         if args.serve_high_rate > 0:
             out["serving_high_load"] = serving.run_serving(n_req=args.serve_requests, rate=args.serve_high_rate)
+        if args.serve_saturation_rate > 0:
+            out["serving_saturation"] = serving.run_serving(n_req=args.serve_requests, rate=args.serve_saturation_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, w, ORACLE_RECIPE[headline_recipe])
     print(json.dumps(out), flush=True)
