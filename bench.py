@@ -159,6 +159,17 @@ def main():
         plan.evaluate(ctx, reqs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # the same steps replayed through a HIP graph (captured once, with the
+    # same two lanes) on a stream of its own
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        plan.evaluate(ctx, reqs, graph=True, stream=gs)   # capture
+        gs.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            plan.evaluate(ctx, reqs, graph=True, stream=gs)
+        gs.synchronize()
+        elapsed_graph = time.perf_counter() - tg
     # roofline: the same steps with the key-switch inner kernel timed by HIP
     # events on its launch stream; kernel timing runs the batch as one lane,
     # so every launch is timed alone
@@ -196,6 +207,19 @@ def main():
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
     lat = np.array(lat)
+    # the same, replayed through a HIP graph
+    lat_g = []
+    with torch.cuda.stream(gs):
+        plan.evaluate(ctx, one, graph=True, stream=gs)   # capture
+        gs.synchronize()
+        for _ in range(args.latency_runs):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(gs)
+            plan.evaluate(ctx, one, graph=True, stream=gs)
+            e1.record(gs)
+            e1.synchronize()
+            lat_g.append(e0.elapsed_time(e1))
+    lat_g = np.array(lat_g)
 
     # NTT throughput: batched forward transforms of 7*512 limbs
     nl = 7 * 512
@@ -249,7 +273,12 @@ def main():
                    "batch_requests": B, "client_key_sets": C, "lanes": args.lanes, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
-                       "single_request_inferences_per_s": round(1e3 / float(np.median(lat)), 2)},
+                       "single_request_inferences_per_s": round(1e3 / float(np.median(lat)), 2),
+                       "graph_replay_p50": round(float(np.percentile(lat_g, 50)), 3),
+                       "graph_replay_p99": round(float(np.percentile(lat_g, 99)), 3)},
+        "graph_replay": {"ms_per_step": round(elapsed_graph / args.steps * 1e3, 3),
+                         "inferences_per_s": round(B * args.steps / elapsed_graph, 2),
+                         "note": "the timed steps replayed from one captured HIP graph"},
         "roofline": {"bound": "alu", "kernel": "ks_inner_kernel<14>",
                      "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 1),
                      "unit": "T VALU lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4),

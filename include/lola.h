@@ -424,8 +424,9 @@ int lola_evaluate(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint
 /* Upper bound on the lanes of lola_evaluate: 1 or 2 (the default). */
 int lola_plan_set_lanes(lola_plan *plan, uint32_t max_lanes);
 /* Same, replayed through a HIP graph captured on the first call for this
- * exact set of buffers (re-captured when any pointer or n_req changes); one
- * lane. */
+ * exact set of buffers (re-captured when any pointer, n_req or the number of
+ * lanes changes).  A batch of 16 or more requests is captured as two lanes,
+ * forked onto the plan's second stream and joined back inside the graph. */
 int lola_evaluate_graph(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs, uint32_t n_req,
                         lola_stream stream);
 

@@ -266,7 +266,7 @@ int prepare(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n, h
         auto ptrs = request_ptrs(p, reqs + off, cnt);
         if (ln.prog_valid && ptrs == ln.bound_ptrs) continue;
         ln.prog_valid = false;
-        if (k == 0) release_graph(p);
+        release_graph(p);   // a captured graph runs the lanes' programs
         if (cnt == 0) {   // unused lane: nothing bound
             ln.prog = Program();
             ln.bound_ptrs = ptrs;
@@ -383,6 +383,32 @@ void lola_plan_destroy(lola_plan *p) {
     delete p;
 }
 
+// The second lane's stream (default priority) and its fork/join events.
+static int ensure_side(lola_plan *p) {
+    if (p->side_stream) return LOLA_OK;
+    LOLA_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
+    LOLA_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+    LOLA_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
+    return LOLA_OK;
+}
+
+// Issues the bound lanes' programs: one lane on s, or two forked from s onto
+// the plan's side stream and joined back (also while s is being captured:
+// the side stream then joins the capture through the fork event, so the
+// stream and events must exist before the capture begins).
+static int run_lanes(lola_ctx *ctx, lola_plan *p, uint32_t n_lanes, hipStream_t s) {
+    if (n_lanes == 1) return program_run(ctx, p->lanes[0].prog, p->lanes[0].d_blob, s);
+    int rc = ensure_side(p);
+    if (rc) return rc;
+    LOLA_HIP(hipEventRecord(p->fork_ev, s));   // inputs and uploads on s come first
+    LOLA_HIP(hipStreamWaitEvent(p->side_stream, p->fork_ev, 0));
+    rc = run_two(ctx, p->lanes[0], s, p->lanes[1], p->side_stream);
+    // join even after an error, so s never runs ahead of queued side work
+    LOLA_HIP(hipEventRecord(p->join_ev, p->side_stream));
+    LOLA_HIP(hipStreamWaitEvent(s, p->join_ev, 0));
+    return rc;
+}
+
 int lola_evaluate(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n, lola_stream stream) {
     if (!ctx || !p || (!reqs && n)) return set_error(LOLA_E_INVAL, "null argument");
     if (n == 0) return LOLA_OK;
@@ -393,19 +419,7 @@ int lola_evaluate(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_
     const uint32_t n_lanes = (!ctx->timing && n >= EXEC_LANE_MIN_REQUESTS && p->max_lanes >= 2) ? 2 : 1;
     int rc = prepare(ctx, p, reqs, n, s, n_lanes);
     if (rc) return rc;
-    if (n_lanes == 1) return program_run(ctx, p->lanes[0].prog, p->lanes[0].d_blob, s);
-    if (!p->side_stream) {
-        LOLA_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
-        LOLA_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
-        LOLA_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
-    }
-    LOLA_HIP(hipEventRecord(p->fork_ev, s));   // inputs and uploads on s come first
-    LOLA_HIP(hipStreamWaitEvent(p->side_stream, p->fork_ev, 0));
-    rc = run_two(ctx, p->lanes[0], s, p->lanes[1], p->side_stream);
-    // join even after an error, so s never runs ahead of queued side work
-    LOLA_HIP(hipEventRecord(p->join_ev, p->side_stream));
-    LOLA_HIP(hipStreamWaitEvent(s, p->join_ev, 0));
-    return rc;
+    return run_lanes(ctx, p, n_lanes, s);
 }
 
 int lola_plan_set_lanes(lola_plan *p, uint32_t max_lanes) {
@@ -421,12 +435,15 @@ int lola_evaluate_graph(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, u
     if (ctx->timing) return set_error(LOLA_E_INVAL, "kernel timing and graph replay are exclusive");
     hipStream_t s = (hipStream_t)stream;
     if (!s) return set_error(LOLA_E_INVAL, "graph replay needs a non-default stream");
-    int rc = prepare(ctx, p, reqs, n, s, 1);
+    // the same lanes as lola_evaluate (kernel timing is off here)
+    const uint32_t n_lanes = (n >= EXEC_LANE_MIN_REQUESTS && p->max_lanes >= 2) ? 2 : 1;
+    int rc = prepare(ctx, p, reqs, n, s, n_lanes);
     if (rc) return rc;
     if (!p->graph_valid) {
+        if (n_lanes == 2 && (rc = ensure_side(p))) return rc;
         LOLA_HIP(hipStreamSynchronize(s));   // blob upload done before capture
         LOLA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        rc = program_run(ctx, p->lanes[0].prog, p->lanes[0].d_blob, s);
+        rc = run_lanes(ctx, p, n_lanes, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (rc) {

@@ -223,7 +223,8 @@ def test_batched_requests_equal_single_and_graph_replay():
 def test_two_lane_batch_equals_single_requests():
     """A batch of 17 requests (two lanes of 9 and 8 on two streams) equals
     each request evaluated alone; so does the same batch as one lane (kernel
-    timing on) and as a graph replay, and a second two-lane run after them."""
+    timing on) and as graph replays captured with two lanes and with one,
+    with eager runs between the replays."""
     import torch
     from paper_1812_10659_amd import lola, networks
     _, W = wl.dense64_inputs()
@@ -260,15 +261,23 @@ def test_two_lane_batch_equals_single_requests():
     lola.kernel_timing(ctx)
     check("one lane")
     s = torch.cuda.Stream()
-    with torch.cuda.stream(s):
-        plan.evaluate(ctx, reqs, graph=True, stream=s)
-    s.synchronize()
-    check("graph")
+
+    def replay(tag):
+        with torch.cuda.stream(s):
+            plan.evaluate(ctx, reqs, graph=True, stream=s)
+        s.synchronize()
+        check(tag)
+
+    replay("graph (two lanes captured)")
     plan.evaluate(ctx, reqs)
     torch.cuda.synchronize()
     check("two lanes again")
+    replay("graph replayed after eager work")
     plan.set_lanes(1)
     plan.evaluate(ctx, reqs)
     torch.cuda.synchronize()
     check("lanes limited to one")
+    replay("graph recaptured as one lane")
+    replay("one-lane graph replayed")
     plan.set_lanes(2)
+    replay("graph recaptured as two lanes")
