@@ -129,6 +129,11 @@ int lola_keygen_switch(lola_ctx *ctx, uint64_t seed, const uint32_t *sk_dev, uin
  * reduced mod t); pt_dev: N words in [0, t). */
 int lola_encode(lola_ctx *ctx, const int64_t *slots_dev, uint32_t *pt_dev, lola_stream stream);
 int lola_decode(lola_ctx *ctx, const uint32_t *pt_dev, int64_t *slots_dev, lola_stream stream);
+/* The same over n messages stored back to back: slots_dev n * N int64,
+ * pt_dev n * N words; message i equals the single call on message i.  A
+ * client's whole input (25 messages of the MNIST network) is one call. */
+int lola_encode_batch(lola_ctx *ctx, const int64_t *slots_dev, uint32_t n, uint32_t *pt_dev, lola_stream stream);
+int lola_decode_batch(lola_ctx *ctx, const uint32_t *pt_dev, uint32_t n, int64_t *slots_dev, lola_stream stream);
 /* Plaintext forms: mul form = centred lift [m]_t per prime (for
  * lola_mul_plain); add form = floor(Q/t) * m per prime (for lola_add_plain). */
 int lola_plain_mul_form(lola_ctx *ctx, const uint32_t *pt_dev, uint32_t *out_dev, lola_stream stream);
@@ -156,6 +161,15 @@ int lola_encrypt(lola_ctx *ctx, const uint32_t *pk_dev, const uint32_t *pt_dev, 
  * exactly (mixed-radix, no floating point).  size = 2 or 3. */
 int lola_decrypt(lola_ctx *ctx, const uint32_t *sk_dev, const uint32_t *ct_dev, uint32_t size,
                  uint32_t *pt_dev, lola_stream stream);
+/* The same over n messages stored back to back (pt_dev n * N words, ct_dev
+ * n ciphertexts of 2 * L * N words; for decryption, of size * L * N words):
+ * message i of lola_encrypt_batch is encrypted with object id nonce0 + i and
+ * equals lola_encrypt with that nonce word for word (LOLA_E_INVAL when
+ * nonce0 + n exceeds 2^32).  Scratch is taken 16 messages at a time. */
+int lola_encrypt_batch(lola_ctx *ctx, const uint32_t *pk_dev, const uint32_t *pt_dev, uint32_t n, uint64_t seed,
+                       uint32_t nonce0, uint32_t *ct_dev, lola_stream stream);
+int lola_decrypt_batch(lola_ctx *ctx, const uint32_t *sk_dev, const uint32_t *ct_dev, uint32_t n, uint32_t size,
+                       uint32_t *pt_dev, lola_stream stream);
 
 /* ------------------------------------------------------------- operations */
 /* out = a + b.  `size` components (2 or 3). */

@@ -1,6 +1,9 @@
 // Element-wise ciphertext operations in the NTT domain, slot encoding and
 // plaintext forms.  These are HBM-bound streams: each thread moves 4 words
 // with 128-bit loads and stores; the limb of a word is (word / N) mod L.
+#include <algorithm>
+#include <vector>
+
 #include "lola_internal.hpp"
 
 namespace lola {
@@ -60,21 +63,26 @@ __global__ void ew_add_plain_kernel(const uint4 *__restrict__ ct, const uint4 *_
     out[i] = x;
 }
 
+// grid (N / 256, messages): message blockIdx.y at offset blockIdx.y * N
 __global__ void encode_scatter_kernel(const int64_t *__restrict__ slots, const uint32_t *__restrict__ pos,
                                       uint32_t *__restrict__ buf, uint32_t N, uint32_t t) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
-    int64_t v = slots[s] % (int64_t)t;
+    const size_t m = (size_t)blockIdx.y * N;
+    int64_t v = slots[m + s] % (int64_t)t;
     if (v < 0) v += t;
-    buf[pos[s]] = (uint32_t)v;
+    buf[m + pos[s]] = (uint32_t)v;
 }
 
 __global__ void decode_gather_kernel(const uint32_t *__restrict__ buf, const uint32_t *__restrict__ pos,
                                      int64_t *__restrict__ slots, uint32_t N) {
     uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
-    slots[s] = (int64_t)buf[pos[s]];
+    const size_t m = (size_t)blockIdx.y * N;
+    slots[m + s] = (int64_t)buf[m + pos[s]];
 }
+
+constexpr uint32_t CODEC_CHUNK = 64;   // messages per scratch fill (256 KiB each at N = 16384)
 
 static inline dim3 grid_for(size_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
 
@@ -134,32 +142,54 @@ int lola_add_plain(lola_ctx *ctx, const uint32_t *ct, const uint32_t *pta, uint3
     return LOLA_OK;
 }
 
+int lola_encode_batch(lola_ctx *ctx, const int64_t *slots, uint32_t n, uint32_t *pt, lola_stream stream) {
+    if (!ctx || (n && (!slots || !pt))) return set_error(LOLA_E_INVAL, "null argument");
+    const size_t N = ctx->N;
+    hipStream_t s = (hipStream_t)stream;
+    for (uint32_t m0 = 0; m0 < n; m0 += CODEC_CHUNK) {
+        const uint32_t c = std::min(CODEC_CHUNK, n - m0);
+        void *buf = nullptr;
+        int rc = scratch_get(ctx, c * N * 4, &buf);
+        if (rc) return rc;
+        hipLaunchKernelGGL(encode_scatter_kernel, dim3((unsigned)((N + 255) / 256), c), dim3(256), 0, s,
+                           slots + m0 * N, ctx->d_slotpos, (uint32_t *)buf, ctx->N, ctx->t);
+        LOLA_HIP(hipGetLastError());
+        std::vector<NttJob> jobs(c);
+        for (uint32_t m = 0; m < c; ++m)
+            jobs[m] = NttJob{(const uint32_t *)buf + m * N, pt + (m0 + m) * N, ctx->idxT(), NTT_INVERSE};
+        if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)c, s))) return rc;
+    }
+    return LOLA_OK;
+}
+
+int lola_decode_batch(lola_ctx *ctx, const uint32_t *pt, uint32_t n, int64_t *slots, lola_stream stream) {
+    if (!ctx || (n && (!slots || !pt))) return set_error(LOLA_E_INVAL, "null argument");
+    const size_t N = ctx->N;
+    hipStream_t s = (hipStream_t)stream;
+    for (uint32_t m0 = 0; m0 < n; m0 += CODEC_CHUNK) {
+        const uint32_t c = std::min(CODEC_CHUNK, n - m0);
+        void *buf = nullptr;
+        int rc = scratch_get(ctx, c * N * 4, &buf);
+        if (rc) return rc;
+        std::vector<NttJob> jobs(c);
+        for (uint32_t m = 0; m < c; ++m)
+            jobs[m] = NttJob{pt + (m0 + m) * N, (uint32_t *)buf + m * N, ctx->idxT(), NTT_SRC_REDUCE};
+        if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)c, s))) return rc;
+        hipLaunchKernelGGL(decode_gather_kernel, dim3((unsigned)((N + 255) / 256), c), dim3(256), 0, s,
+                           (const uint32_t *)buf, ctx->d_slotpos, slots + m0 * N, ctx->N);
+        LOLA_HIP(hipGetLastError());
+    }
+    return LOLA_OK;
+}
+
 int lola_encode(lola_ctx *ctx, const int64_t *slots, uint32_t *pt, lola_stream stream) {
     if (!ctx || !slots || !pt) return set_error(LOLA_E_INVAL, "null argument");
-    void *buf = nullptr;
-    int rc = scratch_get(ctx, (size_t)ctx->N * 4, &buf);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(encode_scatter_kernel, grid_for(ctx->N, 256), dim3(256), 0, s, slots, ctx->d_slotpos,
-                       (uint32_t *)buf, ctx->N, ctx->t);
-    LOLA_HIP(hipGetLastError());
-    NttJob job{(const uint32_t *)buf, pt, ctx->idxT(), NTT_INVERSE};
-    return launch_ntt_jobs(ctx, &job, 1, s);
+    return lola_encode_batch(ctx, slots, 1, pt, stream);
 }
 
 int lola_decode(lola_ctx *ctx, const uint32_t *pt, int64_t *slots, lola_stream stream) {
     if (!ctx || !slots || !pt) return set_error(LOLA_E_INVAL, "null argument");
-    void *buf = nullptr;
-    int rc = scratch_get(ctx, (size_t)ctx->N * 4, &buf);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    NttJob job{pt, (uint32_t *)buf, ctx->idxT(), NTT_SRC_REDUCE};
-    rc = launch_ntt_jobs(ctx, &job, 1, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(decode_gather_kernel, grid_for(ctx->N, 256), dim3(256), 0, s, (const uint32_t *)buf,
-                       ctx->d_slotpos, slots, ctx->N);
-    LOLA_HIP(hipGetLastError());
-    return LOLA_OK;
+    return lola_decode_batch(ctx, pt, 1, slots, stream);
 }
 
 int lola_plain_mul_form(lola_ctx *ctx, const uint32_t *pt, uint32_t *out, lola_stream stream) {

@@ -4,6 +4,9 @@
 // seed hi, 0, ..., 0), nonce = (domain, object, limb), block counter =
 // coefficient / 8, word = coefficient mod 8.  Uniform residues are word mod m,
 // ternary values word mod 3 - 1, errors a centred binomial over 2 x 21 bits.
+#include <algorithm>
+#include <vector>
+
 #include "lola_internal.hpp"
 #include "mrc.hpp"
 
@@ -85,6 +88,8 @@ static int launch_samples(lola_ctx *ctx, uint64_t seed, const std::vector<Sample
     return LOLA_OK;
 }
 
+constexpr uint32_t CLIENT_CHUNK = 16;   // messages per scratch fill in encrypt / decrypt
+
 // a*b mod q for residues in normal form (two Montgomery steps).
 __device__ __forceinline__ uint32_t mulmod_plain(uint32_t a, uint32_t b, const ModConst &c) {
     return mont_mul(mont_mul(a, b, c.q, c.qneg_inv), c.r2_mod, c.q, c.qneg_inv);
@@ -137,14 +142,21 @@ __global__ void sprime_kernel(const uint32_t *__restrict__ sk, uint32_t *__restr
 }
 
 // c0 = pk0 u + e1 + Delta m, c1 = pk1 u + e2 (NTT domain).  grid (N/256, L)
+// grid (N/256, L, messages): message z reads its transformed samples at
+// z * msg_words past uh, e1h, e2h and mh, and writes ciphertext z.
 __global__ void enc_combine_kernel(const uint32_t *__restrict__ pk, const uint32_t *__restrict__ uh,
                                    const uint32_t *__restrict__ e1h, const uint32_t *__restrict__ e2h,
-                                   const uint32_t *__restrict__ mh, uint32_t *__restrict__ ct, uint32_t N,
-                                   uint32_t L, const ModConst *__restrict__ mcs) {
+                                   const uint32_t *__restrict__ mh, size_t msg_words, uint32_t *__restrict__ ct,
+                                   uint32_t N, uint32_t L, const ModConst *__restrict__ mcs) {
     const uint32_t j = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const ModConst c = mcs[j];
-    const size_t o = (size_t)j * N + k, P1 = (size_t)L * N;
+    const size_t P1 = (size_t)L * N, o = (size_t)j * N + k, om = blockIdx.z * msg_words + o;
+    uh += om - o;
+    e1h += om - o;
+    e2h += om - o;
+    mh += om - o;
+    ct += blockIdx.z * 2 * P1;
     const uint32_t u = uh[o];
     uint32_t c0 = mont_mul(u, pk[o], c.q, c.qneg_inv);
     c0 = add_mod(add_mod(c0, e1h[o], c.q), mh[o], c.q);
@@ -154,6 +166,8 @@ __global__ void enc_combine_kernel(const uint32_t *__restrict__ pk, const uint32
 }
 
 // x_j = c0 + c1 s (+ c2 s^2) per limb (NTT domain)
+// grid (N/256, L, messages): ciphertext z (size * L * N words apart) into
+// x + z * L * N
 __global__ void dec_phase_kernel(const uint32_t *__restrict__ ct, uint32_t size, const uint32_t *__restrict__ sk,
                                  uint32_t *__restrict__ x, uint32_t N, uint32_t L,
                                  const ModConst *__restrict__ mcs) {
@@ -161,6 +175,8 @@ __global__ void dec_phase_kernel(const uint32_t *__restrict__ ct, uint32_t size,
     if (k >= N) return;
     const ModConst c = mcs[j];
     const size_t o = (size_t)j * N + k, P1 = (size_t)L * N;
+    ct += blockIdx.z * size * P1;
+    x += blockIdx.z * P1;
     const uint32_t s = sk[o];
     uint32_t v = add_mod(ct[o], mulmod_plain(ct[P1 + o], s, c), c.q);
     if (size == 3) v = add_mod(v, mulmod_plain(ct[2 * P1 + o], mulmod_plain(s, s, c), c), c.q);
@@ -168,11 +184,14 @@ __global__ void dec_phase_kernel(const uint32_t *__restrict__ ct, uint32_t size,
 }
 
 // m = round(t x / Q) mod t from the coefficient residues of x, exactly.
+// grid (N/256, messages): x + y * L * N (coefficient form) into pt + y * N
 __global__ void dec_round_kernel(const uint32_t *__restrict__ x, uint32_t *__restrict__ pt, uint32_t N,
                                  const ModConst *__restrict__ mcs, const MrcConst *__restrict__ mrc) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const int L = (int)mrc->L;
+    x += (size_t)blockIdx.y * L * N;
+    pt += (size_t)blockIdx.y * N;
     const uint32_t t = mrc->t;
     uint32_t r[MAXL], v[MAXL];
 #pragma unroll
@@ -265,56 +284,81 @@ int lola_keygen_switch(lola_ctx *ctx, uint64_t seed, const uint32_t *sk, uint32_
     return LOLA_OK;
 }
 
+int lola_encrypt_batch(lola_ctx *ctx, const uint32_t *pk, const uint32_t *pt, uint32_t n, uint64_t seed,
+                       uint32_t nonce0, uint32_t *ct, lola_stream stream) {
+    if (!ctx || !pk || (n && (!pt || !ct))) return set_error(LOLA_E_INVAL, "null argument");
+    if ((uint64_t)nonce0 + n > (1ull << 32)) return set_error(LOLA_E_INVAL, "nonce0 + n exceeds 2^32");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = ctx->N, L = ctx->L, W = 3 * N + 4 * L * N;   // scratch words per message
+    for (uint32_t m0 = 0; m0 < n; m0 += CLIENT_CHUNK) {
+        const uint32_t c = std::min(CLIENT_CHUNK, n - m0);
+        void *buf = nullptr;
+        int rc = scratch_get(ctx, c * W * 4, &buf);
+        if (rc) return rc;
+        std::vector<SampleJob> sj;
+        std::vector<NttJob> jobs;
+        for (uint32_t m = 0; m < c; ++m) {
+            uint32_t *U = (uint32_t *)buf + m * W, *E1 = U + N, *E2 = E1 + N, *Uh = E2 + N, *E1h = Uh + L * N,
+                     *E2h = E1h + L * N, *Mh = E2h + L * N;
+            const uint32_t nonce = nonce0 + m0 + m;
+            sj.push_back(SampleJob{U, DOM_ENC_U, nonce, 0, SAMPLE_TERNARY, 0, 0});
+            sj.push_back(SampleJob{E1, DOM_ENC_E1, nonce, 0, SAMPLE_CBD, 0, 0});
+            sj.push_back(SampleJob{E2, DOM_ENC_E2, nonce, 0, SAMPLE_CBD, 0, 0});
+            for (uint32_t j = 0; j < L; ++j) {
+                jobs.push_back(NttJob{U, Uh + j * N, j, NTT_SRC_SIGNED32});
+                jobs.push_back(NttJob{E1, E1h + j * N, j, NTT_SRC_SIGNED32});
+                jobs.push_back(NttJob{E2, E2h + j * N, j, NTT_SRC_SIGNED32});
+                jobs.push_back(NttJob{pt + (m0 + m) * N, Mh + j * N, j, NTT_MUL_DELTA});
+            }
+        }
+        if ((rc = launch_samples(ctx, seed, sj, s))) return rc;
+        if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
+        const uint32_t *Uh = (const uint32_t *)buf + 3 * N;
+        hipLaunchKernelGGL(enc_combine_kernel, dim3((unsigned)(N / 256), (unsigned)L, c), dim3(256), 0, s, pk, Uh,
+                           Uh + L * N, Uh + 2 * L * N, Uh + 3 * L * N, W, ct + m0 * 2 * L * N, (uint32_t)N,
+                           (uint32_t)L, ctx->d_mc);
+        LOLA_HIP(hipGetLastError());
+    }
+    return LOLA_OK;
+}
+
 int lola_encrypt(lola_ctx *ctx, const uint32_t *pk, const uint32_t *pt, uint64_t seed, uint32_t nonce,
                  uint32_t *ct, lola_stream stream) {
     if (!ctx || !pk || !pt || !ct) return set_error(LOLA_E_INVAL, "null argument");
+    return lola_encrypt_batch(ctx, pk, pt, 1, seed, nonce, ct, stream);
+}
+
+int lola_decrypt_batch(lola_ctx *ctx, const uint32_t *sk, const uint32_t *ct, uint32_t n, uint32_t size,
+                       uint32_t *pt, lola_stream stream) {
+    if (!ctx || !sk || (n && (!ct || !pt))) return set_error(LOLA_E_INVAL, "null argument");
+    if (size != 2 && size != 3) return set_error(LOLA_E_SHAPE, "ciphertext size must be 2 or 3");
     hipStream_t s = (hipStream_t)stream;
     const size_t N = ctx->N, L = ctx->L;
-    void *buf = nullptr;
-    int rc = scratch_get(ctx, (3 * N + 4 * L * N) * 4, &buf);
-    if (rc) return rc;
-    uint32_t *U = (uint32_t *)buf, *E1 = U + N, *E2 = E1 + N, *Uh = E2 + N, *E1h = Uh + L * N,
-             *E2h = E1h + L * N, *Mh = E2h + L * N;
-    rc = launch_samples(ctx, seed,
-                        {SampleJob{U, DOM_ENC_U, nonce, 0, SAMPLE_TERNARY, 0, 0},
-                         SampleJob{E1, DOM_ENC_E1, nonce, 0, SAMPLE_CBD, 0, 0},
-                         SampleJob{E2, DOM_ENC_E2, nonce, 0, SAMPLE_CBD, 0, 0}},
-                        s);
-    if (rc) return rc;
-    std::vector<NttJob> jobs;
-    for (uint32_t j = 0; j < L; ++j) {
-        jobs.push_back(NttJob{U, Uh + j * N, j, NTT_SRC_SIGNED32});
-        jobs.push_back(NttJob{E1, E1h + j * N, j, NTT_SRC_SIGNED32});
-        jobs.push_back(NttJob{E2, E2h + j * N, j, NTT_SRC_SIGNED32});
-        jobs.push_back(NttJob{pt, Mh + j * N, j, NTT_MUL_DELTA});
+    for (uint32_t m0 = 0; m0 < n; m0 += CLIENT_CHUNK) {
+        const uint32_t c = std::min(CLIENT_CHUNK, n - m0);
+        void *buf = nullptr;
+        int rc = scratch_get(ctx, 2 * c * L * N * 4, &buf);
+        if (rc) return rc;
+        uint32_t *X = (uint32_t *)buf, *Xc = X + c * L * N;
+        hipLaunchKernelGGL(dec_phase_kernel, dim3((unsigned)(N / 256), (unsigned)L, c), dim3(256), 0, s,
+                           ct + m0 * size * L * N, size, sk, X, (uint32_t)N, (uint32_t)L, ctx->d_mc);
+        LOLA_HIP(hipGetLastError());
+        std::vector<NttJob> jobs;
+        for (uint32_t m = 0; m < c; ++m)
+            for (uint32_t j = 0; j < L; ++j)
+                jobs.push_back(NttJob{X + (m * L + j) * N, Xc + (m * L + j) * N, j, NTT_INVERSE});
+        if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
+        hipLaunchKernelGGL(dec_round_kernel, dim3((unsigned)(N / 256), c), dim3(256), 0, s, Xc, pt + m0 * N,
+                           (uint32_t)N, ctx->d_mc, ctx->d_mrc);
+        LOLA_HIP(hipGetLastError());
     }
-    if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
-    hipLaunchKernelGGL(enc_combine_kernel, dim3((unsigned)(N / 256), (unsigned)L), dim3(256), 0, s, pk, Uh, E1h,
-                       E2h, Mh, ct, (uint32_t)N, (uint32_t)L, ctx->d_mc);
-    LOLA_HIP(hipGetLastError());
     return LOLA_OK;
 }
 
 int lola_decrypt(lola_ctx *ctx, const uint32_t *sk, const uint32_t *ct, uint32_t size, uint32_t *pt,
                  lola_stream stream) {
     if (!ctx || !sk || !ct || !pt) return set_error(LOLA_E_INVAL, "null argument");
-    if (size != 2 && size != 3) return set_error(LOLA_E_SHAPE, "ciphertext size must be 2 or 3");
-    hipStream_t s = (hipStream_t)stream;
-    const size_t N = ctx->N, L = ctx->L;
-    void *buf = nullptr;
-    int rc = scratch_get(ctx, 2 * L * N * 4, &buf);
-    if (rc) return rc;
-    uint32_t *X = (uint32_t *)buf, *Xc = X + L * N;
-    hipLaunchKernelGGL(dec_phase_kernel, dim3((unsigned)(N / 256), (unsigned)L), dim3(256), 0, s, ct, size, sk, X,
-                       (uint32_t)N, (uint32_t)L, ctx->d_mc);
-    LOLA_HIP(hipGetLastError());
-    std::vector<NttJob> jobs;
-    for (uint32_t j = 0; j < L; ++j) jobs.push_back(NttJob{X + j * N, Xc + j * N, j, NTT_INVERSE});
-    if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
-    hipLaunchKernelGGL(dec_round_kernel, dim3((unsigned)(N / 256)), dim3(256), 0, s, Xc, pt, (uint32_t)N, ctx->d_mc,
-                       ctx->d_mrc);
-    LOLA_HIP(hipGetLastError());
-    return LOLA_OK;
+    return lola_decrypt_batch(ctx, sk, ct, 1, size, pt, stream);
 }
 
 int lola_export_sk(lola_ctx *ctx, const uint32_t *sk, uint32_t *out, lola_stream stream) {

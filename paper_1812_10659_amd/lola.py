@@ -76,10 +76,14 @@ def lib() -> ctypes.CDLL:
             "lola_keygen_switch": [vp, u64, vp, u32, vp, vp],
             "lola_encode": [vp, vp, vp, vp],
             "lola_decode": [vp, vp, vp, vp],
+            "lola_encode_batch": [vp, vp, u32, vp, vp],
+            "lola_decode_batch": [vp, vp, u32, vp, vp],
             "lola_plain_mul_form": [vp, vp, vp, vp],
             "lola_plain_add_form": [vp, vp, vp, vp],
             "lola_encrypt": [vp, vp, vp, u64, u32, vp, vp],
             "lola_decrypt": [vp, vp, vp, u32, vp, vp],
+            "lola_encrypt_batch": [vp, vp, vp, u32, u64, u32, vp, vp],
+            "lola_decrypt_batch": [vp, vp, vp, u32, u32, vp, vp],
             "lola_add": [vp, vp, vp, u32, vp, vp],
             "lola_add_plain": [vp, vp, vp, vp, vp],
             "lola_mul_plain": [vp, vp, vp, vp, vp],
@@ -200,6 +204,23 @@ class Context:
         _check(lib().lola_decode(self.h, _p(pt), _p(s), _stream()))
         return s
 
+    def encode_batch(self, slots, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """slots: [n][N] integers (host array or device int64 tensor), one host
+        to device copy for all; returns [n][N] plaintexts."""
+        s = slots if isinstance(slots, torch.Tensor) else torch.as_tensor(np.asarray(slots, dtype=np.int64))
+        s = s.to(device=self.device, dtype=torch.int64).contiguous()
+        n = s.shape[0]
+        pt = self.empty(n, self.N) if out is None else out
+        _check(lib().lola_encode_batch(self.h, _p(s), n, _p(pt), _stream()))
+        return pt
+
+    def decode_batch(self, pts: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """[n][N] plaintexts -> [n][N] device int64 slots in [0, t)."""
+        n = pts.shape[0]
+        s = torch.empty((n, self.N), dtype=torch.int64, device=self.device) if out is None else out
+        _check(lib().lola_decode_batch(self.h, _p(pts), n, _p(s), _stream()))
+        return s
+
     def plain_mul_form(self, pt: torch.Tensor) -> torch.Tensor:
         out = self.empty(self.L, self.N)
         _check(lib().lola_plain_mul_form(self.h, _p(pt), _p(out), _stream()))
@@ -211,10 +232,26 @@ class Context:
         return out
 
     # ---- encrypt / decrypt
-    def encrypt(self, pk, pt, seed: int, nonce: int) -> torch.Tensor:
-        ct = self.empty_ct()
+    def encrypt(self, pk, pt, seed: int, nonce: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        ct = self.empty_ct() if out is None else out
         _check(lib().lola_encrypt(self.h, _p(pk), _p(pt), seed, nonce, _p(ct), _stream()))
         return ct
+
+    def encrypt_batch(self, pk, pts: torch.Tensor, seed: int, nonce0: int,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """[n][N] plaintexts -> [n][2][L][N] ciphertexts, message i with
+        object id nonce0 + i."""
+        n = pts.shape[0]
+        ct = self.empty(n, 2, self.L, self.N) if out is None else out
+        _check(lib().lola_encrypt_batch(self.h, _p(pk), _p(pts), n, seed, nonce0, _p(ct), _stream()))
+        return ct
+
+    def decrypt_batch(self, sk, cts: torch.Tensor) -> torch.Tensor:
+        """[n][size][L][N] ciphertexts -> [n][N] plaintexts."""
+        n, size = cts.shape[0], cts.shape[1]
+        pt = self.empty(n, self.N)
+        _check(lib().lola_decrypt_batch(self.h, _p(sk), _p(cts), n, size, _p(pt), _stream()))
+        return pt
 
     def decrypt(self, sk, ct) -> torch.Tensor:
         pt = self.empty(self.N)

@@ -176,6 +176,51 @@ def test_decrypt_matches_oracle(env):
     assert np.array_equal(d3, bfv.decrypt(octx, env["okeys"], c3))
 
 
+def test_client_batches_match_oracle_and_single_calls(env):
+    """Batched encode / decode / encrypt / decrypt: every message equals the
+    single call word for word, across the scratch chunks (64 messages for the
+    codec, 16 for encryption), and sampled messages equal the oracle."""
+    import torch
+    from paper_1812_10659_amd import lola
+    ctx, octx, p = env["ctx"], env["octx"], env["p"]
+    rs = np.random.default_rng(7)
+    v = rs.integers(-3 * p.t, 3 * p.t, (70, p.N))
+    pts = ctx.encode_batch(v)
+    for i in (0, 63, 64, 69):
+        assert np.array_equal(_u32(pts[i]).astype(np.uint64), bfv.encode(octx, v[i])), i
+    for i in range(70):
+        assert torch.equal(pts[i], ctx.encode(v[i])), i
+    assert np.array_equal(ctx.decode_batch(pts).cpu().numpy(), np.mod(v, p.t))
+
+    n = 19
+    m = rs.integers(0, p.t, (n, p.N)).astype(np.uint64)
+    m[0] = env["m"][0]
+    mp = lola.from_numpy_u32(m.astype(np.uint32), ctx.device)
+    cts = ctx.encrypt_batch(env["pk"], mp, 11, 1)
+    got = _down(ctx, cts[0])
+    assert np.array_equal(got[0], env["c"][0][0]) and np.array_equal(got[1], env["c"][0][1])
+    ref = bfv.encrypt(octx, env["okeys"], m[17], 11, 18)
+    got = _down(ctx, cts[17])
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    for i in range(n):
+        assert torch.equal(cts[i], ctx.encrypt(env["pk"], mp[i], 11, 1 + i)), i
+    assert np.array_equal(_u32(ctx.decrypt_batch(env["sk"], cts)).astype(np.uint64), m)
+
+    # size-3 ciphertexts (products before relinearization)
+    c3 = torch.stack([ctx.mul(cts[i], cts[i + 1]) for i in range(3)])
+    d3 = ctx.decrypt_batch(env["sk"], c3)
+    for i in range(3):
+        assert torch.equal(d3[i], ctx.decrypt(env["sk"], c3[i])), i
+    prod = bfv.mul(octx, list(_down(ctx, cts[1])), list(_down(ctx, cts[2])))
+    assert np.array_equal(_u32(d3[1]).astype(np.uint64), bfv.decrypt(octx, env["okeys"], prod))
+    # empty batches are no-ops; object ids past 2^32 are refused
+    ctx.encode_batch(np.zeros((0, p.N), dtype=np.int64))
+    ctx.encrypt_batch(env["pk"], mp[:0], 11, 1)
+    with pytest.raises(lola.LolaError):
+        ctx.encrypt_batch(env["pk"], mp[:3], 11, (1 << 32) - 2)
+    torch.cuda.synchronize()
+
+
 def test_linear_ops_match_oracle(env):
     from paper_1812_10659_amd import lola
     ctx, octx, p = env["ctx"], env["octx"], env["p"]
