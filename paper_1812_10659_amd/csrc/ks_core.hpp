@@ -91,7 +91,8 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
     uint32_t v[NTT_E];
     ks_read_sigma<LOGN>(x + ((size_t)ii << LOGN), g, tid, sh, v);
     store_spectral<LOGN>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
-    ntt_inv_regs<LOGN>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);   // starts with a barrier
+    // padded LDS placement (measured faster here); starts with a barrier
+    ntt_inv_regs<LOGN, 0, true>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
     const GBuf D = gbuf(scratch + ((size_t)ii << LOGN), N);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN>(tid, r), v[r]);
@@ -140,7 +141,7 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
             for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
-            ntt_fwd_regs<LOGN, true, KSI>(x, tid, sh + (half << LOGN), tw + ((size_t)jj << LOGN), mc.q);
+            ntt_fwd_regs<LOGN, true, KSI>(x, tid, sh + half * ntt_lds_words<LOGN>(), tw + ((size_t)jj << LOGN), mc.q);
             half ^= 1u;
         }
         // The key offset passes through an opaque copy placed after the
@@ -247,7 +248,7 @@ __device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uin
     if (j < L) {
         store_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + j) << LOGN), N), tid, u);
     } else {
-        ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
+        ntt_inv_regs<LOGN, 0, true>(u, tid, sh, itw + ((size_t)j << LOGN), mc);   // padded LDS placement
         const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
@@ -278,7 +279,7 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
         const uint32_t v = gld(UP, natural_index<LOGN>(tid, r));
         x[r] = reduce32(v + (v > halfP ? negPq : 0u), mc.q, mc.one_shoup);
     }
-    ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
+    ntt_fwd_regs<LOGN, false, 0, true>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);   // padded LDS placement
     const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
     uint32_t u[NTT_E];
     load_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + jj) << LOGN), N), tid, u);

@@ -175,18 +175,49 @@ LOLA_HD void inv_pass_regs(uint32_t (&x)[NTT_E], uint32_t tid, const TwPair *__r
     }
 }
 
-template <int LOGN, int S0, int NS>
+// LDS placement of a transform's residues, chosen per call site (PAD):
+// either plain (g) or with NTT_LDS_PAD words of padding after every 64
+// (g -> g + 4 floor(g / 64)).  In the middle passes a wave's lanes touch
+// residues 64 or more apart for one register (e.g. stride 4 within groups of
+// 4 lanes); plain, these fall on a few banks, padded they spread over all of
+// them, at the price of the 256-byte strides that let pairs of accesses
+// share one instruction.  Which one is faster depends on the kernel around
+// the transform (measured), so both exist.  Padding by whole 16-byte groups
+// keeps the 4-aligned runs of the last pass aligned.  Every transform buffer
+// is sized for the padded placement: N + N/16 words.
+constexpr uint32_t NTT_LDS_PAD = 4;
+LOLA_HD constexpr uint32_t lds_pad(uint32_t g) { return g + NTT_LDS_PAD * (g >> 6); }
+template <int LOGN>
+constexpr uint32_t ntt_lds_words() { return lds_pad(1u << LOGN); }
+
+// A register's index is base(tid, v) + k STR with the sub-transform's span
+// STR * SUB a power of two and base mod span = u mod STR < STR, so adding
+// k STR never carries out of the low 6 bits of base past what k STR itself
+// carries: lds_pad(base + k STR) = lds_pad(base) + lds_pad(k STR), and the
+// per-register part is a compile-time offset.
+template <bool PAD>
+LOLA_HD constexpr uint32_t lds_place(uint32_t g) { return PAD ? lds_pad(g) : g; }
+
+template <int LOGN, int S0, int NS, bool PAD = false>
 LOLA_HD void regs_to_lds(const uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh) {
     using PS = NttPass<LOGN, S0, NS>;
 #pragma unroll
-    for (uint32_t r = 0; r < NTT_E; ++r) sh[PS::index(tid, r)] = x[r];
+    for (uint32_t v = 0; v < PS::PER; ++v) {
+        const uint32_t pb = lds_place<PAD>(PS::base(tid, v));
+#pragma unroll
+        for (uint32_t k = 0; k < PS::SUB; ++k) sh[pb + lds_place<PAD>(k * PS::STR)] = x[v * PS::SUB + k];
+    }
 }
 
-template <int LOGN, int S0, int NS>
+template <int LOGN, int S0, int NS, bool PAD = false>
 LOLA_HD void lds_to_regs(uint32_t (&x)[NTT_E], uint32_t tid, const uint32_t *sh) {
     using PS = NttPass<LOGN, S0, NS>;
 #pragma unroll
-    for (uint32_t r = 0; r < NTT_E; ++r) x[r] = sh[PS::index(tid, r)];
+    for (uint32_t v = 0; v < PS::PER; ++v) {
+        const uint32_t pb = lds_place<PAD>(PS::base(tid, v));
+#pragma unroll
+        for (uint32_t k = 0; k < PS::SUB; ++k) x[v * PS::SUB + k] = sh[pb + lds_place<PAD>(k * PS::STR)];
+    }
 }
 
 // Pass P of the forward transform under radix split SPLIT.
@@ -223,14 +254,14 @@ LOLA_HD void pass_exchange_sync() {
 }
 
 // Device-side driver.  x enters in the first pass's layout and leaves in the
-// last pass's layout (reduced to [0, q)).  sh: N words of LDS.  A barrier is
+// last pass's layout (reduced to [0, q)).  sh: ntt_lds_words<LOGN>() words of LDS.  A barrier is
 // taken before the first LDS write, so a previous use of sh by the same
 // workgroup is complete.
 // FRESH: no wave of the workgroup can still be reading sh from an earlier
 // use (e.g. the caller alternates two buffers and the transform before the
 // previous one ended behind a workgroup barrier), so the first exchange
 // needs no barrier before its writes.
-template <int LOGN, int P = 0, bool FRESH = false, int SPLIT = 0>
+template <int LOGN, int P = 0, bool FRESH = false, int SPLIT = 0, bool PAD = false>
 struct FwdDriver {
     LOLA_HD static void run(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
         constexpr int NPASS = NttShape<LOGN, SPLIT>::NPASS;
@@ -246,24 +277,24 @@ struct FwdDriver {
             } else {
                 pass_exchange_sync<LOGN, PA, PB>();
             }
-            regs_to_lds<LOGN, PA::S0, PA::NS>(x, tid, sh);
+            regs_to_lds<LOGN, PA::S0, PA::NS, PAD>(x, tid, sh);
             pass_exchange_sync<LOGN, PA, PB>();
-            lds_to_regs<LOGN, PB::S0, PB::NS>(x, tid, sh);
-            FwdDriver<LOGN, P + 1, FRESH, SPLIT>::run(x, tid, sh, tw, q);
+            lds_to_regs<LOGN, PB::S0, PB::NS, PAD>(x, tid, sh);
+            FwdDriver<LOGN, P + 1, FRESH, SPLIT, PAD>::run(x, tid, sh, tw, q);
         }
     }
 };
 
-template <int LOGN, bool FRESH = false, int SPLIT = 0>
+template <int LOGN, bool FRESH = false, int SPLIT = 0, bool PAD = false>
 LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
-    FwdDriver<LOGN, 0, FRESH, SPLIT>::run(x, tid, sh, tw, q);
+    FwdDriver<LOGN, 0, FRESH, SPLIT, PAD>::run(x, tid, sh, tw, q);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(csub(x[r], 2 * q), q);
 }
 
 // Inverse: x enters in the last forward pass's layout (values in [0, 2q))
 // and leaves in the first pass's layout, reduced to [0, q).
-template <int LOGN, int P, int SPLIT = 0>
+template <int LOGN, int P, int SPLIT = 0, bool PAD = false>
 struct InvDriver {
     LOLA_HD static void run(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *itw,
                             const ModConst &mc) {
@@ -273,18 +304,18 @@ struct InvDriver {
             using PB = FwdPassAt<LOGN, P - 1, SPLIT>;
             if constexpr (P == NttShape<LOGN, SPLIT>::NPASS - 1) LOLA_BARRIER();
             else pass_exchange_sync<LOGN, PA, PB>();
-            regs_to_lds<LOGN, PA::S0, PA::NS>(x, tid, sh);
+            regs_to_lds<LOGN, PA::S0, PA::NS, PAD>(x, tid, sh);
             pass_exchange_sync<LOGN, PA, PB>();
-            lds_to_regs<LOGN, PB::S0, PB::NS>(x, tid, sh);
-            InvDriver<LOGN, P - 1, SPLIT>::run(x, tid, sh, itw, mc);
+            lds_to_regs<LOGN, PB::S0, PB::NS, PAD>(x, tid, sh);
+            InvDriver<LOGN, P - 1, SPLIT, PAD>::run(x, tid, sh, itw, mc);
         }
     }
 };
 
-template <int LOGN, int SPLIT = 0>
+template <int LOGN, int SPLIT = 0, bool PAD = false>
 LOLA_HD void ntt_inv_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *itw,
                           const ModConst &mc) {
-    InvDriver<LOGN, NttShape<LOGN, SPLIT>::NPASS - 1, SPLIT>::run(x, tid, sh, itw, mc);
+    InvDriver<LOGN, NttShape<LOGN, SPLIT>::NPASS - 1, SPLIT, PAD>::run(x, tid, sh, itw, mc);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(x[r], mc.q);
 }

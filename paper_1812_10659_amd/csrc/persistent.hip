@@ -57,7 +57,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void chain_persistent_kernel(
     uint32_t *__restrict__ counter, uint32_t *__restrict__ scratch, size_t scratch_per_wg, uint32_t L,
     const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw, const TwPair *__restrict__ itw,
     const MrcConst *__restrict__ mrc) {
-    __shared__ uint32_t sh[2 << LOGN];
+    __shared__ uint32_t sh[2 * ntt_lds_words<LOGN>()];
     __shared__ uint32_t item;
     uint32_t *scr = scratch + scratch_per_wg * blockIdx.x;
     for (;;) {

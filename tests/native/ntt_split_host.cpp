@@ -38,7 +38,7 @@ static uint32_t brv(uint32_t x, int bits) {
 using Regs = std::vector<std::array<uint32_t, NTT_E>>;
 static uint32_t (&regs(Regs &X, int t))[NTT_E] { return *reinterpret_cast<uint32_t(*)[NTT_E]>(X[t].data()); }
 
-template <int LOGN, int SPLIT, int P>
+template <int LOGN, int SPLIT, int P, bool PAD>
 struct EmuFwd {
     static void run(Regs &X, uint32_t *sh, const TwPair *tw, uint32_t q) {
         constexpr int T = NttShape<LOGN, SPLIT>::T;
@@ -46,13 +46,13 @@ struct EmuFwd {
         for (int t = 0; t < T; t++) fwd_pass_regs<LOGN, PA::S0, PA::NS>(regs(X, t), t, tw, q);
         if constexpr (P + 1 < NttShape<LOGN, SPLIT>::NPASS) {
             using PB = FwdPassAt<LOGN, P + 1, SPLIT>;
-            for (int t = 0; t < T; t++) regs_to_lds<LOGN, PA::S0, PA::NS>(regs(X, t), t, sh);
-            for (int t = 0; t < T; t++) lds_to_regs<LOGN, PB::S0, PB::NS>(regs(X, t), t, sh);
-            EmuFwd<LOGN, SPLIT, P + 1>::run(X, sh, tw, q);
+            for (int t = 0; t < T; t++) regs_to_lds<LOGN, PA::S0, PA::NS, PAD>(regs(X, t), t, sh);
+            for (int t = 0; t < T; t++) lds_to_regs<LOGN, PB::S0, PB::NS, PAD>(regs(X, t), t, sh);
+            EmuFwd<LOGN, SPLIT, P + 1, PAD>::run(X, sh, tw, q);
         }
     }
 };
-template <int LOGN, int SPLIT, int P>
+template <int LOGN, int SPLIT, int P, bool PAD>
 struct EmuInv {
     static void run(Regs &X, uint32_t *sh, const TwPair *itw, const ModConst &mc) {
         constexpr int T = NttShape<LOGN, SPLIT>::T;
@@ -60,9 +60,9 @@ struct EmuInv {
         for (int t = 0; t < T; t++) inv_pass_regs<LOGN, PA::S0, PA::NS, (P == 0)>(regs(X, t), t, itw, mc);
         if constexpr (P > 0) {
             using PB = FwdPassAt<LOGN, P - 1, SPLIT>;
-            for (int t = 0; t < T; t++) regs_to_lds<LOGN, PA::S0, PA::NS>(regs(X, t), t, sh);
-            for (int t = 0; t < T; t++) lds_to_regs<LOGN, PB::S0, PB::NS>(regs(X, t), t, sh);
-            EmuInv<LOGN, SPLIT, P - 1>::run(X, sh, itw, mc);
+            for (int t = 0; t < T; t++) regs_to_lds<LOGN, PA::S0, PA::NS, PAD>(regs(X, t), t, sh);
+            for (int t = 0; t < T; t++) lds_to_regs<LOGN, PB::S0, PB::NS, PAD>(regs(X, t), t, sh);
+            EmuInv<LOGN, SPLIT, P - 1, PAD>::run(X, sh, itw, mc);
         }
     }
 };
@@ -90,6 +90,75 @@ int wave_local_exchanges() {
         }
         return bad + wave_local_exchanges<LOGN, SPLIT, P + 1>();
     }
+}
+
+// The padded LDS placement: the split that regs_to_lds / lds_to_regs use
+// (lds_pad(base) + lds_pad(k STR)) equals lds_pad of the register's index,
+// stays inside ntt_lds_words, and is one to one.  worst[P]: the most lanes of
+// one wave on one of 32 four-byte banks for one register access of pass P.
+template <int LOGN, int SPLIT, int P>
+int padded_placement(int (&worst)[8]) {
+    if constexpr (P >= NttShape<LOGN, SPLIT>::NPASS) {
+        return 0;
+    } else {
+        using PA = FwdPassAt<LOGN, P, SPLIT>;
+        using A = NttPass<LOGN, PA::S0, PA::NS>;
+        constexpr int N = 1 << LOGN, T = N / NTT_E;
+        constexpr uint32_t W = ntt_lds_words<LOGN>();
+        int bad = 0;
+        std::vector<int> hit(W, 0);
+        std::vector<uint32_t> addr((size_t)T * NTT_E);
+        for (int t = 0; t < T; t++)
+            for (uint32_t v = 0; v < A::PER; v++)
+                for (uint32_t k = 0; k < A::SUB; k++) {
+                    const uint32_t r = v * A::SUB + k;
+                    const uint32_t a = lds_pad(A::base(t, v)) + lds_pad(k * A::STR);
+                    bad += a != lds_pad(A::index(t, r)) || a >= W;
+                    if (a < W) hit[a]++;
+                    addr[(size_t)t * NTT_E + r] = a;
+                }
+        for (uint32_t a = 0; a < W; a++) bad += hit[a] > 1;
+        int deg = 0;
+        for (int w0 = 0; w0 < T; w0 += WAVE)
+            for (int r = 0; r < NTT_E; r++) {
+                int cnt[32] = {};
+                for (int l = 0; l < WAVE && w0 + l < T; l++) {
+                    const int c = ++cnt[addr[(size_t)(w0 + l) * NTT_E + r] % 32];
+                    deg = c > deg ? c : deg;
+                }
+            }
+        worst[P] = deg;
+        return bad + padded_placement<LOGN, SPLIT, P + 1>(worst);
+    }
+}
+
+// Forward transform of a (against ref at every index, each index written
+// once), then the inverse back to a, with the plain (PAD = false) or the
+// padded LDS placement.
+template <int LOGN, int SPLIT, bool PAD>
+int round_trip(const std::vector<uint32_t> &a, const std::vector<uint64_t> &ref, const std::vector<TwPair> &tw,
+               const std::vector<TwPair> &itw, const ModConst &mc, uint32_t q) {
+    constexpr int N = 1 << LOGN, T = NttShape<LOGN, SPLIT>::T;
+    int bad = 0;
+    Regs X(T);
+    std::vector<uint32_t> sh(ntt_lds_words<LOGN>());
+    for (int t = 0; t < T; t++)
+        for (int k = 0; k < NTT_E; k++) X[t][k] = a[natural_index<LOGN, SPLIT>(t, k)];
+    EmuFwd<LOGN, SPLIT, 0, PAD>::run(X, sh.data(), tw.data(), q);
+    std::vector<int> seen(N, 0);
+    for (int t = 0; t < T; t++)
+        for (int k = 0; k < NTT_E; k++) {
+            const uint32_t i = spectral_index<LOGN, SPLIT>(t, k);
+            const uint32_t v = csub(csub(X[t][k], 2 * q), q);
+            seen[i]++;
+            bad += v != ref[i];
+            X[t][k] = v;
+        }
+    for (int i = 0; i < N; i++) bad += seen[i] != 1;
+    EmuInv<LOGN, SPLIT, NttShape<LOGN, SPLIT>::NPASS - 1, PAD>::run(X, sh.data(), itw.data(), mc);
+    for (int t = 0; t < T; t++)
+        for (int k = 0; k < NTT_E; k++) bad += csub(X[t][k], q) != a[natural_index<LOGN, SPLIT>(t, k)];
+    return bad;
 }
 
 template <int LOGN, int SPLIT>
@@ -137,24 +206,7 @@ int check(uint32_t q) {
         for (int j = N - 1; j >= 0; j--) acc = ((u128)acc * x + a[j]) % q;
         bad += acc != ref[k];
     }
-    Regs X(T);
-    std::vector<uint32_t> sh(N);
-    for (int t = 0; t < T; t++)
-        for (int k = 0; k < NTT_E; k++) X[t][k] = a[natural_index<LOGN, SPLIT>(t, k)];
-    EmuFwd<LOGN, SPLIT, 0>::run(X, sh.data(), tw.data(), q);
-    std::vector<int> seen(N, 0);
-    for (int t = 0; t < T; t++)
-        for (int k = 0; k < NTT_E; k++) {
-            const uint32_t i = spectral_index<LOGN, SPLIT>(t, k);
-            const uint32_t v = csub(csub(X[t][k], 2 * q), q);
-            seen[i]++;
-            bad += v != ref[i];
-            X[t][k] = v;
-        }
-    for (int i = 0; i < N; i++) bad += seen[i] != 1;
-    EmuInv<LOGN, SPLIT, NttShape<LOGN, SPLIT>::NPASS - 1>::run(X, sh.data(), itw.data(), mc);
-    for (int t = 0; t < T; t++)
-        for (int k = 0; k < NTT_E; k++) bad += csub(X[t][k], q) != a[natural_index<LOGN, SPLIT>(t, k)];
+    bad += round_trip<LOGN, SPLIT, false>(a, ref, tw, itw, mc, q) + round_trip<LOGN, SPLIT, true>(a, ref, tw, itw, mc, q);
     bad += wave_local_exchanges<LOGN, SPLIT, 0>();
     if (spectral_vec4<LOGN, SPLIT>()) {   // 16-byte accesses: registers 4r..4r+3 are 4 aligned neighbours
         for (int t = 0; t < T; t++)
@@ -163,8 +215,15 @@ int check(uint32_t q) {
                     bad += spectral_index<LOGN, SPLIT>(t, r + k) != spectral_index<LOGN, SPLIT>(t, r) + k ||
                            spectral_index<LOGN, SPLIT>(t, r) % 4 != 0;
     }
-    std::printf("N=%d split=%d (passes %d) q=%u: %s\n", N, SPLIT, NttShape<LOGN, SPLIT>::NPASS, q,
-                bad ? "FAIL" : "ok");
+    int worst[8] = {};
+    bad += padded_placement<LOGN, SPLIT, 0>(worst);
+    // at N = 16384 the exchanges of every pass but the last (which moves
+    // 16-byte groups) take the minimum of two lanes per bank
+    if (LOGN == 14 && (SPLIT == 0 || SPLIT == 4433))
+        for (int p = 0; p + 1 < NttShape<LOGN, SPLIT>::NPASS; p++) bad += worst[p] > 2;
+    std::printf("N=%d split=%d (passes %d) q=%u lanes per bank", N, SPLIT, NttShape<LOGN, SPLIT>::NPASS, q);
+    for (int p = 0; p < NttShape<LOGN, SPLIT>::NPASS; p++) std::printf(" %d", worst[p]);
+    std::printf(": %s\n", bad ? "FAIL" : "ok");
     return bad != 0;
 }
 

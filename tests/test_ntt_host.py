@@ -2,8 +2,10 @@
 layouts) under every radix split the batched kernel is compiled with, run on
 the host thread by thread with the host compiler: the forward transform equals
 a textbook negacyclic NTT at every index (evaluation at odd powers of psi),
-every index is written once, the inverse returns the input, and exchanges that
-skip the workgroup barrier stay inside one wave."""
+every index is written once, the inverse returns the input, exchanges that
+skip the workgroup barrier stay inside one wave, and the padded LDS placement is
+one to one, in bounds and (at N = 16384) spreads each register access of the
+strided passes over the banks."""
 import os
 import shutil
 import subprocess
