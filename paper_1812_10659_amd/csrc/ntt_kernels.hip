@@ -20,7 +20,7 @@ template <int LOGN, int SPLIT, int LPW>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E, 8) void ntt_jobs_kernel(
     const NttJob *__restrict__ jobs, uint32_t n, const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw,
     const TwPair *__restrict__ itw, uint32_t t, const MrcConst *__restrict__ mrc) {
-    __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];   // plain placement
     constexpr uint32_t N = 1u << LOGN;
     for (uint32_t k = 0; k < (uint32_t)LPW; ++k) {
         // the same for every thread of the workgroup: the exit is uniform;

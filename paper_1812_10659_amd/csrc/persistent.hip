@@ -36,7 +36,9 @@ __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key
                           uint32_t *scr, uint32_t *sh, const ModConst *mcs, const TwPair *tw,
                           const TwPair *itw, const MrcConst *mrc) {
     const uint32_t *c1 = in + ((size_t)L << LOGN);
-    for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN>(c1, g, scr, i, L, sh, mcs[i], itw);
+    // plain LDS placement throughout, in two halves of N words (the padded
+    // placement's larger buffer measured slower inside this kernel)
+    for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN, false>(c1, g, scr, i, L, sh, mcs[i], itw);
     __syncthreads();
     for (uint32_t j = 0; j <= L; ++j) {
         // the default radix split here: the 4433 split that suits the
@@ -47,7 +49,7 @@ __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key
     const uint32_t P = mcs[L].q;
     for (uint32_t c = 0; c < 2; ++c)
         for (uint32_t j = 0; j < L; ++j)
-            ks_stage_moddown<LOGN>(scr, j, c, L, c == 0 ? in : nullptr, g, nullptr, out, sh, mcs[j], tw, mrc, P);
+            ks_stage_moddown<LOGN, false>(scr, j, c, L, c == 0 ? in : nullptr, g, nullptr, out, sh, mcs[j], tw, mrc, P);
     __syncthreads();   // out is the next rotation's input
 }
 
@@ -57,7 +59,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void chain_persistent_kernel(
     uint32_t *__restrict__ counter, uint32_t *__restrict__ scratch, size_t scratch_per_wg, uint32_t L,
     const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw, const TwPair *__restrict__ itw,
     const MrcConst *__restrict__ mrc) {
-    __shared__ uint32_t sh[2 * ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[2 << LOGN];   // two halves of N words: plain placement only
     __shared__ uint32_t item;
     uint32_t *scr = scratch + scratch_per_wg * blockIdx.x;
     for (;;) {

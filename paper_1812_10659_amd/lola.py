@@ -368,10 +368,12 @@ class Context:
         return k.value, [(v.split, v.limbs_per_wg, float(v.ms)) for v in arr]
 
     def ntt_limbs(self, x: torch.Tensor, prime_idx: Iterable[int], inverse: bool = False) -> torch.Tensor:
-        idx = list(prime_idx)
-        arr = (ctypes.c_uint32 * len(idx))(*idx)
+        """prime_idx: one prime index per limb; a uint32 numpy array passes
+        through without conversion (a list is converted on every call)."""
+        idx = np.ascontiguousarray(np.asarray(prime_idx, dtype=np.uint32))
         out = torch.empty_like(x)
-        _check(lib().lola_ntt_limbs(self.h, _p(x), _p(out), len(idx), arr, int(inverse), _stream()))
+        _check(lib().lola_ntt_limbs(self.h, _p(x), _p(out), idx.size,
+                                    idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(inverse), _stream()))
         return out
 
 
