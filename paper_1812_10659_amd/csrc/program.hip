@@ -4,23 +4,40 @@
 namespace lola {
 
 // dst = sum_k w_k src_k (+ add on component 0).  grid (2LN/4/256, jobs)
+//
+// A block's 1024 words lie in one limb (N >= 1024), so the limb and the
+// weights are uniform and come from scalar loads.  Sources are taken in
+// groups of LIN_GROUP with all their loads issued before any product: a
+// group past the last source repeats the last source's address with weight
+// 0 (a zero term), which keeps the group one straight block instead of a
+// test and a wait per source.
+constexpr uint32_t LIN_GROUP = 8;
+
 __global__ void lin_kernel(const LinJob *__restrict__ jobs, uint32_t logN, uint32_t L,
                            const ModConst *__restrict__ mcs) {
     const LinJob &job = jobs[blockIdx.y];
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n4 = ((size_t)2 * L << logN) / 4;
     if (i >= n4) return;
-    const uint32_t cl = (uint32_t)((i * 4) >> logN);   // component * L + limb
+    const uint32_t cl = (uint32_t)(((size_t)blockIdx.x * blockDim.x * 4) >> logN);   // component * L + limb
     const uint32_t limb = cl % L;
     const uint32_t q = mcs[limb].q;
+    const uint32_t n = job.n_src;
     uint4 acc = make_uint4(0, 0, 0, 0);
-    for (uint32_t k = 0; k < job.n_src; ++k) {
-        const uint4 x = ((const uint4 *)jobs[blockIdx.y].srcs[k])[i];
-        const uint32_t w = job.w[(2 * k) * L + limb], wp = job.w[(2 * k + 1) * L + limb];
-        acc.x = add_mod(acc.x, shoup(x.x, w, wp, q), q);
-        acc.y = add_mod(acc.y, shoup(x.y, w, wp, q), q);
-        acc.z = add_mod(acc.z, shoup(x.z, w, wp, q), q);
-        acc.w = add_mod(acc.w, shoup(x.w, w, wp, q), q);
+    for (uint32_t k0 = 0; k0 < n; k0 += LIN_GROUP) {
+        uint4 x[LIN_GROUP];
+#pragma unroll
+        for (uint32_t b = 0; b < LIN_GROUP; ++b) x[b] = ((const uint4 *)job.srcs[min(k0 + b, n - 1)])[i];
+#pragma unroll
+        for (uint32_t b = 0; b < LIN_GROUP; ++b) {
+            // weights of the clamped source, masked to 0 past the last one
+            const uint32_t k = min(k0 + b, n - 1), mask = 0u - (uint32_t)(k0 + b < n);
+            const uint32_t w = job.w[(2 * k) * L + limb] & mask, wp = job.w[(2 * k + 1) * L + limb] & mask;
+            acc.x = add_mod(acc.x, shoup(x[b].x, w, wp, q), q);
+            acc.y = add_mod(acc.y, shoup(x[b].y, w, wp, q), q);
+            acc.z = add_mod(acc.z, shoup(x[b].z, w, wp, q), q);
+            acc.w = add_mod(acc.w, shoup(x[b].w, w, wp, q), q);
+        }
     }
     if (job.add && cl < L) {
         const uint4 y = ((const uint4 *)job.add)[i];
