@@ -43,8 +43,12 @@ __global__ void tensor_extend_kernel(const MulJob *__restrict__ jobs, uint32_t N
     uint32_t *dst = job.scr + offBx;
     const int L = (int)mrc->L, nB = (int)mrc->nB;
     uint32_t r[MAXL], v[MAXL];
+    // every load issued unconditionally (limbs past L read limb L-1 again and
+    // are zeroed after): a test per limb would wait for each load in turn
 #pragma unroll
-    for (int i = 0; i < MAXL; ++i) r[i] = i < L ? src[((size_t)p * L + i) * N + k] : 0;
+    for (int i = 0; i < MAXL; ++i) r[i] = src[((size_t)p * L + min(i, L - 1)) * N + k];
+#pragma unroll
+    for (int i = 0; i < MAXL; ++i) r[i] = i < L ? r[i] : 0;
     mrc_digits<MAXL>(r, v, L, mcs, mrc->invQ, mrc->invQp);
     const bool neg = mrc_greater<MAXL>(v, L, mrc->hQ);
     const ModConst *mb = mcs + L + 1;
@@ -106,10 +110,15 @@ __global__ void tensor_round_kernel(const MulJob *__restrict__ jobs, uint32_t N,
     const uint32_t *dq = job.scr + offDq, *db = job.scr + offDb;
     uint32_t *out = job.scr + offOc;
     const int L = (int)mrc->L, nB = (int)mrc->nB;
-    uint32_t r[MAXL], v[MAXL];
+    uint32_t r[MAXL], v[MAXL], tdb[MAXB];
+    // all loads first, unconditionally (limbs past L or nB read the last one
+    // again and are ignored): a test per limb would wait for each load in turn
 #pragma unroll
-    for (int i = 0; i < MAXL; ++i)
-        r[i] = i < L ? shoup(dq[((size_t)p * L + i) * N + k], mrc->tq[i], mrc->tqp[i], mcs[i].q) : 0;
+    for (int i = 0; i < MAXL; ++i) r[i] = dq[((size_t)p * L + min(i, L - 1)) * N + k];
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) tdb[j] = db[((size_t)p * nB + min(j, nB - 1)) * N + k];
+#pragma unroll
+    for (int i = 0; i < MAXL; ++i) r[i] = i < L ? shoup(r[i], mrc->tq[i], mrc->tqp[i], mcs[i].q) : 0;
     mrc_digits<MAXL>(r, v, L, mcs, mrc->invQ, mrc->invQp);   // digits of R = t d mod Q
     const uint32_t carry = mrc_greater<MAXL>(v, L, mrc->hQ) ? 1u : 0u;
     const ModConst *mb = mcs + L + 1;
@@ -119,7 +128,7 @@ __global__ void tensor_round_kernel(const MulJob *__restrict__ jobs, uint32_t N,
         if (j < nB) {
             const uint32_t bq = mb[j].q;
             const uint32_t Rb = mrc_eval<MAXL>(v, L, mrc->wQb[j], mrc->wQbp[j], bq);
-            const uint32_t td = shoup(db[((size_t)p * nB + j) * N + k], mrc->tb[j], mrc->tbp[j], bq);
+            const uint32_t td = shoup(tdb[j], mrc->tb[j], mrc->tbp[j], bq);
             uint32_t y = shoup(sub_mod(td, Rb, bq), mrc->Qinvb[j], mrc->Qinvbp[j], bq);
             z[j] = add_mod(y, carry, bq);
         } else {
