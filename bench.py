@@ -759,7 +759,48 @@ def cpu_baseline(p, w, recipe):
     return {"value": round(1.0 / dt, 5), "unit": "inferences/s", "cores": bfv.max_threads(), "kind": "oracle",
             "sample": f"1 full inference, the timed plan's schedule ({sched.count('rotate')} rotations, "
                       f"{sched.count('square')} squares), {dt:.1f} s",
-            "cpu": _cpu_model()}
+            "cpu": _cpu_model(), "batched_primitives_per_op": oracle_batch_ops()}
+
+
+def oracle_batch_ops():
+    """The oracle's per-operation times at the batched-primitive shape
+    (N=16384, L=8), on all host threads and on one, and the batch's time
+    extrapolated from them (512 mul_plain, 256 mul + relin and the batch's
+    uneven rotation chains; not measured as a whole)."""
+    import numpy as np
+
+    from oracle import bfv
+    from paper_1812_10659_amd import workloads as wl
+    p = wl.PARAMS["batch_n16384"]
+    octx = bfv.Context(p)
+    keys = bfv.keygen(octx, wl.key_seed(2), [bfv.galois_element(p.N, 1)])
+    rs = wl.rng(wl.workload_seed(2), 21)
+    m1, m2 = (rs.integers(0, p.t, p.N).astype(np.uint64) for _ in range(2))
+    c1, c2 = bfv.encrypt(octx, keys, m1, 1, 1), bfv.encrypt(octx, keys, m2, 1, 2)
+    all_threads = bfv.max_threads()
+
+    def timed(f, *a):
+        t0 = time.perf_counter()
+        r = f(*a)
+        return time.perf_counter() - t0, r
+
+    per = {}
+    for th in sorted({all_threads, 1}, reverse=True):
+        bfv.set_threads(th)
+        t_mp, _ = timed(bfv.mul_plain, octx, c1, m2)
+        t_mul, c3 = timed(bfv.mul, octx, c1, c2)
+        t_rl, _ = timed(bfv.relin, octx, c3, keys.rlk)
+        t_rot, _ = timed(bfv.rotate, octx, c1, 1, keys)
+        per[f"threads_{th}"] = {"mul_plain_s": round(t_mp, 4), "mul_s": round(t_mul, 4), "relin_s": round(t_rl, 4),
+                                "rotate_s": round(t_rot, 4)}
+    bfv.set_threads(all_threads)
+    a = per[f"threads_{all_threads}"]
+    rot = int(wl.batch_rotation_counts(512).sum())
+    est = 512 * a["mul_plain_s"] + 256 * (a["mul_s"] + a["relin_s"]) + rot * a["rotate_s"]
+    return {"config": "N=16384, L=8 (the batched-primitive shape)", **per,
+            "extrapolated_batch_s": round(est, 1),
+            "extrapolated_note": f"512 mul_plain + 256 (mul + relin) + {rot} rotations at the all-thread per-op "
+                                 f"times; extrapolated, not measured"}
 
 
 def _cpu_model():

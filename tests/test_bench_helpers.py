@@ -51,3 +51,16 @@ def test_reported_work_and_bytes_per_key_switch():
     # ciphertext in, key once, result out
     assert bench.ks_bytes(N, L) == 4 * N * (2 * L + 2 * L * (L + 1) + 2 * L) == 9175040
     assert np.isclose(bench.PEAK_VALU_LANE_OPS, 39.3216e12)
+
+
+def test_oracle_per_op_times_and_their_extrapolation():
+    r = bench.oracle_batch_ops()
+    keys = [k for k in r if k.startswith("threads_")]
+    from oracle import bfv
+    assert "threads_1" in keys and len(keys) == len({bfv.max_threads(), 1})
+    for k in keys:
+        assert set(r[k]) == {"mul_plain_s", "mul_s", "relin_s", "rotate_s"} and all(v > 0 for v in r[k].values())
+    a = r[max(keys, key=lambda k: int(k.split("_")[1]))]
+    rot = int(wl.batch_rotation_counts(512).sum())
+    est = 512 * a["mul_plain_s"] + 256 * (a["mul_s"] + a["relin_s"]) + rot * a["rotate_s"]
+    assert abs(r["extrapolated_batch_s"] - round(est, 1)) < 0.11 and "extrapolated" in r["extrapolated_note"]
