@@ -1,7 +1,12 @@
 """bench.py's own references, on the CPU: the plain networks its spot checks
 compare decrypted results with must equal the oracle's plaintext networks, and
 the algorithmic work and bytes of one key switch it reports are the stated
-formulas."""
+formulas; it refuses more than one GPU.  The oracle's per-operation timing
+helper reports both thread settings and its labelled extrapolation."""
+import os
+import subprocess
+import sys
+
 import numpy as np
 
 import bench
@@ -64,3 +69,10 @@ def test_oracle_per_op_times_and_their_extrapolation():
     rot = int(wl.batch_rotation_counts(512).sum())
     est = 512 * a["mul_plain_s"] + 256 * (a["mul_s"] + a["relin_s"]) + rot * a["rotate_s"]
     assert abs(r["extrapolated_batch_s"] - round(est, 1)) < 0.11 and "extrapolated" in r["extrapolated_note"]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
