@@ -259,7 +259,10 @@ int lola_export_ksk(lola_ctx *ctx, const uint32_t *ksk_dev, uint32_t *out_dev, l
 /* Diagnostic: forward or inverse NTT of n limbs, limb k modulo prime index
  * prime_idx_host[k] (0..L-1 ciphertext primes, L = P, L+1+n_aux = t), natural
  * coefficient order <-> bit-reversed evaluation order:
- * out[k] = a(psi^(2 brv(k) + 1)) with psi the smallest primitive 2N-th root. */
+ * out[k] = a(psi^(2 brv(k) + 1)) with psi the smallest primitive 2N-th root.
+ * When prime_idx_host[k] = k mod L for every k (the limbs of consecutive
+ * polynomials) the launch carries no per-limb descriptors; any other list
+ * is uploaded as descriptors first.  The results are the same. */
 int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uint32_t n_limbs,
                    const uint32_t *prime_idx_host, int inverse, lola_stream stream);
 

@@ -150,6 +150,10 @@ enum : uint32_t {
 };
 int launch_ntt_jobs(lola_ctx *ctx, const NttJob *host_jobs, int n, hipStream_t s);
 int launch_ntt_jobs_dev(lola_ctx *ctx, const NttJob *d_jobs, int n, hipStream_t s);
+// n contiguous limbs, limb k under prime k mod cycle, one flag set: launched
+// without descriptors.
+int launch_ntt_strided(lola_ctx *ctx, const uint32_t *in, uint32_t *out, uint32_t n, uint32_t cycle,
+                       uint32_t flags, hipStream_t s);
 
 // One key switch: out = (add0' + KS(x)_0, add1 + KS(x)_1) (+ addct), where
 // add0' is add0 under the automorphism when galois > 1.

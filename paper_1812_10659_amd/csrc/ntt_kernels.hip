@@ -14,12 +14,22 @@
 
 namespace lola {
 
+// Jobs without descriptors: job k transforms limb k of the contiguous array
+// `in` into limb k of `out`, under prime k mod `cycle` (the limbs of
+// consecutive [..][L][N] polynomials), all with the same flags.
+struct NttStrided {
+    const uint32_t *in;
+    uint32_t *out;
+    uint32_t cycle, flags;
+};
+
 // Launch bound: at least 8 waves per SIMD, i.e. at most 64 VGPRs, so two
 // 1024-thread workgroups (64 KiB of LDS each) fit one CU at N = 16384.
+// jobs: device descriptors, or null for the strided jobs of `sd`.
 template <int LOGN, int SPLIT, int LPW>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E, 8) void ntt_jobs_kernel(
     const NttJob *__restrict__ jobs, uint32_t n, const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw,
-    const TwPair *__restrict__ itw, uint32_t t, const MrcConst *__restrict__ mrc) {
+    const TwPair *__restrict__ itw, uint32_t t, const MrcConst *__restrict__ mrc, NttStrided sd) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];   // plain placement
     constexpr uint32_t N = 1u << LOGN;
     for (uint32_t k = 0; k < (uint32_t)LPW; ++k) {
@@ -28,7 +38,9 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E, 8) void ntt_jobs_kernel(
         // LDS write, so consecutive jobs can share sh
         const uint32_t jb = blockIdx.x * LPW + k;
         if (jb >= n) return;
-        const NttJob job = jobs[jb];
+        const NttJob job = jobs ? jobs[jb]
+                                : NttJob{sd.in + ((size_t)jb << LOGN), sd.out + ((size_t)jb << LOGN), jb % sd.cycle,
+                                         sd.flags};
         const ModConst mc = mcs[job.prime];
         const uint32_t tid = threadIdx.x;
         const size_t toff = (size_t)job.prime << LOGN;
@@ -89,7 +101,7 @@ constexpr uint32_t split_code(int logn, int split) {
 }
 
 using NttKernelFn = void (*)(const NttJob *, uint32_t, const ModConst *, const TwPair *, const TwPair *, uint32_t,
-                             const MrcConst *);
+                             const MrcConst *, NttStrided);
 struct NttVariant {
     uint32_t split, lpw;
     NttKernelFn fn;
@@ -131,7 +143,7 @@ static bool ntt_variant_list(uint32_t logN, const NttVariant **v, uint32_t *coun
 #undef LOLA_NTT_LIST
 }
 
-int launch_ntt_jobs_dev(lola_ctx *ctx, const NttJob *d_jobs, int n, hipStream_t s) {
+static int launch_ntt_any(lola_ctx *ctx, const NttJob *d_jobs, NttStrided sd, int n, hipStream_t s) {
     if (n <= 0) return LOLA_OK;
     const NttVariant *vs = nullptr;
     uint32_t count = 0;
@@ -142,9 +154,22 @@ int launch_ntt_jobs_dev(lola_ctx *ctx, const NttJob *d_jobs, int n, hipStream_t 
     const TwPair *tw = ctx->d_tw, *itw = ctx->d_itw;
     uint32_t t = ctx->t;
     const MrcConst *mrc = ctx->d_mrc;
-    void *args[] = {(void *)&d_jobs, (void *)&nj, (void *)&mc, (void *)&tw, (void *)&itw, (void *)&t, (void *)&mrc};
+    void *args[] = {(void *)&d_jobs, (void *)&nj, (void *)&mc, (void *)&tw, (void *)&itw, (void *)&t, (void *)&mrc,
+                    (void *)&sd};
     LOLA_HIP(hipLaunchKernel((const void *)v.fn, dim3((nj + v.lpw - 1) / v.lpw), dim3(ctx->N / NTT_E), args, 0, s));
     return LOLA_OK;
+}
+
+int launch_ntt_jobs_dev(lola_ctx *ctx, const NttJob *d_jobs, int n, hipStream_t s) {
+    return launch_ntt_any(ctx, d_jobs, NttStrided{}, n, s);
+}
+
+// n limbs of `in` to n limbs of `out`, limb k under prime k mod cycle: no
+// descriptors to upload.
+int launch_ntt_strided(lola_ctx *ctx, const uint32_t *in, uint32_t *out, uint32_t n, uint32_t cycle,
+                       uint32_t flags, hipStream_t s) {
+    if (cycle == 0 || cycle > ctx->nprimes()) return set_error(LOLA_E_INVAL, "prime cycle out of range");
+    return launch_ntt_any(ctx, nullptr, NttStrided{in, out, cycle, flags}, (int)n, s);
 }
 
 // Residues for tuning: limb k holds pseudo-random values below its prime.
@@ -294,6 +319,12 @@ int lola_ntt_autotune(lola_ctx *ctx, uint32_t n_limbs, uint32_t reps, lola_ntt_v
 int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uint32_t n_limbs,
                    const uint32_t *prime_idx_host, int inverse, lola_stream stream) {
     if (!ctx || !in_dev || !out_dev || !prime_idx_host) return set_error(LOLA_E_INVAL, "null argument");
+    // limb k under prime k mod L (consecutive polynomials of L limbs): no
+    // descriptors at all
+    bool cyclic = true;
+    for (uint32_t k = 0; k < n_limbs && cyclic; ++k) cyclic = prime_idx_host[k] == k % ctx->L;
+    if (cyclic) return launch_ntt_strided(ctx, in_dev, out_dev, n_limbs, ctx->L, inverse ? NTT_INVERSE : 0u,
+                                          (hipStream_t)stream);
     std::vector<NttJob> jobs(n_limbs);
     for (uint32_t k = 0; k < n_limbs; ++k) {
         if (prime_idx_host[k] >= ctx->nprimes()) return set_error(LOLA_E_INVAL, "prime index out of range");
@@ -306,25 +337,13 @@ int lola_ntt_limbs(lola_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, uin
 int lola_to_coeff(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n_polys, uint32_t *out_dev,
                   lola_stream stream) {
     if (!ctx || !in_dev || !out_dev) return set_error(LOLA_E_INVAL, "null argument");
-    std::vector<NttJob> jobs;
-    for (uint32_t p = 0; p < n_polys; ++p)
-        for (uint32_t i = 0; i < ctx->L; ++i) {
-            size_t off = ((size_t)p * ctx->L + i) * ctx->N;
-            jobs.push_back(NttJob{in_dev + off, out_dev + off, i, NTT_INVERSE});
-        }
-    return launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), (hipStream_t)stream);
+    return launch_ntt_strided(ctx, in_dev, out_dev, n_polys * ctx->L, ctx->L, NTT_INVERSE, (hipStream_t)stream);
 }
 
 int lola_from_coeff(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n_polys, uint32_t *out_dev,
                     lola_stream stream) {
     if (!ctx || !in_dev || !out_dev) return set_error(LOLA_E_INVAL, "null argument");
-    std::vector<NttJob> jobs;
-    for (uint32_t p = 0; p < n_polys; ++p)
-        for (uint32_t i = 0; i < ctx->L; ++i) {
-            size_t off = ((size_t)p * ctx->L + i) * ctx->N;
-            jobs.push_back(NttJob{in_dev + off, out_dev + off, i, NTT_SRC_REDUCE});
-        }
-    return launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), (hipStream_t)stream);
+    return launch_ntt_strided(ctx, in_dev, out_dev, n_polys * ctx->L, ctx->L, NTT_SRC_REDUCE, (hipStream_t)stream);
 }
 
 }  // extern "C"

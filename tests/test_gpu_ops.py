@@ -104,6 +104,28 @@ def _ntt_case(env):
     return idx, x, lola.from_numpy_u32(x, ctx.device), np.stack(exp)
 
 
+def test_ntt_cyclic_limbs_equal_the_descriptor_path(env):
+    """Limbs under primes 0, 1, .., L-1, 0, 1, .. (consecutive polynomials,
+    with a ragged last one) launch without descriptors; the same limbs in
+    reverse order go through descriptors.  Both directions agree word for
+    word."""
+    import torch
+    from paper_1812_10659_amd import lola
+    ctx, p = env["ctx"], env["p"]
+    L = p.L
+    n = 3 * L + 2
+    idx = np.arange(n, dtype=np.uint32) % L
+    rs = np.random.default_rng(5)
+    x = np.stack([rs.integers(0, p.q[i], p.N) for i in idx]).astype(np.uint32)
+    xd = lola.from_numpy_u32(x, ctx.device)
+    xr = lola.from_numpy_u32(np.ascontiguousarray(x[::-1]), ctx.device)
+    for inverse in (False, True):
+        y1 = _u32(ctx.ntt_limbs(xd, idx, inverse=inverse))
+        y2 = _u32(ctx.ntt_limbs(xr, np.ascontiguousarray(idx[::-1]), inverse=inverse))
+        assert np.array_equal(y1, y2[::-1]), inverse
+    torch.cuda.synchronize()
+
+
 def test_every_ntt_variant_is_evaluation_at_odd_powers(env):
     """Every compiled batched-NTT variant (radix split x limbs per workgroup)
     gives the oracle's evaluation and inverts exactly."""
