@@ -456,7 +456,10 @@ int lola_evaluate_graph(lola_ctx *ctx, lola_plan *plan, const lola_request *reqs
  * budget, up to max_inflight; a queued request enters when a slot is free.
  * Every lola_server_step admits queued requests and issues, per model, the
  * next wave of all its in-flight requests as one batched launch set, so
- * requests that arrive while others are on the GPU join them at once.  The
+ * requests that arrive while others are on the GPU join them at once.  A
+ * model granted 16 or more slots (and a second scratch area within the
+ * budget) runs a round of 16 or more requests as two lanes: half of them on
+ * a second stream, forked and joined within the round.  The
  * caller keeps a request's buffers alive until its tag is returned by
  * lola_server_poll.  Results equal those of lola_evaluate on the request
  * alone, word for word. */
@@ -465,7 +468,7 @@ int lola_server_create(size_t hbm_budget_bytes, lola_server **out);
 void lola_server_destroy(lola_server *srv);
 int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint32_t max_inflight,
                           uint32_t *model_id);
-/* Slots granted, HBM bytes per slot, the model's scratch bytes, jobs launched. */
+/* Slots granted, HBM bytes per slot, the model's scratch bytes (both lanes'), jobs launched. */
 int lola_server_model_info(const lola_server *srv, uint32_t model_id, uint32_t *slots, uint64_t *footprint_bytes,
                            uint64_t *scratch_bytes, uint64_t *launched_jobs);
 int lola_server_submit(lola_server *srv, uint32_t model_id, const lola_request *req, uint64_t tag);

@@ -144,6 +144,22 @@ void program_level(const lola_ctx *ctx, Program &prog, LevelJobs &jobs, uint32_t
     }
 }
 
+// Launches two programs, interleaved launch by launch so both streams have
+// work queued from the start.
+int run_two(lola_ctx *ctx, const Program &a, const uint8_t *da, hipStream_t sa, const Program &b,
+            const uint8_t *db, hipStream_t sb) {
+    const size_t na = a.launches.size(), nb = b.launches.size();
+    size_t i = 0, j = 0;
+    while (i < na || j < nb) {
+        // keep the two lanes' progress proportional
+        const bool take_a = j >= nb || (i < na && i * nb <= j * na);
+        int rc = take_a ? program_run_launch(ctx, a.launches[i++], da, sa)
+                        : program_run_launch(ctx, b.launches[j++], db, sb);
+        if (rc) return rc;
+    }
+    return LOLA_OK;
+}
+
 namespace {
 
 int release_graph(lola_plan *p) {
@@ -282,19 +298,9 @@ int prepare(lola_ctx *ctx, lola_plan *p, const lola_request *reqs, uint32_t n, h
     return LOLA_OK;
 }
 
-// Launches two bound programs, interleaved launch by launch so both streams
-// have work queued from the start.
+// The two bound lanes' programs, as above.
 int run_two(lola_ctx *ctx, const ExecLane &a, hipStream_t sa, const ExecLane &b, hipStream_t sb) {
-    const size_t na = a.prog.launches.size(), nb = b.prog.launches.size();
-    size_t i = 0, j = 0;
-    while (i < na || j < nb) {
-        // keep the two lanes' progress proportional
-        const bool take_a = j >= nb || (i < na && i * nb <= j * na);
-        int rc = take_a ? program_run_launch(ctx, a.prog.launches[i++], a.d_blob, sa)
-                        : program_run_launch(ctx, b.prog.launches[j++], b.d_blob, sb);
-        if (rc) return rc;
-    }
-    return LOLA_OK;
+    return run_two(ctx, a.prog, a.d_blob, sa, b.prog, b.d_blob, sb);
 }
 
 void free_consts(lola_plan *p) {

@@ -109,6 +109,10 @@ void program_level(const lola_ctx *ctx, Program &prog, LevelJobs &jobs, uint32_t
                    uint32_t mul_chunk);
 // Scratch words that program_level needs for chunk sizes ks_chunk / mul_chunk.
 size_t level_scratch_words(const lola_ctx *ctx, uint32_t ks_chunk, uint32_t mul_chunk);
+// Two programs (descriptors already on the device at da / db) on two
+// streams, interleaved launch by launch.
+int run_two(lola_ctx *ctx, const Program &a, const uint8_t *da, hipStream_t sa, const Program &b,
+            const uint8_t *db, hipStream_t sb);
 // Checks a request's arrays against the plan (keys, inputs, outputs, aliasing).
 int validate_request(const lola_plan *p, const lola_request &r);
 

@@ -7,8 +7,11 @@
 // wave of every in-flight request -- requests at different depths of the plan
 // share the round -- and issues it as one batched launch set on the model's
 // stream.  Models of different ring sizes run on separate streams, so their
-// work overlaps on the device.  A request's slot is released when the event
-// recorded after its last wave has completed.
+// work overlaps on the device.  With SRV_LANE_MIN or more requests in flight
+// a model's round runs as two lanes: half of its requests on a second stream
+// forked from and joined back to the model's stream within the round, so one
+// half's kernels fill the other's launch tails.  A request's slot is
+// released when the event recorded after its last wave has completed.
 #include <chrono>
 #include <deque>
 
@@ -20,6 +23,7 @@ namespace {
 constexpr uint32_t SRV_KS_CHUNK = 256;
 constexpr uint32_t SRV_MUL_CHUNK = 16;
 constexpr uint32_t SRV_LOOKAHEAD = 2;   // rounds in flight per model
+constexpr uint32_t SRV_LANE_MIN = 16;   // requests in flight from which a round runs as two lanes
 
 struct Pending {
     uint64_t tag;
@@ -45,8 +49,10 @@ struct Model {
     lola_ctx *ctx = nullptr;
     lola_plan *plan = nullptr;
     hipStream_t stream = nullptr;
-    uint32_t *ws = nullptr;         // slots' registers and temporaries, then scratch
-    uint32_t *scratch = nullptr;
+    hipStream_t stream2 = nullptr;  // second lane (models granted SRV_LANE_MIN or more slots)
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    uint32_t *ws = nullptr;         // slots' registers and temporaries, then scratch (two with two lanes)
+    uint32_t *scratch = nullptr, *scratch2 = nullptr;
     size_t footprint_bytes = 0;     // per slot
     std::vector<Slot> slots;
     std::deque<Pending> queue;
@@ -103,25 +109,50 @@ int round_model(lola_server *srv, Model &m) {
         m.queue.pop_front();
         s.rq = s.req.view();
     }
-    LevelJobs jobs;
-    std::vector<Slot *> finishing;
-    for (Slot &s : m.slots) {
-        if (!s.busy || s.finished) continue;
+    std::vector<Slot *> active, finishing;
+    for (Slot &s : m.slots)
+        if (s.busy && !s.finished) active.push_back(&s);
+    const uint32_t n_lanes = (m.stream2 && active.size() >= SRV_LANE_MIN) ? 2 : 1;
+    const size_t half = (active.size() + 1) / 2;
+    LevelJobs jobs[2];
+    for (size_t k = 0; k < active.size(); ++k) {
+        Slot &s = *active[k];
         ReqView rv{&s.rq, s.regs, s.sq, s.hoist};
-        int rc = emit_level(m.ctx, p, rv, s.level, jobs);
+        int rc = emit_level(m.ctx, p, rv, s.level, jobs[n_lanes == 2 && k >= half ? 1 : 0]);
         if (rc) return rc;
         if (++s.level > p->n_waves) finishing.push_back(&s);
     }
-    if (jobs.count() == 0) return LOLA_OK;
+    if (jobs[0].count() + jobs[1].count() == 0) return LOLA_OK;
     while (m.inflight.size() >= SRV_LOOKAHEAD) {
         int rc = retire(m, srv->completed, true);
         if (rc) return rc;
     }
-    Program prog;
-    program_level(m.ctx, prog, jobs, m.scratch, SRV_KS_CHUNK, SRV_MUL_CHUNK);
-    int rc = program_run_now(m.ctx, prog, m.stream);
+    Program prog[2];
+    void *blob[2] = {nullptr, nullptr};
+    for (uint32_t l = 0; l < n_lanes; ++l) {
+        program_level(m.ctx, prog[l], jobs[l], l ? m.scratch2 : m.scratch, SRV_KS_CHUNK, SRV_MUL_CHUNK);
+        // both lanes' descriptors go up on the model's stream before the fork,
+        // so the descriptor ring's reuse events (recorded on that stream, after
+        // this round's join) cover the second lane's reads too
+        if (!prog[l].launches.empty()) {
+            int rc = desc_upload(m.ctx, prog[l].blob.data(), prog[l].blob.size(), m.stream, &blob[l]);
+            if (rc) return rc;
+        }
+    }
+    int rc = LOLA_OK;
+    if (n_lanes == 1) {
+        rc = program_run(m.ctx, prog[0], (const uint8_t *)blob[0], m.stream);
+    } else {
+        LOLA_HIP(hipEventRecord(m.fork_ev, m.stream));
+        LOLA_HIP(hipStreamWaitEvent(m.stream2, m.fork_ev, 0));
+        rc = run_two(m.ctx, prog[0], (const uint8_t *)blob[0], m.stream, prog[1], (const uint8_t *)blob[1],
+                     m.stream2);
+        // join even after an error, so the model's stream never runs ahead
+        LOLA_HIP(hipEventRecord(m.join_ev, m.stream2));
+        LOLA_HIP(hipStreamWaitEvent(m.stream, m.join_ev, 0));
+    }
     if (rc) return rc;
-    m.launched_jobs += jobs.count();
+    m.launched_jobs += jobs[0].count() + jobs[1].count();
     hipEvent_t ev;
     if (m.free_events.empty()) LOLA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     else { ev = m.free_events.back(); m.free_events.pop_back(); }
@@ -152,11 +183,15 @@ int lola_server_create(size_t hbm_budget_bytes, lola_server **out) {
 void lola_server_destroy(lola_server *srv) {
     if (!srv) return;
     for (Model &m : srv->models) {
-        if (m.stream) (void)hipStreamSynchronize(m.stream);
+        if (m.stream) (void)hipStreamSynchronize(m.stream);   // joined with stream2 every round
+        if (m.stream2) (void)hipStreamSynchronize(m.stream2);
         for (auto &f : m.inflight) (void)hipEventDestroy(f.second);
         for (hipEvent_t e : m.free_events) (void)hipEventDestroy(e);
+        if (m.fork_ev) (void)hipEventDestroy(m.fork_ev);
+        if (m.join_ev) (void)hipEventDestroy(m.join_ev);
         if (m.ws) (void)hipFree(m.ws);
         if (m.stream) (void)hipStreamDestroy(m.stream);
+        if (m.stream2) (void)hipStreamDestroy(m.stream2);
     }
     delete srv;
 }
@@ -171,14 +206,29 @@ int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint
     const size_t avail = srv->budget > srv->used ? srv->budget - srv->used : 0;
     if (avail < (scratch_words + slot_words) * 4)
         return set_error(LOLA_E_NOMEM, "HBM budget too small for one request of this model");
-    const uint32_t fit = (uint32_t)std::min<size_t>(max_inflight, (avail / 4 - scratch_words) / slot_words);
+    uint32_t fit = (uint32_t)std::min<size_t>(max_inflight, (avail / 4 - scratch_words) / slot_words);
+    // a second lane needs a second scratch; it is taken only where the model
+    // still gets SRV_LANE_MIN slots beside it
+    bool two = false;
+    if (fit >= SRV_LANE_MIN && avail / 4 >= 2 * scratch_words + (size_t)SRV_LANE_MIN * slot_words) {
+        const uint32_t fit2 = (uint32_t)std::min<size_t>(max_inflight, (avail / 4 - 2 * scratch_words) / slot_words);
+        if (fit2 >= SRV_LANE_MIN) {
+            fit = fit2;
+            two = true;
+        }
+    }
     Model m;
     m.ctx = ctx;
     m.plan = plan;
     m.footprint_bytes = slot_words * 4;
-    const size_t words = fit * slot_words + scratch_words;
+    const size_t words = fit * slot_words + (two ? 2 : 1) * scratch_words;
     if (hipMalloc(&m.ws, words * 4) != hipSuccess) return set_error(LOLA_E_NOMEM, "server workspace allocation failed");
     LOLA_HIP(hipStreamCreateWithFlags(&m.stream, hipStreamNonBlocking));
+    if (two) {
+        LOLA_HIP(hipStreamCreateWithFlags(&m.stream2, hipStreamNonBlocking));
+        LOLA_HIP(hipEventCreateWithFlags(&m.fork_ev, hipEventDisableTiming));
+        LOLA_HIP(hipEventCreateWithFlags(&m.join_ev, hipEventDisableTiming));
+    }
     m.slots.resize(fit);
     for (uint32_t k = 0; k < fit; ++k) {
         m.slots[k].regs = m.ws + k * slot_words;
@@ -186,6 +236,7 @@ int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint
         m.slots[k].hoist = m.slots[k].sq + nsq * CT3;
     }
     m.scratch = m.ws + fit * slot_words;
+    if (two) m.scratch2 = m.scratch + scratch_words;
     srv->used += words * 4;
     srv->models.push_back(std::move(m));
     *model_id = (uint32_t)srv->models.size() - 1;
@@ -198,7 +249,8 @@ int lola_server_model_info(const lola_server *srv, uint32_t model_id, uint32_t *
     const Model &m = srv->models[model_id];
     if (slots) *slots = (uint32_t)m.slots.size();
     if (footprint_bytes) *footprint_bytes = m.footprint_bytes;
-    if (scratch_bytes) *scratch_bytes = level_scratch_words(m.ctx, SRV_KS_CHUNK, SRV_MUL_CHUNK) * 4;
+    if (scratch_bytes)
+        *scratch_bytes = level_scratch_words(m.ctx, SRV_KS_CHUNK, SRV_MUL_CHUNK) * 4 * (m.stream2 ? 2 : 1);
     if (launched_jobs) *launched_jobs = m.launched_jobs;
     return LOLA_OK;
 }

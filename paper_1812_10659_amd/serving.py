@@ -211,6 +211,7 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
         "by_model": {},
         "checked_alone_vs_mixed": len(served_copy), "mismatches": mismatches,
         "slots": {k: srv.model_info(v)["slots"] for k, v in mids.items()},
+        "scratch_bytes": {k: srv.model_info(v)["scratch_bytes"] for k, v in mids.items()},
     }
     for k in (1, 0):
         sel = kinds == k

@@ -16,6 +16,26 @@ def test_serving_mixed_stream_equals_alone():
     assert res["slots"]["mnist"] >= 1 and res["slots"]["dense64"] >= 1
 
 
+def test_serving_two_lane_rounds_equal_alone():
+    """A burst that keeps 16 or more requests of a model in flight runs its
+    rounds as two lanes (the model holds a second scratch area); every served
+    result still equals the request evaluated alone."""
+    from paper_1812_10659_amd import serving
+    print("[gpu-serve] 64 requests, rate 20000/s, 32 slots, every result checked", flush=True)
+    res = serving.run_serving(n_req=64, rate=20000.0, clients=3, max_inflight=32, hbm_budget_gb=48,
+                              check_every=1, baseline=False)
+    assert res["checked_alone_vs_mixed"] == 64
+    assert res["mismatches"] == 0
+    assert res["slots"]["mnist"] == 32 and res["slots"]["dense64"] == 32
+    # one lane's scratch, from a model granted a single slot
+    for name in ("mnist", "dense64"):
+        m = serving.ModelSetup(name, clients=1, inputs_per_client=1, out_pool=1)
+        probe = serving.Server(64 << 30)
+        one = probe.model_info(probe.add_model(m.ctx, m.plan, 1))["scratch_bytes"]
+        probe.close()
+        assert res["scratch_bytes"][name] == 2 * one, name
+
+
 def test_serving_admission_respects_budget():
     """A budget that fits two MNIST slots gives the model exactly two slots;
     requests beyond that queue and still complete."""
