@@ -121,6 +121,23 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    serving_out = {}
+    if args.serve_requests > 0 and not args.headline_only:
+        # Serving first, in a process that has created no other streams yet:
+        # the host drives every scheduling round, and each model runs on two
+        # streams of its own, which measured 20% slower at saturation once
+        # the headline's streams existed (2745/s against 3345-3700/s).
+        # Poisson arrivals: 70% N=16384 MNIST-shaped, 30% N=4096 dense-64,
+        # 8 resident key sets per ring size, continuous batching vs one at a time.
+        from paper_1812_10659_amd import serving
+        serving_out["serving"] = serving.run_serving(n_req=args.serve_requests)
+        if args.serve_high_rate > 0:
+            serving_out["serving_high_load"] = serving.run_serving(n_req=args.serve_requests,
+                                                                   rate=args.serve_high_rate)
+        if args.serve_saturation_rate > 0:
+            serving_out["serving_saturation"] = serving.run_serving(n_req=args.serve_requests,
+                                                                    rate=args.serve_saturation_rate)
+        torch.cuda.empty_cache()
     p = wl.PARAMS["mnist_n16384"]
     N, L = p.N, p.L
     w = wl.mnist_weights()
@@ -328,22 +345,8 @@ def main():
     if args.headline_only:
         print(json.dumps(out), flush=True)
         return
-    if args.serve_requests > 0:
-        # Poisson arrivals at 200/s: 70% N=16384 MNIST-shaped, 30% N=4096 dense-64,
-        # 8 resident key sets per ring size, continuous batching vs one at a time.
-        # Run first after the headline, from a lean process: the host drives
-        # every scheduling round, so at saturation its own overhead shows.
-        import gc
-        from paper_1812_10659_amd import serving
-        reqs, keys = None, None
-        gc.collect()
-        torch.cuda.empty_cache()
-        out["serving"] = serving.run_serving(n_req=args.serve_requests)
-        if args.serve_high_rate > 0:
-            out["serving_high_load"] = serving.run_serving(n_req=args.serve_requests, rate=args.serve_high_rate)
-        if args.serve_saturation_rate > 0:
-            out["serving_saturation"] = serving.run_serving(n_req=args.serve_requests, rate=args.serve_saturation_rate)
-        torch.cuda.empty_cache()
+    if serving_out:
+        out.update(serving_out)
     out["paper_layout"] = paper_layout_run(ctx, w, images, B, C, args.latency_runs)
     out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
     out["mnist_dense_input"] = dense_input_run(B, C, args.latency_runs)
