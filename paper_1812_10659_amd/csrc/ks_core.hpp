@@ -57,13 +57,13 @@ inline uint32_t xcd_grid(uint32_t n, uint32_t units) { return (n + N_XCD - 1) / 
 // with coalesced 16-byte loads and gathered from there (a gather straight from
 // global memory touches a different cache line per lane).  g is the same for
 // the whole workgroup.  Uses sh (N words) between two workgroup barriers.
-template <int LOGN>
+template <int LOGN, int SPLIT = 0>
 __device__ __forceinline__ void ks_read_sigma(const uint32_t *src, uint32_t g, uint32_t tid, uint32_t *sh,
                                               uint32_t (&v)[NTT_E]) {
     constexpr uint32_t N = 1u << LOGN, T = N / NTT_E;
     const GBuf S = gbuf(src, N);
     if (g <= 1) {
-        load_spectral<LOGN>(S, tid, v);
+        load_spectral<LOGN, SPLIT>(S, tid, v);
         return;
     }
     __syncthreads();   // earlier readers of sh are done
@@ -75,7 +75,7 @@ __device__ __forceinline__ void ks_read_sigma(const uint32_t *src, uint32_t g, u
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) v[r] = sh[galois_src_index(spectral_index<LOGN>(tid, r), g, LOGN)];
+    for (int r = 0; r < NTT_E; ++r) v[r] = sh[galois_src_index(spectral_index<LOGN, SPLIT>(tid, r), g, LOGN)];
 }
 
 // Stage 1 for digit i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
@@ -190,33 +190,50 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
     }
 }
 
-// Stage 2 split for launches of few jobs (latency): the term of digit i for
-// target modulus m_j alone, (x_i mod m_j) * key[i][c][j] for c = 0, 1, by one
-// workgroup, written canonical to the job's term area; ks_stage_fold then adds
-// the L terms of each (j, c).  A sum of Montgomery reductions is congruent to
-// the reduction of the sum, and both are canonical, so the words equal those
-// of ks_stage_inner.  Term area: limb 4L + 2 + 2 (j L + i) + c of the job's
-// scratch.
+// Latency form (launches of few jobs): stage 2 split into one workgroup per
+// term, (x_i mod m_j) * key[i][c][j] for c = 0, 1, written canonical to the
+// job's term area, and the L terms of each (j, c) summed afterwards.  A sum
+// of Montgomery reductions is congruent to the reduction of the sum, and
+// both are canonical, so the words equal those of ks_stage_inner.  Term
+// area: limb 4L + 2 + 2 (j L + i) + c of the job's scratch.
 __host__ __device__ constexpr size_t ks_term_limb(uint32_t L, uint32_t j, uint32_t i, uint32_t c) {
     return (size_t)(4 * L + 2) + 2 * ((size_t)j * L + i) + c;
 }
 
+// The term of digit i for target m_j, computed straight from the input (the
+// digit stage folded in).  sigma_g(x_i) is gathered through LDS; for i != j
+// it is brought back to coefficients mod q_i (the digit D_i, which each
+// target's workgroup recomputes: few jobs leave the GPU idle, so a kernel
+// boundary costs more than the repeated transform), reduced mod m_j and
+// transformed; then both key products, each reduced to a canonical term.
+// The digits equal ks_stage_digit's, so the terms are those ks_stage_inner
+// accumulates.
 template <int LOGN>
-__device__ __forceinline__ void ks_stage_term(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t i,
-                                              uint32_t L, uint32_t *sh, const ModConst &mc, const TwPair *tw) {
+__device__ __forceinline__ void ks_stage_term_direct(const uint32_t *x, uint32_t g, const uint32_t *key,
+                                                     uint32_t *scratch, uint32_t j, uint32_t i, uint32_t L,
+                                                     uint32_t *sh, const ModConst &mi, const ModConst &mj,
+                                                     const TwPair *tw, const TwPair *itw) {
     constexpr uint32_t N = 1u << LOGN;
     constexpr int KSI = ks_inner_split<LOGN>();
+    // the inverse transform (default split) leaves the registers in its first
+    // pass's layout, which must be the layout the KSI forward transform takes
+    static_assert(split_width(LOGN, 0, 0) == split_width(LOGN, KSI, 0), "first passes must match");
     const uint32_t M = L + 1;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    uint32_t x[NTT_E];
+    uint32_t ii = i;
+    asm volatile("" : "+s"(ii));
+    uint32_t v[NTT_E];
     if (i == j) {
-        load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
+        ks_read_sigma<LOGN, KSI>(x + ((size_t)ii << LOGN), g, tid, sh, v);   // X'_i
     } else {
-        const GBuf D = gbuf(scratch + ((size_t)i << LOGN), N);
+        ks_read_sigma<LOGN>(x + ((size_t)ii << LOGN), g, tid, sh, v);
+        ntt_inv_regs<LOGN>(v, tid, sh, itw + ((size_t)ii << LOGN), mi);   // D_i; starts with a barrier
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
-        ntt_fwd_regs<LOGN, false, KSI>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
+        for (int r = 0; r < NTT_E; ++r) v[r] = reduce32(v[r], mj.q, mj.one_shoup);
+        uint32_t jj = j;
+        asm volatile("" : "+s"(jj));
+        ntt_fwd_regs<LOGN, false, KSI>(v, tid, sh, tw + ((size_t)jj << LOGN), mj.q);
     }
     uint32_t koff = i * 2 * M + j;
     asm volatile("" : "+s"(koff));
@@ -226,36 +243,75 @@ __device__ __forceinline__ void ks_stage_term(const uint32_t *key, uint32_t *scr
         load_spectral<LOGN, KSI>(gbuf(key + ((size_t)(koff + c * M) << LOGN), N), tid, kv);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) {
-            const uint64_t a = (uint64_t)x[r] * kv[r];
-            u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mc);
+            const uint64_t a = (uint64_t)v[r] * kv[r];
+            u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mj);
         }
         store_spectral<LOGN, KSI>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, u);
     }
 }
 
-// Fold for (target m_j, component c): the sum of the L terms, stored where
-// ks_stage_inner stores its result (U, or for P back in coefficients, UP).
+// Sum of the L terms of (target m_j, component c), canonical, in the default
+// spectral layout.  Terms are loaded three limbs at a time, all three loads
+// in flight together; limbs past the last repeat it and are not added.
 template <int LOGN>
-__device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L, uint32_t *sh,
-                                              const ModConst &mc, const TwPair *itw) {
+__device__ __forceinline__ void ks_sum_terms(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
+                                             uint32_t tid, uint32_t q, uint32_t (&u)[NTT_E]) {
+    constexpr uint32_t N = 1u << LOGN, G = 3;
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) u[r] = 0;
+    for (uint32_t i0 = 0; i0 < L; i0 += G) {
+        uint32_t v[G][NTT_E];
+#pragma unroll
+        for (uint32_t b = 0; b < G; ++b)
+            load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, min(i0 + b, L - 1), c) << LOGN), N), tid, v[b]);
+#pragma unroll
+        for (uint32_t b = 0; b < G; ++b) {
+            const uint32_t live = 0u - (uint32_t)(i0 + b < L);   // all ones for a real term
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) u[r] = add_mod(u[r], v[b][r] & live, q);
+        }
+    }
+}
+
+// The sum of the terms folded into the mod-down, for (target q_j, component
+// c): the P terms summed and brought back to coefficients (u_P, recomputed by
+// each target's workgroup), lifted into q_j and transformed; the q_j terms
+// summed (U); then out as in ks_stage_moddown.  The sums equal ks_stage_inner's
+// U and UP, so the words equal the batched form's.
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_fold_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
+                                                      const uint32_t *add, uint32_t g, const uint32_t *addct,
+                                                      uint32_t *out, uint32_t *sh, const ModConst &mj,
+                                                      const ModConst &mP, const TwPair *tw, const TwPair *itw,
+                                                      const MrcConst *mrc) {
     constexpr uint32_t N = 1u << LOGN;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    uint32_t u[NTT_E], v[NTT_E];
-    load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, 0, c) << LOGN), N), tid, u);
-    for (uint32_t i = 1; i < L; ++i) {
-        load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, v);
+    uint32_t jj = j, LL = L;
+    asm volatile("" : "+s"(jj), "+s"(LL));
+    uint32_t x[NTT_E], u[NTT_E];
+    ks_sum_terms<LOGN>(scratch, L, c, L, tid, mP.q, x);
+    ntt_inv_regs<LOGN, 0, true>(x, tid, sh, itw + ((size_t)LL << LOGN), mP);   // u_P, coefficients
+    // [u_P]_P mod q_j: v, or v - P for v > P/2 (see ks_stage_moddown)
+    const uint32_t halfP = mP.q >> 1, negPq = mj.q - mrc->Pq[jj];
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) u[r] = add_mod(u[r], v[r], mc.q);
-    }
-    if (j < L) {
-        store_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + j) << LOGN), N), tid, u);
-    } else {
-        ntt_inv_regs<LOGN, 0, true>(u, tid, sh, itw + ((size_t)j << LOGN), mc);   // padded LDS placement
-        const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+    for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(x[r] + (x[r] > halfP ? negPq : 0u), mj.q, mj.one_shoup);
+    ntt_fwd_regs<LOGN, false, 0, true>(x, tid, sh, tw + ((size_t)jj << LOGN), mj.q);
+    ks_sum_terms<LOGN>(scratch, j, c, L, tid, mj.q, u);
+    const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
+    for (int r = 0; r < NTT_E; ++r) x[r] = csub(shoup_lazy(u[r] + mj.q - x[r], pinv, pinvp, mj.q), mj.q);
+    if (add) {
+        ks_read_sigma<LOGN>(add + ((size_t)jj << LOGN), g, tid, sh, u);   // after the transform's last use of sh
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], u[r], mj.q);
     }
+    if (addct) {
+        load_spectral<LOGN>(gbuf(addct + ((size_t)(c * L + jj) << LOGN), N), tid, u);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], u[r], mj.q);
+    }
+    store_spectral<LOGN>(gbuf(out + ((size_t)(c * L + jj) << LOGN), N), tid, x);
 }
 
 // Stage 3 for (target q_j, component c): lift [u_P]_P into q_j, transform,
@@ -350,6 +406,7 @@ __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, cons
     for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
+#pragma unroll 1
     for (uint32_t i = 0; i < L; ++i) {
         const uint32_t *src = i == j ? x + ((size_t)i << LOGN) : hoist + (ks_hoist_limb(L, j, i) << LOGN);
         const GBuf S = gbuf(src, N);
@@ -361,18 +418,26 @@ __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, cons
             sh[w] = v.x, sh[w + 1] = v.y, sh[w + 2] = v.z, sh[w + 3] = v.w;
         }
         __syncthreads();
+        // The gather addresses are the same for every digit; an opaque copy
+        // of g keeps the compiler from holding all 16 across the loop (with
+        // the accumulators that spilled registers to scratch memory).
+        uint32_t gi = g;
+        asm volatile("" : "+s"(gi));
         uint32_t xv[NTT_E];
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) xv[r] = sh[galois_src_index(spectral_index<LOGN>(tid, r), g, LOGN)];
-        const uint32_t koff = i * 2 * M + j;
-        uint32_t kb[NTT_E], ka[NTT_E];
-        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kb);
-        load_spectral<LOGN>(gbuf(key + ((size_t)(koff + M) << LOGN), N), tid, ka);
+        for (int r = 0; r < NTT_E; ++r) xv[r] = sh[galois_src_index(spectral_index<LOGN>(tid, r), gi, LOGN)];
+        // one key component at a time: both at once (32 more registers
+        // beside the 64 of the accumulators) spilled to scratch memory
+        uint32_t koff = i * 2 * M + j;
+        uint32_t kv[NTT_E];
+        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) {
-            a0[r] += (uint64_t)xv[r] * kb[r];
-            a1[r] += (uint64_t)xv[r] * ka[r];
-        }
+        for (int r = 0; r < NTT_E; ++r) a0[r] += (uint64_t)xv[r] * kv[r];
+        koff += M;
+        asm volatile("" : "+s"(koff));   // the second component's loads after the first products
+        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) a1[r] += (uint64_t)xv[r] * kv[r];
     }
     uint32_t u[NTT_E];
     if (j < L) {
@@ -386,18 +451,26 @@ __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, cons
         // the transforms below reuse sh, which other waves may still be
         // reading for the last digit's gather
         __syncthreads();
+        // both sums reduced to 32 bits first, so the 64-bit accumulators are
+        // not live across the transforms
+        uint32_t u1[NTT_E];
 #pragma unroll
-        for (uint32_t c = 0; c < 2; ++c) {
-            const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) {
-                const uint64_t a = c == 0 ? a0[r] : a1[r];
-                u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mc);
-            }
-            ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
+        for (int r = 0; r < NTT_E; ++r) {
+            u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
+            u1[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
         }
+        ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
+        const GBuf UP0 = gbuf(scratch + ((size_t)(4 * L) << LOGN), N);
+        const GBuf UP1 = gbuf(scratch + ((size_t)(4 * L + 1) << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP0, natural_index<LOGN>(tid, r), u[r]);
+        // the second transform's arithmetic stays after the first: overlapped
+        // by the scheduler, the two needed far more registers
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) asm volatile("" : "+v"(u1[r]));
+        ntt_inv_regs<LOGN>(u1, tid, sh, itw + ((size_t)j << LOGN), mc);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP1, natural_index<LOGN>(tid, r), u1[r]);
     }
 }
 
