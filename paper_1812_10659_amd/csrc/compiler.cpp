@@ -587,6 +587,8 @@ float predict_latency_us(const lola_plan *p) {
     auto rounds = [](double wgs) { return std::ceil(wgs / 256.0); };
     auto ks_us = [&](double n) {
         if (n <= 0) return 0.0;
+        if (n * L * (L + 1) <= 256)   // terms straight from the input, then fold and mod-down together
+            return 33.0 * sl + 34.0 * sl * rounds(2 * n * L);
         double t = 17.0 * sl * (rounds(n * L) + rounds(2 * n * L));   // digits, mod-down
         if (n <= 16) t += 19.0 * sl * (rounds(n * L * (L + 1)) + rounds(2 * n * (L + 1)));   // terms, fold
         else t += 13.0 * sl * L * rounds(n * (L + 1));

@@ -46,6 +46,38 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
     ks_stage_inner<LOGN>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
 }
 
+// Latency form of the inner stage (launches of at most KS_TERM_MAX_JOBS
+// jobs): L (L+1) workgroups per job, one digit term each, then 2 (L+1) that
+// fold the terms.  The special prime's units come first, as above.  Grid =
+// jobs x units, workgroup k taking unit k mod units of job k / units: the
+// units of one job spread over all XCDs (few jobs, so latency, not key reuse
+// through L2, is what matters).
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_term_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                    uint32_t L, const ModConst *__restrict__ mcs,
+                                                                    const TwPair *__restrict__ tw) {
+    __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
+    const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
+    if (jb >= n) return;
+    const KsJob job = jobs[jb];
+    const uint32_t jr = unit / L, i = unit % L;
+    const uint32_t j = jr == 0 ? L : jr - 1;
+    ks_stage_term<LOGN>(job.key, job.scratch, j, i, L, sh, mcs[j], tw);
+}
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_fold_kernel(const KsJob *__restrict__ jobs, uint32_t n,
+                                                                    uint32_t L, const ModConst *__restrict__ mcs,
+                                                                    const TwPair *__restrict__ itw) {
+    __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
+    const uint32_t units = 2 * (L + 1), jb = blockIdx.x / units, unit = blockIdx.x % units;
+    if (jb >= n) return;
+    const KsJob job = jobs[jb];
+    const uint32_t jr = unit / 2, c = unit % 2;
+    const uint32_t j = jr == 0 ? L : jr - 1;
+    ks_stage_fold<LOGN>(job.scratch, j, c, L, sh, mcs[j], itw);
+}
+
 // Latency form, two kernels: terms straight from the input (digits folded
 // in), then fold and mod-down together.  Grids are jobs x units with a job's
 // units spread over all XCDs.
@@ -130,6 +162,10 @@ size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) *
 // words per job.
 static constexpr uint32_t KS_TERM_MAX_JOBS = 16;
 static bool ks_term_mode(uint32_t n) { return n <= KS_TERM_MAX_JOBS; }
+// Within the latency form: terms straight from the input (two kernels) while
+// they fit one round of workgroups over the CUs; beyond it the digit
+// transforms each target repeats cost more than the two launches they save.
+static bool ks_direct_mode(uint32_t n, uint32_t L) { return n * L * (L + 1) <= 256; }
 static size_t ks_job_words(const lola_ctx *ctx, uint32_t n) {
     const size_t L = ctx->L;
     return ks_scratch_words(ctx) + (ks_term_mode(n) ? 2 * L * (L + 1) * ctx->N : 0);
@@ -149,10 +185,10 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t
         if (rc) return rc;
         ctx->timed_jobs += n;
     }
-    const bool term = ks_term_mode(n);
+    const bool term = ks_term_mode(n), direct = term && ks_direct_mode(n, L);
 #define LOLA_KS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
-        if (term) {                                                                                          \
+        if (direct) {                                                                                        \
             if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                         \
             hipLaunchKernelGGL(ks_term_direct_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L,   \
                                ctx->d_mc, ctx->d_tw, ctx->d_itw);                                             \
@@ -164,8 +200,15 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t
         hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L, ctx->d_mc,    \
                            ctx->d_itw);                                                                       \
         if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                             \
-        hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L,          \
-                           ctx->d_mc, ctx->d_tw, ctx->d_itw);                                                 \
+        if (term) {                                                                                          \
+            hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, ctx->d_mc, \
+                               ctx->d_tw);                                                                    \
+            hipLaunchKernelGGL(ks_fold_kernel<LG>, dim3(n * 2 * (L + 1)), block, 0, s, d_jobs, n, L, ctx->d_mc,  \
+                               ctx->d_itw);                                                                   \
+        } else {                                                                                             \
+            hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L,      \
+                               ctx->d_mc, ctx->d_tw, ctx->d_itw);                                             \
+        }                                                                                                    \
         if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                             \
         hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, L,         \
                            ctx->d_mc, ctx->d_tw, ctx->d_mrc);                                                 \

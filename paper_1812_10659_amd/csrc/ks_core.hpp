@@ -200,6 +200,65 @@ __host__ __device__ constexpr size_t ks_term_limb(uint32_t L, uint32_t j, uint32
     return (size_t)(4 * L + 2) + 2 * ((size_t)j * L + i) + c;
 }
 
+// One term from the stored digits (ks_stage_digit), for launches whose terms
+// take more than one round of workgroups.
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_term(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t i,
+                                              uint32_t L, uint32_t *sh, const ModConst &mc, const TwPair *tw) {
+    constexpr uint32_t N = 1u << LOGN;
+    constexpr int KSI = ks_inner_split<LOGN>();
+    const uint32_t M = L + 1;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t x[NTT_E];
+    if (i == j) {
+        load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
+    } else {
+        const GBuf D = gbuf(scratch + ((size_t)i << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
+        ntt_fwd_regs<LOGN, false, KSI>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
+    }
+    uint32_t koff = i * 2 * M + j;
+    asm volatile("" : "+s"(koff));
+    uint32_t kv[NTT_E], u[NTT_E];
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c) {
+        load_spectral<LOGN, KSI>(gbuf(key + ((size_t)(koff + c * M) << LOGN), N), tid, kv);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) {
+            const uint64_t a = (uint64_t)x[r] * kv[r];
+            u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mc);
+        }
+        store_spectral<LOGN, KSI>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, u);
+    }
+}
+
+// Fold for (target m_j, component c): the sum of the L terms, stored where
+// ks_stage_inner stores its result (U, or for P back in coefficients, UP).
+template <int LOGN>
+__device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L, uint32_t *sh,
+                                              const ModConst &mc, const TwPair *itw) {
+    constexpr uint32_t N = 1u << LOGN;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint32_t u[NTT_E], v[NTT_E];
+    load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, 0, c) << LOGN), N), tid, u);
+    for (uint32_t i = 1; i < L; ++i) {
+        load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, v);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) u[r] = add_mod(u[r], v[r], mc.q);
+    }
+    if (j < L) {
+        store_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + j) << LOGN), N), tid, u);
+    } else {
+        ntt_inv_regs<LOGN, 0, true>(u, tid, sh, itw + ((size_t)j << LOGN), mc);   // padded LDS placement
+        const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
+    }
+}
+
 // The term of digit i for target m_j, computed straight from the input (the
 // digit stage folded in).  sigma_g(x_i) is gathered through LDS; for i != j
 // it is brought back to coefficients mod q_i (the digit D_i, which each

@@ -299,14 +299,14 @@ def test_latency_model_tracks_depth_and_launch_rounds():
     by rounds of workgroups, so a plan with fewer rotations but more waves is not
     automatically faster alone, and a wave of many rotations costs more than one
     of a few.  Values in microseconds, measured counterparts in the design notes
-    (MNIST shared 2.57 ms, paper's layout 2.66 ms, LoLa-Small 1.37 ms)."""
+    (MNIST shared 2.23 ms, paper's layout 2.50 ms, LoLa-Small 1.27 ms)."""
     lola = _lola()
     from paper_1812_10659_amd import networks
     pm, w = wl.PARAMS["mnist_n16384"], wl.mnist_weights()
     shared = lola.Plan(pm, networks.mnist_layers(w), recipe=lola.RECIPE_SHARED_REDUCTION).info
     full = lola.Plan(pm, networks.mnist_layers(w), recipe=lola.RECIPE_FULL_REDUCTION).info
     small = lola.Plan(pm, networks.mnist_small_layers(wl.mnist_small_weights())).info
-    for info, ms in [(shared, 2.57), (full, 2.66), (small, 1.37)]:
+    for info, ms in [(shared, 2.23), (full, 2.50), (small, 1.27)]:
         assert abs(info["predicted_latency_us"] / 1e3 - ms) < 0.15 * ms
     # per rotation, the shared layout's waves are costlier alone (fewer rotations per wave)
     assert shared["predicted_latency_us"] / shared["n_rotations"] > full["predicted_latency_us"] / full["n_rotations"]

@@ -335,12 +335,15 @@ def test_rotate_hoisted_matches_oracle(env):
         assert list(bfv.decrypt(octx, ok, ref)) == list(bfv.decrypt(octx, ok, bfv.rotate(octx, c1, step, ok)))
 
 
-@pytest.mark.parametrize("n_jobs", [1, 16, 17, 40])
+@pytest.mark.parametrize("n_jobs", [1, 4, 5, 16, 17, 40])
 def test_keyswitch_both_inner_forms(env, n_jobs):
     """Launches of at most 16 jobs split the key inner product into one
     workgroup per (prime, digit) term plus a fold; larger ones accumulate all
-    digits per prime.  Both give the oracle's words (16 and 17 jobs sit on
-    either side of the switch)."""
+    digits per prime.  Launches whose L (L+1) terms per job fit one round of
+    256 workgroups compute the terms straight from the input and fold them
+    inside the mod-down (two kernels).  All give the oracle's words (4 and 5
+    jobs sit on either side of the two-kernel form at L = 7, 16 and 17 on
+    either side of the term split)."""
     ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
     c1, c2 = env["c"]
     c3 = bfv.mul(octx, c1, c2)
