@@ -324,28 +324,40 @@ int lola_plan_load(lola_ctx *ctx, lola_plan *p, lola_stream stream) {
     if (p->N != ctx->N || p->L != ctx->L || p->t != ctx->t) return set_error(LOLA_E_SHAPE, "plan compiled for other parameters");
     hipStream_t s = (hipStream_t)stream;
     const size_t N = ctx->N, L = ctx->L;
-    free_consts(p);
-    p->d_cmul.assign(p->consts.size(), nullptr);
-    p->d_cadd.assign(p->consts.size(), nullptr);
-    p->d_wtab.assign(p->ops.size(), nullptr);
+    // Everything is built into fresh buffers first.  On any failure they are
+    // freed and the plan keeps its previous constants, binding and graph, all
+    // still valid; only a complete load replaces them.
+    std::vector<uint32_t *> cmul(p->consts.size(), nullptr), cadd(p->consts.size(), nullptr),
+        wtab(p->ops.size(), nullptr);
     int64_t *d_slots = nullptr;
     uint32_t *d_pt = nullptr;
-    LOLA_HIP(hipMalloc(&d_slots, N * 8));
-    LOLA_HIP(hipMalloc(&d_pt, N * 4));
+    auto release_new = [&]() {
+        (void)hipStreamSynchronize(s);   // no queued work may still read them
+        for (auto *v : {&cmul, &cadd, &wtab})
+            for (uint32_t *q : *v)
+                if (q) (void)hipFree(q);
+        if (d_slots) (void)hipFree(d_slots);
+        if (d_pt) (void)hipFree(d_pt);
+    };
     int rc = LOLA_OK;
+    if (hipMalloc(&d_slots, N * 8) != hipSuccess || hipMalloc(&d_pt, N * 4) != hipSuccess)
+        rc = set_error(LOLA_E_NOMEM, "staging allocation");
     for (size_t c = 0; c < p->consts.size() && !rc; ++c) {
-        LOLA_HIP(hipMemcpyAsync(d_slots, p->consts[c].data(), N * 8, hipMemcpyHostToDevice, s));
+        if (hipMemcpyAsync(d_slots, p->consts[c].data(), N * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+            rc = set_error(LOLA_E_DEVICE, "constant upload");
+            break;
+        }
         rc = lola_encode(ctx, d_slots, d_pt, stream);
         if (!rc && p->const_mul[c]) {
-            if (hipMalloc(&p->d_cmul[c], L * N * 4) != hipSuccess) rc = set_error(LOLA_E_NOMEM, "constant allocation");
-            else rc = lola_plain_mul_form(ctx, d_pt, p->d_cmul[c], stream);
+            if (hipMalloc(&cmul[c], L * N * 4) != hipSuccess) rc = set_error(LOLA_E_NOMEM, "constant allocation");
+            else rc = lola_plain_mul_form(ctx, d_pt, cmul[c], stream);
         }
         if (!rc && p->const_add[c]) {
-            if (hipMalloc(&p->d_cadd[c], L * N * 4) != hipSuccess) rc = set_error(LOLA_E_NOMEM, "constant allocation");
-            else rc = lola_plain_add_form(ctx, d_pt, p->d_cadd[c], stream);
+            if (hipMalloc(&cadd[c], L * N * 4) != hipSuccess) rc = set_error(LOLA_E_NOMEM, "constant allocation");
+            else rc = lola_plain_add_form(ctx, d_pt, cadd[c], stream);
         }
         // the slot staging buffer is reused: wait for this constant's upload
-        if (!rc) LOLA_HIP(hipStreamSynchronize(s));
+        if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = set_error(LOLA_E_DEVICE, "constant upload");
     }
     // linear-combination scalars: [w]_t reduced per prime, with Shoup companions
     for (size_t i = 0; i < p->ops.size() && !rc; ++i) {
@@ -364,15 +376,25 @@ int lola_plan_load(lola_ctx *ctx, lola_plan *p, lola_stream stream) {
                 tab[(2 * k + 1) * L + j] = shoup_companion((uint32_t)r, (uint32_t)q);
             }
         }
-        if (hipMalloc(&p->d_wtab[i], tab.size() * 4) != hipSuccess) rc = set_error(LOLA_E_NOMEM, "table allocation");
-        else LOLA_HIP(hipMemcpy(p->d_wtab[i], tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
+        if (hipMalloc(&wtab[i], tab.size() * 4) != hipSuccess) rc = set_error(LOLA_E_NOMEM, "table allocation");
+        else if (hipMemcpy(wtab[i], tab.data(), tab.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            rc = set_error(LOLA_E_DEVICE, "table upload");
+    }
+    if (rc) {
+        release_new();
+        return rc;
     }
     (void)hipFree(d_slots);
     (void)hipFree(d_pt);
-    if (rc) return rc;
-    p->loaded_for = ctx;
+    // replace the previous constants: nothing bound or captured may refer to
+    // them afterwards (hipFree waits for the device)
     p->lanes[0].prog_valid = p->lanes[1].prog_valid = false;
     release_graph(p);
+    free_consts(p);
+    p->d_cmul.swap(cmul);
+    p->d_cadd.swap(cadd);
+    p->d_wtab.swap(wtab);
+    p->loaded_for = ctx;
     return LOLA_OK;
 }
 
