@@ -73,6 +73,84 @@ def ks_bytes(N, L):
     return 4 * N * (4 * L + 2 * L * (L + 1))
 
 
+def valu_probe_run(iters=4000, reps=3):
+    """The library's VALU probe: eight independent chains of one 32-bit
+    instruction per thread over the whole GPU, best of reps, as lane-ops/s
+    and as a fraction of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz."""
+    import torch
+    from paper_1812_10659_amd import lola
+    props = torch.cuda.get_device_properties(0)
+    out = {"metric": "VALU lane-instructions/s", "peak_lane_ops_per_s": PEAK_VALU_LANE_OPS,
+           "compute_units": props.multi_processor_count, "gpu": props.name, "rates": {}}
+    for op, name in enumerate(("v_mul_lo_u32", "v_mul_hi_u32", "v_add_u32")):
+        lola.valu_probe(op, 10)   # warm up
+        best = max(lola.valu_probe(op, iters) for _ in range(reps))
+        out["rates"][name] = {"lane_ops_per_s": round(best / 1e12, 3) * 1e12,
+                              "frac_of_peak": round(best / PEAK_VALU_LANE_OPS, 4)}
+    return out
+
+
+def inner_bytes(N, L):
+    """Algorithmic HBM bytes of the inner kernel per key switch: the key, the
+    digits D and permuted limbs X' in, the accumulators U and u_P out."""
+    return 8 * N * (L * (L + 1) + 2 * L + 1)
+
+
+def ks_ops(N, L):
+    """Algorithmic VALU lane-ops of one whole key switch: L digit INTTs, the
+    inner kernel's work, and 2L mod-down units of one NTT and ~10 ops a
+    coefficient."""
+    T = BFLY_OPS * (N // 2) * int(math.log2(N))
+    return L * T + ks_inner_ops(N, L) + 2 * L * (T + 10 * N)
+
+
+def kernel_table(stats, steps):
+    """Per timed kernel: launches, work units and the library's algorithmic
+    bytes and lane-ops per launch, the average event time of a launch, and
+    the fractions of the HBM and VALU peaks; the binding fraction is the
+    larger (the kernel's time against max(bytes / 8 TB/s, ops / 39.3 T))."""
+    out = {}
+    for name, k in sorted(stats.items(), key=lambda kv: -kv[1]["ms"]):
+        n = max(k["launches"], 1)
+        sec = k["ms"] / 1e3
+        hb = k["alg_bytes"] / sec / PEAK_HBM if sec > 0 else 0.0
+        va = k["alg_ops"] / sec / PEAK_VALU_LANE_OPS if sec > 0 else 0.0
+        out[name] = {"launches": k["launches"], "launches_per_step": round(k["launches"] / steps, 1),
+                     "units_per_launch": round(k["units"] / n, 2),
+                     "alg_bytes_per_launch": round(k["alg_bytes"] / n), "alg_ops_per_launch": round(k["alg_ops"] / n),
+                     "avg_launch_ms": round(k["ms"] / n, 5), "ms_per_step": round(k["ms"] / steps, 4),
+                     "hbm_frac": round(hb, 4), "valu_frac": round(va, 4),
+                     "bound": "hbm" if hb >= va else "alu", "binding_frac": round(max(hb, va), 4)}
+    return out
+
+
+KS_KERNELS = ("ks_digits_kernel", "ks_inner_kernel", "ks_moddown_kernel",
+              "ks_term_kernel", "ks_fold_kernel", "ks_term_direct_kernel", "ks_fold_moddown_kernel")
+
+
+def whole_keyswitch(stats, N, L):
+    """The whole key switch (digits, inner and mod-down kernels, or a small
+    launch's latency-form kernels) per job over all key switches of the timed
+    pass: time, algorithmic HBM GB/s and VALU fraction.  Hoisted rotations
+    run other kernels and are not counted here."""
+    names = [n for n in KS_KERNELS if n in stats]
+    jobs = sum(stats[n]["units"] for n in ("ks_inner_kernel", "ks_term_kernel", "ks_term_direct_kernel")
+               if n in stats)
+    ms = sum(stats[n]["ms"] for n in names)
+    if jobs == 0 or ms <= 0:
+        return None
+    sec = ms / 1e3
+    gbps = ks_bytes(N, L) * jobs / sec / 1e9
+    valu = ks_ops(N, L) * jobs / sec / PEAK_VALU_LANE_OPS
+    split = {n: round(stats[n]["ms"] / jobs * 1e3, 3) for n in names}
+    return {"jobs": jobs, "us_per_job": round(ms / jobs * 1e3, 3), "us_per_job_by_kernel": split,
+            "gbps": round(gbps, 1), "hbm_frac": round(gbps * 1e9 / PEAK_HBM, 4),
+            "ops_per_job": ks_ops(N, L), "valu_frac": round(valu, 4),
+            "bytes_per_job": ks_bytes(N, L),
+            "note": "4N(4L + 2L(L+1)) bytes (ciphertext in, key once, result out) and the three kernels' "
+                    "algorithmic lane-ops per key switch, over their summed HIP-event time"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,7 +176,13 @@ def main():
                          "or CPU section (for profiler runs whose per-kernel sums must cover that workload alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device once (scale for HBM counters) and exit")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only measure the 32-bit VALU issue rates (mul_lo, mul_hi, add) against the "
+                         "CU x SIMD x lane x clock peak and exit")
     args = ap.parse_args()
+    if args.valu_probe:
+        print(json.dumps(valu_probe_run()), flush=True)
+        return
     if args.calibrate_copy:
         import torch
         src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
@@ -145,25 +229,9 @@ def main():
     plan = lola.Plan(p, networks.mnist_layers(w))
     plan.load(ctx)
     plan.set_lanes(args.lanes)
-    gal = plan.galois()
+    from paper_1812_10659_amd import requests as rq
     B, C = args.batch, max(1, min(args.clients, args.batch))
-    keys = []
-    for c in range(C):
-        ks = wl.key_seed(1) + 7919 * c
-        sk = ctx.keygen_secret(ks)
-        pk = ctx.keygen_public(ks, sk)
-        keys.append(dict(sk=sk, pk=pk, rlk=ctx.keygen_switch(ks, sk, 0),
-                         gks=[ctx.keygen_switch(ks, sk, g) for g in gal]))
-    imap = plan.input_map()
-    reqs, images = [], []
-    for r in range(B):
-        img = wl.mnist_image(index=r)
-        images.append(img)
-        k = keys[r % C]
-        msgs = networks.pack_inputs(imap, networks.mnist_input_values(img))
-        ins = [ctx.encrypt(k["pk"], ctx.encode(m), wl.enc_seed(1) + r, i) for i, m in enumerate(msgs)]
-        reqs.append(dict(rlk=k["rlk"], gks=k["gks"], inputs=ins,
-                         outputs=[ctx.empty_ct() for _ in range(plan.info["n_outputs"])]))
+    reqs, keys, images = rq.mnist_batch(ctx, plan, B, C)
     torch.cuda.synchronize()
 
     # warmup (also binds the batch: descriptors uploaded once)
@@ -200,13 +268,11 @@ def main():
     torch.cuda.synchronize()
     elapsed_one_lane = time.perf_counter() - t1
     lola.timing_enable(ctx, False)
-    ks_ms, ks_launches, ks_jobs = lola.kernel_timing(ctx)
+    kstats = lola.kernel_stats(ctx)
 
-    # correctness spot check of the timed batch (first and last request)
-    for r in (0, B - 1):
-        k = keys[r % C]
-        slots = np.stack([ctx.decode(ctx.decrypt(k["sk"], o)) for o in reqs[r]["outputs"]])
-        got = networks.unpack_outputs(plan.output_map(), slots)
+    # every request of the timed batch decrypts to the plain network's logits
+    for r in range(B):
+        got = rq.decrypted_outputs(ctx, plan, keys[r % C]["sk"], reqs[r])
         exp = _plain_logits_mod_t(images[r], w, p.t)
         assert [int(v) for v in got] == [int(v) for v in exp], f"request {r}: decrypted logits differ"
 
@@ -282,15 +348,18 @@ def main():
 
     ms_per_step = elapsed / args.steps * 1e3
     value = B * args.steps / elapsed
+    kernels = kernel_table(kstats, args.steps)
+    inner = kstats.get("ks_inner_kernel", dict(ms=0.0, launches=0, units=0, alg_ops=0.0, alg_bytes=0.0))
+    ks_jobs, ks_launches, ks_ms = inner["units"], inner["launches"], inner["ms"]
     ops_per_job = ks_inner_ops(N, L)
     ks_avg_ms = ks_ms / max(ks_launches, 1)
     jobs_per_launch = ks_jobs / max(ks_launches, 1)
     achieved = ops_per_job * ks_jobs / (ks_ms / 1e3) if ks_ms > 0 else 0.0
-    ks_gbps = ks_bytes(N, L) * ks_jobs / (ks_ms / 1e3) / 1e9 if ks_ms > 0 else 0.0
+    whole_ks = whole_keyswitch(kstats, N, L)
     traffic = None
     if ks_inner_digest() == KS_INNER_TRAFFIC["digest"] and (B, C) == (64, 8):
         tb = (KS_INNER_TRAFFIC["fetch_per_job"] + KS_INNER_TRAFFIC["write_per_job"]) * jobs_per_launch
-        traffic = {"bytes_per_launch": round(tb), "algorithmic_bytes_per_launch": round(ks_bytes(N, L) * jobs_per_launch),
+        traffic = {"bytes_per_launch": round(tb), "algorithmic_bytes_per_launch": round(inner_bytes(N, L) * jobs_per_launch),
                    "gbps": round(tb / (ks_avg_ms / 1e3) / 1e9, 1)}
 
     out = {
@@ -337,8 +406,12 @@ def main():
                              f"lane so that each launch is timed alone "
                              f"({B * args.steps / elapsed_one_lane:.1f} inferences/s in that pass)"},
         "hbm": {"ntt_gbps": round(ntt_gbps, 1), "ntt_frac": round(ntt_gbps * 1e9 / PEAK_HBM, 4),
-                "keyswitch_gbps": round(ks_gbps, 1), "keyswitch_frac": round(ks_gbps * 1e9 / PEAK_HBM, 4),
-                "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job"},
+                "keyswitch_gbps": whole_ks and whole_ks["gbps"],
+                "keyswitch_frac": whole_ks and whole_ks["hbm_frac"],
+                "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job over the "
+                        "summed time of its three kernels (digits, inner, mod-down) in the timed pass"},
+        "keyswitch": whole_ks,
+        "kernels": kernels,
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
     headline_recipe = plan.info["recipe"]

@@ -367,6 +367,19 @@ typedef struct {
  * LOLA_E_UNSUPPORTED).  lola_compile = AUTO, THROUGHPUT. */
 enum { LOLA_OBJECTIVE_THROUGHPUT = 0, LOLA_OBJECTIVE_LATENCY = 1 };
 /* Candidates:
+ *  - Any other chain of DENSE and SQUARE layers (DENSE first, sizes <= N),
+ *    one query per message (Sec. 4.2.2): each dense layer takes the recipe
+ *    its input's representation calls for -- dense vector - row major on a
+ *    dense input (per row a product and a whole-message rotate-and-sum, so
+ *    every slot holds the output: one message per row, sparse), sparse
+ *    vector - column major on a sparse input (W v = sum_i v_i c^i: one
+ *    product per input with column i at slots 0..r-1, summed; dense output,
+ *    no rotation); a square squares every message.  DENSE_CHAIN: the client
+ *    sends one dense message (value i at slot i); SPARSE_COLUMN_MAJOR: the
+ *    client sends in_dim messages, message i holding value i in every slot
+ *    (input map).  Outputs: one message (value j at slot j) after a column
+ *    major layer, one message per value (at slot 0, and every other slot)
+ *    after a row major one.  Both can be forced on any such chain.
  *  - DENSE, SQUARE, DENSE with in_dim <= N/2 (Sec. 4.2.2): DENSE_ROW_MAJOR
  *    (dense vector - row major, N/period queries per message) or
  *    STACKED_ROW_MAJOR (stacked vector - row major, one query per message).
@@ -383,7 +396,8 @@ enum { LOLA_OBJECTIVE_THROUGHPUT = 0, LOLA_OBJECTIVE_LATENCY = 1 };
  *  - Everything else: FIXED. */
 enum { LOLA_RECIPE_AUTO = 0, LOLA_RECIPE_DENSE_ROW_MAJOR = 1, LOLA_RECIPE_STACKED_ROW_MAJOR = 2,
        LOLA_RECIPE_FIXED = 3 /* reported for patterns with a single recipe */,
-       LOLA_RECIPE_FULL_REDUCTION = 4, LOLA_RECIPE_SHARED_REDUCTION = 5 };
+       LOLA_RECIPE_FULL_REDUCTION = 4, LOLA_RECIPE_SHARED_REDUCTION = 5,
+       LOLA_RECIPE_DENSE_CHAIN = 6, LOLA_RECIPE_SPARSE_COLUMN_MAJOR = 7 };
 typedef struct {
     int32_t objective;
     int32_t recipe;
@@ -478,12 +492,58 @@ int lola_server_step(lola_server *srv, uint32_t *pending);
 /* Tags of requests completed since the last poll (at most cap). */
 int lola_server_poll(lola_server *srv, uint64_t *tags, uint32_t cap, uint32_t *n);
 
-/* Kernel timing (for measurement): when enabled, the library records HIP
- * events around every launch of the key-switching inner kernel (the
- * per-modulus NTT + key inner product) on the launch stream; the totals are
- * read with lola_kernel_timing (synchronises). */
+/* Kernel timing (for measurement).  While enabled, the library records a HIP
+ * event pair on the launch stream around every launch of its hot-path
+ * kernels: the batched NTT, each key-switch stage, the three product stages,
+ * the linear-combination and plaintext kernels and the persistent chain
+ * kernel.  Events between launches serialise them, so timed passes measure
+ * launches alone (plans then run one lane).  Both readers below synchronise
+ * on the recorded events, then clear every total. */
 int lola_timing_enable(lola_ctx *ctx, int on);
+/* The key-switch inner-product stage (ks_inner, or the latency forms'
+ * term/fold kernels): summed ms, launches, and key switches issued. */
 int lola_kernel_timing(lola_ctx *ctx, double *total_ms, uint64_t *launches, uint64_t *jobs);
+/* Per kernel: summed event time, launches, work units, and the algorithmic
+ * HBM bytes and VALU lane-ops the library charges for them.  Bytes count
+ * each distinct buffer a launch reads once (jobs of a batch share keys,
+ * sources and constants); lane-ops count every job's work.  Units and the
+ * charges (N ring degree, L ciphertext primes, T = 9 (N/2) log2 N lane-ops of
+ * one limb transform, K = 8N L(L+1) bytes of one switching key):
+ *   ntt_jobs_kernel          limb             8N B,  T
+ *   ks_digits_kernel         (job, digit)     12N B, T
+ *   ks_inner_kernel          job              K per distinct key + 8N (2L+1) B, (L^2+2) T + 14 L (L+1) N
+ *   ks_moddown_kernel        (job, prime, component)  16N B, T + 10N
+ *   ks_modup_kernel          source           8N L^2 B, L^2 T
+ *   ks_digits_kernel/hoist, ks_moddown_kernel/hoist: the same kernels run
+ *                            for hoisted rotations, charged as above
+ *   ks_hoisted_inner_kernel  rotation         K per distinct key + 4N L(L+1) per distinct
+ *                            source + 8N (L+1) B, 2T + 14 L (L+1) N
+ *   tensor_*_kernel, lin_kernel, plain_kernel, latency-form and chain
+ *   kernels: as documented at their launch sites.
+ * Writes at most cap entries (kernels with no launch are skipped) and sets
+ * *n_out to the number of kernels with launches; returns LOLA_E_INVAL when
+ * that exceeds cap.  `name` points to a static string. */
+typedef struct {
+    const char *name;
+    double total_ms;
+    uint64_t launches;
+    uint64_t units;
+    double alg_bytes;
+    double alg_ops;
+} lola_kernel_stat;
+int lola_kernel_stats(lola_ctx *ctx, lola_kernel_stat *out, uint32_t cap, uint32_t *n_out);
+
+/* VALU issue-rate probe, for stating the integer peak the kernels are
+ * measured against: op 0 v_mul_lo_u32, 1 v_mul_hi_u32, 2 v_add_u32, each
+ * thread running eight independent chains of `iters` x 16 steps of the one
+ * instruction, 8 workgroups of 256 threads per compute unit.  out_dev is a
+ * device buffer of out_words >= 2048 x (compute units) words that the probe
+ * overwrites (values meaningless).  *lane_ops_per_s receives the achieved
+ * rate (lane-instructions per second, HIP events on `stream`); synchronises.
+ * Errors: LOLA_E_INVAL (bad op, null pointer, iters 0), LOLA_E_SHAPE (buffer
+ * too small), LOLA_E_DEVICE. */
+int lola_valu_probe(int op, uint32_t iters, uint32_t *out_dev, uint32_t out_words, double *lane_ops_per_s,
+                    lola_stream stream);
 
 const char *lola_strerror(int code);
 const char *lola_last_error(void);

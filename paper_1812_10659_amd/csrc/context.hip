@@ -396,7 +396,10 @@ void lola_ctx_destroy(lola_ctx *ctx) {
                     (void *)ctx->d_ring})
         if (p) (void)hipFree(p);
     if (ctx->h_ring) (void)hipHostFree(ctx->h_ring);
-    for (hipEvent_t e : ctx->timing_events) (void)hipEventDestroy(e);
+    for (const lola::TimedLaunch &t : ctx->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
     for (hipEvent_t e : ctx->timing_pool) (void)hipEventDestroy(e);
     for (int i = 0; i < lola_ctx::RING_SLABS; ++i)
         if (ctx->ring_ev[i]) (void)hipEventDestroy(ctx->ring_ev[i]);

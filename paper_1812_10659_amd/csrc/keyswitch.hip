@@ -175,43 +175,86 @@ size_t ks_chunk_words(const lola_ctx *ctx, uint32_t chunk) {
     return std::max(ks_launch_words(ctx, chunk), ks_launch_words(ctx, std::min(chunk, KS_TERM_MAX_JOBS)));
 }
 
-int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
+// Algorithmic cost of each key-switch kernel per launch of n jobs (bytes,
+// lane-ops), with T the lane-ops of one limb transform:
+//   digits       per (job, digit): reads x_i, writes X'_i and D_i: 12N B; one INTT
+//   inner        per job: key 2L(L+1)N words, D and X' 2LN, U 2LN + 2N out;
+//                L^2 + 2 transforms and 2L(L+1)N multiply-accumulates
+//   moddown      per (job, prime, component): U, u_P, addend in, result out:
+//                16N B; one NTT and ~10 ops a coefficient
+//   term         per job: L(L+1) units, each a digit limb and two key limbs in,
+//                two terms out (20N B); L^2 transforms, 2L(L+1)N products
+//   fold         per job: 2(L+1) units, each L terms in and one limb out; the
+//                special prime's two also INTT
+//   term_direct  as term, plus each unit's digit INTT (i != j): 2 L^2 transforms
+//   fold_moddown per job: 2L units, each the 2L terms of its prime and of P and
+//                the addend in, one limb out; two transforms each
+//   modup        per source: L^2 units (i != j), each one limb in and out, one NTT
+//   hoisted      per rotation: key, the source's L(L+1) transformed digit limbs,
+//                U and u_P out; two INTTs and the multiply-accumulates
+// Bytes count each distinct key (2L(L+1)N words) and hoisting source's
+// transformed digits (L(L+1)N words) once per launch: jobs that share them
+// read them from HBM once.
+struct KsCost {
+    double N, L, T;
+    explicit KsCost(const lola_ctx *ctx) : N(ctx->N), L(ctx->L), T(xform_ops(ctx)) {}
+    double key_b() const { return 8 * N * L * (L + 1); }
+    double digits_b() const { return 12 * N; }
+    double inner_b(double n, double keys) const { return keys * key_b() + n * 8 * N * (2 * L + 1); }
+    double inner_o() const { return (L * L + 2) * T + 2 * COST_MAC * L * (L + 1) * N; }
+    double moddown_b() const { return 16 * N; }
+    double moddown_o() const { return T + 10 * N; }
+    double term_b() const { return 20 * N * L * (L + 1); }
+    double term_o() const { return L * L * T + 2 * COST_MUL * L * (L + 1) * N; }
+    double fold_b() const { return 8 * N * (L + 1) * (L + 1); }
+    double fold_o() const { return 2 * T + 2 * (L + 1) * L * N * COST_ADD; }
+    double direct_o() const { return 2 * L * L * T + 2 * COST_MUL * L * (L + 1) * N; }
+    double foldmd_b() const { return 16 * N * L * (L + 1); }
+    double foldmd_o() const { return 2 * L * (2 * T + 2 * L * N * COST_ADD + 10 * N); }
+    double modup_b() const { return 8 * N * L * L; }
+    double modup_o() const { return L * L * T; }
+    double hoist_b(double n, double keys, double srcs) const {
+        return keys * key_b() + srcs * 4 * N * L * (L + 1) + n * 8 * N * (L + 1);
+    }
+    double hoist_o() const { return 2 * T + 2 * COST_MAC * L * (L + 1) * N; }
+};
+
+int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, const uint64_t *aux, hipStream_t s) {
     if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
     const dim3 block(ctx->N / NTT_E);
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (ctx->timing) {
-        int rc = timing_pair(ctx, &t0, &t1);
-        if (rc) return rc;
-        ctx->timed_jobs += n;
-    }
+    const KsCost c(ctx);
+    if (ctx->timing) ctx->timed_jobs += n;
     const bool term = ks_term_mode(n), direct = term && ks_direct_mode(n, L);
 #define LOLA_KS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
         if (direct) {                                                                                        \
-            if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                         \
-            hipLaunchKernelGGL(ks_term_direct_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L,   \
-                               ctx->d_mc, ctx->d_tw, ctx->d_itw);                                             \
-            if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                         \
-            hipLaunchKernelGGL(ks_fold_moddown_kernel<LG>, dim3(n * 2 * L), block, 0, s, d_jobs, n, L,        \
-                               ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc);                                 \
+            LOLA_TIMED(ctx, s, KID_KS_TERM_DIRECT, n, c.term_b() * n, c.direct_o() * n,                       \
+                       hipLaunchKernelGGL(ks_term_direct_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, \
+                                          n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw));                           \
+            LOLA_TIMED(ctx, s, KID_KS_FOLD_MODDOWN, n, c.foldmd_b() * n, c.foldmd_o() * n,                    \
+                       hipLaunchKernelGGL(ks_fold_moddown_kernel<LG>, dim3(n * 2 * L), block, 0, s, d_jobs, n, \
+                                          L, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc));                  \
             break;                                                                                           \
         }                                                                                                    \
-        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L, ctx->d_mc,    \
-                           ctx->d_itw);                                                                       \
-        if (t0) LOLA_HIP(hipEventRecord(t0, s));                                                             \
+        LOLA_TIMED(ctx, s, KID_KS_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                           \
+                   hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L,    \
+                                      ctx->d_mc, ctx->d_itw));                                                \
         if (term) {                                                                                          \
-            hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, ctx->d_mc, \
-                               ctx->d_tw);                                                                    \
-            hipLaunchKernelGGL(ks_fold_kernel<LG>, dim3(n * 2 * (L + 1)), block, 0, s, d_jobs, n, L, ctx->d_mc,  \
-                               ctx->d_itw);                                                                   \
+            LOLA_TIMED(ctx, s, KID_KS_TERM, n, c.term_b() * n, c.term_o() * n,                                \
+                       hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, \
+                                          ctx->d_mc, ctx->d_tw));                                             \
+            LOLA_TIMED(ctx, s, KID_KS_FOLD, n, c.fold_b() * n, c.fold_o() * n,                                \
+                       hipLaunchKernelGGL(ks_fold_kernel<LG>, dim3(n * 2 * (L + 1)), block, 0, s, d_jobs, n, L, \
+                                          ctx->d_mc, ctx->d_itw));                                            \
         } else {                                                                                             \
-            hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L,      \
-                               ctx->d_mc, ctx->d_tw, ctx->d_itw);                                             \
+            LOLA_TIMED(ctx, s, KID_KS_INNER, n, c.inner_b(n, (double)aux[0]), c.inner_o() * n,                             \
+                       hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, \
+                                          L, ctx->d_mc, ctx->d_tw, ctx->d_itw));                              \
         }                                                                                                    \
-        if (t1) LOLA_HIP(hipEventRecord(t1, s));                                                             \
-        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, L,         \
-                           ctx->d_mc, ctx->d_tw, ctx->d_mrc);                                                 \
+        LOLA_TIMED(ctx, s, KID_KS_MODDOWN, n * 2 * L, c.moddown_b() * n * 2 * L, c.moddown_o() * n * 2 * L,    \
+                   hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, \
+                                      L, ctx->d_mc, ctx->d_tw, ctx->d_mrc));                                  \
         break;
     switch (ctx->logN) {
         LOLA_KS_CASE(10)
@@ -230,12 +273,15 @@ int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, h
     if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
     const dim3 block(ctx->N / NTT_E);
+    const KsCost c(ctx);
 #define LOLA_HS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
-        hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L, ctx->d_mc,    \
-                           ctx->d_itw);                                                                       \
-        hipLaunchKernelGGL(ks_modup_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, ctx->d_mc,  \
-                           ctx->d_tw);                                                                        \
+        LOLA_TIMED(ctx, s, KID_KS_HOIST_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                           \
+                   hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L,    \
+                                      ctx->d_mc, ctx->d_itw));                                                \
+        LOLA_TIMED(ctx, s, KID_KS_MODUP, n, c.modup_b() * n, c.modup_o() * n,                                 \
+                   hipLaunchKernelGGL(ks_modup_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L,    \
+                                      ctx->d_mc, ctx->d_tw));                                                 \
         break;
     switch (ctx->logN) {
         LOLA_HS_CASE(10)
@@ -250,16 +296,20 @@ int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, h
     return LOLA_OK;
 }
 
-int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
+int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, const uint64_t *aux,
+                               hipStream_t s) {
     if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
     const dim3 block(ctx->N / NTT_E);
+    const KsCost c(ctx);
 #define LOLA_HR_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
-        hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, L,  \
-                           ctx->d_mc, ctx->d_itw);                                                            \
-        hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, L,         \
-                           ctx->d_mc, ctx->d_tw, ctx->d_mrc);                                                 \
+        LOLA_TIMED(ctx, s, KID_KS_HOISTED_INNER, n, c.hoist_b(n, (double)aux[0], (double)aux[1]), c.hoist_o() * n, \
+                   hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, \
+                                      n, L, ctx->d_mc, ctx->d_itw));                                          \
+        LOLA_TIMED(ctx, s, KID_KS_HOIST_MODDOWN, n * 2 * L, c.moddown_b() * n * 2 * L, c.moddown_o() * n * 2 * L,    \
+                   hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, \
+                                      L, ctx->d_mc, ctx->d_tw, ctx->d_mrc));                                  \
         break;
     switch (ctx->logN) {
         LOLA_HR_CASE(10)

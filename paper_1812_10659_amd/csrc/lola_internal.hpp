@@ -44,6 +44,41 @@ struct MrcConst {
     uint32_t Pq[MAXL], Pqp[MAXL], Pinvq[MAXL], Pinvqp[MAXL];
 };
 
+// Kernels whose launches the library times when kernel timing is on, each
+// with its unit of work (what `units` counts) and the algorithmic HBM bytes and
+// VALU lane-ops the launch site charges per unit.
+enum KernelId : uint32_t {
+    KID_NTT,               // one limb transform
+    KID_KS_DIGITS,         // one (key switch, digit)
+    KID_KS_INNER,          // one key switch
+    KID_KS_MODDOWN,        // one (key switch, prime, component)
+    KID_KS_TERM,           // one key switch (latency form)
+    KID_KS_FOLD,           // one key switch (latency form)
+    KID_KS_TERM_DIRECT,    // one key switch (two-kernel latency form)
+    KID_KS_FOLD_MODDOWN,   // one key switch (two-kernel latency form)
+    KID_KS_MODUP,          // one hoisting source
+    KID_KS_HOISTED_INNER,  // one hoisted rotation
+    KID_TENSOR_EXTEND,     // one ciphertext pair
+    KID_TENSOR_PRODUCT,    // one ciphertext pair
+    KID_TENSOR_ROUND,      // one ciphertext pair
+    KID_LIN,               // one linear combination
+    KID_PLAIN,             // one plaintext product / add
+    KID_CHAIN,             // one rotation of the persistent chain kernel
+    KID_KS_HOIST_DIGITS,   // ks_digits_kernel for hoisting sources: one (source, digit)
+    KID_KS_HOIST_MODDOWN,  // ks_moddown_kernel for hoisted rotations: one (rotation, prime, component)
+    KID_COUNT
+};
+struct TimedLaunch {
+    uint32_t kid;
+    uint64_t units;
+    double bytes, ops;
+    hipEvent_t a, b;
+};
+struct KernelTotal {
+    double ms = 0, bytes = 0, ops = 0;
+    uint64_t launches = 0, units = 0;
+};
+
 }  // namespace lola
 
 // Prime index layout inside a context: [0, L) ciphertext primes, L = special
@@ -73,11 +108,13 @@ struct lola_ctx {
     size_t ring_off = 0;
     hipEvent_t ring_ev[RING_SLABS] = {};
     bool ring_ev_valid[RING_SLABS] = {};
-    // kernel timing (event pairs around the key-switch inner kernel)
+    // kernel timing: an event pair around every timed kernel launch, resolved
+    // into per-kernel totals when read
     bool timing = false;
-    std::vector<hipEvent_t> timing_events;   // pairs, in use
+    std::vector<lola::TimedLaunch> timed;    // launches not yet resolved
     std::vector<hipEvent_t> timing_pool;     // free events
-    uint64_t timed_jobs = 0;
+    lola::KernelTotal ktot[lola::KID_COUNT];
+    uint64_t timed_jobs = 0;                 // key switches issued while timing
     // batched NTT variant (index into the variant list of this N; 0 = default)
     uint32_t ntt_variant = 0;
     uint32_t idxP() const { return L; }
@@ -99,8 +136,33 @@ int check_hip(hipError_t e, const char *what);
 
 // scratch arena (device); grows with a device synchronisation
 int scratch_get(lola_ctx *ctx, size_t bytes, void **out);
-// a start/stop event pair for kernel timing (kept until lola_kernel_timing)
-int timing_pair(lola_ctx *ctx, hipEvent_t *a, hipEvent_t *b);
+// Kernel timing around one launch: ktime_begin records a start event when
+// timing is on (*a stays null otherwise); ktime_end records the stop event and
+// keeps the launch with its kernel id, units and algorithmic cost.
+int ktime_begin(lola_ctx *ctx, hipStream_t s, hipEvent_t *a);
+int ktime_end(lola_ctx *ctx, hipStream_t s, hipEvent_t a, uint32_t kid, uint64_t units, double bytes, double ops);
+#define LOLA_TIMED(ctx, s, kid, units, bytes, ops, ...)                                      \
+    do {                                                                                     \
+        hipEvent_t _ta = nullptr;                                                            \
+        if ((ctx)->timing) {                                                                 \
+            int _tr = ::lola::ktime_begin((ctx), (s), &_ta);                                 \
+            if (_tr) return _tr;                                                             \
+        }                                                                                    \
+        __VA_ARGS__;                                                                         \
+        if (_ta) {                                                                           \
+            int _tr = ::lola::ktime_end((ctx), (s), _ta, (kid), (units), (bytes), (ops));    \
+            if (_tr) return _tr;                                                             \
+        }                                                                                    \
+    } while (0)
+
+// Algorithmic cost conventions shared by the launch sites (VALU lane-ops):
+// a lazy Harvey butterfly is 9 ops (Shoup product 3 multiplies + 1 subtract,
+// add, subtract, one conditional correction of 2); a modular product 4; a
+// modular add or subtract 2; a key multiply-accumulate 7 (a Montgomery
+// product and an add, although the kernels accumulate in 64 bits and reduce
+// once).  A limb transform is 9 (N/2) log2 N.
+constexpr double COST_BFLY = 9, COST_MUL = 4, COST_ADD = 2, COST_MAC = 7;
+inline double xform_ops(const lola_ctx *ctx) { return COST_BFLY * (ctx->N / 2) * ctx->logN; }
 // descriptor upload area (device), copied asynchronously on the stream
 int desc_upload(lola_ctx *ctx, const void *host, size_t bytes, hipStream_t s, void **dev);
 

@@ -156,7 +156,9 @@ static int launch_ntt_any(lola_ctx *ctx, const NttJob *d_jobs, NttStrided sd, in
     const MrcConst *mrc = ctx->d_mrc;
     void *args[] = {(void *)&d_jobs, (void *)&nj, (void *)&mc, (void *)&tw, (void *)&itw, (void *)&t, (void *)&mrc,
                     (void *)&sd};
-    LOLA_HIP(hipLaunchKernel((const void *)v.fn, dim3((nj + v.lpw - 1) / v.lpw), dim3(ctx->N / NTT_E), args, 0, s));
+    LOLA_TIMED(ctx, s, KID_NTT, nj, 8.0 * ctx->N * nj, xform_ops(ctx) * nj,
+               LOLA_HIP(hipLaunchKernel((const void *)v.fn, dim3((nj + v.lpw - 1) / v.lpw), dim3(ctx->N / NTT_E),
+                                        args, 0, s)));
     return LOLA_OK;
 }
 

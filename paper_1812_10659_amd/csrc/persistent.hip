@@ -125,10 +125,17 @@ int lola_rotate_chains(lola_ctx *ctx, const lola_chain *chains, uint32_t n, uint
     const ChainStep *dst = (const ChainStep *)((uint8_t *)d + os);
     hipLaunchKernelGGL(chain_counter_reset, dim3(1), dim3(64), 0, s, counter);
     const dim3 block(ctx->N / NTT_E);
+    // cost per rotation: the ciphertext in and out and the key read once
+    // (4N (4L + 2L(L+1)) B); the digit INTTs, the inner stage and the mod-down
+    const double dN = ctx->N, dL = ctx->L, T = xform_ops(ctx);
+    const double rot_b = 4 * dN * (4 * dL + 2 * dL * (dL + 1));
+    const double rot_o = dL * T + (dL * dL + 2) * T + 2 * COST_MAC * dL * (dL + 1) * dN + 2 * dL * (T + 10 * dN);
+    const uint64_t rots = st.size();
 #define LOLA_CHAIN_CASE(LG)                                                                                  \
     case LG:                                                                                                 \
-        hipLaunchKernelGGL(chain_persistent_kernel<LG>, dim3(n_wg), block, 0, s, dcd, n, dst, counter, scr, per, \
-                           ctx->L, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc);                             \
+        LOLA_TIMED(ctx, s, KID_CHAIN, rots, rot_b * rots, rot_o * rots,                                      \
+                   hipLaunchKernelGGL(chain_persistent_kernel<LG>, dim3(n_wg), block, 0, s, dcd, n, dst, counter, \
+                                      scr, per, ctx->L, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc));       \
         break;
     switch (ctx->logN) {
         LOLA_CHAIN_CASE(10)

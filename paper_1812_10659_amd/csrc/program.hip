@@ -70,18 +70,31 @@ __global__ void plain_kernel(const PlainJob *__restrict__ jobs, uint32_t logN, u
     ((uint4 *)job.dst)[i] = x;
 }
 
-int launch_lin_dev(lola_ctx *ctx, const LinJob *d, uint32_t n, hipStream_t s) {
+// Cost: the launch's distinct sources and constants are read once (2LN and
+// LN words), every job writes its ciphertext; each source word of each job
+// takes a Shoup product and an add, each constant word an add.
+int launch_lin_dev(lola_ctx *ctx, const LinJob *d, uint32_t n, const uint64_t *aux, hipStream_t s) {
     const size_t n4 = (size_t)2 * ctx->L * ctx->N / 4;
-    hipLaunchKernelGGL(lin_kernel, dim3((unsigned)((n4 + 255) / 256), n), dim3(256), 0, s, d, ctx->logN, ctx->L,
-                       ctx->d_mc);
+    const double ln = (double)ctx->L * ctx->N;
+    LOLA_TIMED(ctx, s, KID_LIN, n, 4 * ln * (2.0 * (aux[1] + n) + aux[3]),
+               ln * (2.0 * aux[0] * (COST_MUL + COST_ADD) + aux[2] * COST_ADD),
+               hipLaunchKernelGGL(lin_kernel, dim3((unsigned)((n4 + 255) / 256), n), dim3(256), 0, s, d, ctx->logN,
+                                  ctx->L, ctx->d_mc));
     LOLA_HIP(hipGetLastError());
     return LOLA_OK;
 }
 
-int launch_plain_dev(lola_ctx *ctx, const PlainJob *d, uint32_t n, hipStream_t s) {
+// Cost: every job reads and writes one ciphertext; the launch's distinct
+// product and add constants (LN words) are read once; a product is a
+// Montgomery product per word of both components, an add one per word of
+// component 0.
+int launch_plain_dev(lola_ctx *ctx, const PlainJob *d, uint32_t n, const uint64_t *aux, hipStream_t s) {
     const size_t n4 = (size_t)2 * ctx->L * ctx->N / 4;
-    hipLaunchKernelGGL(plain_kernel, dim3((unsigned)((n4 + 255) / 256), n), dim3(256), 0, s, d, ctx->logN,
-                       ctx->L, ctx->d_mc);
+    const double ln = (double)ctx->L * ctx->N;
+    LOLA_TIMED(ctx, s, KID_PLAIN, n, 4 * ln * (4.0 * n + aux[1] + aux[3]),
+               ln * (2.0 * aux[0] * COST_MUL + aux[2] * COST_ADD),
+               hipLaunchKernelGGL(plain_kernel, dim3((unsigned)((n4 + 255) / 256), n), dim3(256), 0, s, d,
+                                  ctx->logN, ctx->L, ctx->d_mc));
     LOLA_HIP(hipGetLastError());
     return LOLA_OK;
 }
@@ -90,14 +103,14 @@ int program_run_launch(lola_ctx *ctx, const Launch &l, const uint8_t *d_blob, hi
     const void *d = d_blob + l.off;
     switch (l.kind) {
         case LK_NTT: return launch_ntt_jobs_dev(ctx, (const NttJob *)d, (int)l.n, s);
-        case LK_LIN: return launch_lin_dev(ctx, (const LinJob *)d, l.n, s);
-        case LK_PLAIN: return launch_plain_dev(ctx, (const PlainJob *)d, l.n, s);
-        case LK_KS: return launch_keyswitch(ctx, (const KsJob *)d, l.n, s);
+        case LK_LIN: return launch_lin_dev(ctx, (const LinJob *)d, l.n, l.aux, s);
+        case LK_PLAIN: return launch_plain_dev(ctx, (const PlainJob *)d, l.n, l.aux, s);
+        case LK_KS: return launch_keyswitch(ctx, (const KsJob *)d, l.n, l.aux, s);
         case LK_KS_HSRC: return launch_keyswitch_hoist_src(ctx, (const KsJob *)d, l.n, s);
-        case LK_KS_HROT: return launch_keyswitch_hoist_rot(ctx, (const KsJob *)d, l.n, s);
+        case LK_KS_HROT: return launch_keyswitch_hoist_rot(ctx, (const KsJob *)d, l.n, l.aux, s);
         case LK_MUL_EXTEND:
         case LK_MUL_PRODUCT:
-        case LK_MUL_ROUND: return launch_mul_stage(ctx, l.kind, (const MulJob *)d, l.n, s);
+        case LK_MUL_ROUND: return launch_mul_stage(ctx, l.kind, (const MulJob *)d, l.n, l.aux[0], s);
         default: return set_error(LOLA_E_INVAL, "bad launch kind");
     }
 }
@@ -118,20 +131,78 @@ int program_run_now(lola_ctx *ctx, const Program &p, hipStream_t s) {
     return program_run(ctx, p, (const uint8_t *)d, s);
 }
 
-int timing_pair(lola_ctx *ctx, hipEvent_t *a, hipEvent_t *b) {
-    for (int k = 0; k < 2; ++k) {
-        if (ctx->timing_pool.empty()) {
-            hipEvent_t e;
-            LOLA_HIP(hipEventCreate(&e));
-            ctx->timing_pool.push_back(e);
-        }
-        hipEvent_t e = ctx->timing_pool.back();
-        ctx->timing_pool.pop_back();
-        ctx->timing_events.push_back(e);
-        (k == 0 ? *a : *b) = e;
+static int pool_event(lola_ctx *ctx, hipEvent_t *e) {
+    if (ctx->timing_pool.empty()) {
+        hipEvent_t x;
+        LOLA_HIP(hipEventCreate(&x));
+        ctx->timing_pool.push_back(x);
     }
+    *e = ctx->timing_pool.back();
+    ctx->timing_pool.pop_back();
     return LOLA_OK;
 }
+
+int ktime_begin(lola_ctx *ctx, hipStream_t s, hipEvent_t *a) {
+    *a = nullptr;
+    if (!ctx->timing) return LOLA_OK;
+    hipEvent_t e;
+    int rc = pool_event(ctx, &e);
+    if (rc) return rc;
+    if (hipEventRecord(e, s) != hipSuccess) {
+        ctx->timing_pool.push_back(e);
+        return set_error(LOLA_E_DEVICE, "timing event");
+    }
+    *a = e;
+    return LOLA_OK;
+}
+
+int ktime_end(lola_ctx *ctx, hipStream_t s, hipEvent_t a, uint32_t kid, uint64_t units, double bytes, double ops) {
+    hipEvent_t b;
+    int rc = pool_event(ctx, &b);
+    if (rc) {
+        ctx->timing_pool.push_back(a);
+        return rc;
+    }
+    if (hipEventRecord(b, s) != hipSuccess) {
+        ctx->timing_pool.push_back(a);
+        ctx->timing_pool.push_back(b);
+        return set_error(LOLA_E_DEVICE, "timing event");
+    }
+    ctx->timed.push_back(TimedLaunch{kid, units, bytes, ops, a, b});
+    return LOLA_OK;
+}
+
+// Waits for every recorded launch and adds it to the per-kernel totals.
+static int resolve_timing(lola_ctx *ctx) {
+    int rc = LOLA_OK;
+    for (const TimedLaunch &t : ctx->timed) {
+        float ms = 0;
+        if (!rc && (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess))
+            rc = set_error(LOLA_E_DEVICE, "timing event");
+        KernelTotal &k = ctx->ktot[t.kid];
+        k.ms += ms;
+        k.launches += 1;
+        k.units += t.units;
+        k.bytes += t.bytes;
+        k.ops += t.ops;
+        ctx->timing_pool.push_back(t.a);
+        ctx->timing_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
+    return rc;
+}
+
+static void reset_timing(lola_ctx *ctx) {
+    for (KernelTotal &k : ctx->ktot) k = KernelTotal{};
+    ctx->timed_jobs = 0;
+}
+
+static const char *const KERNEL_NAMES[KID_COUNT] = {
+    "ntt_jobs_kernel",      "ks_digits_kernel",       "ks_inner_kernel",  "ks_moddown_kernel",
+    "ks_term_kernel",       "ks_fold_kernel",         "ks_term_direct_kernel", "ks_fold_moddown_kernel",
+    "ks_modup_kernel",      "ks_hoisted_inner_kernel", "tensor_extend_kernel", "tensor_product_kernel",
+    "tensor_round_kernel",  "lin_kernel",             "plain_kernel",     "chain_persistent_kernel",
+    "ks_digits_kernel/hoist", "ks_moddown_kernel/hoist"};
 
 }  // namespace lola
 
@@ -147,22 +218,34 @@ int lola_timing_enable(lola_ctx *ctx, int on) {
 
 int lola_kernel_timing(lola_ctx *ctx, double *total_ms, uint64_t *launches, uint64_t *jobs) {
     if (!ctx || !total_ms || !launches || !jobs) return set_error(LOLA_E_INVAL, "null argument");
+    int rc = resolve_timing(ctx);
+    // the key-switch inner-product stage in whichever form each launch took
     double tot = 0;
-    const size_t npairs = ctx->timing_events.size() / 2;
-    for (size_t k = 0; k < npairs; ++k) {
-        hipEvent_t a = ctx->timing_events[2 * k], b = ctx->timing_events[2 * k + 1];
-        LOLA_HIP(hipEventSynchronize(b));
-        float ms = 0;
-        LOLA_HIP(hipEventElapsedTime(&ms, a, b));
-        tot += ms;
+    uint64_t nl = 0;
+    for (uint32_t k : {KID_KS_INNER, KID_KS_TERM, KID_KS_FOLD, KID_KS_TERM_DIRECT}) {
+        tot += ctx->ktot[k].ms;
+        nl += k == KID_KS_FOLD ? 0 : ctx->ktot[k].launches;   // a term launch and its fold are one stage
     }
     *total_ms = tot;
-    *launches = npairs;
+    *launches = nl;
     *jobs = ctx->timed_jobs;
-    for (hipEvent_t e : ctx->timing_events) ctx->timing_pool.push_back(e);
-    ctx->timing_events.clear();
-    ctx->timed_jobs = 0;
-    return LOLA_OK;
+    reset_timing(ctx);
+    return rc;
+}
+
+int lola_kernel_stats(lola_ctx *ctx, lola_kernel_stat *out, uint32_t cap, uint32_t *n_out) {
+    if (!ctx || !n_out || (cap && !out)) return set_error(LOLA_E_INVAL, "null argument");
+    int rc = resolve_timing(ctx);
+    uint32_t n = 0;
+    for (uint32_t k = 0; k < KID_COUNT; ++k) {
+        const KernelTotal &t = ctx->ktot[k];
+        if (t.launches == 0) continue;
+        if (n < cap) out[n] = lola_kernel_stat{KERNEL_NAMES[k], t.ms, t.launches, t.units, t.bytes, t.ops};
+        ++n;
+    }
+    *n_out = n;
+    reset_timing(ctx);
+    return rc ? rc : (n > cap ? set_error(LOLA_E_INVAL, "more kernels than cap (n_out holds the count)") : LOLA_OK);
 }
 
 }  // extern "C"

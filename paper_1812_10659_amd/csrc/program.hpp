@@ -39,7 +39,53 @@ enum LaunchKind : uint32_t {
 struct Launch {
     uint32_t kind, n;
     size_t off;              // byte offset of the descriptors in the blob
+    uint64_t aux[4] = {0, 0, 0, 0};   // job counts for the algorithmic cost (launch_aux)
 };
+
+// What a launch's algorithmic cost depends on beyond its job count.  Bytes
+// count each distinct buffer a launch reads once (jobs of a batch share
+// sources, constants and keys, read from HBM once and then from cache);
+// lane-ops count every job's work.
+//   LinJob:   sum of n_src, distinct sources, jobs with a constant, distinct constants
+//   PlainJob: jobs with a product, distinct product constants, jobs with an add, distinct add constants
+//   MulJob:   squares (a == b: one operand extended and read)
+//   KsJob:    distinct keys, distinct hoisting sources
+template <class T, class F>
+inline uint64_t n_distinct(const std::vector<T> &v, F key) {
+    std::vector<const void *> k;
+    for (const T &j : v)
+        if (key(j)) k.push_back(key(j));
+    std::sort(k.begin(), k.end());
+    return (uint64_t)(std::unique(k.begin(), k.end()) - k.begin());
+}
+inline void launch_aux(const std::vector<LinJob> &v, uint64_t *a) {
+    std::vector<const void *> src;
+    for (const LinJob &j : v) {
+        a[0] += j.n_src;
+        a[2] += j.add != nullptr;
+        src.insert(src.end(), j.srcs, j.srcs + j.n_src);
+    }
+    std::sort(src.begin(), src.end());
+    a[1] = (uint64_t)(std::unique(src.begin(), src.end()) - src.begin());
+    a[3] = n_distinct(v, [](const LinJob &j) { return (const void *)j.add; });
+}
+inline void launch_aux(const std::vector<PlainJob> &v, uint64_t *a) {
+    for (const PlainJob &j : v) {
+        a[0] += j.mul != nullptr;
+        a[2] += j.add != nullptr;
+    }
+    a[1] = n_distinct(v, [](const PlainJob &j) { return (const void *)j.mul; });
+    a[3] = n_distinct(v, [](const PlainJob &j) { return (const void *)j.add; });
+}
+inline void launch_aux(const std::vector<MulJob> &v, uint64_t *a) {
+    for (const MulJob &j : v) a[0] += j.a == j.b;
+}
+inline void launch_aux(const std::vector<KsJob> &v, uint64_t *a) {
+    a[0] = n_distinct(v, [](const KsJob &j) { return (const void *)j.key; });
+    a[1] = n_distinct(v, [](const KsJob &j) { return (const void *)j.hoist; });
+}
+template <class T>
+inline void launch_aux(const std::vector<T> &, uint64_t *) {}
 
 struct Program {
     std::vector<uint8_t> blob;
@@ -60,7 +106,9 @@ struct Program {
     template <class T>
     void launch(LaunchKind k, const std::vector<T> &v) {
         if (v.empty()) return;
-        launches.push_back(Launch{(uint32_t)k, (uint32_t)v.size(), put(v)});
+        Launch l{(uint32_t)k, (uint32_t)v.size(), put(v)};
+        launch_aux(v, l.aux);
+        launches.push_back(l);
     }
 };
 
@@ -80,13 +128,13 @@ int program_run_launch(lola_ctx *ctx, const Launch &l, const uint8_t *d_blob, hi
 int program_run_now(lola_ctx *ctx, const Program &p, hipStream_t s);
 
 // Kernel launchers on device descriptor arrays.
-int launch_lin_dev(lola_ctx *ctx, const LinJob *d, uint32_t n, hipStream_t s);
-int launch_plain_dev(lola_ctx *ctx, const PlainJob *d, uint32_t n, hipStream_t s);
-int launch_keyswitch(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s);
+int launch_lin_dev(lola_ctx *ctx, const LinJob *d, uint32_t n, const uint64_t *aux, hipStream_t s);
+int launch_plain_dev(lola_ctx *ctx, const PlainJob *d, uint32_t n, const uint64_t *aux, hipStream_t s);
+int launch_keyswitch(lola_ctx *ctx, const KsJob *d, uint32_t n, const uint64_t *aux, hipStream_t s);
 // Hoisted rotations: sources (x = c1, scratch = hoist area, galois 1), then
 // rotations (hoist = the source's area, scratch = their own).
 int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s);
-int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s);
-int launch_mul_stage(lola_ctx *ctx, uint32_t stage, const MulJob *d, uint32_t n, hipStream_t s);
+int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d, uint32_t n, const uint64_t *aux, hipStream_t s);
+int launch_mul_stage(lola_ctx *ctx, uint32_t stage, const MulJob *d, uint32_t n, uint64_t n_squares, hipStream_t s);
 
 }  // namespace lola

@@ -150,18 +150,37 @@ __global__ void tensor_round_kernel(const MulJob *__restrict__ jobs, uint32_t N,
 
 size_t mul_scratch_words(const lola_ctx *ctx) { return mul_layout(ctx->L, ctx->nB, ctx->N).total; }
 
-int launch_mul_stage(lola_ctx *ctx, uint32_t stage, const MulJob *d, uint32_t n, hipStream_t s) {
+// Algorithmic cost per pair (a square extends and reads its operand once):
+//   extend   per input polynomial: L limbs in, nB out; Garner digits over Q
+//            (L(L-1)/2 products and subtracts), the sign test, and nB
+//            evaluations of L digits (a product and an add each)
+//   product  per limb of Q u B: the operands in, three limbs out; two Shoup
+//            and four Montgomery products and an add a coefficient
+//   round    per output polynomial: L + nB limbs in, L out; t d mod Q's
+//            digits, per b in B the evaluation, scaling and carry, the digits
+//            over B, and per q in Q the evaluation and sign correction
+int launch_mul_stage(lola_ctx *ctx, uint32_t stage, const MulJob *d, uint32_t n, uint64_t n_squares,
+                     hipStream_t s) {
     const uint32_t N = ctx->N, L = ctx->L, nB = ctx->nB;
     const MulLayout ml = mul_layout(L, nB, N);
+    const double dN = N, dL = L, dB = nB, polys = 4.0 * n - 2.0 * n_squares;
+    const double M = COST_MUL, A = COST_ADD;
     if (stage == LK_MUL_EXTEND)
-        hipLaunchKernelGGL(tensor_extend_kernel, dim3(N / 256, 4, n), dim3(256), 0, s, d, N, ml.Ac, ml.Bx,
-                           ctx->d_mc, ctx->d_mrc);
+        LOLA_TIMED(ctx, s, KID_TENSOR_EXTEND, n, polys * 4 * dN * (dL + dB),
+                   polys * dN * (dL * (dL - 1) / 2 * (M + A) + dL + dB * dL * (M + A)),
+                   hipLaunchKernelGGL(tensor_extend_kernel, dim3(N / 256, 4, n), dim3(256), 0, s, d, N, ml.Ac,
+                                      ml.Bx, ctx->d_mc, ctx->d_mrc));
     else if (stage == LK_MUL_PRODUCT)
-        hipLaunchKernelGGL(tensor_product_kernel, dim3(N / 256, L + nB, n), dim3(256), 0, s, d, N, L, nB, ml.Bx,
-                           ml.Dq, ml.Db, ctx->d_mc);
+        LOLA_TIMED(ctx, s, KID_TENSOR_PRODUCT, n, (polys + 3.0 * n) * 4 * dN * (dL + dB),
+                   n * dN * (dL + dB) * (6 * M + A),
+                   hipLaunchKernelGGL(tensor_product_kernel, dim3(N / 256, L + nB, n), dim3(256), 0, s, d, N, L,
+                                      nB, ml.Bx, ml.Dq, ml.Db, ctx->d_mc));
     else
-        hipLaunchKernelGGL(tensor_round_kernel, dim3(N / 256, 3, n), dim3(256), 0, s, d, N, ml.Dq, ml.Db, ml.Oc,
-                           ctx->d_mc, ctx->d_mrc);
+        LOLA_TIMED(ctx, s, KID_TENSOR_ROUND, n, 3.0 * n * 4 * dN * (2 * dL + dB),
+                   3.0 * n * dN * (dL * M + dL * (dL - 1) / 2 * (M + A) + dL + dB * (dL * (M + A) + 2 * M + 2 * A) +
+                                   dB * (dB - 1) / 2 * (M + A) + dB + dL * (dB * (M + A) + A)),
+                   hipLaunchKernelGGL(tensor_round_kernel, dim3(N / 256, 3, n), dim3(256), 0, s, d, N, ml.Dq, ml.Db,
+                                      ml.Oc, ctx->d_mc, ctx->d_mrc));
     LOLA_HIP(hipGetLastError());
     return LOLA_OK;
 }
@@ -204,12 +223,16 @@ void program_mul(const lola_ctx *ctx, Program &p, const std::vector<MulJob> &pai
             }
         }
         const size_t dj = p.put(jobs);
+        Launch ml_launch{LK_MUL_EXTEND, (uint32_t)m, dj};
+        launch_aux(jobs, ml_launch.aux);
         p.launch(LK_NTT, n1);
-        p.launches.push_back(Launch{LK_MUL_EXTEND, (uint32_t)m, dj});
+        p.launches.push_back(ml_launch);
         p.launch(LK_NTT, n2);
-        p.launches.push_back(Launch{LK_MUL_PRODUCT, (uint32_t)m, dj});
+        ml_launch.kind = LK_MUL_PRODUCT;
+        p.launches.push_back(ml_launch);
         p.launch(LK_NTT, n3);
-        p.launches.push_back(Launch{LK_MUL_ROUND, (uint32_t)m, dj});
+        ml_launch.kind = LK_MUL_ROUND;
+        p.launches.push_back(ml_launch);
         p.launch(LK_NTT, n4);
     }
 }

@@ -410,6 +410,7 @@ class _CompileOptions(ctypes.Structure):
 OBJECTIVE_THROUGHPUT, OBJECTIVE_LATENCY = 0, 1
 RECIPE_AUTO, RECIPE_DENSE_ROW_MAJOR, RECIPE_STACKED_ROW_MAJOR, RECIPE_FIXED = 0, 1, 2, 3
 RECIPE_FULL_REDUCTION, RECIPE_SHARED_REDUCTION = 4, 5
+RECIPE_DENSE_CHAIN, RECIPE_SPARSE_COLUMN_MAJOR = 6, 7
 
 
 class Request(ctypes.Structure):
@@ -443,6 +444,11 @@ def _params_struct(params):
     return _Params(params.N, params.t, len(params.q), q, params.P, int(getattr(params, "insecure_ok", False))), q
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("total_ms", ctypes.c_double), ("launches", ctypes.c_uint64),
+                ("units", ctypes.c_uint64), ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
+
+
 def _plan_sig():
     L = lib()
     if getattr(L, "_plan_sig_done", False):
@@ -465,6 +471,7 @@ def _plan_sig():
         "lola_timing_enable": [vp, ctypes.c_int],
         "lola_kernel_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                ctypes.POINTER(ctypes.c_uint64)],
+        "lola_kernel_stats": [vp, ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)],
         "lola_plan_destroy": [vp],
     }
     for name, args in sig.items():
@@ -578,3 +585,31 @@ def kernel_timing(ctx: "Context"):
     ms, n, j = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
     _check(_plan_sig().lola_kernel_timing(ctx.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(j)))
     return ms.value, n.value, j.value
+
+
+def kernel_stats(ctx: "Context") -> dict:
+    """Per timed kernel since the last read: {name: dict(ms, launches, units,
+    alg_bytes, alg_ops)} (the library's event times and algorithmic charges)."""
+    L = _plan_sig()
+    cap = 64
+    arr = (KernelStat * cap)()
+    n = ctypes.c_uint32()
+    _check(L.lola_kernel_stats(ctx.h, arr, cap, ctypes.byref(n)))
+    return {arr[i].name.decode(): dict(ms=arr[i].total_ms, launches=int(arr[i].launches), units=int(arr[i].units),
+                                       alg_bytes=arr[i].alg_bytes, alg_ops=arr[i].alg_ops)
+            for i in range(n.value)}
+
+
+def valu_probe(op: int, iters: int = 2000) -> float:
+    """Achieved lane-instructions per second of one 32-bit VALU instruction
+    kind (0 v_mul_lo_u32, 1 v_mul_hi_u32, 2 v_add_u32) over the whole GPU."""
+    L = lib()
+    f = L.lola_valu_probe
+    f.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
+                  ctypes.c_void_p]
+    f.restype = ctypes.c_int32
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    buf = torch.empty(2048 * cus, dtype=torch.int32, device="cuda")
+    rate = ctypes.c_double()
+    _check(f(int(op), int(iters), ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.byref(rate), _stream()))
+    return rate.value
