@@ -285,7 +285,7 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
     out["rotations_wavewise"] = {"ms": round(s_w * 1e3, 2), "rot_per_s": round(rot / s_w, 1),
                                  "rounds": int(counts.max()), "equal_to_persistent": same}
     out["_tensors"] = dict(ctx=ctx, cts=cts, pts=pts, prod=prod, t3=t3, rl=rl, outs=pers, steps=raw_steps,
-                           rlk=rlk, keys=keys, sk=sk, slots=slots, seed=seed)
+                           rlk=rlk, keys=keys, sk=sk, slots=slots, seed=seed, ntt_fwd=ref)
     return out
 
 

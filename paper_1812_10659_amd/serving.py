@@ -4,8 +4,10 @@ queries, several resident client key sets per ring size).
 
 The driver submits requests at their arrival times, steps the server
 (continuous batching across requests and ring sizes), measures each request's
-latency from arrival to observed completion, checks a sample of served
-results word for word against the same request evaluated alone, and replays
+latency from arrival to observed completion, checks every served result word
+for word against the reference words of its (client, input set) -- that
+pair evaluated alone once -- and a sample against the same request evaluated
+alone again afterwards, and replays
 the same arrival trace through the one-request-at-a-time GPU path for
 comparison.  Argument marshalling and bookkeeping only: all homomorphic work
 runs in the library.
@@ -124,8 +126,11 @@ class ModelSetup:
         imap = self.plan.input_map()
         self.keys, self.inputs, self.values = [], [], []
         base = wl.workload_seed(4) * 31 + (1 if kind == "mnist" else 2)
+        self.key_seeds, self.enc_seeds = [], []
         for c in range(clients):
             ks = base + 1009 * c
+            self.key_seeds.append(ks)
+            self.enc_seeds.append([ks + 7 * k + 3 for k in range(inputs_per_client)])
             sk = self.ctx.keygen_secret(ks)
             pk = self.ctx.keygen_public(ks, sk)
             self.keys.append(dict(sk=sk, rlk=self.ctx.keygen_switch(ks, sk, 0),
@@ -142,6 +147,7 @@ class ModelSetup:
                 vals.append(v)
             self.inputs.append(sets)
             self.values.append(vals)
+        self._refs = {}
         n_out = self.plan.info["n_outputs"]
         self.free_outputs = [[self.ctx.empty_ct() for _ in range(n_out)] for _ in range(out_pool)]
 
@@ -149,10 +155,22 @@ class ModelSetup:
         k = self.keys[client]
         return dict(rlk=k["rlk"], gks=k["gks"], inputs=self.inputs[client][which], outputs=outputs)
 
+    def reference(self, client: int, which: int):
+        """The output words of (client, input set) evaluated alone, computed
+        once and kept."""
+        key = (client, which)
+        if key not in self._refs:
+            outs = [self.ctx.empty_ct() for _ in range(self.plan.info["n_outputs"])]
+            self.plan.evaluate(self.ctx, [self.request(client, which, outs)])
+            torch.cuda.synchronize()
+            self._refs[key] = outs
+        return self._refs[key]
+
 
 def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, clients: int = 8,
                 max_inflight: int = 64, hbm_budget_gb: float = 96.0, check_every: int = 50,
-                baseline: bool = True, seed: int | None = None) -> dict:
+                baseline: bool = True, seed: int | None = None, check_all: bool = True,
+                keep_models: bool = False) -> dict:
     assert torch.cuda.is_available()
     arrivals, kinds = wl.serving_arrivals(n_req, rate, p_large, seed)
     g = wl.rng(wl.workload_seed(4) if seed is None else seed, 9)
@@ -164,11 +182,15 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
     srv = Server(int(hbm_budget_gb * (1 << 30)))
     mids = {k: srv.add_model(m.ctx, m.plan, max_inflight) for k, m in models.items()}
     kind_name = lambda k: "mnist" if k == 1 else "dense64"  # noqa: E731
-    out_of, latency, served_copy = {}, np.zeros(n_req), {}
+    out_of, latency, served_copy, kept = {}, np.zeros(n_req), {}, {}
     pending = []          # arrived but waiting for an output buffer
+    copying = []          # (event, model, buffers): returned to the pool once their copies are done
     nxt, done = 0, 0
     t0 = time.perf_counter()
     while done < n_req:
+        while copying and copying[0][0].query():
+            _, m, bufs = copying.pop(0)
+            m.free_outputs.append(bufs)
         now = time.perf_counter() - t0
         while nxt < n_req and arrivals[nxt] <= now:
             pending.append(nxt)
@@ -187,11 +209,25 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
         for tag in srv.poll():
             latency[tag] = time.perf_counter() - t0 - arrivals[tag]
             m = models[kind_name(kinds[tag])]
+            bufs = out_of.pop(tag)
+            copied = False
             if tag % check_every == 0:
-                served_copy[tag] = [o.clone() for o in out_of[tag]]
-            m.free_outputs.append(out_of.pop(tag))
+                served_copy[tag] = [o.clone() for o in bufs]
+                copied = True
+            if check_all:
+                kept[tag] = [o.clone() for o in bufs]
+                copied = True
+            if copied:
+                # the copies run on torch's stream, which does not order with
+                # the server's streams: the buffers go back to the pool (and
+                # to a later request) only once the copies have completed
+                ev = torch.cuda.Event()
+                ev.record()
+                copying.append((ev, m, bufs))
+            else:
+                m.free_outputs.append(bufs)
             done += 1
-        if inflight == 0 and not pending and nxt < n_req:
+        if inflight == 0 and not pending and not copying and nxt < n_req:
             time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))
     wall = time.perf_counter() - t0
     torch.cuda.synchronize()
@@ -203,6 +239,12 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
         m.plan.evaluate(m.ctx, [m.request(int(client_of[tag]), int(input_of[tag]), alone)])
         torch.cuda.synchronize()
         mismatches += sum(0 if torch.equal(a, b) else 1 for a, b in zip(alone, outs))
+    # every served result equals its (client, input set)'s reference words
+    ref_mismatches = 0
+    for tag, outs in kept.items():
+        ref = models[kind_name(kinds[tag])].reference(int(client_of[tag]), int(input_of[tag]))
+        ref_mismatches += sum(0 if torch.equal(a, b) else 1 for a, b in zip(ref, outs))
+    kept.clear()
     res = {
         "requests": n_req, "rate_per_s": rate, "wall_s": round(wall, 3),
         "inferences_per_s": round(n_req / wall, 2),
@@ -210,6 +252,8 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
         "p99_ms": round(float(np.percentile(latency, 99)) * 1e3, 2),
         "by_model": {},
         "checked_alone_vs_mixed": len(served_copy), "mismatches": mismatches,
+        "checked_vs_reference": n_req if check_all else 0, "reference_mismatches": ref_mismatches,
+        "references": {k: len(m._refs) for k, m in models.items()},
         "slots": {k: srv.model_info(v)["slots"] for k, v in mids.items()},
         "scratch_bytes": {k: srv.model_info(v)["scratch_bytes"] for k, v in mids.items()},
     }
@@ -222,6 +266,8 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
     srv.close()
     if baseline:
         res["one_at_a_time"] = one_at_a_time(models, arrivals, kinds, client_of, input_of)
+    if keep_models:
+        res["_models"] = models
     return res
 
 

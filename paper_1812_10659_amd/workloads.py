@@ -21,7 +21,8 @@ import numpy as np
 PRIMES_4096 = [1073692673, 1073668097, 1073651713, 1073643521, 1073569793,
                1073479681, 1073430529, 1073299457]
 PRIMES_16384 = [1073643521, 1073479681, 1073184769, 1073053697, 1072857089,
-                1072496641, 1071513601, 1071415297, 1071087617, 1070727169]
+                1072496641, 1071513601, 1071415297, 1071087617, 1070727169,
+                1070432257, 1069219841, 1068564481]
 
 # Classical 128-bit security caps on log2(Q*P) for a ternary secret, per ring
 # degree (the homomorphic-encryption security standard's table).
@@ -61,6 +62,9 @@ PARAMS: Dict[str, ParamSet] = {
     "cifar_n16384": ParamSet("cifar_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
     # Transfer-learning head: six data primes.
     "head_n16384": ParamSet("head_n16384", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
+    # The largest ciphertext-prime count the library accepts: twelve data
+    # primes (log2(QP) = 390 <= 438), for tests at that limit.
+    "l12_n16384": ParamSet("l12_n16384", 16384, 1146881, tuple(PRIMES_16384[:12]), PRIMES_16384[12]),
     # N=8192 for tests of that ring size: five data primes, log2(QP) = 180 <= 218.
     "n8192": ParamSet("n8192", 8192, 65537, tuple(PRIMES_16384[:5]), PRIMES_16384[5]),
     # Small sets for tests (not secure; flagged).

@@ -163,19 +163,53 @@ def test_head_stacked_recipe_truncated_matches_oracle():
     _run_and_compare(env, sched, nw.head_plain(f[0], wt))
 
 
-def test_head_network_full_size_decrypts_to_network():
-    """Full 4096 -> 256 -> 10 head with 4 queries per ciphertext: the oracle's
-    ciphertext run is too slow here, so the check is the exact decrypted
-    result against the plaintext network (mod t)."""
-    import torch
+@pytest.mark.timeout(900)
+def test_head_network_full_size_matches_oracle():
+    """Full 4096 -> 256 -> 10 head with 4 queries per ciphertext (dense vector
+    - row major, 3407 rotations): ciphertext words against the oracle's
+    schedule, and the decrypted results against the plaintext network."""
     from paper_1812_10659_amd import networks
     w, f = wl.head_weights(), wl.head_features(4)
-    print("[gpu-net] head, full", flush=True)
-    env = _setup("head_n16384", networks.head_layers(w), None, f, wl.key_seed(3), wl.enc_seed(3), with_oracle=False)
-    env["plan"].evaluate(env["ctx"], [env["req"]])
-    torch.cuda.synchronize()
+    print("[gpu-net] head, full size, dense recipe (oracle: ~3400 rotations)", flush=True)
+    sched = nw.head_schedule(w)
+    env = _setup("head_n16384", networks.head_layers(w), sched, f, wl.key_seed(3), wl.enc_seed(3))
     expected = np.concatenate([nw.head_plain(f[q], w) for q in range(4)])
-    assert list(_decrypt_values(env)) == list(nw._mod(expected, env["p"].t))
+    _run_and_compare(env, sched, expected)
+
+
+@pytest.mark.timeout(900)
+def test_head_stacked_recipe_full_size_matches_oracle():
+    """The full head compiled with the stacked vector - row major recipe (one
+    query per message), ciphertext words against the oracle's schedule."""
+    from paper_1812_10659_amd import lola, networks
+    w, f = wl.head_weights(), wl.head_features(1)
+    print("[gpu-net] head, full size, stacked recipe", flush=True)
+    sched = nw.head_stacked_schedule(w)
+    env = _setup("head_n16384", networks.head_layers(w), sched, f[0], wl.key_seed(3) + 2, wl.enc_seed(3) + 2,
+                 recipe=lola.RECIPE_STACKED_ROW_MAJOR)
+    assert env["plan"].info["n_rotations"] == sched.count("rotate")
+    _run_and_compare(env, sched, nw.head_plain(f[0], w))
+
+
+@pytest.mark.parametrize("recipe,sparse", [(6, False), (7, True)])
+def test_dense_chain_matches_oracle(recipe, sparse):
+    """DENSE 64->32, SQUARE, DENSE 32->16, SQUARE, DENSE 16->10 on one query:
+    dense vector - row major on dense inputs and sparse vector - column major
+    on sparse ones (Sec. 4.2.2), ciphertext words against the oracle."""
+    from paper_1812_10659_amd import lola
+    rs = wl.rng(31, 3)
+    dims = [64, 32, 16, 10]
+    Ws = [rs.integers(-128, 128, (dims[i + 1], dims[i])) for i in range(3)]
+    bs = [rs.integers(-1000, 1000, dims[i + 1]) for i in range(3)]
+    layers = [lola.dense(Ws[0], bs[0]), lola.square(), lola.dense(Ws[1], bs[1]), lola.square(),
+              lola.dense(Ws[2], bs[2])]
+    ol = [("dense", Ws[0], bs[0]), ("square",), ("dense", Ws[1], bs[1]), ("square",), ("dense", Ws[2], bs[2])]
+    x = rs.integers(-128, 128, 64)
+    print(f"[gpu-net] dense chain, recipe {recipe}", flush=True)
+    sched = nw.dense_chain_schedule(ol, 16384, sparse)
+    env = _setup("mnist_n16384", layers, sched, x, wl.key_seed(6) + recipe, wl.enc_seed(6) + recipe, recipe=recipe)
+    assert env["plan"].info["recipe"] == recipe
+    _run_and_compare(env, sched, nw.dense_chain_plain(x, ol))
 
 
 def test_batched_requests_equal_single_and_graph_replay():

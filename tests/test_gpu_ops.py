@@ -8,7 +8,7 @@ from paper_1812_10659_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PSETS = ["toy1024", "toy2048", "n4096_3q", "n8192", "mnist_n16384"]
+PSETS = ["toy1024", "toy2048", "n4096_3q", "n8192", "mnist_n16384", "l12_n16384"]
 STEPS = [1, -1, 7, bfv.ROW_SWAP]
 SEED = 0x5EED_0001
 

@@ -1,7 +1,12 @@
 """Serving loop on the GPU: a mixed stream of N=16384 and N=4096 requests with
 continuous batching; every served result equals the same request evaluated
-alone, word for word."""
+alone, word for word, and the reference words of each (client, input set)
+equal the oracle's ciphertext run."""
+import numpy as np
 import pytest
+
+from oracle import bfv
+from oracle import network as nw
 
 pytestmark = pytest.mark.gpu
 
@@ -13,7 +18,37 @@ def test_serving_mixed_stream_equals_alone():
                               check_every=1, baseline=False)
     assert res["checked_alone_vs_mixed"] == 48
     assert res["mismatches"] == 0
+    assert res["checked_vs_reference"] == 48 and res["reference_mismatches"] == 0
     assert res["slots"]["mnist"] >= 1 and res["slots"]["dense64"] >= 1
+
+
+@pytest.mark.timeout(600)
+def test_serving_references_match_oracle():
+    """A mixed stream in which every served result is compared with the
+    reference words of its (client, input set); each reference used is then
+    pinned to the oracle's run of the same schedule under the same keys and
+    encryption seeds."""
+    from paper_1812_10659_amd import lola, networks, serving
+    print("[gpu-serve] 40 requests, every result against its oracle-pinned reference", flush=True)
+    res = serving.run_serving(n_req=40, rate=400.0, clients=3, max_inflight=8, hbm_budget_gb=24,
+                              check_every=1000, baseline=False, keep_models=True)
+    models = res.pop("_models")
+    assert res["checked_vs_reference"] == 40 and res["reference_mismatches"] == 0
+    for kind, m in models.items():
+        assert m._refs, kind
+        sched = nw.mnist_schedule(m.w, recipe="shared") if kind == "mnist" else nw.dense64_schedule(m.W)
+        octx = bfv.Context(m.p)
+        okeys = {}
+        for (c, k), outs in sorted(m._refs.items()):
+            print(f"[gpu-serve] {kind} client {c} input {k} against the oracle", flush=True)
+            if c not in okeys:
+                okeys[c] = bfv.keygen(octx, m.key_seeds[c], nw.galois_elements(sched))
+            msgs = networks.pack_inputs(m.plan.input_map(), m.values[c][k])
+            octs = [bfv.encrypt(octx, okeys[c], bfv.encode(octx, x), m.enc_seeds[c][k], i) for i, x in enumerate(msgs)]
+            oouts, _ = nw.run_ciphertexts(octx, okeys[c], sched, octs)
+            for j, (g, o) in enumerate(zip(outs, oouts)):
+                got = lola.to_numpy_u32(m.ctx.to_coeff(g)).astype(np.uint64)
+                assert np.array_equal(got, np.stack(o)), f"{kind} client {c} input {k} output {j}"
 
 
 def test_serving_two_lane_rounds_equal_alone():
@@ -26,6 +61,7 @@ def test_serving_two_lane_rounds_equal_alone():
                               check_every=1, baseline=False)
     assert res["checked_alone_vs_mixed"] == 64
     assert res["mismatches"] == 0
+    assert res["checked_vs_reference"] == 64 and res["reference_mismatches"] == 0
     assert res["slots"]["mnist"] == 32 and res["slots"]["dense64"] == 32
     # one lane's scratch, from a model granted a single slot
     for name in ("mnist", "dense64"):
