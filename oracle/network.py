@@ -579,6 +579,91 @@ def cifar_schedule(wts, n_in: int, N: int = 16384) -> Schedule:
     return Schedule(N, C * k1 * k1, b.ops, outs, [{0: f"logit{o}"} for o in range(len(outs))])
 
 
+# Chains of dense layers and squares on one query, with the two recipes that
+# take a vector in one representation and give it in the other (Sec. 4.2.2):
+# dense vector - row major turns a dense input into a sparse output, sparse
+# vector - column major turns a sparse input into a dense output.
+def dense_chain_plain(x, layers):
+    """The plaintext network on integers: layers are ("dense", W, b) (b may be
+    None) and ("square",)."""
+    a = np.asarray(x, dtype=np.int64).astype(object)
+    for ly in layers:
+        if ly[0] == "square":
+            a = a * a
+        else:
+            W = np.asarray(ly[1], dtype=np.int64).astype(object)
+            a = W.dot(a)
+            if ly[2] is not None:
+                a = a + np.asarray(ly[2], dtype=np.int64).astype(object)
+    return a
+
+
+def _dense_row_major_full(b: _Builder, src: int, W, bias, N: int) -> List[int]:
+    """Dense vector - row major (Sec. 4.2.2) with the output in sparse form:
+    per row j, the product with row j (value W[j, i] at slot i), then a
+    rotate-and-sum over 1, 2, ..., N/4 and the row swap, after which every
+    slot holds the dot product; the bias is added in every slot.  One message
+    per row."""
+    full = [1 << i for i in range(_log2(N // 2))] + [ROW_SWAP]
+    outs = []
+    for j in range(W.shape[0]):
+        z = b.emit("mul_plain", b.reg(), src, {i: int(W[j, i]) for i in range(W.shape[1])})
+        z = _rotate_and_sum(b, z, full)
+        if bias is not None:
+            z = b.emit("add_plain", b.reg(), z, {s: int(bias[j]) for s in range(N)})
+        outs.append(z)
+    return outs
+
+
+def _sparse_column_major(b: _Builder, srcs: Sequence[int], W, bias) -> int:
+    """Sparse vector - column major (Sec. 4.2.2): value i of the input is the
+    message srcs[i] with v_i in every slot, so W v = sum_i v_i c^i is one
+    product of message i with column i (value W[j, i] at slot j) per input
+    and the sum of the products; the bias is added at slots 0..r-1.  The
+    result is dense: value j at slot j, zero elsewhere."""
+    acc = None
+    for i, s in enumerate(srcs):
+        t = b.emit("mul_plain", b.reg(), s, {j: int(W[j, i]) for j in range(W.shape[0])})
+        acc = t if acc is None else b.emit("add", b.reg(), acc, t)
+    if bias is not None:
+        acc = b.emit("add_plain", b.reg(), acc, {j: int(bias[j]) for j in range(W.shape[0])})
+    return acc
+
+
+def dense_chain_inputs(x, N: int, sparse_input: bool):
+    """Client side: the dense representation (value i at slot i, one message)
+    or the sparse one (message i with x_i in every slot)."""
+    x = np.asarray(x, dtype=np.int64)
+    if sparse_input:
+        return [{s: int(v) for s in range(N)} for v in x]
+    return [{i: int(v) for i, v in enumerate(x)}]
+
+
+def dense_chain_schedule(layers, N: int, sparse_input: bool) -> Schedule:
+    """Each dense layer takes the recipe its input's representation calls
+    for: sparse vector - column major on a sparse input (k products, no
+    rotation, dense result), dense vector - row major on a dense input (a
+    full rotate-and-sum per row, sparse result); a square acts on every
+    message of the representation.  The outputs are the r messages of a
+    sparse result (value j in every slot of message j) or the one message of
+    a dense result (value j at slot j)."""
+    k = np.asarray(layers[0][1]).shape[1]
+    b = _Builder(N, k if sparse_input else 1)
+    regs, sparse = (list(range(k)), True) if sparse_input else ([0], False)
+    for ly in layers:
+        if ly[0] == "square":
+            regs = [b.emit("square", b.reg(), r) for r in regs]
+            continue
+        W = np.asarray(ly[1], dtype=np.int64)
+        if sparse:
+            regs, sparse = [_sparse_column_major(b, regs, W, ly[2])], False
+        else:
+            regs, sparse = _dense_row_major_full(b, regs[0], W, ly[2], N), True
+    r = len(regs) if sparse else np.asarray([ly for ly in layers if ly[0] == "dense"][-1][1]).shape[0]
+    out_slots = [{0: f"y{j}"} for j in range(r)] if sparse else [{j: f"y{j}" for j in range(r)}]
+    return Schedule(N, b.n_inputs, b.ops, regs, out_slots)
+
+
 # Transfer-learning head (N = 16384, 4 queries per ciphertext, query q in the
 # 4096-slot block starting at slot 4096 q).
 HEAD_BLOCK = 4096

@@ -23,7 +23,15 @@
 //     collects every occupied slot into slot 0 (sparse output);
 //   dense vector - row major (Sec. 4.2.2): per output row, product with the
 //     row in every query block, rotate-and-sum over the block, mask, then
-//     combination into an interleaved vector (value j of query q at P*q + j).
+//     combination into an interleaved vector (value j of query q at P*q + j);
+//     in chains of dense layers, the row's product summed over the whole
+//     message (rotations 1 .. N/4 and the row swap) so that every slot holds
+//     the output: one message per row (sparse output);
+//   sparse vector - column major (Sec. 4.2.2): on a sparse input (message i
+//     holds v_i in every slot), W v = sum_i v_i c^i, one product of message i
+//     with column i laid out at slots 0..r-1 per input, summed: a dense
+//     output with no rotation.  The two-convolution network's gather of its
+//     sparse outputs into one message is this recipe with W = I.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -147,6 +155,13 @@ struct Builder {
             k += m;
         }
         return acc;
+    }
+    // Sparse vector - column major: one term v_i c^i (the sparse message of
+    // input i times column i as a plaintext), then the sum of the terms with
+    // an optional add-form constant (the bias at the output slots).
+    int column_term(int sparse_src, std::vector<int64_t> column) { return mulplain(sparse_src, cst(std::move(column), true)); }
+    int column_sum(const std::vector<int> &terms, int cadd) {
+        return lincomb_any(terms, std::vector<int64_t>(terms.size(), 1), cadd);
     }
     int combine_tree(std::vector<int> regs, int32_t unit) {
         int32_t stride = unit;
@@ -778,13 +793,15 @@ int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n
         }
         int z = parts.size() == 1 ? parts[0] : b.lincomb_any(parts, std::vector<int64_t>(parts.size(), 1), -1);
         z = b.rotate_and_sum(z, full);
+        // the sparse outputs into one dense message: sparse vector - column
+        // major with W = I (column j one-hot at slot j)
         auto onehot = b.zeros();
         onehot[j] = 1;
-        gathered.push_back(b.mulplain(z, b.cst(onehot, true)));
+        gathered.push_back(b.column_term(z, std::move(onehot)));
         bias2[j] = bias_at(c2, mo);
     }
-    // the sparse outputs into one dense message (+ all biases at once)
-    int h = b.lincomb_any(gathered, std::vector<int64_t>(gathered.size(), 1), c2.bias ? b.cst(bias2, false) : -1);
+    // (+ all biases at once)
+    int h = b.column_sum(gathered, c2.bias ? b.cst(bias2, false) : -1);
     h = b.square(h);
     std::vector<int32_t> steps;
     for (uint32_t s = 1; s < next_pow2((uint32_t)H); s *= 2) steps.push_back((int32_t)s);
@@ -806,17 +823,129 @@ int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n
     return LOLA_OK;
 }
 
+// Chains of DENSE and SQUARE layers on one query, each dense layer taking the
+// recipe its input's representation calls for: sparse vector - column major
+// on a sparse input (dense result, no rotation), dense vector - row major
+// with a whole-message sum per row on a dense input (sparse result, one
+// message per row); a square acts on every message.  sparse_input: the
+// client sends value i as message i with v_i in every slot, so the first
+// layer is column major (LOLA_RECIPE_SPARSE_COLUMN_MAJOR); otherwise one
+// dense message, value i at slot i (LOLA_RECIPE_DENSE_CHAIN).
+static bool is_dense_chain(const lola_layer *ls, uint32_t n) {
+    if (n == 0 || ls[0].kind != LOLA_LAYER_DENSE) return false;
+    for (uint32_t i = 0; i < n; ++i)
+        if (ls[i].kind != LOLA_LAYER_DENSE && ls[i].kind != LOLA_LAYER_SQUARE) return false;
+    return true;
+}
+
+int compile_dense_chain(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n, bool sparse_input) {
+    const uint32_t N = p->N;
+    if (!is_dense_chain(ls, n)) return unsupported("a dense chain holds DENSE and SQUARE layers, DENSE first");
+    int dim = ls[0].in_dim;
+    for (uint32_t l = 0; l < n; ++l) {
+        if (ls[l].kind != LOLA_LAYER_DENSE) continue;
+        if (ls[l].in_dim != dim || ls[l].out_dim <= 0 || !ls[l].weight)
+            return unsupported("dense layer sizes must chain");
+        if ((uint32_t)ls[l].in_dim > N || (uint32_t)ls[l].out_dim > N)
+            return unsupported("dense layer larger than a message");
+        dim = ls[l].out_dim;
+    }
+    const int k = ls[0].in_dim;
+    p->queries = 1;
+    std::vector<int> regs;
+    if (sparse_input) {
+        p->n_inputs = (uint32_t)k;
+        p->input_map.assign((size_t)k * N, -1);
+        for (int i = 0; i < k; ++i) {
+            std::fill(p->input_map.begin() + (size_t)i * N, p->input_map.begin() + (size_t)(i + 1) * N, i);
+            regs.push_back(i);
+        }
+    } else {
+        p->n_inputs = 1;
+        p->input_map.assign(N, -1);
+        for (int i = 0; i < k; ++i) p->input_map[i] = i;
+        regs.push_back(0);
+    }
+    p->n_regs = p->n_inputs;
+    std::vector<int32_t> full;
+    for (uint32_t s = 1; s < N / 2; s *= 2) full.push_back((int32_t)s);
+    full.push_back(LOLA_ROW_SWAP);
+    bool sparse = sparse_input;
+    int r = k;
+    for (uint32_t l = 0; l < n; ++l) {
+        const lola_layer &ly = ls[l];
+        if (ly.kind == LOLA_LAYER_SQUARE) {
+            for (int &x : regs) x = b.square(x);
+            continue;
+        }
+        const int in = ly.in_dim;
+        r = ly.out_dim;
+        if (sparse) {
+            std::vector<int> terms;
+            for (int i = 0; i < in; ++i) {
+                auto col = b.zeros();
+                for (int j = 0; j < r; ++j) col[j] = ly.weight[(size_t)j * in + i];
+                terms.push_back(b.column_term(regs[i], std::move(col)));
+            }
+            int cadd = -1;
+            if (ly.bias) {
+                auto bv = b.zeros();
+                for (int j = 0; j < r; ++j) bv[j] = ly.bias[j];
+                cadd = b.cst(bv, false);
+            }
+            regs = {b.column_sum(terms, cadd)};
+        } else {
+            std::vector<int> outs;
+            for (int j = 0; j < r; ++j) {
+                auto row = b.zeros();
+                for (int i = 0; i < in; ++i) row[i] = ly.weight[(size_t)j * in + i];
+                int z = b.rotate_and_sum(b.mulplain(regs[0], b.cst(row, true)), full);
+                if (ly.bias) z = b.addplain(z, b.cst(std::vector<int64_t>(N, ly.bias[j]), false));
+                outs.push_back(z);
+            }
+            regs = outs;
+        }
+        sparse = !sparse;
+    }
+    p->outputs = regs;
+    p->output_map.assign((size_t)regs.size() * N, -1);
+    if (sparse)
+        for (int j = 0; j < r; ++j) p->output_map[(size_t)j * N] = j;
+    else
+        for (int j = 0; j < r; ++j) p->output_map[j] = j;
+    p->recipe = sparse_input ? LOLA_RECIPE_SPARSE_COLUMN_MAJOR : LOLA_RECIPE_DENSE_CHAIN;
+    return LOLA_OK;
+}
+
 // The recipes that apply to a layer list: DENSE, SQUARE, DENSE has two for
 // its dense layers, the five-layer convolution networks two for their
 // reductions; everything else has one (LOLA_RECIPE_FIXED).
+// The dense-chain recipes take any chain of DENSE and SQUARE layers and are
+// the candidates for chains that no other pattern covers; they can be forced
+// on the others.
+static bool dense_pattern(const lola_layer *layers, uint32_t n_layers) {
+    const lola_layer &l0 = layers[0];
+    if (l0.kind != LOLA_LAYER_DENSE) return false;
+    if (n_layers == 3 && layers[1].kind == LOLA_LAYER_SQUARE && layers[2].kind == LOLA_LAYER_DENSE) return true;
+    return n_layers == 1 || (n_layers == 2 && layers[1].kind == LOLA_LAYER_SQUARE);
+}
 static std::vector<int> recipe_candidates(const lola_layer *layers, uint32_t n_layers) {
     const lola_layer &l0 = layers[0];
-    if (l0.kind == LOLA_LAYER_DENSE && n_layers == 3)
+    if (l0.kind == LOLA_LAYER_DENSE && n_layers == 3 && dense_pattern(layers, n_layers))
         return {LOLA_RECIPE_DENSE_ROW_MAJOR, LOLA_RECIPE_STACKED_ROW_MAJOR};
     if ((l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) && n_layers == 5 &&
         layers[2].kind != LOLA_LAYER_CONV2D)
         return {LOLA_RECIPE_FULL_REDUCTION, LOLA_RECIPE_SHARED_REDUCTION};
+    if (is_dense_chain(layers, n_layers) && !dense_pattern(layers, n_layers))
+        return {LOLA_RECIPE_DENSE_CHAIN, LOLA_RECIPE_SPARSE_COLUMN_MAJOR};
     return {LOLA_RECIPE_FIXED};
+}
+static bool recipe_applies(const lola_layer *layers, uint32_t n_layers, int recipe) {
+    if ((recipe == LOLA_RECIPE_DENSE_CHAIN || recipe == LOLA_RECIPE_SPARSE_COLUMN_MAJOR) &&
+        is_dense_chain(layers, n_layers))
+        return true;
+    const std::vector<int> cand = recipe_candidates(layers, n_layers);
+    return std::find(cand.begin(), cand.end(), recipe) != cand.end();
 }
 
 // Compiles with one recipe (one of recipe_candidates()).
@@ -832,7 +961,9 @@ static int compile_with(const lola_params *prm, const lola_layer *layers, uint32
     const lola_layer &l0 = layers[0];
     const uint32_t N = prm->N;
     const bool head = l0.kind == LOLA_LAYER_DENSE && n_layers == 3;
-    if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
+    if (recipe == LOLA_RECIPE_DENSE_CHAIN || recipe == LOLA_RECIPE_SPARSE_COLUMN_MAJOR) {
+        rc = compile_dense_chain(p, b, layers, n_layers, recipe == LOLA_RECIPE_SPARSE_COLUMN_MAJOR);
+    } else if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
         rc = compile_cifar_net(p, b, layers, n_layers);
     } else if (l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) {
         rc = compile_conv_net(p, b, layers, n_layers, recipe == LOLA_RECIPE_SHARED_REDUCTION);
@@ -876,11 +1007,11 @@ int lola_compile_ex(const lola_params *prm, const lola_layer *layers, uint32_t n
     const int recipe = opts ? opts->recipe : LOLA_RECIPE_AUTO;
     if (objective != LOLA_OBJECTIVE_THROUGHPUT && objective != LOLA_OBJECTIVE_LATENCY)
         return set_error(LOLA_E_INVAL, "unknown objective");
-    if (recipe < LOLA_RECIPE_AUTO || recipe > LOLA_RECIPE_SHARED_REDUCTION)
+    if (recipe < LOLA_RECIPE_AUTO || recipe > LOLA_RECIPE_SPARSE_COLUMN_MAJOR)
         return set_error(LOLA_E_INVAL, "unknown recipe");
     const std::vector<int> cand = recipe_candidates(layers, n_layers);
     if (recipe != LOLA_RECIPE_AUTO) {
-        if (std::find(cand.begin(), cand.end(), recipe) == cand.end())
+        if (!recipe_applies(layers, n_layers, recipe))
             return unsupported("the recipe does not apply to this layer list");
         return compile_with(prm, layers, n_layers, recipe, out);
     }

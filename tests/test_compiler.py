@@ -320,7 +320,7 @@ def test_compile_options_are_validated():
     lola = _lola()
     from paper_1812_10659_amd import networks
     pm, lm = wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights())
-    for obj, rec in [(2, 0), (-1, 0), (0, 6), (0, -1)]:
+    for obj, rec in [(2, 0), (-1, 0), (0, 8), (0, -1)]:
         with pytest.raises(lola.LolaError) as e:
             lola.Plan(pm, lm, objective=obj, recipe=rec)
         assert e.value.code == -1
@@ -349,3 +349,62 @@ def test_compiler_rejects_unsupported():
     assert e.value.code == -8
     with pytest.raises(lola.LolaError):
         lola.Plan(p, [lola.dense(np.ones((3, 9000), dtype=np.int64))])
+
+
+def _chain(dims, seed=11):
+    """A chain DENSE, SQUARE, DENSE, SQUARE, DENSE with seeded int8 weights
+    and integer biases (lola layers, oracle layers, input vector)."""
+    lola = _lola()
+    rs = wl.rng(seed, 3)
+    Ws = [rs.integers(-128, 128, (dims[i + 1], dims[i])) for i in range(len(dims) - 1)]
+    bs = [rs.integers(-1000, 1000, dims[i + 1]) for i in range(len(dims) - 1)]
+    layers, ol = [], []
+    for i, (W, b) in enumerate(zip(Ws, bs)):
+        if i:
+            layers.append(lola.square())
+            ol.append(("square",))
+        layers.append(lola.dense(W, b))
+        ol.append(("dense", W, b))
+    return layers, ol, rs.integers(-128, 128, dims[0])
+
+
+@pytest.mark.parametrize("recipe,sparse", [(6, False), (7, True)])
+def test_compiler_dense_chain(recipe, sparse):
+    """DENSE, SQUARE, DENSE, SQUARE, DENSE (no fixed pattern): dense vector -
+    row major on dense inputs and sparse vector - column major on sparse ones
+    (Sec. 4.2.2), against the oracle's schedule of the same chain."""
+    lola = _lola()
+    p = wl.PARAMS["n4096_3q"]
+    layers, ol, x = _chain([64, 32, 16, 10])
+    sched = nw.dense_chain_schedule(ol, p.N, sparse)
+    plan = _check_plan(lola, p, layers, x, nw.dense_chain_plain(x, ol), sched, recipe=recipe)
+    assert plan.info["recipe"] == recipe
+    # column-major layers need no rotation: only the row-major ones rotate
+    full = 11 + 1   # 1 .. N/4 and the row swap
+    rows = [16] if sparse else [32, 10]
+    assert plan.info["n_rotations"] == full * sum(rows)
+    assert plan.info["n_inputs"] == (64 if sparse else 1)
+
+
+def test_compiler_dense_chain_recipe_choice():
+    """With no fixed pattern for the chain, both chain recipes are candidates
+    and the cost model keeps the cheaper (here the sparse input, whose first
+    layer needs no rotation); either can be forced, also on the DENSE,
+    SQUARE, DENSE pattern, whose default stays with its own recipes."""
+    lola = _lola()
+    p = wl.PARAMS["n4096_3q"]
+    layers, ol, x = _chain([64, 32, 16, 10])
+    auto = lola.Plan(p, layers)
+    costs = {r: lola.Plan(p, layers, recipe=r).info["predicted_us"] for r in (6, 7)}
+    assert auto.info["recipe"] == min(costs, key=costs.get)
+    head, hol, hx = _chain([64, 16, 10], seed=12)
+    assert lola.Plan(p, head).info["recipe"] in (1, 2)
+    for r, sp in ((6, False), (7, True)):
+        _check_plan(lola, p, head, hx, nw.dense_chain_plain(hx, hol), nw.dense_chain_schedule(hol, p.N, sp), recipe=r)
+    with pytest.raises(lola.LolaError):
+        lola.Plan(p, networks_mnist_layers(), recipe=7)
+
+
+def networks_mnist_layers():
+    from paper_1812_10659_amd import networks
+    return networks.mnist_layers(wl.mnist_weights())

@@ -344,3 +344,34 @@ def test_bruteforce_chacha_quarter_round_vector():
     key = [int(w, 16) for w in rows["key"]]
     out = bf.chacha20_block(key, 1, [int(w, 16) for w in rows["nonce"]])
     assert [f"{x:08x}" for x in out] == rows["out"]
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_dense_chain_ciphertexts_decrypt_to_network(sparse):
+    """Sparse vector - column major and dense vector - row major (Sec. 4.2.2)
+    on ciphertexts: the oracle's chain DENSE, SQUARE, DENSE at N = 2048
+    decrypts to the plaintext integer network mod t, and its slot-level run
+    equals it too."""
+    from oracle import network as nw
+    p = wl.PARAMS["toy2048"]
+    rs = wl.rng(21, 1)
+    W1, W2 = rs.integers(-128, 128, (6, 8)), rs.integers(-128, 128, (4, 6))
+    b1, b2 = rs.integers(-1000, 1000, 6), rs.integers(-1000, 1000, 4)
+    ol = [("dense", W1, b1), ("square",), ("dense", W2, b2)]
+    x = rs.integers(-128, 128, 8)
+    exp = list(nw._mod(nw.dense_chain_plain(x, ol), p.t))
+    assert exp == [int(v) % p.t for v in (W2.dot((W1.dot(x) + b1) ** 2) + b2)]
+    sched = nw.dense_chain_schedule(ol, p.N, sparse)
+    ins = nw.dense_chain_inputs(x, p.N, sparse)
+    slots, _ = nw.run_slots(sched, ins, p.t)
+    octx = bfv.Context(p)
+    keys = bfv.keygen(octx, 5, nw.galois_elements(sched))
+    cts = [bfv.encrypt(octx, keys, bfv.encode(octx, nw.dense_slots(m, p.N, p.t)), 6, i) for i, m in enumerate(ins)]
+    outs, _ = nw.run_ciphertexts(octx, keys, sched, cts)
+    dec = [bfv.decode(octx, bfv.decrypt(octx, keys, o)) for o in outs]
+    if not sparse:   # dense input: row major, then column major last: one dense message
+        assert [int(dec[0][j]) for j in range(4)] == exp and [int(slots[0][j]) for j in range(4)] == exp
+        assert not np.any(dec[0][4:]) and len(outs) == 1
+    else:            # sparse input: column major, then row major last: every slot of message j holds y_j
+        assert [int(d[0]) for d in dec] == exp and all(np.all(d == d[0]) for d in dec)
+        assert [int(s[0]) for s in slots] == exp
