@@ -207,6 +207,22 @@ int lola_rotate(lola_ctx *ctx, const uint32_t *gk_dev, uint32_t galois, const ui
 int lola_rotate_hoisted(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n, const uint32_t *galois,
                         const uint32_t *const *keys, uint32_t *const *out_dev, lola_stream stream);
 
+/* lola_rotate for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same rotation, the same words, computed with the batched key-switch
+ * kernels on one job whose scratch, (4L + 2) N words, lies in a fixed device
+ * array of the library of (4 x 12 + 2) x 16384 words (3.1 MiB; set up per
+ * device when a context is created and held until the process ends) and
+ * whose descriptor is passed by value; nothing is allocated and no
+ * descriptor is uploaded.  Every call on one GPU shares that array, so calls
+ * that overlap on one GPU (two streams, two threads) race: the caller
+ * orders them.  Nothing in the array needs clearing between calls.  Errors:
+ * LOLA_E_NOKEY (no key), LOLA_E_INVAL (null pointer, Galois element 0, even
+ * or >= 2N, out == ct), LOLA_E_SHAPE (scratch above the fixed size, which no
+ * accepted parameter set reaches), LOLA_E_DEVICE. */
+int lola_rotate_noalloc(lola_ctx *ctx, const uint32_t *gk_dev, uint32_t galois, const uint32_t *ct_dev,
+                        uint32_t *out_dev, lola_stream stream);
+
 /* Batched key switching: n independent rotations / relinearisations in one
  * set of launches (uneven per-ciphertext work is just more descriptors). */
 typedef struct {

@@ -379,6 +379,7 @@ int lola_ctx_create(const lola_params *p, int device, lola_ctx **out) {
     ctx->primes.push_back(p->t);
     int rc = build_tables(ctx);
     if (rc == LOLA_OK) rc = build_mrc(ctx);
+    if (rc == LOLA_OK) rc = noalloc_setup(device);   // the device's fixed key-switch scratch (lola_rotate_noalloc)
     if (rc != LOLA_OK) {
         lola_ctx_destroy(ctx);
         return rc;

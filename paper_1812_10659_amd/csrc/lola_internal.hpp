@@ -136,6 +136,9 @@ int check_hip(hipError_t e, const char *what);
 
 // scratch arena (device); grows with a device synchronisation
 int scratch_get(lola_ctx *ctx, size_t bytes, void **out);
+// Takes the device address of the fixed scratch array that
+// lola_rotate_noalloc uses, once per device (idempotent).
+int noalloc_setup(int device);
 // Kernel timing around one launch: ktime_begin records a start event when
 // timing is on (*a stays null otherwise); ktime_end records the stop event and
 // keeps the launch with its kernel id, units and algorithmic cost.
