@@ -176,12 +176,20 @@ def main():
                          "or CPU section (for profiler runs whose per-kernel sums must cover that workload alone)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device once (scale for HBM counters) and exit")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default NTT and key-switch variants (no autotuning before the timed steps)")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="only run the CPU oracle on whole workloads (dense-64 query, MNIST-shaped network, "
+                         "transfer head in both recipes) on all host threads and on one, and exit")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only measure the 32-bit VALU issue rates (mul_lo, mul_hi, add) against the "
                          "CU x SIMD x lane x clock peak and exit")
     args = ap.parse_args()
     if args.valu_probe:
         print(json.dumps(valu_probe_run()), flush=True)
+        return
+    if args.cpu_baseline_full:
+        print(json.dumps(cpu_baseline_full()), flush=True)
         return
     if args.calibrate_copy:
         import torch
@@ -229,6 +237,19 @@ def main():
     plan = lola.Plan(p, networks.mnist_layers(w))
     plan.load(ctx)
     plan.set_lanes(args.lanes)
+    tuned = None
+    if not args.no_autotune:
+        # radix splits, LDS placements and tiles of the batched NTT and of the
+        # three key-switch stages, timed on the device (each variant checked
+        # word for word against the default first) and cached per (N, L)
+        from paper_1812_10659_amd import batched
+        ntt_c, ks_c = batched.autotune_ntt(ctx, N, L), batched.autotune_ks(ctx, N, L)
+        tuned = {"ntt": {"chosen": dict(zip(("split", "limbs_per_wg"), ctx.ntt_variants()[ctx.ntt_variant()])),
+                         "trials_ms": ntt_c.get("ntt_trials_ms")},
+                 "keyswitch": {"chosen": {lola.KS_STAGES[st]: dict(zip(("split", "padded"),
+                                                                       ctx.ks_variants(st)[ctx.ks_variant(st)]))
+                                          for st in range(3)},
+                               "trials_ms": ks_c.get("ks_trials_ms"), "trial_jobs": ks_c.get("ks_trial_jobs")}}
     from paper_1812_10659_amd import requests as rq
     B, C = args.batch, max(1, min(args.clients, args.batch))
     reqs, keys, images = rq.mnist_batch(ctx, plan, B, C)
@@ -412,6 +433,7 @@ def main():
                         "summed time of its three kernels (digits, inner, mod-down) in the timed pass"},
         "keyswitch": whole_ks,
         "kernels": kernels,
+        "autotune": tuned,
         "context": {"paper_latency_s": 2.2, "paper_hw": "8 vCPU Azure B8ms, SEAL 2.3.1"},
     }
     headline_recipe = plan.info["recipe"]
@@ -841,6 +863,72 @@ def cpu_baseline(p, w, recipe):
             "sample": f"1 full inference, the timed plan's schedule ({sched.count('rotate')} rotations, "
                       f"{sched.count('square')} squares), {dt:.1f} s",
             "cpu": _cpu_model(), "batched_primitives_per_op": oracle_batch_ops()}
+
+
+def cpu_baseline_full():
+    """The oracle on whole workloads, on all host threads and on one: the
+    dense-64 query at N=4096, the MNIST-shaped network (the timed plan's
+    shared-reduction schedule), and the transfer head at N=16384 in both
+    recipes (dense row major, 4 queries per message, 3407 rotations; stacked
+    row major, one query, 911 rotations).  Per workload and thread count:
+    key generation, encryption of the inputs, the evaluation, decryption and
+    decoding, each timed; the decrypted results are checked against the plain
+    network.  Progress goes to stderr as the evaluation proceeds."""
+    import numpy as np
+
+    from oracle import bfv
+    from oracle import network as nw
+    from paper_1812_10659_amd import workloads as wl
+    x64, W64 = wl.dense64_inputs()
+    mw, img = wl.mnist_weights(), wl.mnist_image(index=0)
+    hw, hf = wl.head_weights(), wl.head_features(4)
+    cases = [
+        ("cfg0 dense-64 query, N=4096, L=3", "n4096_3q", nw.dense64_schedule(W64), nw.dense64_inputs(x64, 4096),
+         list(nw._mod(nw.dense64_plain(x64, W64), wl.PARAMS["n4096_3q"].t)), 1),
+        ("cfg1 MNIST-shaped, N=16384, L=7 (shared reduction, 58 rotations)", "mnist_n16384",
+         nw.mnist_schedule(mw, recipe="shared"), nw.mnist_inputs(img),
+         list(nw._mod(nw.mnist_plain(img, mw), wl.PARAMS["mnist_n16384"].t)), 1),
+        ("cfg3 transfer head, N=16384, L=6, dense row major (4 queries per message)", "head_n16384",
+         nw.head_schedule(hw), nw.head_inputs(hf),
+         list(nw._mod(np.concatenate([nw.head_plain(hf[q], hw) for q in range(4)]), wl.PARAMS["head_n16384"].t)), 4),
+        ("cfg3 transfer head, N=16384, L=6, stacked row major (1 query per message)", "head_n16384",
+         nw.head_stacked_schedule(hw), nw.head_stacked_inputs(hf[:1]),
+         list(nw._mod(nw.head_plain(hf[0], hw), wl.PARAMS["head_n16384"].t)), 1),
+    ]
+    all_threads = bfv.max_threads()
+    out = {"cpu": _cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+           "kind": "oracle", "runs": []}
+    for th in (all_threads, 1):
+        bfv.set_threads(th)
+        for name, pname, sched, ins, expected, queries in cases:
+            p = wl.PARAMS[pname]
+            octx = bfv.Context(p)
+            t0 = time.perf_counter()
+            keys = bfv.keygen(octx, 77, nw.galois_elements(sched))
+            t1 = time.perf_counter()
+            cts = [bfv.encrypt(octx, keys, bfv.encode(octx, nw.dense_slots(m, p.N, p.t)), 5, i)
+                   for i, m in enumerate(ins)]
+            t2 = time.perf_counter()
+
+            def progress(done, total, name=name, th=th):
+                print(f"[cpu-baseline] {name}, {th} threads: {done}/{total} ops", file=sys.stderr, flush=True)
+            outs, _ = nw.run_ciphertexts(octx, keys, sched, cts, progress=progress)
+            t3 = time.perf_counter()
+            slots = [bfv.decode(octx, bfv.decrypt(octx, keys, o)) for o in outs]
+            t4 = time.perf_counter()
+            # the labelled result slots hold the network's outputs (compared as
+            # a multiset: the labels order them per schedule)
+            got = sorted(int(o_slots[s]) for o_slots, where in zip(slots, sched.out_slots) for s in where)
+            ok = got == sorted(int(v) for v in expected)
+            run = {"workload": name, "threads": th, "rotations": sched.count("rotate"),
+                   "squares": sched.count("square"), "mul_plain": sched.count("mul_plain"), "queries": queries,
+                   "keygen_s": round(t1 - t0, 3), "encrypt_s": round(t2 - t1, 3), "evaluate_s": round(t3 - t2, 3),
+                   "decrypt_s": round(t4 - t3, 3), "inferences_per_s": round(queries / (t3 - t2), 5),
+                   "client_inclusive_inferences_per_s": round(queries / (t4 - t1), 5), "decrypts_to_network": ok}
+            print(f"[cpu-baseline] {json.dumps(run)}", file=sys.stderr, flush=True)
+            out["runs"].append(run)
+    bfv.set_threads(all_threads)
+    return out
 
 
 def oracle_batch_ops():

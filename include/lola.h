@@ -111,7 +111,13 @@ int lola_reserve(lola_ctx *ctx, uint32_t n_ct);
 uint32_t lola_galois_element(uint32_t N, int32_t step);
 
 /* ------------------------------------------------------------------- keys */
-/* Random values come from ChaCha20 (RFC 8439) with key = (seed lo, seed hi,
+/* Keys of the scheme of Sec. 3.1 (the paper takes BFV from its library; the
+ * public-key and switching-key forms are this library's reading: ternary s,
+ * pk = (-(a s + e), a), switching keys with one digit per ciphertext prime
+ * and one special prime P).  sk_dev [L+1][N], pk_dev [2][L][N], ksk_dev
+ * [L][2][L+1][N] (caller-owned device buffers, written).  Errors:
+ * LOLA_E_INVAL (null pointer, bad Galois element).
+ * Random values come from ChaCha20 (RFC 8439) with key = (seed lo, seed hi,
  * 0...), nonce = (domain, object, limb), one 64-bit word per coefficient;
  * uniform = word mod m, ternary = word mod 3 - 1, error = centred binomial
  * popcount(w & 0x1fffff) - popcount((w >> 21) & 0x1fffff). */
@@ -153,12 +159,16 @@ int lola_crt_combine(const int64_t *const *residues_dev, const uint32_t *moduli,
                      int64_t *out_dev, uint32_t words, lola_stream stream);
 
 /* ------------------------------------------------------ encrypt / decrypt */
-/* c = (pk0 u + e1 + floor(Q/t) m, pk1 u + e2), u ternary, e1, e2 errors drawn
- * with the seed and the object id `nonce`. */
+/* Encryption E of Sec. 3.1: c = (pk0 u + e1 + floor(Q/t) m, pk1 u + e2), u
+ * ternary, e1, e2 errors drawn with the seed and the object id `nonce`.
+ * pt_dev: N words in [0, t) (lola_encode output); ct_dev: [2][L][N] written.
+ * Errors: LOLA_E_INVAL (null pointer). */
 int lola_encrypt(lola_ctx *ctx, const uint32_t *pk_dev, const uint32_t *pt_dev, uint64_t seed,
                  uint32_t nonce, uint32_t *ct_dev, lola_stream stream);
-/* m_k = round(t x_k / Q) mod t, x = c0 + c1 s (+ c2 s^2) mod Q, computed
- * exactly (mixed-radix, no floating point).  size = 2 or 3. */
+/* Decryption D of Sec. 3.1: m_k = round(t x_k / Q) mod t, x = c0 + c1 s
+ * (+ c2 s^2) mod Q, computed exactly (mixed-radix, no floating point).
+ * size = 2 or 3; pt_dev: N words written.  Errors: LOLA_E_INVAL (null
+ * pointer, size not 2 or 3). */
 int lola_decrypt(lola_ctx *ctx, const uint32_t *sk_dev, const uint32_t *ct_dev, uint32_t size,
                  uint32_t *pt_dev, lola_stream stream);
 /* The same over n messages stored back to back (pt_dev n * N words, ct_dev
@@ -172,26 +182,38 @@ int lola_decrypt_batch(lola_ctx *ctx, const uint32_t *sk_dev, const uint32_t *ct
                        uint32_t *pt_dev, lola_stream stream);
 
 /* ------------------------------------------------------------- operations */
-/* out = a + b.  `size` components (2 or 3). */
+/* Homomorphic sum of Sec. 3.1: out = a + b, `size` components (2 or 3);
+ * may run in place.  Errors: LOLA_E_INVAL. */
 int lola_add(lola_ctx *ctx, const uint32_t *a_dev, const uint32_t *b_dev, uint32_t size,
              uint32_t *out_dev, lola_stream stream);
-/* out = (c0 + floor(Q/t) m, c1). */
+/* Plaintext sum (Sec. 3.1; biases of Sec. 4.3): out = (c0 + floor(Q/t) m,
+ * c1), pt_add_dev from lola_plain_add_form; may run in place. */
 int lola_add_plain(lola_ctx *ctx, const uint32_t *ct_dev, const uint32_t *pt_add_dev,
                    uint32_t *out_dev, lola_stream stream);
-/* out = (c0 [m]_t, c1 [m]_t). */
+/* Plaintext product, slot by slot (Sec. 3.1 batching; the point-wise
+ * products of Sec. 4.2.2): out = (c0 [m]_t, c1 [m]_t), pt_mul_dev from
+ * lola_plain_mul_form; may run in place. */
 int lola_mul_plain(lola_ctx *ctx, const uint32_t *ct_dev, const uint32_t *pt_mul_dev,
                    uint32_t *out_dev, lola_stream stream);
 /* out = [w]_t * ct (message times scalar, Sec. 4.2.2). */
 int lola_mul_scalar(lola_ctx *ctx, const uint32_t *ct_dev, int64_t w, uint32_t *out_dev,
                     lola_stream stream);
-/* Size-3 product: d_j = round(t (a (x) b)_j / Q) mod Q for the tensor of the
- * centred lifts, computed exactly. */
+/* Homomorphic product of Sec. 3.1 (the square activation of Sec. 4.3):
+ * size-3 result d_j = round(t (a (x) b)_j / Q) mod Q for the tensor of the
+ * centred lifts, computed exactly.  out3_dev [3][L][N] may not alias an
+ * input (LOLA_E_INVAL). */
 int lola_mul(lola_ctx *ctx, const uint32_t *a_dev, const uint32_t *b_dev, uint32_t *out3_dev,
              lola_stream stream);
-/* (d0, d1) + KeySwitch_{s^2 -> s}(d2). */
+/* Relinearisation, the step that brings a product of Sec. 3.1 back to two
+ * components: (d0, d1) + KeySwitch_{s^2 -> s}(d2), rlk_dev from
+ * lola_keygen_switch with galois 0.  LOLA_E_NOKEY without a key. */
 int lola_relin(lola_ctx *ctx, const uint32_t *rlk_dev, const uint32_t *in3_dev, uint32_t *out_dev,
                lola_stream stream);
-/* (sigma_g(c0), 0) + KeySwitch_{sigma_g(s) -> s}(sigma_g(c1)). */
+/* Rotation of the slot matrix (Sec. 3.1: row swap, column rotation; the
+ * rotate-and-sum reductions of Sec. 4.1 and 4.2.2): (sigma_g(c0), 0) +
+ * KeySwitch_{sigma_g(s) -> s}(sigma_g(c1)), galois from lola_galois_element,
+ * gk_dev from lola_keygen_switch with that element.  Errors: LOLA_E_NOKEY,
+ * LOLA_E_INVAL (Galois element 0, even or >= 2N). */
 int lola_rotate(lola_ctx *ctx, const uint32_t *gk_dev, uint32_t galois, const uint32_t *ct_dev,
                 uint32_t *out_dev, lola_stream stream);
 /* n rotations of one ciphertext in_dev [2][L][N], by galois[k] (host, odd,
@@ -206,6 +228,30 @@ int lola_rotate(lola_ctx *ctx, const uint32_t *gk_dev, uint32_t galois, const ui
  * chunks of 128. */
 int lola_rotate_hoisted(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n, const uint32_t *galois,
                         const uint32_t *const *keys, uint32_t *const *out_dev, lola_stream stream);
+
+/* Key-switch autotuner.  At N = 16384 the three batched key-switch stages
+ * (0 digits, 1 inner product, 2 mod-down) are each compiled in several
+ * variants: the radix split of their transforms (stages per register pass,
+ * written as digits, e.g. 4433) and the LDS placement (padded or plain).
+ * Every variant computes the same words.  lola_ks_variants lists a stage's
+ * variants (*count = how many, at most cap written; other N: one default);
+ * get / set choose the context's variant per stage (LOLA_E_INVAL for an
+ * index past the list).  lola_ks_autotune, stage by stage with the others at
+ * their best so far, runs a batch of n_jobs (1..128) rotations on synthetic
+ * residues with every variant, checks each one's output words against the
+ * default's (LOLA_E_DEVICE on a difference), times the whole key switch
+ * reps times, and keeps the fastest per stage in the context (chosen[3]).
+ * out receives one entry per variant timed, stages in order (ms = average
+ * time of the batch); it allocates and synchronises. */
+typedef struct {
+    uint32_t stage, index, split, padded;
+    float ms;
+} lola_ks_variant;
+int lola_ks_variants(const lola_ctx *ctx, uint32_t stage, lola_ks_variant *out, uint32_t cap, uint32_t *count);
+int lola_ks_get_variant(const lola_ctx *ctx, uint32_t stage, uint32_t *index);
+int lola_ks_set_variant(lola_ctx *ctx, uint32_t stage, uint32_t index);
+int lola_ks_autotune(lola_ctx *ctx, uint32_t n_jobs, uint32_t reps, lola_ks_variant *out, uint32_t cap,
+                     uint32_t *chosen, lola_stream stream);
 
 /* lola_rotate for callers that cannot allocate device memory (code under
  * graph capture, tight serving loops, harnesses that forbid allocation): the

@@ -206,6 +206,37 @@ def autotune_ntt(ctx, N, L, n_limbs=2048, reps=3):
     return cache
 
 
+def autotune_ks(ctx, N, L, n_jobs=64, reps=3):
+    """Radix split and LDS placement of each batched key-switch stage, picked
+    by the library's autotuner (every variant's words checked against the
+    default, then the whole key switch of n_jobs rotations timed); cached per
+    (N, L) in the same file as the NTT's choice."""
+    path = os.path.join(AUTOTUNE_DIR, f"autotune_N{N}_L{L}.json")
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        cache = {}
+    hit = cache.get("ks_variant")
+    variants = [ctx.ks_variants(st) for st in range(3)]
+    if hit and all(0 <= hit[st] < len(variants[st]) for st in range(3)):
+        for st in range(3):
+            ctx.ks_set_variant(st, hit[st])
+        return cache
+    chosen, table = ctx.ks_autotune(n_jobs=n_jobs, reps=reps)
+    cache.update({"ks_variant": chosen,
+                  "ks_trials_ms": {f"{lola.KS_STAGES[st]}/{sp}{'p' if pad else ''}": round(ms, 4)
+                                   for st, _, sp, pad, ms in table},
+                  "ks_trial_jobs": n_jobs})
+    try:
+        os.makedirs(AUTOTUNE_DIR, exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f)
+    except OSError:
+        pass
+    return cache
+
+
 def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tune: bool = True) -> dict:
     p = wl.PARAMS["batch_n16384"]
     N, L = p.N, p.L
@@ -230,6 +261,7 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
     # 1. forward + inverse NTT of every limb of both components, with the
     # radix split and tile the autotuner picked (the default timed beside it)
     ntt_cache = autotune_ntt(ctx, N, L) if tune else {}
+    ks_cache = autotune_ks(ctx, N, L) if tune else {}
     chosen = ctx.ntt_variant()
     limbs = torch.stack(cts).reshape(-1, N)
     idx = np.arange(limbs.shape[0], dtype=np.uint32) % L   # built once, as a caller would
@@ -279,6 +311,8 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
     same = all(torch.equal(x, y) for x, y in zip(pers, outs))
     rot = int(counts.sum())
     ks_bytes = 4 * N * (4 * L + 2 * L * (L + 1))
+    out["ks_autotune"] = {"chosen": {lola.KS_STAGES[st]: ctx.ks_variants(st)[ctx.ks_variant(st)] for st in range(3)},
+                          "trials_ms": ks_cache.get("ks_trials_ms"), "trial_jobs": ks_cache.get("ks_trial_jobs")}
     out["rotations_persistent"] = {"ms": round(s_p * 1e3, 2), "rot_per_s": round(rot / s_p, 1),
                                    "gbps": round(rot * ks_bytes / s_p / 1e9, 1), "workgroups": wg,
                                    "autotune": cache.get("chain_wg_trials_s")}

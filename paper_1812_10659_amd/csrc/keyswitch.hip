@@ -12,25 +12,29 @@
 //                               optional whole-ciphertext addend (fused
 //                               rotate-and-add).
 #include <algorithm>
+#include <cstring>
 
 #include "ks_core.hpp"
 #include "program.hpp"
 
 namespace lola {
 
-template <int LOGN>
+// Stage kernels are compiled in several radix splits and LDS placements
+// (the key-switch autotuner's variants, below); SPLIT 0 is the default
+// grouping of stages into passes.
+template <int LOGN, int SPLIT = 0, bool PAD = true>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                       uint32_t L, const ModConst *__restrict__ mcs,
                                                                       const TwPair *__restrict__ itw) {
-    __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[ntt_lds_words<LOGN, PAD>()];
     const JobUnit ju = xcd_job_unit(blockIdx.x, L, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t i = ju.unit;
-    ks_stage_digit<LOGN>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw);
+    ks_stage_digit<LOGN, PAD, SPLIT>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw);
 }
 
-template <int LOGN>
+template <int LOGN, int KSI = ks_inner_split<LOGN>()>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                      uint32_t L, const ModConst *__restrict__ mcs,
                                                                      const TwPair *__restrict__ tw,
@@ -43,7 +47,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
     // half again as long as the others, is dispatched first of its job so the
     // launch's tail holds short units
     const uint32_t j = ju.unit == 0 ? L : ju.unit - 1;
-    ks_stage_inner<LOGN>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
+    ks_stage_inner<LOGN, KSI>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
 }
 
 // Latency form of the inner stage (launches of at most KS_TERM_MAX_JOBS
@@ -140,21 +144,95 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_hoisted_inner_kernel(
     ks_stage_hoisted_inner<LOGN>(job.key, job.x, job.hoist, job.scratch, job.galois, j, L, sh, mcs[j], itw);
 }
 
-template <int LOGN>
+template <int LOGN, int SPLIT = 0, bool PAD = true>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                        uint32_t L, const ModConst *__restrict__ mcs,
                                                                        const TwPair *__restrict__ tw,
                                                                        const MrcConst *__restrict__ mrc) {
-    __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
+    __shared__ uint32_t sh[ntt_lds_words<LOGN, PAD>()];
     const JobUnit ju = xcd_job_unit(blockIdx.x, 2 * L, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t j = ju.unit % L, c = ju.unit / L;
-    ks_stage_moddown<LOGN>(job.scratch, j, c, L, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
-                           job.addct, job.out, sh, mcs[j], tw, mrc, mcs[L].q);
+    ks_stage_moddown<LOGN, PAD, SPLIT>(job.scratch, j, c, L, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
+                                       job.addct, job.out, sh, mcs[j], tw, mrc, mcs[L].q);
+}
+
+// ---- stage variants (radix split x LDS placement) and their launchers ----
+// At N = 16384 each batched stage is compiled in a few variants; the
+// context's ks_var[stage] picks one (0 = default).  Every variant computes
+// the same words; lola_ks_autotune times them and keeps the fastest.
+struct KsStageVariant {
+    uint32_t split, padded;
+};
+static const KsStageVariant KS_VARIANTS[3][4] = {
+    {{4442, 1}, {4442, 0}, {4433, 1}, {4244, 1}},   // digits
+    {{4433, 0}, {4442, 0}, {4424, 0}, {0, 0}},      // inner (plain placement, two LDS halves)
+    {{4442, 1}, {4442, 0}, {4433, 1}, {4244, 1}}};  // mod-down
+static uint32_t ks_variant_count(uint32_t logN, uint32_t stage) {
+    if (logN != 14 || stage > 2) return 1;
+    return stage == 1 ? 3 : 4;
+}
+
+template <int LG>
+static void launch_ks_digits(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s) {
+    const uint32_t L = ctx->L;
+    const dim3 g(xcd_grid(n, L)), b(ctx->N / NTT_E);
+    if constexpr (LG == 14) {
+        switch (ctx->ks_var[0]) {
+            case 1: hipLaunchKernelGGL((ks_digits_kernel<14, 0, false>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw); return;
+            case 2: hipLaunchKernelGGL((ks_digits_kernel<14, 4433, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw); return;
+            case 3: hipLaunchKernelGGL((ks_digits_kernel<14, 4244, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw); return;
+            default: break;
+        }
+    }
+    hipLaunchKernelGGL((ks_digits_kernel<LG, 0, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw);
+}
+
+template <int LG>
+static void launch_ks_inner(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s) {
+    const uint32_t L = ctx->L;
+    const dim3 g(xcd_grid(n, L + 1)), b(ctx->N / NTT_E);
+    if constexpr (LG == 14) {
+        switch (ctx->ks_var[1]) {
+            case 1: hipLaunchKernelGGL((ks_inner_kernel<14, 0>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw); return;
+            case 2: hipLaunchKernelGGL((ks_inner_kernel<14, 4424>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw); return;
+            default: break;
+        }
+    }
+    hipLaunchKernelGGL((ks_inner_kernel<LG>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw);
+}
+
+template <int LG>
+static void launch_ks_moddown(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s) {
+    const uint32_t L = ctx->L;
+    const dim3 g(xcd_grid(n, 2 * L)), b(ctx->N / NTT_E);
+    if constexpr (LG == 14) {
+        switch (ctx->ks_var[2]) {
+            case 1: hipLaunchKernelGGL((ks_moddown_kernel<14, 0, false>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
+            case 2: hipLaunchKernelGGL((ks_moddown_kernel<14, 4433, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
+            case 3: hipLaunchKernelGGL((ks_moddown_kernel<14, 4244, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
+            default: break;
+        }
+    }
+    hipLaunchKernelGGL((ks_moddown_kernel<LG, 0, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc);
 }
 
 size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }
+
+// Autotuning inputs: pseudo-random words below `bound` (every modulus of the
+// context exceeds it, so each word is a valid residue in any limb).
+__global__ void ks_tune_fill_kernel(uint32_t *x, size_t nx, uint32_t *k, size_t nk, uint32_t bound) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx + nk) return;
+    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 32;
+    const uint32_t v = (uint32_t)(h % bound);
+    if (i < nx) x[i] = v;
+    else k[i - nx] = v;
+}
 
 // Launches of at most this many jobs take the latency form of the inner
 // stage (ks_term + ks_fold): L (L+1) workgroups per job instead of L+1, each
@@ -238,8 +316,7 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, const uint6
             break;                                                                                           \
         }                                                                                                    \
         LOLA_TIMED(ctx, s, KID_KS_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                           \
-                   hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L,    \
-                                      ctx->d_mc, ctx->d_itw));                                                \
+                   launch_ks_digits<LG>(ctx, d_jobs, n, s));                                                  \
         if (term) {                                                                                          \
             LOLA_TIMED(ctx, s, KID_KS_TERM, n, c.term_b() * n, c.term_o() * n,                                \
                        hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, \
@@ -248,13 +325,11 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, const uint6
                        hipLaunchKernelGGL(ks_fold_kernel<LG>, dim3(n * 2 * (L + 1)), block, 0, s, d_jobs, n, L, \
                                           ctx->d_mc, ctx->d_itw));                                            \
         } else {                                                                                             \
-            LOLA_TIMED(ctx, s, KID_KS_INNER, n, c.inner_b(n, (double)aux[0]), c.inner_o() * n,                             \
-                       hipLaunchKernelGGL(ks_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, n, \
-                                          L, ctx->d_mc, ctx->d_tw, ctx->d_itw));                              \
+            LOLA_TIMED(ctx, s, KID_KS_INNER, n, c.inner_b(n, (double)aux[0]), c.inner_o() * n,                 \
+                       launch_ks_inner<LG>(ctx, d_jobs, n, s));                                               \
         }                                                                                                    \
         LOLA_TIMED(ctx, s, KID_KS_MODDOWN, n * 2 * L, c.moddown_b() * n * 2 * L, c.moddown_o() * n * 2 * L,    \
-                   hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, \
-                                      L, ctx->d_mc, ctx->d_tw, ctx->d_mrc));                                  \
+                   launch_ks_moddown<LG>(ctx, d_jobs, n, s));                                                 \
         break;
     switch (ctx->logN) {
         LOLA_KS_CASE(10)
@@ -276,9 +351,8 @@ int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, h
     const KsCost c(ctx);
 #define LOLA_HS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
-        LOLA_TIMED(ctx, s, KID_KS_HOIST_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                           \
-                   hipLaunchKernelGGL(ks_digits_kernel<LG>, dim3(xcd_grid(n, L)), block, 0, s, d_jobs, n, L,    \
-                                      ctx->d_mc, ctx->d_itw));                                                \
+        LOLA_TIMED(ctx, s, KID_KS_HOIST_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                     \
+                   launch_ks_digits<LG>(ctx, d_jobs, n, s));                                                  \
         LOLA_TIMED(ctx, s, KID_KS_MODUP, n, c.modup_b() * n, c.modup_o() * n,                                 \
                    hipLaunchKernelGGL(ks_modup_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L,    \
                                       ctx->d_mc, ctx->d_tw));                                                 \
@@ -307,9 +381,8 @@ int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, c
         LOLA_TIMED(ctx, s, KID_KS_HOISTED_INNER, n, c.hoist_b(n, (double)aux[0], (double)aux[1]), c.hoist_o() * n, \
                    hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, \
                                       n, L, ctx->d_mc, ctx->d_itw));                                          \
-        LOLA_TIMED(ctx, s, KID_KS_HOIST_MODDOWN, n * 2 * L, c.moddown_b() * n * 2 * L, c.moddown_o() * n * 2 * L,    \
-                   hipLaunchKernelGGL(ks_moddown_kernel<LG>, dim3(xcd_grid(n, 2 * L)), block, 0, s, d_jobs, n, \
-                                      L, ctx->d_mc, ctx->d_tw, ctx->d_mrc));                                  \
+        LOLA_TIMED(ctx, s, KID_KS_HOIST_MODDOWN, n * 2 * L, c.moddown_b() * n * 2 * L, c.moddown_o() * n * 2 * L, \
+                   launch_ks_moddown<LG>(ctx, d_jobs, n, s));                                                 \
         break;
     switch (ctx->logN) {
         LOLA_HR_CASE(10)
@@ -371,6 +444,120 @@ int lola_reserve(lola_ctx *ctx, uint32_t n_ct) {
     void *buf = nullptr;
     const uint32_t n = std::min<uint32_t>(std::max<uint32_t>(n_ct, 1), KS_CHUNK);
     return scratch_get(ctx, std::max(ks_chunk_words(ctx, n), n * mul_scratch_words(ctx)) * 4, &buf);
+}
+
+int lola_ks_variants(const lola_ctx *ctx, uint32_t stage, lola_ks_variant *out, uint32_t cap, uint32_t *count) {
+    if (!ctx || !count || (cap && !out) || stage > 2) return set_error(LOLA_E_INVAL, "bad argument");
+    const uint32_t nv = ks_variant_count(ctx->logN, stage);
+    for (uint32_t v = 0; v < nv && v < cap; ++v) {
+        const KsStageVariant &k = KS_VARIANTS[stage][v];
+        out[v] = lola_ks_variant{stage, v, ctx->logN == 14 ? k.split : 0u, ctx->logN == 14 ? k.padded : 1u, 0.f};
+    }
+    *count = nv;
+    return LOLA_OK;
+}
+
+int lola_ks_get_variant(const lola_ctx *ctx, uint32_t stage, uint32_t *index) {
+    if (!ctx || !index || stage > 2) return set_error(LOLA_E_INVAL, "bad argument");
+    *index = ctx->ks_var[stage];
+    return LOLA_OK;
+}
+
+int lola_ks_set_variant(lola_ctx *ctx, uint32_t stage, uint32_t index) {
+    if (!ctx || stage > 2) return set_error(LOLA_E_INVAL, "bad argument");
+    if (index >= ks_variant_count(ctx->logN, stage)) return set_error(LOLA_E_INVAL, "no such key-switch variant");
+    ctx->ks_var[stage] = index;
+    return LOLA_OK;
+}
+
+int lola_ks_autotune(lola_ctx *ctx, uint32_t n_jobs, uint32_t reps, lola_ks_variant *out, uint32_t cap,
+                     uint32_t *chosen, lola_stream stream) {
+    if (!ctx || !chosen || (cap && !out) || n_jobs == 0 || n_jobs > KS_CHUNK || reps == 0)
+        return set_error(LOLA_E_INVAL, "bad argument (1 <= n_jobs <= 128, reps >= 1)");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = ctx->N, L = ctx->L, ct = 2 * L * N, key = L * 2 * (L + 1) * N;
+    const size_t words = n_jobs * ct * 2 + key;   // inputs, outputs, one key
+    const uint32_t saved[3] = {ctx->ks_var[0], ctx->ks_var[1], ctx->ks_var[2]};
+    uint32_t *buf = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto fail = [&](int rc) {
+        if (buf) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(buf);
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (int k = 0; k < 3; ++k) ctx->ks_var[k] = saved[k];
+        return rc;
+    };
+    if (hipMalloc(&buf, words * 4) != hipSuccess) return fail(set_error(LOLA_E_NOMEM, "autotune buffers"));
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(set_error(LOLA_E_DEVICE, "autotune events"));
+    uint32_t *in = buf, *outb = buf + n_jobs * ct, *kd = buf + 2 * n_jobs * ct;
+    // residues below every modulus of the context, so valid in each limb
+    uint32_t bound = ctx->primes[0];
+    for (uint32_t k = 0; k <= ctx->L; ++k) bound = std::min(bound, ctx->primes[k]);
+    hipLaunchKernelGGL(ks_tune_fill_kernel, dim3((unsigned)((n_jobs * ct + key + 255) / 256)), dim3(256), 0, s, in,
+                       n_jobs * ct, kd, key, bound);
+    // rotations by 3 (sigma_3), one key, as many jobs as given
+    std::vector<KsJob> jobs(n_jobs);
+    for (uint32_t k = 0; k < n_jobs; ++k)
+        jobs[k] = KsJob{in + k * ct + L * N, kd, in + k * ct, nullptr, nullptr, outb + k * ct, nullptr, 3, 0};
+    std::vector<uint32_t> ref(n_jobs * ct), got(n_jobs * ct);
+    auto run = [&]() -> int {
+        std::vector<KsJob> j = jobs;
+        return keyswitch_host_jobs(ctx, j, s);
+    };
+    for (int k = 0; k < 3; ++k) ctx->ks_var[k] = 0;
+    int rc = run();
+    if (rc) return fail(rc);
+    if (hipMemcpyAsync(ref.data(), outb, ref.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(set_error(LOLA_E_DEVICE, "autotune reference"));
+    // stage by stage, the others at their best so far: every variant must
+    // give the default's words before it is timed (the whole key switch,
+    // reps times)
+    uint32_t written = 0;
+    for (uint32_t stage = 0; stage < 3; ++stage) {
+        const uint32_t nv = ks_variant_count(ctx->logN, stage);
+        float best_ms = 0;
+        uint32_t best = 0;
+        for (uint32_t v = 0; v < nv; ++v) {
+            ctx->ks_var[stage] = v;
+            if ((rc = run())) return fail(rc);
+            if (hipMemcpyAsync(got.data(), outb, got.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(set_error(LOLA_E_DEVICE, "autotune readback"));
+            if (memcmp(got.data(), ref.data(), got.size() * 4) != 0)
+                return fail(set_error(LOLA_E_DEVICE, "autotune: key-switch stage " + std::to_string(stage) +
+                                                         " variant " + std::to_string(v) + " differs from the default"));
+            if (hipEventRecord(e0, s) != hipSuccess) return fail(set_error(LOLA_E_DEVICE, "autotune event"));
+            for (uint32_t r = 0; r < reps; ++r)
+                if ((rc = run())) return fail(rc);
+            float t = 0;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                return fail(set_error(LOLA_E_DEVICE, "autotune timing"));
+            t /= (float)reps;
+            if (v == 0 || t < best_ms) {
+                best_ms = t;
+                best = v;
+            }
+            if (written < cap) {
+                const KsStageVariant &k = KS_VARIANTS[stage][v];
+                out[written] = lola_ks_variant{stage, v, ctx->logN == 14 ? k.split : 0u,
+                                               ctx->logN == 14 ? k.padded : 1u, t};
+            }
+            ++written;
+        }
+        ctx->ks_var[stage] = best;
+        chosen[stage] = best;
+    }
+    const uint32_t picked[3] = {chosen[0], chosen[1], chosen[2]};
+    fail(LOLA_OK);   // frees the buffers and restores the saved variants
+    for (int k = 0; k < 3; ++k) ctx->ks_var[k] = picked[k];
+    return written > cap ? set_error(LOLA_E_INVAL, "more variants than cap (all were timed and the best kept)")
+                         : LOLA_OK;
 }
 
 int lola_rotate_hoisted(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n, const uint32_t *galois,

@@ -79,7 +79,9 @@ __device__ __forceinline__ void ks_read_sigma(const uint32_t *src, uint32_t g, u
 }
 
 // Stage 1 for digit i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
-template <int LOGN, bool PAD = true>
+// SPLIT / PAD: the transform's radix split and LDS placement (every choice
+// reads and writes the same global layouts).
+template <int LOGN, bool PAD = true, int SPLIT = 0>
 __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, uint32_t *scratch, uint32_t i,
                                                uint32_t L, uint32_t *sh, const ModConst &mc,
                                                const TwPair *itw) {
@@ -89,14 +91,13 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
     uint32_t ii = i;
     asm volatile("" : "+s"(ii));
     uint32_t v[NTT_E];
-    ks_read_sigma<LOGN>(x + ((size_t)ii << LOGN), g, tid, sh, v);
-    store_spectral<LOGN>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
-    // LDS placement: padded in the digit kernel (measured faster there);
+    ks_read_sigma<LOGN, SPLIT>(x + ((size_t)ii << LOGN), g, tid, sh, v);
+    store_spectral<LOGN, SPLIT>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
     // starts with a barrier
-    ntt_inv_regs<LOGN, 0, PAD>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
+    ntt_inv_regs<LOGN, SPLIT, PAD>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
     const GBuf D = gbuf(scratch + ((size_t)ii << LOGN), N);
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN>(tid, r), v[r]);
+    for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN, SPLIT>(tid, r), v[r]);
 }
 
 // Stage 2 for target modulus j (q_j for j < L, P for j == L): for every
@@ -377,7 +378,7 @@ __device__ __forceinline__ void ks_stage_fold_moddown(const uint32_t *scratch, u
 // out = (U - lift) * P^-1, plus the optional addends: `add` ([L][N], read
 // through sigma_g when g > 1: the rotation's c0 or the relinearisation's d0 /
 // d1) and `addct` ([2][L][N], a whole ciphertext: fused rotate-and-add).
-template <int LOGN, bool PAD = true>
+template <int LOGN, bool PAD = true, int SPLIT = 0>
 __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
                                                  const uint32_t *add, uint32_t g, const uint32_t *addct,
                                                  uint32_t *out, uint32_t *sh, const ModConst &mc,
@@ -394,27 +395,27 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
     uint32_t x[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) {
-        const uint32_t v = gld(UP, natural_index<LOGN>(tid, r));
+        const uint32_t v = gld(UP, natural_index<LOGN, SPLIT>(tid, r));
         x[r] = reduce32(v + (v > halfP ? negPq : 0u), mc.q, mc.one_shoup);
     }
-    ntt_fwd_regs<LOGN, false, 0, PAD>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);   // padded in the mod-down kernel
+    ntt_fwd_regs<LOGN, false, SPLIT, PAD>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
     const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
     uint32_t u[NTT_E];
-    load_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + jj) << LOGN), N), tid, u);
+    load_spectral<LOGN, SPLIT>(gbuf(scratch + ((size_t)((2 + c) * L + jj) << LOGN), N), tid, u);
     // (U - lift) P^-1: U + q - lift < 2q feeds the lazy product directly
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(shoup_lazy(u[r] + mc.q - x[r], pinv, pinvp, mc.q), mc.q);
     if (add) {
-        ks_read_sigma<LOGN>(add + ((size_t)jj << LOGN), g, tid, sh, u);   // after the transform's last use of sh
+        ks_read_sigma<LOGN, SPLIT>(add + ((size_t)jj << LOGN), g, tid, sh, u);   // after the transform's last use of sh
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], u[r], mc.q);
     }
     if (addct) {
-        load_spectral<LOGN>(gbuf(addct + ((size_t)(c * L + jj) << LOGN), N), tid, u);
+        load_spectral<LOGN, SPLIT>(gbuf(addct + ((size_t)(c * L + jj) << LOGN), N), tid, u);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) x[r] = add_mod(x[r], u[r], mc.q);
     }
-    store_spectral<LOGN>(gbuf(out + ((size_t)(c * L + jj) << LOGN), N), tid, x);
+    store_spectral<LOGN, SPLIT>(gbuf(out + ((size_t)(c * L + jj) << LOGN), N), tid, x);
 }
 
 // ---- hoisted rotations ---------------------------------------------------

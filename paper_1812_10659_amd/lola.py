@@ -57,6 +57,14 @@ class NttVariant(ctypes.Structure):
     _fields_ = [("split", ctypes.c_uint32), ("limbs_per_wg", ctypes.c_uint32), ("ms", ctypes.c_float)]
 
 
+class KsVariant(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_uint32), ("index", ctypes.c_uint32), ("split", ctypes.c_uint32),
+                ("padded", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+
+KS_STAGES = ("digits", "inner", "moddown")
+
+
 def lib() -> ctypes.CDLL:
     """The loaded library; raises if it has not been built."""
     global _lib
@@ -103,6 +111,10 @@ def lib() -> ctypes.CDLL:
             "lola_ntt_get_variant": [vp, ctypes.POINTER(u32)],
             "lola_ntt_set_variant": [vp, u32],
             "lola_ntt_autotune": [vp, u32, u32, ctypes.POINTER(NttVariant), u32, ctypes.POINTER(u32), vp],
+            "lola_ks_variants": [vp, u32, ctypes.POINTER(KsVariant), u32, ctypes.POINTER(u32)],
+            "lola_ks_get_variant": [vp, u32, ctypes.POINTER(u32)],
+            "lola_ks_set_variant": [vp, u32, u32],
+            "lola_ks_autotune": [vp, u32, u32, ctypes.POINTER(KsVariant), u32, ctypes.POINTER(u32), vp],
             "lola_strerror": [i32],
             "lola_last_error": [],
         }
@@ -357,6 +369,34 @@ class Context:
 
     def ntt_set_variant(self, index: int) -> None:
         _check(lib().lola_ntt_set_variant(self.h, int(index)))
+
+    def ks_variants(self, stage: int) -> list:
+        """[(split, padded)] of a key-switch stage's variants (0 digits, 1
+        inner, 2 mod-down) compiled for this N."""
+        n = ctypes.c_uint32()
+        _check(lib().lola_ks_variants(self.h, int(stage), None, 0, ctypes.byref(n)))
+        arr = (KsVariant * n.value)()
+        _check(lib().lola_ks_variants(self.h, int(stage), arr, n.value, ctypes.byref(n)))
+        return [(v.split, v.padded) for v in arr]
+
+    def ks_variant(self, stage: int) -> int:
+        k = ctypes.c_uint32()
+        _check(lib().lola_ks_get_variant(self.h, int(stage), ctypes.byref(k)))
+        return k.value
+
+    def ks_set_variant(self, stage: int, index: int) -> None:
+        _check(lib().lola_ks_set_variant(self.h, int(stage), int(index)))
+
+    def ks_autotune(self, n_jobs: int = 64, reps: int = 3):
+        """Times every key-switch stage variant (a batch of n_jobs rotations,
+        each variant's words checked against the default first), keeps the
+        fastest per stage; returns (chosen [3], [(stage, index, split,
+        padded, ms)])."""
+        n = sum(len(self.ks_variants(st)) for st in range(3))
+        arr = (KsVariant * n)()
+        ch = (ctypes.c_uint32 * 3)()
+        _check(lib().lola_ks_autotune(self.h, int(n_jobs), int(reps), arr, n, ch, _stream()))
+        return list(ch), [(v.stage, v.index, v.split, v.padded, float(v.ms)) for v in arr]
 
     def ntt_autotune(self, n_limbs: int = 512, reps: int = 5):
         """Times every batched NTT variant (forward + inverse of n_limbs limbs),

@@ -359,3 +359,57 @@ def test_keyswitch_both_inner_forms(env, n_jobs):
     outs = ctx.keyswitch_batch(items)
     for k, o in enumerate(outs):
         assert np.array_equal(_down(ctx, o), np.stack(refs[k % len(base)])), f"job {k} of {n_jobs}"
+
+
+def _ks_items(env, n_jobs=20):
+    """n_jobs key switches (four rotations and a relinearisation, cycled) and
+    their oracle results."""
+    ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
+    c1, c2 = env["c"]
+    c3 = bfv.mul(octx, c1, c2)
+    base, refs = [], []
+    for k, step in enumerate([1, bfv.ROW_SWAP, -1, 7]):
+        src = c1 if k % 2 == 0 else c2
+        g = bfv.galois_element(env["p"].N, step)
+        base.append((_up(ctx, src), env["gks"][g], g))
+        refs.append(bfv.rotate(octx, src, step, ok))
+    base.append((_up(ctx, c3), env["rlk"], 0))
+    refs.append(bfv.relin(octx, c3, ok.rlk))
+    return [base[k % len(base)] for k in range(n_jobs)], [refs[k % len(base)] for k in range(n_jobs)]
+
+
+def test_every_ks_variant_gives_the_oracle_words(env):
+    """Every compiled variant of each batched key-switch stage (radix split x
+    LDS placement; several at N = 16384, one elsewhere), the other stages at
+    their defaults, gives the oracle's words on a 20-job batch."""
+    ctx = env["ctx"]
+    items, refs = _ks_items(env)
+    counts = [len(ctx.ks_variants(st)) for st in range(3)]
+    assert counts == ([4, 3, 4] if env["p"].N == 16384 else [1, 1, 1])
+    for st in range(3):
+        for v in range(counts[st]):
+            ctx.ks_set_variant(st, v)
+            outs = ctx.keyswitch_batch(items)
+            for k, o in enumerate(outs):
+                assert np.array_equal(_down(ctx, o), np.stack(refs[k])), f"stage {st} variant {v} job {k}"
+        ctx.ks_set_variant(st, 0)
+
+
+def test_ks_autotune_keeps_the_words(env):
+    """The key-switch autotuner times every variant (each checked against the
+    default by the library), keeps the fastest per stage, and the batch
+    afterwards still gives the oracle's words."""
+    ctx = env["ctx"]
+    items, refs = _ks_items(env)
+    chosen, table = ctx.ks_autotune(n_jobs=24, reps=1)
+    counts = [len(ctx.ks_variants(st)) for st in range(3)]
+    assert len(table) == sum(counts) and all(ms > 0 for *_, ms in table)
+    assert [ctx.ks_variant(st) for st in range(3)] == chosen
+    for st in range(3):
+        times = [ms for s, _, _, _, ms in table if s == st]
+        assert times[chosen[st]] == min(times)
+    outs = ctx.keyswitch_batch(items)
+    for k, o in enumerate(outs):
+        assert np.array_equal(_down(ctx, o), np.stack(refs[k])), f"job {k} after autotuning"
+    for st in range(3):
+        ctx.ks_set_variant(st, 0)
