@@ -822,9 +822,10 @@ def _sources(op):
     return [op[2], op[3]] if op[0] == "add" else [op[2]]
 
 
-def run_ciphertexts(ctx: bfv.Context, keys: bfv.Keys, sched: Schedule, cts, keep=False):
+def run_ciphertexts(ctx: bfv.Context, keys: bfv.Keys, sched: Schedule, cts, keep=False, progress=None):
     """Evaluates the schedule on ciphertexts with the oracle's operations.
-    Intermediate registers are dropped after their last use unless keep."""
+    Intermediate registers are dropped after their last use unless keep;
+    progress(done, total) is called every 250 ops when given."""
     last_use = {}
     for idx, op in enumerate(sched.ops):
         for r in _sources(op):
@@ -863,4 +864,6 @@ def run_ciphertexts(ctx: bfv.Context, keys: bfv.Keys, sched: Schedule, cts, keep
             for r in _sources(op):
                 if last_use.get(r) == idx and r not in sched.outputs:
                     reg.pop(r, None)
+        if progress is not None and (idx + 1) % 250 == 0:
+            progress(idx + 1, len(sched.ops))
     return [reg[o] for o in sched.outputs], reg

@@ -112,6 +112,19 @@ struct Program {
     }
 };
 
+// Appends src's descriptors and launches to dst (offsets moved to where the
+// descriptors land in dst's blob).
+inline void append_program(Program &dst, const Program &src) {
+    if (src.blob.empty()) return;
+    const size_t base = dst.reserve_bytes(src.blob.size());
+    std::memcpy(dst.blob.data() + base, src.blob.data(), src.blob.size());
+    for (Launch l : src.launches) {
+        l.off += base;
+        dst.launches.push_back(l);
+    }
+    dst.ks_jobs += src.ks_jobs;
+}
+
 // Builders.  Key switches and products are split into chunks that reuse the
 // scratch region [scratch, scratch + chunk * per-job words) in stream order.
 void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs, uint32_t *scratch,

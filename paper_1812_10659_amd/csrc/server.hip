@@ -24,6 +24,7 @@ constexpr uint32_t SRV_KS_CHUNK = 256;
 constexpr uint32_t SRV_MUL_CHUNK = 16;
 constexpr uint32_t SRV_LOOKAHEAD = 2;   // rounds in flight per model
 constexpr uint32_t SRV_LANE_MIN = 16;   // requests in flight from which a round runs as two lanes
+constexpr uint32_t SRV_SOLO_WAVES = 8;  // waves a lone request takes per round
 
 struct Pending {
     uint64_t tag;
@@ -112,25 +113,52 @@ int round_model(lola_server *srv, Model &m) {
     std::vector<Slot *> active, finishing;
     for (Slot &s : m.slots)
         if (s.busy && !s.finished) active.push_back(&s);
-    const uint32_t n_lanes = (m.stream2 && active.size() >= SRV_LANE_MIN) ? 2 : 1;
+    // A lone request (one in flight, none queued) takes up to SRV_SOLO_WAVES
+    // waves per round (as many as fit one descriptor slab): with nothing to
+    // batch it with, host work between single waves would add to its
+    // latency, while a request arriving meanwhile waits at most one such
+    // round (about half a millisecond for the MNIST-shaped plan) before the
+    // two are batched at their own depths.
+    const bool solo = active.size() == 1 && m.queue.empty();
+    const uint32_t n_lanes = (!solo && m.stream2 && active.size() >= SRV_LANE_MIN) ? 2 : 1;
     const size_t half = (active.size() + 1) / 2;
     LevelJobs jobs[2];
-    for (size_t k = 0; k < active.size(); ++k) {
-        Slot &s = *active[k];
+    Program prog[2];
+    size_t n_jobs = 0;
+    if (solo) {
+        Slot &s = *active[0];
         ReqView rv{&s.rq, s.regs, s.sq, s.hoist};
-        int rc = emit_level(m.ctx, p, rv, s.level, jobs[n_lanes == 2 && k >= half ? 1 : 0]);
-        if (rc) return rc;
-        if (++s.level > p->n_waves) finishing.push_back(&s);
+        for (uint32_t w = 0; w < SRV_SOLO_WAVES && s.level <= p->n_waves; ++w) {
+            LevelJobs lj;
+            int rc = emit_level(m.ctx, p, rv, s.level, lj);
+            if (rc) return rc;
+            Program one;
+            program_level(m.ctx, one, lj, m.scratch, SRV_KS_CHUNK, SRV_MUL_CHUNK);
+            if (!prog[0].launches.empty() && prog[0].blob.size() + one.blob.size() + 256 > lola_ctx::RING_SLAB) break;
+            append_program(prog[0], one);
+            n_jobs += lj.count();
+            ++s.level;
+        }
+        if (s.level > p->n_waves) finishing.push_back(&s);
+    } else {
+        for (size_t k = 0; k < active.size(); ++k) {
+            Slot &s = *active[k];
+            ReqView rv{&s.rq, s.regs, s.sq, s.hoist};
+            int rc = emit_level(m.ctx, p, rv, s.level, jobs[n_lanes == 2 && k >= half ? 1 : 0]);
+            if (rc) return rc;
+            if (++s.level > p->n_waves) finishing.push_back(&s);
+        }
+        n_jobs = jobs[0].count() + jobs[1].count();
     }
-    if (jobs[0].count() + jobs[1].count() == 0) return LOLA_OK;
+    if (n_jobs == 0) return LOLA_OK;
     while (m.inflight.size() >= SRV_LOOKAHEAD) {
         int rc = retire(m, srv->completed, true);
         if (rc) return rc;
     }
-    Program prog[2];
     void *blob[2] = {nullptr, nullptr};
     for (uint32_t l = 0; l < n_lanes; ++l) {
-        program_level(m.ctx, prog[l], jobs[l], l ? m.scratch2 : m.scratch, SRV_KS_CHUNK, SRV_MUL_CHUNK);
+        if (!solo)
+            program_level(m.ctx, prog[l], jobs[l], l ? m.scratch2 : m.scratch, SRV_KS_CHUNK, SRV_MUL_CHUNK);
         // both lanes' descriptors go up on the model's stream before the fork,
         // so the descriptor ring's reuse events (recorded on that stream, after
         // this round's join) cover the second lane's reads too
@@ -152,7 +180,7 @@ int round_model(lola_server *srv, Model &m) {
         LOLA_HIP(hipStreamWaitEvent(m.stream, m.join_ev, 0));
     }
     if (rc) return rc;
-    m.launched_jobs += jobs[0].count() + jobs[1].count();
+    m.launched_jobs += n_jobs;
     hipEvent_t ev;
     if (m.free_events.empty()) LOLA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     else { ev = m.free_events.back(); m.free_events.pop_back(); }
