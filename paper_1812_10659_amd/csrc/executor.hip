@@ -58,10 +58,11 @@ int emit_level(const lola_ctx *ctx, const lola_plan *p, const ReqView &rv, uint3
             case OP_LINCOMB: {
                 LinJob j{};
                 for (size_t k = 0; k < o.srcs.size(); ++k) j.srcs[k] = ptr(o.srcs[k]);
-                j.w = p->d_wtab[i];
-                j.add = o.cadd >= 0 ? p->d_cadd[o.cadd] : nullptr;
-                j.dst = dst;
+                j.w[0] = p->d_wtab[i];
+                j.add[0] = o.cadd >= 0 ? p->d_cadd[o.cadd] : nullptr;
+                j.dst[0] = dst;
                 j.n_src = (uint32_t)o.srcs.size();
+                j.n_dst = 1;
                 out.lin.push_back(j);
                 break;
             }
@@ -129,7 +130,7 @@ size_t level_scratch_words(const lola_ctx *ctx, uint32_t ks_chunk, uint32_t mul_
 
 void program_level(const lola_ctx *ctx, Program &prog, LevelJobs &jobs, uint32_t *scratch, uint32_t ks_chunk,
                    uint32_t mul_chunk) {
-    prog.launch(LK_LIN, jobs.lin);
+    prog.launch(LK_LIN, group_lincombs(jobs.lin));
     prog.launch(LK_PLAIN, jobs.plain);
     if (!jobs.muls.empty()) {
         program_mul(ctx, prog, jobs.muls, scratch, mul_chunk);
@@ -359,7 +360,8 @@ int lola_plan_load(lola_ctx *ctx, lola_plan *p, lola_stream stream) {
         // the slot staging buffer is reused: wait for this constant's upload
         if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = set_error(LOLA_E_DEVICE, "constant upload");
     }
-    // linear-combination scalars: [w]_t reduced per prime, with Shoup companions
+    // linear-combination scalars: [w]_t reduced per prime, and in Montgomery
+    // form (w 2^32 mod q) for the kernel's 64-bit multiply-add
     for (size_t i = 0; i < p->ops.size() && !rc; ++i) {
         const Op &o = p->ops[i];
         if (o.kind != OP_LINCOMB) continue;
@@ -373,7 +375,7 @@ int lola_plan_load(lola_ctx *ctx, lola_plan *p, lola_stream stream) {
                 int64_t r = w % q;
                 if (r < 0) r += q;
                 tab[(2 * k) * L + j] = (uint32_t)r;
-                tab[(2 * k + 1) * L + j] = shoup_companion((uint32_t)r, (uint32_t)q);
+                tab[(2 * k + 1) * L + j] = (uint32_t)mulmod_host((uint64_t)r, (1ull << 32) % (uint64_t)q, (uint64_t)q);
             }
         }
         if (hipMalloc(&wtab[i], tab.size() * 4) != hipSuccess) rc = set_error(LOLA_E_NOMEM, "table allocation");

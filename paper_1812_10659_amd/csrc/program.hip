@@ -3,15 +3,24 @@
 
 namespace lola {
 
-// dst = sum_k w_k src_k (+ add on component 0).  grid (2LN/4/256, jobs)
+// dst[d] = sum_k w[d]_k src_k (+ add[d] on component 0) for the job's n_dst
+// outputs.  grid (2LN/4/256, jobs)
 //
 // A block's 1024 words lie in one limb (N >= 1024), so the limb and the
 // weights are uniform and come from scalar loads.  Sources are taken in
 // groups of LIN_GROUP with all their loads issued before any product: a
 // group past the last source repeats the last source's address with weight
 // 0 (a zero term), which keeps the group one straight block instead of a
-// test and a wait per source.
-constexpr uint32_t LIN_GROUP = 8;
+// test and a wait per source.  Each source word is loaded once for all the
+// job's outputs.  The weights are in Montgomery form (w' = w 2^32 mod q),
+// every term x w' (< q^2 < 2^60) is added into a 64-bit accumulator with one
+// multiply-add, and one Montgomery reduction at the end gives
+// sum_k x_k w_k mod q.  Every LIN_LAZY terms the accumulator is brought back
+// below q^2 without changing its residue: r = acc 2^-32 mod q, acc = r (2^32
+// mod q), so at most LIN_LAZY terms and one such value (13 q^2 < 2^64) are
+// ever summed.
+constexpr uint32_t LIN_GROUP = 4, LIN_LAZY = 12;
+static_assert(LIN_LAZY % LIN_GROUP == 0, "reductions fall between groups of sources");
 
 __global__ void lin_kernel(const LinJob *__restrict__ jobs, uint32_t logN, uint32_t L,
                            const ModConst *__restrict__ mcs) {
@@ -21,30 +30,53 @@ __global__ void lin_kernel(const LinJob *__restrict__ jobs, uint32_t logN, uint3
     if (i >= n4) return;
     const uint32_t cl = (uint32_t)(((size_t)blockIdx.x * blockDim.x * 4) >> logN);   // component * L + limb
     const uint32_t limb = cl % L;
-    const uint32_t q = mcs[limb].q;
-    const uint32_t n = job.n_src;
-    uint4 acc = make_uint4(0, 0, 0, 0);
+    const ModConst mc = mcs[limb];
+    const uint32_t q = mc.q;
+    const uint32_t n = job.n_src, nd = job.n_dst;
+    uint64_t acc[LIN_OUT][4];
+#pragma unroll
+    for (uint32_t d = 0; d < LIN_OUT; ++d)
+        for (uint32_t c = 0; c < 4; ++c) acc[d][c] = 0;
     for (uint32_t k0 = 0; k0 < n; k0 += LIN_GROUP) {
         uint4 x[LIN_GROUP];
 #pragma unroll
         for (uint32_t b = 0; b < LIN_GROUP; ++b) x[b] = ((const uint4 *)job.srcs[min(k0 + b, n - 1)])[i];
+        const bool reduce = (k0 + LIN_GROUP) % LIN_LAZY == 0 && k0 + LIN_GROUP < n;
 #pragma unroll
-        for (uint32_t b = 0; b < LIN_GROUP; ++b) {
-            // weights of the clamped source, masked to 0 past the last one
-            const uint32_t k = min(k0 + b, n - 1), mask = 0u - (uint32_t)(k0 + b < n);
-            const uint32_t w = job.w[(2 * k) * L + limb] & mask, wp = job.w[(2 * k + 1) * L + limb] & mask;
-            acc.x = add_mod(acc.x, shoup(x[b].x, w, wp, q), q);
-            acc.y = add_mod(acc.y, shoup(x[b].y, w, wp, q), q);
-            acc.z = add_mod(acc.z, shoup(x[b].z, w, wp, q), q);
-            acc.w = add_mod(acc.w, shoup(x[b].w, w, wp, q), q);
+        for (uint32_t d = 0; d < LIN_OUT; ++d) {
+            if (d >= nd) break;
+            const uint32_t *wt = job.w[d];
+#pragma unroll
+            for (uint32_t b = 0; b < LIN_GROUP; ++b) {
+                // the clamped source's Montgomery weight, masked to 0 past the last one
+                const uint32_t k = min(k0 + b, n - 1), mask = 0u - (uint32_t)(k0 + b < n);
+                const uint32_t w = wt[(2 * k + 1) * L + limb] & mask;
+                acc[d][0] += (uint64_t)x[b].x * w;
+                acc[d][1] += (uint64_t)x[b].y * w;
+                acc[d][2] += (uint64_t)x[b].z * w;
+                acc[d][3] += (uint64_t)x[b].w * w;
+            }
+            if (reduce) {
+#pragma unroll
+                for (uint32_t c = 0; c < 4; ++c)
+                    acc[d][c] = (uint64_t)acc_reduce_mont(Acc64{(uint32_t)acc[d][c], (uint32_t)(acc[d][c] >> 32)}, mc) *
+                                mc.r_mod;
+            }
         }
     }
-    if (job.add && cl < L) {
-        const uint4 y = ((const uint4 *)job.add)[i];
-        acc = make_uint4(add_mod(acc.x, y.x, q), add_mod(acc.y, y.y, q), add_mod(acc.z, y.z, q),
-                         add_mod(acc.w, y.w, q));
+#pragma unroll
+    for (uint32_t d = 0; d < LIN_OUT; ++d) {
+        if (d >= nd) break;
+        uint32_t r[4];
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c) r[c] = acc_reduce_mont(Acc64{(uint32_t)acc[d][c], (uint32_t)(acc[d][c] >> 32)}, mc);
+        if (job.add[d] && cl < L) {
+            const uint4 y = ((const uint4 *)job.add[d])[i];
+            r[0] = add_mod(r[0], y.x, q), r[1] = add_mod(r[1], y.y, q), r[2] = add_mod(r[2], y.z, q),
+            r[3] = add_mod(r[3], y.w, q);
+        }
+        ((uint4 *)job.dst[d])[i] = make_uint4(r[0], r[1], r[2], r[3]);
     }
-    ((uint4 *)job.dst)[i] = acc;
 }
 
 // dst = src * mul (+ add on component 0).  grid (2LN/4/256, jobs)
@@ -71,12 +103,14 @@ __global__ void plain_kernel(const PlainJob *__restrict__ jobs, uint32_t logN, u
 }
 
 // Cost: the launch's distinct sources and constants are read once (2LN and
-// LN words), every job writes its ciphertext; each source word of each job
-// takes a Shoup product and an add, each constant word an add.
+// LN words), every output ciphertext is written; each source word takes a
+// modular product and an add per output (counted so although the kernel
+// multiply-adds into 64 bits and reduces every 16 terms), each constant word
+// an add.
 int launch_lin_dev(lola_ctx *ctx, const LinJob *d, uint32_t n, const uint64_t *aux, hipStream_t s) {
     const size_t n4 = (size_t)2 * ctx->L * ctx->N / 4;
     const double ln = (double)ctx->L * ctx->N;
-    LOLA_TIMED(ctx, s, KID_LIN, n, 4 * ln * (2.0 * (aux[1] + n) + aux[3]),
+    LOLA_TIMED(ctx, s, KID_LIN, aux[4], 4 * ln * (2.0 * (aux[1] + aux[4]) + aux[3]),
                ln * (2.0 * aux[0] * (COST_MUL + COST_ADD) + aux[2] * COST_ADD),
                hipLaunchKernelGGL(lin_kernel, dim3((unsigned)((n4 + 255) / 256), n), dim3(256), 0, s, d, ctx->logN,
                                   ctx->L, ctx->d_mc));

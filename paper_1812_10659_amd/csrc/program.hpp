@@ -12,13 +12,48 @@ namespace lola {
 
 // Element-wise jobs (one ciphertext each, 2 L N words).
 constexpr uint32_t LIN_MAX = 32;   // sources of one linear combination
-struct LinJob {              // dst = sum_k w_k src_k (+ add-form constant on c0)
+constexpr uint32_t LIN_OUT = 8;    // outputs of one job (combinations of the same sources)
+struct LinJob {              // dst[d] = sum_k w[d]_k src_k (+ add-form constant add[d] on c0), d < n_dst
     const uint32_t *srcs[LIN_MAX];
-    const uint32_t *w;             // device [n_src][2][L]: residue, Shoup companion per limb
-    const uint32_t *add;           // [L][N] add-form constant or null
-    uint32_t *dst;
-    uint32_t n_src, pad;
+    const uint32_t *w[LIN_OUT];    // device [n_src][2][L]: residue, Montgomery form (w 2^32 mod q) per limb
+    const uint32_t *add[LIN_OUT];  // [L][N] add-form constant or null
+    uint32_t *dst[LIN_OUT];
+    uint32_t n_src, n_dst;
 };
+
+// Merges single-output jobs whose source lists are equal (the maps of a
+// convolution over the same input messages) into jobs of up to LIN_OUT
+// outputs, so each source is read once for all of them.  Order within a
+// launch does not matter: the jobs of one level are independent.
+inline std::vector<LinJob> group_lincombs(const std::vector<LinJob> &single) {
+    std::vector<LinJob> out;
+    std::vector<size_t> open;   // indices in out of groups that still take outputs
+    for (const LinJob &j : single) {
+        size_t g = out.size();
+        for (size_t k : open) {
+            const LinJob &c = out[k];
+            if (c.n_dst < LIN_OUT && c.n_src == j.n_src &&
+                std::equal(j.srcs, j.srcs + j.n_src, c.srcs)) {
+                g = k;
+                break;
+            }
+        }
+        if (g == out.size()) {
+            out.push_back(j);
+            open.push_back(g);
+            continue;
+        }
+        LinJob &c = out[g];
+        for (uint32_t d = 0; d < j.n_dst && c.n_dst < LIN_OUT; ++d) {
+            c.w[c.n_dst] = j.w[d];
+            c.add[c.n_dst] = j.add[d];
+            c.dst[c.n_dst] = j.dst[d];
+            ++c.n_dst;
+        }
+        if (c.n_dst == LIN_OUT) open.erase(std::find(open.begin(), open.end(), g));
+    }
+    return out;
+}
 struct PlainJob {            // dst = src * mul (+ add on c0); mul or add may be null
     const uint32_t *src;
     const uint32_t *mul;     // [L][N] Montgomery mul-form constant
@@ -39,14 +74,15 @@ enum LaunchKind : uint32_t {
 struct Launch {
     uint32_t kind, n;
     size_t off;              // byte offset of the descriptors in the blob
-    uint64_t aux[4] = {0, 0, 0, 0};   // job counts for the algorithmic cost (launch_aux)
+    uint64_t aux[6] = {0, 0, 0, 0, 0, 0};   // job counts for the algorithmic cost (launch_aux)
 };
 
 // What a launch's algorithmic cost depends on beyond its job count.  Bytes
 // count each distinct buffer a launch reads once (jobs of a batch share
 // sources, constants and keys, read from HBM once and then from cache);
 // lane-ops count every job's work.
-//   LinJob:   sum of n_src, distinct sources, jobs with a constant, distinct constants
+//   LinJob:   source-output terms, distinct sources, outputs with a constant,
+//             distinct constants, outputs
 //   PlainJob: jobs with a product, distinct product constants, jobs with an add, distinct add constants
 //   MulJob:   squares (a == b: one operand extended and read)
 //   KsJob:    distinct keys, distinct hoisting sources
@@ -59,15 +95,21 @@ inline uint64_t n_distinct(const std::vector<T> &v, F key) {
     return (uint64_t)(std::unique(k.begin(), k.end()) - k.begin());
 }
 inline void launch_aux(const std::vector<LinJob> &v, uint64_t *a) {
-    std::vector<const void *> src;
+    std::vector<const void *> src, add;
     for (const LinJob &j : v) {
-        a[0] += j.n_src;
-        a[2] += j.add != nullptr;
+        a[0] += (uint64_t)j.n_src * j.n_dst;
+        a[4] += j.n_dst;
         src.insert(src.end(), j.srcs, j.srcs + j.n_src);
+        for (uint32_t d = 0; d < j.n_dst; ++d)
+            if (j.add[d]) {
+                ++a[2];
+                add.push_back(j.add[d]);
+            }
     }
     std::sort(src.begin(), src.end());
     a[1] = (uint64_t)(std::unique(src.begin(), src.end()) - src.begin());
-    a[3] = n_distinct(v, [](const LinJob &j) { return (const void *)j.add; });
+    std::sort(add.begin(), add.end());
+    a[3] = (uint64_t)(std::unique(add.begin(), add.end()) - add.begin());
 }
 inline void launch_aux(const std::vector<PlainJob> &v, uint64_t *a) {
     for (const PlainJob &j : v) {
