@@ -118,9 +118,16 @@ uint32_t lola_galois_element(uint32_t N, int32_t step);
  * [L][2][L+1][N] (caller-owned device buffers, written).  Errors:
  * LOLA_E_INVAL (null pointer, bad Galois element).
  * Random values come from ChaCha20 (RFC 8439) with key = (seed lo, seed hi,
- * 0...), nonce = (domain, object, limb), one 64-bit word per coefficient;
- * uniform = word mod m, ternary = word mod 3 - 1, error = centred binomial
- * popcount(w & 0x1fffff) - popcount((w >> 21) & 0x1fffff). */
+ * k2..k7), k2..k7 the context's key words, nonce = (domain, object, limb),
+ * one 64-bit word per coefficient; uniform = word mod m, ternary = word mod 3
+ * - 1, error = centred binomial popcount(w & 0x1fffff) - popcount((w >> 21)
+ * & 0x1fffff).  Security: the secret key, the switching keys and every
+ * encryption's randomness follow from the key, so seed and key words must be
+ * secret and uniformly random; with the key words left at zero the key has
+ * only the seed's 64 bits, fit for tests, not for deployment.
+ * lola_set_key_words sets k2..k7 (words_host: 6 words; NULL = zeros) for
+ * every later key generation and encryption on the context (a 256-bit key). */
+int lola_set_key_words(lola_ctx *ctx, const uint32_t *words_host);
 int lola_keygen_secret(lola_ctx *ctx, uint64_t seed, uint32_t *sk_dev, lola_stream stream);
 int lola_keygen_public(lola_ctx *ctx, uint64_t seed, const uint32_t *sk_dev, uint32_t *pk_dev,
                        lola_stream stream);
@@ -240,7 +247,8 @@ int lola_rotate_hoisted(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n, const
  * their best so far, runs a batch of n_jobs (1..128) rotations on synthetic
  * residues with every variant, checks each one's output words against the
  * default's (LOLA_E_DEVICE on a difference), times the whole key switch
- * reps times, and keeps the fastest per stage in the context (chosen[3]).
+ * reps times, and keeps the fastest per stage in the context (chosen[3]),
+ * where a variant displaces the one before it only when at least 1% faster.
  * out receives one entry per variant timed, stages in order (ms = average
  * time of the batch); it allocates and synchronises. */
 typedef struct {

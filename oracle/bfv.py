@@ -33,7 +33,8 @@ the row-swap / column-rotation operations on the 2 x N/2 slot matrix):
             P; result (u - [u mod P]_P) / P mod q_j.
 
 Every random value is drawn from ChaCha20 (RFC 8439) with
-key = seed, nonce = (domain, object, limb), one 64-bit word per coefficient.
+key = the 256-bit seed's eight words (least significant first), nonce =
+(domain, object, limb), one 64-bit word per coefficient.
 """
 from __future__ import annotations
 
@@ -75,10 +76,10 @@ def lib():
         L.or_poly_mul_many.argtypes = [u64p, u64p, u64p, c_u32, u64p, c_u32]
         L.or_automorph.argtypes = [u64p, u64p, c_u32, c_u64, c_u64]
         L.or_chacha20_block.argtypes = [u32p, c_u32, u32p, u32p]
-        L.or_stream_words.argtypes = [c_u64, c_u32, c_u32, c_u32, c_u32, u64p]
-        L.or_sample_uniform.argtypes = [c_u64, c_u32, c_u32, c_u32, c_u32, c_u64, u64p]
-        L.or_sample_ternary.argtypes = [c_u64, c_u32, c_u32, c_u32, i64p]
-        L.or_sample_cbd.argtypes = [c_u64, c_u32, c_u32, c_u32, i64p]
+        L.or_stream_words.argtypes = [u32p, c_u32, c_u32, c_u32, c_u32, u64p]
+        L.or_sample_uniform.argtypes = [u32p, c_u32, c_u32, c_u32, c_u32, c_u64, u64p]
+        L.or_sample_ternary.argtypes = [u32p, c_u32, c_u32, c_u32, i64p]
+        L.or_sample_cbd.argtypes = [u32p, c_u32, c_u32, c_u32, i64p]
         L.or_max_threads.restype = ctypes.c_int
         L.or_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -130,27 +131,36 @@ def chacha20_block(key_words: Sequence[int], counter: int, nonce_words: Sequence
     return out
 
 
+def seed_key(seed: int) -> np.ndarray:
+    """The ChaCha20 key of a seed: its eight 32-bit words, least significant
+    first (seeds are integers in [0, 2^256); one below 2^64 leaves words 2..7
+    zero)."""
+    seed = int(seed)
+    assert 0 <= seed < 1 << 256
+    return np.array([(seed >> (32 * k)) & 0xFFFFFFFF for k in range(8)], np.uint32)
+
+
 def stream_words(seed: int, domain: int, obj: int, limb: int, n: int) -> np.ndarray:
     out = np.empty(n, np.uint64)
-    lib().or_stream_words(seed, domain, obj, limb, n, out)
+    lib().or_stream_words(seed_key(seed), domain, obj, limb, n, out)
     return out
 
 
 def sample_uniform(seed, domain, obj, limb, n, m) -> np.ndarray:
     out = np.empty(n, np.uint64)
-    lib().or_sample_uniform(seed, domain, obj, limb, n, m, out)
+    lib().or_sample_uniform(seed_key(seed), domain, obj, limb, n, m, out)
     return out
 
 
 def sample_ternary(seed, domain, obj, n) -> np.ndarray:
     out = np.empty(n, np.int64)
-    lib().or_sample_ternary(seed, domain, obj, n, out)
+    lib().or_sample_ternary(seed_key(seed), domain, obj, n, out)
     return out
 
 
 def sample_cbd(seed, domain, obj, n) -> np.ndarray:
     out = np.empty(n, np.int64)
-    lib().or_sample_cbd(seed, domain, obj, n, out)
+    lib().or_sample_cbd(seed_key(seed), domain, obj, n, out)
     return out
 
 

@@ -216,13 +216,13 @@ void or_chacha20_block(const uint32_t key[8], uint32_t counter, const uint32_t n
     for (int i = 0; i < 16; ++i) out[i] = x[i] + s[i];
 }
 
-/* The random word of coefficient i for stream (seed, domain, object, limb):
- * key = (lo32 seed, hi32 seed, 0,...,0), nonce = (domain, object, limb),
+/* The random word of coefficient i for stream (key, domain, object, limb):
+ * key = the eight 32-bit words of the 256-bit seed, least significant first
+ * (a seed below 2^64 leaves words 2..7 zero), nonce = (domain, object, limb),
  * block counter = i / 8, word = 64-bit little-endian word (i mod 8) of the
  * 64-byte block. */
-void or_stream_words(uint64_t seed, uint32_t domain, uint32_t object, uint32_t limb,
+void or_stream_words(const uint32_t *key, uint32_t domain, uint32_t object, uint32_t limb,
                      uint32_t n, uint64_t *out) {
-    uint32_t key[8] = {(uint32_t)seed, (uint32_t)(seed >> 32), 0, 0, 0, 0, 0, 0};
     uint32_t nonce[3] = {domain, object, limb};
     uint32_t blk[16];
     for (uint32_t i = 0; i < n; ++i) {
@@ -233,27 +233,27 @@ void or_stream_words(uint64_t seed, uint32_t domain, uint32_t object, uint32_t l
 }
 
 /* Uniform residue mod m: word mod m. */
-void or_sample_uniform(uint64_t seed, uint32_t domain, uint32_t object, uint32_t limb,
+void or_sample_uniform(const uint32_t *key, uint32_t domain, uint32_t object, uint32_t limb,
                        uint32_t n, uint64_t m, uint64_t *out) {
-    or_stream_words(seed, domain, object, limb, n, out);
+    or_stream_words(key, domain, object, limb, n, out);
     for (uint32_t i = 0; i < n; ++i) out[i] %= m;
 }
 
 /* Ternary value in {-1,0,1}: (word mod 3) - 1. */
-void or_sample_ternary(uint64_t seed, uint32_t domain, uint32_t object, uint32_t n,
+void or_sample_ternary(const uint32_t *key, uint32_t domain, uint32_t object, uint32_t n,
                        int64_t *out) {
     uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * n);
-    or_stream_words(seed, domain, object, 0, n, w);
+    or_stream_words(key, domain, object, 0, n, w);
     for (uint32_t i = 0; i < n; ++i) out[i] = (int64_t)(w[i] % 3) - 1;
     free(w);
 }
 
 /* Centred binomial with 21 coin pairs: popcount of the low 21 bits minus the
  * popcount of the next 21 bits (variance 10.5). */
-void or_sample_cbd(uint64_t seed, uint32_t domain, uint32_t object, uint32_t n,
+void or_sample_cbd(const uint32_t *key, uint32_t domain, uint32_t object, uint32_t n,
                    int64_t *out) {
     uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * n);
-    or_stream_words(seed, domain, object, 0, n, w);
+    or_stream_words(key, domain, object, 0, n, w);
     for (uint32_t i = 0; i < n; ++i) {
         uint64_t lo = w[i] & 0x1FFFFFull, hi = (w[i] >> 21) & 0x1FFFFFull;
         int64_t c = 0;

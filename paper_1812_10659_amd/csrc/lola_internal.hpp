@@ -117,6 +117,8 @@ struct lola_ctx {
     uint64_t timed_jobs = 0;                 // key switches issued while timing
     // batched NTT variant (index into the variant list of this N; 0 = default)
     uint32_t ntt_variant = 0;
+    // ChaCha20 key words 2..7 of every random stream (words 0, 1: the call's seed)
+    uint32_t key_hi[6] = {0, 0, 0, 0, 0, 0};
     // batched key-switch stage variants (0 digits, 1 inner, 2 mod-down; 0 = default)
     uint32_t ks_var[3] = {0, 0, 0};
     uint32_t idxP() const { return L; }

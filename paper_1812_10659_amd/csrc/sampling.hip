@@ -1,7 +1,8 @@
 // Randomness (ChaCha20, RFC 8439), key generation, encryption, decryption.
 //
 // Every random value is a 64-bit word of a ChaCha20 stream: key = (seed lo,
-// seed hi, 0, ..., 0), nonce = (domain, object, limb), block counter =
+// seed hi, k2, ..., k7) with k2..k7 the context's key words (zero unless set
+// with lola_set_key_words), nonce = (domain, object, limb), block counter =
 // coefficient / 8, word = coefficient mod 8.  Uniform residues are word mod m,
 // ternary values word mod 3 - 1, errors a centred binomial over 2 x 21 bits.
 #include <algorithm>
@@ -25,10 +26,14 @@ __device__ __forceinline__ uint32_t rotl(uint32_t x, int n) { return (x << n) | 
     a += b; d ^= a; d = rotl(d, 8);         \
     c += d; b ^= c; b = rotl(b, 7);
 
-__device__ void chacha20_block(uint32_t k0, uint32_t k1, uint32_t counter, uint32_t n0, uint32_t n1,
-                               uint32_t n2, uint32_t (&out)[16]) {
-    const uint32_t s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, k0, k1, 0, 0,
-                            0, 0, 0, 0, counter, n0, n1, n2};
+struct ChachaKey {
+    uint32_t w[8];
+};
+
+__device__ void chacha20_block(const ChachaKey &k, uint32_t counter, uint32_t n0, uint32_t n1, uint32_t n2,
+                               uint32_t (&out)[16]) {
+    const uint32_t s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, k.w[0], k.w[1], k.w[2], k.w[3],
+                            k.w[4], k.w[5], k.w[6], k.w[7], counter, n0, n1, n2};
     uint32_t x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) x[i] = s[i];
@@ -55,12 +60,12 @@ struct SampleJob {
 };
 
 // grid: (N/8 blocks of 8 coefficients / blockDim, jobs)
-__global__ void sample_kernel(const SampleJob *__restrict__ jobs, uint32_t N, uint32_t k0, uint32_t k1) {
+__global__ void sample_kernel(const SampleJob *__restrict__ jobs, uint32_t N, ChachaKey key) {
     const SampleJob job = jobs[blockIdx.y];
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= N / 8) return;
     uint32_t o[16];
-    chacha20_block(k0, k1, b, job.domain, job.object, job.limb, o);
+    chacha20_block(key, b, job.domain, job.object, job.limb, o);
 #pragma unroll
     for (int w = 0; w < 8; ++w) {
         const uint64_t word = (uint64_t)o[2 * w] | ((uint64_t)o[2 * w + 1] << 32);
@@ -82,8 +87,10 @@ static int launch_samples(lola_ctx *ctx, uint64_t seed, const std::vector<Sample
     int rc = desc_upload(ctx, jobs.data(), jobs.size() * sizeof(SampleJob), s, &d);
     if (rc) return rc;
     const uint32_t nb = ctx->N / 8;
+    ChachaKey key{{(uint32_t)seed, (uint32_t)(seed >> 32), 0, 0, 0, 0, 0, 0}};
+    for (int k = 0; k < 6; ++k) key.w[2 + k] = ctx->key_hi[k];
     hipLaunchKernelGGL(sample_kernel, dim3((nb + 127) / 128, (unsigned)jobs.size()), dim3(128), 0, s,
-                       (const SampleJob *)d, ctx->N, (uint32_t)seed, (uint32_t)(seed >> 32));
+                       (const SampleJob *)d, ctx->N, key);
     LOLA_HIP(hipGetLastError());
     return LOLA_OK;
 }
@@ -211,6 +218,12 @@ __global__ void dec_round_kernel(const uint32_t *__restrict__ x, uint32_t *__res
 using namespace lola;
 
 extern "C" {
+
+int lola_set_key_words(lola_ctx *ctx, const uint32_t *words_host) {
+    if (!ctx) return set_error(LOLA_E_INVAL, "null argument");
+    for (int k = 0; k < 6; ++k) ctx->key_hi[k] = words_host ? words_host[k] : 0u;
+    return LOLA_OK;
+}
 
 int lola_keygen_secret(lola_ctx *ctx, uint64_t seed, uint32_t *sk, lola_stream stream) {
     if (!ctx || !sk) return set_error(LOLA_E_INVAL, "null argument");

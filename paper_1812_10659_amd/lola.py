@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
             "lola_ks_get_variant": [vp, u32, ctypes.POINTER(u32)],
             "lola_ks_set_variant": [vp, u32, u32],
             "lola_ks_autotune": [vp, u32, u32, ctypes.POINTER(KsVariant), u32, ctypes.POINTER(u32), vp],
+            "lola_set_key_words": [vp, ctypes.POINTER(u32)],
             "lola_strerror": [i32],
             "lola_last_error": [],
         }
@@ -185,6 +186,12 @@ class Context:
         _check(lib().lola_reserve(self.h, n_ct))
 
     # ---- keys
+    def set_key_words(self, words) -> None:
+        """ChaCha20 key words 2..7 (six 32-bit values) for every later key
+        generation and encryption; None = zeros (the 64-bit seed alone)."""
+        arr = None if words is None else (ctypes.c_uint32 * 6)(*[int(w) & 0xFFFFFFFF for w in words])
+        _check(lib().lola_set_key_words(self.h, arr))
+
     def keygen_secret(self, seed: int) -> torch.Tensor:
         sk = self.empty(self.L + 1, self.N)
         _check(lib().lola_keygen_secret(self.h, seed, _p(sk), _stream()))
@@ -387,7 +394,7 @@ class Context:
     def ks_set_variant(self, stage: int, index: int) -> None:
         _check(lib().lola_ks_set_variant(self.h, int(stage), int(index)))
 
-    def ks_autotune(self, n_jobs: int = 64, reps: int = 3):
+    def ks_autotune(self, n_jobs: int = 128, reps: int = 10):
         """Times every key-switch stage variant (a batch of n_jobs rotations,
         each variant's words checked against the default first), keeps the
         fastest per stage; returns (chosen [3], [(stage, index, split,

@@ -43,7 +43,7 @@ def chacha20_block(key: List[int], counter: int, nonce: List[int]) -> List[int]:
 
 
 def words(seed, domain, obj, limb, n):
-    key = [seed & MASK32, (seed >> 32) & MASK32] + [0] * 6
+    key = [(seed >> (32 * k)) & MASK32 for k in range(8)]   # the 256-bit seed, low word first
     out = []
     for i in range(n):
         blk = chacha20_block(key, i // 8, [domain, obj, limb])

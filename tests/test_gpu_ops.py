@@ -407,9 +407,42 @@ def test_ks_autotune_keeps_the_words(env):
     assert [ctx.ks_variant(st) for st in range(3)] == chosen
     for st in range(3):
         times = [ms for s, _, _, _, ms in table if s == st]
-        assert times[chosen[st]] == min(times)
+        # kept: no other variant is more than 1% faster than the chosen one
+        assert min(times) >= 0.99 * times[chosen[st]] - 1e-6 or times[chosen[st]] == min(times)
     outs = ctx.keyswitch_batch(items)
     for k, o in enumerate(outs):
         assert np.array_equal(_down(ctx, o), np.stack(refs[k])), f"job {k} after autotuning"
     for st in range(3):
         ctx.ks_set_variant(st, 0)
+
+
+def test_keys_and_encryption_with_256_bit_key(env):
+    """Key words 2..7 set on the context (a full 256-bit ChaCha20 key): the
+    secret, public and switching keys and an encryption equal the oracle's
+    under the 256-bit seed; the words are reset afterwards."""
+    from paper_1812_10659_amd import lola
+    ctx, octx, p = env["ctx"], env["octx"], env["p"]
+    words = [(0x9E3779B9 * (k + 3)) & 0xFFFFFFFF for k in range(6)]
+    lo = 0x0123_4567_89AB_CDEF
+    big = lo | sum(w << (64 + 32 * k) for k, w in enumerate(words))
+    g = env["gal"][0]
+    ok = bfv.keygen(octx, big, [g], relin=False)
+    ctx.set_key_words(words)
+    try:
+        sk = ctx.keygen_secret(lo)
+        pk = ctx.keygen_public(lo, sk)
+        gk = ctx.keygen_switch(lo, sk, g)
+        m = env["m"][1]
+        ct = ctx.encrypt(pk, lola.from_numpy_u32(m.astype(np.uint32), ctx.device), lo ^ 0x55, 9)
+    finally:
+        ctx.set_key_words(None)
+    assert np.array_equal(_u32(ctx.export_sk(sk)).astype(np.uint64), octx.small_to_limbs(ok.sk.s, octx.moduli))
+    pkh = _u32(ctx.export_pk(pk)).astype(np.uint64)
+    assert np.array_equal(pkh[0], ok.pk0) and np.array_equal(pkh[1], ok.pk1)
+    k = _u32(ctx.export_ksk(gk)).astype(np.uint64)
+    assert np.array_equal(k[:, 0], ok.galois[g].b) and np.array_equal(k[:, 1], ok.galois[g].a)
+    oc = bfv.encrypt(octx, ok, m, (lo ^ 0x55) | (big >> 64 << 64), 9)
+    got = _down(ctx, ct)
+    assert np.array_equal(got[0], oc[0]) and np.array_equal(got[1], oc[1])
+    # the same seed without the key words gives other keys
+    assert not np.array_equal(_u32(ctx.export_sk(ctx.keygen_secret(lo))), _u32(ctx.export_sk(sk)))

@@ -120,3 +120,26 @@ def test_decrypt_of_size3_match(setup):
     p, ctx, tiny, gs, keys, bkeys, (m1, m2), (c1, c2), (b1, b2) = setup
     d = bfv.mul(ctx, c1, c2)
     assert list(bfv.decrypt(ctx, keys, d)) == tiny.decrypt(bkeys, tiny.mul(b1, b2))
+
+
+def test_256_bit_seed_keys_and_encryption_match():
+    """A seed with all eight key words set (a full 256-bit ChaCha20 key): the
+    oracle's keys and encryption equal the brute force's word for word, and
+    differ from those of the same seed's low 64 bits alone."""
+    p = TINY[0]
+    ctx = bfv.Context(p)
+    tiny = bf.Tiny(p.N, p.t, p.q, p.P)
+    g = [bfv.galois_element(p.N, 1)]
+    seed = int.from_bytes(bytes(range(1, 33)), "little")
+    keys, bkeys = bfv.keygen(ctx, seed, g), tiny.keygen(seed, g)
+    assert list(keys.sk.s) == bkeys["s"]
+    assert np.array_equal(keys.pk0, _np(bkeys["pk0"])) and np.array_equal(keys.pk1, _np(bkeys["pk1"]))
+    b, a = bkeys["gal"][g[0]]
+    for i in range(ctx.L):
+        for j in range(ctx.L + 1):
+            assert list(keys.galois[g[0]].b[i, j]) == b[i][j] and list(keys.galois[g[0]].a[i, j]) == a[i][j]
+    m = np.arange(p.N) % p.t
+    _eq(bfv.encrypt(ctx, keys, m, seed + 5, 2), tiny.encrypt(bkeys, [int(v) for v in m], seed + 5, 2))
+    low = bfv.keygen(ctx, seed & ((1 << 64) - 1), g)
+    assert not np.array_equal(low.pk0, keys.pk0)
+    assert list(bfv.seed_key(seed)) == [int.from_bytes(bytes(range(4 * k + 1, 4 * k + 5)), "little") for k in range(8)]
