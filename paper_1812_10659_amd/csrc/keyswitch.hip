@@ -40,12 +40,12 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
                                                                      const TwPair *__restrict__ tw,
                                                                      const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[2 << LOGN];   // two halves for the plain placement
-    const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1, n);
+    // target modulus: q_j (j < L) or P (j == L); the special prime's unit,
+    // half again as long as the others, is dispatched ahead of the XCD's
+    // other units so the launch's tail holds short ones
+    const JobUnit ju = xcd_job_unit_lead(blockIdx.x, L + 1, 1, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
-    // target modulus: q_j (j < L) or P (j == L); the special prime's unit,
-    // half again as long as the others, is dispatched first of its job so the
-    // launch's tail holds short units
     const uint32_t j = ju.unit == 0 ? L : ju.unit - 1;
     ks_stage_inner<LOGN, KSI>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
 }
@@ -137,11 +137,14 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_hoisted_inner_kernel(
     const KsJob *__restrict__ jobs, uint32_t n, uint32_t L, const ModConst *__restrict__ mcs,
     const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
-    const JobUnit ju = xcd_job_unit(blockIdx.x, L + 1, n);
+    // L + 2 units per job: the special prime's two (one per key component,
+    // each with an inverse transform, so the longest) ahead of the XCD's
+    // other units, then q_0..q_{L-1}
+    const JobUnit ju = xcd_job_unit_lead(blockIdx.x, L + 2, 2, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
-    const uint32_t j = ju.unit == 0 ? L : ju.unit - 1;
-    ks_stage_hoisted_inner<LOGN>(job.key, job.x, job.hoist, job.scratch, job.galois, j, L, sh, mcs[j], itw);
+    const uint32_t j = ju.unit < 2 ? L : ju.unit - 2, c = ju.unit < 2 ? ju.unit : 0;
+    ks_stage_hoisted_inner<LOGN>(job.key, job.x, job.hoist, job.scratch, job.galois, j, c, L, sh, mcs[j], itw);
 }
 
 template <int LOGN, int SPLIT = 0, bool PAD = true>
@@ -379,7 +382,7 @@ int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, c
 #define LOLA_HR_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
         LOLA_TIMED(ctx, s, KID_KS_HOISTED_INNER, n, c.hoist_b(n, (double)aux[0], (double)aux[1]), c.hoist_o() * n, \
-                   hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 1)), block, 0, s, d_jobs, \
+                   hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 2)), block, 0, s, d_jobs, \
                                       n, L, ctx->d_mc, ctx->d_itw));                                          \
         LOLA_TIMED(ctx, s, KID_KS_HOIST_MODDOWN, n * 2 * L, c.moddown_b() * n * 2 * L, c.moddown_o() * n * 2 * L, \
                    launch_ks_moddown<LG>(ctx, d_jobs, n, s));                                                 \

@@ -44,9 +44,23 @@ constexpr uint32_t N_XCD = 8;
 struct JobUnit {
     uint32_t job, unit;
 };
-__device__ __forceinline__ JobUnit xcd_job_unit(uint32_t k, uint32_t units, uint32_t n) {
+__host__ __device__ inline JobUnit xcd_job_unit(uint32_t k, uint32_t units, uint32_t n) {
     const uint32_t x = k % N_XCD, r = k / N_XCD, per_xcd = (n + N_XCD - 1) / N_XCD;
     return JobUnit{x * per_xcd + r / units, r % units};
+}
+// As xcd_job_unit, for jobs whose first `lead` units are the long ones: within
+// each XCD those of all its jobs come first (in job order), then the other
+// units of each job in turn.  The workgroups an XCD receives are dispatched in
+// block order over its CUs, so the long units start first and the launch's
+// tail holds short ones (longest first, as a list schedule wants; with each
+// job's long unit ahead of only its own short ones, 13 jobs on an XCD's 32
+// CUs leave a tail about 10% longer).
+__host__ __device__ inline JobUnit xcd_job_unit_lead(uint32_t k, uint32_t units, uint32_t lead, uint32_t n) {
+    const uint32_t x = k % N_XCD, r = k / N_XCD, per_xcd = (n + N_XCD - 1) / N_XCD;
+    const uint32_t head = per_xcd * lead;
+    if (r < head) return JobUnit{x * per_xcd + r / lead, r % lead};
+    const uint32_t t = r - head, rest = units - lead;
+    return JobUnit{x * per_xcd + t / rest, lead + t % rest};
 }
 // Grid size for n jobs of `units` workgroups each (ids past the last job exit).
 inline uint32_t xcd_grid(uint32_t n, uint32_t units) { return (n + N_XCD - 1) / N_XCD * N_XCD * units; }
@@ -449,58 +463,70 @@ __device__ __forceinline__ void ks_stage_modup(uint32_t *hoist, uint32_t j, uint
     store_spectral<LOGN>(gbuf(hoist + (ks_hoist_limb(L, j, i) << LOGN), N), tid, x);
 }
 
+// Digit limb src (NTT form) read through sigma_g at this thread's positions:
+// staged in LDS with coalesced 16-byte loads, then gathered.  Uses sh (N
+// words) between two workgroup barriers.
+template <int LOGN>
+__device__ __forceinline__ void ks_hoist_gather(const uint32_t *src, uint32_t g, uint32_t tid, uint32_t *sh,
+                                                uint32_t (&xv)[NTT_E]) {
+    constexpr uint32_t N = 1u << LOGN, T = N / NTT_E;
+    const GBuf S = gbuf(src, N);
+    __syncthreads();   // the previous digit's gathers are done
+#pragma unroll
+    for (uint32_t r = 0; r < NTT_E / 4; ++r) {
+        const uint32_t w = 4 * (tid + r * T);
+        const u32x4 v = gld4(S, w);
+        sh[w] = v.x, sh[w + 1] = v.y, sh[w + 2] = v.z, sh[w + 3] = v.w;
+    }
+    __syncthreads();
+    // The gather addresses are the same for every digit; an opaque copy of g
+    // keeps the compiler from holding all 16 across the caller's loop.
+    uint32_t gi = g;
+    asm volatile("" : "+s"(gi));
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) xv[r] = sh[galois_src_index(spectral_index<LOGN>(tid, r), gi, LOGN)];
+}
+
 // Inner product of one hoisted rotation for target modulus m_j: each digit's
-// transform (c1's own limb when i == j) is staged in LDS with coalesced
-// 16-byte loads, read back through sigma_g, and multiplied by the key as in
-// ks_stage_inner, whose results (U, or the special prime's sums back in
-// coefficients) it writes to the same places.
+// transform (c1's own limb when i == j) is read through sigma_g and
+// multiplied by the key as in ks_stage_inner, whose results (U, or the
+// special prime's sums back in coefficients) it writes to the same places.
+// A data prime's workgroup forms both key components' sums; the special
+// prime has one workgroup per component c, each with one 64-bit sum and one
+// inverse transform (both sums live across two transforms do not fit the
+// register file).
 template <int LOGN>
 __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, const uint32_t *x,
                                                        const uint32_t *hoist, uint32_t *scratch, uint32_t g,
-                                                       uint32_t j, uint32_t L, uint32_t *sh, const ModConst &mc,
-                                                       const TwPair *itw) {
-    constexpr uint32_t N = 1u << LOGN, T = N / NTT_E;
+                                                       uint32_t j, uint32_t c, uint32_t L, uint32_t *sh,
+                                                       const ModConst &mc, const TwPair *itw) {
+    constexpr uint32_t N = 1u << LOGN;
     const uint32_t M = L + 1;
-    uint64_t a0[NTT_E], a1[NTT_E];
-#pragma unroll
-    for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-#pragma unroll 1
-    for (uint32_t i = 0; i < L; ++i) {
-        const uint32_t *src = i == j ? x + ((size_t)i << LOGN) : hoist + (ks_hoist_limb(L, j, i) << LOGN);
-        const GBuf S = gbuf(src, N);
-        __syncthreads();   // the previous digit's gathers are done
-#pragma unroll
-        for (uint32_t r = 0; r < NTT_E / 4; ++r) {
-            const uint32_t w = 4 * (tid + r * T);
-            const u32x4 v = gld4(S, w);
-            sh[w] = v.x, sh[w + 1] = v.y, sh[w + 2] = v.z, sh[w + 3] = v.w;
-        }
-        __syncthreads();
-        // The gather addresses are the same for every digit; an opaque copy
-        // of g keeps the compiler from holding all 16 across the loop (with
-        // the accumulators that spilled registers to scratch memory).
-        uint32_t gi = g;
-        asm volatile("" : "+s"(gi));
-        uint32_t xv[NTT_E];
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) xv[r] = sh[galois_src_index(spectral_index<LOGN>(tid, r), gi, LOGN)];
-        // one key component at a time: both at once (32 more registers
-        // beside the 64 of the accumulators) spilled to scratch memory
-        uint32_t koff = i * 2 * M + j;
-        uint32_t kv[NTT_E];
-        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) a0[r] += (uint64_t)xv[r] * kv[r];
-        koff += M;
-        asm volatile("" : "+s"(koff));   // the second component's loads after the first products
-        load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) a1[r] += (uint64_t)xv[r] * kv[r];
-    }
     uint32_t u[NTT_E];
     if (j < L) {
+        uint64_t a0[NTT_E], a1[NTT_E];
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
+#pragma unroll 1
+        for (uint32_t i = 0; i < L; ++i) {
+            uint32_t xv[NTT_E];
+            ks_hoist_gather<LOGN>(i == j ? x + ((size_t)i << LOGN) : hoist + (ks_hoist_limb(L, j, i) << LOGN), g,
+                                  tid, sh, xv);
+            // one key component at a time: both at once (32 more registers
+            // beside the 64 of the sums) spilled to scratch memory
+            uint32_t koff = i * 2 * M + j;
+            uint32_t kv[NTT_E];
+            load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) a0[r] += (uint64_t)xv[r] * kv[r];
+            koff += M;
+            asm volatile("" : "+s"(koff));   // the second component's loads after the first products
+            load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) a1[r] += (uint64_t)xv[r] * kv[r];
+        }
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
         store_spectral<LOGN>(gbuf(scratch + ((size_t)(2 * L + j) << LOGN), N), tid, u);
@@ -508,29 +534,29 @@ __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, cons
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
         store_spectral<LOGN>(gbuf(scratch + ((size_t)(3 * L + j) << LOGN), N), tid, u);
     } else {
-        // the transforms below reuse sh, which other waves may still be
+        uint64_t a[NTT_E];
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) a[r] = 0;
+#pragma unroll 1
+        for (uint32_t i = 0; i < L; ++i) {
+            uint32_t xv[NTT_E];
+            ks_hoist_gather<LOGN>(hoist + (ks_hoist_limb(L, j, i) << LOGN), g, tid, sh, xv);
+            uint32_t koff = i * 2 * M + c * M + j;
+            asm volatile("" : "+s"(koff));
+            uint32_t kv[NTT_E];
+            load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) a[r] += (uint64_t)xv[r] * kv[r];
+        }
+        // the transform below reuses sh, which other waves may still be
         // reading for the last digit's gather
         __syncthreads();
-        // both sums reduced to 32 bits first, so the 64-bit accumulators are
-        // not live across the transforms
-        uint32_t u1[NTT_E];
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) {
-            u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
-            u1[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
-        }
+        for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a[r], (uint32_t)(a[r] >> 32)}, mc);
         ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
-        const GBuf UP0 = gbuf(scratch + ((size_t)(4 * L) << LOGN), N);
-        const GBuf UP1 = gbuf(scratch + ((size_t)(4 * L + 1) << LOGN), N);
+        const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) gst(UP0, natural_index<LOGN>(tid, r), u[r]);
-        // the second transform's arithmetic stays after the first: overlapped
-        // by the scheduler, the two needed far more registers
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) asm volatile("" : "+v"(u1[r]));
-        ntt_inv_regs<LOGN>(u1, tid, sh, itw + ((size_t)j << LOGN), mc);
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) gst(UP1, natural_index<LOGN>(tid, r), u1[r]);
+        for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
     }
 }
 

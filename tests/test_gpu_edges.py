@@ -188,6 +188,19 @@ def test_plan_errors():
     with pytest.raises(lola.LolaError) as e:
         plan.evaluate(ctx, [dict(rlk=rlk, gks=gks, inputs=ins, outputs=[ins[0]] + outs[1:])])
     assert e.value.code == -1
+    # a load that fails keeps the loaded constants, and a reload replaces them
+    # (the next evaluation binds the new buffers): the words stay the same
+    def words():
+        plan.evaluate(ctx, [dict(rlk=rlk, gks=gks, inputs=ins, outputs=outs)])
+        torch.cuda.synchronize()
+        return [lola.to_numpy_u32(o).copy() for o in outs]
+    ref = words()
+    with pytest.raises(lola.LolaError) as e:
+        plan.load(other)
+    assert e.value.code == -4
+    assert all(np.array_equal(a, b) for a, b in zip(words(), ref))
+    plan.load(ctx)
+    assert all(np.array_equal(a, b) for a, b in zip(words(), ref))
     # graph replay needs a stream of its own
     with pytest.raises(lola.LolaError) as e:
         plan.evaluate(ctx, [dict(rlk=rlk, gks=gks, inputs=ins, outputs=outs)], graph=True,
