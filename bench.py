@@ -44,7 +44,7 @@ MAC_OPS = 7                                 # Montgomery product + modular add
 # copy (FETCH_SIZE read 0.5 GiB: x2.0; WRITE_SIZE read 1 GiB: x1.0).  These
 # count L2 misses, so reads served by the last-level cache count too.  Valid
 # only for kernel sources with this digest; otherwise the traffic is null.
-KS_INNER_TRAFFIC = {"digest": "dcc1b77964de99ca", "fetch_per_job": 5.3603e6, "write_per_job": 1.0486e6}
+KS_INNER_TRAFFIC = {"digest": "b1a54abb8a5ded5d", "fetch_per_job": 4.1703e6, "write_per_job": 1.0486e6}
 KS_INNER_SOURCES = ["keyswitch.hip", "ks_core.hpp", "ntt_core.hpp", "modarith.hpp", "lola_internal.hpp"]
 
 
@@ -181,6 +181,11 @@ def main():
     ap.add_argument("--cpu-baseline-full", action="store_true",
                     help="only run the CPU oracle on whole workloads (dense-64 query, MNIST-shaped network, "
                          "transfer head in both recipes) on all host threads and on one, and exit")
+    ap.add_argument("--cpu-workloads", default="cfg0,cfg1,cfg3d,cfg3s",
+                    help="with --cpu-baseline-full: which workloads (cfg0 dense-64, cfg1 MNIST-shaped, "
+                         "cfg3d / cfg3s transfer head dense / stacked recipe)")
+    ap.add_argument("--cpu-threads", default="all,1",
+                    help="with --cpu-baseline-full: thread counts ('all' = every host thread)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only measure the 32-bit VALU issue rates (mul_lo, mul_hi, add) against the "
                          "CU x SIMD x lane x clock peak and exit")
@@ -189,7 +194,7 @@ def main():
         print(json.dumps(valu_probe_run()), flush=True)
         return
     if args.cpu_baseline_full:
-        print(json.dumps(cpu_baseline_full()), flush=True)
+        print(json.dumps(cpu_baseline_full(args.cpu_workloads.split(","), args.cpu_threads.split(","))), flush=True)
         return
     if args.calibrate_copy:
         import torch
@@ -865,7 +870,7 @@ def cpu_baseline(p, w, recipe):
             "cpu": _cpu_model(), "batched_primitives_per_op": oracle_batch_ops()}
 
 
-def cpu_baseline_full():
+def cpu_baseline_full(workloads=("cfg0", "cfg1", "cfg3d", "cfg3s"), threads=("all", "1")):
     """The oracle on whole workloads, on all host threads and on one: the
     dense-64 query at N=4096, the MNIST-shaped network (the timed plan's
     shared-reduction schedule), and the transfer head at N=16384 in both
@@ -883,24 +888,26 @@ def cpu_baseline_full():
     mw, img = wl.mnist_weights(), wl.mnist_image(index=0)
     hw, hf = wl.head_weights(), wl.head_features(4)
     cases = [
-        ("cfg0 dense-64 query, N=4096, L=3", "n4096_3q", nw.dense64_schedule(W64), nw.dense64_inputs(x64, 4096),
+        ("cfg0", "cfg0 dense-64 query, N=4096, L=3", "n4096_3q", nw.dense64_schedule(W64), nw.dense64_inputs(x64, 4096),
          list(nw._mod(nw.dense64_plain(x64, W64), wl.PARAMS["n4096_3q"].t)), 1),
-        ("cfg1 MNIST-shaped, N=16384, L=7 (shared reduction, 58 rotations)", "mnist_n16384",
+        ("cfg1", "cfg1 MNIST-shaped, N=16384, L=7 (shared reduction, 58 rotations)", "mnist_n16384",
          nw.mnist_schedule(mw, recipe="shared"), nw.mnist_inputs(img),
          list(nw._mod(nw.mnist_plain(img, mw), wl.PARAMS["mnist_n16384"].t)), 1),
-        ("cfg3 transfer head, N=16384, L=6, dense row major (4 queries per message)", "head_n16384",
+        ("cfg3d", "cfg3 transfer head, N=16384, L=6, dense row major (4 queries per message)", "head_n16384",
          nw.head_schedule(hw), nw.head_inputs(hf),
          list(nw._mod(np.concatenate([nw.head_plain(hf[q], hw) for q in range(4)]), wl.PARAMS["head_n16384"].t)), 4),
-        ("cfg3 transfer head, N=16384, L=6, stacked row major (1 query per message)", "head_n16384",
+        ("cfg3s", "cfg3 transfer head, N=16384, L=6, stacked row major (1 query per message)", "head_n16384",
          nw.head_stacked_schedule(hw), nw.head_stacked_inputs(hf[:1]),
          list(nw._mod(nw.head_plain(hf[0], hw), wl.PARAMS["head_n16384"].t)), 1),
     ]
     all_threads = bfv.max_threads()
     out = {"cpu": _cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
            "kind": "oracle", "runs": []}
-    for th in (all_threads, 1):
+    for th in [all_threads if x == "all" else int(x) for x in threads]:
         bfv.set_threads(th)
-        for name, pname, sched, ins, expected, queries in cases:
+        for key, name, pname, sched, ins, expected, queries in cases:
+            if key not in workloads:
+                continue
             p = wl.PARAMS[pname]
             octx = bfv.Context(p)
             t0 = time.perf_counter()

@@ -206,7 +206,7 @@ def autotune_ntt(ctx, N, L, n_limbs=2048, reps=3):
     return cache
 
 
-def autotune_ks(ctx, N, L, n_jobs=64, reps=3):
+def autotune_ks(ctx, N, L, n_jobs=128, reps=10):
     """Radix split and LDS placement of each batched key-switch stage, picked
     by the library's autotuner (every variant's words checked against the
     default, then the whole key switch of n_jobs rotations timed); cached per
