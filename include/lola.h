@@ -396,6 +396,13 @@ int lola_ntt_autotune(lola_ctx *ctx, uint32_t n_limbs, uint32_t reps, lola_ntt_v
  *   CONV2D, SQUARE, DENSE   (the small variant of Sec. 4.3) the same front
  *       end, then one stacked-row-major round as the output layer (out_dim <=
  *       N / period): one message, output o at slot period*o;
+ *   CONV2D (or CONV2D_DENSE_INPUT), SQUARE, DENSE, then any other chain of
+ *       DENSE and SQUARE layers: the same front end and stacked-row-major
+ *       rounds up to the interleaved hidden vector, then every further dense
+ *       layer with the recipe its input's representation calls for, as in a
+ *       dense chain (below): dense vector - row major on the interleaved or
+ *       dense vector (a sparse result), sparse vector - column major on a
+ *       sparse one (a dense result);
  *   DENSE [, SQUARE]   with in_dim <= N/4: stacked input (period = next power
  *       of two >= in_dim), one row per block, output j at slot period*j;
  *   DENSE, SQUARE, DENSE   with in_dim <= N/2, two recipes (see
@@ -453,8 +460,8 @@ enum { LOLA_OBJECTIVE_THROUGHPUT = 0, LOLA_OBJECTIVE_LATENCY = 1 };
  *  - DENSE, SQUARE, DENSE with in_dim <= N/2 (Sec. 4.2.2): DENSE_ROW_MAJOR
  *    (dense vector - row major, N/period queries per message) or
  *    STACKED_ROW_MAJOR (stacked vector - row major, one query per message).
- *  - CONV2D or CONV2D_DENSE_INPUT, SQUARE, DENSE, SQUARE, DENSE (Sec. 4.3,
- *    App. C): FULL_REDUCTION, the layout the paper describes (every stacked
+ *  - CONV2D or CONV2D_DENSE_INPUT, SQUARE, DENSE and at least one more
+ *    layer, e.g. SQUARE, DENSE (Sec. 4.3, App. C): FULL_REDUCTION, the layout the paper describes (every stacked
  *    round summed over its whole block, masked and combined; one output
  *    message per class: 154 rotations for the MNIST network), or
  *    SHARED_REDUCTION (each round summed only within groups of
@@ -462,7 +469,9 @@ enum { LOLA_OBJECTIVE_THROUGHPUT = 0, LOLA_OBJECTIVE_LATENCY = 1 };
  *    rotate-and-sum over the rest of the block for all rounds together; the
  *    last layer on shifted copies of its input into one packed message, class
  *    o at slot next_pow2(rounds)*o: 58 rotations for the MNIST network).  Both
- *    give the same values at the valid slots of every layer.
+ *    give the same values at the valid slots of every layer.  With a longer
+ *    chain after the first dense layer, the recipe chooses that layer's
+ *    reduction; the rest of the chain is compiled as a dense chain.
  *  - Everything else: FIXED. */
 enum { LOLA_RECIPE_AUTO = 0, LOLA_RECIPE_DENSE_ROW_MAJOR = 1, LOLA_RECIPE_STACKED_ROW_MAJOR = 2,
        LOLA_RECIPE_FIXED = 3 /* reported for patterns with a single recipe */,

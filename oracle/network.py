@@ -598,16 +598,17 @@ def dense_chain_plain(x, layers):
     return a
 
 
-def _dense_row_major_full(b: _Builder, src: int, W, bias, N: int) -> List[int]:
+def _dense_row_major_full(b: _Builder, src: int, W, bias, N: int, pos=None) -> List[int]:
     """Dense vector - row major (Sec. 4.2.2) with the output in sparse form:
-    per row j, the product with row j (value W[j, i] at slot i), then a
-    rotate-and-sum over 1, 2, ..., N/4 and the row swap, after which every
-    slot holds the dot product; the bias is added in every slot.  One message
-    per row."""
+    per row j, the product with row j (value W[j, i] at the input's slot
+    pos[i], slot i by default), then a rotate-and-sum over 1, 2, ..., N/4
+    and the row swap, after which every slot holds the dot product; the bias
+    is added in every slot.  One message per row."""
     full = [1 << i for i in range(_log2(N // 2))] + [ROW_SWAP]
+    pos = list(range(W.shape[1])) if pos is None else list(pos)
     outs = []
     for j in range(W.shape[0]):
-        z = b.emit("mul_plain", b.reg(), src, {i: int(W[j, i]) for i in range(W.shape[1])})
+        z = b.emit("mul_plain", b.reg(), src, {pos[i]: int(W[j, i]) for i in range(W.shape[1])})
         z = _rotate_and_sum(b, z, full)
         if bias is not None:
             z = b.emit("add_plain", b.reg(), z, {s: int(bias[j]) for s in range(N)})
@@ -662,6 +663,65 @@ def dense_chain_schedule(layers, N: int, sparse_input: bool) -> Schedule:
     r = len(regs) if sparse else np.asarray([ly for ly in layers if ly[0] == "dense"][-1][1]).shape[0]
     out_slots = [{0: f"y{j}"} for j in range(r)] if sparse else [{j: f"y{j}" for j in range(r)}]
     return Schedule(N, b.n_inputs, b.ops, regs, out_slots)
+
+
+# The MNIST-shaped convolution front end followed by any chain of dense layers
+# and squares (the first layer after the convolution's square is dense).
+def conv_chain_plain(img, conv_w, conv_b, layers):
+    """Exact integers: the 5x5 stride-2 convolution with five maps over the
+    zero-padded 29x29 image, squared, flattened (index 169 m + 13 y + x),
+    then the chain (`dense_chain_plain`)."""
+    p = mnist_padded(img).astype(object)
+    conv = np.zeros((5, MNIST_OUT, MNIST_OUT), dtype=object)
+    for m in range(5):
+        for y in range(MNIST_OUT):
+            for x in range(MNIST_OUT):
+                win = p[2 * y:2 * y + 5, 2 * x:2 * x + 5]
+                conv[m, y, x] = int((win * np.asarray(conv_w[m]).astype(object)).sum()) + int(conv_b[m])
+    return dense_chain_plain((conv * conv).reshape(845), layers)
+
+
+def conv_chain_schedule(conv_w, conv_b, layers, N: int = 16384, recipe: str = "full") -> Schedule:
+    """The front end of `mnist_schedule` (convolution, combine, square, 16
+    stacked copies at stride 1024) and the first dense layer as its stacked
+    rounds (`_stacked_rounds`, recipe "full" or "shared"), giving the
+    interleaved hidden vector, value 16 rho + c at slot 1024 c + rho; every
+    later dense layer takes the recipe its input's representation calls for
+    (Sec. 4.2.2): dense vector - row major on the interleaved or dense vector
+    (`_dense_row_major_full` with the values' slots, a sparse result), sparse
+    vector - column major on a sparse one (a dense result, value j at slot
+    j); a square squares every message."""
+    assert N == 16384 and layers[0][0] == "dense"
+    b = _Builder(N, 25)
+    maps = []
+    for m in range(5):
+        acc = None
+        for a in range(5):
+            for c in range(5):
+                t = b.emit("mul_scalar", b.reg(), 5 * a + c, int(conv_w[m][a][c]))
+                acc = t if acc is None else b.emit("add", b.reg(), acc, t)
+        acc = b.emit("add_plain", b.reg(), acc, {s: int(conv_b[m]) for s in range(169)})
+        maps.append(acc)
+    y = _combine_tree(b, maps, 169)
+    y = b.emit("square", b.reg(), y)
+    s = _rotate_and_sum(b, y, [-1024, -2048, -4096, ROW_SWAP])
+    W1 = np.asarray(layers[0][1], dtype=np.int64)
+    R = -(-W1.shape[0] // 16)
+    regs = [_stacked_rounds(b, s, 1024, 16, R, range(845), W1, layers[0][2], recipe)]
+    pos, sparse = [1024 * (j % 16) + j // 16 for j in range(W1.shape[0])], False
+    width = W1.shape[0]
+    for ly in layers[1:]:
+        if ly[0] == "square":
+            regs = [b.emit("square", b.reg(), r) for r in regs]
+            continue
+        W = np.asarray(ly[1], dtype=np.int64)
+        if sparse:
+            regs, sparse, pos = [_sparse_column_major(b, regs, W, ly[2])], False, list(range(W.shape[0]))
+        else:
+            regs, sparse = _dense_row_major_full(b, regs[0], W, ly[2], N, pos), True
+        width = W.shape[0]
+    out_slots = [{0: f"y{j}"} for j in range(width)] if sparse else [{pos[j]: f"y{j}" for j in range(width)}]
+    return Schedule(N, 25, b.ops, regs, out_slots)
 
 
 # Transfer-learning head (N = 16384, 4 queries per ciphertext, query q in the

@@ -189,14 +189,103 @@ int64_t bias_at(const lola_layer &l, int j) { return l.bias ? l.bias[j] : 0; }
 // reduction tail and a packed output message (LOLA_RECIPE_SHARED_REDUCTION);
 // otherwise every stacked round is summed over its whole block and each
 // output gets its own message (LOLA_RECIPE_FULL_REDUCTION).
+// A vector between layers: sparse (value i in every slot of message regs[i])
+// or dense (value i at slot pos[i] of the one message regs[0]).
+struct ChainVec {
+    std::vector<int> regs;
+    bool sparse = false;
+    std::vector<uint32_t> pos;
+    int width = 0;
+};
+
+// DENSE and SQUARE layers ls[from..n) on v, each dense layer with the recipe
+// its input's representation calls for (Sec. 4.2.2): dense vector - row
+// major on a dense input (per row, the product with the row laid out at the
+// input's slots, then a rotate-and-sum over every slot: a sparse result) and
+// sparse vector - column major on a sparse input (the sum of v_i c^i, no
+// rotation: a dense result, value j at slot j); a square acts on every
+// message of the representation.
+int emit_chain(Builder &b, const lola_layer *ls, uint32_t from, uint32_t n, ChainVec &v) {
+    const uint32_t N = b.p->N;
+    int dim = v.width;
+    for (uint32_t l = from; l < n; ++l) {
+        if (ls[l].kind == LOLA_LAYER_SQUARE) continue;
+        if (ls[l].kind != LOLA_LAYER_DENSE) return unsupported("a chain holds DENSE and SQUARE layers");
+        if (ls[l].in_dim != dim || ls[l].out_dim <= 0 || !ls[l].weight)
+            return unsupported("dense layer sizes must chain");
+        if ((uint32_t)ls[l].in_dim > N || (uint32_t)ls[l].out_dim > N)
+            return unsupported("dense layer larger than a message");
+        dim = ls[l].out_dim;
+    }
+    std::vector<int32_t> full;
+    for (uint32_t s = 1; s < N / 2; s *= 2) full.push_back((int32_t)s);
+    full.push_back(LOLA_ROW_SWAP);
+    for (uint32_t l = from; l < n; ++l) {
+        const lola_layer &ly = ls[l];
+        if (ly.kind == LOLA_LAYER_SQUARE) {
+            for (int &x : v.regs) x = b.square(x);
+            continue;
+        }
+        const int in = ly.in_dim, r = ly.out_dim;
+        if (v.sparse) {
+            std::vector<int> terms;
+            for (int i = 0; i < in; ++i) {
+                auto col = b.zeros();
+                for (int j = 0; j < r; ++j) col[j] = ly.weight[(size_t)j * in + i];
+                terms.push_back(b.column_term(v.regs[i], std::move(col)));
+            }
+            int cadd = -1;
+            if (ly.bias) {
+                auto bv = b.zeros();
+                for (int j = 0; j < r; ++j) bv[j] = ly.bias[j];
+                cadd = b.cst(bv, false);
+            }
+            v.regs = {b.column_sum(terms, cadd)};
+            v.pos.resize(r);
+            for (int j = 0; j < r; ++j) v.pos[j] = (uint32_t)j;
+        } else {
+            std::vector<int> outs;
+            for (int j = 0; j < r; ++j) {
+                auto row = b.zeros();
+                for (int i = 0; i < in; ++i) row[v.pos[i]] = ly.weight[(size_t)j * in + i];
+                int z = b.rotate_and_sum(b.mulplain(v.regs[0], b.cst(row, true)), full);
+                if (ly.bias) z = b.addplain(z, b.cst(std::vector<int64_t>(N, ly.bias[j]), false));
+                outs.push_back(z);
+            }
+            v.regs = outs;
+            v.pos.clear();
+        }
+        v.sparse = !v.sparse;
+        v.width = r;
+    }
+    return LOLA_OK;
+}
+
+// The plan's outputs: the chain's messages and where each value lies.
+void chain_outputs(lola_plan *p, const ChainVec &v) {
+    const uint32_t N = p->N;
+    p->outputs = v.regs;
+    p->output_map.assign((size_t)v.regs.size() * N, -1);
+    for (int j = 0; j < v.width; ++j) {
+        if (v.sparse) p->output_map[(size_t)j * N] = j;
+        else p->output_map[v.pos[j]] = j;
+    }
+}
+
 int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n, bool shared) {
-    // CONV2D (or CONV2D_DENSE_INPUT), SQUARE, DENSE [, SQUARE, DENSE]
+    // CONV2D (or CONV2D_DENSE_INPUT), SQUARE, DENSE, then any chain of DENSE
+    // and SQUARE layers.  SQUARE, DENSE after the first dense layer ends in
+    // an interleaved vector - row major output layer (Table 1); other chains
+    // continue from the interleaved hidden vector with emit_chain.
     const bool small = n == 3;
+    const bool two = n == 5 && ls[3].kind == LOLA_LAYER_SQUARE && ls[4].kind == LOLA_LAYER_DENSE;
     const bool dense_in = ls[0].kind == LOLA_LAYER_CONV2D_DENSE_INPUT;
-    if ((n != 5 && n != 3) || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE ||
-        (!small && (ls[3].kind != LOLA_LAYER_SQUARE || ls[4].kind != LOLA_LAYER_DENSE)))
-        return unsupported("convolution networks must be CONV2D, SQUARE, DENSE [, SQUARE, DENSE]");
-    const lola_layer &cv = ls[0], &d1 = ls[2], &d2 = ls[small ? 2 : 4];
+    if (n < 3 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_DENSE)
+        return unsupported("convolution networks must be CONV2D, SQUARE, DENSE, then DENSE and SQUARE layers");
+    for (uint32_t l = 3; l < n; ++l)
+        if (ls[l].kind != LOLA_LAYER_DENSE && ls[l].kind != LOLA_LAYER_SQUARE)
+            return unsupported("convolution networks must be CONV2D, SQUARE, DENSE, then DENSE and SQUARE layers");
+    const lola_layer &cv = ls[0], &d1 = ls[2], &d2 = ls[two ? 4 : 2];
     const uint32_t N = p->N;
     if (cv.in_h != cv.in_w || cv.k <= 0 || cv.stride <= 0 || cv.maps <= 0 || cv.in_h < cv.k || !cv.weight)
         return unsupported("bad convolution shape");
@@ -213,7 +302,7 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n,
     if (dense_in) {
         // window corners at stride*(y*W + x); maps go to the four parity
         // classes of that lattice (stride 2), further ones to bands below
-        if (cv.stride != 2 || small) return unsupported("dense-input convolution: stride 2, five-layer network");
+        if (cv.stride != 2 || small) return unsupported("dense-input convolution: stride 2 and layers after the first dense one");
         const uint32_t W = (uint32_t)cv.in_w, band = W * (uint32_t)(2 * n_out);
         const uint32_t cls[4] = {0, 1, W, W + 1};
         for (int m = 0; m < cv.maps; ++m) offs.push_back(cls[m % 4] + band * (uint32_t)(m / 4));
@@ -235,7 +324,7 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n,
     const uint32_t R = ((uint32_t)d1.out_dim + C - 1) / C;
     if (small && R != 1) return unsupported("a final dense layer after the convolution needs out_dim <= N / next_pow2(in_dim)");
     if (R > P) return unsupported("too many stacked rounds for the interleaved layout");
-    if (!small && (d2.in_dim != d1.out_dim || !d2.weight || d2.out_dim <= 0))
+    if (two && (d2.in_dim != d1.out_dim || !d2.weight || d2.out_dim <= 0))
         return unsupported("second dense layer shape");
     std::vector<int> ins(K2);
     std::vector<uint32_t> corner((size_t)V);   // slot of window (y, x) in the conv messages
@@ -349,6 +438,19 @@ int compile_conv_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n,
     }
     int h = b.combine_tree(rounds, 1);
     if (shared) h = b.rotate_and_sum(h, tail);
+    if (!two) {
+        // any other chain continues from the interleaved hidden vector,
+        // value C rho + c at slot P c + rho
+        ChainVec v;
+        v.regs = {h};
+        v.width = d1.out_dim;
+        for (int j = 0; j < d1.out_dim; ++j) v.pos.push_back(P * ((uint32_t)j % C) + (uint32_t)j / C);
+        const int rc = emit_chain(b, ls, 3, n, v);
+        if (rc) return rc;
+        chain_outputs(p, v);
+        p->recipe = shared ? LOLA_RECIPE_SHARED_REDUCTION : LOLA_RECIPE_FULL_REDUCTION;
+        return LOLA_OK;
+    }
     h = b.square(h);
     // interleaved row major: value j = C*rho + c at slot P*c + rho
     const uint32_t GR = next_pow2(R);
@@ -841,85 +943,40 @@ static bool is_dense_chain(const lola_layer *ls, uint32_t n) {
 int compile_dense_chain(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n, bool sparse_input) {
     const uint32_t N = p->N;
     if (!is_dense_chain(ls, n)) return unsupported("a dense chain holds DENSE and SQUARE layers, DENSE first");
-    int dim = ls[0].in_dim;
-    for (uint32_t l = 0; l < n; ++l) {
-        if (ls[l].kind != LOLA_LAYER_DENSE) continue;
-        if (ls[l].in_dim != dim || ls[l].out_dim <= 0 || !ls[l].weight)
-            return unsupported("dense layer sizes must chain");
-        if ((uint32_t)ls[l].in_dim > N || (uint32_t)ls[l].out_dim > N)
-            return unsupported("dense layer larger than a message");
-        dim = ls[l].out_dim;
-    }
     const int k = ls[0].in_dim;
+    if (k <= 0 || (uint32_t)k > N) return unsupported("dense layer larger than a message");
     p->queries = 1;
-    std::vector<int> regs;
+    ChainVec v;
+    v.width = k;
+    v.sparse = sparse_input;
     if (sparse_input) {
         p->n_inputs = (uint32_t)k;
         p->input_map.assign((size_t)k * N, -1);
         for (int i = 0; i < k; ++i) {
             std::fill(p->input_map.begin() + (size_t)i * N, p->input_map.begin() + (size_t)(i + 1) * N, i);
-            regs.push_back(i);
+            v.regs.push_back(i);
         }
     } else {
         p->n_inputs = 1;
         p->input_map.assign(N, -1);
-        for (int i = 0; i < k; ++i) p->input_map[i] = i;
-        regs.push_back(0);
+        for (int i = 0; i < k; ++i) {
+            p->input_map[i] = i;
+            v.pos.push_back((uint32_t)i);
+        }
+        v.regs.push_back(0);
     }
     p->n_regs = p->n_inputs;
-    std::vector<int32_t> full;
-    for (uint32_t s = 1; s < N / 2; s *= 2) full.push_back((int32_t)s);
-    full.push_back(LOLA_ROW_SWAP);
-    bool sparse = sparse_input;
-    int r = k;
-    for (uint32_t l = 0; l < n; ++l) {
-        const lola_layer &ly = ls[l];
-        if (ly.kind == LOLA_LAYER_SQUARE) {
-            for (int &x : regs) x = b.square(x);
-            continue;
-        }
-        const int in = ly.in_dim;
-        r = ly.out_dim;
-        if (sparse) {
-            std::vector<int> terms;
-            for (int i = 0; i < in; ++i) {
-                auto col = b.zeros();
-                for (int j = 0; j < r; ++j) col[j] = ly.weight[(size_t)j * in + i];
-                terms.push_back(b.column_term(regs[i], std::move(col)));
-            }
-            int cadd = -1;
-            if (ly.bias) {
-                auto bv = b.zeros();
-                for (int j = 0; j < r; ++j) bv[j] = ly.bias[j];
-                cadd = b.cst(bv, false);
-            }
-            regs = {b.column_sum(terms, cadd)};
-        } else {
-            std::vector<int> outs;
-            for (int j = 0; j < r; ++j) {
-                auto row = b.zeros();
-                for (int i = 0; i < in; ++i) row[i] = ly.weight[(size_t)j * in + i];
-                int z = b.rotate_and_sum(b.mulplain(regs[0], b.cst(row, true)), full);
-                if (ly.bias) z = b.addplain(z, b.cst(std::vector<int64_t>(N, ly.bias[j]), false));
-                outs.push_back(z);
-            }
-            regs = outs;
-        }
-        sparse = !sparse;
-    }
-    p->outputs = regs;
-    p->output_map.assign((size_t)regs.size() * N, -1);
-    if (sparse)
-        for (int j = 0; j < r; ++j) p->output_map[(size_t)j * N] = j;
-    else
-        for (int j = 0; j < r; ++j) p->output_map[j] = j;
+    const int rc = emit_chain(b, ls, 0, n, v);
+    if (rc) return rc;
+    chain_outputs(p, v);
     p->recipe = sparse_input ? LOLA_RECIPE_SPARSE_COLUMN_MAJOR : LOLA_RECIPE_DENSE_CHAIN;
     return LOLA_OK;
 }
 
 // The recipes that apply to a layer list: DENSE, SQUARE, DENSE has two for
-// its dense layers, the five-layer convolution networks two for their
-// reductions; everything else has one (LOLA_RECIPE_FIXED).
+// its dense layers, convolution networks with layers after the first dense
+// one two for that layer's reduction; everything else has one
+// (LOLA_RECIPE_FIXED).
 // The dense-chain recipes take any chain of DENSE and SQUARE layers and are
 // the candidates for chains that no other pattern covers; they can be forced
 // on the others.
@@ -933,7 +990,7 @@ static std::vector<int> recipe_candidates(const lola_layer *layers, uint32_t n_l
     const lola_layer &l0 = layers[0];
     if (l0.kind == LOLA_LAYER_DENSE && n_layers == 3 && dense_pattern(layers, n_layers))
         return {LOLA_RECIPE_DENSE_ROW_MAJOR, LOLA_RECIPE_STACKED_ROW_MAJOR};
-    if ((l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) && n_layers == 5 &&
+    if ((l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) && n_layers >= 4 &&
         layers[2].kind != LOLA_LAYER_CONV2D)
         return {LOLA_RECIPE_FULL_REDUCTION, LOLA_RECIPE_SHARED_REDUCTION};
     if (is_dense_chain(layers, n_layers) && !dense_pattern(layers, n_layers))

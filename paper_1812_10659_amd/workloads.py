@@ -60,6 +60,10 @@ PARAMS: Dict[str, ParamSet] = {
     # CIFAR-shaped network: the same noise demand (seven primes leave no
     # budget after the second convolution's one-hot products); eight primes.
     "cifar_n16384": ParamSet("cifar_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
+    # A convolution front end followed by a longer dense chain (three squares
+    # after the convolution's, each row-major layer's products on top): ten
+    # data primes, log2(QP) = 330 <= 438.
+    "chain_n16384": ParamSet("chain_n16384", 16384, 1146881, tuple(PRIMES_16384[:10]), PRIMES_16384[10]),
     # Transfer-learning head: six data primes.
     "head_n16384": ParamSet("head_n16384", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
     # The largest ciphertext-prime count the library accepts: twelve data

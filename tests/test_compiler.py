@@ -408,3 +408,80 @@ def test_compiler_dense_chain_recipe_choice():
 def networks_mnist_layers():
     from paper_1812_10659_amd import networks
     return networks.mnist_layers(wl.mnist_weights())
+
+
+def conv_chain(hidden, seed=13):
+    """The MNIST-shaped convolution front end followed by DENSE 845 -> h0,
+    SQUARE, DENSE h0 -> h1, ..., SQUARE, DENSE -> 10, with seeded int8
+    weights and integer biases: (lola layers, the oracle's chain layers,
+    convolution weights, image)."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w = wl.mnist_weights()
+    rs = wl.rng(seed, 4)
+    dims = [845] + list(hidden) + [10]
+    layers = [lola.conv2d(w.conv_w, w.conv_b, networks.MNIST_PAD, 2), lola.square()]
+    ol = []
+    for i in range(len(dims) - 1):
+        W = rs.integers(-128, 128, (dims[i + 1], dims[i]))
+        b = rs.integers(-1000, 1000, dims[i + 1])
+        if i:
+            layers.append(lola.square())
+            ol.append(("square",))
+        layers.append(lola.dense(W, b))
+        ol.append(("dense", W, b))
+    return layers, ol, w, wl.mnist_image(index=3)
+
+
+@pytest.mark.parametrize("recipe,name", [(4, "full"), (5, "shared")])
+def test_compiler_conv_then_dense_chain(recipe, name):
+    """CONV2D, SQUARE, DENSE, SQUARE, DENSE, SQUARE, DENSE (no fixed pattern):
+    the MNIST front end and the first dense layer's stacked rounds (either
+    reduction) up to the interleaved hidden vector, then dense vector - row
+    major on it (a sparse result) and sparse vector - column major on that (a
+    dense result, value j at slot j): against the oracle's schedule of the
+    same network and the plain network."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    p = wl.PARAMS["cifar_n16384"]
+    layers, ol, w, img = conv_chain([32, 16])
+    sched = nw.conv_chain_schedule(w.conv_w, w.conv_b, ol, p.N, name)
+    plan = _check_plan(lola, p, layers, networks.mnist_input_values(img),
+                       nw.conv_chain_plain(img, w.conv_w, w.conv_b, ol), sched, recipe=recipe)
+    info = plan.info
+    # squares: the convolution's, the hidden vector's, and one per message of
+    # the 16 sparse outputs of the row-major layer
+    assert info["recipe"] == recipe and info["n_square"] == 2 + 16 and info["n_outputs"] == 1
+    # the row-major layer rotates over the whole message per row (13 steps of
+    # N/2 = 8192 slots plus the row swap); the column-major layer does not rotate
+    rounds = {"full": 2 * 10 + 1, "shared": 2 * 1 + 1 + 9}[name]
+    assert info["n_rotations"] == 4 + 4 + rounds + 16 * 14
+    om = plan.output_map()
+    assert [int(np.nonzero(om.reshape(-1) == j)[0][0]) for j in range(10)] == list(range(10))
+
+
+def test_compiler_conv_chain_recipe_choice_and_tails():
+    """Convolution networks with layers after the first dense one have both
+    reductions as candidates and AUTO keeps the cheaper; a chain ending on a
+    row-major layer gives one message per output, and a trailing square is
+    applied to every message; the classic SQUARE, DENSE tail keeps its own
+    output layer."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    p = wl.PARAMS["cifar_n16384"]
+    layers, ol, w, img = conv_chain([32, 16])
+    costs = {r: lola.Plan(p, layers, recipe=r).info["predicted_us"] for r in (4, 5)}
+    assert lola.Plan(p, layers).info["recipe"] == min(costs, key=costs.get)
+    # DENSE 845 -> 32, SQUARE, DENSE 32 -> 10, SQUARE: the last dense layer is
+    # row major on the interleaved vector, one message per output, squared
+    short, sol, _, _ = conv_chain([32], seed=14)
+    short = short + [lola.square()]
+    sol = sol + [("square",)]
+    for r, name in ((4, "full"), (5, "shared")):
+        sched = nw.conv_chain_schedule(w.conv_w, w.conv_b, sol, p.N, name)
+        plan = _check_plan(lola, p, short, networks.mnist_input_values(img),
+                           nw.conv_chain_plain(img, w.conv_w, w.conv_b, sol), sched, recipe=r)
+        assert plan.info["n_outputs"] == 10 and plan.info["n_square"] == 2 + 10
+    # the MNIST network itself (SQUARE, DENSE after the first dense layer)
+    # keeps the interleaved output layer: 58 rotations in the shared layout
+    assert lola.Plan(wl.PARAMS["mnist_n16384"], networks.mnist_layers(w)).info["n_rotations"] == 58

@@ -101,6 +101,37 @@ def test_mnist_dense_input_network_matches_oracle(name, recipe):
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
 
 
+@pytest.mark.timeout(600)
+def test_conv_then_dense_chain_matches_oracle():
+    """A convolution network with a longer dense chain, which no fixed
+    pattern covers: CONV2D, SQUARE, DENSE 845 -> 16, SQUARE, DENSE 16 -> 12,
+    SQUARE, DENSE 12 -> 10 (the first dense layer in stacked rounds with the
+    shared reduction, then dense vector - row major on the interleaved
+    vector and sparse vector - column major on its sparse result; ten data
+    primes): words against the oracle's schedule of the same network, and
+    the decrypted outputs against the plain network."""
+    from paper_1812_10659_amd import lola, networks
+    w, img = wl.mnist_weights(), wl.mnist_image(index=3)
+    rs = wl.rng(23, 1)
+    dims = [845, 16, 12, 10]
+    layers = [lola.conv2d(w.conv_w, w.conv_b, networks.MNIST_PAD, 2), lola.square()]
+    ol = []
+    for i in range(len(dims) - 1):
+        W = rs.integers(-128, 128, (dims[i + 1], dims[i]))
+        b = rs.integers(-1000, 1000, dims[i + 1])
+        if i:
+            layers.append(lola.square())
+            ol.append(("square",))
+        layers.append(lola.dense(W, b))
+        ol.append(("dense", W, b))
+    print("[gpu-net] convolution then a dense chain", flush=True)
+    sched = nw.conv_chain_schedule(w.conv_w, w.conv_b, ol, 16384, "shared")
+    env = _setup("chain_n16384", layers, sched, networks.mnist_input_values(img), wl.key_seed(1) + 13,
+                 wl.enc_seed(1) + 13, recipe=lola.RECIPE_SHARED_REDUCTION)
+    assert env["plan"].info["recipe"] == lola.RECIPE_SHARED_REDUCTION
+    _run_and_compare(env, sched, nw.conv_chain_plain(img, w.conv_w, w.conv_b, ol))
+
+
 def test_cifar_shaped_small_matches_oracle():
     """The two-convolution recipe on a reduced case (3x16x16 image, 5 and 3
     maps), ciphertext words against the oracle's schedule."""

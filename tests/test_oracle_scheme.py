@@ -375,3 +375,30 @@ def test_dense_chain_ciphertexts_decrypt_to_network(sparse):
     else:            # sparse input: column major, then row major last: every slot of message j holds y_j
         assert [int(d[0]) for d in dec] == exp and all(np.all(d == d[0]) for d in dec)
         assert [int(s[0]) for s in slots] == exp
+
+
+@pytest.mark.parametrize("recipe", ["full", "shared"])
+def test_conv_chain_schedule_equals_plain_network(recipe):
+    """The MNIST front end followed by a longer chain (DENSE 845 -> 24,
+    SQUARE, DENSE 24 -> 12, SQUARE, DENSE 12 -> 10): the plain network with
+    the MNIST layers is `mnist_plain`; the slot-level run of the oracle's
+    schedule (stacked rounds, then dense vector - row major on the
+    interleaved vector, then sparse vector - column major) gives the plain
+    network mod t at slots 0..9 of its one output message, under both
+    reductions of the first dense layer."""
+    from oracle import network as nw
+    wts, img = wl.mnist_weights(), wl.mnist_image(index=2)
+    mn = [("dense", wts.w1, wts.b1), ("square",), ("dense", wts.w2, wts.b2)]
+    assert list(nw.conv_chain_plain(img, wts.conv_w, wts.conv_b, mn)) == list(nw.mnist_plain(img, wts))
+    rs = wl.rng(22, 1)
+    W1, W2, W3 = rs.integers(-128, 128, (24, 845)), rs.integers(-128, 128, (12, 24)), rs.integers(-128, 128, (10, 12))
+    b1, b2, b3 = rs.integers(-1000, 1000, 24), rs.integers(-1000, 1000, 12), rs.integers(-1000, 1000, 10)
+    ol = [("dense", W1, b1), ("square",), ("dense", W2, b2), ("square",), ("dense", W3, b3)]
+    t = 1146881
+    exp = list(nw._mod(nw.conv_chain_plain(img, wts.conv_w, wts.conv_b, ol), t))
+    sched = nw.conv_chain_schedule(wts.conv_w, wts.conv_b, ol, 16384, recipe)
+    outs, _ = nw.run_slots(sched, nw.mnist_inputs(img), t)
+    assert len(outs) == 1 and [int(outs[0][j]) for j in range(10)] == exp
+    assert sched.out_slots == [{j: f"y{j}" for j in range(10)}]
+    # 12 rows of the row-major layer, each summed over the whole message
+    assert sum(1 for op in sched.ops if op[0] == "rotate" and op[3] == nw.ROW_SWAP) == 1 + 12
