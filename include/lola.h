@@ -393,6 +393,10 @@ int lola_ntt_autotune(lola_ctx *ctx, uint32_t n_limbs, uint32_t reps, lola_ntt_v
  *       whole message (rotations 1 .. N/4 and the row swap), then the one-hot
  *       product that keeps slot j; the outputs summed into one message,
  *       squared, and one message per logit (value at slot 0);
+ *   CONV2D, SQUARE, CONV2D, then any other chain of DENSE and SQUARE
+ *       layers: the same two-convolution front end up to the second
+ *       convolution's dense output (value j at slot j), then the chain as
+ *       in a dense chain (below);
  *   CONV2D, SQUARE, DENSE   (the small variant of Sec. 4.3) the same front
  *       end, then one stacked-row-major round as the output layer (out_dim <=
  *       N / period): one message, output o at slot period*o;

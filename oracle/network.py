@@ -517,6 +517,23 @@ def cifar_schedule(wts, n_in: int, N: int = 16384) -> Schedule:
       square;
       dense:   per logit, the product with its row, rotate-and-sum over the
                next power of two above the hidden size -> logit at slot 0."""
+    b = _Builder(N, wts.conv1_w.shape[1] * wts.conv1_w.shape[2] ** 2)
+    gathered, H = _cifar_front(b, wts, n_in, N)
+    h = b.emit("square", b.reg(), gathered)
+    steps = [1 << i for i in range(max(1, int(np.ceil(np.log2(H)))))]
+    outs = []
+    for o in range(wts.w3.shape[0]):
+        z = b.emit("mul_plain", b.reg(), h, {j: int(wts.w3[o, j]) for j in range(H)})
+        z = _rotate_and_sum(b, z, steps)
+        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b3[o])})
+        outs.append(z)
+    return Schedule(N, b.n_inputs, b.ops, outs, [{0: f"logit{o}"} for o in range(len(outs))])
+
+
+def _cifar_front(b: _Builder, wts, n_in: int, N: int):
+    """The CIFAR-shaped network up to the second convolution's outputs with
+    their biases (before its square): one dense message, output j at slot
+    j.  Returns (register, number of outputs)."""
     m1, C, k1, _ = wts.conv1_w.shape
     m2, _, k2, _ = wts.conv2_w.shape
     n1 = (n_in - k1) // 2 + 1
@@ -525,7 +542,6 @@ def cifar_schedule(wts, n_in: int, N: int = 16384) -> Schedule:
     H = m2 * V2
     place, R = cifar_layout(m1, n1, N)
     G = max(g for g, _ in place) + 1
-    b = _Builder(N, C * k1 * k1)
     maps = []
     for m in range(m1):
         acc = None
@@ -568,15 +584,7 @@ def cifar_schedule(wts, n_in: int, N: int = 16384) -> Schedule:
         z = b.emit("mul_plain", b.reg(), z, {j: 1})
         gathered = z if gathered is None else b.emit("add", b.reg(), gathered, z)
     gathered = b.emit("add_plain", b.reg(), gathered, {j: int(wts.conv2_b[j // V2]) for j in range(H)})
-    h = b.emit("square", b.reg(), gathered)
-    steps = [1 << i for i in range(max(1, int(np.ceil(np.log2(H)))))]
-    outs = []
-    for o in range(wts.w3.shape[0]):
-        z = b.emit("mul_plain", b.reg(), h, {j: int(wts.w3[o, j]) for j in range(H)})
-        z = _rotate_and_sum(b, z, steps)
-        z = b.emit("add_plain", b.reg(), z, {0: int(wts.b3[o])})
-        outs.append(z)
-    return Schedule(N, C * k1 * k1, b.ops, outs, [{0: f"logit{o}"} for o in range(len(outs))])
+    return gathered, H
 
 
 # Chains of dense layers and squares on one query, with the two recipes that
@@ -707,10 +715,19 @@ def conv_chain_schedule(conv_w, conv_b, layers, N: int = 16384, recipe: str = "f
     s = _rotate_and_sum(b, y, [-1024, -2048, -4096, ROW_SWAP])
     W1 = np.asarray(layers[0][1], dtype=np.int64)
     R = -(-W1.shape[0] // 16)
-    regs = [_stacked_rounds(b, s, 1024, 16, R, range(845), W1, layers[0][2], recipe)]
-    pos, sparse = [1024 * (j % 16) + j // 16 for j in range(W1.shape[0])], False
-    width = W1.shape[0]
-    for ly in layers[1:]:
+    h = _stacked_rounds(b, s, 1024, 16, R, range(845), W1, layers[0][2], recipe)
+    return _chain_tail(b, h, [1024 * (j % 16) + j // 16 for j in range(W1.shape[0])], layers[1:])
+
+
+def _chain_tail(b: _Builder, src: int, pos, layers) -> Schedule:
+    """The rest of a network from one dense message (value j at slot pos[j]):
+    each dense layer with the recipe its input's representation calls for
+    (Sec. 4.2.2), dense vector - row major on a dense vector (a sparse
+    result: one message per value, the value in every slot), sparse vector -
+    column major on a sparse one (a dense result, value j at slot j); a
+    square squares every message."""
+    regs, sparse, pos, width = [src], False, list(pos), len(pos)
+    for ly in layers:
         if ly[0] == "square":
             regs = [b.emit("square", b.reg(), r) for r in regs]
             continue
@@ -718,10 +735,28 @@ def conv_chain_schedule(conv_w, conv_b, layers, N: int = 16384, recipe: str = "f
         if sparse:
             regs, sparse, pos = [_sparse_column_major(b, regs, W, ly[2])], False, list(range(W.shape[0]))
         else:
-            regs, sparse = _dense_row_major_full(b, regs[0], W, ly[2], N, pos), True
+            regs, sparse = _dense_row_major_full(b, regs[0], W, ly[2], b.N, pos), True
         width = W.shape[0]
     out_slots = [{0: f"y{j}"} for j in range(width)] if sparse else [{pos[j]: f"y{j}" for j in range(width)}]
-    return Schedule(N, 25, b.ops, regs, out_slots)
+    return Schedule(b.N, b.n_inputs, b.ops, regs, out_slots)
+
+
+def cifar_chain_plain(padded, wts, tail):
+    """Exact integers: the CIFAR-shaped network's two convolutions (the
+    first squared), the second's outputs flattened (index V2 m + n2 y + x),
+    then the chain `tail` of dense layers and squares (`dense_chain_plain`)."""
+    a1 = _conv_plain(np.asarray(padded).astype(object), wts.conv1_w, wts.conv1_b, 2)
+    a2 = _conv_plain(a1 * a1, wts.conv2_w, wts.conv2_b, 2)
+    return dense_chain_plain(a2.reshape(-1), tail)
+
+
+def cifar_chain_schedule(wts, tail, n_in: int, N: int = 16384) -> Schedule:
+    """The CIFAR-shaped front end of `cifar_schedule` up to the second
+    convolution's dense output (before its square), then the chain `tail`
+    (`_chain_tail`), e.g. SQUARE, DENSE, SQUARE, DENSE."""
+    b = _Builder(N, wts.conv1_w.shape[1] * wts.conv1_w.shape[2] ** 2)
+    gathered, H = _cifar_front(b, wts, n_in, N)
+    return _chain_tail(b, gathered, range(H), tail)
 
 
 # Transfer-learning head (N = 16384, 4 queries per ciphertext, query q in the

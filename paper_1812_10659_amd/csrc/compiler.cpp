@@ -811,11 +811,16 @@ using namespace lola;
 extern "C" {
 
 int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n) {
-    // CONV2D (C channels), SQUARE, CONV2D (over all maps), SQUARE, DENSE
-    if (n != 5 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_CONV2D ||
-        ls[3].kind != LOLA_LAYER_SQUARE || ls[4].kind != LOLA_LAYER_DENSE)
-        return unsupported("two-convolution networks must be CONV2D, SQUARE, CONV2D, SQUARE, DENSE");
-    const lola_layer &c1 = ls[0], &c2 = ls[2], &d = ls[4];
+    // CONV2D (C channels), SQUARE, CONV2D (over all maps), then SQUARE, DENSE
+    // (one message per logit) or any other chain of DENSE and SQUARE layers,
+    // continued from the second convolution's dense output with emit_chain
+    if (n < 4 || ls[1].kind != LOLA_LAYER_SQUARE || ls[2].kind != LOLA_LAYER_CONV2D)
+        return unsupported("two-convolution networks must be CONV2D, SQUARE, CONV2D, then DENSE and SQUARE layers");
+    for (uint32_t l = 3; l < n; ++l)
+        if (ls[l].kind != LOLA_LAYER_DENSE && ls[l].kind != LOLA_LAYER_SQUARE)
+            return unsupported("two-convolution networks must be CONV2D, SQUARE, CONV2D, then DENSE and SQUARE layers");
+    const bool classic = n == 5 && ls[3].kind == LOLA_LAYER_SQUARE && ls[4].kind == LOLA_LAYER_DENSE;
+    const lola_layer &c1 = ls[0], &c2 = ls[2], &d = ls[classic ? 4 : 2];
     const uint32_t N = p->N;
     const int C = c1.in_dim > 0 ? c1.in_dim : 1;
     if (c1.in_h != c1.in_w || c1.k <= 0 || c1.stride <= 0 || c1.maps <= 0 || c1.in_h < c1.k || !c1.weight ||
@@ -827,7 +832,8 @@ int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n
         return unsupported("second convolution must cover the first one's maps and outputs");
     const int n2 = (n1 - c2.k) / c2.stride + 1, V2 = n2 * n2, H = c2.maps * V2;
     if ((uint32_t)V1 > N / 2 || (uint32_t)H > N / 2) return unsupported("layer larger than a slot row");
-    if (d.in_dim != H || !d.weight || d.out_dim <= 0) return unsupported("dense layer must take maps2*n2*n2 inputs");
+    if (classic && (d.in_dim != H || !d.weight || d.out_dim <= 0))
+        return unsupported("dense layer must take maps2*n2*n2 inputs");
     // inputs: convolution representation of every channel
     p->n_inputs = (uint32_t)K;
     p->queries = 1;
@@ -904,6 +910,17 @@ int compile_cifar_net(lola_plan *p, Builder &b, const lola_layer *ls, uint32_t n
     }
     // (+ all biases at once)
     int h = b.column_sum(gathered, c2.bias ? b.cst(bias2, false) : -1);
+    if (!classic) {
+        // a dense vector, value j at slot j
+        ChainVec v;
+        v.regs = {h};
+        v.width = H;
+        for (int j = 0; j < H; ++j) v.pos.push_back((uint32_t)j);
+        const int rc = emit_chain(b, ls, 3, n, v);
+        if (rc) return rc;
+        chain_outputs(p, v);
+        return LOLA_OK;
+    }
     h = b.square(h);
     std::vector<int32_t> steps;
     for (uint32_t s = 1; s < next_pow2((uint32_t)H); s *= 2) steps.push_back((int32_t)s);
@@ -1020,7 +1037,7 @@ static int compile_with(const lola_params *prm, const lola_layer *layers, uint32
     const bool head = l0.kind == LOLA_LAYER_DENSE && n_layers == 3;
     if (recipe == LOLA_RECIPE_DENSE_CHAIN || recipe == LOLA_RECIPE_SPARSE_COLUMN_MAJOR) {
         rc = compile_dense_chain(p, b, layers, n_layers, recipe == LOLA_RECIPE_SPARSE_COLUMN_MAJOR);
-    } else if (l0.kind == LOLA_LAYER_CONV2D && n_layers == 5 && layers[2].kind == LOLA_LAYER_CONV2D) {
+    } else if (l0.kind == LOLA_LAYER_CONV2D && n_layers >= 4 && layers[2].kind == LOLA_LAYER_CONV2D) {
         rc = compile_cifar_net(p, b, layers, n_layers);
     } else if (l0.kind == LOLA_LAYER_CONV2D || l0.kind == LOLA_LAYER_CONV2D_DENSE_INPUT) {
         rc = compile_conv_net(p, b, layers, n_layers, recipe == LOLA_RECIPE_SHARED_REDUCTION);

@@ -485,3 +485,50 @@ def test_compiler_conv_chain_recipe_choice_and_tails():
     # the MNIST network itself (SQUARE, DENSE after the first dense layer)
     # keeps the interleaved output layer: 58 rotations in the shared layout
     assert lola.Plan(wl.PARAMS["mnist_n16384"], networks.mnist_layers(w)).info["n_rotations"] == 58
+
+
+def cifar_chain(m1, m2, side, hidden, seed=15):
+    """The CIFAR-shaped front end on a reduced case, its second convolution
+    followed by SQUARE, DENSE H -> hidden, SQUARE, DENSE hidden -> 10 instead
+    of SQUARE, DENSE: (lola layers, the oracle's tail, weights, image,
+    padded input size)."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    n1 = (side + 2 - 8) // 2 + 1
+    n2 = (n1 - 6) // 2 + 1
+    w = wl.cifar_weights(m1=m1, m2=m2, v2=n2 * n2)
+    H = m2 * n2 * n2
+    rs = wl.rng(seed, 4)
+    W1, b1 = rs.integers(-128, 128, (hidden, H)), rs.integers(-1000, 1000, hidden)
+    W2, b2 = rs.integers(-128, 128, (10, hidden)), rs.integers(-1000, 1000, 10)
+    tail = [("square",), ("dense", W1, b1), ("square",), ("dense", W2, b2)]
+    layers = networks.cifar_layers(w, side + 2)[:3] + [lola.square(), lola.dense(W1, b1), lola.square(),
+                                                      lola.dense(W2, b2)]
+    return layers, tail, w, wl.cifar_image(index=1)[:, :side, :side], side + 2
+
+
+def test_compiler_two_convolutions_then_dense_chain():
+    """CONV2D, SQUARE, CONV2D, SQUARE, DENSE, SQUARE, DENSE (two
+    convolutions followed by two dense layers): the CIFAR-shaped front end
+    up to the second convolution's dense output, then dense vector - row
+    major (a sparse result) and sparse vector - column major (a dense
+    result): against the oracle's schedule and the plain network."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    layers, tail, w, img, n_in = cifar_chain(5, 3, 16, 6)
+    pad = nw.cifar_padded(img)
+    p = wl.PARAMS["chain_n16384"]
+    sched = nw.cifar_chain_schedule(w, tail, n_in)
+    plan = _check_plan(lola, p, layers, networks.cifar_input_values(img), nw.cifar_chain_plain(pad, w, tail), sched)
+    info = plan.info
+    assert info["recipe"] == lola.RECIPE_FIXED and info["n_outputs"] == 1
+    # squares: after each convolution, then one per message of the 6 sparse
+    # hidden values; the row-major layer sums each of its 6 rows over the
+    # whole message
+    assert info["n_square"] == 1 + 1 + 6
+    H = w.conv2_w.shape[0] * 1
+    assert info["n_rotations"] == sched.count("rotate") and sched.count("rotate") >= (H + 6) * 14
+    # a chain ending on a row-major layer: one message per output
+    short = layers[:5]
+    out = lola.Plan(p, short).info
+    assert out["n_outputs"] == 6 and out["n_square"] == 2

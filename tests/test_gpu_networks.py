@@ -132,6 +132,29 @@ def test_conv_then_dense_chain_matches_oracle():
     _run_and_compare(env, sched, nw.conv_chain_plain(img, w.conv_w, w.conv_b, ol))
 
 
+@pytest.mark.timeout(600)
+def test_two_convolutions_then_dense_chain_matches_oracle():
+    """Two convolutions followed by two dense layers (CONV2D, SQUARE, CONV2D,
+    SQUARE, DENSE 3 -> 6, SQUARE, DENSE 6 -> 10; the CIFAR-shaped front end
+    on a 3x16x16 image with 5 and 3 maps, ten data primes): words against
+    the oracle's schedule, and the decrypted outputs against the plain
+    network."""
+    from paper_1812_10659_amd import lola, networks
+    w = wl.cifar_weights(m1=5, m2=3, v2=1)
+    img = wl.cifar_image(index=2)[:, :16, :16]
+    rs = wl.rng(25, 1)
+    W1, b1 = rs.integers(-128, 128, (6, 3)), rs.integers(-1000, 1000, 6)
+    W2, b2 = rs.integers(-128, 128, (10, 6)), rs.integers(-1000, 1000, 10)
+    tail = [("square",), ("dense", W1, b1), ("square",), ("dense", W2, b2)]
+    layers = networks.cifar_layers(w, 18)[:3] + [lola.square(), lola.dense(W1, b1), lola.square(),
+                                                 lola.dense(W2, b2)]
+    print("[gpu-net] two convolutions then a dense chain", flush=True)
+    sched = nw.cifar_chain_schedule(w, tail, 18)
+    env = _setup("chain_n16384", layers, sched, networks.cifar_input_values(img), wl.key_seed(1) + 17,
+                 wl.enc_seed(1) + 17)
+    _run_and_compare(env, sched, nw.cifar_chain_plain(nw.cifar_padded(img), w, tail))
+
+
 def test_cifar_shaped_small_matches_oracle():
     """The two-convolution recipe on a reduced case (3x16x16 image, 5 and 3
     maps), ciphertext words against the oracle's schedule."""

@@ -402,3 +402,25 @@ def test_conv_chain_schedule_equals_plain_network(recipe):
     assert sched.out_slots == [{j: f"y{j}" for j in range(10)}]
     # 12 rows of the row-major layer, each summed over the whole message
     assert sum(1 for op in sched.ops if op[0] == "rotate" and op[3] == nw.ROW_SWAP) == 1 + 12
+
+
+def test_cifar_chain_schedule_equals_plain_network():
+    """The CIFAR-shaped front end followed by a chain: with the tail SQUARE,
+    DENSE the plain network is `cifar_plain`; with SQUARE, DENSE H -> 6,
+    SQUARE, DENSE 6 -> 10 the slot-level run of the oracle's schedule (dense
+    vector - row major on the second convolution's dense output, then sparse
+    vector - column major) equals the plain network mod t at slots 0..9."""
+    from oracle import network as nw
+    w = wl.cifar_weights(m1=5, m2=3, v2=1)
+    img = wl.cifar_image(index=1)[:, :16, :16]
+    pad = nw.cifar_padded(img)
+    assert list(nw.cifar_chain_plain(pad, w, [("square",), ("dense", w.w3, w.b3)])) == list(nw.cifar_plain(pad, w))
+    rs = wl.rng(24, 1)
+    W1, b1 = rs.integers(-128, 128, (6, 3)), rs.integers(-1000, 1000, 6)
+    W2, b2 = rs.integers(-128, 128, (10, 6)), rs.integers(-1000, 1000, 10)
+    tail = [("square",), ("dense", W1, b1), ("square",), ("dense", W2, b2)]
+    t = 1146881
+    exp = list(nw._mod(nw.cifar_chain_plain(pad, w, tail), t))
+    sched = nw.cifar_chain_schedule(w, tail, 18)
+    outs, _ = nw.run_slots(sched, nw.cifar_inputs(pad), t)
+    assert len(outs) == 1 and [int(outs[0][j]) for j in range(10)] == exp
