@@ -532,3 +532,30 @@ def test_compiler_two_convolutions_then_dense_chain():
     short = layers[:5]
     out = lola.Plan(p, short).info
     assert out["n_outputs"] == 6 and out["n_square"] == 2
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_compiler_random_dense_chains(case):
+    """Seeded random chains (1 to 4 dense layers of 2..40 units, a square
+    after some of them, biases or none) under both chain recipes: the plan
+    replayed at slot level equals the plain network, and its op counts and
+    keys equal the oracle's schedule of the same chain."""
+    lola = _lola()
+    p = wl.PARAMS["n4096_3q"]
+    rs = wl.rng(100 + case, 5)
+    n_dense = int(rs.integers(1, 5))
+    dims = [int(d) for d in rs.integers(2, 41, n_dense + 1)]
+    layers, ol = [], []
+    for i in range(n_dense):
+        W = rs.integers(-128, 128, (dims[i + 1], dims[i]))
+        b = rs.integers(-1000, 1000, dims[i + 1]) if rs.integers(0, 2) else None
+        layers.append(lola.dense(W, b))
+        ol.append(("dense", W, b))
+        if rs.integers(0, 2):
+            layers.append(lola.square())
+            ol.append(("square",))
+    x = rs.integers(-128, 128, dims[0])
+    for recipe, sparse in ((lola.RECIPE_DENSE_CHAIN, False), (lola.RECIPE_SPARSE_COLUMN_MAJOR, True)):
+        plan = _check_plan(lola, p, layers, x, nw.dense_chain_plain(x, ol), nw.dense_chain_schedule(ol, p.N, sparse),
+                           recipe=recipe)
+        assert plan.info["recipe"] == recipe
