@@ -206,8 +206,8 @@ def main():
         print(json.dumps({"copied_bytes": src.numel() * 4}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(requests shard across GPUs by request; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(a deployment would shard requests across GPUs, one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
