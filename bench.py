@@ -447,6 +447,9 @@ def main():
         return
     if serving_out:
         out.update(serving_out)
+    out["latency_plan"] = latency_plan_run(ctx, p, w, images[0], args.latency_runs)
+    out["latency_ms"]["latency_plan_p50"] = out["latency_plan"]["p50_ms"]
+    out["latency_ms"]["latency_plan_p99"] = out["latency_plan"]["p99_ms"]
     out["paper_layout"] = paper_layout_run(ctx, w, images, B, C, args.latency_runs)
     out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
     out["mnist_dense_input"] = dense_input_run(B, C, args.latency_runs)
@@ -473,6 +476,62 @@ def main():
 ORACLE_RECIPE = {4: "full", 5: "shared"}
 RECIPE_NAMES = {1: "dense vector - row major", 2: "stacked vector - row major", 3: "fixed",
                 4: "full reduction (the paper's layout)", 5: "shared reduction"}
+
+
+def latency_plan_run(ctx, p, w, img, latency_runs):
+    """The MNIST network compiled for the latency objective (the compiler
+    prices both forms of the sums with every candidate recipe and keeps the
+    lowest predicted single-request latency: the hoisted form, more rotations
+    in fewer levels), timed on one request alone as `latency_ms` is, eager and
+    replayed from a HIP graph; its logits checked against the plain network."""
+    import numpy as np
+    import torch
+
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import requests as rq
+    from paper_1812_10659_amd import workloads as wl
+    plan = lola.Plan(p, networks.mnist_layers(w), objective=lola.OBJECTIVE_LATENCY)
+    plan.load(ctx)
+    key = rq.client_keys(ctx, plan, 1, wl.key_seed(1) + 101)[0]
+    req = rq.encrypted_request(ctx, plan, key, networks.mnist_input_values(img), wl.enc_seed(1) + 101)
+    one = [req]
+    plan.evaluate(ctx, one)
+    torch.cuda.synchronize()
+    got = rq.decrypted_outputs(ctx, plan, key["sk"], req)
+    exp = _plain_logits_mod_t(img, w, p.t)
+    assert [int(v) for v in got] == [int(v) for v in exp], "latency plan: decrypted logits differ"
+    s = torch.cuda.current_stream()
+    lat = []
+    for _ in range(latency_runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        plan.evaluate(ctx, one)
+        e1.record(s)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    gs = torch.cuda.Stream()
+    lat_g = []
+    with torch.cuda.stream(gs):
+        plan.evaluate(ctx, one, graph=True, stream=gs)   # capture
+        gs.synchronize()
+        for _ in range(latency_runs):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(gs)
+            plan.evaluate(ctx, one, graph=True, stream=gs)
+            e1.record(gs)
+            e1.synchronize()
+            lat_g.append(e0.elapsed_time(e1))
+    info = plan.info
+    res = {"recipe": RECIPE_NAMES.get(info["recipe"], str(info["recipe"])),
+           "sums": {1: "sequential", 2: "hoisted"}.get(info["sums"], str(info["sums"])),
+           "rotations": info["n_rotations"], "levels": info["n_waves"], "galois_keys": info["n_galois"],
+           "predicted_latency_ms": round(info["predicted_latency_us"] / 1e3, 3),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "graph_replay_p50_ms": round(float(np.percentile(lat_g, 50)), 3), "checked": 1,
+           "note": "one request alone under the plan compiled for the latency objective; its logits equal the "
+                   "plain network"}
+    plan.close()
+    return res
 
 
 def paper_layout_run(ctx, w, images, B, C, latency_runs, steps=5):

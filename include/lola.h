@@ -435,6 +435,7 @@ typedef struct {
     uint32_t recipe;           /* LOLA_RECIPE_* used for the network's dense layers */
     float predicted_us;        /* cost model: one request (all its queries) inside a large batch, MI355X */
     float predicted_latency_us; /* cost model: one request alone (waves in turn), MI355X */
+    uint32_t sums;             /* LOLA_SUMS_SEQUENTIAL or LOLA_SUMS_HOISTED (lola_compile_options) */
 } lola_plan_info;
 
 /* Representation choice.  Where more than one recipe applies (candidates
@@ -481,9 +482,23 @@ enum { LOLA_RECIPE_AUTO = 0, LOLA_RECIPE_DENSE_ROW_MAJOR = 1, LOLA_RECIPE_STACKE
        LOLA_RECIPE_FIXED = 3 /* reported for patterns with a single recipe */,
        LOLA_RECIPE_FULL_REDUCTION = 4, LOLA_RECIPE_SHARED_REDUCTION = 5,
        LOLA_RECIPE_DENSE_CHAIN = 6, LOLA_RECIPE_SPARSE_COLUMN_MAJOR = 7 };
+/* Form of the rotate-and-sum reductions and shifted combinations
+ * (Sec. 4.2.2).  SEQUENTIAL: x += rot(x, s) step by step, and binary trees of
+ * rotate-and-adds: the fewest rotations, one level each.  HOISTED (a layout
+ * for single requests, where the GPU is mostly idle and the depth sets the
+ * latency): consecutive steps other than the row swap in groups of up to
+ * three, each group the 2^k - 1 rotations of the current message by the
+ * group's subset sums, hoisted (one decomposition for all), added to it in
+ * one linear combination; combinations of shifted messages in one level (every
+ * member rotated by its own offset, then one linear combination).  The same
+ * slots, more rotations (and keys), fewer levels.  AUTO: SEQUENTIAL for the
+ * throughput objective; for the latency objective both are built and priced
+ * with every candidate recipe. */
+enum { LOLA_SUMS_AUTO = 0, LOLA_SUMS_SEQUENTIAL = 1, LOLA_SUMS_HOISTED = 2 };
 typedef struct {
     int32_t objective;
     int32_t recipe;
+    int32_t sums;              /* LOLA_SUMS_* */
 } lola_compile_options;
 
 int lola_compile(const lola_params *params, const lola_layer *layers, uint32_t n_layers, lola_plan **out);

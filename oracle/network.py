@@ -118,11 +118,15 @@ class Schedule:
 
 
 class _Builder:
-    def __init__(self, N, n_inputs):
+    def __init__(self, N, n_inputs, sums="sequential"):
         self.N = N
         self.n_inputs = n_inputs
         self.ops = []
         self.next = n_inputs
+        # "sequential" or "hoisted": the form of rotate-and-sum and of the
+        # combinations of shifted messages (`_rotate_and_sum`, `_combine_tree`)
+        assert sums in ("sequential", "hoisted")
+        self.sums = sums
 
     def reg(self):
         r = self.next
@@ -135,11 +139,41 @@ class _Builder:
 
 
 def _rotate_and_sum(b: _Builder, src: int, steps: Sequence) -> int:
-    """x += rot(x, k) for k in steps (left rotations / row swap)."""
+    """x += rot(x, k) for k in steps (left rotations / row swap).
+
+    With b.sums == "hoisted" the same slots come from groups of up to three
+    consecutive steps other than the row swap: after a group {s_1, .., s_k}
+    the message is the sum over all subsets S of rot(x, sum(S)), formed as x
+    plus its 2^k - 1 hoisted rotations by the non-empty subset sums (subsets in
+    the order of their bit masks, bit i for s_i), added in that order; a row
+    swap or a lone step stays x += rot(x, s)."""
     cur = src
-    for k in steps:
-        r = b.emit("rotate", b.reg(), cur, k)
-        cur = b.emit("add", b.reg(), cur, r)
+    if b.sums == "sequential":
+        for k in steps:
+            r = b.emit("rotate", b.reg(), cur, k)
+            cur = b.emit("add", b.reg(), cur, r)
+        return cur
+    i = 0
+    while i < len(steps):
+        grp = []
+        while i < len(steps) and steps[i] != ROW_SWAP and len(grp) < 3:
+            grp.append(steps[i])
+            i += 1
+        if len(grp) < 2:
+            k = grp[0] if grp else steps[i]
+            if not grp:
+                i += 1
+            r = b.emit("rotate", b.reg(), cur, k)
+            cur = b.emit("add", b.reg(), cur, r)
+            continue
+        terms = [cur]
+        for m in range(1, 1 << len(grp)):
+            amount = sum(grp[j] for j in range(len(grp)) if m >> j & 1)
+            terms.append(b.emit("rotate_hoisted", b.reg(), cur, amount))
+        acc = terms[0]
+        for t in terms[1:]:
+            acc = b.emit("add", b.reg(), acc, t)
+        cur = acc
     return cur
 
 
@@ -148,7 +182,15 @@ def _combine_tree(b: _Builder, regs: Sequence[int], unit: int) -> int:
     member of each pair is rotated right by unit*2^l and added to the even one.
     Rotating right by unit*j is the composition of the rotations for the set
     bits of j, so the result is the same slot vector as the direct sum, with the
-    same number of rotations (len-1) but only log2(len) distinct steps."""
+    same number of rotations (len-1) but only log2(len) distinct steps.
+    With b.sums == "hoisted" (and more than two members): every member j >= 1
+    rotated right by unit*j, then all added in order, one level."""
+    if b.sums == "hoisted" and len(regs) > 2:
+        acc = regs[0]
+        rots = [b.emit("rotate", b.reg(), regs[j], -unit * j) for j in range(1, len(regs))]
+        for r in rots:
+            acc = b.emit("add", b.reg(), acc, r)
+        return acc
     cur = list(regs)
     stride = unit
     while len(cur) > 1:
@@ -304,7 +346,7 @@ def mnist_inputs(img, N=16384):
             for m in conv_representation(mnist_padded(img), 5, 2)]
 
 
-def mnist_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
+def mnist_schedule(wts, N: int = 16384, recipe: str = "full", sums: str = "sequential") -> Schedule:
     """The LoLa MNIST pipeline of Table 1, laid out for N = 16384 as the paper
     does for LoLa-Dense in App. C (16 stacked copies, 7 rounds):
       conv:    per map, sum_{a,b} w[m,a,b] * M_{a,b} (message x scalar) + bias
@@ -323,9 +365,11 @@ def mnist_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
     per logit (7 rotations each) -> 154 rotations.  recipe "shared" sums the
     rounds only within groups of 8 slots before combining them and finishes
     with one shared rotate-and-sum, and packs the ten logits into one message
-    -> 58 rotations, the same values at the valid slots."""
+    -> 58 rotations, the same values at the valid slots.
+    sums "hoisted": every rotate-and-sum and combination in the hoisted form
+    (`_rotate_and_sum`, `_combine_tree`)."""
     assert N == 16384
-    b = _Builder(N, 25)
+    b = _Builder(N, 25, sums)
     maps = []
     for m in range(5):
         acc = None

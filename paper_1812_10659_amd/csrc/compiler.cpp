@@ -50,6 +50,15 @@ uint32_t next_pow2(uint32_t x) {
 
 struct Builder {
     lola_plan *p;
+    // Hoisted sums (the latency layout, LOLA_SUMS_HOISTED): rotate_and_sum
+    // takes its steps in groups of up to three consecutive steps other than
+    // the row swap; a group is the 2^k - 1 rotations of the current message by
+    // the group's subset sums, all hoisted (one decomposition), added to it in
+    // one linear combination: one level instead of k.  combine_tree becomes
+    // one level too: every member after the first rotated by its own offset,
+    // then one linear combination.  The slots are those of the sequential
+    // forms (rotations within a row compose additively).
+    bool hoist_sums = false;
     int reg() { return (int)p->n_regs++; }
     int cst(std::vector<int64_t> v, bool mul) {
         for (auto &x : v) {
@@ -135,7 +144,27 @@ struct Builder {
     }
     int rotate_and_sum(int src, const std::vector<int32_t> &steps) {
         int cur = src;
-        for (int32_t k : steps) cur = rotadd(cur, k, cur);
+        if (!hoist_sums) {
+            for (int32_t k : steps) cur = rotadd(cur, k, cur);
+            return cur;
+        }
+        size_t i = 0;
+        while (i < steps.size()) {
+            std::vector<int32_t> grp;
+            while (i < steps.size() && steps[i] != LOLA_ROW_SWAP && grp.size() < 3) grp.push_back(steps[i++]);
+            if (grp.size() < 2) {   // a row swap or a lone step: a fused rotate-and-add
+                cur = rotadd(cur, grp.empty() ? steps[i++] : grp[0], cur);
+                continue;
+            }
+            std::vector<int> terms{cur};
+            for (uint32_t m = 1; m < (1u << grp.size()); ++m) {
+                int32_t a = 0;
+                for (size_t k = 0; k < grp.size(); ++k)
+                    if (m >> k & 1) a += grp[k];
+                terms.push_back(rot(cur, a, true));
+            }
+            cur = lincomb(terms, std::vector<int64_t>(terms.size(), 1), -1);
+        }
         return cur;
     }
     // sum_k w[k] * srcs[k] (+ cadd) for any number of sources: linear
@@ -164,6 +193,11 @@ struct Builder {
         return lincomb_any(terms, std::vector<int64_t>(terms.size(), 1), cadd);
     }
     int combine_tree(std::vector<int> regs, int32_t unit) {
+        if (hoist_sums && regs.size() > 2) {
+            std::vector<int> terms{regs[0]};
+            for (size_t j = 1; j < regs.size(); ++j) terms.push_back(rot(regs[j], -unit * (int32_t)j));
+            return lincomb_any(terms, std::vector<int64_t>(terms.size(), 1), -1);
+        }
         int32_t stride = unit;
         while (regs.size() > 1) {
             std::vector<int> nxt;
@@ -1024,13 +1058,15 @@ static bool recipe_applies(const lola_layer *layers, uint32_t n_layers, int reci
 
 // Compiles with one recipe (one of recipe_candidates()).
 static int compile_with(const lola_params *prm, const lola_layer *layers, uint32_t n_layers, int recipe,
-                        lola_plan **out) {
+                        int sums, lola_plan **out) {
     *out = nullptr;
     lola_plan *p = new lola_plan();
     p->N = prm->N;
     p->L = prm->L;
     p->t = prm->t;
+    p->sums = (uint32_t)sums;
     Builder b{p};
+    b.hoist_sums = sums == LOLA_SUMS_HOISTED;
     int rc;
     const lola_layer &l0 = layers[0];
     const uint32_t N = prm->N;
@@ -1079,15 +1115,23 @@ int lola_compile_ex(const lola_params *prm, const lola_layer *layers, uint32_t n
         return set_error(LOLA_E_PARAMS, "bad N, t or L");
     const int objective = opts ? opts->objective : LOLA_OBJECTIVE_THROUGHPUT;
     const int recipe = opts ? opts->recipe : LOLA_RECIPE_AUTO;
+    const int sums = opts ? opts->sums : LOLA_SUMS_AUTO;
     if (objective != LOLA_OBJECTIVE_THROUGHPUT && objective != LOLA_OBJECTIVE_LATENCY)
         return set_error(LOLA_E_INVAL, "unknown objective");
     if (recipe < LOLA_RECIPE_AUTO || recipe > LOLA_RECIPE_SPARSE_COLUMN_MAJOR)
         return set_error(LOLA_E_INVAL, "unknown recipe");
-    const std::vector<int> cand = recipe_candidates(layers, n_layers);
+    if (sums < LOLA_SUMS_AUTO || sums > LOLA_SUMS_HOISTED) return set_error(LOLA_E_INVAL, "unknown sums form");
+    // sums forms to build: the one asked for; by default the sequential form,
+    // and for the latency objective the hoisted one beside it
+    std::vector<int> forms;
+    if (sums != LOLA_SUMS_AUTO) forms = {sums};
+    else if (objective == LOLA_OBJECTIVE_LATENCY) forms = {LOLA_SUMS_SEQUENTIAL, LOLA_SUMS_HOISTED};
+    else forms = {LOLA_SUMS_SEQUENTIAL};
+    std::vector<int> cand = recipe_candidates(layers, n_layers);
     if (recipe != LOLA_RECIPE_AUTO) {
         if (!recipe_applies(layers, n_layers, recipe))
             return unsupported("the recipe does not apply to this layer list");
-        return compile_with(prm, layers, n_layers, recipe, out);
+        cand = {recipe};
     }
     // every candidate; keep the cheapest for the objective (the first on ties)
     auto cost = [&](const lola_plan *q) {
@@ -1095,20 +1139,21 @@ int lola_compile_ex(const lola_params *prm, const lola_layer *layers, uint32_t n
     };
     lola_plan *best = nullptr;
     int first_rc = LOLA_OK;
-    for (int r : cand) {
-        lola_plan *q = nullptr;
-        const int rc = compile_with(prm, layers, n_layers, r, &q);
-        if (rc) {
-            if (!first_rc) first_rc = rc;
-            continue;
+    for (int f : forms)
+        for (int r : cand) {
+            lola_plan *q = nullptr;
+            const int rc = compile_with(prm, layers, n_layers, r, f, &q);
+            if (rc) {
+                if (!first_rc) first_rc = rc;
+                continue;
+            }
+            if (!best || cost(q) < cost(best)) {
+                delete best;
+                best = q;
+            } else {
+                delete q;
+            }
         }
-        if (!best || cost(q) < cost(best)) {
-            delete best;
-            best = q;
-        } else {
-            delete q;
-        }
-    }
     if (!best) return first_rc;
     *out = best;
     return LOLA_OK;
@@ -1132,6 +1177,7 @@ int lola_plan_get_info(const lola_plan *p, lola_plan_info *info) {
     info->recipe = p->recipe;
     info->predicted_us = p->predicted_us;
     info->predicted_latency_us = p->predicted_latency_us;
+    info->sums = p->sums;
     for (const Op &o : p->ops) {
         switch (o.kind) {
             case OP_LINCOMB:

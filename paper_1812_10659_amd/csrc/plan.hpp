@@ -47,6 +47,7 @@ struct lola_plan {
     uint32_t N = 0, L = 0, t = 0;
     uint32_t n_inputs = 0, queries = 1;
     uint32_t recipe = 3;                        // LOLA_RECIPE_*
+    uint32_t sums = 1;                          // LOLA_SUMS_SEQUENTIAL or LOLA_SUMS_HOISTED
     float predicted_us = 0;                     // cost model, one request inside a large batch
     float predicted_latency_us = 0;             // cost model, one request alone
     uint32_t n_regs = 0;                        // virtual registers (SSA)

@@ -447,17 +447,19 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n_inputs", "n_outputs", "n_ops", "n_consts", "n_galois", "n_waves", "queries",
         "n_rotations", "n_mul_plain", "n_mul_scalar", "n_square", "n_add_plain", "n_add", "n_phys_regs",
-        "recipe")] + [("predicted_us", ctypes.c_float), ("predicted_latency_us", ctypes.c_float)]
+        "recipe")] + [("predicted_us", ctypes.c_float), ("predicted_latency_us", ctypes.c_float),
+                      ("sums", ctypes.c_uint32)]
 
 
 class _CompileOptions(ctypes.Structure):
-    _fields_ = [("objective", ctypes.c_int32), ("recipe", ctypes.c_int32)]
+    _fields_ = [("objective", ctypes.c_int32), ("recipe", ctypes.c_int32), ("sums", ctypes.c_int32)]
 
 
 OBJECTIVE_THROUGHPUT, OBJECTIVE_LATENCY = 0, 1
 RECIPE_AUTO, RECIPE_DENSE_ROW_MAJOR, RECIPE_STACKED_ROW_MAJOR, RECIPE_FIXED = 0, 1, 2, 3
 RECIPE_FULL_REDUCTION, RECIPE_SHARED_REDUCTION = 4, 5
 RECIPE_DENSE_CHAIN, RECIPE_SPARSE_COLUMN_MAJOR = 6, 7
+SUMS_AUTO, SUMS_SEQUENTIAL, SUMS_HOISTED = 0, 1, 2
 
 
 class Request(ctypes.Structure):
@@ -533,7 +535,8 @@ def _plan_sig():
 class Plan:
     """lola_plan: a layer list compiled for a parameter set (host logic)."""
 
-    def __init__(self, params, layers, objective: int = OBJECTIVE_THROUGHPUT, recipe: int = RECIPE_AUTO):
+    def __init__(self, params, layers, objective: int = OBJECTIVE_THROUGHPUT, recipe: int = RECIPE_AUTO,
+                 sums: int = SUMS_AUTO):
         L = _plan_sig()
         arr = (Layer * len(layers))()
         self._keep = []
@@ -549,7 +552,7 @@ class Plan:
             arr[k] = ly
         ps, self._q = _params_struct(params)
         h = ctypes.c_void_p()
-        opts = _CompileOptions(int(objective), int(recipe))
+        opts = _CompileOptions(int(objective), int(recipe), int(sums))
         _check(L.lola_compile_ex(ctypes.byref(ps), arr, len(layers), ctypes.byref(opts), ctypes.byref(h)))
         self.h = h
         self._keep = []

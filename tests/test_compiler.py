@@ -82,8 +82,8 @@ def dump_to_oracle_ops(plan):
     return nw.Schedule(plan.N, plan.info["n_inputs"], ops, outputs)
 
 
-def _check_plan(lola, params, layers, inputs_values, expected, oracle_sched, recipe=0):
-    plan = lola.Plan(params, layers, recipe=recipe)
+def _check_plan(lola, params, layers, inputs_values, expected, oracle_sched, recipe=0, sums=0):
+    plan = lola.Plan(params, layers, recipe=recipe, sums=sums)
     sched = dump_to_oracle_ops(plan)
     msgs = lola_pack(plan, inputs_values)
     outs, _ = nw.run_slots(sched, [{k: int(v) for k, v in enumerate(m) if v} for m in msgs], params.t)
@@ -559,3 +559,51 @@ def test_compiler_random_dense_chains(case):
         plan = _check_plan(lola, p, layers, x, nw.dense_chain_plain(x, ol), nw.dense_chain_schedule(ol, p.N, sparse),
                            recipe=recipe)
         assert plan.info["recipe"] == recipe
+
+
+@pytest.mark.parametrize("recipe,name", [(4, "full"), (5, "shared")])
+def test_compiler_mnist_hoisted_sums(recipe, name):
+    """The hoisted form of the sums (LOLA_SUMS_HOISTED): every rotate-and-sum
+    in groups of up to three steps as hoisted rotations by the subset sums,
+    every combination of shifted messages in one level.  The plan replayed at
+    slot level equals the plain network; rotations, hoisted rotations,
+    products, squares and keys equal the oracle's schedule in the same form;
+    the plan is shallower than the sequential one."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    w, img = wl.mnist_weights(), wl.mnist_image(index=4)
+    p = wl.PARAMS["mnist_n16384"]
+    layers = networks.mnist_layers(w)
+    sched = nw.mnist_schedule(w, recipe=name, sums="hoisted")
+    plan = lola.Plan(p, layers, recipe=recipe, sums=lola.SUMS_HOISTED)
+    assert plan.info["sums"] == lola.SUMS_HOISTED
+    _check_plan(lola, p, layers, networks.mnist_input_values(img), nw.mnist_plain(img, w), sched, recipe=recipe,
+                sums=lola.SUMS_HOISTED)
+    seq = lola.Plan(p, layers, recipe=recipe, sums=lola.SUMS_SEQUENTIAL).info
+    assert seq["sums"] == lola.SUMS_SEQUENTIAL
+    assert plan.info["n_waves"] < seq["n_waves"] and plan.info["n_rotations"] > seq["n_rotations"]
+    assert plan.info["n_rotations"] == {"full": 322, "shared": 106}[name]
+
+
+def test_sums_form_follows_the_objective():
+    """AUTO builds the sequential form for throughput; for latency both forms
+    of every candidate recipe are priced and the lowest predicted latency is
+    kept (here the hoisted shared reduction); a forced form is honoured and
+    an unknown one is an argument error."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    p, layers = wl.PARAMS["mnist_n16384"], networks.mnist_layers(wl.mnist_weights())
+    thr = lola.Plan(p, layers).info
+    assert thr["sums"] == lola.SUMS_SEQUENTIAL and thr["recipe"] == lola.RECIPE_SHARED_REDUCTION
+    lat = lola.Plan(p, layers, objective=lola.OBJECTIVE_LATENCY).info
+    pred = {(r, f): lola.Plan(p, layers, recipe=r, sums=f).info["predicted_latency_us"]
+            for r in (lola.RECIPE_FULL_REDUCTION, lola.RECIPE_SHARED_REDUCTION)
+            for f in (lola.SUMS_SEQUENTIAL, lola.SUMS_HOISTED)}
+    assert (lat["recipe"], lat["sums"]) == min(pred, key=pred.get)
+    assert (lat["recipe"], lat["sums"]) == (lola.RECIPE_SHARED_REDUCTION, lola.SUMS_HOISTED)
+    forced = lola.Plan(p, layers, objective=lola.OBJECTIVE_LATENCY, sums=lola.SUMS_SEQUENTIAL).info
+    assert forced["sums"] == lola.SUMS_SEQUENTIAL
+    for bad in (-1, 3):
+        with pytest.raises(lola.LolaError) as e:
+            lola.Plan(p, layers, sums=bad)
+        assert e.value.code == -1

@@ -13,12 +13,12 @@ from paper_1812_10659_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def _setup(pname, layers, oracle_sched, values, key_seed, enc_seed, with_oracle=True, recipe=0):
+def _setup(pname, layers, oracle_sched, values, key_seed, enc_seed, with_oracle=True, recipe=0, sums=0):
     import torch
     from paper_1812_10659_amd import lola, networks
     p = wl.PARAMS[pname]
     ctx = lola.Context(p)
-    plan = lola.Plan(p, layers, recipe=recipe)
+    plan = lola.Plan(p, layers, recipe=recipe, sums=sums)
     plan.load(ctx)
     gal = plan.galois()
     sk = ctx.keygen_secret(key_seed)
@@ -85,6 +85,32 @@ def test_mnist_network_matches_oracle(name, recipe):
                  wl.key_seed(1), wl.enc_seed(1), recipe=recipe)
     assert env["plan"].info["recipe"] == recipe
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
+
+
+def test_mnist_hoisted_sums_matches_oracle():
+    """The MNIST network in the layout for single requests (shared reduction,
+    every rotate-and-sum and combination in the hoisted form: 106 rotations
+    of which 93 hoisted, in fewer levels): words against the oracle's
+    schedule in the same form, decrypted logits against the plain network;
+    the batched evaluation of two requests equals their single runs."""
+    import torch
+    from paper_1812_10659_amd import lola, networks
+    w, img = wl.mnist_weights(), wl.mnist_image(index=5)
+    print("[gpu-net] mnist shared, hoisted sums", flush=True)
+    sched = nw.mnist_schedule(w, recipe="shared", sums="hoisted")
+    env = _setup("mnist_n16384", networks.mnist_layers(w), sched, networks.mnist_input_values(img),
+                 wl.key_seed(1) + 21, wl.enc_seed(1) + 21, recipe=lola.RECIPE_SHARED_REDUCTION,
+                 sums=lola.SUMS_HOISTED)
+    assert env["plan"].info["sums"] == lola.SUMS_HOISTED and env["plan"].info["n_rotations"] == 106
+    _run_and_compare(env, sched, nw.mnist_plain(img, w))
+    ctx, plan, req = env["ctx"], env["plan"], env["req"]
+    single = [_coeff(ctx, o) for o in req["outputs"]]
+    twin = dict(req, outputs=[ctx.empty_ct() for _ in req["outputs"]])
+    plan.evaluate(ctx, [req, twin])
+    torch.cuda.synchronize()
+    for a, b in zip(req["outputs"], twin["outputs"]):
+        assert np.array_equal(_coeff(ctx, a), _coeff(ctx, b))
+    assert all(np.array_equal(_coeff(ctx, o), s) for o, s in zip(req["outputs"], single))
 
 
 @pytest.mark.parametrize("name,recipe", RECIPES)

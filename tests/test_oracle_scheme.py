@@ -424,3 +424,32 @@ def test_cifar_chain_schedule_equals_plain_network():
     sched = nw.cifar_chain_schedule(w, tail, 18)
     outs, _ = nw.run_slots(sched, nw.cifar_inputs(pad), t)
     assert len(outs) == 1 and [int(outs[0][j]) for j in range(10)] == exp
+
+
+@pytest.mark.parametrize("recipe", ["full", "shared"])
+def test_hoisted_sums_schedule_equals_plain_network(recipe):
+    """The hoisted form of the MNIST schedule's sums (groups of up to three
+    rotate-and-sum steps as hoisted rotations by their subset sums, shifted
+    combinations in one level) gives the plain network at the valid slots,
+    as the sequential form does, with more rotations in fewer levels of key
+    switches."""
+    from oracle import network as nw
+    wts, img = wl.mnist_weights(), wl.mnist_image(index=6)
+    t = 1146881
+    exp = list(nw._mod(nw.mnist_plain(img, wts), t))
+    seq = nw.mnist_schedule(wts, recipe=recipe)
+    hoi = nw.mnist_schedule(wts, recipe=recipe, sums="hoisted")
+    outs, _ = nw.run_slots(hoi, nw.mnist_inputs(img), t)
+    got = [int(o[0]) for o in outs] if recipe == "full" else [int(outs[0][8 * o]) for o in range(10)]
+    assert got == exp
+    assert hoi.count("rotate") > seq.count("rotate") and hoi.count("rotate_hoisted") > seq.count("rotate_hoisted")
+
+    def depth(sc):
+        # longest chain of key switches (rotations and squares) through the ops
+        d = {}
+        for op in sc.ops:
+            srcs = [op[2], op[3]] if op[0] == "add" else [op[2]]
+            base = max((d.get(x, 0) for x in srcs), default=0)
+            d[op[1]] = base + (1 if op[0] in ("rotate", "rotate_hoisted", "square") else 0)
+        return max(d[o] for o in sc.outputs)
+    assert depth(hoi) < depth(seq)
