@@ -447,9 +447,9 @@ def main():
         return
     if serving_out:
         out.update(serving_out)
-    out["latency_plan"] = latency_plan_run(ctx, p, w, images[0], args.latency_runs)
-    out["latency_ms"]["latency_plan_p50"] = out["latency_plan"]["p50_ms"]
-    out["latency_ms"]["latency_plan_p99"] = out["latency_plan"]["p99_ms"]
+    out["latency_plans"] = latency_plans_run(ctx, w, images[0], args.latency_runs)
+    out["latency_ms"]["latency_plan_p50"] = out["latency_plans"]["mnist"]["latency_plan"]["p50_ms"]
+    out["latency_ms"]["latency_plan_p99"] = out["latency_plans"]["mnist"]["latency_plan"]["p99_ms"]
     out["paper_layout"] = paper_layout_run(ctx, w, images, B, C, args.latency_runs)
     out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
     out["mnist_dense_input"] = dense_input_run(B, C, args.latency_runs)
@@ -478,60 +478,89 @@ RECIPE_NAMES = {1: "dense vector - row major", 2: "stacked vector - row major", 
                 4: "full reduction (the paper's layout)", 5: "shared reduction"}
 
 
-def latency_plan_run(ctx, p, w, img, latency_runs):
-    """The MNIST network compiled for the latency objective (the compiler
-    prices both forms of the sums with every candidate recipe and keeps the
-    lowest predicted single-request latency: the hoisted form, more rotations
-    in fewer levels), timed on one request alone as `latency_ms` is, eager and
-    replayed from a HIP graph; its logits checked against the plain network."""
+def _one_request_latency(ctx, plan, req, runs):
+    """p50 and p99 (ms) of one request evaluated alone, HIP events around
+    each call on the current stream."""
     import numpy as np
     import torch
-
-    from paper_1812_10659_amd import lola, networks
-    from paper_1812_10659_amd import requests as rq
-    from paper_1812_10659_amd import workloads as wl
-    plan = lola.Plan(p, networks.mnist_layers(w), objective=lola.OBJECTIVE_LATENCY)
-    plan.load(ctx)
-    key = rq.client_keys(ctx, plan, 1, wl.key_seed(1) + 101)[0]
-    req = rq.encrypted_request(ctx, plan, key, networks.mnist_input_values(img), wl.enc_seed(1) + 101)
     one = [req]
     plan.evaluate(ctx, one)
     torch.cuda.synchronize()
-    got = rq.decrypted_outputs(ctx, plan, key["sk"], req)
-    exp = _plain_logits_mod_t(img, w, p.t)
-    assert [int(v) for v in got] == [int(v) for v in exp], "latency plan: decrypted logits differ"
     s = torch.cuda.current_stream()
     lat = []
-    for _ in range(latency_runs):
+    for _ in range(runs):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         plan.evaluate(ctx, one)
         e1.record(s)
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
-    gs = torch.cuda.Stream()
-    lat_g = []
-    with torch.cuda.stream(gs):
-        plan.evaluate(ctx, one, graph=True, stream=gs)   # capture
-        gs.synchronize()
-        for _ in range(latency_runs):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(gs)
-            plan.evaluate(ctx, one, graph=True, stream=gs)
-            e1.record(gs)
-            e1.synchronize()
-            lat_g.append(e0.elapsed_time(e1))
-    info = plan.info
-    res = {"recipe": RECIPE_NAMES.get(info["recipe"], str(info["recipe"])),
-           "sums": {1: "sequential", 2: "hoisted"}.get(info["sums"], str(info["sums"])),
-           "rotations": info["n_rotations"], "levels": info["n_waves"], "galois_keys": info["n_galois"],
-           "predicted_latency_ms": round(info["predicted_latency_us"] / 1e3, 3),
-           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "graph_replay_p50_ms": round(float(np.percentile(lat_g, 50)), 3), "checked": 1,
-           "note": "one request alone under the plan compiled for the latency objective; its logits equal the "
-                   "plain network"}
-    plan.close()
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+
+def _latency_plan_case(ctx, p, layers, values, expected, runs, key_seed):
+    """One network under the plan compiled for the latency objective and under
+    the default (throughput) plan, each timed on one request alone; the
+    latency plan's outputs checked against the plain network mod t."""
+    import numpy as np
+
+    from paper_1812_10659_amd import lola
+    from paper_1812_10659_amd import requests as rq
+    res = {}
+    for tag, obj in (("throughput_plan", lola.OBJECTIVE_THROUGHPUT), ("latency_plan", lola.OBJECTIVE_LATENCY)):
+        plan = lola.Plan(p, layers, objective=obj)
+        plan.load(ctx)
+        key = rq.client_keys(ctx, plan, 1, key_seed)[0]
+        # a plan packing several queries per message gets the same query in each
+        req = rq.encrypted_request(ctx, plan, key, np.tile(np.asarray(values), plan.info["queries"]), key_seed + 1)
+        p50, p99 = _one_request_latency(ctx, plan, req, runs)
+        info = plan.info
+        res[tag] = {"recipe": RECIPE_NAMES.get(info["recipe"], str(info["recipe"])),
+                    "sums": {1: "sequential", 2: "hoisted"}.get(info["sums"], str(info["sums"])),
+                    "rotations": info["n_rotations"], "levels": info["n_waves"], "galois_keys": info["n_galois"],
+                    "predicted_latency_ms": round(info["predicted_latency_us"] / 1e3, 3),
+                    "p50_ms": round(p50, 3), "p99_ms": round(p99, 3)}
+        if obj == lola.OBJECTIVE_LATENCY:
+            got = rq.decrypted_outputs(ctx, plan, key["sk"], req)
+            n = len(expected)
+            assert [int(v) for v in got[:n]] == [int(v) % p.t for v in expected], "latency plan: outputs differ"
+            res[tag]["checked"] = 1
+        plan.close()
     return res
+
+
+def latency_plans_run(ctx, w, img, latency_runs):
+    """Single-request latency of each network under the plan compiled for the
+    latency objective (the compiler prices both forms of the sums, sequential
+    and hoisted, with every candidate recipe and keeps the lowest predicted
+    latency) beside the default throughput plan, both timed here the same
+    way; every latency plan's outputs checked against the plain network."""
+    import numpy as np
+
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import workloads as wl
+    out = {}
+    pm = wl.PARAMS["mnist_n16384"]
+    mv = networks.mnist_input_values(img)
+    out["mnist"] = _latency_plan_case(ctx, pm, networks.mnist_layers(w), mv, _plain_logits_mod_t(img, w, pm.t),
+                                      latency_runs, wl.key_seed(1) + 101)
+    ws = wl.mnist_small_weights()
+    out["mnist_small"] = _latency_plan_case(ctx, pm, networks.mnist_small_layers(ws), mv,
+                                            _plain_small_logits(img, ws), latency_runs, wl.key_seed(1) + 103)
+    pd = wl.PARAMS["mnist_dense_n16384"]
+    out["mnist_dense_input"] = _latency_plan_case(lola.Context(pd), pd, networks.mnist_dense_layers(w), mv,
+                                                  _plain_logits_mod_t(img, w, pd.t), latency_runs,
+                                                  wl.key_seed(1) + 105)
+    ph, wh = wl.PARAMS["head_n16384"], wl.head_weights()
+    f = wl.head_features(1)[0]
+    out["head"] = _latency_plan_case(lola.Context(ph), ph, networks.head_layers(wh), f, _head_plain(f, wh),
+                                     latency_runs, wl.key_seed(3) + 107)
+    p0 = wl.PARAMS["n4096_3q"]
+    x, W = wl.dense64_inputs()
+    y = W.astype(object).dot(np.asarray(x).astype(object))
+    out["dense64"] = _latency_plan_case(lola.Context(p0), p0, networks.dense64_layers(W), x, list(y * y),
+                                        latency_runs, wl.key_seed(0) + 109)
+    return out
 
 
 def paper_layout_run(ctx, w, images, B, C, latency_runs, steps=5):

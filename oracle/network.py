@@ -306,13 +306,13 @@ def dense64_inputs(x, N):
     return [{s: int(x[s % 64]) for s in range(N)}]
 
 
-def dense64_schedule(W, N: int = 4096) -> Schedule:
+def dense64_schedule(W, N: int = 4096, sums: str = "sequential") -> Schedule:
     """Stacked vector - row major (Sec. 4.2.2): one point-wise product with the
     64 rows of W laid out row j at slots 64j..64j+63, then rotations of size
     1, 2, ..., 32 and additions; value j ends at slot 64j (interleaved), then
     squared."""
     assert N == 4096
-    b = _Builder(N, 1)
+    b = _Builder(N, 1, sums)
     W = np.asarray(W, dtype=np.int64)
     rows = {64 * j + i: int(W[j, i]) for j in range(64) for i in range(64)}
     z = b.emit("mul_plain", b.reg(), 0, rows)
@@ -388,7 +388,7 @@ def mnist_schedule(wts, N: int = 16384, recipe: str = "full", sums: str = "seque
     return Schedule(N, 25, b.ops, outs, slots)
 
 
-def mnist_small_schedule(wts, N: int = 16384) -> Schedule:
+def mnist_small_schedule(wts, N: int = 16384, sums: str = "sequential") -> Schedule:
     """LoLa-Small (Sec. 4.3: a convolution layer, the square activation and one
     dense layer), laid out like the first half of `mnist_schedule`:
       conv, combine (tree over 169, 338, 676), square, stack 16 copies at
@@ -397,7 +397,7 @@ def mnist_small_schedule(wts, N: int = 16384) -> Schedule:
                in block o (o < 10), rotate-and-sum 1..512, bias added at slot
                1024 o -> logit o at slot 1024 o of the one output message."""
     assert N == 16384
-    b = _Builder(N, 25)
+    b = _Builder(N, 25, sums)
     maps = []
     for m in range(5):
         acc = None
@@ -430,7 +430,7 @@ def mnist_dense_inputs(img, N=16384):
     return [{29 * i + j: int(p[i, j]) for i in range(29) for j in range(29) if p[i, j]}]
 
 
-def mnist_dense_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
+def mnist_dense_schedule(wts, N: int = 16384, recipe: str = "full", sums: str = "sequential") -> Schedule:
     """LoLa-Dense (App. C, Table 3) for N = 16384:
       masks:   message (a, b) = the input rotated left by 29 a + b (so padded
                pixel (2y + a, 2x + b) sits at slot 58 y + 2 x) times the 0/1
@@ -452,7 +452,7 @@ def mnist_dense_schedule(wts, N: int = 16384, recipe: str = "full") -> Schedule:
     assert N == 16384
     P, C = MNIST_DENSE_BLOCK, N // MNIST_DENSE_BLOCK
     R = (100 + C - 1) // C
-    b = _Builder(N, 1)
+    b = _Builder(N, 1, sums)
     corners = {58 * y + 2 * x: 1 for y in range(MNIST_OUT) for x in range(MNIST_OUT)}
     msgs = []
     for a in range(5):
@@ -815,7 +815,8 @@ def head_inputs(features, N=16384):
     return [{HEAD_BLOCK * q + i: int(f[q, i]) for q in range(f.shape[0]) for i in range(HEAD_BLOCK)}]
 
 
-def head_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int = 10) -> Schedule:
+def head_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int = 10,
+                  sums: str = "sequential") -> Schedule:
     """Dense vector - row major (Sec. 4.2.2) for 4096 -> 256: per hidden unit
     j, product with row j repeated in every block, rotate-and-sum over
     1..2048 (each block's sum lands at its first slot), mask, then rotate
@@ -826,7 +827,7 @@ def head_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int =
     assert N == 16384
     nb = N // HEAD_BLOCK
     nh = wts.w1.shape[0] if n_hidden is None else n_hidden
-    b = _Builder(N, 1)
+    b = _Builder(N, 1, sums)
     hidden = []
     for j in range(nh):
         rows = {HEAD_BLOCK * q + i: int(wts.w1[j, i]) for q in range(nb) for i in range(HEAD_BLOCK)}
@@ -857,7 +858,8 @@ def head_stacked_inputs(features, N=16384):
     return [{HEAD_BLOCK * c + i: int(f[i]) for c in range(N // HEAD_BLOCK) for i in range(f.size)}]
 
 
-def head_stacked_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int = 10) -> Schedule:
+def head_stacked_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_out: int = 10,
+                          sums: str = "sequential") -> Schedule:
     """The same head, one query per message, with the stacked vector - row
     major method (Sec. 4.2.2) for the hidden layer:
       rounds:  C = N / 4096 copies; round rho multiplies by rows C rho + c in
@@ -874,7 +876,7 @@ def head_stacked_schedule(wts, N: int = 16384, n_hidden: int | None = None, n_ou
     C = N // P
     nh = wts.w1.shape[0] if n_hidden is None else n_hidden
     R = (nh + C - 1) // C
-    b = _Builder(N, 1)
+    b = _Builder(N, 1, sums)
     rounds = []
     for rho in range(R):
         rows, mask, bias = {}, {}, {}

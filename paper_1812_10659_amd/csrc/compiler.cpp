@@ -771,7 +771,12 @@ float predict_latency_us(const lola_plan *p) {
         if (hrot > 0) {   // sources' digits and transforms, then gathered products and mod-down
             const double ns = (double)hsrc.size();
             us += 17.0 * sl * rounds(ns * L) + 19.0 * sl * rounds(ns * L * (L + 1));
-            us += 14.0 * sl * (L / 7.0) * rounds(hrot * (L + 1)) + 17.0 * sl * rounds(2 * hrot * L);
+            // the gathered products read each rotation's key and its source's
+            // transformed digits, 3 L (L+1) limbs: many hoisted rotations in a
+            // wave are bound by that traffic (about 5.5 TB/s measured)
+            const double limb_bytes = 4.0 * (double)p->N;
+            const double bytes_us = hrot * 3.0 * L * (L + 1) * limb_bytes / 5.5e6;
+            us += std::max(14.0 * sl * (L / 7.0) * rounds(hrot * (L + 2)), bytes_us) + 17.0 * sl * rounds(2 * hrot * L);
         }
     }
     return (float)us;

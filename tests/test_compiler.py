@@ -607,3 +607,44 @@ def test_sums_form_follows_the_objective():
         with pytest.raises(lola.LolaError) as e:
             lola.Plan(p, layers, sums=bad)
         assert e.value.code == -1
+
+
+@pytest.mark.parametrize("net", ["dense64", "small", "dense_input", "head", "head_stacked"])
+def test_compiler_hoisted_sums_every_network(net):
+    """The hoisted form of the sums on the other networks (dense-64, LoLa-Small,
+    LoLa-Dense in the shared reduction, the head under both recipes): the plan
+    replayed at slot level equals the plain network, and its rotations,
+    hoisted rotations, products, squares and keys equal the oracle's schedule
+    in the same form; the plan is no deeper than the sequential one."""
+    lola = _lola()
+    from paper_1812_10659_amd import networks
+    H = lola.SUMS_HOISTED
+    if net == "dense64":
+        x, W = wl.dense64_inputs()
+        p, layers, vals, exp = wl.PARAMS["n4096_3q"], networks.dense64_layers(W), x, nw.dense64_plain(x, W)
+        sched, recipe = nw.dense64_schedule(W, sums="hoisted"), 0
+    elif net == "small":
+        w, img = wl.mnist_small_weights(), wl.mnist_image(index=7)
+        p, layers = wl.PARAMS["mnist_n16384"], networks.mnist_small_layers(w)
+        vals, exp = networks.mnist_input_values(img), nw.mnist_small_plain(img, w)
+        sched, recipe = nw.mnist_small_schedule(w, sums="hoisted"), 0
+    elif net == "dense_input":
+        w, img = wl.mnist_weights(), wl.mnist_image(index=8)
+        p, layers = wl.PARAMS["mnist_dense_n16384"], networks.mnist_dense_layers(w)
+        vals, exp = networks.mnist_input_values(img), nw.mnist_plain(img, w)
+        sched, recipe = nw.mnist_dense_schedule(w, recipe="shared", sums="hoisted"), lola.RECIPE_SHARED_REDUCTION
+    else:
+        w = wl.head_weights()
+        wt = wl.HeadWeights(w.w1[:8], w.b1[:8], w.w2[:, :8], w.b2)
+        p, layers = wl.PARAMS["head_n16384"], networks.head_layers(w, 8)
+        if net == "head":
+            f = wl.head_features(4)
+            vals, exp = f, np.concatenate([nw.head_plain(f[q], wt) for q in range(4)])
+            sched, recipe = nw.head_schedule(w, n_hidden=8, sums="hoisted"), lola.RECIPE_DENSE_ROW_MAJOR
+        else:
+            f = wl.head_features(1)
+            vals, exp = f[0], nw.head_plain(f[0], wt)
+            sched, recipe = nw.head_stacked_schedule(w, n_hidden=8, sums="hoisted"), lola.RECIPE_STACKED_ROW_MAJOR
+    plan = _check_plan(lola, p, layers, vals, exp, sched, recipe=recipe, sums=H)
+    seq = lola.Plan(p, layers, recipe=recipe, sums=lola.SUMS_SEQUENTIAL).info
+    assert plan.info["sums"] == H and plan.info["n_waves"] <= seq["n_waves"]

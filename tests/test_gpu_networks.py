@@ -113,6 +113,27 @@ def test_mnist_hoisted_sums_matches_oracle():
     assert all(np.array_equal(_coeff(ctx, o), s) for o, s in zip(req["outputs"], single))
 
 
+@pytest.mark.parametrize("net", ["dense64", "small"])
+def test_hoisted_sums_small_networks_match_oracle(net):
+    """Dense-64 at N=4096 and LoLa-Small with hoisted sums: words against the
+    oracle's schedules in the same form, outputs against the plain networks."""
+    from paper_1812_10659_amd import lola, networks
+    print(f"[gpu-net] {net}, hoisted sums", flush=True)
+    if net == "dense64":
+        x, W = wl.dense64_inputs()
+        sched = nw.dense64_schedule(W, sums="hoisted")
+        env = _setup("n4096_3q", networks.dense64_layers(W), sched, x, wl.key_seed(0) + 23, wl.enc_seed(0) + 23,
+                     sums=lola.SUMS_HOISTED)
+        _run_and_compare(env, sched, nw.dense64_plain(x, W))
+    else:
+        w, img = wl.mnist_small_weights(), wl.mnist_image(index=7)
+        sched = nw.mnist_small_schedule(w, sums="hoisted")
+        env = _setup("mnist_n16384", networks.mnist_small_layers(w), sched, networks.mnist_input_values(img),
+                     wl.key_seed(1) + 25, wl.enc_seed(1) + 25, sums=lola.SUMS_HOISTED)
+        _run_and_compare(env, sched, nw.mnist_small_plain(img, w))
+    assert env["plan"].info["sums"] == lola.SUMS_HOISTED
+
+
 @pytest.mark.parametrize("name,recipe", RECIPES)
 def test_mnist_dense_input_network_matches_oracle(name, recipe):
     """LoLa-Dense: one dense input message, masks and rotations build the
