@@ -584,11 +584,33 @@ int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint
 int lola_server_model_info(const lola_server *srv, uint32_t model_id, uint32_t *slots, uint64_t *footprint_bytes,
                            uint64_t *scratch_bytes, uint64_t *launched_jobs);
 int lola_server_submit(lola_server *srv, uint32_t model_id, const lola_request *req, uint64_t tag);
+/* A solo plan for a model: the same network compiled for one request alone
+ * (lola_compile_ex with the latency objective; more rotations in fewer
+ * levels), loaded on the model's context, with the same input and output
+ * maps as the model's plan.  It gets one slot of its own (charged to the
+ * budget).  A request submitted with keys for it (lola_server_submit_ex) that
+ * finds the model idle -- nothing else in flight or queued -- runs under the
+ * solo plan; requests arriving meanwhile run under the model's plan, their
+ * waves in the same rounds.  Set before any request is submitted
+ * (LOLA_E_INVAL otherwise; LOLA_E_SHAPE for other maps, LOLA_E_NOMEM past the
+ * budget).  A result's words are those of lola_evaluate on the request alone
+ * under the plan that served it (lola_server_poll_ex says which); both
+ * decrypt to the same values. */
+int lola_server_set_solo_plan(lola_server *srv, uint32_t model_id, lola_plan *solo);
+/* lola_server_submit with the Galois keys of the solo plan (in the order of
+ * its lola_plan_galois; NULL: the request always runs under the model's
+ * plan).  The request's other buffers serve both plans. */
+int lola_server_submit_ex(lola_server *srv, uint32_t model_id, const lola_request *req,
+                          const uint32_t *const *solo_gk_dev, uint64_t tag);
 /* One scheduling round (non-blocking except to keep two rounds in flight per
  * model); *pending = queued + in-flight requests. */
 int lola_server_step(lola_server *srv, uint32_t *pending);
 /* Tags of requests completed since the last poll (at most cap). */
 int lola_server_poll(lola_server *srv, uint64_t *tags, uint32_t cap, uint32_t *n);
+/* As lola_server_poll, with the plan that served each request in forms[i]
+ * (forms may be NULL). */
+enum { LOLA_SERVED_PLAN = 0, LOLA_SERVED_SOLO = 1 };
+int lola_server_poll_ex(lola_server *srv, uint64_t *tags, uint32_t *forms, uint32_t cap, uint32_t *n);
 
 /* Kernel timing (for measurement).  While enabled, the library records a HIP
  * event pair on the launch stream around every launch of its hot-path

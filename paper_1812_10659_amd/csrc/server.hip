@@ -12,6 +12,12 @@
 // forked from and joined back to the model's stream within the round, so one
 // half's kernels fill the other's launch tails.  A request's slot is
 // released when the event recorded after its last wave has completed.
+//
+// A model may also hold a solo plan (the same network compiled for one
+// request alone: more rotations in fewer levels) with one slot of its own.  A
+// request that arrives to an idle model, with keys for the solo plan, runs
+// under it; requests arriving meanwhile run under the model's plan, and their
+// waves share the rounds with the solo request's.
 #include <chrono>
 #include <deque>
 
@@ -29,14 +35,15 @@ constexpr uint32_t SRV_SOLO_WAVES = 8;  // waves a lone request takes per round
 struct Pending {
     uint64_t tag;
     const uint32_t *rlk;
-    std::vector<const uint32_t *> gk, in;
+    std::vector<const uint32_t *> gk, gk_solo, in;   // gk_solo: keys of the solo plan, or empty
     std::vector<uint32_t *> out;
-    lola_request view() const {
-        return lola_request{rlk, gk.data(), in.data(), out.data()};
+    lola_request view(bool solo) const {
+        return lola_request{rlk, solo ? gk_solo.data() : gk.data(), in.data(), out.data()};
     }
 };
 
 struct Slot {
+    const lola_plan *plan = nullptr;   // the model's plan, or its solo plan for the solo slot
     bool busy = false;
     bool finished = false;      // last wave issued; waiting for its round event
     uint64_t finish_round = 0;
@@ -49,6 +56,9 @@ struct Slot {
 struct Model {
     lola_ctx *ctx = nullptr;
     lola_plan *plan = nullptr;
+    lola_plan *solo = nullptr;      // plan for a request alone (optional), run in solo_slot
+    Slot solo_slot;
+    uint32_t *ws_solo = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t stream2 = nullptr;  // second lane (models granted SRV_LANE_MIN or more slots)
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -70,14 +80,14 @@ struct Model {
 struct lola_server {
     size_t budget = 0, used = 0;
     std::vector<lola::Model> models;
-    std::vector<uint64_t> completed;   // tags since the last poll
+    std::vector<std::pair<uint64_t, uint32_t>> completed;   // (tag, plan form) since the last poll
     uint64_t rounds = 0;
 };
 
 namespace lola {
 namespace {
 
-int retire(Model &m, std::vector<uint64_t> &completed, bool wait_one) {
+int retire(Model &m, std::vector<std::pair<uint64_t, uint32_t>> &completed, bool wait_one) {
     while (!m.inflight.empty()) {
         auto &f = m.inflight.front();
         hipError_t e = wait_one ? hipEventSynchronize(f.second) : hipEventQuery(f.second);
@@ -88,17 +98,33 @@ int retire(Model &m, std::vector<uint64_t> &completed, bool wait_one) {
         m.inflight.pop_front();
         wait_one = false;
     }
-    for (Slot &s : m.slots)
+    auto done = [&](Slot &s, uint32_t form) {
         if (s.busy && s.finished && s.finish_round <= m.done_round) {
-            completed.push_back(s.req.tag);
+            completed.emplace_back(s.req.tag, form);
             s.busy = false;
             s.finished = false;
         }
+    };
+    for (Slot &s : m.slots) done(s, LOLA_SERVED_PLAN);
+    if (m.solo) done(m.solo_slot, LOLA_SERVED_SOLO);
     return LOLA_OK;
 }
 
 int round_model(lola_server *srv, Model &m) {
-    lola_plan *p = m.plan;
+    // a lone request to an idle model runs under the solo plan, in its slot
+    if (m.solo && !m.solo_slot.busy && m.queue.size() == 1 && !m.queue.front().gk_solo.empty()) {
+        bool idle = true;
+        for (const Slot &s : m.slots) idle = idle && !(s.busy && !s.finished);
+        if (idle) {
+            Slot &s = m.solo_slot;
+            s.busy = true;
+            s.finished = false;
+            s.level = 1;
+            s.req = std::move(m.queue.front());
+            m.queue.pop_front();
+            s.rq = s.req.view(true);
+        }
+    }
     // admission into free slots (each slot's footprint was reserved at registration)
     for (Slot &s : m.slots) {
         if (m.queue.empty()) break;
@@ -108,9 +134,10 @@ int round_model(lola_server *srv, Model &m) {
         s.level = 1;
         s.req = std::move(m.queue.front());
         m.queue.pop_front();
-        s.rq = s.req.view();
+        s.rq = s.req.view(false);
     }
     std::vector<Slot *> active, finishing;
+    if (m.solo && m.solo_slot.busy && !m.solo_slot.finished) active.push_back(&m.solo_slot);
     for (Slot &s : m.slots)
         if (s.busy && !s.finished) active.push_back(&s);
     // A lone request (one in flight, none queued) takes up to SRV_SOLO_WAVES
@@ -127,6 +154,7 @@ int round_model(lola_server *srv, Model &m) {
     size_t n_jobs = 0;
     if (solo) {
         Slot &s = *active[0];
+        const lola_plan *p = s.plan;
         ReqView rv{&s.rq, s.regs, s.sq, s.hoist};
         for (uint32_t w = 0; w < SRV_SOLO_WAVES && s.level <= p->n_waves; ++w) {
             LevelJobs lj;
@@ -144,9 +172,9 @@ int round_model(lola_server *srv, Model &m) {
         for (size_t k = 0; k < active.size(); ++k) {
             Slot &s = *active[k];
             ReqView rv{&s.rq, s.regs, s.sq, s.hoist};
-            int rc = emit_level(m.ctx, p, rv, s.level, jobs[n_lanes == 2 && k >= half ? 1 : 0]);
+            int rc = emit_level(m.ctx, s.plan, rv, s.level, jobs[n_lanes == 2 && k >= half ? 1 : 0]);
             if (rc) return rc;
-            if (++s.level > p->n_waves) finishing.push_back(&s);
+            if (++s.level > s.plan->n_waves) finishing.push_back(&s);
         }
         n_jobs = jobs[0].count() + jobs[1].count();
     }
@@ -218,6 +246,7 @@ void lola_server_destroy(lola_server *srv) {
         if (m.fork_ev) (void)hipEventDestroy(m.fork_ev);
         if (m.join_ev) (void)hipEventDestroy(m.join_ev);
         if (m.ws) (void)hipFree(m.ws);
+        if (m.ws_solo) (void)hipFree(m.ws_solo);
         if (m.stream) (void)hipStreamDestroy(m.stream);
         if (m.stream2) (void)hipStreamDestroy(m.stream2);
     }
@@ -259,6 +288,7 @@ int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint
     }
     m.slots.resize(fit);
     for (uint32_t k = 0; k < fit; ++k) {
+        m.slots[k].plan = plan;
         m.slots[k].regs = m.ws + k * slot_words;
         m.slots[k].sq = m.slots[k].regs + plan->n_phys * CT;
         m.slots[k].hoist = m.slots[k].sq + nsq * CT3;
@@ -268,6 +298,34 @@ int lola_server_add_model(lola_server *srv, lola_ctx *ctx, lola_plan *plan, uint
     srv->used += words * 4;
     srv->models.push_back(std::move(m));
     *model_id = (uint32_t)srv->models.size() - 1;
+    return LOLA_OK;
+}
+
+int lola_server_set_solo_plan(lola_server *srv, uint32_t model_id, lola_plan *solo) {
+    if (!srv || !solo || model_id >= srv->models.size()) return set_error(LOLA_E_INVAL, "bad argument");
+    Model &m = srv->models[model_id];
+    if (m.solo) return set_error(LOLA_E_INVAL, "the model already has a solo plan");
+    if (solo->loaded_for != m.ctx) return set_error(LOLA_E_INVAL, "solo plan not loaded on the model's context");
+    if (!m.queue.empty()) return set_error(LOLA_E_INVAL, "requests already submitted");
+    for (const Slot &s : m.slots)
+        if (s.busy) return set_error(LOLA_E_INVAL, "requests already submitted");
+    // the same request buffers and result layout as the model's plan
+    const lola_plan *p = m.plan;
+    if (solo->n_inputs != p->n_inputs || solo->outputs.size() != p->outputs.size() ||
+        solo->input_map != p->input_map || solo->output_map != p->output_map)
+        return set_error(LOLA_E_SHAPE, "solo plan takes other inputs or gives other outputs");
+    const size_t N = m.ctx->N, L = m.ctx->L, CT = 2 * L * N, CT3 = 3 * L * N;
+    const uint32_t nsq = std::max<uint32_t>(solo->max_squares_per_wave, 1);
+    const size_t words = solo->n_phys * CT + nsq * CT3 + (size_t)solo->max_hoist_per_wave * ks_hoist_words(m.ctx);
+    if (srv->budget < srv->used + words * 4) return set_error(LOLA_E_NOMEM, "HBM budget too small for the solo slot");
+    if (hipMalloc(&m.ws_solo, words * 4) != hipSuccess) return set_error(LOLA_E_NOMEM, "solo slot allocation failed");
+    Slot &s = m.solo_slot;
+    s.plan = solo;
+    s.regs = m.ws_solo;
+    s.sq = s.regs + solo->n_phys * CT;
+    s.hoist = s.sq + nsq * CT3;
+    m.solo = solo;
+    srv->used += words * 4;
     return LOLA_OK;
 }
 
@@ -283,12 +341,20 @@ int lola_server_model_info(const lola_server *srv, uint32_t model_id, uint32_t *
     return LOLA_OK;
 }
 
-int lola_server_submit(lola_server *srv, uint32_t model_id, const lola_request *req, uint64_t tag) {
+int lola_server_submit_ex(lola_server *srv, uint32_t model_id, const lola_request *req,
+                          const uint32_t *const *solo_gk_dev, uint64_t tag) {
     if (!srv || !req || model_id >= srv->models.size()) return set_error(LOLA_E_INVAL, "bad argument");
     Model &m = srv->models[model_id];
     int rc = validate_request(m.plan, *req);
     if (rc) return rc;
     Pending pd;
+    if (solo_gk_dev && m.solo) {
+        lola_request rs = *req;
+        rs.gk_dev = solo_gk_dev;
+        if ((rc = validate_request(m.solo, rs))) return rc;
+        pd.gk_solo.assign(solo_gk_dev, solo_gk_dev + m.solo->galois.size());
+        if (pd.gk_solo.empty()) pd.gk_solo.push_back(nullptr);   // a solo plan without rotations still marks the request
+    }
     pd.tag = tag;
     pd.rlk = req->rlk_dev;
     pd.gk.assign(req->gk_dev, req->gk_dev + m.plan->galois.size());
@@ -296,6 +362,10 @@ int lola_server_submit(lola_server *srv, uint32_t model_id, const lola_request *
     pd.out.assign(req->out_dev, req->out_dev + m.plan->outputs.size());
     m.queue.push_back(std::move(pd));
     return LOLA_OK;
+}
+
+int lola_server_submit(lola_server *srv, uint32_t model_id, const lola_request *req, uint64_t tag) {
+    return lola_server_submit_ex(srv, model_id, req, nullptr, tag);
 }
 
 int lola_server_step(lola_server *srv, uint32_t *pending) {
@@ -310,22 +380,30 @@ int lola_server_step(lola_server *srv, uint32_t *pending) {
     for (Model &m : srv->models) {
         n += (uint32_t)m.queue.size();
         for (const Slot &s : m.slots) n += s.busy ? 1u : 0u;
+        if (m.solo) n += m.solo_slot.busy ? 1u : 0u;
     }
     if (pending) *pending = n;
     return LOLA_OK;
 }
 
-int lola_server_poll(lola_server *srv, uint64_t *tags, uint32_t cap, uint32_t *n) {
+int lola_server_poll_ex(lola_server *srv, uint64_t *tags, uint32_t *forms, uint32_t cap, uint32_t *n) {
     if (!srv || !n || (!tags && cap)) return set_error(LOLA_E_INVAL, "null argument");
     for (Model &m : srv->models) {
         int rc = retire(m, srv->completed, false);
         if (rc) return rc;
     }
     const uint32_t k = (uint32_t)std::min<size_t>(cap, srv->completed.size());
-    std::copy(srv->completed.begin(), srv->completed.begin() + k, tags);
+    for (uint32_t i = 0; i < k; ++i) {
+        tags[i] = srv->completed[i].first;
+        if (forms) forms[i] = srv->completed[i].second;
+    }
     srv->completed.erase(srv->completed.begin(), srv->completed.begin() + k);
     *n = k;
     return LOLA_OK;
+}
+
+int lola_server_poll(lola_server *srv, uint64_t *tags, uint32_t cap, uint32_t *n) {
+    return lola_server_poll_ex(srv, tags, nullptr, cap, n);
 }
 
 }  // extern "C"

@@ -35,8 +35,11 @@ def _sig():
         "lola_server_model_info": [vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u64),
                                    ctypes.POINTER(u64)],
         "lola_server_submit": [vp, u32, ctypes.POINTER(lola.Request), u64],
+        "lola_server_set_solo_plan": [vp, u32, vp],
+        "lola_server_submit_ex": [vp, u32, ctypes.POINTER(lola.Request), ctypes.POINTER(vp), u64],
         "lola_server_step": [vp, ctypes.POINTER(u32)],
         "lola_server_poll": [vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)],
+        "lola_server_poll_ex": [vp, ctypes.POINTER(u64), ctypes.POINTER(u32), u32, ctypes.POINTER(u32)],
         "lola_server_destroy": [vp],
     }
     for n, a in sig.items():
@@ -77,10 +80,19 @@ class Server:
                                                   ctypes.byref(j)))
         return dict(slots=s.value, footprint_bytes=f.value, scratch_bytes=sc.value, launched_jobs=j.value)
 
+    def set_solo_plan(self, mid: int, plan) -> None:
+        lola._check(_sig().lola_server_set_solo_plan(self.h, mid, plan.h))
+
     def submit(self, mid: int, req: dict, tag: int) -> None:
+        """req may carry gks_solo, the solo plan's Galois keys."""
         keep = []
         rs = _request_struct(req, keep)
-        lola._check(_sig().lola_server_submit(self.h, mid, ctypes.byref(rs), tag))
+        solo = None
+        if req.get("gks_solo") is not None:
+            arr = (ctypes.c_void_p * max(len(req["gks_solo"]), 1))(*[t.data_ptr() for t in req["gks_solo"]])
+            keep.append(arr)
+            solo = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        lola._check(_sig().lola_server_submit_ex(self.h, mid, ctypes.byref(rs), solo, tag))
 
     def step(self) -> int:
         n = ctypes.c_uint32()
@@ -88,9 +100,16 @@ class Server:
         return n.value
 
     def poll(self, cap: int = 4096):
+        """Tags completed since the last poll; self.forms[tag] = 1 if the solo
+        plan served it, else 0."""
         tags = (ctypes.c_uint64 * cap)()
+        forms = (ctypes.c_uint32 * cap)()
         n = ctypes.c_uint32()
-        lola._check(_sig().lola_server_poll(self.h, tags, cap, ctypes.byref(n)))
+        lola._check(_sig().lola_server_poll_ex(self.h, tags, forms, cap, ctypes.byref(n)))
+        if not hasattr(self, "forms"):
+            self.forms = {}
+        for i in range(n.value):
+            self.forms[int(tags[i])] = int(forms[i])
         return [int(tags[i]) for i in range(n.value)]
 
     def close(self):
@@ -106,8 +125,10 @@ class Server:
 
 
 class ModelSetup:
-    """A ring size's context, loaded plan, client key sets, pre-encrypted
-    input sets and a pool of output buffers."""
+    """A ring size's context, loaded plan (and solo plan: the network compiled
+    for the latency objective, where that differs), client key sets with the
+    Galois keys of both plans, pre-encrypted input sets and a pool of output
+    buffers."""
 
     def __init__(self, kind: str, clients: int, inputs_per_client: int, out_pool: int):
         self.kind = kind
@@ -122,7 +143,15 @@ class ModelSetup:
         self.ctx = lola.Context(self.p)
         self.plan = lola.Plan(self.p, layers)
         self.plan.load(self.ctx)
+        solo = lola.Plan(self.p, layers, objective=lola.OBJECTIVE_LATENCY)
+        if (solo.info["recipe"], solo.info["sums"]) != (self.plan.info["recipe"], self.plan.info["sums"]):
+            self.solo_plan = solo
+            self.solo_plan.load(self.ctx)
+        else:
+            solo.close()
+            self.solo_plan = None
         gal = self.plan.galois()
+        gal_solo = self.solo_plan.galois() if self.solo_plan is not None else []
         imap = self.plan.input_map()
         self.keys, self.inputs, self.values = [], [], []
         base = wl.workload_seed(4) * 31 + (1 if kind == "mnist" else 2)
@@ -133,8 +162,9 @@ class ModelSetup:
             self.enc_seeds.append([ks + 7 * k + 3 for k in range(inputs_per_client)])
             sk = self.ctx.keygen_secret(ks)
             pk = self.ctx.keygen_public(ks, sk)
-            self.keys.append(dict(sk=sk, rlk=self.ctx.keygen_switch(ks, sk, 0),
-                                  gks=[self.ctx.keygen_switch(ks, sk, g) for g in gal]))
+            gk = {g: self.ctx.keygen_switch(ks, sk, g) for g in sorted(set(gal) | set(gal_solo))}
+            self.keys.append(dict(sk=sk, rlk=self.ctx.keygen_switch(ks, sk, 0), gks=[gk[g] for g in gal],
+                                  gks_solo=[gk[g] for g in gal_solo] if self.solo_plan is not None else None))
             sets, vals = [], []
             for k in range(inputs_per_client):
                 g = wl.rng(base + c, 100 + k)
@@ -153,15 +183,27 @@ class ModelSetup:
 
     def request(self, client: int, which: int, outputs):
         k = self.keys[client]
-        return dict(rlk=k["rlk"], gks=k["gks"], inputs=self.inputs[client][which], outputs=outputs)
+        return dict(rlk=k["rlk"], gks=k["gks"], gks_solo=k["gks_solo"], inputs=self.inputs[client][which],
+                    outputs=outputs)
 
-    def reference(self, client: int, which: int):
-        """The output words of (client, input set) evaluated alone, computed
-        once and kept."""
-        key = (client, which)
+    def plan_of(self, form: int):
+        """The plan that serves form 0 (the model's plan) or 1 (the solo plan)."""
+        return self.solo_plan if form == 1 else self.plan
+
+    def evaluate_alone(self, client: int, which: int, outputs, form: int = 0) -> None:
+        """(client, input set) evaluated alone under the plan of the form."""
+        req = self.request(client, which, outputs)
+        if form == 1:
+            req = dict(req, gks=req["gks_solo"])
+        self.plan_of(form).evaluate(self.ctx, [req])
+
+    def reference(self, client: int, which: int, form: int = 0):
+        """The output words of (client, input set) evaluated alone under the
+        plan of the form, computed once and kept."""
+        key = (client, which, form)
         if key not in self._refs:
             outs = [self.ctx.empty_ct() for _ in range(self.plan.info["n_outputs"])]
-            self.plan.evaluate(self.ctx, [self.request(client, which, outs)])
+            self.evaluate_alone(client, which, outs, form)
             torch.cuda.synchronize()
             self._refs[key] = outs
         return self._refs[key]
@@ -181,6 +223,9 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
     torch.cuda.synchronize()
     srv = Server(int(hbm_budget_gb * (1 << 30)))
     mids = {k: srv.add_model(m.ctx, m.plan, max_inflight) for k, m in models.items()}
+    for k, m in models.items():
+        if m.solo_plan is not None:
+            srv.set_solo_plan(mids[k], m.solo_plan)
     kind_name = lambda k: "mnist" if k == 1 else "dense64"  # noqa: E731
     out_of, latency, served_copy, kept = {}, np.zeros(n_req), {}, {}
     pending = []          # arrived but waiting for an output buffer
@@ -232,17 +277,19 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
     wall = time.perf_counter() - t0
     torch.cuda.synchronize()
     # served results equal the request evaluated alone, word for word
+    # (under the plan that served it: the model's, or its solo plan)
+    forms = srv.forms if hasattr(srv, "forms") else {}
     mismatches = 0
     for tag, outs in served_copy.items():
         m = models[kind_name(kinds[tag])]
         alone = [m.ctx.empty_ct() for _ in outs]
-        m.plan.evaluate(m.ctx, [m.request(int(client_of[tag]), int(input_of[tag]), alone)])
+        m.evaluate_alone(int(client_of[tag]), int(input_of[tag]), alone, forms.get(tag, 0))
         torch.cuda.synchronize()
         mismatches += sum(0 if torch.equal(a, b) else 1 for a, b in zip(alone, outs))
     # every served result equals its (client, input set)'s reference words
     ref_mismatches = 0
     for tag, outs in kept.items():
-        ref = models[kind_name(kinds[tag])].reference(int(client_of[tag]), int(input_of[tag]))
+        ref = models[kind_name(kinds[tag])].reference(int(client_of[tag]), int(input_of[tag]), forms.get(tag, 0))
         ref_mismatches += sum(0 if torch.equal(a, b) else 1 for a, b in zip(ref, outs))
     kept.clear()
     res = {
@@ -254,6 +301,8 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
         "checked_alone_vs_mixed": len(served_copy), "mismatches": mismatches,
         "checked_vs_reference": n_req if check_all else 0, "reference_mismatches": ref_mismatches,
         "references": {k: len(m._refs) for k, m in models.items()},
+        "served_by_solo_plan": {k: sum(1 for t, f in forms.items() if f == 1 and kind_name(kinds[t]) == k)
+                                for k in models},
         "slots": {k: srv.model_info(v)["slots"] for k, v in mids.items()},
         "scratch_bytes": {k: srv.model_info(v)["scratch_bytes"] for k, v in mids.items()},
     }
@@ -273,7 +322,9 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
 
 def one_at_a_time(models, arrivals, kinds, client_of, input_of) -> dict:
     """The same arrival trace served by evaluating one request at a time, in
-    arrival order, on the GPU (each request waits for the previous one)."""
+    arrival order, on the GPU (each request waits for the previous one), each
+    under the model's plan for a request alone (its solo plan where it has
+    one)."""
     n = len(arrivals)
     outs = {k: [m.ctx.empty_ct() for _ in range(m.plan.info["n_outputs"])] for k, m in models.items()}
     lat = np.zeros(n)
@@ -284,7 +335,7 @@ def one_at_a_time(models, arrivals, kinds, client_of, input_of) -> dict:
             time.sleep(arrivals[r] - now)
         k = "mnist" if kinds[r] == 1 else "dense64"
         m = models[k]
-        m.plan.evaluate(m.ctx, [m.request(int(client_of[r]), int(input_of[r]), outs[k])])
+        m.evaluate_alone(int(client_of[r]), int(input_of[r]), outs[k], 1 if m.solo_plan is not None else 0)
         torch.cuda.synchronize()
         lat[r] = time.perf_counter() - t0 - arrivals[r]
     wall = time.perf_counter() - t0

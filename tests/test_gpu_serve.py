@@ -20,14 +20,18 @@ def test_serving_mixed_stream_equals_alone():
     assert res["mismatches"] == 0
     assert res["checked_vs_reference"] == 48 and res["reference_mismatches"] == 0
     assert res["slots"]["mnist"] >= 1 and res["slots"]["dense64"] >= 1
+    # at this rate most requests find their model idle and run under its solo plan
+    assert sum(res["served_by_solo_plan"].values()) >= 1
 
 
 @pytest.mark.timeout(600)
 def test_serving_references_match_oracle():
     """A mixed stream in which every served result is compared with the
-    reference words of its (client, input set); each reference used is then
-    pinned to the oracle's run of the same schedule under the same keys and
-    encryption seeds."""
+    reference words of its (client, input set) under the plan that served it
+    (the model's plan, or its solo plan for a request that found the model
+    idle); each reference used is then pinned to the oracle's run of the same
+    schedule (sequential or hoisted sums) under the same keys and encryption
+    seeds."""
     from paper_1812_10659_amd import lola, networks, serving
     print("[gpu-serve] 40 requests, every result against its oracle-pinned reference", flush=True)
     res = serving.run_serving(n_req=40, rate=400.0, clients=3, max_inflight=8, hbm_budget_gb=24,
@@ -36,16 +40,20 @@ def test_serving_references_match_oracle():
     assert res["checked_vs_reference"] == 40 and res["reference_mismatches"] == 0
     for kind, m in models.items():
         assert m._refs, kind
-        sched = nw.mnist_schedule(m.w, recipe="shared") if kind == "mnist" else nw.dense64_schedule(m.W)
+        assert m.solo_plan is not None and m.solo_plan.info["sums"] == lola.SUMS_HOISTED
+        scheds = {f: nw.mnist_schedule(m.w, recipe="shared", sums=sm) if kind == "mnist"
+                  else nw.dense64_schedule(m.W, sums=sm) for f, sm in ((0, "sequential"), (1, "hoisted"))}
         octx = bfv.Context(m.p)
         okeys = {}
-        for (c, k), outs in sorted(m._refs.items()):
-            print(f"[gpu-serve] {kind} client {c} input {k} against the oracle", flush=True)
-            if c not in okeys:
-                okeys[c] = bfv.keygen(octx, m.key_seeds[c], nw.galois_elements(sched))
+        for (c, k, form), outs in sorted(m._refs.items()):
+            sched = scheds[form]
+            print(f"[gpu-serve] {kind} client {c} input {k} plan form {form} against the oracle", flush=True)
+            if (c, form) not in okeys:
+                okeys[(c, form)] = bfv.keygen(octx, m.key_seeds[c], nw.galois_elements(sched))
             msgs = networks.pack_inputs(m.plan.input_map(), m.values[c][k])
-            octs = [bfv.encrypt(octx, okeys[c], bfv.encode(octx, x), m.enc_seeds[c][k], i) for i, x in enumerate(msgs)]
-            oouts, _ = nw.run_ciphertexts(octx, okeys[c], sched, octs)
+            octs = [bfv.encrypt(octx, okeys[(c, form)], bfv.encode(octx, x), m.enc_seeds[c][k], i)
+                    for i, x in enumerate(msgs)]
+            oouts, _ = nw.run_ciphertexts(octx, okeys[(c, form)], sched, octs)
             for j, (g, o) in enumerate(zip(outs, oouts)):
                 got = lola.to_numpy_u32(m.ctx.to_coeff(g)).astype(np.uint64)
                 assert np.array_equal(got, np.stack(o)), f"{kind} client {c} input {k} output {j}"
@@ -95,4 +103,31 @@ def test_serving_admission_respects_budget():
         srv.step()
         done += srv.poll()
     assert sorted(done) == list(range(6))
+    srv.close()
+
+
+def test_solo_plan_request_is_pending_until_done():
+    """A request that finds its model idle runs under the solo plan; the
+    server reports it as pending until its tag is polled, and its words equal
+    the request evaluated alone under the solo plan."""
+    import torch
+    from paper_1812_10659_amd import serving
+    m = serving.ModelSetup("dense64", clients=1, inputs_per_client=1, out_pool=2)
+    assert m.solo_plan is not None
+    torch.cuda.synchronize()
+    srv = serving.Server(8 << 30)
+    mid = srv.add_model(m.ctx, m.plan, 4)
+    srv.set_solo_plan(mid, m.solo_plan)
+    outs = m.free_outputs[0]
+    srv.submit(mid, m.request(0, 0, outs), 7)
+    done = []
+    while not done:
+        pending = srv.step()
+        done = srv.poll()
+        assert done or pending >= 1
+    assert done == [7] and srv.forms[7] == 1
+    alone = m.free_outputs[1]
+    m.evaluate_alone(0, 0, alone, 1)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(alone, outs))
     srv.close()
