@@ -22,15 +22,22 @@ the row-swap / column-rotation operations on the 2 x N/2 slot matrix):
             the row swap uses X -> X^(2N-1).  The paper's rotation "by k to the
             right" is rotate(-k).
   keys      s ternary; pk = (-(a s + e), a) mod Q; a key-switching key for a
-            target s' is, for each digit i < L and each modulus m in
-            {q_0..q_{L-1}, P}:  b_i = -a_i s + e_i + [m == q_i] (P mod q_i) s',
-            a_i uniform.
+            target s' is, for each digit d and each modulus m in
+            {q_0..q_{L-1}, p_0..p_{K-1}}:
+            b_d = -a_d s + e_d + [m is a prime of digit d] (P mod m) s',
+            a_d uniform, P = p_0 ... p_{K-1}.
   encrypt   c = (pk0 u + e1 + Delta m, pk1 u + e2) mod Q.
   decrypt   x = c0 + c1 s (+ c2 s^2) mod Q lifted to [0,Q); m_k = round(t x_k/Q) mod t.
   mul       exact: lift the four inputs to centred integers, take the three
             negacyclic tensor products over Z, then round(t d_j / Q) mod Q.
-  keyswitch digits D_i = x mod q_i; u = sum_i D_i * ksk_i modulo every q_j and
-            P; result (u - [u mod P]_P) / P mod q_j.
+  keyswitch hybrid key switching with K special primes and digits of K
+            consecutive ciphertext primes (the last may hold fewer): digit d
+            of modulus Q_d (the product of its primes) is D_d = x mod Q_d in
+            [0, Q_d); u = sum_d D_d * ksk_d modulo every q_j and p_k; result
+            (u - [u mod P]_P) / P mod q_j with [.]_P centred.  K = 1 gives
+            one digit per prime.  The gadget P (Q/Q_d) ((Q/Q_d)^-1 mod Q_d)
+            that digit d's key carries is P mod q_j at its own primes and 0
+            at every other modulus, so sum_d D_d gadget_d = P x mod QP.
 
 Every random value is drawn from ChaCha20 (RFC 8439) with
 key = the 256-bit seed's eight words (least significant first), nonce =
@@ -178,18 +185,23 @@ def max_threads() -> int:
 
 # ------------------------------------------------------------ parameters --
 class Context:
-    """Derived constants of a parameter set (N, t, q_0..q_{L-1}, P)."""
+    """Derived constants of a parameter set (N, t, q_0..q_{L-1}, the special
+    primes P and, when the set has one, P2)."""
 
     def __init__(self, params):
         self.params = params
         self.N = int(params.N)
         self.t = int(params.t)
         self.q = [int(x) for x in params.q]
-        self.P = int(params.P)
+        self.special = [int(params.P)] + ([int(params.P2)] if getattr(params, "P2", 0) else [])
+        self.K = len(self.special)
+        self.P = math.prod(self.special)
         self.L = len(self.q)
         self.Q = math.prod(self.q)
         self.delta = self.Q // self.t
-        self.moduli = self.q + [self.P]
+        self.moduli = self.q + self.special
+        # key-switching digits: K consecutive ciphertext primes each
+        self.digits = [list(range(i, min(i + self.K, self.L))) for i in range(0, self.L, self.K)]
         self.zeta = min_root_2n(self.t, self.N)
         if self.zeta == 0:
             raise ValueError("t has no primitive 2N-th root")
@@ -268,7 +280,7 @@ class SecretKey:
 
 
 class KeySwitchKey:
-    """b[i][j], a[i][j]: digit i < L, modulus j < L+1 (index L is P)."""
+    """b[d][j], a[d][j]: digit d, modulus j < L+K (index L+k is p_k)."""
 
     def __init__(self, b: np.ndarray, a: np.ndarray, g: int):
         self.b, self.a, self.g = b, a, g
@@ -295,29 +307,29 @@ def public_key(ctx: Context, seed: int, sk: SecretKey):
 
 
 def keyswitch_key(ctx: Context, seed: int, sk: SecretKey, s_target_limbs, key_id: int) -> KeySwitchKey:
-    """Key switching s_target -> s.  s_target_limbs: [L+1][N] residues of s'
-    (over q_0..q_{L-1}, P).  key_id = 0 for relinearisation, else the Galois
-    element; the ChaCha20 object id of digit i is (key_id << 8) | i."""
-    L, N = ctx.L, ctx.N
+    """Key switching s_target -> s.  s_target_limbs: [L+K][N] residues of s'
+    (over q_0..q_{L-1}, p_0..p_{K-1}).  key_id = 0 for relinearisation, else
+    the Galois element; the ChaCha20 object id of digit d is (key_id << 8) | d."""
+    N, M, dn = ctx.N, len(ctx.moduli), len(ctx.digits)
     s_l = ctx.small_to_limbs(sk.s, ctx.moduli)
-    b = np.empty((L, L + 1, N), np.uint64)
-    a = np.empty((L, L + 1, N), np.uint64)
+    b = np.empty((dn, M, N), np.uint64)
+    a = np.empty((dn, M, N), np.uint64)
     pairs = []
-    for i in range(L):
-        obj = (key_id << 8) | i
+    for d in range(dn):
+        obj = (key_id << 8) | d
         for j, m in enumerate(ctx.moduli):
-            a[i, j] = sample_uniform(seed, DOM_KSK_A, obj, j, N, m)
-            pairs.append((a[i, j], s_l[j], m))
+            a[d, j] = sample_uniform(seed, DOM_KSK_A, obj, j, N, m)
+            pairs.append((a[d, j], s_l[j], m))
     prods = poly_mul_many(pairs)
-    for i in range(L):
-        obj = (key_id << 8) | i
+    for d in range(dn):
+        obj = (key_id << 8) | d
         e_l = ctx.small_to_limbs(sample_cbd(seed, DOM_KSK_E, obj, N), ctx.moduli)
         for j, m in enumerate(ctx.moduli):
-            v = (m - prods[i * (L + 1) + j]) % m
+            v = (m - prods[d * M + j]) % m
             v = (v + e_l[j]) % m
-            if j == i:
+            if j in ctx.digits[d]:
                 v = (v + (ctx.P % m) * s_target_limbs[j] % m) % m
-            b[i, j] = v
+            b[d, j] = v
     return KeySwitchKey(b, a, key_id)
 
 
@@ -522,45 +534,73 @@ def mul(ctx: Context, a, b) -> List[np.ndarray]:
     return out
 
 
+def _crt_digit(ctx: Context, x, primes) -> np.ndarray:
+    """The integer in [0, Q_d) congruent to x mod each prime of the digit
+    (Q_d their product), by the CRT sum; one prime: x itself."""
+    if len(primes) == 1:
+        return np.asarray(x[primes[0]], np.uint64)
+    Qd = math.prod(ctx.q[k] for k in primes)
+    acc = np.zeros(ctx.N, dtype=object)
+    for k in primes:
+        c = (Qd // ctx.q[k]) * pow(Qd // ctx.q[k], -1, ctx.q[k])
+        acc = acc + np.asarray(x[k], np.uint64).astype(object) * c
+    return acc % Qd
+
+
+def _residues(v, m: int) -> np.ndarray:
+    if v.dtype == object:
+        return (v % m).astype(np.uint64)
+    return v % np.uint64(m)
+
+
 def keyswitch(ctx: Context, x, ksk: KeySwitchKey, digit_galois: int = 1):
     """x: [L][N] residues of a polynomial under s'.  Returns (k0, k1) with
     k0 + k1 s ~ x s' (mod Q).
 
-    digit_galois = g > 1: the digits are sigma_g(|x|_{q_i}), the automorphism
+    digit_galois = g > 1: the digits are sigma_g(|x|_{Q_d}), the automorphism
     applied to each digit as an integer polynomial (coefficients in
-    (-q_i, q_i)), i.e. to its residues mod every modulus; then the call
-    switches sigma_g(x) (each digit is still congruent to sigma_g(x) mod q_i),
-    and all rotations of one x share the digits |x|_{q_i} -- the hoisted
-    rotation."""
-    L, N = ctx.L, ctx.N
-    D = [np.asarray(x[i], np.uint64) for i in range(L)]     # digits in [0, q_i)
+    (-Q_d, Q_d)), i.e. to its residues mod every modulus; then the call
+    switches sigma_g(x) (each digit is still congruent to sigma_g(x) mod
+    Q_d), and all rotations of one x share the digits |x|_{Q_d} -- the
+    hoisted rotation."""
+    L, N, K = ctx.L, ctx.N, ctx.K
+    D = [_crt_digit(ctx, x, dg) for dg in ctx.digits]     # digits in [0, Q_d)
     pairs = []
     for j, m in enumerate(ctx.moduli):
-        for i in range(L):
-            Dij = D[i] % np.uint64(m)
+        for d in range(len(D)):
+            Ddj = _residues(D[d], m)
             if digit_galois != 1:
-                Dij = automorph(Dij, m, digit_galois)
-            pairs.append((Dij, ksk.b[i, j], m))
-            pairs.append((Dij, ksk.a[i, j], m))
+                Ddj = automorph(Ddj, m, digit_galois)
+            pairs.append((Ddj, ksk.b[d, j], m))
+            pairs.append((Ddj, ksk.a[d, j], m))
     prods = poly_mul_many(pairs)
-    u0 = np.empty((L + 1, N), np.uint64)
-    u1 = np.empty((L + 1, N), np.uint64)
+    nd = len(D)
+    u0 = np.empty((L + K, N), np.uint64)
+    u1 = np.empty((L + K, N), np.uint64)
     for j, m in enumerate(ctx.moduli):
         s0 = np.zeros(N, dtype=np.uint64)
         s1 = np.zeros(N, dtype=np.uint64)
-        for i in range(L):
-            s0 = (s0 + prods[(j * L + i) * 2]) % m
-            s1 = (s1 + prods[(j * L + i) * 2 + 1]) % m
+        for d in range(nd):
+            s0 = (s0 + prods[(j * nd + d) * 2]) % m
+            s1 = (s1 + prods[(j * nd + d) * 2 + 1]) % m
         u0[j], u1[j] = s0, s1
     P = ctx.P
     out = []
     for u in (u0, u1):
-        uP = u[L].astype(np.int64)
-        uPc = np.where(uP > P // 2, uP - P, uP)           # [u mod P]_P, centred
+        # [u mod P]_P, centred: the CRT lift over the special primes
+        if K == 1:
+            uP = u[L].astype(np.int64)
+        else:
+            uP = np.zeros(N, dtype=object)
+            for k, pk in enumerate(ctx.special):
+                uP = uP + u[L + k].astype(object) * ((P // pk) * pow(P // pk, -1, pk))
+            uP = uP % P
+        uPc = np.where(uP > P // 2, uP - P, uP)
         limbs = np.empty((L, N), np.uint64)
         for j, qj in enumerate(ctx.q):
             pinv = pow(P, -1, qj)
-            diff = (u[j].astype(np.int64) - np.mod(uPc, qj)) % qj
+            r = (uPc % qj).astype(np.int64)
+            diff = (u[j].astype(np.int64) - r) % qj
             limbs[j] = (diff.astype(np.uint64) * np.uint64(pinv)) % np.uint64(qj)
         out.append(limbs)
     return out[0], out[1]
@@ -589,9 +629,9 @@ def rotate(ctx: Context, ct, step, keys: Keys) -> List[np.ndarray]:
 
 def rotate_hoisted(ctx: Context, ct, step, keys: Keys) -> List[np.ndarray]:
     """The same rotation as `rotate` (it decrypts to the same slots), with the
-    key switch's digits taken before the automorphism: digit i is
-    sigma_g(|c1|_{q_i}) (see keyswitch).  Rotations of one ciphertext by
-    several g then share |c1|_{q_i} and its reductions to every modulus; the
+    key switch's digits taken before the automorphism: digit d is
+    sigma_g(|c1|_{Q_d}) (see keyswitch).  Rotations of one ciphertext by
+    several g then share |c1|_{Q_d} and its reductions to every modulus; the
     words differ from `rotate`'s where sigma_g negates a coefficient."""
     g = galois_element(ctx.N, step)
     if g == 1:

@@ -37,10 +37,15 @@ class ParamSet:
     q: tuple          # ciphertext (data) primes q_0..q_{L-1}
     P: int            # special prime used by key switching
     insecure_ok: bool = False   # toy sets for tests only
+    P2: int = 0       # second special prime: key-switching digits of two primes
 
     @property
     def L(self) -> int:
         return len(self.q)
+
+    @property
+    def special(self) -> tuple:
+        return (self.P, self.P2) if self.P2 else (self.P,)
 
 
 PARAMS: Dict[str, ParamSet] = {
@@ -52,6 +57,10 @@ PARAMS: Dict[str, ParamSet] = {
     "n4096_3q": ParamSet("n4096_3q", 4096, 65537, tuple(PRIMES_4096[:3]), 417793),
     # MNIST-shaped network, N=16384, t ~ 2^20.13, seven data primes.
     "mnist_n16384": ParamSet("mnist_n16384", 16384, 1146881, tuple(PRIMES_16384[:7]), PRIMES_16384[7]),
+    # The same ciphertext primes with key-switching digits of two primes and
+    # two special primes: 4 digits instead of 7, log2(QP) = 270 <= 438.
+    "mnist_n16384_k2": ParamSet("mnist_n16384_k2", 16384, 1146881, tuple(PRIMES_16384[:7]), PRIMES_16384[7],
+                                P2=PRIMES_16384[8]),
     # Batched primitive microbenchmark: eight data primes.
     "batch_n16384": ParamSet("batch_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
     # LoLa-Dense input path: the mask products at the input cost noise that
@@ -77,6 +86,8 @@ PARAMS: Dict[str, ParamSet] = {
                         insecure_ok=True),
     "toy2048": ParamSet("toy2048", 2048, 40961, tuple(PRIMES_16384[:4]), PRIMES_16384[4],
                         insecure_ok=True),
+    "toy1024_k2": ParamSet("toy1024_k2", 1024, 12289, tuple(PRIMES_16384[:3]), PRIMES_16384[3],
+                           insecure_ok=True, P2=PRIMES_16384[4]),
 }
 
 # Plaintext moduli for exact integer outputs of the MNIST-shaped network by

@@ -94,14 +94,23 @@ def automorphism(a, g):
 
 
 class Tiny:
-    def __init__(self, N, t, q, P):
-        self.N, self.t, self.q, self.P = N, t, list(q), P
+    """special: the special prime P, or a tuple of K special primes; key
+    switching then takes digits of K consecutive ciphertext primes."""
+
+    def __init__(self, N, t, q, special):
+        self.special = list(special) if isinstance(special, (tuple, list)) else [special]
+        self.N, self.t, self.q = N, t, list(q)
+        self.P = 1
+        for p in self.special:
+            self.P *= p
         self.L = len(q)
         self.Q = 1
         for x in q:
             self.Q *= x
         self.delta = self.Q // t
-        self.moduli = self.q + [P]
+        self.moduli = self.q + self.special
+        K = len(self.special)
+        self.groups = [list(range(i, min(i + K, self.L))) for i in range(0, self.L, K)]
         self.zeta = next(g for g in range(2, t) if pow(g, N, t) == t - 1)
 
     # slots
@@ -158,20 +167,31 @@ class Tiny:
         return keys
 
     def ksk(self, seed, s, s_target, key_id):
-        N, L = self.N, self.L
-        b = [[None] * (L + 1) for _ in range(L)]
-        a = [[None] * (L + 1) for _ in range(L)]
-        for i in range(L):
+        N, M = self.N, len(self.moduli)
+        b = [[None] * M for _ in self.groups]
+        a = [[None] * M for _ in self.groups]
+        for i, grp in enumerate(self.groups):
             obj = (key_id << 8) | i
             e = cbd(seed, 5, obj, N)
             for j, m in enumerate(self.moduli):
                 aij = uniform(seed, 4, obj, j, N, m)
                 as_ = negacyclic(aij, s, m)
                 v = [(-x + y) % m for x, y in zip(as_, e)]
-                if j == i:
+                if j in grp:
                     v = [(x + (self.P % m) * st) % m for x, st in zip(v, s_target)]
                 a[i][j], b[i][j] = aij, v
         return (b, a)
+
+    @staticmethod
+    def garner(res, mods):
+        """The integer in [0, prod mods) with the given residues, built one
+        modulus at a time: v <- v + (prod so far) * ((r - v) / (prod so far)
+        mod m)."""
+        v, w = 0, 1
+        for r, m in zip(res, mods):
+            v += w * (((r - v) * pow(w, -1, m)) % m)
+            w *= m
+        return v
 
     def encrypt(self, keys, m, seed, nonce):
         N = self.N
@@ -233,24 +253,29 @@ class Tiny:
         return out
 
     def keyswitch(self, x, key, digit_g=1):
-        """digit_g > 1: digit i is the automorphism of x's residues mod q_i
-        taken as an integer polynomial (signed), reduced mod each modulus."""
+        """Digit d is x mod Q_d (its primes' product) in [0, Q_d).  digit_g > 1:
+        the automorphism of each digit taken as an integer polynomial (signed),
+        reduced mod each modulus."""
         b, a = key
         L, N, P = self.L, self.N, self.P
+        digits = [[self.garner([x[k][c] for k in grp], [self.q[k] for k in grp]) for c in range(N)]
+                  for grp in self.groups]
         u0, u1 = [], []
         for j, m in enumerate(self.moduli):
             s0 = [0] * N
             s1 = [0] * N
-            for i in range(L):
-                xi = automorphism(x[i], digit_g) if digit_g != 1 else x[i]
+            for i, dg in enumerate(digits):
+                xi = automorphism(dg, digit_g) if digit_g != 1 else dg
                 Di = [v % m for v in xi]
                 s0 = [(p + r) % m for p, r in zip(s0, negacyclic(Di, b[i][j], m))]
                 s1 = [(p + r) % m for p, r in zip(s1, negacyclic(Di, a[i][j], m))]
             u0.append(s0)
             u1.append(s1)
         out = []
+        sp = self.special
         for u in (u0, u1):
-            uP = [v - P if v > P // 2 else v for v in u[L]]
+            uP = [self.garner([u[L + k][c] for k in range(len(sp))], sp) for c in range(N)]
+            uP = [v - P if v > P // 2 else v for v in uP]
             out.append([[((u[j][k] - uP[k]) * pow(P, -1, qj)) % qj for k in range(N)]
                         for j, qj in enumerate(self.q)])
         return out

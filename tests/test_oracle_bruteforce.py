@@ -8,11 +8,18 @@ from tests import bruteforce_bfv as bf
 
 
 class _P:
-    def __init__(self, N, t, q, P):
-        self.N, self.t, self.q, self.P = N, t, tuple(q), P
+    def __init__(self, N, t, q, P, P2=0):
+        self.N, self.t, self.q, self.P, self.P2 = N, t, tuple(q), P, P2
+
+    def special(self):
+        return (self.P, self.P2) if self.P2 else self.P
 
 
-TINY = [_P(16, 97, (193, 257, 353), 449), _P(32, 193, (257, 449, 577), 641)]
+# One digit per prime with one special prime; digits of two primes with two
+# special primes (an odd and an even prime count: a one-prime last digit, and
+# none).
+TINY = [_P(16, 97, (193, 257, 353), 449), _P(32, 193, (257, 449, 577), 641),
+        _P(16, 97, (193, 257, 353), 449, 577), _P(32, 193, (257, 449, 577, 641), 769, 1153)]
 
 
 def _np(limbs):
@@ -25,11 +32,11 @@ def _eq(ct_oracle, ct_bf):
         assert np.array_equal(np.asarray(a, np.uint64), _np(b))
 
 
-@pytest.fixture(params=TINY, ids=lambda p: f"N{p.N}")
+@pytest.fixture(params=TINY, ids=lambda p: f"N{p.N}_L{len(p.q)}" + ("_K2" if p.P2 else ""))
 def setup(request):
     p = request.param
     ctx = bfv.Context(p)
-    tiny = bf.Tiny(p.N, p.t, p.q, p.P)
+    tiny = bf.Tiny(p.N, p.t, p.q, p.special())
     gs = [bfv.galois_element(p.N, 1), bfv.galois_element(p.N, -3), bfv.galois_element(p.N, bfv.ROW_SWAP)]
     seed = 0x1234_5678_9ABC
     keys = bfv.keygen(ctx, seed, gs)
@@ -54,14 +61,16 @@ def test_keys_match(setup):
     assert np.array_equal(keys.pk0, _np(bkeys["pk0"]))
     assert np.array_equal(keys.pk1, _np(bkeys["pk1"]))
     b, a = bkeys["rlk"]
-    for i in range(ctx.L):
-        for j in range(ctx.L + 1):
+    nd, M = len(ctx.digits), len(ctx.moduli)
+    assert keys.rlk.b.shape[:2] == (nd, M) and nd == (ctx.L + ctx.K - 1) // ctx.K
+    for i in range(nd):
+        for j in range(M):
             assert list(keys.rlk.b[i, j]) == b[i][j]
             assert list(keys.rlk.a[i, j]) == a[i][j]
     for g in gs:
         b, a = bkeys["gal"][g]
         assert all(list(keys.galois[g].b[i, j]) == b[i][j]
-                   for i in range(ctx.L) for j in range(ctx.L + 1))
+                   for i in range(nd) for j in range(M))
 
 
 def test_encode_decode_match(setup):
@@ -128,15 +137,15 @@ def test_256_bit_seed_keys_and_encryption_match():
     differ from those of the same seed's low 64 bits alone."""
     p = TINY[0]
     ctx = bfv.Context(p)
-    tiny = bf.Tiny(p.N, p.t, p.q, p.P)
+    tiny = bf.Tiny(p.N, p.t, p.q, p.special())
     g = [bfv.galois_element(p.N, 1)]
     seed = int.from_bytes(bytes(range(1, 33)), "little")
     keys, bkeys = bfv.keygen(ctx, seed, g), tiny.keygen(seed, g)
     assert list(keys.sk.s) == bkeys["s"]
     assert np.array_equal(keys.pk0, _np(bkeys["pk0"])) and np.array_equal(keys.pk1, _np(bkeys["pk1"]))
     b, a = bkeys["gal"][g[0]]
-    for i in range(ctx.L):
-        for j in range(ctx.L + 1):
+    for i in range(len(ctx.digits)):
+        for j in range(len(ctx.moduli)):
             assert list(keys.galois[g[0]].b[i, j]) == b[i][j] and list(keys.galois[g[0]].a[i, j]) == a[i][j]
     m = np.arange(p.N) % p.t
     _eq(bfv.encrypt(ctx, keys, m, seed + 5, 2), tiny.encrypt(bkeys, [int(v) for v in m], seed + 5, 2))

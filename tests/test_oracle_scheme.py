@@ -134,15 +134,53 @@ def test_keyswitch_error_bound(ctx1024, keys1024):
     assert max(abs(int(e)) for e in err) < ctx.Q // (2 * ctx.t)
 
 
+def test_two_prime_digits_decrypt_and_meet_their_bound():
+    """Key switching with digits of two primes and two special primes at
+    N = 1024: rotations (plain and hoisted) and relinearisation decrypt to the
+    slot results, the error of a key switch stays under
+    (d N max Q_d B_e + P N)/P + N for d digits of modulus Q_d, and the noise
+    budget left by a rotation is within a bit of the one-prime-digit set's
+    (P grows with the digits)."""
+    ctx = bfv.Context(wl.PARAMS["toy1024_k2"])
+    assert ctx.K == 2 and ctx.digits == [[0, 1], [2]]
+    steps = [1, -5, bfv.ROW_SWAP]
+    keys = bfv.keygen(ctx, 2025, [bfv.galois_element(1024, s) for s in steps])
+    rs = np.random.default_rng(4)
+    v, w = rs.integers(0, ctx.t, ctx.N), rs.integers(0, ctx.t, ctx.N)
+    c1 = bfv.encrypt(ctx, keys, bfv.encode(ctx, v), 6, 1)
+    c2 = bfv.encrypt(ctx, keys, bfv.encode(ctx, w), 6, 2)
+    dec = lambda c: bfv.decode(ctx, bfv.decrypt(ctx, keys, c))  # noqa: E731
+    for step in steps:
+        assert np.array_equal(dec(bfv.rotate(ctx, c1, step, keys)), nw.rotate_slots(v, step))
+        assert np.array_equal(dec(bfv.rotate_hoisted(ctx, c1, step, keys)), nw.rotate_slots(v, step))
+    assert np.array_equal(dec(bfv.relin(ctx, bfv.mul(ctx, c1, c2), keys.rlk)), (v * w) % ctx.t)
+    x = np.stack([rs.integers(0, q, ctx.N, dtype=np.uint64) for q in ctx.q])
+    g = bfv.galois_element(ctx.N, 1)
+    k0, k1 = bfv.keyswitch(ctx, x, keys.galois[g])
+    s_l = ctx.small_to_limbs(keys.sk.s)
+    diff = []
+    for j, q in enumerate(ctx.q):
+        xs = bfv.poly_mul(x[j], bfv.automorph(s_l[j], q, g), q)
+        diff.append((k0[j] + bfv.poly_mul(k1[j], s_l[j], q) + (q - xs)) % q)
+    err = max(abs(int(e)) for e in ctx.centred_lift(diff))
+    qd = max(math.prod(ctx.q[k] for k in dg) for dg in ctx.digits)
+    assert err <= (len(ctx.digits) * ctx.N * qd * 21 + ctx.P * ctx.N) // ctx.P + ctx.N
+    c1_ = bfv.Context(wl.PARAMS["toy1024"])
+    k1_ = bfv.keygen(c1_, 2025, [g])
+    r1 = bfv.rotate(c1_, bfv.encrypt(c1_, k1_, bfv.encode(c1_, v), 6, 1), 1, k1_)
+    b2, b1 = bfv.noise_budget(ctx, keys, bfv.rotate(ctx, c1, 1, keys)), bfv.noise_budget(c1_, k1_, r1)
+    assert abs(b2 - b1) < 1.0, (b2, b1)
+
+
 # ---------------------------------------------- parameters and failure ----
 def test_parameter_sets_meet_security_caps():
     for p in wl.PARAMS.values():
-        bits = sum(math.log2(x) for x in (*p.q, p.P))
+        bits = sum(math.log2(x) for x in (*p.q, *p.special))
         if not p.insecure_ok:
             assert bits <= wl.SECURITY_CAP_LOG2[p.N], p.name
         assert math.gcd(p.t, math.prod(p.q)) == 1
-        assert len(set((*p.q, p.P))) == p.L + 1
-        assert all(bf_is_prime(x) for x in (*p.q, p.P, p.t))
+        assert len(set((*p.q, *p.special))) == p.L + len(p.special)
+        assert all(bf_is_prime(x) for x in (*p.q, *p.special, p.t))
 
 
 def bf_is_prime(n):
