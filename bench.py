@@ -36,6 +36,7 @@ PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 39.3
 PEAK_HBM = 8.0e12                           # bytes/s
 BFLY_OPS = 9                                # VALU ops of one lazy Harvey butterfly
 MAC_OPS = 7                                 # Montgomery product + modular add
+GARNER_OPS = 14                             # two modular products, three adds or reductions
 
 
 # HBM-side bytes per job of the key-switch inner kernel on this workload
@@ -44,7 +45,10 @@ MAC_OPS = 7                                 # Montgomery product + modular add
 # copy (FETCH_SIZE read 0.5 GiB: x2.0; WRITE_SIZE read 1 GiB: x1.0).  These
 # count L2 misses, so reads served by the last-level cache count too.  Valid
 # only for kernel sources with this digest; otherwise the traffic is null.
-KS_INNER_TRAFFIC = {"digest": "b1a54abb8a5ded5d", "fetch_per_job": 4.1703e6, "write_per_job": 1.0486e6}
+KS_INNER_TRAFFIC = {"digest": "b1a54abb8a5ded5d", "fetch_per_job": 4.1703e6, "write_per_job": 1.0486e6, "K": 1}
+# parameter set of the MNIST-shaped workload (--params): seven ciphertext
+# primes with key-switching digits of two primes and two special primes
+MNIST_PARAMS = "mnist_n16384_k2"
 KS_INNER_SOURCES = ["keyswitch.hip", "ks_core.hpp", "ntt_core.hpp", "modarith.hpp", "lola_internal.hpp"]
 
 
@@ -57,20 +61,36 @@ def ks_inner_digest():
     return h.hexdigest()[:16]
 
 
-def ks_inner_ops(N, L):
-    """Algorithmic VALU lane-ops of one key switch in the inner kernel:
-    L^2 + 2 transforms of N/2 log2 N butterflies (L-1 per ciphertext prime, L
-    for the special prime plus two inverse transforms) and 2 L (L+1) N
-    multiply-accumulates."""
-    bfly = (L * L + 2) * (N // 2) * int(math.log2(N))
-    macs = 2 * L * (L + 1) * N
-    return BFLY_OPS * bfly + MAC_OPS * macs
+def ks_shape(L, K):
+    """Key-switching digits (K consecutive ciphertext primes each), target
+    moduli L + K, the (target, digit) pairs that need a transform, and those
+    whose digit has two primes (a Garner step each)."""
+    dn = -(-L // K)
+    M = L + K
+    widths = [min(K, L - d * K) for d in range(dn)]
+    X = dn * M - L
+    G = sum(M - w for w in widths if w == 2)
+    return dn, M, X, G
 
 
-def ks_bytes(N, L):
+def ks_inner_ops(N, L, K=1):
+    """Algorithmic VALU lane-ops of one key switch in the inner kernel: a
+    transform of N/2 log2 N butterflies for every (target modulus, digit)
+    pair whose digit does not hold the target (L^2 with one special prime)
+    plus two inverse transforms per special prime, 2 dn (L+K) N
+    multiply-accumulates, and a Garner step per coefficient of a two-prime
+    digit's pairs."""
+    dn, M, X, G = ks_shape(L, K)
+    bfly = (X + 2 * K) * (N // 2) * int(math.log2(N))
+    macs = 2 * dn * M * N
+    return BFLY_OPS * bfly + MAC_OPS * macs + GARNER_OPS * G * N
+
+
+def ks_bytes(N, L, K=1):
     """Algorithmic HBM bytes of one key switch: ciphertext in (2 L N words),
-    key read once (2 L (L+1) N words), result out (2 L N words)."""
-    return 4 * N * (4 * L + 2 * L * (L + 1))
+    key read once (2 dn (L+K) N words), result out (2 L N words)."""
+    dn, M, _, _ = ks_shape(L, K)
+    return 4 * N * (4 * L + 2 * dn * M)
 
 
 def valu_probe_run(iters=4000, reps=3):
@@ -90,18 +110,19 @@ def valu_probe_run(iters=4000, reps=3):
     return out
 
 
-def inner_bytes(N, L):
+def inner_bytes(N, L, K=1):
     """Algorithmic HBM bytes of the inner kernel per key switch: the key, the
-    digits D and permuted limbs X' in, the accumulators U and u_P out."""
-    return 8 * N * (L * (L + 1) + 2 * L + 1)
+    limbs x and permuted limbs X' in, the accumulators U and u_P out."""
+    dn, M, _, _ = ks_shape(L, K)
+    return 8 * N * (dn * M + 2 * L + K)
 
 
-def ks_ops(N, L):
-    """Algorithmic VALU lane-ops of one whole key switch: L digit INTTs, the
-    inner kernel's work, and 2L mod-down units of one NTT and ~10 ops a
-    coefficient."""
+def ks_ops(N, L, K=1):
+    """Algorithmic VALU lane-ops of one whole key switch: L INTTs of the
+    digit stage, the inner kernel's work, and 2L mod-down units of one NTT
+    and ~10 ops a coefficient (plus a Garner step with two special primes)."""
     T = BFLY_OPS * (N // 2) * int(math.log2(N))
-    return L * T + ks_inner_ops(N, L) + 2 * L * (T + 10 * N)
+    return L * T + ks_inner_ops(N, L, K) + 2 * L * (T + 10 * N + (GARNER_OPS * N if K > 1 else 0))
 
 
 def kernel_table(stats, steps):
@@ -128,7 +149,7 @@ KS_KERNELS = ("ks_digits_kernel", "ks_inner_kernel", "ks_moddown_kernel",
               "ks_term_kernel", "ks_fold_kernel", "ks_term_direct_kernel", "ks_fold_moddown_kernel")
 
 
-def whole_keyswitch(stats, N, L):
+def whole_keyswitch(stats, N, L, K=1):
     """The whole key switch (digits, inner and mod-down kernels, or a small
     launch's latency-form kernels) per job over all key switches of the timed
     pass: time, algorithmic HBM GB/s and VALU fraction.  Hoisted rotations
@@ -140,18 +161,19 @@ def whole_keyswitch(stats, N, L):
     if jobs == 0 or ms <= 0:
         return None
     sec = ms / 1e3
-    gbps = ks_bytes(N, L) * jobs / sec / 1e9
-    valu = ks_ops(N, L) * jobs / sec / PEAK_VALU_LANE_OPS
+    gbps = ks_bytes(N, L, K) * jobs / sec / 1e9
+    valu = ks_ops(N, L, K) * jobs / sec / PEAK_VALU_LANE_OPS
     split = {n: round(stats[n]["ms"] / jobs * 1e3, 3) for n in names}
     return {"jobs": jobs, "us_per_job": round(ms / jobs * 1e3, 3), "us_per_job_by_kernel": split,
             "gbps": round(gbps, 1), "hbm_frac": round(gbps * 1e9 / PEAK_HBM, 4),
-            "ops_per_job": ks_ops(N, L), "valu_frac": round(valu, 4),
-            "bytes_per_job": ks_bytes(N, L),
-            "note": "4N(4L + 2L(L+1)) bytes (ciphertext in, key once, result out) and the three kernels' "
+            "ops_per_job": ks_ops(N, L, K), "valu_frac": round(valu, 4),
+            "bytes_per_job": ks_bytes(N, L, K), "special_primes": K, "digits": ks_shape(L, K)[0],
+            "note": "4N(4L + 2 dn (L+K)) bytes (ciphertext in, key once, result out) and the three kernels' "
                     "algorithmic lane-ops per key switch, over their summed HIP-event time"}
 
 
 def main():
+    global MNIST_PARAMS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -186,6 +208,9 @@ def main():
                          "cfg3d / cfg3s transfer head dense / stacked recipe)")
     ap.add_argument("--cpu-threads", default="all,1",
                     help="with --cpu-baseline-full: thread counts ('all' = every host thread)")
+    ap.add_argument("--params", default=MNIST_PARAMS, choices=("mnist_n16384", "mnist_n16384_k2"),
+                    help="parameter set of the MNIST-shaped workload: one special prime and a key-switching "
+                         "digit per ciphertext prime, or two special primes and digits of two primes")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only measure the 32-bit VALU issue rates (mul_lo, mul_hi, add) against the "
                          "CU x SIMD x lane x clock peak and exit")
@@ -227,16 +252,19 @@ def main():
         # Poisson arrivals: 70% N=16384 MNIST-shaped, 30% N=4096 dense-64,
         # 8 resident key sets per ring size, continuous batching vs one at a time.
         from paper_1812_10659_amd import serving
-        serving_out["serving"] = serving.run_serving(n_req=args.serve_requests)
+        serving_out["serving"] = serving.run_serving(n_req=args.serve_requests, mnist_params=args.params)
         if args.serve_high_rate > 0:
             serving_out["serving_high_load"] = serving.run_serving(n_req=args.serve_requests,
-                                                                   rate=args.serve_high_rate)
+                                                                   rate=args.serve_high_rate,
+                                                                   mnist_params=args.params)
         if args.serve_saturation_rate > 0:
             serving_out["serving_saturation"] = serving.run_serving(n_req=args.serve_requests,
-                                                                    rate=args.serve_saturation_rate)
+                                                                    rate=args.serve_saturation_rate,
+                                                                    mnist_params=args.params)
         torch.cuda.empty_cache()
-    p = wl.PARAMS["mnist_n16384"]
-    N, L = p.N, p.L
+    MNIST_PARAMS = args.params
+    p = wl.PARAMS[MNIST_PARAMS]
+    N, L, K = p.N, p.L, len(p.special)
     w = wl.mnist_weights()
     ctx = lola.Context(p)
     plan = lola.Plan(p, networks.mnist_layers(w))
@@ -377,15 +405,15 @@ def main():
     kernels = kernel_table(kstats, args.steps)
     inner = kstats.get("ks_inner_kernel", dict(ms=0.0, launches=0, units=0, alg_ops=0.0, alg_bytes=0.0))
     ks_jobs, ks_launches, ks_ms = inner["units"], inner["launches"], inner["ms"]
-    ops_per_job = ks_inner_ops(N, L)
+    ops_per_job = ks_inner_ops(N, L, K)
     ks_avg_ms = ks_ms / max(ks_launches, 1)
     jobs_per_launch = ks_jobs / max(ks_launches, 1)
     achieved = ops_per_job * ks_jobs / (ks_ms / 1e3) if ks_ms > 0 else 0.0
-    whole_ks = whole_keyswitch(kstats, N, L)
+    whole_ks = whole_keyswitch(kstats, N, L, K)
     traffic = None
-    if ks_inner_digest() == KS_INNER_TRAFFIC["digest"] and (B, C) == (64, 8):
+    if ks_inner_digest() == KS_INNER_TRAFFIC["digest"] and (B, C) == (64, 8) and K == KS_INNER_TRAFFIC["K"]:
         tb = (KS_INNER_TRAFFIC["fetch_per_job"] + KS_INNER_TRAFFIC["write_per_job"]) * jobs_per_launch
-        traffic = {"bytes_per_launch": round(tb), "algorithmic_bytes_per_launch": round(inner_bytes(N, L) * jobs_per_launch),
+        traffic = {"bytes_per_launch": round(tb), "algorithmic_bytes_per_launch": round(inner_bytes(N, L, K) * jobs_per_launch),
                    "gbps": round(tb / (ks_avg_ms / 1e3) / 1e9, 1)}
 
     out = {
@@ -403,6 +431,7 @@ def main():
         "data": "synthetic (seeded uniform 28x28 images, seeded int8 weights)",
         "config": {"workload": "MNIST-shaped: conv5x5s2x5 -> sq -> fc845x100 -> sq -> fc100x10, "
                                "BFV N=16384 L=7 t=1146881",
+                   "params": p.name, "special_primes": K, "keyswitch_digits": ks_shape(L, K)[0],
                    "plan": {"recipe": RECIPE_NAMES.get(plan.info["recipe"], str(plan.info["recipe"])),
                             "rotations": plan.info["n_rotations"], "mul_plain": plan.info["n_mul_plain"],
                             "mul_scalar": plan.info["n_mul_scalar"], "squares": plan.info["n_square"],
@@ -434,7 +463,7 @@ def main():
         "hbm": {"ntt_gbps": round(ntt_gbps, 1), "ntt_frac": round(ntt_gbps * 1e9 / PEAK_HBM, 4),
                 "keyswitch_gbps": whole_ks and whole_ks["gbps"],
                 "keyswitch_frac": whole_ks and whole_ks["hbm_frac"],
-                "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2L(L+1)) per job over the "
+                "note": "algorithmic bytes: NTT 8N per limb; key switch 4N(4L + 2 dn (L+K)) per job over the "
                         "summed time of its three kernels (digits, inner, mod-down) in the timed pass"},
         "keyswitch": whole_ks,
         "kernels": kernels,
@@ -451,6 +480,9 @@ def main():
     out["latency_ms"]["latency_plan_p50"] = out["latency_plans"]["mnist"]["latency_plan"]["p50_ms"]
     out["latency_ms"]["latency_plan_p99"] = out["latency_plans"]["mnist"]["latency_plan"]["p99_ms"]
     out["paper_layout"] = paper_layout_run(ctx, w, images, B, C, args.latency_runs)
+    other = "mnist_n16384" if args.params != "mnist_n16384" else "mnist_n16384_k2"
+    out["other_keyswitch_shape"] = keyswitch_shape_run(other, w, B, C, args.steps, args.warmup, args.lanes,
+                                                       not args.no_autotune, args.latency_runs)
     out["mnist_small"] = small_network_run(ctx, B, C, args.latency_runs)
     out["mnist_dense_input"] = dense_input_run(B, C, args.latency_runs)
     out["cifar_shaped"] = cifar_run()
@@ -540,7 +572,7 @@ def latency_plans_run(ctx, w, img, latency_runs):
     from paper_1812_10659_amd import lola, networks
     from paper_1812_10659_amd import workloads as wl
     out = {}
-    pm = wl.PARAMS["mnist_n16384"]
+    pm = wl.PARAMS[MNIST_PARAMS]
     mv = networks.mnist_input_values(img)
     out["mnist"] = _latency_plan_case(ctx, pm, networks.mnist_layers(w), mv, _plain_logits_mod_t(img, w, pm.t),
                                       latency_runs, wl.key_seed(1) + 101)
@@ -572,7 +604,7 @@ def paper_layout_run(ctx, w, images, B, C, latency_runs, steps=5):
     import torch
     from paper_1812_10659_amd import lola, networks
     from paper_1812_10659_amd import workloads as wl
-    p = wl.PARAMS["mnist_n16384"]
+    p = wl.PARAMS[MNIST_PARAMS]
     plan = lola.Plan(p, networks.mnist_layers(w), recipe=lola.RECIPE_FULL_REDUCTION)
     plan.load(ctx)
     keys = []
@@ -630,7 +662,7 @@ def small_network_run(ctx, B, C, latency_runs, steps=5):
     from paper_1812_10659_amd import lola, networks
     from paper_1812_10659_amd import workloads as wl
     w = wl.mnist_small_weights()
-    p = wl.PARAMS["mnist_n16384"]
+    p = wl.PARAMS[MNIST_PARAMS]
     plan = lola.Plan(p, networks.mnist_small_layers(w))
     plan.load(ctx)
     keys = []
@@ -920,6 +952,70 @@ def _plain_logits_exact(img, w):
     h = [sum(int(a) * int(b) for a, b in zip(row, a1)) + int(bb) for row, bb in zip(w.w1, w.b1)]
     a2 = [v * v for v in h]
     return [sum(int(a) * int(b) for a, b in zip(row, a2)) + int(bb) for row, bb in zip(w.w2, w.b2)]
+
+
+def keyswitch_shape_run(pname, w, B, C, steps, warmup, lanes, tune, latency_runs):
+    """The headline batch under the other key-switching shape (one prime per
+    digit with one special prime, or digits of two primes with two): the same
+    network, batch, lanes and autotuning, timed the same way; the one-lane
+    kernel-timing pass gives the whole key switch per job; every request
+    decrypts to the plain network's logits."""
+    import numpy as np
+    import torch
+
+    from paper_1812_10659_amd import lola, networks
+    from paper_1812_10659_amd import requests as rq
+    from paper_1812_10659_amd import workloads as wl
+    p = wl.PARAMS[pname]
+    ctx = lola.Context(p)
+    plan = lola.Plan(p, networks.mnist_layers(w))
+    plan.load(ctx)
+    plan.set_lanes(lanes)
+    if tune:
+        from paper_1812_10659_amd import batched
+        batched.autotune_ntt(ctx, p.N, p.L)
+        batched.autotune_ks(ctx, p.N, p.L)
+    reqs, keys, images = rq.mnist_batch(ctx, plan, B, C)
+    for _ in range(warmup):
+        plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lola.timing_enable(ctx, True)
+    plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    lola.kernel_timing(ctx)
+    for _ in range(steps):
+        plan.evaluate(ctx, reqs)
+    torch.cuda.synchronize()
+    lola.timing_enable(ctx, False)
+    whole = whole_keyswitch(lola.kernel_stats(ctx), p.N, p.L, len(p.special))
+    for r in range(B):
+        got = rq.decrypted_outputs(ctx, plan, keys[r % C]["sk"], reqs[r])
+        assert [int(v) for v in got] == [int(v) for v in _plain_logits_mod_t(images[r], w, p.t)], f"request {r}"
+    one = [reqs[0]]
+    plan.evaluate(ctx, one)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(latency_runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.evaluate(ctx, one)
+        e1.record()
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    res = {"params": pname, "special_primes": len(p.special), "keyswitch_digits": ks_shape(p.L, len(p.special))[0],
+           "inferences_per_s": round(B * steps / elapsed, 2), "ms_per_step": round(elapsed / steps * 1e3, 3),
+           "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "keyswitch_us_per_job": whole and whole["us_per_job"],
+           "keyswitch_us_per_job_by_kernel": whole and whole["us_per_job_by_kernel"],
+           "keyswitch_valu_frac": whole and whole["valu_frac"], "decrypted": B}
+    del reqs, keys, plan, ctx
+    torch.cuda.empty_cache()
+    return res
 
 
 def _plain_logits_mod_t(img, w, t):

@@ -69,10 +69,17 @@ enum {
 #define LOLA_ROW_SWAP 0x7fffffff /* step value of the row swap in rotation calls */
 
 /* Parameter set.  N in {1024, 2048, 4096, 8192, 16384}; t prime, t = 1 mod 2N,
- * t < 2^26; q[0..L-1] and P distinct primes below 2^30, each = 1 mod 2N;
- * 1 <= L <= 12.  Unless allow_insecure, log2(Q*P) must not exceed the
+ * t < 2^26; q[0..L-1], P (and P2) distinct primes below 2^30, each = 1 mod
+ * 2N; 1 <= L <= 12.  Unless allow_insecure, log2(Q*P) must not exceed the
  * homomorphic-encryption standard's 128-bit classical cap for N (27, 54, 109,
- * 218, 438 for N = 1024 ... 16384). */
+ * 218, 438 for N = 1024 ... 16384).
+ * Key switching (hybrid, with special primes): P2 = 0 gives one special
+ * prime P and one digit per ciphertext prime (L digits); P2 != 0 gives two
+ * special primes P, P2 (their product is the P of the mod-down) and digits
+ * of two consecutive ciphertext primes (ceil(L/2) digits: fewer transforms,
+ * key products and key words per key switch at the same noise), and then
+ * every modulus must exceed 2^29.  K below is the number of special primes,
+ * dn the number of digits. */
 typedef struct {
     uint32_t N;
     uint32_t t;
@@ -80,6 +87,7 @@ typedef struct {
     const uint32_t *q; /* host array of L primes */
     uint32_t P;
     int allow_insecure;
+    uint32_t P2;       /* second special prime, or 0 */
 } lola_params;
 
 typedef struct lola_ctx lola_ctx;
@@ -88,9 +96,10 @@ typedef struct {
     uint32_t N, L, t, n_aux;       /* n_aux: primes of the exact product's extra basis */
     uint64_t ct_words;             /* 2*L*N */
     uint64_t poly_words;           /* L*N */
-    uint64_t sk_words;             /* (L+1)*N */
-    uint64_t ksk_words;            /* L*2*(L+1)*N */
+    uint64_t sk_words;             /* (L+K)*N */
+    uint64_t ksk_words;            /* dn*2*(L+K)*N */
     uint64_t scratch_bytes;        /* current scratch arena */
+    uint32_t K, dnum;              /* special primes, key-switching digits */
 } lola_info;
 
 /* ---------------------------------------------------------------- context */

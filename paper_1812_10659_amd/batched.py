@@ -5,7 +5,8 @@ product, then pairs (2i, 2i+1) multiply and relinearise, and every ciphertext
 runs its own chain of 1..64 rotations (seeded, uneven) over the power-of-two
 steps and the row swap -- the chains in one persistent work-queue launch.
 The chains are also run wave by wave (batched key switches) for comparison.
-Two choices are autotuned and cached per (N, L) in a JSON file: the batched
+Two choices are autotuned and cached per (N, L) (and number of special
+primes) in a JSON file: the batched
 NTT's radix split and tile (limbs per workgroup), timed by the library over
 every compiled variant, and the persistent launch's workgroup count.
 
@@ -151,9 +152,16 @@ def _timed(fn, reps=3):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def _cache_path(ctx, N, L):
+    """The autotune cache of one (N, L) and key-switching shape (the number
+    of special primes)."""
+    k = f"_K{ctx.K}" if getattr(ctx, "K", 1) > 1 else ""
+    return os.path.join(AUTOTUNE_DIR, f"autotune_N{N}_L{L}{k}.json")
+
+
 def autotune_chain_wg(ctx, ins, outs, tmps, steps, keys, N, L, candidates=(128, 256, 384, 512)):
     """Workgroup count of the persistent launch: measured, cached per (N, L)."""
-    path = os.path.join(AUTOTUNE_DIR, f"autotune_N{N}_L{L}.json")
+    path = _cache_path(ctx, N, L)
     try:
         with open(path) as f:
             cache = json.load(f)
@@ -182,7 +190,7 @@ def autotune_ntt(ctx, N, L, n_limbs=2048, reps=3):
     the library's autotuner (every variant timed on the device, forward +
     inverse of n_limbs limbs, each checked word for word against the default
     first); the choice is cached per (N, L) beside the chain workgroup count."""
-    path = os.path.join(AUTOTUNE_DIR, f"autotune_N{N}_L{L}.json")
+    path = _cache_path(ctx, N, L)
     try:
         with open(path) as f:
             cache = json.load(f)
@@ -211,7 +219,7 @@ def autotune_ks(ctx, N, L, n_jobs=128, reps=10):
     by the library's autotuner (every variant's words checked against the
     default, then the whole key switch of n_jobs rotations timed); cached per
     (N, L) in the same file as the NTT's choice."""
-    path = os.path.join(AUTOTUNE_DIR, f"autotune_N{N}_L{L}.json")
+    path = _cache_path(ctx, N, L)
     try:
         with open(path) as f:
             cache = json.load(f)
@@ -310,7 +318,7 @@ def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, 
     s_w = _timed(bind_chains_wavewise(ctx, cts, outs, tmps, steps, keys), reps=1)
     same = all(torch.equal(x, y) for x, y in zip(pers, outs))
     rot = int(counts.sum())
-    ks_bytes = 4 * N * (4 * L + 2 * L * (L + 1))
+    ks_bytes = 4 * N * (4 * L + 2 * ctx.dnum * (L + ctx.K))
     out["ks_autotune"] = {"chosen": {lola.KS_STAGES[st]: ctx.ks_variants(st)[ctx.ks_variant(st)] for st in range(3)},
                           "trials_ms": ks_cache.get("ks_trials_ms"), "trial_jobs": ks_cache.get("ks_trial_jobs")}
     out["rotations_persistent"] = {"ms": round(s_p * 1e3, 2), "rot_per_s": round(rot / s_p, 1),

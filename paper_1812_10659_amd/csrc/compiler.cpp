@@ -697,11 +697,13 @@ int compile_dense_head_stacked(lola_plan *p, Builder &b, const lola_layer *ls, u
 // rotation 0.69 of that plus 0.48 of it once per source and wave, ct x ct
 // product and relinearisation 24, plaintext product 0.55, one source of a
 // linear combination 0.35, plaintext add 0.5); key switches and products
-// scale with N log N and the number of limb transforms (L^2 + 3L + 2),
-// element-wise passes with L N.
+// scale with N log N and the number of limb transforms (L digit INTTs,
+// dn (L+K) - L + 2K in the inner product, 2L in the mod-down: L^2 + 3L + 2
+// with one special prime), element-wise passes with L N.
 float predict_us(const lola_plan *p) {
-    const double sN = (double)p->N / 16384.0, L = (double)p->L;
-    const double ks = sN * (L * L + 3 * L + 2) / 72.0, ew = sN * L / 7.0;
+    const double sN = (double)p->N / 16384.0, L = (double)p->L, K = (double)p->K;
+    const double dn = std::ceil(L / K), M = L + K;
+    const double ks = sN * (dn * M + 2 * K + 2 * L) / 72.0, ew = sN * L / 7.0;
     double us = 0;
     std::set<std::pair<int, int>> hoist_sources;   // (wave, source)
     for (const Op &o : p->ops) {
@@ -730,19 +732,21 @@ float predict_us(const lola_plan *p) {
 // rounds of workgroups over the 256 CUs.  Per round, measured on MI355X for
 // single-request launches at N = 16384: one transform per workgroup (digits,
 // mod-down, the key switch's latency form) 17-19 us, one transform plus its key
-// products 13 us each in the batched inner stage (L of them per workgroup),
+// products 13 us each in the batched inner stage (dn of them per workgroup),
 // the exact product of a square 42 us at L = 7, a linear combination 12 us, a
-// plaintext op 5 us.  Transform times scale with log2 N.
+// plaintext op 5 us.  Transform times scale with log2 N.  With K special
+// primes a key switch has dn = ceil(L/K) digits and L + K target moduli.
 float predict_latency_us(const lola_plan *p) {
-    const double sl = std::log2((double)p->N) / 14.0, L = (double)p->L;
+    const double sl = std::log2((double)p->N) / 14.0, L = (double)p->L, K = (double)p->K;
+    const double dn = std::ceil(L / K), M = L + K;
     auto rounds = [](double wgs) { return std::ceil(wgs / 256.0); };
     auto ks_us = [&](double n) {
         if (n <= 0) return 0.0;
-        if (n * L * (L + 1) <= 256)   // terms straight from the input, then fold and mod-down together
+        if (K == 1 && n * dn * M <= 256)   // terms straight from the input, then fold and mod-down together
             return 33.0 * sl + 34.0 * sl * rounds(2 * n * L);
         double t = 17.0 * sl * (rounds(n * L) + rounds(2 * n * L));   // digits, mod-down
-        if (n <= 16) t += 19.0 * sl * (rounds(n * L * (L + 1)) + rounds(2 * n * (L + 1)));   // terms, fold
-        else t += 13.0 * sl * L * rounds(n * (L + 1));
+        if (n <= 16) t += 19.0 * sl * (rounds(n * dn * M) + rounds(2 * n * M));   // terms, fold
+        else t += 13.0 * sl * dn * rounds(n * M);
         return t;
     };
     double us = 0;
@@ -770,13 +774,13 @@ float predict_latency_us(const lola_plan *p) {
         us += ks_us(rot);
         if (hrot > 0) {   // sources' digits and transforms, then gathered products and mod-down
             const double ns = (double)hsrc.size();
-            us += 17.0 * sl * rounds(ns * L) + 19.0 * sl * rounds(ns * L * (L + 1));
+            us += 17.0 * sl * rounds(ns * L) + 19.0 * sl * rounds(ns * dn * M);
             // the gathered products read each rotation's key and its source's
-            // transformed digits, 3 L (L+1) limbs: many hoisted rotations in a
-            // wave are bound by that traffic (about 5.5 TB/s measured)
+            // transformed digits, 3 dn (L+K) limbs: many hoisted rotations in
+            // a wave are bound by that traffic (about 5.5 TB/s measured)
             const double limb_bytes = 4.0 * (double)p->N;
-            const double bytes_us = hrot * 3.0 * L * (L + 1) * limb_bytes / 5.5e6;
-            us += std::max(14.0 * sl * (L / 7.0) * rounds(hrot * (L + 2)), bytes_us) + 17.0 * sl * rounds(2 * hrot * L);
+            const double bytes_us = hrot * 3.0 * dn * M * limb_bytes / 5.5e6;
+            us += std::max(14.0 * sl * (dn / 7.0) * rounds(hrot * (L + 2 * K)), bytes_us) + 17.0 * sl * rounds(2 * hrot * L);
         }
     }
     return (float)us;
@@ -1068,6 +1072,7 @@ static int compile_with(const lola_params *prm, const lola_layer *layers, uint32
     lola_plan *p = new lola_plan();
     p->N = prm->N;
     p->L = prm->L;
+    p->K = prm->P2 ? 2u : 1u;
     p->t = prm->t;
     p->sums = (uint32_t)sums;
     Builder b{p};

@@ -219,7 +219,7 @@ static int build_mrc(lola_ctx *ctx) {
     MrcConst &m = ctx->mrc_host;
     memset(&m, 0, sizeof m);
     const uint32_t L = ctx->L, nB = ctx->nB, t = ctx->t;
-    m.L = L; m.nB = nB; m.t = t;
+    m.L = L; m.nB = nB; m.t = t; m.K = ctx->K;
     std::vector<uint64_t> q(L), b(nB);
     for (uint32_t i = 0; i < L; ++i) q[i] = ctx->primes[i];
     for (uint32_t j = 0; j < nB; ++j) b[j] = ctx->primes[ctx->idxB(j)];
@@ -273,10 +273,29 @@ static int build_mrc(lola_ctx *ctx) {
         std::vector<uint64_t> hd = mrc_host(hr, b);
         for (uint32_t j = 0; j < nB; ++j) m.hB[j] = (uint32_t)hd[j];
     }
-    const uint64_t P = ctx->primes[ctx->idxP()];
+    const uint32_t K = ctx->K;
     for (uint32_t i = 0; i < L; ++i) {
-        pair((uint32_t)(P % q[i]), (uint32_t)q[i], m.Pq[i], m.Pqp[i]);
-        pair((uint32_t)invmod_host(P % q[i], q[i]), (uint32_t)q[i], m.Pinvq[i], m.Pinvqp[i]);
+        uint64_t P = 1;   // the special primes' product mod q_i
+        for (uint32_t k = 0; k < K; ++k) P = mulmod_host(P, ctx->primes[L + k] % q[i], q[i]);
+        pair((uint32_t)P, (uint32_t)q[i], m.Pq[i], m.Pqp[i]);
+        pair((uint32_t)invmod_host(P, q[i]), (uint32_t)q[i], m.Pinvq[i], m.Pinvqp[i]);
+    }
+    if (K == 2) {
+        const uint64_t p0 = ctx->primes[L], p1 = ctx->primes[L + 1];
+        m.sp1 = (uint32_t)p1;
+        pair((uint32_t)invmod_host(p0 % p1, p1), (uint32_t)p1, m.sp_inv, m.sp_invp);
+        m.sp_half0 = (uint32_t)((p0 - 1) / 2);
+        m.sp_half1 = (uint32_t)((p1 - 1) / 2);
+        for (uint32_t i = 0; i < L; ++i) pair((uint32_t)(p0 % q[i]), (uint32_t)q[i], m.p0q[i], m.p0qp[i]);
+        for (uint32_t d = 0; 2 * d + 1 < L; ++d) {
+            const uint64_t qa = q[2 * d], qb = q[2 * d + 1];
+            m.gqb[d] = (uint32_t)qb;
+            pair((uint32_t)invmod_host(qa % qb, qb), (uint32_t)qb, m.ginv[d], m.ginvp[d]);
+            for (uint32_t j = 0; j < L + K; ++j) {
+                const uint64_t mj = ctx->primes[j];
+                pair((uint32_t)(qa % mj), (uint32_t)mj, m.gq[d][j], m.gqp[d][j]);
+            }
+        }
     }
     LOLA_HIP(hipMalloc(&ctx->d_mrc, sizeof(MrcConst)));
     LOLA_HIP(hipMemcpy(ctx->d_mrc, &m, sizeof(MrcConst), hipMemcpyHostToDevice));
@@ -325,9 +344,14 @@ int lola_ctx_create(const lola_params *p, int device, lola_ctx **out) {
     const uint64_t twoN = 2ull * N;
     std::vector<uint32_t> mods(p->q, p->q + p->L);
     mods.push_back(p->P);
+    if (p->P2) mods.push_back(p->P2);
     for (uint32_t m : mods) {
         if (m >= (1u << 30) || !is_prime_u32(m) || (m - 1) % twoN)
             return set_error(LOLA_E_PARAMS, "modulus " + std::to_string(m) + " is not a prime < 2^30 with m = 1 mod 2N");
+        // the two-prime digit and special-prime conversions reduce a residue
+        // of one such modulus mod another with one conditional subtraction
+        if (p->P2 && m < (1u << 29))
+            return set_error(LOLA_E_PARAMS, "with a second special prime every modulus must exceed 2^29");
     }
     for (size_t i = 0; i < mods.size(); ++i)
         for (size_t k = 0; k < i; ++k)
@@ -352,6 +376,7 @@ int lola_ctx_create(const lola_params *p, int device, lola_ctx **out) {
     ctx->logN = 0;
     while ((1u << ctx->logN) < N) ++ctx->logN;
     ctx->L = p->L;
+    ctx->K = p->P2 ? 2u : 1u;
     ctx->t = p->t;
     ctx->primes = mods;
     // auxiliary basis: primes b = 1 mod 2N below 2^30, outside Q, P and t,
@@ -415,8 +440,10 @@ int lola_ctx_info(const lola_ctx *ctx, lola_info *info) {
     info->n_aux = ctx->nB;
     info->poly_words = (uint64_t)ctx->L * ctx->N;
     info->ct_words = 2 * info->poly_words;
-    info->sk_words = (uint64_t)(ctx->L + 1) * ctx->N;
-    info->ksk_words = (uint64_t)ctx->L * 2 * (ctx->L + 1) * ctx->N;
+    info->sk_words = (uint64_t)(ctx->L + ctx->K) * ctx->N;
+    info->ksk_words = (uint64_t)ctx->dnum() * 2 * (ctx->L + ctx->K) * ctx->N;
+    info->K = ctx->K;
+    info->dnum = ctx->dnum();
     info->scratch_bytes = ctx->scratch_bytes;
     return LOLA_OK;
 }

@@ -322,7 +322,8 @@ extern "C" {
 
 int lola_plan_load(lola_ctx *ctx, lola_plan *p, lola_stream stream) {
     if (!ctx || !p) return set_error(LOLA_E_INVAL, "null argument");
-    if (p->N != ctx->N || p->L != ctx->L || p->t != ctx->t) return set_error(LOLA_E_SHAPE, "plan compiled for other parameters");
+    if (p->N != ctx->N || p->L != ctx->L || p->t != ctx->t || p->K != ctx->K)
+        return set_error(LOLA_E_SHAPE, "plan compiled for other parameters");
     hipStream_t s = (hipStream_t)stream;
     const size_t N = ctx->N, L = ctx->L;
     // Everything is built into fresh buffers first.  On any failure they are

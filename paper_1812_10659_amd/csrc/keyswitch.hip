@@ -2,11 +2,13 @@
 //
 // Three launches per batch, one workgroup per limb-sized unit of work (the
 // stages themselves are in ks_core.hpp):
-//   ks_digits   (L per job):    gather sigma_g(x_i) (kept), INTT -> D_i (coefficients)
-//   ks_inner    (L+1 per job):  for target modulus m_j: for each digit i,
-//                               reduce D_i mod m_j, NTT (i == j reuses x_i),
-//                               multiply-accumulate with the key; for P the
-//                               two sums are also brought back to coefficients
+//   ks_digits   (L per job):    gather sigma_g(x_i) (kept), INTT -> x_i in coefficients
+//   ks_inner    (L+K per job):  for target modulus m_j: for each digit d,
+//                               its value mod m_j (Garner for a digit of two
+//                               primes), NTT (a digit holding q_j reuses
+//                               x_j), multiply-accumulate with the key; for a
+//                               special prime the two sums are also brought
+//                               back to coefficients
 //   ks_moddown  (2L per job):   lift [u_P]_P into q_j, NTT, subtract, times
 //                               P^-1, add the c0 (or d0 / d1) term and an
 //                               optional whole-ciphertext addend (fused
@@ -34,52 +36,62 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const Ks
     ks_stage_digit<LOGN, PAD, SPLIT>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw);
 }
 
+// Target modulus of unit u of a job whose first K units are the special
+// primes' (p_u), the others q_0..q_{L-1}.
+__device__ __forceinline__ uint32_t ks_unit_modulus(const KsDims &kd, uint32_t u) {
+    return u < kd.K ? kd.L + u : u - kd.K;
+}
+
 template <int LOGN, int KSI = ks_inner_split<LOGN>()>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJob *__restrict__ jobs, uint32_t n,
-                                                                     uint32_t L, const ModConst *__restrict__ mcs,
+                                                                     const KsDims kd,
+                                                                     const ModConst *__restrict__ mcs,
                                                                      const TwPair *__restrict__ tw,
-                                                                     const TwPair *__restrict__ itw) {
+                                                                     const TwPair *__restrict__ itw,
+                                                                     const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[2 << LOGN];   // two halves for the plain placement
-    // target modulus: q_j (j < L) or P (j == L); the special prime's unit,
-    // half again as long as the others, is dispatched ahead of the XCD's
-    // other units so the launch's tail holds short ones
-    const JobUnit ju = xcd_job_unit_lead(blockIdx.x, L + 1, 1, n);
+    // target modulus: q_j (j < L) or p_k (j = L + k); the special primes'
+    // units, longer than the others by their two inverse transforms, are
+    // dispatched ahead of the XCD's other units so the launch's tail holds
+    // short ones
+    const JobUnit ju = xcd_job_unit_lead(blockIdx.x, kd.M(), kd.K, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
-    const uint32_t j = ju.unit == 0 ? L : ju.unit - 1;
-    ks_stage_inner<LOGN, KSI>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
+    const uint32_t j = ks_unit_modulus(kd, ju.unit);
+    ks_stage_inner<LOGN, KSI>(job.key, job.scratch, j, kd, sh, mcs[j], tw, itw, mrc);
 }
 
 // Latency form of the inner stage (launches of at most KS_TERM_MAX_JOBS
-// jobs): L (L+1) workgroups per job, one digit term each, then 2 (L+1) that
-// fold the terms.  The special prime's units come first, as above.  Grid =
+// jobs): (L+K) dn workgroups per job, one digit term each, then 2 (L+K) that
+// fold the terms.  The special primes' units come first, as above.  Grid =
 // jobs x units, workgroup k taking unit k mod units of job k / units: the
 // units of one job spread over all XCDs (few jobs, so latency, not key reuse
 // through L2, is what matters).
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_term_kernel(const KsJob *__restrict__ jobs, uint32_t n,
-                                                                    uint32_t L, const ModConst *__restrict__ mcs,
-                                                                    const TwPair *__restrict__ tw) {
+                                                                    const KsDims kd,
+                                                                    const ModConst *__restrict__ mcs,
+                                                                    const TwPair *__restrict__ tw,
+                                                                    const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
-    const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
+    const uint32_t units = kd.M() * kd.dn, jb = blockIdx.x / units, unit = blockIdx.x % units;
     if (jb >= n) return;
     const KsJob job = jobs[jb];
-    const uint32_t jr = unit / L, i = unit % L;
-    const uint32_t j = jr == 0 ? L : jr - 1;
-    ks_stage_term<LOGN>(job.key, job.scratch, j, i, L, sh, mcs[j], tw);
+    const uint32_t j = ks_unit_modulus(kd, unit / kd.dn), d = unit % kd.dn;
+    ks_stage_term<LOGN>(job.key, job.scratch, j, d, kd, sh, mcs[j], tw, mrc);
 }
 
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_fold_kernel(const KsJob *__restrict__ jobs, uint32_t n,
-                                                                    uint32_t L, const ModConst *__restrict__ mcs,
+                                                                    const KsDims kd,
+                                                                    const ModConst *__restrict__ mcs,
                                                                     const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
-    const uint32_t units = 2 * (L + 1), jb = blockIdx.x / units, unit = blockIdx.x % units;
+    const uint32_t units = 2 * kd.M(), jb = blockIdx.x / units, unit = blockIdx.x % units;
     if (jb >= n) return;
     const KsJob job = jobs[jb];
-    const uint32_t jr = unit / 2, c = unit % 2;
-    const uint32_t j = jr == 0 ? L : jr - 1;
-    ks_stage_fold<LOGN>(job.scratch, j, c, L, sh, mcs[j], itw);
+    const uint32_t j = ks_unit_modulus(kd, unit / 2), c = unit % 2;
+    ks_stage_fold<LOGN>(job.scratch, j, c, kd, sh, mcs[j], itw);
 }
 
 // Latency form, two kernels: terms straight from the input (digits folded
@@ -87,77 +99,81 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_fold_kernel(const KsJo
 // units spread over all XCDs.
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_term_direct_kernel(const KsJob *__restrict__ jobs,
-                                                                           uint32_t n, uint32_t L,
+                                                                           uint32_t n, const KsDims kd,
                                                                            const ModConst *__restrict__ mcs,
                                                                            const TwPair *__restrict__ tw,
-                                                                           const TwPair *__restrict__ itw) {
+                                                                           const TwPair *__restrict__ itw,
+                                                                           const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
-    const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
+    const uint32_t units = kd.M() * kd.dn, jb = blockIdx.x / units, unit = blockIdx.x % units;
     if (jb >= n) return;
     const KsJob job = jobs[jb];
-    const uint32_t jr = unit / L, i = unit % L;
-    const uint32_t j = jr == 0 ? L : jr - 1;
-    ks_stage_term_direct<LOGN>(job.x, job.galois, job.key, job.scratch, j, i, L, sh, mcs[i], mcs[j], tw, itw);
+    const uint32_t j = ks_unit_modulus(kd, unit / kd.dn), d = unit % kd.dn;
+    ks_stage_term_direct<LOGN>(job.x, job.galois, job.key, job.scratch, j, d, kd, sh, mcs, tw, itw, mrc);
 }
 
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_fold_moddown_kernel(const KsJob *__restrict__ jobs,
-                                                                            uint32_t n, uint32_t L,
+                                                                            uint32_t n, const KsDims kd,
                                                                             const ModConst *__restrict__ mcs,
                                                                             const TwPair *__restrict__ tw,
                                                                             const TwPair *__restrict__ itw,
                                                                             const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
-    const uint32_t units = 2 * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
+    const uint32_t L = kd.L, units = 2 * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
     if (jb >= n) return;
     const KsJob job = jobs[jb];
     const uint32_t j = unit % L, c = unit / L;
-    ks_stage_fold_moddown<LOGN>(job.scratch, j, c, L, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
-                                job.addct, job.out, sh, mcs[j], mcs[L], tw, itw, mrc);
+    ks_stage_fold_moddown<LOGN>(job.scratch, j, c, kd, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
+                                job.addct, job.out, sh, mcs, tw, itw, mrc);
 }
 
 // Hoisted rotations (see ks_stage_hoisted_inner).  Mod-up: one workgroup per
-// (source, modulus j, digit i), units with i == j exit at once; grid = jobs x
-// units so one source spreads over all XCDs.
+// (source, modulus j, digit d), units whose digit holds q_j exit at once;
+// grid = jobs x units so one source spreads over all XCDs.
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_modup_kernel(const KsJob *__restrict__ jobs, uint32_t n,
-                                                                     uint32_t L, const ModConst *__restrict__ mcs,
-                                                                     const TwPair *__restrict__ tw) {
+                                                                     const KsDims kd,
+                                                                     const ModConst *__restrict__ mcs,
+                                                                     const TwPair *__restrict__ tw,
+                                                                     const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
-    const uint32_t units = (L + 1) * L, jb = blockIdx.x / units, unit = blockIdx.x % units;
+    const uint32_t units = kd.M() * kd.dn, jb = blockIdx.x / units, unit = blockIdx.x % units;
     if (jb >= n) return;
-    const uint32_t jr = unit / L, i = unit % L;
-    const uint32_t j = jr == 0 ? L : jr - 1;
-    if (i == j) return;   // c1's own limb, used as is
-    ks_stage_modup<LOGN>(jobs[jb].scratch, j, i, sh, mcs[j], tw, L);
+    const uint32_t j = ks_unit_modulus(kd, unit / kd.dn), d = unit % kd.dn;
+    if (kd.owns(d, j)) return;   // c1's own limb, used as is
+    ks_stage_modup<LOGN>(jobs[jb].scratch, j, d, sh, mcs[j], tw, kd, mrc);
 }
 
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_hoisted_inner_kernel(
-    const KsJob *__restrict__ jobs, uint32_t n, uint32_t L, const ModConst *__restrict__ mcs,
+    const KsJob *__restrict__ jobs, uint32_t n, const KsDims kd, const ModConst *__restrict__ mcs,
     const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, false>()];
-    // L + 2 units per job: the special prime's two (one per key component,
-    // each with an inverse transform, so the longest) ahead of the XCD's
-    // other units, then q_0..q_{L-1}
-    const JobUnit ju = xcd_job_unit_lead(blockIdx.x, L + 2, 2, n);
+    // L + 2K units per job: the special primes' two each (one per key
+    // component, each with an inverse transform, so the longest) ahead of the
+    // XCD's other units, then q_0..q_{L-1}
+    const uint32_t lead = 2 * kd.K;
+    const JobUnit ju = xcd_job_unit_lead(blockIdx.x, kd.L + lead, lead, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
-    const uint32_t j = ju.unit < 2 ? L : ju.unit - 2, c = ju.unit < 2 ? ju.unit : 0;
-    ks_stage_hoisted_inner<LOGN>(job.key, job.x, job.hoist, job.scratch, job.galois, j, c, L, sh, mcs[j], itw);
+    const uint32_t j = ju.unit < lead ? kd.L + ju.unit / 2 : ju.unit - lead, c = ju.unit < lead ? ju.unit % 2 : 0;
+    ks_stage_hoisted_inner<LOGN>(job.key, job.x, job.hoist, job.scratch, job.galois, j, c, kd, sh, mcs[j], itw);
 }
 
 template <int LOGN, int SPLIT = 0, bool PAD = true>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_moddown_kernel(const KsJob *__restrict__ jobs, uint32_t n,
-                                                                       uint32_t L, const ModConst *__restrict__ mcs,
+                                                                       const KsDims kd,
+                                                                       const ModConst *__restrict__ mcs,
                                                                        const TwPair *__restrict__ tw,
                                                                        const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, PAD>()];
+    const uint32_t L = kd.L;
     const JobUnit ju = xcd_job_unit(blockIdx.x, 2 * L, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t j = ju.unit % L, c = ju.unit / L;
-    ks_stage_moddown<LOGN, PAD, SPLIT>(job.scratch, j, c, L, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
+    ks_stage_moddown<LOGN, PAD, SPLIT>(job.scratch, j, c, kd, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
                                        job.addct, job.out, sh, mcs[j], tw, mrc, mcs[L].q);
 }
 
@@ -194,34 +210,34 @@ static void launch_ks_digits(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStrea
 
 template <int LG>
 static void launch_ks_inner(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s) {
-    const uint32_t L = ctx->L;
-    const dim3 g(xcd_grid(n, L + 1)), b(ctx->N / NTT_E);
+    const KsDims kd = ks_dims(ctx);
+    const dim3 g(xcd_grid(n, kd.M())), b(ctx->N / NTT_E);
     if constexpr (LG == 14) {
         switch (ctx->ks_var[1]) {
-            case 1: hipLaunchKernelGGL((ks_inner_kernel<14, 0>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw); return;
-            case 2: hipLaunchKernelGGL((ks_inner_kernel<14, 4424>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw); return;
+            case 1: hipLaunchKernelGGL((ks_inner_kernel<14, 0>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc); return;
+            case 2: hipLaunchKernelGGL((ks_inner_kernel<14, 4424>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc); return;
             default: break;
         }
     }
-    hipLaunchKernelGGL((ks_inner_kernel<LG>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw);
+    hipLaunchKernelGGL((ks_inner_kernel<LG>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc);
 }
 
 template <int LG>
 static void launch_ks_moddown(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s) {
-    const uint32_t L = ctx->L;
-    const dim3 g(xcd_grid(n, 2 * L)), b(ctx->N / NTT_E);
+    const KsDims kd = ks_dims(ctx);
+    const dim3 g(xcd_grid(n, 2 * kd.L)), b(ctx->N / NTT_E);
     if constexpr (LG == 14) {
         switch (ctx->ks_var[2]) {
-            case 1: hipLaunchKernelGGL((ks_moddown_kernel<14, 0, false>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
-            case 2: hipLaunchKernelGGL((ks_moddown_kernel<14, 4433, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
-            case 3: hipLaunchKernelGGL((ks_moddown_kernel<14, 4244, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
+            case 1: hipLaunchKernelGGL((ks_moddown_kernel<14, 0, false>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
+            case 2: hipLaunchKernelGGL((ks_moddown_kernel<14, 4433, true>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
+            case 3: hipLaunchKernelGGL((ks_moddown_kernel<14, 4244, true>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_mrc); return;
             default: break;
         }
     }
-    hipLaunchKernelGGL((ks_moddown_kernel<LG, 0, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_tw, ctx->d_mrc);
+    hipLaunchKernelGGL((ks_moddown_kernel<LG, 0, true>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_mrc);
 }
 
-size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2) * ctx->N; }
+size_t ks_scratch_words(const lola_ctx *ctx) { return (size_t)(4 * ctx->L + 2 * ctx->K) * ctx->N; }
 
 // Autotuning inputs: pseudo-random words below `bound` (every modulus of the
 // context exceeds it, so each word is a valid residue in any limb).
@@ -238,18 +254,22 @@ __global__ void ks_tune_fill_kernel(uint32_t *x, size_t nx, uint32_t *k, size_t 
 }
 
 // Launches of at most this many jobs take the latency form of the inner
-// stage (ks_term + ks_fold): L (L+1) workgroups per job instead of L+1, each
-// one transform deep instead of L, at the price of 2 L (L+1) N more scratch
-// words per job.
+// stage (ks_term + ks_fold): (L+K) dn workgroups per job instead of L+K, each
+// one transform deep instead of dn, at the price of 2 (L+K) dn N more
+// scratch words per job.
 static constexpr uint32_t KS_TERM_MAX_JOBS = 16;
 static bool ks_term_mode(uint32_t n) { return n <= KS_TERM_MAX_JOBS; }
 // Within the latency form: terms straight from the input (two kernels) while
 // they fit one round of workgroups over the CUs; beyond it the digit
 // transforms each target repeats cost more than the two launches they save.
-static bool ks_direct_mode(uint32_t n, uint32_t L) { return n * L * (L + 1) <= 256; }
+// Only with one prime per digit: a digit of two primes makes each of the two
+// kernels three transforms deep (two inverse transforms before the term's
+// transform, two special primes' before the mod-down's), against one per
+// kernel in the four-kernel form.
+static bool ks_direct_mode(uint32_t n, const KsDims &kd) { return kd.K == 1 && n * kd.dn * kd.M() <= 256; }
 static size_t ks_job_words(const lola_ctx *ctx, uint32_t n) {
-    const size_t L = ctx->L;
-    return ks_scratch_words(ctx) + (ks_term_mode(n) ? 2 * L * (L + 1) * ctx->N : 0);
+    const KsDims kd = ks_dims(ctx);
+    return ks_scratch_words(ctx) + (ks_term_mode(n) ? 2 * (size_t)kd.M() * kd.dn * ctx->N : 0);
 }
 size_t ks_launch_words(const lola_ctx *ctx, uint32_t n) { return (size_t)n * ks_job_words(ctx, n); }
 size_t ks_chunk_words(const lola_ctx *ctx, uint32_t chunk) {
@@ -257,75 +277,102 @@ size_t ks_chunk_words(const lola_ctx *ctx, uint32_t chunk) {
 }
 
 // Algorithmic cost of each key-switch kernel per launch of n jobs (bytes,
-// lane-ops), with T the lane-ops of one limb transform:
-//   digits       per (job, digit): reads x_i, writes X'_i and D_i: 12N B; one INTT
-//   inner        per job: key 2L(L+1)N words, D and X' 2LN, U 2LN + 2N out;
-//                L^2 + 2 transforms and 2L(L+1)N multiply-accumulates
+// lane-ops), with T the lane-ops of one limb transform, M = L + K target
+// moduli, dn digits, X = dn M - L the (target, digit) pairs that need a
+// transform (a digit holding the target reuses x_j), and G the pairs whose
+// digit has two primes (a Garner step per coefficient, COST_GARNER):
+//   digits       per (job, prime): reads x_i, writes X'_i and x_i: 12N B; one INTT
+//   inner        per job: key 2 dn M N words, x and X' 2LN, U 2LN + 2KN out;
+//                X + 2K transforms and 2 dn M N multiply-accumulates
 //   moddown      per (job, prime, component): U, u_P, addend in, result out:
-//                16N B; one NTT and ~10 ops a coefficient
-//   term         per job: L(L+1) units, each a digit limb and two key limbs in,
-//                two terms out (20N B); L^2 transforms, 2L(L+1)N products
-//   fold         per job: 2(L+1) units, each L terms in and one limb out; the
-//                special prime's two also INTT
-//   term_direct  as term, plus each unit's digit INTT (i != j): 2 L^2 transforms
-//   fold_moddown per job: 2L units, each the 2L terms of its prime and of P and
-//                the addend in, one limb out; two transforms each
-//   modup        per source: L^2 units (i != j), each one limb in and out, one NTT
-//   hoisted      per rotation: key, the source's L(L+1) transformed digit limbs,
-//                U and u_P out; two INTTs and the multiply-accumulates
-// Bytes count each distinct key (2L(L+1)N words) and hoisting source's
-// transformed digits (L(L+1)N words) once per launch: jobs that share them
+//                16N B (20N with two special primes); one NTT and ~10 ops a
+//                coefficient (plus a Garner step with two special primes)
+//   term         per job: dn M units, each a digit's limbs and two key limbs
+//                in, two terms out; X transforms, 2 dn M N products
+//   fold         per job: 2M units, each dn terms in and one limb out; the
+//                special primes' also INTT
+//   term_direct  as term, plus each unit's digit INTTs (one per prime of the
+//                digit, unless the digit holds the target)
+//   fold_moddown per job: 2L units, each the dn terms of its prime and of every
+//                special prime and the addend in, one limb out; K + 1 transforms
+//   modup        per source: X units, each the digit's limbs in and one out, one NTT
+//   hoisted      per rotation: key, the source's dn M transformed digit limbs,
+//                U and u_P out; 2K INTTs and the multiply-accumulates
+// Bytes count each distinct key (2 dn M N words) and hoisting source's
+// transformed digits (dn M N words) once per launch: jobs that share them
 // read them from HBM once.
 struct KsCost {
-    double N, L, T;
-    explicit KsCost(const lola_ctx *ctx) : N(ctx->N), L(ctx->L), T(xform_ops(ctx)) {}
-    double key_b() const { return 8 * N * L * (L + 1); }
-    double digits_b() const { return 12 * N; }
-    double inner_b(double n, double keys) const { return keys * key_b() + n * 8 * N * (2 * L + 1); }
-    double inner_o() const { return (L * L + 2) * T + 2 * COST_MAC * L * (L + 1) * N; }
-    double moddown_b() const { return 16 * N; }
-    double moddown_o() const { return T + 10 * N; }
-    double term_b() const { return 20 * N * L * (L + 1); }
-    double term_o() const { return L * L * T + 2 * COST_MUL * L * (L + 1) * N; }
-    double fold_b() const { return 8 * N * (L + 1) * (L + 1); }
-    double fold_o() const { return 2 * T + 2 * (L + 1) * L * N * COST_ADD; }
-    double direct_o() const { return 2 * L * L * T + 2 * COST_MUL * L * (L + 1) * N; }
-    double foldmd_b() const { return 16 * N * L * (L + 1); }
-    double foldmd_o() const { return 2 * L * (2 * T + 2 * L * N * COST_ADD + 10 * N); }
-    double modup_b() const { return 8 * N * L * L; }
-    double modup_o() const { return L * L * T; }
-    double hoist_b(double n, double keys, double srcs) const {
-        return keys * key_b() + srcs * 4 * N * L * (L + 1) + n * 8 * N * (L + 1);
+    double N, L, K, M, dn, T, X, G, W;
+    explicit KsCost(const lola_ctx *ctx) : N(ctx->N), L(ctx->L), K(ctx->K), T(xform_ops(ctx)) {
+        const KsDims kd = ks_dims(ctx);
+        M = kd.M();
+        dn = kd.dn;
+        X = dn * M - L;
+        G = 0;
+        W = 0;   // digit-limb INTTs of the direct form's units
+        for (uint32_t d = 0; d < kd.dn; ++d) {
+            const double own = kd.width(d), tgt = M - own;
+            if (kd.width(d) == 2) G += tgt;
+            W += tgt * own;
+        }
     }
-    double hoist_o() const { return 2 * T + 2 * COST_MAC * L * (L + 1) * N; }
+    double key_b() const { return 8 * N * dn * M; }
+    double digits_b() const { return 12 * N; }
+    double inner_b(double n, double keys) const { return keys * key_b() + n * 8 * N * (2 * L + K); }
+    double inner_o() const { return (X + 2 * K) * T + 2 * COST_MAC * dn * M * N + G * N * COST_GARNER; }
+    double moddown_b() const { return (12 + 4 * K) * N; }
+    double moddown_o() const { return T + 10 * N + (K > 1 ? COST_GARNER * N : 0); }
+    double term_b() const { return 20 * N * dn * M + 4 * N * G; }
+    double term_o() const { return X * T + 2 * COST_MUL * dn * M * N + G * N * COST_GARNER; }
+    double fold_b() const { return 8 * N * M * (dn + 1); }
+    double fold_o() const { return 2 * K * T + 2 * M * dn * N * COST_ADD; }
+    double direct_o() const { return (X + W) * T + 2 * COST_MUL * dn * M * N + G * N * COST_GARNER; }
+    double foldmd_b() const { return 8 * N * L * ((K + 1) * dn + 2); }
+    double foldmd_o() const {
+        return 2 * L * ((K + 1) * T + (K + 1) * dn * N * COST_ADD + 10 * N + (K > 1 ? COST_GARNER * N : 0));
+    }
+    double modup_b() const { return 8 * N * X + 4 * N * G; }
+    double modup_o() const { return X * T + G * N * COST_GARNER; }
+    double hoist_b(double n, double keys, double srcs) const {
+        return keys * key_b() + srcs * 4 * N * dn * M + n * 8 * N * (L + K);
+    }
+    double hoist_o() const { return 2 * K * T + 2 * COST_MAC * dn * M * N; }
 };
+
+double ks_whole_ops(const lola_ctx *ctx) {
+    const KsCost c(ctx);
+    return c.L * c.T + c.inner_o() + 2 * c.L * c.moddown_o();
+}
+double ks_whole_bytes(const lola_ctx *ctx) { return 4.0 * ctx->N * (4.0 * ctx->L + 2.0 * ctx->dnum() * (ctx->L + ctx->K)); }
 
 int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, const uint64_t *aux, hipStream_t s) {
     if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
+    const KsDims kd = ks_dims(ctx);
+    const uint32_t TU = kd.M() * kd.dn;   // term units per job
     const dim3 block(ctx->N / NTT_E);
     const KsCost c(ctx);
     if (ctx->timing) ctx->timed_jobs += n;
-    const bool term = ks_term_mode(n), direct = term && ks_direct_mode(n, L);
+    const bool term = ks_term_mode(n), direct = term && ks_direct_mode(n, kd);
 #define LOLA_KS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
         if (direct) {                                                                                        \
             LOLA_TIMED(ctx, s, KID_KS_TERM_DIRECT, n, c.term_b() * n, c.direct_o() * n,                       \
-                       hipLaunchKernelGGL(ks_term_direct_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, \
-                                          n, L, ctx->d_mc, ctx->d_tw, ctx->d_itw));                           \
+                       hipLaunchKernelGGL(ks_term_direct_kernel<LG>, dim3(n * TU), block, 0, s, d_jobs, n, kd,  \
+                                          ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc));                     \
             LOLA_TIMED(ctx, s, KID_KS_FOLD_MODDOWN, n, c.foldmd_b() * n, c.foldmd_o() * n,                    \
                        hipLaunchKernelGGL(ks_fold_moddown_kernel<LG>, dim3(n * 2 * L), block, 0, s, d_jobs, n, \
-                                          L, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc));                  \
+                                          kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc));                 \
             break;                                                                                           \
         }                                                                                                    \
         LOLA_TIMED(ctx, s, KID_KS_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                           \
                    launch_ks_digits<LG>(ctx, d_jobs, n, s));                                                  \
         if (term) {                                                                                          \
             LOLA_TIMED(ctx, s, KID_KS_TERM, n, c.term_b() * n, c.term_o() * n,                                \
-                       hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L, \
-                                          ctx->d_mc, ctx->d_tw));                                             \
+                       hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * TU), block, 0, s, d_jobs, n, kd,         \
+                                          ctx->d_mc, ctx->d_tw, ctx->d_mrc));                                 \
             LOLA_TIMED(ctx, s, KID_KS_FOLD, n, c.fold_b() * n, c.fold_o() * n,                                \
-                       hipLaunchKernelGGL(ks_fold_kernel<LG>, dim3(n * 2 * (L + 1)), block, 0, s, d_jobs, n, L, \
+                       hipLaunchKernelGGL(ks_fold_kernel<LG>, dim3(n * 2 * kd.M()), block, 0, s, d_jobs, n, kd, \
                                           ctx->d_mc, ctx->d_itw));                                            \
         } else {                                                                                             \
             LOLA_TIMED(ctx, s, KID_KS_INNER, n, c.inner_b(n, (double)aux[0]), c.inner_o() * n,                 \
@@ -350,6 +397,7 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, const uint6
 int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, hipStream_t s) {
     if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
+    const KsDims kd = ks_dims(ctx);
     const dim3 block(ctx->N / NTT_E);
     const KsCost c(ctx);
 #define LOLA_HS_CASE(LG)                                                                                     \
@@ -357,8 +405,8 @@ int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, h
         LOLA_TIMED(ctx, s, KID_KS_HOIST_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                     \
                    launch_ks_digits<LG>(ctx, d_jobs, n, s));                                                  \
         LOLA_TIMED(ctx, s, KID_KS_MODUP, n, c.modup_b() * n, c.modup_o() * n,                                 \
-                   hipLaunchKernelGGL(ks_modup_kernel<LG>, dim3(n * (L + 1) * L), block, 0, s, d_jobs, n, L,    \
-                                      ctx->d_mc, ctx->d_tw));                                                 \
+                   hipLaunchKernelGGL(ks_modup_kernel<LG>, dim3(n * kd.M() * kd.dn), block, 0, s, d_jobs, n, kd, \
+                                      ctx->d_mc, ctx->d_tw, ctx->d_mrc));                                     \
         break;
     switch (ctx->logN) {
         LOLA_HS_CASE(10)
@@ -377,13 +425,14 @@ int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, c
                                hipStream_t s) {
     if (n == 0) return LOLA_OK;
     const uint32_t L = ctx->L;
+    const KsDims kd = ks_dims(ctx);
     const dim3 block(ctx->N / NTT_E);
     const KsCost c(ctx);
 #define LOLA_HR_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
         LOLA_TIMED(ctx, s, KID_KS_HOISTED_INNER, n, c.hoist_b(n, (double)aux[0], (double)aux[1]), c.hoist_o() * n, \
-                   hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 2)), block, 0, s, d_jobs, \
-                                      n, L, ctx->d_mc, ctx->d_itw));                                          \
+                   hipLaunchKernelGGL(ks_hoisted_inner_kernel<LG>, dim3(xcd_grid(n, L + 2 * kd.K)), block, 0, s,   \
+                                      d_jobs, n, kd, ctx->d_mc, ctx->d_itw));                                 \
         LOLA_TIMED(ctx, s, KID_KS_HOIST_MODDOWN, n * 2 * L, c.moddown_b() * n * 2 * L, c.moddown_o() * n * 2 * L, \
                    launch_ks_moddown<LG>(ctx, d_jobs, n, s));                                                 \
         break;
@@ -400,9 +449,9 @@ int launch_keyswitch_hoist_rot(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, c
     return LOLA_OK;
 }
 
-size_t ks_hoist_words(const lola_ctx *ctx) { return ks_hoist_limbs(ctx->L) * ctx->N; }
+size_t ks_hoist_words(const lola_ctx *ctx) { return ks_hoist_limbs(ks_dims(ctx)) * ctx->N; }
 
-// Jobs per launch: bounds the scratch arena ((4L+2) N words per job).
+// Jobs per launch: bounds the scratch arena ((4L+2K) N words per job).
 static constexpr uint32_t KS_CHUNK = 128;
 
 void program_keyswitch(const lola_ctx *ctx, Program &p, std::vector<KsJob> jobs, uint32_t *scratch,
@@ -478,7 +527,7 @@ int lola_ks_autotune(lola_ctx *ctx, uint32_t n_jobs, uint32_t reps, lola_ks_vari
     if (!ctx || !chosen || (cap && !out) || n_jobs == 0 || n_jobs > KS_CHUNK || reps == 0)
         return set_error(LOLA_E_INVAL, "bad argument (1 <= n_jobs <= 128, reps >= 1)");
     hipStream_t s = (hipStream_t)stream;
-    const size_t N = ctx->N, L = ctx->L, ct = 2 * L * N, key = L * 2 * (L + 1) * N;
+    const size_t N = ctx->N, L = ctx->L, ct = 2 * L * N, key = (size_t)ctx->dnum() * 2 * (L + ctx->K) * N;
     const size_t words = n_jobs * ct * 2 + key;   // inputs, outputs, one key
     const uint32_t saved[3] = {ctx->ks_var[0], ctx->ks_var[1], ctx->ks_var[2]};
     uint32_t *buf = nullptr;
@@ -499,7 +548,7 @@ int lola_ks_autotune(lola_ctx *ctx, uint32_t n_jobs, uint32_t reps, lola_ks_vari
     uint32_t *in = buf, *outb = buf + n_jobs * ct, *kd = buf + 2 * n_jobs * ct;
     // residues below every modulus of the context, so valid in each limb
     uint32_t bound = ctx->primes[0];
-    for (uint32_t k = 0; k <= ctx->L; ++k) bound = std::min(bound, ctx->primes[k]);
+    for (uint32_t k = 0; k < ctx->L + ctx->K; ++k) bound = std::min(bound, ctx->primes[k]);
     hipLaunchKernelGGL(ks_tune_fill_kernel, dim3((unsigned)((n_jobs * ct + key + 255) / 256)), dim3(256), 0, s, in,
                        n_jobs * ct, kd, key, bound);
     // rotations by 3 (sigma_3), one key, as many jobs as given

@@ -3,21 +3,25 @@
 // limb-sized unit) and by the persistent kernel (one workgroup runs all
 // stages of a rotation).
 //
-// For a polynomial x (NTT form, [L][N]) and a switching key for s' -> s with
-// digits D_i = x mod q_i in [0, q_i):
-//   u_m = sum_i D_i * key_i   modulo every q_j and P      (key inner product)
+// For a polynomial x (NTT form, [L][N]), K special primes p_0..p_{K-1}
+// (P = their product) and a switching key for s' -> s whose digits are groups
+// of K consecutive ciphertext primes (dn = ceil(L / K) of them; the last may
+// hold fewer), with D_d = x mod Q_d in [0, Q_d) for the product Q_d of digit
+// d's primes:
+//   u_m = sum_d D_d * key_d   modulo every q_j and p_k    (key inner product)
 //   out_j = (u_j - [u_P]_P) * P^-1 mod q_j                 (mod-down by P)
-// A Galois automorphism sigma_g acts on NTT-form limbs as a permutation of
-// evaluation points, so a rotation folds it into the loads of x and of c0.
+// K = 1 is one digit per prime.  A Galois automorphism sigma_g acts on
+// NTT-form limbs as a permutation of evaluation points, so a rotation folds
+// it into the loads of x and of c0.
 //
-// Scratch of one key switch, (4L + 2) N words:
-//   D  [L][N]   digits in coefficient form          (words 0 .. L N)
-//   X' [L][N]   sigma_g(x_i) in NTT form             (L N .. 2 L N)
-//   U  [2][L][N] inner products mod q_j, NTT form    (2 L N .. 4 L N)
-//   UP [2][N]   inner products mod P, coefficients   (4 L N .. (4L+2) N)
+// Scratch of one key switch, (4L + 2K) N words:
+//   D  [L][N]    x_i in coefficient form, per prime    (words 0 .. L N)
+//   X' [L][N]    sigma_g(x_i) in NTT form               (L N .. 2 L N)
+//   U  [2][L][N] inner products mod q_j, NTT form       (2 L N .. 4 L N)
+//   UP [2][K][N] inner products mod p_k, coefficients   (4 L N .. (4L+2K) N)
 //
-// Key layout: [i][0 = b, 1 = a][m][N], m over q_0..q_{L-1}, P, stored times
-// 2^32 mod m (Montgomery form), canonical.
+// Key layout: [d][0 = b, 1 = a][m][N], m over q_0..q_{L-1}, p_0..p_{K-1},
+// stored times 2^32 mod m (Montgomery form), canonical.
 //
 // Every index that depends only on the thread id goes through an opaque copy
 // (asm volatile with a "+v" or "+s" constraint) inside loops: otherwise the
@@ -29,6 +33,18 @@
 #include "ntt_core.hpp"
 
 namespace lola {
+
+// Key-switching shape of a context: L ciphertext primes, K special primes
+// (context moduli L .. L+K-1), digits of K consecutive ciphertext primes.
+struct KsDims {
+    uint32_t L, K, dn;
+    __host__ __device__ constexpr uint32_t M() const { return L + K; }
+    __host__ __device__ constexpr uint32_t first(uint32_t d) const { return d * K; }
+    __host__ __device__ constexpr uint32_t width(uint32_t d) const { return L - d * K < K ? L - d * K : K; }
+    // digit d holds ciphertext prime j (whose X'_j is then the digit mod q_j)
+    __host__ __device__ constexpr bool owns(uint32_t d, uint32_t j) const { return j < L && j / K == d; }
+};
+inline KsDims ks_dims(const lola_ctx *ctx) { return KsDims{ctx->L, ctx->K, (ctx->L + ctx->K - 1) / ctx->K}; }
 
 // Workgroups go to the GPU's 8 XCDs round robin by linear id.  The batched
 // stages map linear id k to (job, unit) so that all `units` workgroups of a job
@@ -92,7 +108,7 @@ __device__ __forceinline__ void ks_read_sigma(const uint32_t *src, uint32_t g, u
     for (int r = 0; r < NTT_E; ++r) v[r] = sh[galois_src_index(spectral_index<LOGN, SPLIT>(tid, r), g, LOGN)];
 }
 
-// Stage 1 for digit i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
+// Stage 1 for prime i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
 // SPLIT / PAD: the transform's radix split and LDS placement (every choice
 // reads and writes the same global layouts).
 template <int LOGN, bool PAD = true, int SPLIT = 0>
@@ -114,10 +130,59 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
     for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN, SPLIT>(tid, r), v[r]);
 }
 
-// Stage 2 for target modulus j (q_j for j < L, P for j == L): for every
-// digit, reduce it mod the target, transform it (j == i reuses X'_i), and
-// accumulate its products with both key components.  The sums mod q_j go to
-// U in NTT form; the sums mod P are brought back to coefficients into UP.
+// Digit d reduced mod m_j from two canonical limbs of its primes a, b:
+// x mod q_a q_b = x_a + q_a y with y = (x_b - x_a) q_a^-1 mod q_b (Garner),
+// in [0, q_a q_b), then reduced mod m_j.  Every modulus exceeds 2^29, so
+// x_a < 2 q_b and one conditional subtraction reduces it mod q_b; the sum
+// x_a + (q_a y mod m_j, lazily < 2 m_j) stays below 2^32.
+LOLA_HD uint32_t ks_garner2(uint32_t xa, uint32_t xb, uint32_t qb, uint32_t iv, uint32_t ivp,
+                                               uint32_t w, uint32_t wp, const ModConst &mj) {
+    const uint32_t y = shoup(xb + qb - csub(xa, qb), iv, ivp, qb);
+    return reduce32(xa + shoup_lazy(y, w, wp, mj.q), mj.q, mj.one_shoup);
+}
+
+// This thread's coefficients (natural_index<LOGN, SPLIT>(tid, r)) of digit d
+// reduced mod m_j, from the coefficient-form limbs D ([L][N], limb i the
+// canonical residue mod q_i).  A digit of one prime is its limb.
+template <int LOGN, int SPLIT = 0>
+__device__ __forceinline__ void ks_digit_to(const uint32_t *D, const KsDims &kd, uint32_t d, uint32_t j,
+                                            const ModConst &mj, const MrcConst *mrc, uint32_t tid,
+                                            uint32_t (&x)[NTT_E]) {
+    constexpr uint32_t N = 1u << LOGN;
+    const uint32_t a = kd.first(d);
+    const GBuf Da = gbuf(D + ((size_t)a << LOGN), N);
+    if (kd.width(d) == 1) {
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(Da, natural_index<LOGN, SPLIT>(tid, r)), mj.q, mj.one_shoup);
+        return;
+    }
+    const GBuf Db = gbuf(D + ((size_t)(a + 1) << LOGN), N);
+    const uint32_t qb = mrc->gqb[d], iv = mrc->ginv[d], ivp = mrc->ginvp[d], w = mrc->gq[d][j], wp = mrc->gqp[d][j];
+#pragma unroll
+    for (int r = 0; r < NTT_E; ++r) {
+        const uint32_t idx = natural_index<LOGN, SPLIT>(tid, r);
+        x[r] = ks_garner2(gld(Da, idx), gld(Db, idx), qb, iv, ivp, w, wp, mj);
+    }
+}
+
+// [u]_P mod q_j for P = p_0 p_1, from u's canonical residues u0 mod p_0 and
+// u1 mod p_1: V = u0 + p_0 z, z = (u1 - u0) p_0^-1 mod p_1, lies in [0, P),
+// and the centred value is V - P when V > P/2, that is when z > (p_1 - 1)/2,
+// or z = (p_1 - 1)/2 and u0 > (p_0 - 1)/2 (both primes odd).
+LOLA_HD uint32_t ks_lift2(uint32_t u0, uint32_t u1, const MrcConst *mrc, uint32_t jj,
+                                             const ModConst &mj) {
+    const uint32_t p1 = mrc->sp1;
+    const uint32_t z = shoup(u1 + p1 - csub(u0, p1), mrc->sp_inv, mrc->sp_invp, p1);
+    const bool big = z > mrc->sp_half1 || (z == mrc->sp_half1 && u0 > mrc->sp_half0);
+    return reduce32(u0 + shoup_lazy(z, mrc->p0q[jj], mrc->p0qp[jj], mj.q) + (big ? mj.q - mrc->Pq[jj] : 0u), mj.q,
+                    mj.one_shoup);
+}
+
+// Stage 2 for target modulus j (q_j for j < L, p_{j-L} for j >= L): for
+// every digit, reduce it mod the target, transform it (a digit holding q_j
+// reuses X'_j), and accumulate its products with both key components.  The
+// sums mod q_j go to U in NTT form; the sums mod p_k are brought back to
+// coefficients into UP.
 // sh: 2N words of LDS.  Consecutive transforms alternate between its halves,
 // so each needs only the workgroup barrier inside its first exchange: when a
 // transform starts writing a half, every wave has passed that barrier of the
@@ -132,14 +197,19 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
 template <int LOGN>
 constexpr int ks_inner_split() { return LOGN == 14 ? 4433 : 0; }
 
+// UP limb of (component c, special prime k).
+__host__ __device__ constexpr size_t ks_up_limb(const KsDims &kd, uint32_t c, uint32_t k) {
+    return 4 * (size_t)kd.L + (size_t)c * kd.K + k;
+}
+
 // HALF: words between the two LDS halves (the transforms here take the plain
 // placement, which needs N).
 template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN)>
-__device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t L,
+__device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, const KsDims kd,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
-                                               const TwPair *itw) {
+                                               const TwPair *itw, const MrcConst *mrc) {
     constexpr uint32_t N = 1u << LOGN;
-    const uint32_t M = L + 1;
+    const uint32_t L = kd.L, M = kd.M();
     // 64-bit accumulators: every term is x * key with x < q (a transform's
     // output is canonical) and key < q, so at most 12 digits sum below
     // 12 q^2 < 2^64; one Montgomery reduction at the end.
@@ -147,16 +217,14 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
     uint32_t half = 0;   // LDS half of the next transform
-    for (uint32_t i = 0; i < L; ++i) {
+    for (uint32_t d = 0; d < kd.dn; ++d) {
         uint32_t tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         uint32_t x[NTT_E];
-        if (i == j) {
-            load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
+        if (kd.owns(d, j)) {
+            load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + j) << LOGN), N), tid, x);
         } else {
-            const GBuf D = gbuf(scratch + ((size_t)i << LOGN), N);
-#pragma unroll
-            for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
+            ks_digit_to<LOGN, KSI>(scratch, kd, d, j, mc, mrc, tid, x);
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
             ntt_fwd_regs<LOGN, true, KSI>(x, tid, sh + half * HALF, tw + ((size_t)jj << LOGN), mc.q);
@@ -164,7 +232,7 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
         }
         // The key offset passes through an opaque copy placed after the
         // transform, so the key loads are not scheduled ahead of it.
-        uint32_t koff = i * 2 * M + j;
+        uint32_t koff = d * 2 * M + j;
         asm volatile("" : "+s"(koff));
         uint32_t kb[NTT_E], ka[NTT_E];
         load_spectral<LOGN, KSI>(gbuf(key + ((size_t)koff << LOGN), N), tid, kb);
@@ -186,8 +254,8 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a1[r], (uint32_t)(a1[r] >> 32)}, mc);
         store_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(3 * L + j) << LOGN), N), tid, u);
     } else {
-        const GBuf UP0 = gbuf(scratch + ((size_t)(4 * L) << LOGN), N);
-        const GBuf UP1 = gbuf(scratch + ((size_t)(4 * L + 1) << LOGN), N);
+        const GBuf UP0 = gbuf(scratch + (ks_up_limb(kd, 0, j - L) << LOGN), N);
+        const GBuf UP1 = gbuf(scratch + (ks_up_limb(kd, 1, j - L) << LOGN), N);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a0[r], (uint32_t)(a0[r] >> 32)}, mc);
         ntt_inv_regs<LOGN, KSI>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
@@ -206,35 +274,34 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
 }
 
 // Latency form (launches of few jobs): stage 2 split into one workgroup per
-// term, (x_i mod m_j) * key[i][c][j] for c = 0, 1, written canonical to the
-// job's term area, and the L terms of each (j, c) summed afterwards.  A sum
+// term, (D_d mod m_j) * key[d][c][j] for c = 0, 1, written canonical to the
+// job's term area, and the dn terms of each (j, c) summed afterwards.  A sum
 // of Montgomery reductions is congruent to the reduction of the sum, and
 // both are canonical, so the words equal those of ks_stage_inner.  Term
-// area: limb 4L + 2 + 2 (j L + i) + c of the job's scratch.
-__host__ __device__ constexpr size_t ks_term_limb(uint32_t L, uint32_t j, uint32_t i, uint32_t c) {
-    return (size_t)(4 * L + 2) + 2 * ((size_t)j * L + i) + c;
+// area: limb 4L + 2K + 2 (j dn + d) + c of the job's scratch.
+__host__ __device__ constexpr size_t ks_term_limb(const KsDims &kd, uint32_t j, uint32_t d, uint32_t c) {
+    return (size_t)(4 * kd.L + 2 * kd.K) + 2 * ((size_t)j * kd.dn + d) + c;
 }
 
-// One term from the stored digits (ks_stage_digit), for launches whose terms
+// One term from the stored limbs (ks_stage_digit), for launches whose terms
 // take more than one round of workgroups.
 template <int LOGN>
-__device__ __forceinline__ void ks_stage_term(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t i,
-                                              uint32_t L, uint32_t *sh, const ModConst &mc, const TwPair *tw) {
+__device__ __forceinline__ void ks_stage_term(const uint32_t *key, uint32_t *scratch, uint32_t j, uint32_t d,
+                                              const KsDims kd, uint32_t *sh, const ModConst &mc, const TwPair *tw,
+                                              const MrcConst *mrc) {
     constexpr uint32_t N = 1u << LOGN;
     constexpr int KSI = ks_inner_split<LOGN>();
-    const uint32_t M = L + 1;
+    const uint32_t M = kd.M();
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     uint32_t x[NTT_E];
-    if (i == j) {
-        load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + i) << LOGN), N), tid, x);
+    if (kd.owns(d, j)) {
+        load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(kd.L + j) << LOGN), N), tid, x);
     } else {
-        const GBuf D = gbuf(scratch + ((size_t)i << LOGN), N);
-#pragma unroll
-        for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN, KSI>(tid, r)), mc.q, mc.one_shoup);
+        ks_digit_to<LOGN, KSI>(scratch, kd, d, j, mc, mrc, tid, x);
         ntt_fwd_regs<LOGN, false, KSI>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
     }
-    uint32_t koff = i * 2 * M + j;
+    uint32_t koff = d * 2 * M + j;
     asm volatile("" : "+s"(koff));
     uint32_t kv[NTT_E], u[NTT_E];
 #pragma unroll
@@ -245,22 +312,23 @@ __device__ __forceinline__ void ks_stage_term(const uint32_t *key, uint32_t *scr
             const uint64_t a = (uint64_t)x[r] * kv[r];
             u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mc);
         }
-        store_spectral<LOGN, KSI>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, u);
+        store_spectral<LOGN, KSI>(gbuf(scratch + (ks_term_limb(kd, j, d, c) << LOGN), N), tid, u);
     }
 }
 
-// Fold for (target m_j, component c): the sum of the L terms, stored where
-// ks_stage_inner stores its result (U, or for P back in coefficients, UP).
+// Fold for (target m_j, component c): the sum of the dn terms, stored where
+// ks_stage_inner stores its result (U, or for p_k back in coefficients, UP).
 template <int LOGN>
-__device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L, uint32_t *sh,
-                                              const ModConst &mc, const TwPair *itw) {
+__device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uint32_t c, const KsDims kd,
+                                              uint32_t *sh, const ModConst &mc, const TwPair *itw) {
     constexpr uint32_t N = 1u << LOGN;
+    const uint32_t L = kd.L;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     uint32_t u[NTT_E], v[NTT_E];
-    load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, 0, c) << LOGN), N), tid, u);
-    for (uint32_t i = 1; i < L; ++i) {
-        load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, v);
+    load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(kd, j, 0, c) << LOGN), N), tid, u);
+    for (uint32_t d = 1; d < kd.dn; ++d) {
+        load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(kd, j, d, c) << LOGN), N), tid, v);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = add_mod(u[r], v[r], mc.q);
     }
@@ -268,48 +336,63 @@ __device__ __forceinline__ void ks_stage_fold(uint32_t *scratch, uint32_t j, uin
         store_spectral<LOGN>(gbuf(scratch + ((size_t)((2 + c) * L + j) << LOGN), N), tid, u);
     } else {
         ntt_inv_regs<LOGN, 0, true>(u, tid, sh, itw + ((size_t)j << LOGN), mc);   // padded LDS placement
-        const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+        const GBuf UP = gbuf(scratch + (ks_up_limb(kd, c, j - L) << LOGN), N);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
     }
 }
 
-// The term of digit i for target m_j, computed straight from the input (the
-// digit stage folded in).  sigma_g(x_i) is gathered through LDS; for i != j
-// it is brought back to coefficients mod q_i (the digit D_i, which each
-// target's workgroup recomputes: few jobs leave the GPU idle, so a kernel
-// boundary costs more than the repeated transform), reduced mod m_j and
-// transformed; then both key products, each reduced to a canonical term.
-// The digits equal ks_stage_digit's, so the terms are those ks_stage_inner
-// accumulates.
+// The term of digit d for target m_j, computed straight from the input (the
+// digit stage folded in).  sigma_g of each of the digit's limbs is gathered
+// through LDS; unless the digit holds q_j, each is brought back to
+// coefficients (which each target's workgroup recomputes: few jobs leave the
+// GPU idle, so a kernel boundary costs more than the repeated transforms),
+// the digit is reduced mod m_j and transformed; then both key products, each
+// reduced to a canonical term.  The digits equal those ks_stage_digit's limbs
+// give, so the terms are those ks_stage_inner accumulates.
 template <int LOGN>
 __device__ __forceinline__ void ks_stage_term_direct(const uint32_t *x, uint32_t g, const uint32_t *key,
-                                                     uint32_t *scratch, uint32_t j, uint32_t i, uint32_t L,
-                                                     uint32_t *sh, const ModConst &mi, const ModConst &mj,
-                                                     const TwPair *tw, const TwPair *itw) {
+                                                     uint32_t *scratch, uint32_t j, uint32_t d, const KsDims kd,
+                                                     uint32_t *sh, const ModConst *mcs, const TwPair *tw,
+                                                     const TwPair *itw, const MrcConst *mrc) {
     constexpr uint32_t N = 1u << LOGN;
     constexpr int KSI = ks_inner_split<LOGN>();
     // the inverse transform (default split) leaves the registers in its first
     // pass's layout, which must be the layout the KSI forward transform takes
     static_assert(split_width(LOGN, 0, 0) == split_width(LOGN, KSI, 0), "first passes must match");
-    const uint32_t M = L + 1;
+    const uint32_t M = kd.M();
+    const ModConst mj = mcs[j];
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    uint32_t ii = i;
-    asm volatile("" : "+s"(ii));
     uint32_t v[NTT_E];
-    if (i == j) {
-        ks_read_sigma<LOGN, KSI>(x + ((size_t)ii << LOGN), g, tid, sh, v);   // X'_i
+    if (kd.owns(d, j)) {
+        uint32_t jj = j;
+        asm volatile("" : "+s"(jj));
+        ks_read_sigma<LOGN, KSI>(x + ((size_t)jj << LOGN), g, tid, sh, v);   // X'_j
     } else {
-        ks_read_sigma<LOGN>(x + ((size_t)ii << LOGN), g, tid, sh, v);
-        ntt_inv_regs<LOGN>(v, tid, sh, itw + ((size_t)ii << LOGN), mi);   // D_i; starts with a barrier
+        uint32_t a = kd.first(d);
+        asm volatile("" : "+s"(a));
+        ks_read_sigma<LOGN>(x + ((size_t)a << LOGN), g, tid, sh, v);
+        ntt_inv_regs<LOGN>(v, tid, sh, itw + ((size_t)a << LOGN), mcs[a]);   // x_a; starts with a barrier
+        if (kd.width(d) == 1) {
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) v[r] = reduce32(v[r], mj.q, mj.one_shoup);
+            for (int r = 0; r < NTT_E; ++r) v[r] = reduce32(v[r], mj.q, mj.one_shoup);
+        } else {
+            uint32_t b = a + 1;
+            asm volatile("" : "+s"(b));
+            uint32_t vb[NTT_E];
+            ks_read_sigma<LOGN>(x + ((size_t)b << LOGN), g, tid, sh, vb);
+            ntt_inv_regs<LOGN>(vb, tid, sh, itw + ((size_t)b << LOGN), mcs[b]);   // x_b
+            const uint32_t qb = mrc->gqb[d], iv = mrc->ginv[d], ivp = mrc->ginvp[d];
+            const uint32_t w = mrc->gq[d][j], wp = mrc->gqp[d][j];
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) v[r] = ks_garner2(v[r], vb[r], qb, iv, ivp, w, wp, mj);
+        }
         uint32_t jj = j;
         asm volatile("" : "+s"(jj));
         ntt_fwd_regs<LOGN, false, KSI>(v, tid, sh, tw + ((size_t)jj << LOGN), mj.q);
     }
-    uint32_t koff = i * 2 * M + j;
+    uint32_t koff = d * 2 * M + j;
     asm volatile("" : "+s"(koff));
     uint32_t kv[NTT_E], u[NTT_E];
 #pragma unroll
@@ -320,27 +403,28 @@ __device__ __forceinline__ void ks_stage_term_direct(const uint32_t *x, uint32_t
             const uint64_t a = (uint64_t)v[r] * kv[r];
             u[r] = acc_reduce_mont(Acc64{(uint32_t)a, (uint32_t)(a >> 32)}, mj);
         }
-        store_spectral<LOGN, KSI>(gbuf(scratch + (ks_term_limb(L, j, i, c) << LOGN), N), tid, u);
+        store_spectral<LOGN, KSI>(gbuf(scratch + (ks_term_limb(kd, j, d, c) << LOGN), N), tid, u);
     }
 }
 
-// Sum of the L terms of (target m_j, component c), canonical, in the default
+// Sum of the dn terms of (target m_j, component c), canonical, in the default
 // spectral layout.  Terms are loaded three limbs at a time, all three loads
 // in flight together; limbs past the last repeat it and are not added.
 template <int LOGN>
-__device__ __forceinline__ void ks_sum_terms(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
+__device__ __forceinline__ void ks_sum_terms(const uint32_t *scratch, uint32_t j, uint32_t c, const KsDims &kd,
                                              uint32_t tid, uint32_t q, uint32_t (&u)[NTT_E]) {
     constexpr uint32_t N = 1u << LOGN, G = 3;
+    const uint32_t n = kd.dn;
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) u[r] = 0;
-    for (uint32_t i0 = 0; i0 < L; i0 += G) {
+    for (uint32_t i0 = 0; i0 < n; i0 += G) {
         uint32_t v[G][NTT_E];
 #pragma unroll
         for (uint32_t b = 0; b < G; ++b)
-            load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(L, j, min(i0 + b, L - 1), c) << LOGN), N), tid, v[b]);
+            load_spectral<LOGN>(gbuf(scratch + (ks_term_limb(kd, j, min(i0 + b, n - 1), c) << LOGN), N), tid, v[b]);
 #pragma unroll
         for (uint32_t b = 0; b < G; ++b) {
-            const uint32_t live = 0u - (uint32_t)(i0 + b < L);   // all ones for a real term
+            const uint32_t live = 0u - (uint32_t)(i0 + b < n);   // all ones for a real term
 #pragma unroll
             for (int r = 0; r < NTT_E; ++r) u[r] = add_mod(u[r], v[b][r] & live, q);
         }
@@ -348,30 +432,43 @@ __device__ __forceinline__ void ks_sum_terms(const uint32_t *scratch, uint32_t j
 }
 
 // The sum of the terms folded into the mod-down, for (target q_j, component
-// c): the P terms summed and brought back to coefficients (u_P, recomputed by
-// each target's workgroup), lifted into q_j and transformed; the q_j terms
-// summed (U); then out as in ks_stage_moddown.  The sums equal ks_stage_inner's
-// U and UP, so the words equal the batched form's.
+// c): the terms of each special prime summed and brought back to
+// coefficients (u mod p_k, recomputed by each target's workgroup), [u]_P
+// lifted into q_j and transformed; the q_j terms summed (U); then out as in
+// ks_stage_moddown.  The sums equal ks_stage_inner's U and UP, so the words
+// equal the batched form's.
 template <int LOGN>
-__device__ __forceinline__ void ks_stage_fold_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
+__device__ __forceinline__ void ks_stage_fold_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, const KsDims kd,
                                                       const uint32_t *add, uint32_t g, const uint32_t *addct,
-                                                      uint32_t *out, uint32_t *sh, const ModConst &mj,
-                                                      const ModConst &mP, const TwPair *tw, const TwPair *itw,
-                                                      const MrcConst *mrc) {
+                                                      uint32_t *out, uint32_t *sh, const ModConst *mcs,
+                                                      const TwPair *tw, const TwPair *itw, const MrcConst *mrc) {
     constexpr uint32_t N = 1u << LOGN;
+    const ModConst mj = mcs[j];
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    uint32_t jj = j, LL = L;
+    uint32_t jj = j, LL = kd.L;
     asm volatile("" : "+s"(jj), "+s"(LL));
+    const uint32_t L = kd.L;
     uint32_t x[NTT_E], u[NTT_E];
-    ks_sum_terms<LOGN>(scratch, L, c, L, tid, mP.q, x);
-    ntt_inv_regs<LOGN, 0, true>(x, tid, sh, itw + ((size_t)LL << LOGN), mP);   // u_P, coefficients
-    // [u_P]_P mod q_j: v, or v - P for v > P/2 (see ks_stage_moddown)
-    const uint32_t halfP = mP.q >> 1, negPq = mj.q - mrc->Pq[jj];
+    const ModConst m0 = mcs[LL];
+    ks_sum_terms<LOGN>(scratch, L, c, kd, tid, m0.q, x);
+    ntt_inv_regs<LOGN, 0, true>(x, tid, sh, itw + ((size_t)LL << LOGN), m0);   // u mod p_0, coefficients
+    if (kd.K == 1) {
+        // [u_P]_P mod q_j: v, or v - P for v > P/2 (see ks_stage_moddown)
+        const uint32_t halfP = m0.q >> 1, negPq = mj.q - mrc->Pq[jj];
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(x[r] + (x[r] > halfP ? negPq : 0u), mj.q, mj.one_shoup);
+        for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(x[r] + (x[r] > halfP ? negPq : 0u), mj.q, mj.one_shoup);
+    } else {
+        uint32_t L1 = L + 1;
+        asm volatile("" : "+s"(L1));
+        const ModConst m1 = mcs[L1];
+        ks_sum_terms<LOGN>(scratch, L + 1, c, kd, tid, m1.q, u);
+        ntt_inv_regs<LOGN, 0, true>(u, tid, sh, itw + ((size_t)L1 << LOGN), m1);   // u mod p_1
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = ks_lift2(x[r], u[r], mrc, jj, mj);
+    }
     ntt_fwd_regs<LOGN, false, 0, true>(x, tid, sh, tw + ((size_t)jj << LOGN), mj.q);
-    ks_sum_terms<LOGN>(scratch, j, c, L, tid, mj.q, u);
+    ks_sum_terms<LOGN>(scratch, j, c, kd, tid, mj.q, u);
     const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) x[r] = csub(shoup_lazy(u[r] + mj.q - x[r], pinv, pinvp, mj.q), mj.q);
@@ -392,25 +489,36 @@ __device__ __forceinline__ void ks_stage_fold_moddown(const uint32_t *scratch, u
 // out = (U - lift) * P^-1, plus the optional addends: `add` ([L][N], read
 // through sigma_g when g > 1: the rotation's c0 or the relinearisation's d0 /
 // d1) and `addct` ([2][L][N], a whole ciphertext: fused rotate-and-add).
+// P0: the first special prime (with one special prime, P itself).
 template <int LOGN, bool PAD = true, int SPLIT = 0>
-__device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, uint32_t L,
+__device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, const KsDims kd,
                                                  const uint32_t *add, uint32_t g, const uint32_t *addct,
                                                  uint32_t *out, uint32_t *sh, const ModConst &mc,
-                                                 const TwPair *tw, const MrcConst *mrc, uint32_t P) {
+                                                 const TwPair *tw, const MrcConst *mrc, uint32_t P0) {
     constexpr uint32_t N = 1u << LOGN;
+    const uint32_t L = kd.L;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     uint32_t jj = j;
     asm volatile("" : "+s"(jj));
-    // [u_P]_P mod q_j: v, or v - P for v > P/2, i.e. v + (q_j - P mod q_j);
-    // v < P < 2^30 keeps the sum below 2^31 for one reduction.
-    const uint32_t halfP = P >> 1, negPq = mc.q - mrc->Pq[jj];
-    const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+    const GBuf UP = gbuf(scratch + (ks_up_limb(kd, c, 0) << LOGN), N);
     uint32_t x[NTT_E];
+    if (kd.K == 1) {
+        // [u_P]_P mod q_j: v, or v - P for v > P/2, i.e. v + (q_j - P mod q_j);
+        // v < P < 2^30 keeps the sum below 2^31 for one reduction.
+        const uint32_t halfP = P0 >> 1, negPq = mc.q - mrc->Pq[jj];
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) {
-        const uint32_t v = gld(UP, natural_index<LOGN, SPLIT>(tid, r));
-        x[r] = reduce32(v + (v > halfP ? negPq : 0u), mc.q, mc.one_shoup);
+        for (int r = 0; r < NTT_E; ++r) {
+            const uint32_t v = gld(UP, natural_index<LOGN, SPLIT>(tid, r));
+            x[r] = reduce32(v + (v > halfP ? negPq : 0u), mc.q, mc.one_shoup);
+        }
+    } else {
+        const GBuf UP1 = gbuf(scratch + (ks_up_limb(kd, c, 1) << LOGN), N);
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) {
+            const uint32_t idx = natural_index<LOGN, SPLIT>(tid, r);
+            x[r] = ks_lift2(gld(UP, idx), gld(UP1, idx), mrc, jj, mc);
+        }
     }
     ntt_fwd_regs<LOGN, false, SPLIT, PAD>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
     const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
@@ -434,33 +542,35 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
 
 // ---- hoisted rotations ---------------------------------------------------
 // Rotations of one ciphertext by several Galois elements share its
-// decomposition: the digits D_i = |c1|_{q_i} are taken before the
+// decomposition: the digits D_d = |c1|_{Q_d} are taken before the
 // automorphism, transformed to every other modulus once, and each rotation
 // gathers them through sigma_g in the NTT domain (a permutation of the
 // evaluation points), so its inner product needs no transform.  The key
-// switch then acts on the digits sigma_g(D_i) (signed integer polynomials),
-// which are still congruent to sigma_g(c1) mod q_i; the words differ from a
+// switch then acts on the digits sigma_g(D_d) (signed integer polynomials),
+// which are still congruent to sigma_g(c1) mod Q_d; the words differ from a
 // plain rotation's.  Hoist area of a source, in limbs of N words: [0, L) the
-// digits in coefficients, [L, 2L) a copy of c1 written by the digit stage
-// (unused), and 2L + j L + i digit i transformed to modulus j (j <= L, i != j).
-__host__ __device__ constexpr size_t ks_hoist_limb(uint32_t L, uint32_t j, uint32_t i) {
-    return 2 * (size_t)L + (size_t)j * L + i;
+// limbs of c1 in coefficients, [L, 2L) a copy of c1 written by the digit
+// stage (unused), and 2L + j dn + d digit d transformed to modulus j (every
+// j < L + K that digit d does not hold).
+__host__ __device__ constexpr size_t ks_hoist_limb(const KsDims &kd, uint32_t j, uint32_t d) {
+    return 2 * (size_t)kd.L + (size_t)j * kd.dn + d;
 }
-__host__ __device__ constexpr size_t ks_hoist_limbs(uint32_t L) { return 2 * (size_t)L + (size_t)(L + 1) * L; }
+__host__ __device__ constexpr size_t ks_hoist_limbs(const KsDims &kd) {
+    return 2 * (size_t)kd.L + (size_t)kd.M() * kd.dn;
+}
 
-// Digit i transformed to modulus j (j != i).
+// Digit d transformed to modulus j (a modulus the digit does not hold).
 template <int LOGN>
-__device__ __forceinline__ void ks_stage_modup(uint32_t *hoist, uint32_t j, uint32_t i, uint32_t *sh,
-                                               const ModConst &mc, const TwPair *tw, uint32_t L) {
+__device__ __forceinline__ void ks_stage_modup(uint32_t *hoist, uint32_t j, uint32_t d, uint32_t *sh,
+                                               const ModConst &mc, const TwPair *tw, const KsDims kd,
+                                               const MrcConst *mrc) {
     constexpr uint32_t N = 1u << LOGN;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     uint32_t x[NTT_E];
-    const GBuf D = gbuf(hoist + ((size_t)i << LOGN), N);
-#pragma unroll
-    for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(D, natural_index<LOGN>(tid, r)), mc.q, mc.one_shoup);
+    ks_digit_to<LOGN>(hoist, kd, d, j, mc, mrc, tid, x);
     ntt_fwd_regs<LOGN>(x, tid, sh, tw + ((size_t)j << LOGN), mc.q);
-    store_spectral<LOGN>(gbuf(hoist + (ks_hoist_limb(L, j, i) << LOGN), N), tid, x);
+    store_spectral<LOGN>(gbuf(hoist + (ks_hoist_limb(kd, j, d) << LOGN), N), tid, x);
 }
 
 // Digit limb src (NTT form) read through sigma_g at this thread's positions:
@@ -488,20 +598,20 @@ __device__ __forceinline__ void ks_hoist_gather(const uint32_t *src, uint32_t g,
 }
 
 // Inner product of one hoisted rotation for target modulus m_j: each digit's
-// transform (c1's own limb when i == j) is read through sigma_g and
-// multiplied by the key as in ks_stage_inner, whose results (U, or the
-// special prime's sums back in coefficients) it writes to the same places.
-// A data prime's workgroup forms both key components' sums; the special
+// transform (c1's own limb when the digit holds q_j) is read through sigma_g
+// and multiplied by the key as in ks_stage_inner, whose results (U, or the
+// special primes' sums back in coefficients) it writes to the same places.
+// A ciphertext prime's workgroup forms both key components' sums; a special
 // prime has one workgroup per component c, each with one 64-bit sum and one
 // inverse transform (both sums live across two transforms do not fit the
 // register file).
 template <int LOGN>
 __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, const uint32_t *x,
                                                        const uint32_t *hoist, uint32_t *scratch, uint32_t g,
-                                                       uint32_t j, uint32_t c, uint32_t L, uint32_t *sh,
+                                                       uint32_t j, uint32_t c, const KsDims kd, uint32_t *sh,
                                                        const ModConst &mc, const TwPair *itw) {
     constexpr uint32_t N = 1u << LOGN;
-    const uint32_t M = L + 1;
+    const uint32_t L = kd.L, M = kd.M();
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     uint32_t u[NTT_E];
@@ -510,13 +620,13 @@ __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, cons
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
 #pragma unroll 1
-        for (uint32_t i = 0; i < L; ++i) {
+        for (uint32_t d = 0; d < kd.dn; ++d) {
             uint32_t xv[NTT_E];
-            ks_hoist_gather<LOGN>(i == j ? x + ((size_t)i << LOGN) : hoist + (ks_hoist_limb(L, j, i) << LOGN), g,
-                                  tid, sh, xv);
+            ks_hoist_gather<LOGN>(kd.owns(d, j) ? x + ((size_t)j << LOGN) : hoist + (ks_hoist_limb(kd, j, d) << LOGN),
+                                  g, tid, sh, xv);
             // one key component at a time: both at once (32 more registers
             // beside the 64 of the sums) spilled to scratch memory
-            uint32_t koff = i * 2 * M + j;
+            uint32_t koff = d * 2 * M + j;
             uint32_t kv[NTT_E];
             load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
 #pragma unroll
@@ -538,10 +648,10 @@ __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, cons
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) a[r] = 0;
 #pragma unroll 1
-        for (uint32_t i = 0; i < L; ++i) {
+        for (uint32_t d = 0; d < kd.dn; ++d) {
             uint32_t xv[NTT_E];
-            ks_hoist_gather<LOGN>(hoist + (ks_hoist_limb(L, j, i) << LOGN), g, tid, sh, xv);
-            uint32_t koff = i * 2 * M + c * M + j;
+            ks_hoist_gather<LOGN>(hoist + (ks_hoist_limb(kd, j, d) << LOGN), g, tid, sh, xv);
+            uint32_t koff = d * 2 * M + c * M + j;
             asm volatile("" : "+s"(koff));
             uint32_t kv[NTT_E];
             load_spectral<LOGN>(gbuf(key + ((size_t)koff << LOGN), N), tid, kv);
@@ -554,7 +664,7 @@ __device__ __forceinline__ void ks_stage_hoisted_inner(const uint32_t *key, cons
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) u[r] = acc_reduce_mont(Acc64{(uint32_t)a[r], (uint32_t)(a[r] >> 32)}, mc);
         ntt_inv_regs<LOGN>(u, tid, sh, itw + ((size_t)j << LOGN), mc);
-        const GBuf UP = gbuf(scratch + ((size_t)(4 * L + c) << LOGN), N);
+        const GBuf UP = gbuf(scratch + (ks_up_limb(kd, c, j - L) << LOGN), N);
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) gst(UP, natural_index<LOGN>(tid, r), u[r]);
     }

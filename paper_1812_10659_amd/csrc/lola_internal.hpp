@@ -13,12 +13,13 @@
 namespace lola {
 
 constexpr int MAXL = 12;   // ciphertext primes
+constexpr int MAXK = 2;    // special primes of key switching
 constexpr int MAXB = 14;   // auxiliary primes of the exact ct x ct product
 
 // Constants of the exact mixed-radix conversions, on the device.
 //   Q basis: primes q_0..q_{L-1};  B basis: primes b_0..b_{nB-1}.
 struct MrcConst {
-    uint32_t L, nB, t, pad;
+    uint32_t L, nB, t, K;
     // Garner: q_k^-1 mod q_i (k < i), Shoup pairs.   [i][k]
     uint32_t invQ[MAXL][MAXL], invQp[MAXL][MAXL];
     // W_k = q_0...q_{k-1} reduced mod b_j, Shoup pairs. [j][k]
@@ -40,8 +41,16 @@ struct MrcConst {
     uint32_t wBq[MAXL][MAXB], wBqp[MAXL][MAXB];
     uint32_t hB[MAXB];            // MRC digits of (B-1)/2
     uint32_t Bq[MAXL];            // B mod q_i
-    // key switching: P mod q_i (Shoup), P^-1 mod q_i (Shoup)
+    // key switching: P = p_0 ... p_{K-1} mod q_i (Shoup), P^-1 mod q_i (Shoup)
     uint32_t Pq[MAXL], Pqp[MAXL], Pinvq[MAXL], Pinvqp[MAXL];
+    // two special primes: p_1, p_0^-1 mod p_1 (Shoup), (p_0 - 1)/2, (p_1 - 1)/2,
+    // p_0 mod q_i (Shoup)
+    uint32_t sp1, sp_inv, sp_invp, sp_half0, sp_half1;
+    uint32_t p0q[MAXL], p0qp[MAXL];
+    // digits of two ciphertext primes a = 2d, b = 2d + 1: q_b, q_a^-1 mod q_b
+    // (Shoup), and q_a mod every key-switching modulus m (Shoup)
+    uint32_t gqb[MAXL / 2], ginv[MAXL / 2], ginvp[MAXL / 2];
+    uint32_t gq[MAXL / 2][MAXL + MAXK], gqp[MAXL / 2][MAXL + MAXK];
 };
 
 // Kernels whose launches the library times when kernel timing is on, each
@@ -81,12 +90,14 @@ struct KernelTotal {
 
 }  // namespace lola
 
-// Prime index layout inside a context: [0, L) ciphertext primes, L = special
-// prime P, [L+1, L+1+nB) auxiliary primes, L+1+nB = plaintext modulus t.
+// Prime index layout inside a context: [0, L) ciphertext primes, [L, L+K)
+// the special primes of key switching, [L+K, L+K+nB) auxiliary primes,
+// L+K+nB = plaintext modulus t.
 struct lola_ctx {
     int device = 0;
     uint32_t N = 0, logN = 0;
     uint32_t L = 0, nB = 0;
+    uint32_t K = 1;                      // special primes (digits of K ciphertext primes)
     uint32_t t = 0;
     std::vector<uint32_t> primes;        // all moduli, layout above
     std::vector<lola::ModConst> mc_host;
@@ -122,9 +133,10 @@ struct lola_ctx {
     // batched key-switch stage variants (0 digits, 1 inner, 2 mod-down; 0 = default)
     uint32_t ks_var[3] = {0, 0, 0};
     uint32_t idxP() const { return L; }
-    uint32_t idxB(uint32_t j) const { return L + 1 + j; }
-    uint32_t idxT() const { return L + 1 + nB; }
-    uint32_t nprimes() const { return L + 2 + nB; }
+    uint32_t idxB(uint32_t j) const { return L + K + j; }
+    uint32_t idxT() const { return L + K + nB; }
+    uint32_t nprimes() const { return L + K + 1 + nB; }
+    uint32_t dnum() const { return (L + K - 1) / K; }   // key-switching digits
 };
 
 namespace lola {
@@ -169,6 +181,9 @@ int ktime_end(lola_ctx *ctx, hipStream_t s, hipEvent_t a, uint32_t kid, uint64_t
 // product and an add, although the kernels accumulate in 64 bits and reduce
 // once).  A limb transform is 9 (N/2) log2 N.
 constexpr double COST_BFLY = 9, COST_MUL = 4, COST_ADD = 2, COST_MAC = 7;
+// A Garner step (a digit of two primes, or the two special primes, to another
+// modulus): two modular products and three adds or reductions.
+constexpr double COST_GARNER = 2 * COST_MUL + 3 * COST_ADD;
 inline double xform_ops(const lola_ctx *ctx) { return COST_BFLY * (ctx->N / 2) * ctx->logN; }
 // descriptor upload area (device), copied asynchronously on the stream
 int desc_upload(lola_ctx *ctx, const void *host, size_t bytes, hipStream_t s, void **dev);
@@ -228,12 +243,12 @@ int launch_ntt_strided(lola_ctx *ctx, const uint32_t *in, uint32_t *out, uint32_
 // add0' is add0 under the automorphism when galois > 1.
 struct KsJob {
     const uint32_t *x;      // [L][N] polynomial to switch (NTT form, before sigma_g)
-    const uint32_t *key;    // [L][2][L+1][N] Montgomery NTT form
+    const uint32_t *key;    // [dn][2][L+K][N] Montgomery NTT form
     const uint32_t *add0;   // [L][N] added to component 0 (sigma_g applied), or null
     const uint32_t *add1;   // [L][N] added to component 1, or null
     const uint32_t *addct;  // [2][L][N] added to both components as is, or null
     uint32_t *out;          // [2][L][N]
-    uint32_t *scratch;      // (4L + 2) N words: D [L][N], Xp [L][N], U [2][L][N], UP [2][N]
+    uint32_t *scratch;      // (4L + 2K) N words: D [L][N], Xp [L][N], U [2][L][N], UP [2][K][N]
     uint32_t galois;        // 0/1: no automorphism
     uint32_t pad;
     const uint32_t *hoist;  // hoisted rotation: the source's hoist area (ks_hoist_limb), else null
@@ -248,5 +263,9 @@ size_t ks_scratch_words(const lola_ctx *ctx);    // per key switch job, launches
 size_t ks_launch_words(const lola_ctx *ctx, uint32_t n);     // a launch of n jobs
 size_t ks_chunk_words(const lola_ctx *ctx, uint32_t chunk);  // any launch of at most chunk jobs
 size_t ks_hoist_words(const lola_ctx *ctx);      // hoist area of one source of hoisted rotations
+// Algorithmic lane-ops and HBM bytes of one whole batched key switch (digits,
+// inner product, mod-down; ciphertext in and out, one key read).
+double ks_whole_ops(const lola_ctx *ctx);
+double ks_whole_bytes(const lola_ctx *ctx);
 
 }  // namespace lola

@@ -16,9 +16,9 @@
 
 namespace lola {
 
-// One key switch's scratch, (4L + 2) N words, at the largest L and N the
-// library accepts: 50 x 16384 words = 3.1 MiB.
-constexpr size_t NOALLOC_SCRATCH_WORDS = (size_t)(4 * MAXL + 2) * 16384;
+// One key switch's scratch, (4L + 2K) N words, at the largest L, K and N the
+// library accepts: 52 x 16384 words = 3.25 MiB.
+constexpr size_t NOALLOC_SCRATCH_WORDS = (size_t)(4 * MAXL + 2 * MAXK) * 16384;
 static __device__ __align__(256) uint32_t scratch[NOALLOC_SCRATCH_WORDS];
 
 constexpr int NOALLOC_MAX_DEVICES = 64;
@@ -51,23 +51,25 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks1_digits_kernel(KsJob j
 }
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks1_inner_kernel(KsJob job, uint32_t L,
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks1_inner_kernel(KsJob job, const KsDims kd,
                                                                       const ModConst *__restrict__ mcs,
                                                                       const TwPair *__restrict__ tw,
-                                                                      const TwPair *__restrict__ itw) {
+                                                                      const TwPair *__restrict__ itw,
+                                                                      const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[2 << LOGN];
-    const uint32_t j = blockIdx.x == 0 ? L : blockIdx.x - 1;
-    ks_stage_inner<LOGN>(job.key, job.scratch, j, L, sh, mcs[j], tw, itw);
+    // the special primes' units first
+    const uint32_t j = blockIdx.x < kd.K ? kd.L + blockIdx.x : blockIdx.x - kd.K;
+    ks_stage_inner<LOGN>(job.key, job.scratch, j, kd, sh, mcs[j], tw, itw, mrc);
 }
 
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks1_moddown_kernel(KsJob job, uint32_t L,
+__global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks1_moddown_kernel(KsJob job, const KsDims kd,
                                                                         const ModConst *__restrict__ mcs,
                                                                         const TwPair *__restrict__ tw,
                                                                         const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
-    const uint32_t j = blockIdx.x % L, c = blockIdx.x / L;
-    ks_stage_moddown<LOGN>(job.scratch, j, c, L, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
+    const uint32_t L = kd.L, j = blockIdx.x % L, c = blockIdx.x / L;
+    ks_stage_moddown<LOGN>(job.scratch, j, c, kd, c == 0 ? job.add0 : job.add1, c == 0 ? job.galois : 0u,
                            job.addct, job.out, sh, mcs[j], tw, mrc, mcs[L].q);
 }
 
@@ -83,7 +85,7 @@ int lola_rotate_noalloc(lola_ctx *ctx, const uint32_t *gk, uint32_t galois, cons
     if (!gk) return set_error(LOLA_E_NOKEY, "missing Galois key");
     if (galois == 0 || !(galois & 1) || galois >= 2 * ctx->N) return set_error(LOLA_E_INVAL, "bad Galois element");
     if (out == ct) return set_error(LOLA_E_INVAL, "output aliases the input");
-    const size_t words = (size_t)(4 * ctx->L + 2) * ctx->N;
+    const size_t words = (size_t)(4 * ctx->L + 2 * ctx->K) * ctx->N;
     if (words > NOALLOC_SCRATCH_WORDS)
         return set_error(LOLA_E_SHAPE, "key-switch scratch of " + std::to_string(words) +
                                            " words exceeds the fixed area of " +
@@ -97,13 +99,14 @@ int lola_rotate_noalloc(lola_ctx *ctx, const uint32_t *gk, uint32_t galois, cons
     const KsJob job{ct + P, gk, ct, nullptr, nullptr, out, scr, galois, 0, nullptr};
     hipStream_t s = (hipStream_t)stream;
     const uint32_t L = ctx->L;
+    const KsDims kd = ks_dims(ctx);
     const dim3 block(ctx->N / NTT_E);
 #define LOLA_KS1_CASE(LG)                                                                                    \
     case LG:                                                                                                 \
         hipLaunchKernelGGL(ks1_digits_kernel<LG>, dim3(L), block, 0, s, job, L, ctx->d_mc, ctx->d_itw);      \
-        hipLaunchKernelGGL(ks1_inner_kernel<LG>, dim3(L + 1), block, 0, s, job, L, ctx->d_mc, ctx->d_tw,     \
-                           ctx->d_itw);                                                                       \
-        hipLaunchKernelGGL(ks1_moddown_kernel<LG>, dim3(2 * L), block, 0, s, job, L, ctx->d_mc, ctx->d_tw,   \
+        hipLaunchKernelGGL(ks1_inner_kernel<LG>, dim3(kd.M()), block, 0, s, job, kd, ctx->d_mc, ctx->d_tw,   \
+                           ctx->d_itw, ctx->d_mrc);                                                           \
+        hipLaunchKernelGGL(ks1_moddown_kernel<LG>, dim3(2 * L), block, 0, s, job, kd, ctx->d_mc, ctx->d_tw,  \
                            ctx->d_mrc);                                                                       \
         break;
     switch (ctx->logN) {

@@ -30,33 +30,34 @@ __global__ void chain_counter_reset(uint32_t *counter) {
 }
 
 // One rotation by one workgroup: out = rotate(in) under key, through the
-// three key-switch stages in turn (scratch: (4L+2) N words of its own).
+// three key-switch stages in turn (scratch: (4L+2K) N words of its own).
 template <int LOGN>
-__device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key, uint32_t g, uint32_t L,
+__device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key, uint32_t g, const KsDims kd,
                           uint32_t *scr, uint32_t *sh, const ModConst *mcs, const TwPair *tw,
                           const TwPair *itw, const MrcConst *mrc) {
+    const uint32_t L = kd.L;
     const uint32_t *c1 = in + ((size_t)L << LOGN);
     // plain LDS placement throughout, in two halves of N words (the padded
     // placement's larger buffer measured slower inside this kernel)
     for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN, false>(c1, g, scr, i, L, sh, mcs[i], itw);
     __syncthreads();
-    for (uint32_t j = 0; j <= L; ++j) {
+    for (uint32_t j = 0; j < kd.M(); ++j) {
         // the default radix split here: the 4433 split that suits the
         // batched inner kernel measured slower inside this larger kernel
-        ks_stage_inner<LOGN, 0>(key, scr, j, L, sh, mcs[j], tw, itw);
+        ks_stage_inner<LOGN, 0>(key, scr, j, kd, sh, mcs[j], tw, itw, mrc);
         __syncthreads();   // the next target's transforms reuse both LDS halves
     }
     const uint32_t P = mcs[L].q;
     for (uint32_t c = 0; c < 2; ++c)
         for (uint32_t j = 0; j < L; ++j)
-            ks_stage_moddown<LOGN, false>(scr, j, c, L, c == 0 ? in : nullptr, g, nullptr, out, sh, mcs[j], tw, mrc, P);
+            ks_stage_moddown<LOGN, false>(scr, j, c, kd, c == 0 ? in : nullptr, g, nullptr, out, sh, mcs[j], tw, mrc, P);
     __syncthreads();   // out is the next rotation's input
 }
 
 template <int LOGN>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void chain_persistent_kernel(
     const ChainDesc *__restrict__ chains, uint32_t n_chains, const ChainStep *__restrict__ steps,
-    uint32_t *__restrict__ counter, uint32_t *__restrict__ scratch, size_t scratch_per_wg, uint32_t L,
+    uint32_t *__restrict__ counter, uint32_t *__restrict__ scratch, size_t scratch_per_wg, const KsDims kd,
     const ModConst *__restrict__ mcs, const TwPair *__restrict__ tw, const TwPair *__restrict__ itw,
     const MrcConst *__restrict__ mrc) {
     __shared__ uint32_t sh[2 << LOGN];   // two halves of N words: plain placement only
@@ -73,7 +74,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void chain_persistent_kernel(
         for (uint32_t r = 0; r < ch.n_steps; ++r) {
             uint32_t *dst = ((ch.n_steps - 1 - r) & 1) ? ch.tmp : ch.out;
             const ChainStep st = steps[ch.first + r];
-            wg_rotate<LOGN>(src, dst, st.key, st.galois, L, scr, sh, mcs, tw, itw, mrc);
+            wg_rotate<LOGN>(src, dst, st.key, st.galois, kd, scr, sh, mcs, tw, itw, mrc);
             src = dst;
         }
     }
@@ -125,17 +126,16 @@ int lola_rotate_chains(lola_ctx *ctx, const lola_chain *chains, uint32_t n, uint
     const ChainStep *dst = (const ChainStep *)((uint8_t *)d + os);
     hipLaunchKernelGGL(chain_counter_reset, dim3(1), dim3(64), 0, s, counter);
     const dim3 block(ctx->N / NTT_E);
-    // cost per rotation: the ciphertext in and out and the key read once
-    // (4N (4L + 2L(L+1)) B); the digit INTTs, the inner stage and the mod-down
-    const double dN = ctx->N, dL = ctx->L, T = xform_ops(ctx);
-    const double rot_b = 4 * dN * (4 * dL + 2 * dL * (dL + 1));
-    const double rot_o = dL * T + (dL * dL + 2) * T + 2 * COST_MAC * dL * (dL + 1) * dN + 2 * dL * (T + 10 * dN);
+    // cost per rotation: the ciphertext in and out and the key read once; the
+    // digit INTTs, the inner stage and the mod-down (those of one batched key
+    // switch)
+    const double rot_b = ks_whole_bytes(ctx), rot_o = ks_whole_ops(ctx);
     const uint64_t rots = st.size();
 #define LOLA_CHAIN_CASE(LG)                                                                                  \
     case LG:                                                                                                 \
         LOLA_TIMED(ctx, s, KID_CHAIN, rots, rot_b * rots, rot_o * rots,                                      \
                    hipLaunchKernelGGL(chain_persistent_kernel<LG>, dim3(n_wg), block, 0, s, dcd, n, dst, counter, \
-                                      scr, per, ctx->L, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc));       \
+                                      scr, per, ks_dims(ctx), ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc)); \
         break;
     switch (ctx->logN) {
         LOLA_CHAIN_CASE(10)

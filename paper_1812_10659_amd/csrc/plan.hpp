@@ -45,6 +45,7 @@ struct ExecLane {
 
 struct lola_plan {
     uint32_t N = 0, L = 0, t = 0;
+    uint32_t K = 1;   // special primes of key switching (digits of K ciphertext primes)
     uint32_t n_inputs = 0, queries = 1;
     uint32_t recipe = 3;                        // LOLA_RECIPE_*
     uint32_t sums = 1;                          // LOLA_SUMS_SEQUENTIAL or LOLA_SUMS_HOISTED

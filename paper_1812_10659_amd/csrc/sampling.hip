@@ -119,23 +119,25 @@ __global__ void pk_combine_kernel(const uint32_t *__restrict__ ahat, const uint3
     pk[(size_t)L * N + o] = to_mont(ahat[o], c);
 }
 
-// b_i = -a_i s + e_i + [i==j] (P mod q_j) s'; stored [i][0=b,1=a][j][N], Montgomery.
-// grid (N/256, L+1 moduli, L digits)
+// b_d = -a_d s + e_d + [q_j a prime of digit d] (P mod q_j) s'; stored
+// [d][0=b,1=a][j][N], Montgomery.  Digit d holds the K consecutive
+// ciphertext primes from d K.  grid (N/256, L+K moduli, dn digits)
 __global__ void ksk_combine_kernel(const uint32_t *__restrict__ ahat, const uint32_t *__restrict__ ehat,
                                    const uint32_t *__restrict__ sk, const uint32_t *__restrict__ sprime,
-                                   uint32_t *__restrict__ ksk, uint32_t N, uint32_t L,
+                                   uint32_t *__restrict__ ksk, uint32_t N, uint32_t L, uint32_t K,
                                    const ModConst *__restrict__ mcs, const MrcConst *__restrict__ mrc) {
     const uint32_t j = blockIdx.y, i = blockIdx.z, k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
+    const uint32_t M = L + K;
     const ModConst c = mcs[j];
-    const size_t aoff = ((size_t)i * (L + 1) + j) * N + k;
+    const size_t aoff = ((size_t)i * M + j) * N + k;
     const size_t soff = (size_t)j * N + k;
     uint32_t a = ahat[aoff];
     uint32_t v = sub_mod(ehat[aoff], mulmod_plain(a, sk[soff], c), c.q);
-    if (i == j) v = add_mod(v, shoup(sprime[soff], mrc->Pq[j], mrc->Pqp[j], c.q), c.q);
-    const size_t base = (size_t)i * 2 * (L + 1) * N;
+    if (j < L && j / K == i) v = add_mod(v, shoup(sprime[soff], mrc->Pq[j], mrc->Pqp[j], c.q), c.q);
+    const size_t base = (size_t)i * 2 * M * N;
     ksk[base + (size_t)j * N + k] = to_mont(v, c);
-    ksk[base + (size_t)(L + 1) * N + (size_t)j * N + k] = to_mont(a, c);
+    ksk[base + (size_t)M * N + (size_t)j * N + k] = to_mont(a, c);
 }
 
 // s'_j = s_j^2 (relinearisation) or s_j at the Galois source index.
@@ -234,7 +236,7 @@ int lola_keygen_secret(lola_ctx *ctx, uint64_t seed, uint32_t *sk, lola_stream s
     rc = launch_samples(ctx, seed, {SampleJob{(uint32_t *)buf, DOM_SK, 0, 0, SAMPLE_TERNARY, 0, 0}}, s);
     if (rc) return rc;
     std::vector<NttJob> jobs;
-    for (uint32_t j = 0; j <= ctx->L; ++j)
+    for (uint32_t j = 0; j < ctx->L + ctx->K; ++j)
         jobs.push_back(NttJob{(const uint32_t *)buf, sk + (size_t)j * ctx->N, j, NTT_SRC_SIGNED32});
     return launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s);
 }
@@ -268,19 +270,19 @@ int lola_keygen_switch(lola_ctx *ctx, uint64_t seed, const uint32_t *sk, uint32_
     if (!ctx || !sk || !ksk) return set_error(LOLA_E_INVAL, "null argument");
     if (galois != 0 && (!(galois & 1) || galois >= 2 * ctx->N)) return set_error(LOLA_E_INVAL, "bad Galois element");
     hipStream_t s = (hipStream_t)stream;
-    const size_t N = ctx->N, L = ctx->L, M = L + 1;
+    const size_t N = ctx->N, L = ctx->L, M = L + ctx->K, DN = ctx->dnum();
     void *buf = nullptr;
-    // s' [M][N], per digit: e [N] + a [M][N] raw, then transformed ahat/ehat [L][M][N] each
-    const size_t words = M * N + L * (N + M * N) + 2 * L * M * N;
+    // s' [M][N], per digit: e [N] + a [M][N] raw, then transformed ahat/ehat [dn][M][N] each
+    const size_t words = M * N + DN * (N + M * N) + 2 * DN * M * N;
     int rc = scratch_get(ctx, words * 4, &buf);
     if (rc) return rc;
-    uint32_t *Sp = (uint32_t *)buf, *E = Sp + M * N, *A = E + L * N, *Ah = A + L * M * N, *Eh = Ah + L * M * N;
+    uint32_t *Sp = (uint32_t *)buf, *E = Sp + M * N, *A = E + DN * N, *Ah = A + DN * M * N, *Eh = Ah + DN * M * N;
     hipLaunchKernelGGL(sprime_kernel, dim3((unsigned)(N / 256), (unsigned)M), dim3(256), 0, s, sk, Sp,
                        (uint32_t)N, ctx->logN, galois, ctx->d_mc);
     LOLA_HIP(hipGetLastError());
     std::vector<SampleJob> sj;
     std::vector<NttJob> jobs;
-    for (uint32_t i = 0; i < L; ++i) {
+    for (uint32_t i = 0; i < DN; ++i) {
         const uint32_t obj = (galois << 8) | i;
         sj.push_back(SampleJob{E + i * N, DOM_KSK_E, obj, 0, SAMPLE_CBD, 0, 0});
         for (uint32_t j = 0; j < M; ++j) {
@@ -291,8 +293,8 @@ int lola_keygen_switch(lola_ctx *ctx, uint64_t seed, const uint32_t *sk, uint32_
     }
     if ((rc = launch_samples(ctx, seed, sj, s))) return rc;
     if ((rc = launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), s))) return rc;
-    hipLaunchKernelGGL(ksk_combine_kernel, dim3((unsigned)(N / 256), (unsigned)M, (unsigned)L), dim3(256), 0, s,
-                       Ah, Eh, sk, Sp, ksk, (uint32_t)N, (uint32_t)L, ctx->d_mc, ctx->d_mrc);
+    hipLaunchKernelGGL(ksk_combine_kernel, dim3((unsigned)(N / 256), (unsigned)M, (unsigned)DN), dim3(256), 0, s,
+                       Ah, Eh, sk, Sp, ksk, (uint32_t)N, (uint32_t)L, ctx->K, ctx->d_mc, ctx->d_mrc);
     LOLA_HIP(hipGetLastError());
     return LOLA_OK;
 }
@@ -377,7 +379,7 @@ int lola_decrypt(lola_ctx *ctx, const uint32_t *sk, const uint32_t *ct, uint32_t
 int lola_export_sk(lola_ctx *ctx, const uint32_t *sk, uint32_t *out, lola_stream stream) {
     if (!ctx || !sk || !out) return set_error(LOLA_E_INVAL, "null argument");
     std::vector<NttJob> jobs;
-    for (uint32_t j = 0; j <= ctx->L; ++j)
+    for (uint32_t j = 0; j < ctx->L + ctx->K; ++j)
         jobs.push_back(NttJob{sk + (size_t)j * ctx->N, out + (size_t)j * ctx->N, j, NTT_INVERSE});
     return launch_ntt_jobs(ctx, jobs.data(), (int)jobs.size(), (hipStream_t)stream);
 }
@@ -396,8 +398,8 @@ int lola_export_pk(lola_ctx *ctx, const uint32_t *pk, uint32_t *out, lola_stream
 int lola_export_ksk(lola_ctx *ctx, const uint32_t *ksk, uint32_t *out, lola_stream stream) {
     if (!ctx || !ksk || !out) return set_error(LOLA_E_INVAL, "null argument");
     std::vector<NttJob> jobs;
-    const uint32_t M = ctx->L + 1;
-    for (uint32_t i = 0; i < ctx->L; ++i)
+    const uint32_t M = ctx->L + ctx->K;
+    for (uint32_t i = 0; i < ctx->dnum(); ++i)
         for (uint32_t c = 0; c < 2; ++c)
             for (uint32_t j = 0; j < M; ++j) {
                 size_t o = (((size_t)i * 2 + c) * M + j) * ctx->N;

@@ -51,7 +51,7 @@ __global__ void tensor_extend_kernel(const MulJob *__restrict__ jobs, uint32_t N
     for (int i = 0; i < MAXL; ++i) r[i] = i < L ? r[i] : 0;
     mrc_digits<MAXL>(r, v, L, mcs, mrc->invQ, mrc->invQp);
     const bool neg = mrc_greater<MAXL>(v, L, mrc->hQ);
-    const ModConst *mb = mcs + L + 1;
+    const ModConst *mb = mcs + L + mrc->K;   // the auxiliary primes
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) {
         if (j < nB) {
@@ -67,7 +67,7 @@ __global__ void tensor_extend_kernel(const MulJob *__restrict__ jobs, uint32_t N
 // grid (N/256, L + nB, jobs)
 __global__ void tensor_product_kernel(const MulJob *__restrict__ jobs, uint32_t N, uint32_t L, uint32_t nB,
                                       size_t offBx, size_t offDq, size_t offDb,
-                                      const ModConst *__restrict__ mcs) {
+                                      const ModConst *__restrict__ mcs, const ModConst *__restrict__ mbs) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x, l = blockIdx.y;
     if (k >= N) return;
     const MulJob job = jobs[blockIdx.z];
@@ -79,7 +79,7 @@ __global__ void tensor_product_kernel(const MulJob *__restrict__ jobs, uint32_t 
         a0 = job.a[o]; a1 = job.a[P1 + o]; b0 = job.b[o]; b1 = job.b[P1 + o];
     } else {
         const uint32_t j = l - L;
-        c = mcs[L + 1 + j];
+        c = mbs[j];
         const uint32_t *ext = job.scr + offBx;
         const size_t o = (size_t)j * N + k, PB = (size_t)nB * N, ob = job.a == job.b ? o : 2 * PB + o;
         a0 = ext[o]; a1 = ext[PB + o]; b0 = ext[ob]; b1 = ext[PB + ob];
@@ -121,7 +121,7 @@ __global__ void tensor_round_kernel(const MulJob *__restrict__ jobs, uint32_t N,
     for (int i = 0; i < MAXL; ++i) r[i] = i < L ? shoup(r[i], mrc->tq[i], mrc->tqp[i], mcs[i].q) : 0;
     mrc_digits<MAXL>(r, v, L, mcs, mrc->invQ, mrc->invQp);   // digits of R = t d mod Q
     const uint32_t carry = mrc_greater<MAXL>(v, L, mrc->hQ) ? 1u : 0u;
-    const ModConst *mb = mcs + L + 1;
+    const ModConst *mb = mcs + L + mrc->K;   // the auxiliary primes
     uint32_t z[MAXB], w[MAXB];
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) {
@@ -174,7 +174,7 @@ int launch_mul_stage(lola_ctx *ctx, uint32_t stage, const MulJob *d, uint32_t n,
         LOLA_TIMED(ctx, s, KID_TENSOR_PRODUCT, n, (polys + 3.0 * n) * 4 * dN * (dL + dB),
                    n * dN * (dL + dB) * (6 * M + A),
                    hipLaunchKernelGGL(tensor_product_kernel, dim3(N / 256, L + nB, n), dim3(256), 0, s, d, N, L,
-                                      nB, ml.Bx, ml.Dq, ml.Db, ctx->d_mc));
+                                      nB, ml.Bx, ml.Dq, ml.Db, ctx->d_mc, ctx->d_mc + ctx->idxB(0)));
     else
         LOLA_TIMED(ctx, s, KID_TENSOR_ROUND, n, 3.0 * n * 4 * dN * (2 * dL + dB),
                    3.0 * n * dN * (dL * M + dL * (dL - 1) / 2 * (M + A) + dL + dB * (dL * (M + A) + 2 * M + 2 * A) +

@@ -35,14 +35,15 @@ class LolaError(RuntimeError):
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint32), ("L", ctypes.c_uint32),
                 ("q", ctypes.POINTER(ctypes.c_uint32)), ("P", ctypes.c_uint32),
-                ("allow_insecure", ctypes.c_int)]
+                ("allow_insecure", ctypes.c_int), ("P2", ctypes.c_uint32)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("L", ctypes.c_uint32), ("t", ctypes.c_uint32),
                 ("n_aux", ctypes.c_uint32), ("ct_words", ctypes.c_uint64),
                 ("poly_words", ctypes.c_uint64), ("sk_words", ctypes.c_uint64),
-                ("ksk_words", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64)]
+                ("ksk_words", ctypes.c_uint64), ("scratch_bytes", ctypes.c_uint64),
+                ("K", ctypes.c_uint32), ("dnum", ctypes.c_uint32)]
 
 
 class KsDesc(ctypes.Structure):
@@ -149,19 +150,20 @@ def galois_element(N: int, step) -> int:
 
 
 class Context:
-    """lola_ctx for one parameter set (N, t, q, P) on one device."""
+    """lola_ctx for one parameter set (N, t, q, P and, for digits of two
+    primes, P2) on one device."""
 
     def __init__(self, params, device: int = 0):
         self.params = params
         self.device = torch.device("cuda", device)
-        q = (ctypes.c_uint32 * len(params.q))(*params.q)
-        p = _Params(params.N, params.t, len(params.q), q, params.P, int(getattr(params, "insecure_ok", False)))
+        p, q = _params_struct(params)
         h = ctypes.c_void_p()
         _check(lib().lola_ctx_create(ctypes.byref(p), device, ctypes.byref(h)))
         self.h = h
         info = _Info()
         _check(lib().lola_ctx_info(self.h, ctypes.byref(info)))
         self.N, self.L, self.t, self.n_aux = info.N, info.L, info.t, info.n_aux
+        self.K, self.dnum = info.K, info.dnum
         self.ksk_words = info.ksk_words
 
     def close(self):
@@ -193,7 +195,7 @@ class Context:
         _check(lib().lola_set_key_words(self.h, arr))
 
     def keygen_secret(self, seed: int) -> torch.Tensor:
-        sk = self.empty(self.L + 1, self.N)
+        sk = self.empty(self.L + self.K, self.N)
         _check(lib().lola_keygen_secret(self.h, seed, _p(sk), _stream()))
         return sk
 
@@ -203,7 +205,7 @@ class Context:
         return pk
 
     def keygen_switch(self, seed: int, sk: torch.Tensor, galois: int) -> torch.Tensor:
-        k = self.empty(self.L, 2, self.L + 1, self.N)
+        k = self.empty(self.dnum, 2, self.L + self.K, self.N)
         _check(lib().lola_keygen_switch(self.h, seed, _p(sk), galois, _p(k), _stream()))
         return k
 
@@ -490,7 +492,8 @@ def square() -> dict:
 
 def _params_struct(params):
     q = (ctypes.c_uint32 * len(params.q))(*params.q)
-    return _Params(params.N, params.t, len(params.q), q, params.P, int(getattr(params, "insecure_ok", False))), q
+    return _Params(params.N, params.t, len(params.q), q, params.P, int(getattr(params, "insecure_ok", False)),
+                   int(getattr(params, "P2", 0))), q
 
 
 class KernelStat(ctypes.Structure):

@@ -130,10 +130,11 @@ class ModelSetup:
     Galois keys of both plans, pre-encrypted input sets and a pool of output
     buffers."""
 
-    def __init__(self, kind: str, clients: int, inputs_per_client: int, out_pool: int):
+    def __init__(self, kind: str, clients: int, inputs_per_client: int, out_pool: int,
+                 mnist_params: str = "mnist_n16384_k2"):
         self.kind = kind
         if kind == "mnist":
-            self.p = wl.PARAMS["mnist_n16384"]
+            self.p = wl.PARAMS[mnist_params]
             self.w = wl.mnist_weights()
             layers = networks.mnist_layers(self.w)
         else:
@@ -212,13 +213,13 @@ class ModelSetup:
 def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, clients: int = 8,
                 max_inflight: int = 64, hbm_budget_gb: float = 96.0, check_every: int = 50,
                 baseline: bool = True, seed: int | None = None, check_all: bool = True,
-                keep_models: bool = False) -> dict:
+                keep_models: bool = False, mnist_params: str = "mnist_n16384_k2") -> dict:
     assert torch.cuda.is_available()
     arrivals, kinds = wl.serving_arrivals(n_req, rate, p_large, seed)
     g = wl.rng(wl.workload_seed(4) if seed is None else seed, 9)
     client_of = g.integers(0, clients, size=n_req)
     input_of = g.integers(0, 2, size=n_req)
-    models = {"mnist": ModelSetup("mnist", clients, 2, max_inflight + 16),
+    models = {"mnist": ModelSetup("mnist", clients, 2, max_inflight + 16, mnist_params),
               "dense64": ModelSetup("dense64", clients, 2, max_inflight + 16)}
     torch.cuda.synchronize()
     srv = Server(int(hbm_budget_gb * (1 << 30)))
@@ -293,7 +294,7 @@ def run_serving(n_req: int = 2000, rate: float = 200.0, p_large: float = 0.7, cl
         ref_mismatches += sum(0 if torch.equal(a, b) else 1 for a, b in zip(ref, outs))
     kept.clear()
     res = {
-        "requests": n_req, "rate_per_s": rate, "wall_s": round(wall, 3),
+        "requests": n_req, "rate_per_s": rate, "wall_s": round(wall, 3), "mnist_params": mnist_params,
         "inferences_per_s": round(n_req / wall, 2),
         "p50_ms": round(float(np.percentile(latency, 50)) * 1e3, 2),
         "p99_ms": round(float(np.percentile(latency, 99)) * 1e3, 2),

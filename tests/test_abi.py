@@ -48,7 +48,8 @@ def test_galois_element_host_logic(lib):
 
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint32), ("L", ctypes.c_uint32),
-                ("q", ctypes.POINTER(ctypes.c_uint32)), ("P", ctypes.c_uint32), ("allow_insecure", ctypes.c_int)]
+                ("q", ctypes.POINTER(ctypes.c_uint32)), ("P", ctypes.c_uint32), ("allow_insecure", ctypes.c_int),
+                ("P2", ctypes.c_uint32)]
 
 
 @pytest.mark.parametrize("case,code", [
@@ -57,10 +58,14 @@ class _Params(ctypes.Structure):
     (dict(N=16384, t=12289, q=[1073643521], P=1071415297), -2),                 # t != 1 mod 2N
     (dict(N=4096, t=65537, q=[1073692673, 1073668097, 1073651713], P=1073643521), -3),  # over the cap
     (dict(N=3000, t=65537, q=[1073692673], P=1073668097), -2),                  # N not a power of two
+    # a second special prime: repeated, below 2^29, and over the cap with it
+    (dict(N=16384, t=1146881, q=[1073643521, 1073479681], P=1073184769, P2=1073184769), -2),
+    (dict(N=4096, t=65537, q=[1073692673], P=1073668097, P2=40961), -2),
+    (dict(N=4096, t=65537, q=[1073692673, 1073668097], P=1073651713, P2=1073643521), -3),
 ])
 def test_parameter_validation_errors(lib, case, code):
     q = (ctypes.c_uint32 * len(case["q"]))(*case["q"])
-    p = _Params(case["N"], case["t"], len(case["q"]), q, case["P"], 0)
+    p = _Params(case["N"], case["t"], len(case["q"]), q, case["P"], 0, case.get("P2", 0))
     h = ctypes.c_void_p()
     lib.lola_ctx_create.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
     lib.lola_last_error.restype = ctypes.c_char_p

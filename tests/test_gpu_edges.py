@@ -14,11 +14,13 @@ pytestmark = pytest.mark.gpu
 SEED = 0x5EED_0002
 
 
-@pytest.fixture(scope="module")
-def toy():
+# one prime per key-switching digit, and digits of two primes with two
+# special primes
+@pytest.fixture(scope="module", params=["toy1024", "toy1024_k2"])
+def toy(request):
     import torch
     from paper_1812_10659_amd import lola
-    p = wl.PARAMS["toy1024"]
+    p = wl.PARAMS[request.param]
     print(f"[gpu-edges] params {p.name}", flush=True)
     ctx = lola.Context(p)
     octx = bfv.Context(p)

@@ -1,6 +1,8 @@
 """The benchmark's headline batch, exactly as timed: the MNIST-shaped network
 at N=16384 (compiler's default plan), 64 requests over 8 key sets, run as two
-lanes and replayed from a captured graph.  Every request's output words equal
+lanes and replayed from a captured graph, under both key-switching shapes
+(digits of two primes with two special primes, as timed, and one prime per
+digit).  Every request's output words equal
 its single-request evaluation, two single requests (under different key sets)
 equal the oracle's ciphertext run word for word, and every request decrypts
 to the plaintext network's logits mod t."""
@@ -16,17 +18,17 @@ pytestmark = pytest.mark.gpu
 B, C = 64, 8
 
 
-@pytest.fixture(scope="module")
-def headline():
+@pytest.fixture(scope="module", params=["mnist_n16384_k2", "mnist_n16384"])
+def headline(request):
     import torch
     from paper_1812_10659_amd import lola, networks
     from paper_1812_10659_amd import requests as rq
-    p = wl.PARAMS["mnist_n16384"]
+    p = wl.PARAMS[request.param]
     w = wl.mnist_weights()
     ctx = lola.Context(p)
     plan = lola.Plan(p, networks.mnist_layers(w))
     plan.load(ctx)
-    print(f"[gpu-headline] {B} requests over {C} key sets", flush=True)
+    print(f"[gpu-headline] {p.name}: {B} requests over {C} key sets", flush=True)
     reqs, keys, images = rq.mnist_batch(ctx, plan, B, C)
     torch.cuda.synchronize()
     singles = []

@@ -87,6 +87,24 @@ def test_mnist_network_matches_oracle(name, recipe):
     _run_and_compare(env, sched, nw.mnist_plain(img, w))
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("sums", ["sequential", "hoisted"])
+def test_mnist_two_prime_digits_matches_oracle(sums):
+    """The MNIST network with key-switching digits of two primes and two
+    special primes (mnist_n16384_k2), shared reduction, in both forms of the
+    sums: ciphertext words against the oracle's schedule run with the same
+    key-switching reading, logits against the plain network."""
+    from paper_1812_10659_amd import lola, networks
+    w, img = wl.mnist_weights(), wl.mnist_image(index=5)
+    print(f"[gpu-net] mnist, digits of two primes, {sums} sums", flush=True)
+    sched = nw.mnist_schedule(w, recipe="shared", sums=sums)
+    env = _setup("mnist_n16384_k2", networks.mnist_layers(w), sched, networks.mnist_input_values(img),
+                 wl.key_seed(1) + 33, wl.enc_seed(1) + 33, recipe=lola.RECIPE_SHARED_REDUCTION,
+                 sums=lola.SUMS_HOISTED if sums == "hoisted" else lola.SUMS_SEQUENTIAL)
+    assert env["ctx"].K == 2 and env["ctx"].dnum == 4
+    _run_and_compare(env, sched, nw.mnist_plain(img, w))
+
+
 def test_mnist_hoisted_sums_matches_oracle():
     """The MNIST network in the layout for single requests (shared reduction,
     every rotate-and-sum and combination in the hoisted form: 106 rotations

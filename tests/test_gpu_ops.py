@@ -8,7 +8,8 @@ from paper_1812_10659_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PSETS = ["toy1024", "toy2048", "n4096_3q", "n8192", "mnist_n16384", "l12_n16384"]
+# the last two: key-switching digits of two primes with two special primes
+PSETS = ["toy1024", "toy2048", "n4096_3q", "n8192", "mnist_n16384", "l12_n16384", "toy1024_k2", "mnist_n16384_k2"]
 STEPS = [1, -1, 7, bfv.ROW_SWAP]
 SEED = 0x5EED_0001
 
@@ -67,7 +68,7 @@ def test_galois_elements_agree(env):
 def test_ntt_is_evaluation_at_odd_powers(env):
     from paper_1812_10659_amd import lola
     ctx, p = env["ctx"], env["p"]
-    primes = list(p.q) + [p.P] + [None] * ctx.n_aux + [p.t]
+    primes = list(p.q) + list(p.special) + [None] * ctx.n_aux + [p.t]
     idx = [i for i in range(len(primes)) if primes[i] is not None]
     rs = np.random.default_rng(1)
     x = np.stack([rs.integers(0, primes[i], p.N) for i in idx]).astype(np.uint32)
@@ -90,7 +91,7 @@ def _ntt_case(env):
     the oracle's evaluation at odd powers of the minimal root, bit-reversed."""
     from paper_1812_10659_amd import lola
     ctx, p = env["ctx"], env["p"]
-    primes = list(p.q) + [p.P] + [None] * ctx.n_aux + [p.t]
+    primes = list(p.q) + list(p.special) + [None] * ctx.n_aux + [p.t]
     idx = [0, p.L - 1, p.L, len(primes) - 1, 0]
     rs = np.random.default_rng(7)
     x = np.stack([rs.integers(0, primes[i], p.N) for i in idx]).astype(np.uint32)
@@ -165,7 +166,7 @@ def test_keys_match_oracle(env):
     pk = _u32(ctx.export_pk(env["pk"])).astype(np.uint64)
     assert np.array_equal(pk[0], ok.pk0) and np.array_equal(pk[1], ok.pk1)
     for key, ref in [(env["rlk"], ok.rlk)] + [(env["gks"][g], ok.galois[g]) for g in env["gal"][:2]]:
-        k = _u32(ctx.export_ksk(key)).astype(np.uint64)   # [L][2][L+1][N]
+        k = _u32(ctx.export_ksk(key)).astype(np.uint64)   # [dn][2][L+K][N]
         assert np.array_equal(k[:, 0], ref.b) and np.array_equal(k[:, 1], ref.a)
 
 
@@ -338,12 +339,12 @@ def test_rotate_hoisted_matches_oracle(env):
 @pytest.mark.parametrize("n_jobs", [1, 4, 5, 16, 17, 40])
 def test_keyswitch_both_inner_forms(env, n_jobs):
     """Launches of at most 16 jobs split the key inner product into one
-    workgroup per (prime, digit) term plus a fold; larger ones accumulate all
-    digits per prime.  Launches whose L (L+1) terms per job fit one round of
-    256 workgroups compute the terms straight from the input and fold them
-    inside the mod-down (two kernels).  All give the oracle's words (4 and 5
-    jobs sit on either side of the two-kernel form at L = 7, 16 and 17 on
-    either side of the term split)."""
+    workgroup per (modulus, digit) term plus a fold; larger ones accumulate
+    all digits per modulus.  Launches whose dn (L+K) terms per job fit one
+    round of 256 workgroups compute the terms straight from the input and
+    fold them inside the mod-down (two kernels).  All give the oracle's words
+    (4 and 5 jobs sit on either side of the two-kernel form at L = 7 with one
+    special prime, 16 and 17 on either side of the term split)."""
     ctx, octx, ok = env["ctx"], env["octx"], env["okeys"]
     c1, c2 = env["c"]
     c3 = bfv.mul(octx, c1, c2)

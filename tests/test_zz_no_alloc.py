@@ -1,8 +1,9 @@
 """The rotation that allocates nothing (lola_rotate_noalloc, scratch in a
 fixed device array) against lola_rotate on the same inputs, word for word,
-through the C ABI: two calls in a row, the second on a smaller ring and
-prime count, so that it runs over the first call's leftovers in the shared
-array."""
+through the C ABI: calls in a row, each smaller than the one before (digits
+of two primes with two special primes, then one prime per digit, then a
+smaller ring and prime count), so that each runs over the previous call's
+leftovers in the shared array."""
 import ctypes
 
 import numpy as np
@@ -27,7 +28,7 @@ def test_rotate_noalloc_equals_rotate_second_call_smaller():
     from paper_1812_10659_amd import lola
     f = _noalloc()
     # (parameter set, step): the second call is the smaller one
-    for k, (pname, step) in enumerate([("mnist_n16384", 3), ("n4096_3q", "row_swap")]):
+    for k, (pname, step) in enumerate([("mnist_n16384_k2", 5), ("mnist_n16384", 3), ("n4096_3q", "row_swap")]):
         p = wl.PARAMS[pname]
         print(f"[gpu-noalloc] call {k}: {pname} step {step}", flush=True)
         ctx = lola.Context(p)
@@ -61,7 +62,7 @@ def test_rotate_noalloc_rejects_bad_arguments():
     ctx = lola.Context(p)
     ct, out = ctx.empty_ct(), ctx.empty_ct()
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    key = ctx.empty(p.L, 2, p.L + 1, p.N)
+    key = ctx.empty(ctx.dnum, 2, p.L + ctx.K, p.N)
     code = {v: k for k, v in lola.E_CODES.items()}
     assert f(ctx.h, None, 3, ct.data_ptr(), out.data_ptr(), s) == code["E_NOKEY"]
     assert f(ctx.h, key.data_ptr(), 4, ct.data_ptr(), out.data_ptr(), s) == code["E_INVAL"]
