@@ -45,10 +45,12 @@ GARNER_OPS = 14                             # two modular products, three adds o
 # copy (FETCH_SIZE read 0.5 GiB: x2.0; WRITE_SIZE read 1 GiB: x1.0).  These
 # count L2 misses, so reads served by the last-level cache count too.  Valid
 # only for kernel sources with this digest; otherwise the traffic is null.
-KS_INNER_TRAFFIC = {"digest": "b1a54abb8a5ded5d", "fetch_per_job": 4.1703e6, "write_per_job": 1.0486e6, "K": 1}
+KS_INNER_TRAFFIC = {"digest": "2eb8498a11e5896d", "fetch_per_job": 3.6937e6, "write_per_job": 1.1797e6, "K": 2}
 # parameter set of the MNIST-shaped workload (--params): seven ciphertext
 # primes with key-switching digits of two primes and two special primes
 MNIST_PARAMS = "mnist_n16384_k2"
+# the other networks' parameter sets (two-prime key-switching digits as well)
+DENSE_PARAMS, HEAD_PARAMS, CIFAR_PARAMS = "mnist_dense_n16384_k2", "head_n16384_k2", "cifar_n16384_k2"
 KS_INNER_SOURCES = ["keyswitch.hip", "ks_core.hpp", "ntt_core.hpp", "modarith.hpp", "lola_internal.hpp"]
 
 
@@ -579,11 +581,11 @@ def latency_plans_run(ctx, w, img, latency_runs):
     ws = wl.mnist_small_weights()
     out["mnist_small"] = _latency_plan_case(ctx, pm, networks.mnist_small_layers(ws), mv,
                                             _plain_small_logits(img, ws), latency_runs, wl.key_seed(1) + 103)
-    pd = wl.PARAMS["mnist_dense_n16384"]
+    pd = wl.PARAMS[DENSE_PARAMS]
     out["mnist_dense_input"] = _latency_plan_case(lola.Context(pd), pd, networks.mnist_dense_layers(w), mv,
                                                   _plain_logits_mod_t(img, w, pd.t), latency_runs,
                                                   wl.key_seed(1) + 105)
-    ph, wh = wl.PARAMS["head_n16384"], wl.head_weights()
+    ph, wh = wl.PARAMS[HEAD_PARAMS], wl.head_weights()
     f = wl.head_features(1)[0]
     out["head"] = _latency_plan_case(lola.Context(ph), ph, networks.head_layers(wh), f, _head_plain(f, wh),
                                      latency_runs, wl.key_seed(3) + 107)
@@ -715,7 +717,7 @@ def dense_input_run(B, C, latency_runs, steps=3):
     import torch
     from paper_1812_10659_amd import lola, networks
     from paper_1812_10659_amd import workloads as wl
-    p = wl.PARAMS["mnist_dense_n16384"]
+    p = wl.PARAMS[DENSE_PARAMS]
     w = wl.mnist_weights()
     ctx = lola.Context(p)
     plan = lola.Plan(p, networks.mnist_dense_layers(w))
@@ -771,7 +773,7 @@ def head_recipes_run(n_queries=64, steps=3):
     import torch
     from paper_1812_10659_amd import lola, networks
     from paper_1812_10659_amd import workloads as wl
-    p = wl.PARAMS["head_n16384"]
+    p = wl.PARAMS[HEAD_PARAMS]
     w = wl.head_weights()
     feats = wl.head_features(n_queries)
     exp = [[int(v) % p.t for v in _head_plain(feats[q], w)] for q in range(n_queries)]
@@ -834,7 +836,7 @@ def cifar_run(runs=3):
     import torch
     from paper_1812_10659_amd import lola, networks
     from paper_1812_10659_amd import workloads as wl
-    p = wl.PARAMS["cifar_n16384"]
+    p = wl.PARAMS[CIFAR_PARAMS]
     w = wl.cifar_weights()
     img = wl.cifar_image(index=0)
     t0 = time.perf_counter()

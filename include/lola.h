@@ -29,9 +29,11 @@
  *       plaintext    [N]          coefficients mod t (lola_encode output)
  *       mul-form pt  [L][N]       from lola_plain_mul_form
  *       add-form pt  [L][N]       from lola_plain_add_form
- *       secret key   [L+1][N]     NTT form mod q_0..q_{L-1}, P
+ *       secret key   [L+K][N]     NTT form mod q_0..q_{L-1} and the K special primes
  *       public key   [2][L][N]
- *       switch key   [L][2][L+1][N]  (relinearisation or one Galois element)
+ *       switch key   [dn][2][L+K][N]  (relinearisation or one Galois element;
+ *                                 dn digits of K ciphertext primes, K = 1 or 2,
+ *                                 see lola_params)
  *     Device forms are internal: NTT evaluation order with Montgomery scaling
  *     on key and mul-form data.  lola_to_coeff / lola_*_export give the
  *     canonical coefficient form (residues in [0, q_i)) used for comparisons.
@@ -122,9 +124,12 @@ uint32_t lola_galois_element(uint32_t N, int32_t step);
 /* ------------------------------------------------------------------- keys */
 /* Keys of the scheme of Sec. 3.1 (the paper takes BFV from its library; the
  * public-key and switching-key forms are this library's reading: ternary s,
- * pk = (-(a s + e), a), switching keys with one digit per ciphertext prime
- * and one special prime P).  sk_dev [L+1][N], pk_dev [2][L][N], ksk_dev
- * [L][2][L+1][N] (caller-owned device buffers, written).  Errors:
+ * pk = (-(a s + e), a), hybrid switching keys with special primes: digit d
+ * of K consecutive ciphertext primes carries P s' at exactly its own primes,
+ * P the special primes' product; one digit per prime with one special
+ * prime, or digits of two primes with two).  sk_dev [L+K][N], pk_dev
+ * [2][L][N], ksk_dev [dn][2][L+K][N] (caller-owned device buffers, written).
+ * Errors:
  * LOLA_E_INVAL (null pointer, bad Galois element).
  * Random values come from ChaCha20 (RFC 8439) with key = (seed lo, seed hi,
  * k2..k7), k2..k7 the context's key words, nonce = (domain, object, limb),
@@ -329,14 +334,15 @@ int lola_to_coeff(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n_polys, uint3
                   lola_stream stream);
 int lola_from_coeff(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n_polys, uint32_t *out_dev,
                     lola_stream stream);
-/* Keys in coefficient form: secret [L+1][N] (residues of the ternary s),
- * public [2][L][N], switching [L][2][L+1][N]. */
+/* Keys in coefficient form: secret [L+K][N] (residues of the ternary s),
+ * public [2][L][N], switching [dn][2][L+K][N]. */
 int lola_export_sk(lola_ctx *ctx, const uint32_t *sk_dev, uint32_t *out_dev, lola_stream stream);
 int lola_export_pk(lola_ctx *ctx, const uint32_t *pk_dev, uint32_t *out_dev, lola_stream stream);
 int lola_export_ksk(lola_ctx *ctx, const uint32_t *ksk_dev, uint32_t *out_dev, lola_stream stream);
 
 /* Diagnostic: forward or inverse NTT of n limbs, limb k modulo prime index
- * prime_idx_host[k] (0..L-1 ciphertext primes, L = P, L+1+n_aux = t), natural
+ * prime_idx_host[k] (0..L-1 ciphertext primes, L..L+K-1 the special primes,
+ * L+K..L+K+n_aux-1 the auxiliary primes, L+K+n_aux = t), natural
  * coefficient order <-> bit-reversed evaluation order:
  * out[k] = a(psi^(2 brv(k) + 1)) with psi the smallest primitive 2N-th root.
  * When prime_idx_host[k] = k mod L for every k (the limbs of consecutive
@@ -636,17 +642,21 @@ int lola_kernel_timing(lola_ctx *ctx, double *total_ms, uint64_t *launches, uint
  * HBM bytes and VALU lane-ops the library charges for them.  Bytes count
  * each distinct buffer a launch reads once (jobs of a batch share keys,
  * sources and constants); lane-ops count every job's work.  Units and the
- * charges (N ring degree, L ciphertext primes, T = 9 (N/2) log2 N lane-ops of
- * one limb transform, K = 8N L(L+1) bytes of one switching key):
+ * charges (N ring degree, L ciphertext primes, K special primes, dn digits,
+ * M = L + K, T = 9 (N/2) log2 N lane-ops of one limb transform, KB = 8N dn M
+ * bytes of one switching key, X = dn M - L transformed (target, digit)
+ * pairs, G of them with a two-prime digit, 14 lane-ops per Garner step; with
+ * K = 1: dn = L, X = L^2, G = 0):
  *   ntt_jobs_kernel          limb             8N B,  T
- *   ks_digits_kernel         (job, digit)     12N B, T
- *   ks_inner_kernel          job              K per distinct key + 8N (2L+1) B, (L^2+2) T + 14 L (L+1) N
- *   ks_moddown_kernel        (job, prime, component)  16N B, T + 10N
- *   ks_modup_kernel          source           8N L^2 B, L^2 T
+ *   ks_digits_kernel         (job, prime)     12N B, T
+ *   ks_inner_kernel          job              KB per distinct key + 8N (2L+K) B,
+ *                                             (X + 2K) T + 14 dn M N + 14 G N
+ *   ks_moddown_kernel        (job, prime, component)  (12 + 4K) N B, T + 10N (+ 14N if K = 2)
+ *   ks_modup_kernel          source           8N X + 4N G B, X T + 14 G N
  *   ks_digits_kernel/hoist, ks_moddown_kernel/hoist: the same kernels run
  *                            for hoisted rotations, charged as above
- *   ks_hoisted_inner_kernel  rotation         K per distinct key + 4N L(L+1) per distinct
- *                            source + 8N (L+1) B, 2T + 14 L (L+1) N
+ *   ks_hoisted_inner_kernel  rotation         KB per distinct key + 4N dn M per distinct
+ *                            source + 8N (L+K) B, 2K T + 14 dn M N
  *   tensor_*_kernel, lin_kernel, plain_kernel, latency-form and chain
  *   kernels: as documented at their launch sites.
  * Writes at most cap entries (kernels with no launch are skipped) and sets

@@ -40,11 +40,20 @@ struct KsDims {
     uint32_t L, K, dn;
     __host__ __device__ constexpr uint32_t M() const { return L + K; }
     __host__ __device__ constexpr uint32_t first(uint32_t d) const { return d * K; }
-    __host__ __device__ constexpr uint32_t width(uint32_t d) const { return L - d * K < K ? L - d * K : K; }
+    __host__ __device__ constexpr uint32_t width(uint32_t d) const {
+        return K == 1 ? 1u : (L - d * K < K ? L - d * K : K);   // d < dn
+    }
     // digit d holds ciphertext prime j (whose X'_j is then the digit mod q_j)
     __host__ __device__ constexpr bool owns(uint32_t d, uint32_t j) const { return j < L && j / K == d; }
 };
 inline KsDims ks_dims(const lola_ctx *ctx) { return KsDims{ctx->L, ctx->K, (ctx->L + ctx->K - 1) / ctx->K}; }
+// The shape with K fixed at compile time when KFIX = 1 (one prime per digit,
+// one special prime), so that the two-prime branches compile away; KFIX = 0
+// keeps the runtime shape.
+template <int KFIX>
+__host__ __device__ constexpr KsDims ks_fix(const KsDims kd) {
+    return KFIX == 1 ? KsDims{kd.L, 1u, kd.L} : kd;
+}
 
 // Workgroups go to the GPU's 8 XCDs round robin by linear id.  The batched
 // stages map linear id k to (job, unit) so that all `units` workgroups of a job
@@ -204,11 +213,12 @@ __host__ __device__ constexpr size_t ks_up_limb(const KsDims &kd, uint32_t c, ui
 
 // HALF: words between the two LDS halves (the transforms here take the plain
 // placement, which needs N).
-template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN)>
-__device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, const KsDims kd,
+template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN), int KFIX = 0>
+__device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, const KsDims kd_,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
                                                const TwPair *itw, const MrcConst *mrc) {
     constexpr uint32_t N = 1u << LOGN;
+    const KsDims kd = ks_fix<KFIX>(kd_);
     const uint32_t L = kd.L, M = kd.M();
     // 64-bit accumulators: every term is x * key with x < q (a transform's
     // output is canonical) and key < q, so at most 12 digits sum below
@@ -490,12 +500,13 @@ __device__ __forceinline__ void ks_stage_fold_moddown(const uint32_t *scratch, u
 // through sigma_g when g > 1: the rotation's c0 or the relinearisation's d0 /
 // d1) and `addct` ([2][L][N], a whole ciphertext: fused rotate-and-add).
 // P0: the first special prime (with one special prime, P itself).
-template <int LOGN, bool PAD = true, int SPLIT = 0>
-__device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, const KsDims kd,
+template <int LOGN, bool PAD = true, int SPLIT = 0, int KFIX = 0>
+__device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32_t j, uint32_t c, const KsDims kd_,
                                                  const uint32_t *add, uint32_t g, const uint32_t *addct,
                                                  uint32_t *out, uint32_t *sh, const ModConst &mc,
                                                  const TwPair *tw, const MrcConst *mrc, uint32_t P0) {
     constexpr uint32_t N = 1u << LOGN;
+    const KsDims kd = ks_fix<KFIX>(kd_);
     const uint32_t L = kd.L;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));

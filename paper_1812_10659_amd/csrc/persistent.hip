@@ -31,7 +31,9 @@ __global__ void chain_counter_reset(uint32_t *counter) {
 
 // One rotation by one workgroup: out = rotate(in) under key, through the
 // three key-switch stages in turn (scratch: (4L+2K) N words of its own).
-template <int LOGN>
+// KFIX = 1: contexts with one prime per digit (the shape fixed at compile
+// time, which keeps the two-prime branches out of this large kernel).
+template <int LOGN, int KFIX>
 __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key, uint32_t g, const KsDims kd,
                           uint32_t *scr, uint32_t *sh, const ModConst *mcs, const TwPair *tw,
                           const TwPair *itw, const MrcConst *mrc) {
@@ -44,17 +46,18 @@ __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key
     for (uint32_t j = 0; j < kd.M(); ++j) {
         // the default radix split here: the 4433 split that suits the
         // batched inner kernel measured slower inside this larger kernel
-        ks_stage_inner<LOGN, 0>(key, scr, j, kd, sh, mcs[j], tw, itw, mrc);
+        ks_stage_inner<LOGN, 0, (1u << LOGN), KFIX>(key, scr, j, kd, sh, mcs[j], tw, itw, mrc);
         __syncthreads();   // the next target's transforms reuse both LDS halves
     }
     const uint32_t P = mcs[L].q;
     for (uint32_t c = 0; c < 2; ++c)
         for (uint32_t j = 0; j < L; ++j)
-            ks_stage_moddown<LOGN, false>(scr, j, c, kd, c == 0 ? in : nullptr, g, nullptr, out, sh, mcs[j], tw, mrc, P);
+            ks_stage_moddown<LOGN, false, 0, KFIX>(scr, j, c, kd, c == 0 ? in : nullptr, g, nullptr, out, sh, mcs[j], tw,
+                                                   mrc, P);
     __syncthreads();   // out is the next rotation's input
 }
 
-template <int LOGN>
+template <int LOGN, int KFIX>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void chain_persistent_kernel(
     const ChainDesc *__restrict__ chains, uint32_t n_chains, const ChainStep *__restrict__ steps,
     uint32_t *__restrict__ counter, uint32_t *__restrict__ scratch, size_t scratch_per_wg, const KsDims kd,
@@ -74,7 +77,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void chain_persistent_kernel(
         for (uint32_t r = 0; r < ch.n_steps; ++r) {
             uint32_t *dst = ((ch.n_steps - 1 - r) & 1) ? ch.tmp : ch.out;
             const ChainStep st = steps[ch.first + r];
-            wg_rotate<LOGN>(src, dst, st.key, st.galois, kd, scr, sh, mcs, tw, itw, mrc);
+            wg_rotate<LOGN, KFIX>(src, dst, st.key, st.galois, kd, scr, sh, mcs, tw, itw, mrc);
             src = dst;
         }
     }
@@ -131,11 +134,17 @@ int lola_rotate_chains(lola_ctx *ctx, const lola_chain *chains, uint32_t n, uint
     // switch)
     const double rot_b = ks_whole_bytes(ctx), rot_o = ks_whole_ops(ctx);
     const uint64_t rots = st.size();
+    const KsDims kd = ks_dims(ctx);
 #define LOLA_CHAIN_CASE(LG)                                                                                  \
     case LG:                                                                                                 \
-        LOLA_TIMED(ctx, s, KID_CHAIN, rots, rot_b * rots, rot_o * rots,                                      \
-                   hipLaunchKernelGGL(chain_persistent_kernel<LG>, dim3(n_wg), block, 0, s, dcd, n, dst, counter, \
-                                      scr, per, ks_dims(ctx), ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc)); \
+        if (ctx->K == 1)                                                                                     \
+            LOLA_TIMED(ctx, s, KID_CHAIN, rots, rot_b * rots, rot_o * rots,                                  \
+                       hipLaunchKernelGGL((chain_persistent_kernel<LG, 1>), dim3(n_wg), block, 0, s, dcd, n, dst, \
+                                          counter, scr, per, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc)); \
+        else                                                                                                 \
+            LOLA_TIMED(ctx, s, KID_CHAIN, rots, rot_b * rots, rot_o * rots,                                  \
+                       hipLaunchKernelGGL((chain_persistent_kernel<LG, 0>), dim3(n_wg), block, 0, s, dcd, n, dst, \
+                                          counter, scr, per, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc)); \
         break;
     switch (ctx->logN) {
         LOLA_CHAIN_CASE(10)

@@ -73,8 +73,16 @@ PARAMS: Dict[str, ParamSet] = {
     # after the convolution's, each row-major layer's products on top): ten
     # data primes, log2(QP) = 330 <= 438.
     "chain_n16384": ParamSet("chain_n16384", 16384, 1146881, tuple(PRIMES_16384[:10]), PRIMES_16384[10]),
+    # The LoLa-Dense and CIFAR-shaped sets with key-switching digits of two
+    # primes and two special primes (log2(QP) = 300 <= 438).
+    "mnist_dense_n16384_k2": ParamSet("mnist_dense_n16384_k2", 16384, 1146881, tuple(PRIMES_16384[:8]),
+                                      PRIMES_16384[8], P2=PRIMES_16384[9]),
+    "cifar_n16384_k2": ParamSet("cifar_n16384_k2", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8],
+                                P2=PRIMES_16384[9]),
     # Transfer-learning head: six data primes.
     "head_n16384": ParamSet("head_n16384", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6]),
+    "head_n16384_k2": ParamSet("head_n16384_k2", 16384, 1146881, tuple(PRIMES_16384[:6]), PRIMES_16384[6],
+                               P2=PRIMES_16384[7]),
     # The largest ciphertext-prime count the library accepts: twelve data
     # primes (log2(QP) = 390 <= 438), for tests at that limit.
     "l12_n16384": ParamSet("l12_n16384", 16384, 1146881, tuple(PRIMES_16384[:12]), PRIMES_16384[12]),

@@ -186,6 +186,41 @@ def test_hoisted_sums_larger_networks_match_oracle(net):
     assert env["plan"].info["sums"] == H
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("net", ["dense_input", "head", "head_stacked"])
+def test_two_prime_digits_other_networks_match_oracle(net):
+    """Key-switching digits of two primes with two special primes on
+    LoLa-Dense (eight data primes: four digits) and on the transfer head with
+    8 hidden units under both recipes (six data primes: three digits): words
+    against the oracle's schedules run with the same reading, outputs
+    against the plain networks."""
+    from paper_1812_10659_amd import lola, networks
+    print(f"[gpu-net] {net}, digits of two primes", flush=True)
+    if net == "dense_input":
+        w, img = wl.mnist_weights(), wl.mnist_image(index=11)
+        sched = nw.mnist_dense_schedule(w, recipe="shared")
+        env = _setup("mnist_dense_n16384_k2", networks.mnist_dense_layers(w), sched,
+                     networks.mnist_input_values(img), wl.key_seed(1) + 37, wl.enc_seed(1) + 37,
+                     recipe=lola.RECIPE_SHARED_REDUCTION)
+        _run_and_compare(env, sched, nw.mnist_plain(img, w))
+    else:
+        w = wl.head_weights()
+        wt = wl.HeadWeights(w.w1[:8], w.b1[:8], w.w2[:, :8], w.b2)
+        if net == "head":
+            f = wl.head_features(4)
+            sched = nw.head_schedule(w, n_hidden=8)
+            env = _setup("head_n16384_k2", networks.head_layers(w, 8), sched, f, wl.key_seed(3) + 39,
+                         wl.enc_seed(3) + 39, recipe=lola.RECIPE_DENSE_ROW_MAJOR)
+            _run_and_compare(env, sched, np.concatenate([nw.head_plain(f[q], wt) for q in range(4)]))
+        else:
+            f = wl.head_features(1)
+            sched = nw.head_stacked_schedule(w, n_hidden=8)
+            env = _setup("head_n16384_k2", networks.head_layers(w, 8), sched, f[0], wl.key_seed(3) + 41,
+                         wl.enc_seed(3) + 41, recipe=lola.RECIPE_STACKED_ROW_MAJOR)
+            _run_and_compare(env, sched, nw.head_plain(f[0], wt))
+    assert env["ctx"].K == 2
+
+
 @pytest.mark.parametrize("name,recipe", RECIPES)
 def test_mnist_dense_input_network_matches_oracle(name, recipe):
     """LoLa-Dense: one dense input message, masks and rotations build the
