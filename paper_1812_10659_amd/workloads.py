@@ -22,7 +22,7 @@ PRIMES_4096 = [1073692673, 1073668097, 1073651713, 1073643521, 1073569793,
                1073479681, 1073430529, 1073299457]
 PRIMES_16384 = [1073643521, 1073479681, 1073184769, 1073053697, 1072857089,
                 1072496641, 1071513601, 1071415297, 1071087617, 1070727169,
-                1070432257, 1069219841, 1068564481]
+                1070432257, 1069219841, 1068564481, 1068466177]
 
 # Classical 128-bit security caps on log2(Q*P) for a ternary secret, per ring
 # degree (the homomorphic-encryption security standard's table).
@@ -86,6 +86,11 @@ PARAMS: Dict[str, ParamSet] = {
     # The largest ciphertext-prime count the library accepts: twelve data
     # primes (log2(QP) = 390 <= 438), for tests at that limit.
     "l12_n16384": ParamSet("l12_n16384", 16384, 1146881, tuple(PRIMES_16384[:12]), PRIMES_16384[12]),
+    # The same with two special primes: six digits of two primes, fourteen
+    # key-switching moduli (log2(QP) = 420 <= 438), the largest shape the
+    # library accepts with digits of two primes.
+    "l12_n16384_k2": ParamSet("l12_n16384_k2", 16384, 1146881, tuple(PRIMES_16384[:12]), PRIMES_16384[12],
+                              P2=PRIMES_16384[13]),
     # N=8192 for tests of that ring size: five data primes, log2(QP) = 180 <= 218.
     "n8192": ParamSet("n8192", 8192, 65537, tuple(PRIMES_16384[:5]), PRIMES_16384[5]),
     # Small sets for tests (not secure; flagged).

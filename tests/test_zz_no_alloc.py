@@ -1,9 +1,10 @@
 """The rotation that allocates nothing (lola_rotate_noalloc, scratch in a
 fixed device array) against lola_rotate on the same inputs, word for word,
-through the C ABI: calls in a row, each smaller than the one before (digits
-of two primes with two special primes, then one prime per digit, then a
-smaller ring and prime count), so that each runs over the previous call's
-leftovers in the shared array."""
+through the C ABI: calls in a row, each smaller than the one before (the
+largest shape the fixed array holds, twelve primes with two special primes;
+then seven primes with two-prime digits, with one prime per digit, and a
+smaller ring), so that each runs over the previous call's leftovers in the
+shared array."""
 import ctypes
 
 import numpy as np
@@ -28,7 +29,8 @@ def test_rotate_noalloc_equals_rotate_second_call_smaller():
     from paper_1812_10659_amd import lola
     f = _noalloc()
     # (parameter set, step): the second call is the smaller one
-    for k, (pname, step) in enumerate([("mnist_n16384_k2", 5), ("mnist_n16384", 3), ("n4096_3q", "row_swap")]):
+    for k, (pname, step) in enumerate([("l12_n16384_k2", 7), ("mnist_n16384_k2", 5), ("mnist_n16384", 3),
+                                       ("n4096_3q", "row_swap")]):
         p = wl.PARAMS[pname]
         print(f"[gpu-noalloc] call {k}: {pname} step {step}", flush=True)
         ctx = lola.Context(p)
