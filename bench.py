@@ -1133,7 +1133,7 @@ def oracle_batch_ops():
 
     from oracle import bfv
     from paper_1812_10659_amd import workloads as wl
-    p = wl.PARAMS["batch_n16384"]
+    p = wl.PARAMS["batch_n16384_k2"]
     octx = bfv.Context(p)
     keys = bfv.keygen(octx, wl.key_seed(2), [bfv.galois_element(p.N, 1)])
     rs = wl.rng(wl.workload_seed(2), 21)

@@ -1,4 +1,5 @@
-"""Batched primitive microbenchmark (512 ciphertexts, N=16384, L=8).
+"""Batched primitive microbenchmark (512 ciphertexts, N=16384, L=8; key
+switching with digits of two primes and two special primes by default).
 
 Per ciphertext: forward + inverse NTT of both components, a plaintext
 product, then pairs (2i, 2i+1) multiply and relinearise, and every ciphertext
@@ -245,8 +246,9 @@ def autotune_ks(ctx, N, L, n_jobs=128, reps=10):
     return cache
 
 
-def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tune: bool = True) -> dict:
-    p = wl.PARAMS["batch_n16384"]
+def run_batched(n_ct: int = 512, verify: int = 8, max_steps: int | None = None, tune: bool = True,
+                params: str = "batch_n16384_k2") -> dict:
+    p = wl.PARAMS[params]
     N, L = p.N, p.L
     ctx = lola.Context(p)
     seed = wl.workload_seed(2)

@@ -63,6 +63,8 @@ PARAMS: Dict[str, ParamSet] = {
                                 P2=PRIMES_16384[8]),
     # Batched primitive microbenchmark: eight data primes.
     "batch_n16384": ParamSet("batch_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),
+    "batch_n16384_k2": ParamSet("batch_n16384_k2", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8],
+                                P2=PRIMES_16384[9]),
     # LoLa-Dense input path: the mask products at the input cost noise that
     # seven data primes do not leave room for; eight primes, log2(QP) = 270.
     "mnist_dense_n16384": ParamSet("mnist_dense_n16384", 16384, 1146881, tuple(PRIMES_16384[:8]), PRIMES_16384[8]),

@@ -2,7 +2,8 @@
 batched plaintext products, exact products with relinearisation, and uneven
 rotation chains in one persistent launch -- each checked word for word
 against the oracle on the same inputs; the wave-by-wave batched chains must
-equal the persistent ones."""
+equal the persistent ones.  The small run keeps one prime per key-switching
+digit; the full-size run is the bench's, with digits of two primes."""
 import numpy as np
 import pytest
 
@@ -16,7 +17,7 @@ def test_batched_primitives_match_oracle():
     import torch
     from paper_1812_10659_amd import batched, lola
     print("[gpu-batched] 24 ciphertexts, chains of <= 4 rotations, L=8", flush=True)
-    r = batched.run_batched(n_ct=24, max_steps=4, tune=False)
+    r = batched.run_batched(n_ct=24, max_steps=4, tune=False, params="batch_n16384")
     T = r.pop("_tensors")
     ctx = T["ctx"]
     assert r["ntt"]["roundtrip_exact"]
@@ -49,13 +50,15 @@ def _bitrev_perm(N):
 @pytest.fixture(scope="module")
 def full_size():
     """The bench's configuration, run once: 512 ciphertexts, chains of 1..64
-    rotations in one persistent launch, 256 products with relinearisation;
-    the oracle's keys for every step of the workload."""
+    rotations in one persistent launch, 256 products with relinearisation
+    (key-switching digits of two primes); the oracle's keys for every step
+    of the workload."""
     from paper_1812_10659_amd import batched
     print("[gpu-batched] 512 ciphertexts, full chains", flush=True)
     r = batched.run_batched(n_ct=512, tune=False)
     T = r.pop("_tensors")
-    p = wl.PARAMS["batch_n16384"]
+    p = wl.PARAMS["batch_n16384_k2"]
+    assert T["ctx"].K == 2
     octx = bfv.Context(p)
     need = sorted({bfv.galois_element(p.N, bfv.ROW_SWAP if s == 0 else int(s)) for row in T["steps"] for s in row})
     okeys = bfv.keygen(octx, T["seed"], need)
