@@ -163,6 +163,14 @@ def test_plan_errors():
     with pytest.raises(lola.LolaError) as e:
         plan.load(other)
     assert e.value.code == -4
+    # and for the same ring and primes with another key-switching shape (two
+    # special primes): its keys and scratch differ
+    other_k2 = lola.Context(wl.PARAMS["mnist_n16384_k2"])
+    plan_k1 = lola.Plan(wl.PARAMS["mnist_n16384"], networks.mnist_small_layers(wl.mnist_small_weights()))
+    with pytest.raises(lola.LolaError) as e:
+        plan_k1.load(other_k2)
+    assert e.value.code == -4
+    other_k2.close()
     ctx = lola.Context(p)
     plan.load(ctx)
     sk = ctx.keygen_secret(3)
