@@ -459,6 +459,9 @@ def main():
                      "traffic": traffic and traffic["bytes_per_launch"], "traffic_detail": traffic,
                      "avg_launch_ms": round(ks_avg_ms, 4),
                      "jobs_per_launch": round(jobs_per_launch, 1), "ops_per_job": ops_per_job,
+                     "note": "ops_per_job is the inner product's algorithmic lane-op count for the context's "
+                             "key-switching shape (digits of two primes: fewer transforms and key products than "
+                             "one prime per digit, whose figures are under other_keyswitch_shape)",
                      "pass": f"{args.steps} steps of the same batch and plan after the timed ones, run as one "
                              f"lane so that each launch is timed alone "
                              f"({B * args.steps / elapsed_one_lane:.1f} inferences/s in that pass)"},
@@ -994,7 +997,11 @@ def keyswitch_shape_run(pname, w, B, C, steps, warmup, lanes, tune, latency_runs
         plan.evaluate(ctx, reqs)
     torch.cuda.synchronize()
     lola.timing_enable(ctx, False)
-    whole = whole_keyswitch(lola.kernel_stats(ctx), p.N, p.L, len(p.special))
+    kst = lola.kernel_stats(ctx)
+    whole = whole_keyswitch(kst, p.N, p.L, len(p.special))
+    inner = kst.get("ks_inner_kernel")
+    inner_frac = (ks_inner_ops(p.N, p.L, len(p.special)) * inner["units"] / (inner["ms"] / 1e3) / PEAK_VALU_LANE_OPS
+                  if inner and inner["ms"] > 0 else None)
     for r in range(B):
         got = rq.decrypted_outputs(ctx, plan, keys[r % C]["sk"], reqs[r])
         assert [int(v) for v in got] == [int(v) for v in _plain_logits_mod_t(images[r], w, p.t)], f"request {r}"
@@ -1014,7 +1021,9 @@ def keyswitch_shape_run(pname, w, B, C, steps, warmup, lanes, tune, latency_runs
            "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
            "keyswitch_us_per_job": whole and whole["us_per_job"],
            "keyswitch_us_per_job_by_kernel": whole and whole["us_per_job_by_kernel"],
-           "keyswitch_valu_frac": whole and whole["valu_frac"], "decrypted": B}
+           "keyswitch_valu_frac": whole and whole["valu_frac"],
+           "inner_kernel_valu_frac": inner_frac and round(inner_frac, 4),
+           "inner_kernel_ops_per_job": ks_inner_ops(p.N, p.L, len(p.special)), "decrypted": B}
     del reqs, keys, plan, ctx
     torch.cuda.empty_cache()
     return res
