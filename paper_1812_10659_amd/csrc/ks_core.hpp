@@ -139,20 +139,26 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
     for (int r = 0; r < NTT_E; ++r) gst(D, natural_index<LOGN, SPLIT>(tid, r), v[r]);
 }
 
-// Digit d reduced mod m_j from two canonical limbs of its primes a, b:
+// Digit d mod m_j from two canonical limbs of its primes a, b:
 // x mod q_a q_b = x_a + q_a y with y = (x_b - x_a) q_a^-1 mod q_b (Garner),
-// in [0, q_a q_b), then reduced mod m_j.  Every modulus exceeds 2^29, so
-// x_a < 2 q_b and one conditional subtraction reduces it mod q_b; the sum
-// x_a + (q_a y mod m_j, lazily < 2 m_j) stays below 2^32.
+// in [0, q_a q_b), taken mod m_j.  Every modulus exceeds 2^29, so
+// x_a < 2^30 < 2 q_b: x_b + 2 q_b - x_a is positive, below 3 q_b < 2^32 and
+// congruent to x_b - x_a mod q_b, which the Shoup product takes as is.  The
+// result x_a + (q_a y mod m_j, lazily < 2 m_j) lies in [0, 4 m_j): the range
+// a forward transform takes as input (its first butterflies reduce it), so
+// it is left unreduced.
 LOLA_HD uint32_t ks_garner2(uint32_t xa, uint32_t xb, uint32_t qb, uint32_t iv, uint32_t ivp,
                                                uint32_t w, uint32_t wp, const ModConst &mj) {
-    const uint32_t y = shoup(xb + qb - csub(xa, qb), iv, ivp, qb);
-    return reduce32(xa + shoup_lazy(y, w, wp, mj.q), mj.q, mj.one_shoup);
+    const uint32_t y = shoup(xb + 2 * qb - xa, iv, ivp, qb);
+    return xa + shoup_lazy(y, w, wp, mj.q);
 }
 
 // This thread's coefficients (natural_index<LOGN, SPLIT>(tid, r)) of digit d
-// reduced mod m_j, from the coefficient-form limbs D ([L][N], limb i the
-// canonical residue mod q_i).  A digit of one prime is its limb.
+// mod m_j, from the coefficient-form limbs D ([L][N], limb i the canonical
+// residue mod q_i), in [0, 4 m_j) for a forward transform.  A digit of one
+// prime is its limb: reduced mod m_j with one special prime (moduli of any
+// size), taken as is with two (every modulus exceeds 2^29, so a residue of
+// one is below 4 m_j).
 template <int LOGN, int SPLIT = 0>
 __device__ __forceinline__ void ks_digit_to(const uint32_t *D, const KsDims &kd, uint32_t d, uint32_t j,
                                             const ModConst &mj, const MrcConst *mrc, uint32_t tid,
@@ -161,8 +167,14 @@ __device__ __forceinline__ void ks_digit_to(const uint32_t *D, const KsDims &kd,
     const uint32_t a = kd.first(d);
     const GBuf Da = gbuf(D + ((size_t)a << LOGN), N);
     if (kd.width(d) == 1) {
+        if (kd.K == 1) {
 #pragma unroll
-        for (int r = 0; r < NTT_E; ++r) x[r] = reduce32(gld(Da, natural_index<LOGN, SPLIT>(tid, r)), mj.q, mj.one_shoup);
+            for (int r = 0; r < NTT_E; ++r)
+                x[r] = reduce32(gld(Da, natural_index<LOGN, SPLIT>(tid, r)), mj.q, mj.one_shoup);
+        } else {
+#pragma unroll
+            for (int r = 0; r < NTT_E; ++r) x[r] = gld(Da, natural_index<LOGN, SPLIT>(tid, r));
+        }
         return;
     }
     const GBuf Db = gbuf(D + ((size_t)(a + 1) << LOGN), N);
@@ -177,14 +189,18 @@ __device__ __forceinline__ void ks_digit_to(const uint32_t *D, const KsDims &kd,
 // [u]_P mod q_j for P = p_0 p_1, from u's canonical residues u0 mod p_0 and
 // u1 mod p_1: V = u0 + p_0 z, z = (u1 - u0) p_0^-1 mod p_1, lies in [0, P),
 // and the centred value is V - P when V > P/2, that is when z > (p_1 - 1)/2,
-// or z = (p_1 - 1)/2 and u0 > (p_0 - 1)/2 (both primes odd).
+// or z = (p_1 - 1)/2 and u0 > (p_0 - 1)/2 (both primes odd); u1 + 2 p_1 - u0
+// is positive and below 2^32 as in ks_garner2.  The result is left in
+// [0, 3 q_j), for a forward transform: u0 < 2^30 < 2 q_j and the lazy product
+// is below 2 q_j, so one subtraction of 2 q_j brings their sum below 2 q_j
+// before q_j - (P mod q_j) is added.
 LOLA_HD uint32_t ks_lift2(uint32_t u0, uint32_t u1, const MrcConst *mrc, uint32_t jj,
                                              const ModConst &mj) {
     const uint32_t p1 = mrc->sp1;
-    const uint32_t z = shoup(u1 + p1 - csub(u0, p1), mrc->sp_inv, mrc->sp_invp, p1);
-    const bool big = z > mrc->sp_half1 || (z == mrc->sp_half1 && u0 > mrc->sp_half0);
-    return reduce32(u0 + shoup_lazy(z, mrc->p0q[jj], mrc->p0qp[jj], mj.q) + (big ? mj.q - mrc->Pq[jj] : 0u), mj.q,
-                    mj.one_shoup);
+    const uint32_t z = shoup(u1 + 2 * p1 - u0, mrc->sp_inv, mrc->sp_invp, p1);
+    // z > h1, or z = h1 and u0 > h0, as one comparison: 2z + [u0 > h0] > 2 h1
+    const bool big = 2 * z + (u0 > mrc->sp_half0 ? 1u : 0u) > 2 * mrc->sp_half1;
+    return csub(u0 + shoup_lazy(z, mrc->p0q[jj], mrc->p0qp[jj], mj.q), mj.twoq) + (big ? mj.q - mrc->Pq[jj] : 0u);
 }
 
 // Stage 2 for target modulus j (q_j for j < L, p_{j-L} for j >= L): for

@@ -1,9 +1,10 @@
 // Host check of the two-prime conversions of key switching with digits of
-// two primes: ks_garner2 (a digit x mod q_a q_b, from its two residues,
-// reduced mod another modulus) and ks_lift2 (the centred [u]_P mod q_j for
-// P = p_0 p_1), each against the exact value from 128-bit integers, on
-// random residues and on the edge residues (0, 1, q-1, and the centring
-// threshold).  Exit status = number of failures.
+// two primes: ks_garner2 (a digit x mod q_a q_b, from its two residues, mod
+// another modulus m, left in [0, 4m)) and ks_lift2 (the centred [u]_P mod
+// q_j for P = p_0 p_1, left in [0, 3 q_j)), each against the exact value from
+// 128-bit integers and within its stated range, on random residues and on the
+// edge residues (0, 1, q-1, and the centring threshold).  Exit status =
+// number of failures.
 #include "../../paper_1812_10659_amd/csrc/ks_core.hpp"
 
 #include <cstdio>
@@ -27,6 +28,7 @@ static uint64_t inv(uint64_t a, uint64_t m) { return pw(a, m - 2, m); }   // m p
 static ModConst mconst(uint32_t q) {
     ModConst c{};
     c.q = q;
+    c.twoq = 2 * q;
     c.one_shoup = (uint32_t)((1ull << 32) / q);
     return c;
 }
@@ -62,7 +64,7 @@ int main() {
                     const uint32_t want = (uint32_t)(v % mj);
                     const uint32_t got = ks_garner2(xa, xb, (uint32_t)qb, iv, ivp, w, wp, mc);
                     ++checked;
-                    if (got != want) {
+                    if (got >= 4 * mj || got % mj != want) {
                         if (bad < 5) printf("garner2 qa=%llu qb=%llu m=%llu xa=%u xb=%u got %u want %u\n",
                                             (unsigned long long)qa, (unsigned long long)qb, (unsigned long long)mj,
                                             xa, xb, got, want);
@@ -94,7 +96,7 @@ int main() {
                     if (r < 0) r += mj;
                     const uint32_t got = ks_lift2(u0, u1, &m, 0, mc);
                     ++checked;
-                    if (got != (uint32_t)r) {
+                    if (got >= 3 * mj || got % mj != (uint32_t)r) {
                         if (bad < 5) printf("lift2 p0=%llu p1=%llu q=%llu got %u want %u\n", (unsigned long long)qa,
                                             (unsigned long long)qb, (unsigned long long)mj, got, (uint32_t)r);
                         ++bad;
