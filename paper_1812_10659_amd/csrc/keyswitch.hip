@@ -42,7 +42,7 @@ __device__ __forceinline__ uint32_t ks_unit_modulus(const KsDims &kd, uint32_t u
     return u < kd.K ? kd.L + u : u - kd.K;
 }
 
-template <int LOGN, int KSI = ks_inner_split<LOGN>()>
+template <int LOGN, int KSI = ks_inner_split<LOGN>(), bool LAZY = false>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                      const KsDims kd,
                                                                      const ModConst *__restrict__ mcs,
@@ -58,7 +58,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t j = ks_unit_modulus(kd, ju.unit);
-    ks_stage_inner<LOGN, KSI>(job.key, job.scratch, j, kd, sh, mcs[j], tw, itw, mrc);
+    ks_stage_inner<LOGN, KSI, (1u << LOGN), 0, LAZY>(job.key, job.scratch, j, kd, sh, mcs[j], tw, itw, mrc);
 }
 
 // Latency form of the inner stage (launches of at most KS_TERM_MAX_JOBS
@@ -213,6 +213,15 @@ static void launch_ks_inner(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream
     const KsDims kd = ks_dims(ctx);
     const dim3 g(xcd_grid(n, kd.M())), b(ctx->N / NTT_E);
     if constexpr (LG == 14) {
+        // at most four digits: the transforms' outputs enter the 64-bit sums
+        // unreduced (see ks_stage_inner)
+        if (kd.dn <= 4) {
+            switch (ctx->ks_var[1]) {
+                case 1: hipLaunchKernelGGL((ks_inner_kernel<14, 0, true>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc); return;
+                case 2: hipLaunchKernelGGL((ks_inner_kernel<14, 4424, true>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc); return;
+                default: hipLaunchKernelGGL((ks_inner_kernel<14, 4433, true>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc); return;
+            }
+        }
         switch (ctx->ks_var[1]) {
             case 1: hipLaunchKernelGGL((ks_inner_kernel<14, 0>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc); return;
             case 2: hipLaunchKernelGGL((ks_inner_kernel<14, 4424>), g, b, 0, s, d, n, kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc); return;

@@ -228,8 +228,11 @@ __host__ __device__ constexpr size_t ks_up_limb(const KsDims &kd, uint32_t c, ui
 }
 
 // HALF: words between the two LDS halves (the transforms here take the plain
-// placement, which needs N).
-template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN), int KFIX = 0>
+// placement, which needs N).  LAZY: the digits' transforms leave their
+// output in [0, 4 m_j) (no final reduction); each product is then below
+// 4 m_j^2 and the sum of at most four below 16 m_j^2 < 2^64 (m_j < 2^30), so
+// the caller may choose it when the shape has at most four digits.
+template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN), int KFIX = 0, bool LAZY = false>
 __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, const KsDims kd_,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
                                                const TwPair *itw, const MrcConst *mrc) {
@@ -237,8 +240,9 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
     const KsDims kd = ks_fix<KFIX>(kd_);
     const uint32_t L = kd.L, M = kd.M();
     // 64-bit accumulators: every term is x * key with x < q (a transform's
-    // output is canonical) and key < q, so at most 12 digits sum below
-    // 12 q^2 < 2^64; one Montgomery reduction at the end.
+    // output is canonical; below 4q when LAZY) and key < q, so at most 12
+    // digits sum below 12 q^2 < 2^64 (at most 4 below 16 q^2 when LAZY); one
+    // Montgomery reduction at the end.
     uint64_t a0[NTT_E], a1[NTT_E];
 #pragma unroll
     for (int r = 0; r < NTT_E; ++r) a0[r] = a1[r] = 0;
@@ -253,7 +257,7 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
             ks_digit_to<LOGN, KSI>(scratch, kd, d, j, mc, mrc, tid, x);
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
-            ntt_fwd_regs<LOGN, true, KSI>(x, tid, sh + half * HALF, tw + ((size_t)jj << LOGN), mc.q);
+            ntt_fwd_regs<LOGN, true, KSI, false, LAZY>(x, tid, sh + half * HALF, tw + ((size_t)jj << LOGN), mc.q);
             half ^= 1u;
         }
         // The key offset passes through an opaque copy placed after the

@@ -287,11 +287,15 @@ struct FwdDriver {
     }
 };
 
-template <int LOGN, bool FRESH = false, int SPLIT = 0, bool PAD = false>
+// LAZY: leave the output in [0, 4q), the butterflies' range, for a caller
+// that reduces it later (a 64-bit sum of products).
+template <int LOGN, bool FRESH = false, int SPLIT = 0, bool PAD = false, bool LAZY = false>
 LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
     FwdDriver<LOGN, 0, FRESH, SPLIT, PAD>::run(x, tid, sh, tw, q);
+    if constexpr (!LAZY) {
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) x[r] = csub(csub(x[r], 2 * q), q);
+        for (int r = 0; r < NTT_E; ++r) x[r] = csub(csub(x[r], 2 * q), q);
+    }
 }
 
 // Inverse: x enters in the last forward pass's layout (values in [0, 2q))
