@@ -257,7 +257,8 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
             ks_digit_to<LOGN, KSI>(scratch, kd, d, j, mc, mrc, tid, x);
             uint32_t jj = j;
             asm volatile("" : "+s"(jj));
-            ntt_fwd_regs<LOGN, true, KSI, false, LAZY>(x, tid, sh + half * HALF, tw + ((size_t)jj << LOGN), mc.q);
+            ntt_fwd_regs<LOGN, true, KSI, false, LAZY ? 2 : 0>(x, tid, sh + half * HALF, tw + ((size_t)jj << LOGN),
+                                                              mc.q);
             half ^= 1u;
         }
         // The key offset passes through an opaque copy placed after the
@@ -551,13 +552,14 @@ __device__ __forceinline__ void ks_stage_moddown(const uint32_t *scratch, uint32
             x[r] = ks_lift2(gld(UP, idx), gld(UP1, idx), mrc, jj, mc);
         }
     }
-    ntt_fwd_regs<LOGN, false, SPLIT, PAD>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
+    // the transform's output left in [0, 2q): (U - lift) P^-1 takes
+    // U + 2q - lift, positive and below 3q < 2^32, into the lazy product
+    ntt_fwd_regs<LOGN, false, SPLIT, PAD, 1>(x, tid, sh, tw + ((size_t)jj << LOGN), mc.q);
     const uint32_t pinv = mrc->Pinvq[jj], pinvp = mrc->Pinvqp[jj];
     uint32_t u[NTT_E];
     load_spectral<LOGN, SPLIT>(gbuf(scratch + ((size_t)((2 + c) * L + jj) << LOGN), N), tid, u);
-    // (U - lift) P^-1: U + q - lift < 2q feeds the lazy product directly
 #pragma unroll
-    for (int r = 0; r < NTT_E; ++r) x[r] = csub(shoup_lazy(u[r] + mc.q - x[r], pinv, pinvp, mc.q), mc.q);
+    for (int r = 0; r < NTT_E; ++r) x[r] = csub(shoup_lazy(u[r] + mc.twoq - x[r], pinv, pinvp, mc.q), mc.q);
     if (add) {
         ks_read_sigma<LOGN, SPLIT>(add + ((size_t)jj << LOGN), g, tid, sh, u);   // after the transform's last use of sh
 #pragma unroll

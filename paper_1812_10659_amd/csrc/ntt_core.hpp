@@ -287,14 +287,17 @@ struct FwdDriver {
     }
 };
 
-// LAZY: leave the output in [0, 4q), the butterflies' range, for a caller
-// that reduces it later (a 64-bit sum of products).
-template <int LOGN, bool FRESH = false, int SPLIT = 0, bool PAD = false, bool LAZY = false>
+// LAZY: how far the output is reduced, for a caller that reduces it later:
+// 0 to [0, q), 1 to [0, 2q), 2 not at all ([0, 4q), the butterflies' range).
+template <int LOGN, bool FRESH = false, int SPLIT = 0, bool PAD = false, int LAZY = 0>
 LOLA_HD void ntt_fwd_regs(uint32_t (&x)[NTT_E], uint32_t tid, uint32_t *sh, const TwPair *tw, uint32_t q) {
     FwdDriver<LOGN, 0, FRESH, SPLIT, PAD>::run(x, tid, sh, tw, q);
-    if constexpr (!LAZY) {
+    if constexpr (LAZY == 0) {
 #pragma unroll
         for (int r = 0; r < NTT_E; ++r) x[r] = csub(csub(x[r], 2 * q), q);
+    } else if constexpr (LAZY == 1) {
+#pragma unroll
+        for (int r = 0; r < NTT_E; ++r) x[r] = csub(x[r], 2 * q);
     }
 }
 
