@@ -103,6 +103,11 @@ PARAMS: Dict[str, ParamSet] = {
                         insecure_ok=True),
     "toy1024_k2": ParamSet("toy1024_k2", 1024, 12289, tuple(PRIMES_16384[:3]), PRIMES_16384[3],
                            insecure_ok=True, P2=PRIMES_16384[4]),
+    # one ciphertext prime with two special primes: a single digit holding
+    # fewer primes than the special primes (words only; the noise of a product
+    # exceeds this Delta, so the network checks do not use it)
+    "toy1024_l1_k2": ParamSet("toy1024_l1_k2", 1024, 12289, tuple(PRIMES_16384[:1]), PRIMES_16384[1],
+                              insecure_ok=True, P2=PRIMES_16384[2]),
 }
 
 # Plaintext moduli for exact integer outputs of the MNIST-shaped network by

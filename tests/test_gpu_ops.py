@@ -8,9 +8,10 @@ from paper_1812_10659_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-# the last three: key-switching digits of two primes with two special primes
-PSETS = ["toy1024", "toy2048", "n4096_3q", "n8192", "mnist_n16384", "l12_n16384", "toy1024_k2", "mnist_n16384_k2",
-         "l12_n16384_k2"]
+# the last four: key-switching digits of two primes with two special primes
+# (one ciphertext prime, three, seven and twelve)
+PSETS = ["toy1024", "toy2048", "n4096_3q", "n8192", "mnist_n16384", "l12_n16384", "toy1024_l1_k2", "toy1024_k2",
+         "mnist_n16384_k2", "l12_n16384_k2"]
 STEPS = [1, -1, 7, bfv.ROW_SWAP]
 SEED = 0x5EED_0001
 
