@@ -56,6 +56,19 @@ def test_reported_work_and_bytes_per_key_switch():
     # ciphertext in, key once, result out
     assert bench.ks_bytes(N, L) == 4 * N * (2 * L + 2 * L * (L + 1) + 2 * L) == 9175040
     assert np.isclose(bench.PEAK_VALU_LANE_OPS, 39.3216e12)
+    # digits of two primes with two special primes, counted by hand at L = 7:
+    # digits {0,1} {2,3} {4,5} {6}, nine target moduli.  Each ciphertext
+    # prime's unit transforms the three digits that do not hold it (21), each
+    # special prime's all four (8): 29 transforms, plus two inverse
+    # transforms per special prime; 2 x 4 digits x 9 moduli key products; a
+    # Garner step for every transformed pair whose digit has two primes: the
+    # three two-prime digits times the seven moduli outside each (21)
+    assert bench.ks_shape(L, 2) == (4, 9, 29, 21)
+    assert bench.ks_inner_ops(N, L, 2) == (9 * (29 + 4) * (N // 2) * 14 + 7 * 2 * 4 * 9 * N + 14 * 21 * N
+                                           == 47136768)
+    assert bench.ks_bytes(N, L, 2) == 4 * N * (2 * L + 2 * 4 * 9 + 2 * L) == 6553600
+    # one prime per digit is the same count at K = 1
+    assert bench.ks_shape(L, 1) == (7, 8, 49, 0)
 
 
 def test_oracle_per_op_times_and_their_extrapolation():
