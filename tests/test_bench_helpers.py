@@ -64,8 +64,8 @@ def test_reported_work_and_bytes_per_key_switch():
     # Garner step for every transformed pair whose digit has two primes: the
     # three two-prime digits times the seven moduli outside each (21)
     assert bench.ks_shape(L, 2) == (4, 9, 29, 21)
-    assert bench.ks_inner_ops(N, L, 2) == (9 * (29 + 4) * (N // 2) * 14 + 7 * 2 * 4 * 9 * N + 14 * 21 * N
-                                           == 47136768)
+    by_hand = 9 * (29 + 4) * (N // 2) * 14 + 7 * 2 * 4 * 9 * N + 14 * 21 * N
+    assert bench.ks_inner_ops(N, L, 2) == by_hand == 47136768
     assert bench.ks_bytes(N, L, 2) == 4 * N * (2 * L + 2 * 4 * 9 + 2 * L) == 6553600
     # one prime per digit is the same count at K = 1
     assert bench.ks_shape(L, 1) == (7, 8, 49, 0)
