@@ -278,9 +278,10 @@ int lola_ks_autotune(lola_ctx *ctx, uint32_t n_jobs, uint32_t reps, lola_ks_vari
 /* lola_rotate for callers that cannot allocate device memory (code under
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same rotation, the same words, computed with the batched key-switch
- * kernels on one job whose scratch, (4L + 2) N words, lies in a fixed device
- * array of the library of (4 x 12 + 2) x 16384 words (3.1 MiB; set up per
- * device when a context is created and held until the process ends) and
+ * kernels on one job whose scratch, (4L + 2K) N words (K special primes),
+ * lies in a fixed device array of the library of (4 x 12 + 2 x 2) x 16384
+ * words (3.25 MiB; set up per device when a context is created and held
+ * until the process ends) and
  * whose descriptor is passed by value; nothing is allocated and no
  * descriptor is uploaded.  Every call on one GPU shares that array, so calls
  * that overlap on one GPU (two streams, two threads) race: the caller
