@@ -245,8 +245,8 @@ int lola_rotate(lola_ctx *ctx, const uint32_t *gk_dev, uint32_t galois, const ui
  * transforms to every modulus are computed once for all n.  Each output
  * decrypts to the same slots as lola_rotate's; the words differ from it
  * (Sec. 3.1 rotations; the digits are this library's key-switching reading).
- * Scratch: (L^2 + 3L) N words for the source plus (4L + 2) N per rotation, in
- * chunks of 128. */
+ * Scratch: (2L + (L + K) dnum) N words for the source ((L^2 + 3L) N with one
+ * special prime) plus (4L + 2K) N per rotation, in chunks of 128. */
 int lola_rotate_hoisted(lola_ctx *ctx, const uint32_t *in_dev, uint32_t n, const uint32_t *galois,
                         const uint32_t *const *keys, uint32_t *const *out_dev, lola_stream stream);
 
