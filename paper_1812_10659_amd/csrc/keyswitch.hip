@@ -27,13 +27,13 @@ namespace lola {
 template <int LOGN, int SPLIT = 0, bool PAD = true>
 __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_digits_kernel(const KsJob *__restrict__ jobs, uint32_t n,
                                                                       uint32_t L, const ModConst *__restrict__ mcs,
-                                                                      const TwPair *__restrict__ itw) {
+                                                                      const TwPair *__restrict__ itw, uint32_t keep) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN, PAD>()];
     const JobUnit ju = xcd_job_unit(blockIdx.x, L, n);
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t i = ju.unit;
-    ks_stage_digit<LOGN, PAD, SPLIT>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw);
+    ks_stage_digit<LOGN, PAD, SPLIT>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw, keep != 0);
 }
 
 // Target modulus of unit u of a job whose first K units are the special
@@ -58,7 +58,8 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks_inner_kernel(const KsJ
     if (ju.job >= n) return;
     const KsJob job = jobs[ju.job];
     const uint32_t j = ks_unit_modulus(kd, ju.unit);
-    ks_stage_inner<LOGN, KSI, (1u << LOGN), 0, LAZY>(job.key, job.scratch, j, kd, sh, mcs[j], tw, itw, mrc);
+    ks_stage_inner<LOGN, KSI, (1u << LOGN), 0, LAZY, true>(job.key, job.scratch, j, kd, sh, mcs[j], tw, itw, mrc,
+                                                             job.x, job.galois);
 }
 
 // Latency form of the inner stage (launches of at most KS_TERM_MAX_JOBS
@@ -193,19 +194,21 @@ static uint32_t ks_variant_count(uint32_t logN, uint32_t stage) {
     return stage == 1 ? 3 : 4;
 }
 
+// keep: also store sigma_g(x_i) (needed by the term form only; the inner
+// kernel reads it from the input, and hoisted sources never use it).
 template <int LG>
-static void launch_ks_digits(lola_ctx *ctx, const KsJob *d, uint32_t n, hipStream_t s) {
-    const uint32_t L = ctx->L;
+static void launch_ks_digits(lola_ctx *ctx, const KsJob *d, uint32_t n, bool keep, hipStream_t s) {
+    const uint32_t L = ctx->L, k = keep ? 1u : 0u;
     const dim3 g(xcd_grid(n, L)), b(ctx->N / NTT_E);
     if constexpr (LG == 14) {
         switch (ctx->ks_var[0]) {
-            case 1: hipLaunchKernelGGL((ks_digits_kernel<14, 0, false>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw); return;
-            case 2: hipLaunchKernelGGL((ks_digits_kernel<14, 4433, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw); return;
-            case 3: hipLaunchKernelGGL((ks_digits_kernel<14, 4244, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw); return;
+            case 1: hipLaunchKernelGGL((ks_digits_kernel<14, 0, false>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw, k); return;
+            case 2: hipLaunchKernelGGL((ks_digits_kernel<14, 4433, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw, k); return;
+            case 3: hipLaunchKernelGGL((ks_digits_kernel<14, 4244, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw, k); return;
             default: break;
         }
     }
-    hipLaunchKernelGGL((ks_digits_kernel<LG, 0, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw);
+    hipLaunchKernelGGL((ks_digits_kernel<LG, 0, true>), g, b, 0, s, d, n, L, ctx->d_mc, ctx->d_itw, k);
 }
 
 template <int LG>
@@ -326,7 +329,7 @@ struct KsCost {
         }
     }
     double key_b() const { return 8 * N * dn * M; }
-    double digits_b() const { return 12 * N; }
+    double digits_b(bool keep) const { return (keep ? 12 : 8) * N; }
     double inner_b(double n, double keys) const { return keys * key_b() + n * 8 * N * (2 * L + K); }
     double inner_o() const { return (X + 2 * K) * T + 2 * COST_MAC * dn * M * N + G * N * COST_GARNER; }
     double moddown_b() const { return (12 + 4 * K) * N; }
@@ -374,8 +377,8 @@ int launch_keyswitch(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, const uint6
                                           kd, ctx->d_mc, ctx->d_tw, ctx->d_itw, ctx->d_mrc));                 \
             break;                                                                                           \
         }                                                                                                    \
-        LOLA_TIMED(ctx, s, KID_KS_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                           \
-                   launch_ks_digits<LG>(ctx, d_jobs, n, s));                                                  \
+        LOLA_TIMED(ctx, s, KID_KS_DIGITS, n * L, c.digits_b(term) * n * L, c.T * n * L,                       \
+                   launch_ks_digits<LG>(ctx, d_jobs, n, term, s));                                            \
         if (term) {                                                                                          \
             LOLA_TIMED(ctx, s, KID_KS_TERM, n, c.term_b() * n, c.term_o() * n,                                \
                        hipLaunchKernelGGL(ks_term_kernel<LG>, dim3(n * TU), block, 0, s, d_jobs, n, kd,         \
@@ -411,8 +414,8 @@ int launch_keyswitch_hoist_src(lola_ctx *ctx, const KsJob *d_jobs, uint32_t n, h
     const KsCost c(ctx);
 #define LOLA_HS_CASE(LG)                                                                                     \
     case LG:                                                                                                 \
-        LOLA_TIMED(ctx, s, KID_KS_HOIST_DIGITS, n * L, c.digits_b() * n * L, c.T * n * L,                     \
-                   launch_ks_digits<LG>(ctx, d_jobs, n, s));                                                  \
+        LOLA_TIMED(ctx, s, KID_KS_HOIST_DIGITS, n * L, c.digits_b(false) * n * L, c.T * n * L,                \
+                   launch_ks_digits<LG>(ctx, d_jobs, n, false, s));                                           \
         LOLA_TIMED(ctx, s, KID_KS_MODUP, n, c.modup_b() * n, c.modup_o() * n,                                 \
                    hipLaunchKernelGGL(ks_modup_kernel<LG>, dim3(n * kd.M() * kd.dn), block, 0, s, d_jobs, n, kd, \
                                       ctx->d_mc, ctx->d_tw, ctx->d_mrc));                                     \

@@ -117,13 +117,15 @@ __device__ __forceinline__ void ks_read_sigma(const uint32_t *src, uint32_t g, u
     for (int r = 0; r < NTT_E; ++r) v[r] = sh[galois_src_index(spectral_index<LOGN, SPLIT>(tid, r), g, LOGN)];
 }
 
-// Stage 1 for prime i: X'_i = sigma_g(x_i) (kept), D_i = INTT(X'_i).
+// Stage 1 for prime i: D_i = INTT(X'_i) with X'_i = sigma_g(x_i), and X'_i
+// itself kept in the scratch when `keep` is set (for consumers that cannot
+// read it through sigma_g from x: the latency form's term stage).
 // SPLIT / PAD: the transform's radix split and LDS placement (every choice
 // reads and writes the same global layouts).
 template <int LOGN, bool PAD = true, int SPLIT = 0>
 __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, uint32_t *scratch, uint32_t i,
                                                uint32_t L, uint32_t *sh, const ModConst &mc,
-                                               const TwPair *itw) {
+                                               const TwPair *itw, bool keep = true) {
     constexpr uint32_t N = 1u << LOGN;
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
@@ -131,7 +133,7 @@ __device__ __forceinline__ void ks_stage_digit(const uint32_t *x, uint32_t g, ui
     asm volatile("" : "+s"(ii));
     uint32_t v[NTT_E];
     ks_read_sigma<LOGN, SPLIT>(x + ((size_t)ii << LOGN), g, tid, sh, v);
-    store_spectral<LOGN, SPLIT>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
+    if (keep) store_spectral<LOGN, SPLIT>(gbuf(scratch + ((size_t)(L + ii) << LOGN), N), tid, v);
     // starts with a barrier
     ntt_inv_regs<LOGN, SPLIT, PAD>(v, tid, sh, itw + ((size_t)ii << LOGN), mc);
     const GBuf D = gbuf(scratch + ((size_t)ii << LOGN), N);
@@ -232,10 +234,15 @@ __host__ __device__ constexpr size_t ks_up_limb(const KsDims &kd, uint32_t c, ui
 // output in [0, 4 m_j) (no final reduction); each product is then below
 // 4 m_j^2 and the sum of at most four below 16 m_j^2 < 2^64 (m_j < 2^30), so
 // the caller may choose it when the shape has at most four digits.
-template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN), int KFIX = 0, bool LAZY = false>
+// SIG: the digit holding q_j is read as sigma_g(x_j) from the input x (through
+// an LDS half, like a transform) instead of from the copy ks_stage_digit keeps;
+// the words are the same.
+template <int LOGN, int KSI = ks_inner_split<LOGN>(), uint32_t HALF = (1u << LOGN), int KFIX = 0, bool LAZY = false,
+          bool SIG = false>
 __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *scratch, uint32_t j, const KsDims kd_,
                                                uint32_t *sh, const ModConst &mc, const TwPair *tw,
-                                               const TwPair *itw, const MrcConst *mrc) {
+                                               const TwPair *itw, const MrcConst *mrc,
+                                               const uint32_t *xin = nullptr, uint32_t g = 0) {
     constexpr uint32_t N = 1u << LOGN;
     const KsDims kd = ks_fix<KFIX>(kd_);
     const uint32_t L = kd.L, M = kd.M();
@@ -252,7 +259,15 @@ __device__ __forceinline__ void ks_stage_inner(const uint32_t *key, uint32_t *sc
         asm volatile("" : "+v"(tid));
         uint32_t x[NTT_E];
         if (kd.owns(d, j)) {
-            load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + j) << LOGN), N), tid, x);
+            if constexpr (SIG) {
+                // with an automorphism the read stages the limb in the next
+                // LDS half between two barriers; the transform after it takes
+                // the other half, as after a transform
+                ks_read_sigma<LOGN, KSI>(xin + ((size_t)j << LOGN), g, tid, sh + half * HALF, x);
+                if (g > 1) half ^= 1u;
+            } else {
+                load_spectral<LOGN, KSI>(gbuf(scratch + ((size_t)(L + j) << LOGN), N), tid, x);
+            }
         } else {
             ks_digit_to<LOGN, KSI>(scratch, kd, d, j, mc, mrc, tid, x);
             uint32_t jj = j;

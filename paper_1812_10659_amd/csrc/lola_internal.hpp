@@ -248,7 +248,7 @@ struct KsJob {
     const uint32_t *add1;   // [L][N] added to component 1, or null
     const uint32_t *addct;  // [2][L][N] added to both components as is, or null
     uint32_t *out;          // [2][L][N]
-    uint32_t *scratch;      // (4L + 2K) N words: D [L][N], Xp [L][N], U [2][L][N], UP [2][K][N]
+    uint32_t *scratch;      // (4L + 2K) N words: D [L][N], Xp [L][N] (term form only), U [2][L][N], UP [2][K][N]
     uint32_t galois;        // 0/1: no automorphism
     uint32_t pad;
     const uint32_t *hoist;  // hoisted rotation: the source's hoist area (ks_hoist_limb), else null
