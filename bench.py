@@ -45,7 +45,7 @@ GARNER_OPS = 14                             # two modular products, three adds o
 # copy (FETCH_SIZE read 0.5 GiB: x2.0; WRITE_SIZE read 1 GiB: x1.0).  These
 # count L2 misses, so reads served by the last-level cache count too.  Valid
 # only for kernel sources with this digest; otherwise the traffic is null.
-KS_INNER_TRAFFIC = {"digest": "160ea83db15e8273", "fetch_per_job": 3.5944e6, "write_per_job": 1.1796e6, "K": 2}
+KS_INNER_TRAFFIC = {"digest": "b210ac9b93f1b31b", "fetch_per_job": 3.5944e6, "write_per_job": 1.1796e6, "K": 2}
 # parameter set of the MNIST-shaped workload (--params): seven ciphertext
 # primes with key-switching digits of two primes and two special primes
 MNIST_PARAMS = "mnist_n16384_k2"

@@ -17,6 +17,7 @@
 // Scratch of one key switch, (4L + 2K) N words:
 //   D  [L][N]    x_i in coefficient form, per prime    (words 0 .. L N)
 //   X' [L][N]    sigma_g(x_i) in NTT form               (L N .. 2 L N)
+//                (written for the latency form's term stage only)
 //   U  [2][L][N] inner products mod q_j, NTT form       (2 L N .. 4 L N)
 //   UP [2][K][N] inner products mod p_k, coefficients   (4 L N .. (4L+2K) N)
 //
