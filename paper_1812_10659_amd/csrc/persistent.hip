@@ -41,12 +41,12 @@ __device__ void wg_rotate(const uint32_t *in, uint32_t *out, const uint32_t *key
     const uint32_t *c1 = in + ((size_t)L << LOGN);
     // plain LDS placement throughout, in two halves of N words (the padded
     // placement's larger buffer measured slower inside this kernel)
-    for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN, false>(c1, g, scr, i, L, sh, mcs[i], itw);
+    for (uint32_t i = 0; i < L; ++i) ks_stage_digit<LOGN, false>(c1, g, scr, i, L, sh, mcs[i], itw, false);
     __syncthreads();
     for (uint32_t j = 0; j < kd.M(); ++j) {
         // the default radix split here: the 4433 split that suits the
         // batched inner kernel measured slower inside this larger kernel
-        ks_stage_inner<LOGN, 0, (1u << LOGN), KFIX>(key, scr, j, kd, sh, mcs[j], tw, itw, mrc);
+        ks_stage_inner<LOGN, 0, (1u << LOGN), KFIX, false, true>(key, scr, j, kd, sh, mcs[j], tw, itw, mrc, c1, g);
         __syncthreads();   // the next target's transforms reuse both LDS halves
     }
     const uint32_t P = mcs[L].q;
