@@ -47,7 +47,7 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks1_digits_kernel(KsJob j
                                                                        const TwPair *__restrict__ itw) {
     __shared__ uint32_t sh[ntt_lds_words<LOGN>()];
     const uint32_t i = blockIdx.x;
-    ks_stage_digit<LOGN>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw);
+    ks_stage_digit<LOGN>(job.x, job.galois, job.scratch, i, L, sh, mcs[i], itw, false);
 }
 
 template <int LOGN>
@@ -59,7 +59,8 @@ __global__ __launch_bounds__((1 << LOGN) / NTT_E) void ks1_inner_kernel(KsJob jo
     __shared__ uint32_t sh[2 << LOGN];
     // the special primes' units first
     const uint32_t j = blockIdx.x < kd.K ? kd.L + blockIdx.x : blockIdx.x - kd.K;
-    ks_stage_inner<LOGN>(job.key, job.scratch, j, kd, sh, mcs[j], tw, itw, mrc);
+    ks_stage_inner<LOGN, ks_inner_split<LOGN>(), (1u << LOGN), 0, false, true>(job.key, job.scratch, j, kd, sh, mcs[j], tw,
+                                                                              itw, mrc, job.x, job.galois);
 }
 
 template <int LOGN>
